@@ -1,0 +1,416 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test ties an oracle function to a library routine written by someone
+else (NumPy's Philox, scipy.sparse, LAPACK eigh/svd), to a closed form, to a
+hand-derived sequence (tests/golden), or to an invariant the paper proves.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------ Philox
+
+@pytest.mark.parametrize("seed", [0, 1, 2001, 2002, 2**63 + 12345])
+def test_philox_raw_matches_numpy_bitwise(seed):
+    """Alg. 5 step 1 draws randn; our reading fixes Philox4x64-10 keyed by
+    (seed, 0).  NumPy's Philox is an independent implementation of the same
+    published generator: the raw words must match bit for bit."""
+    ours = oracle.philox_raw(seed, 4099)
+    ref = np.random.Philox(key=seed).random_raw(4099)
+    assert np.array_equal(ours, ref)
+
+
+def test_philox_block_function_with_arbitrary_counter():
+    """The block function with every counter and key word nonzero: NumPy's
+    generator with counter c emits block f(c + 1, key) first."""
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        ctr = rng.integers(0, 2**63, size=4, dtype=np.uint64)
+        key = rng.integers(0, 2**63, size=2, dtype=np.uint64)
+        ref = np.random.Philox(counter=ctr, key=key).random_raw(4)
+        c1 = ctr.copy()
+        c1[0] += np.uint64(1)  # no carry: c[0] < 2^63
+        assert np.array_equal(oracle.philox4x64_10(c1, key), ref)
+
+
+def test_gaussian_distribution():
+    """Box-Muller output must be N(0,1): mean, variance, KS statistic, and
+    independence of the cosine/sine halves of each pair."""
+    from scipy import stats
+    z = oracle.gaussian(2002, 2000, 500).ravel()
+    assert abs(z.mean()) < 5e-3
+    assert abs(z.var() - 1.0) < 5e-3
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    ev, od = z[0::2], z[1::2]
+    assert abs(np.corrcoef(ev, od)[0, 1]) < 5e-3
+    # tail mass: P(|z| > 3) = 0.0026998
+    assert abs(np.mean(np.abs(z) > 3.0) - 0.0026998) < 4e-4
+
+
+def test_gaussian_uses_word_pairs_in_order():
+    """Element 2t and 2t+1 come from raw words 2t, 2t+1 (radius from the
+    first, angle from the second).  Checked through the radius, which the
+    pair shares: z[2t]^2 + z[2t+1]^2 = -2 ln(u1)."""
+    seed, rows, cols = 99, 7, 6
+    z = oracle.gaussian(seed, rows, cols).ravel()
+    w = np.random.Philox(key=seed).random_raw(rows * cols)
+    u1 = ((w[0::2] >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0**-53
+    r2 = z[0::2] ** 2 + z[1::2] ** 2
+    assert np.allclose(r2, -2.0 * np.log(u1), rtol=1e-13, atol=0)
+    u2 = (w[1::2] >> np.uint64(11)).astype(np.float64) * 2.0**-53
+    ang = np.mod(np.arctan2(z[1::2], z[0::2]), 2 * np.pi)
+    d = np.abs(ang - 2 * np.pi * u2)
+    d = np.minimum(d, 2 * np.pi - d)
+    assert d.max() < 1e-12
+
+
+def test_gaussian_odd_length_tail():
+    z_odd = oracle.gaussian(5, 3, 3).ravel()      # 9 elements
+    z_even = oracle.gaussian(5, 2, 5).ravel()     # 10 elements, same stream
+    assert np.array_equal(z_odd, z_even[:9])
+
+
+# ------------------------------------------------------------------ sparse
+
+def _csr_small(seed=3, m=57, n=41, density=0.2):
+    rng = np.random.default_rng(seed)
+    D = rng.standard_normal((m, n)) * (rng.random((m, n)) < density)
+    D[5, :] = 0.0  # an empty row
+    D[:, 7] = 0.0  # an empty column
+    return synth.dense_to_csr(D), D
+
+
+def test_spmm_matches_scipy():
+    A, D = _csr_small()
+    X = np.random.default_rng(1).standard_normal((A.n, 13))
+    Y = oracle.csr_spmm(A.row_ptr, A.col, A.val, X)
+    ref = A.to_scipy() @ X
+    assert np.allclose(Y, ref, rtol=1e-14, atol=1e-14)
+
+
+def test_spmm_integer_values_exact():
+    """Integer-valued inputs make every partial sum exact in FP64."""
+    rng = np.random.default_rng(2)
+    D = rng.integers(-3, 4, size=(40, 30)) * (rng.random((40, 30)) < 0.3)
+    A = synth.dense_to_csr(D.astype(np.float64))
+    X = rng.integers(-5, 6, size=(30, 9)).astype(np.float64)
+    Y = oracle.csr_spmm(A.row_ptr, A.col, A.val, X)
+    assert np.array_equal(Y, D @ X)
+
+
+def test_transpose_matches_scipy_bitwise():
+    A, D = _csr_small(seed=4)
+    rT, cT, vT = oracle.csr_transpose(A.m, A.n, A.row_ptr, A.col, A.val)
+    ref = A.to_scipy().T.tocsr()
+    ref.sort_indices()
+    assert np.array_equal(rT, ref.indptr)
+    assert np.array_equal(cT, ref.indices)
+    assert np.array_equal(vT, ref.data)
+
+
+def test_transpose_zipf_bitwise():
+    A = synth.zipf_csr(3000, 2000, 60000, seed=11)
+    rT, cT, vT = oracle.csr_transpose(A.m, A.n, A.row_ptr, A.col, A.val)
+    ref = A.to_scipy().T.tocsr()
+    ref.sort_indices()
+    assert np.array_equal(rT, ref.indptr)
+    assert np.array_equal(cT, ref.indices)
+    assert np.array_equal(vT, ref.data)
+
+
+# ------------------------------------------------------------------ dense
+
+def test_gram_matches_numpy():
+    Cm = np.random.default_rng(5).standard_normal((300, 17))
+    G = oracle.gram(Cm)
+    assert np.allclose(G, Cm.T @ Cm, rtol=1e-13, atol=1e-12)
+    assert np.array_equal(G, G.T)
+
+
+def test_jacobi_2x2_closed_form():
+    """2x2 symmetric: eigenvalues (a+c)/2 -+ sqrt(((a-c)/2)^2 + b^2)."""
+    for a, b, c in [(2.0, 1.0, 3.0), (1.0, 1e-3, 1.0), (5.0, -2.0, -1.0), (1.0, 0.0, 4.0)]:
+        ev, V, _ = oracle.jacobi_eig(np.array([[a, b], [b, c]]))
+        mid, rad = (a + c) / 2, math.sqrt(((a - c) / 2) ** 2 + b * b)
+        assert np.allclose(ev, [mid - rad, mid + rad], rtol=1e-15, atol=1e-15)
+        G = np.array([[a, b], [b, c]])
+        assert np.allclose(G @ V, V * ev, atol=1e-14)
+
+
+def test_jacobi_diagonal_input():
+    d = np.array([3.0, -1.0, 7.0, 0.5, 0.5])
+    ev, V, sweeps = oracle.jacobi_eig(np.diag(d))
+    assert np.array_equal(ev, np.sort(d))
+    assert sweeps == 1
+    assert np.array_equal(np.abs(V).sum(axis=0), np.ones(5))
+
+
+@pytest.mark.parametrize("l", [3, 16, 30, 75, 120])
+def test_jacobi_matches_lapack_eigh(l):
+    rng = np.random.default_rng(l)
+    B = rng.standard_normal((l + 5, l))
+    G = B.T @ B
+    ev, V, _ = oracle.jacobi_eig(G)
+    ref = np.linalg.eigvalsh(G)
+    nrm = np.linalg.norm(G, 2)
+    assert np.abs(ev - ref).max() <= 50 * l * 2.2e-16 * nrm
+    assert np.abs(V.T @ V - np.eye(l)).max() < 1e-13
+    assert np.linalg.norm(G @ V - V * ev) <= 10 * l * 2.2e-16 * nrm
+
+
+def test_eigsvd_matches_lapack_svd():
+    """Alg. 3: S descending, U = C V S^-1 orthonormal, C = U S V^T."""
+    rng = np.random.default_rng(8)
+    Cm = rng.standard_normal((500, 24)) @ np.diag(np.logspace(0, -2, 24))
+    U, S, V, deficient = oracle.eigsvd(Cm)
+    ref = np.linalg.svd(Cm, compute_uv=False)
+    kappa = ref[0] / ref[-1]
+    assert not deficient
+    assert np.all(np.diff(S) <= 0)
+    assert np.abs(S - ref).max() / ref[0] <= 10 * 2.2e-16 * kappa**2 * 24
+    assert np.abs(U.T @ U - np.eye(24)).max() < 1e-9
+    assert np.allclose(U * S @ V.T, Cm, atol=1e-12)
+
+
+def test_eigsvd_rank_deficient_zeroes_columns():
+    rng = np.random.default_rng(9)
+    Cm = rng.standard_normal((50, 3)) @ rng.standard_normal((3, 6))  # rank 3
+    U, S, V, deficient = oracle.eigsvd(Cm)
+    assert deficient
+    assert np.all(U[:, 3:] == 0.0)
+    assert np.allclose(U[:, :3] * S[:3] @ V[:, :3].T, Cm, atol=1e-10)
+
+
+# ------------------------------------------------------------------ check + shift
+
+def test_pve_ratio_hand_values():
+    """eq. (19) with the surrogate E = S + alpha (Prop. 3): hand-computed."""
+    S = np.array([4.0, 2.0, 1.0])
+    Sp = np.array([3.0, 2.0, 0.5])
+    # E = [4.5, 2.5], E' = [3.25, 2.25]; |diff| = [1.25, 0.25]; denom 1 + 0.5
+    assert oracle.pve_ratio(2, S, Sp, 0.5, 0.25) == pytest.approx(1.25 / 1.5, rel=1e-15)
+    # k = 1: only i = 1 counts; denominator S_2 + alpha = 2.5
+    assert oracle.pve_ratio(1, S, Sp, 0.5, 0.25) == pytest.approx(1.25 / 2.5, rel=1e-15)
+
+
+def test_shift_update_hand_values():
+    """Alg. 5 step 6: strictly-greater test, midpoint update."""
+    assert oracle.shift_update(np.array([5.0, 1.0]), 0.5) == 0.75
+    assert oracle.shift_update(np.array([5.0, 0.4]), 0.5) == 0.5
+    assert oracle.shift_update(np.array([5.0, 0.5]), 0.5) == 0.5
+
+
+def _rank_l_matrix(g):
+    rng = np.random.default_rng(123)
+    m, n = g["m"], g["n"]
+    sig = np.array(g["sigma"])
+    Uo, _ = np.linalg.qr(rng.standard_normal((m, len(sig))))
+    Vo, _ = np.linalg.qr(rng.standard_normal((n, len(sig))))
+    D = (Uo * sig) @ Vo.T
+    return synth.dense_to_csr(D), D, sig
+
+
+@pytest.mark.parametrize("mode", ["R2", "R1", "NONE"])
+def test_rank_l_shift_sequence_golden(mode):
+    g = json.load(open(os.path.join(GOLDEN, "rank_l_shift_sequence.json")))
+    A, D, sig = _rank_l_matrix(g)
+    pol = oracle.SHIFT_NONE if mode == "NONE" else oracle.SHIFT_PAPER
+    pm = oracle.PVE_R1 if mode == "R1" else oracle.PVE_R2
+    r = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, g["k"], g["s"], 10, g["tol"],
+                       seed=4, shift_policy=pol, pve_mode=pm)
+    exp = g[mode]
+    assert r.passes == exp["passes"]
+    assert np.allclose(r.alpha, exp["alpha_used"], rtol=1e-12, atol=1e-12)
+    assert np.allclose(r.ratio, exp["ratio"], rtol=1e-12, atol=1e-12)
+    if "s_hat_pass2" in exp:
+        assert np.allclose(r.s_hat[1], exp["s_hat_pass2"], rtol=1e-12)
+    assert np.allclose(r.S, sig[:g["k"]], rtol=1e-13)
+
+
+# ------------------------------------------------------------------ end to end
+
+def test_rank_l_exact_for_any_pass_count():
+    """rank(A) = l: the sketch spans the row space, sigma_hat = sigma for any p."""
+    g = json.load(open(os.path.join(GOLDEN, "rank_l_shift_sequence.json")))
+    A, D, sig = _rank_l_matrix(g)
+    for p in (0, 1, 3):
+        r = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 4, 2, p, 0.0, seed=9)
+        assert np.allclose(r.S, sig[:4], rtol=1e-13)
+        assert np.allclose(D @ r.V, r.U * r.S, atol=1e-12)
+
+
+def test_small_config_converges_to_lapack():
+    """2000 x 1500 uniform config: with many passes sigma_hat -> sigma (LAPACK)."""
+    A = synth.config_small(np.float64)
+    sv = np.linalg.svd(A.to_dense(), compute_uv=False)
+    r = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 20, 10, 60, 0.0, seed=2001)
+    assert np.abs(r.S - sv[:20]).max() / sv[19] < 1e-10
+    # Prop. 1: computed values lie under the exact ones at every pass count
+    for p in (0, 2, 5):
+        rp = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 20, 10, p, 0.0, seed=2001)
+        assert np.all(rp.S <= sv[:20] * (1 + 1e-12))
+
+
+def test_invariants_props_1_2_3():
+    """Prop. 2 via eq. (14): alpha nondecreasing and alpha_j <= sigma_l^2 / 2.
+    Prop. 3: E_i(j) = S_i + alpha_j <= sigma_i^2.  Prop. 1: S_hat <= sigma.
+    Alg. 3: S descending.  U, V orthonormal."""
+    A = synth.config_small(np.float64)
+    sv = np.linalg.svd(A.to_dense(), compute_uv=False)
+    k, s = 20, 10
+    l = k + s
+    r = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, k, s, 12, 0.0, seed=2001)
+    assert np.all(np.diff(r.alpha) >= 0)
+    assert np.all(r.alpha <= sv[l - 1] ** 2 / 2 * (1 + 1e-12))
+    E = r.s_hat + r.alpha[:, None]
+    assert np.all(E <= (sv[:l] ** 2)[None, :] * (1 + 1e-12))
+    assert np.all(np.diff(r.s_hat, axis=1) <= 0)
+    assert np.all(r.S <= sv[:k] * (1 + 1e-12))
+    assert np.abs(r.U.T @ r.U - np.eye(k)).max() < 1e-12
+    assert np.abs(r.V.T @ r.V - np.eye(k)).max() < 1e-12
+
+
+def test_known_sigma_block_diagonal():
+    """Block-diagonal matrix under random permutations: exact sigma known."""
+    rng = np.random.default_rng(21)
+    blocks = [rng.standard_normal((int(rng.integers(3, 9)), int(rng.integers(2, 6))))
+              * (1.0 / (1 + i)) for i in range(120)]
+    A, sig = synth.block_diag_known_sigma(blocks, seed=5)
+    assert A.m >= A.n
+    r = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 10, 10, 80, 0.0, seed=3)
+    assert np.all(r.S <= sig[:10] * (1 + 1e-12))
+    gaps_ok = (sig[:10] - sig[1:11]) / sig[:10] > 1e-3
+    assert np.abs(r.S - sig[:10])[gaps_ok].max() / sig[0] < 1e-9
+
+
+def test_wide_matrix_orientation():
+    """m < n runs on A^T (Sec. 3.1): U and V exchange roles, sigma unchanged."""
+    A, D = _csr_small(seed=12, m=40, n=70, density=0.4)
+    sv = np.linalg.svd(D, compute_uv=False)
+    r = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 5, 5, 40, 0.0, seed=1)
+    assert r.U.shape == (40, 5) and r.V.shape == (70, 5)
+    assert np.abs(r.S - sv[:5]).max() / sv[0] < 1e-10
+    assert np.allclose(D @ r.V, r.U * r.S, atol=1e-10)
+
+
+def test_tolerance_run_meets_pve():
+    """At tol = 1e-2 the true eps_PVE ends about or below 1e-2 (Sec. 4.3)."""
+    A = synth.config_small(np.float64)
+    sv = np.linalg.svd(A.to_dense(), compute_uv=False)
+    r = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 20, 10, 64, 1e-2, seed=2001)
+    assert r.converged
+    pve, es = oracle.metrics(A.m, A.n, A.row_ptr, A.col, A.val, r.U, r.S, sv)
+    assert pve <= 1e-2
+    # the check cannot pass at the first pass: S' = 0 gives ratio >= 1
+    assert r.ratio[0] >= 1.0
+
+
+def test_theorem_1_bound():
+    """Theorem 1, eq. (15) (with A -> A^T for the m >= n form): the basis Q
+    after p passes satisfies ||A - A Q Q^T|| <= RHS with the shifts used."""
+    rng = np.random.default_rng(31)
+    m, n = 400, 300
+    sig_t = 1.0 / np.sqrt(np.arange(1, n + 1))
+    Uo, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    Vo, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    D = (Uo * sig_t) @ Vo.T
+    A = synth.dense_to_csr(D)
+    k, s, p = 10, 10, 4
+    l = k + s
+    r = oracle.dashsvd(m, n, A.row_ptr, A.col, A.val, k, s, p, 0.0, seed=17)
+    Q = r.Q
+    err = np.linalg.norm(D - D @ Q @ Q.T, 2)
+    # alpha_c for c = 1..p is the shift used in pass c
+    al = r.alpha
+    j = k // 2
+    beta, gamma = 3.0, 3.0
+    sig = sig_t
+    prod1 = np.prod(((sig[j] ** 2 - al) / (sig[j - 1] ** 2 - al)) ** 2)
+    prod2 = np.prod(((sig[k] ** 2 - al) / (sig[j - 1] ** 2 - al)) ** 2)
+    rhs = 2 * math.sqrt((2 * l * l * beta**2 * gamma**2 * prod1 + 1) * sig[j] ** 2 +
+                        (2 * l * (n - k) * beta**2 * gamma**2 * prod2 + 1) * sig[k] ** 2)
+    assert err <= rhs
+    # Corollary 2: the shifted bound is no larger than the unshifted one
+    p1 = np.prod(((sig[j] ** 2) / (sig[j - 1] ** 2)) ** 2 * np.ones(p))
+    p2 = np.prod(((sig[k] ** 2) / (sig[j - 1] ** 2)) ** 2 * np.ones(p))
+    rhs0 = 2 * math.sqrt((2 * l * l * beta**2 * gamma**2 * p1 + 1) * sig[j] ** 2 +
+                         (2 * l * (n - k) * beta**2 * gamma**2 * p2 + 1) * sig[k] ** 2)
+    assert rhs <= rhs0 * (1 + 1e-15)
+
+
+def test_dynamic_shift_beats_no_shift():
+    """Fig. 1's claim: at equal p the dynamically shifted iteration gives
+    lower eps_PVE than the unshifted one (Dense2-style sigma_i = 1/sqrt(i))."""
+    rng = np.random.default_rng(41)
+    m = n = 300
+    sig = 1.0 / np.sqrt(np.arange(1, n + 1))
+    Uo, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    Vo, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    D = (Uo * sig) @ Vo.T
+    A = synth.dense_to_csr(D)
+    wins = 0
+    trials = 10
+    for sd in range(trials):
+        rs = oracle.dashsvd(m, n, A.row_ptr, A.col, A.val, 10, 5, 4, 0.0, seed=100 + sd)
+        r0 = oracle.dashsvd(m, n, A.row_ptr, A.col, A.val, 10, 5, 4, 0.0, seed=100 + sd,
+                            shift_policy=oracle.SHIFT_NONE)
+        e_s, _ = oracle.metrics(m, n, A.row_ptr, A.col, A.val, rs.U, rs.S, sig)
+        e_0, _ = oracle.metrics(m, n, A.row_ptr, A.col, A.val, r0.U, r0.S, sig)
+        wins += e_s <= e_0
+    assert wins >= 9
+
+
+def test_lapack_mirror_trace():
+    """A second route to the same iteration: NumPy with LAPACK eigh in place
+    of the Jacobi eig.  The per-pass S, shift and ratio must agree."""
+    A = synth.uniform_csr(300, 200, 6000, seed=77, dtype=np.float64)
+    D = A.to_dense()
+    k, s, P = 8, 4, 6
+    l = k + s
+    om = oracle.gaussian(55, A.m, l)
+    r = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, k, s, P, 0.0, omega=om)
+
+    def eig_svd(Cm):
+        w, V = np.linalg.eigh(Cm.T @ Cm)
+        w, V = np.maximum(w[::-1], 0.0), V[:, ::-1]
+        S = np.sqrt(w)
+        return Cm @ V / S, S, V
+
+    Q, _, _ = eig_svd(D.T @ om)
+    alpha = 0.0
+    for j in range(P):
+        Q, S, _ = eig_svd(D.T @ (D @ Q) - alpha * Q)
+        assert np.allclose(S, r.s_hat[j], rtol=1e-10)
+        assert alpha == pytest.approx(r.alpha[j], rel=1e-10, abs=1e-14)
+        if S[-1] > alpha:
+            alpha = (S[-1] + alpha) / 2
+    B = D @ Q
+    Ub, Sb, Vb = eig_svd(B)
+    assert np.allclose(Sb[:k], r.S, rtol=1e-11)
+
+
+def test_schedule_policy_with_half_is_paper_rule():
+    """A schedule of 0.5 everywhere reproduces the paper's shift rule."""
+    A = synth.config_small(np.float64)
+    r1 = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 20, 10, 8, 0.0, seed=2001)
+    r2 = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 20, 10, 8, 0.0, seed=2001,
+                        shift_policy=oracle.SHIFT_SCHEDULE, sched=np.full(9, 0.5))
+    assert np.allclose(r1.alpha, r2.alpha, rtol=1e-15, atol=0)
+    assert np.array_equal(r1.S, r2.S)
+
+
+def test_invalid_arguments_rejected():
+    A = synth.config_small(np.float64)
+    with pytest.raises(ValueError):
+        oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 20, 0, 5, 0.0)
+    with pytest.raises(ValueError):
+        oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 1000, 1000, 5, 0.0)
