@@ -1,0 +1,239 @@
+/*
+ * dashsvd.h -- C ABI of the MI355X (gfx950) dashSVD library.
+ *
+ * The library computes a rank-k truncated SVD  A ~ U diag(S) V^T  of a sparse
+ * CSR matrix A (m x n) with randomized, dynamically shifted power iteration
+ * and the per-vector-error (PVE) accuracy control of Feng, Yu, Xie and Tang,
+ * "Faster Randomized SVD with Dynamic Shifts" (dashSVD):
+ *   - Alg. 5 (dashSVD with PVE accuracy control) is the driver; with
+ *     tol == 0 it runs exactly p_max passes, which is Alg. 4;
+ *   - Alg. 3 (eigSVD) orthonormalises each block: Gram matrix, symmetric
+ *     eigendecomposition, rescale, descending order;
+ *   - Sec. 3.1: a matrix with m < n is processed through A^T and U, V are
+ *     exchanged on output.
+ * Every step runs in the library's own HIP kernels on one GPU.  No call
+ * throws; every call returns a dashsvd_status.
+ *
+ * Threading: a handle must be used by one host thread at a time.  Calls are
+ * ordered on the HIP stream given in the options (the null stream if none).
+ */
+#ifndef DASHSVD_H
+#define DASHSVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes.  Negative: error, the handle stays valid and reusable.
+ * Positive: warning, results are valid. */
+typedef int32_t dashsvd_status;
+#define DASHSVD_OK 0
+#define DASHSVD_NOT_CONVERGED 1   /* p_max passes ran without meeting tol (results valid) */
+#define DASHSVD_RANK_DEFICIENT 2  /* some eigSVD column had S <= S_max*sqrt(l*eps) and was zeroed */
+#define DASHSVD_ERR_INVALID_ARG -1
+#define DASHSVD_ERR_BAD_CSR -2    /* row_ptr not monotone / wrong ends, column out of range or not strictly increasing */
+#define DASHSVD_ERR_NONFINITE -3  /* a stored value is NaN or Inf */
+#define DASHSVD_ERR_OOM -4
+#define DASHSVD_ERR_HIP -5        /* a HIP runtime call failed; see dashsvd_last_error */
+#define DASHSVD_ERR_STATE -6      /* call out of order (e.g. get_USV before a successful run) */
+
+/* Element types. */
+#define DASHSVD_F32 0
+#define DASHSVD_F64 1
+#define DASHSVD_BF16 2
+
+/* Precision forms.
+ *   FP32: panels Omega, Q, Y, C in FP32 with FP32 SpMM accumulation; the
+ *         Gram matrix accumulates in FP64 and the l x l eigenproblem is FP64.
+ *   FP64: everything in FP64.
+ *   BF16_PANELS: Omega, Q, Y stored in BF16 (round to nearest even), SpMM
+ *         accumulates FP32, C = A^T Y - alpha Q kept FP32; Gram, eig and the
+ *         final Rayleigh-Ritz step in FP64 / FP32 as in FP32 mode. */
+#define DASHSVD_PREC_FP32 0
+#define DASHSVD_PREC_FP64 1
+#define DASHSVD_PREC_BF16_PANELS 2
+
+/* Shift policies.
+ *   PAPER:    Alg. 5 step 6: if S_l > alpha then alpha = (S_l + alpha)/2.
+ *   NONE:     alpha = 0 throughout (Alg. 1 with eigSVD orthonormalisation).
+ *   FIXED:    the rule applied once after the first pass, then frozen.
+ *   SCHEDULE: after pass j, alpha = max(alpha, c_j * (S_l + alpha)) with
+ *             caller multipliers c_j (c = 0.5 reproduces PAPER); dropped for
+ *             the rest of the run (c = 0.5) once the PVE ratio grows or
+ *             S_{k+1} + alpha shrinks between passes.
+ *   LEARNED:  as SCHEDULE, with the multipliers proposed on the device by the
+ *             handle's MLP from the first two passes (see dashsvd_mlp_*). */
+#define DASHSVD_SHIFT_PAPER 0
+#define DASHSVD_SHIFT_NONE 1
+#define DASHSVD_SHIFT_FIXED 2
+#define DASHSVD_SHIFT_SCHEDULE 3
+#define DASHSVD_SHIFT_LEARNED 4
+
+/* Readings of the PVE check (Alg. 5 step 5 with eq. (19)).
+ *   R2 (default): E_i = S_i + alpha with the alpha that produced S_i, for
+ *       both the current and the previous pass.
+ *   R1: the literal step order, where the stored previous shift is the one
+ *       after its update. */
+#define DASHSVD_PVE_R2 0
+#define DASHSVD_PVE_R1 1
+
+#define DASHSVD_MAX_L 160     /* largest supported l = k + oversampling */
+#define DASHSVD_MAX_TRACE 256 /* passes recorded in dashsvd_info */
+
+/* A sparse matrix in CSR form.  Owned by the caller; must stay valid until
+ * dashsvd_run returns.  row_ptr has m+1 int64 entries with row_ptr[0] = 0
+ * and row_ptr[m] = nnz; col_idx has nnz int32 entries, strictly increasing
+ * within each row and in [0, n); values has nnz entries of value_dtype
+ * (DASHSVD_F32 or DASHSVD_F64).  on_device = 1 means the three pointers are
+ * device memory of the current GPU, 0 means host memory (copied in). */
+typedef struct {
+  int64_t m, n, nnz;
+  const int64_t *row_ptr;
+  const int32_t *col_idx;
+  const void *values;
+  int32_t value_dtype;
+  int32_t on_device;
+} dashsvd_csr;
+
+typedef struct {
+  int32_t precision;      /* DASHSVD_PREC_* (default FP32) */
+  int32_t shift_policy;   /* DASHSVD_SHIFT_* (default PAPER) */
+  int32_t pve_mode;       /* DASHSVD_PVE_* (default R2) */
+  int32_t p_max;          /* pass cap; < 0 selects 64 */
+  uint64_t seed;          /* key of the Philox4x64-10 stream for Omega */
+  void *hip_stream;       /* hipStream_t, NULL = null stream */
+  int32_t long_row;       /* SpMM rows longer than this are split into chunks of this many
+                             nonzeros; <= 0 selects the tuned default */
+  int32_t check_interval; /* passes launched between host reads of the done flag; <= 0: 1 */
+  const double *schedule; /* SHIFT_SCHEDULE multipliers, host, p_max + 1 entries (index = pass) */
+  const void *omega;      /* optional caller-provided Omega (rows = max(m,n), l columns,
+                             row-major, leading dimension l); NULL = draw from seed */
+  int32_t omega_dtype;    /* DASHSVD_F32 / DASHSVD_F64 */
+  int32_t omega_on_device;
+} dashsvd_options;
+
+typedef struct {
+  int32_t passes;          /* N_p: shifted power passes executed */
+  int32_t converged;       /* 1 if the PVE check stopped the loop */
+  int32_t rank_deficient;  /* 1 if some eigSVD zeroed a column */
+  int32_t status;          /* status of the last run */
+  int32_t l;               /* k + oversampling */
+  int32_t learned_fallback;/* 1 if a schedule/learned run fell back to the paper rule */
+  double final_alpha;      /* shift after the last pass */
+  double alpha_used[DASHSVD_MAX_TRACE]; /* shift used in pass j (index j-1) */
+  double ratio[DASHSVD_MAX_TRACE];      /* PVE ratio of pass j */
+  double time_total_ms;    /* host wall time of dashsvd_run */
+  double time_setup_ms;    /* validation, CSR(A^T), SpMM plans, Omega */
+  double time_loop_ms;     /* sketch + power passes */
+  double time_final_ms;    /* final Rayleigh-Ritz and sign normalisation */
+  int64_t long_chunks_A;   /* SpMM chunk tasks of the row-split plan, A side */
+  int64_t long_chunks_AT;  /* same for A^T */
+} dashsvd_info;
+
+typedef struct dashsvd_handle dashsvd_handle;
+
+/* Create a handle.  opt may be NULL (all defaults).  The options are copied. */
+dashsvd_status dashsvd_create(dashsvd_handle **h, const dashsvd_options *opt);
+/* Release a handle and its device workspace.  NULL is ignored. */
+void dashsvd_destroy(dashsvd_handle *h);
+
+/* Replace the options of an existing handle (workspace kept). */
+dashsvd_status dashsvd_set_options(dashsvd_handle *h, const dashsvd_options *opt);
+
+/* Alg. 5 (Alg. 4 when tol == 0): rank k, oversampling p (l = k + p),
+ * tolerance tol of the PVE check.  Requires 1 <= k, 1 <= p (the check reads
+ * S_{k+1}), k + p <= min(m, n), k + p <= DASHSVD_MAX_L, tol >= 0.  Returns
+ * OK, NOT_CONVERGED (tol > 0 and p_max passes ran), RANK_DEFICIENT, or an
+ * error.  Results stay in the handle until the next run or destroy. */
+dashsvd_status dashsvd_run(dashsvd_handle *h, const dashsvd_csr *A, int32_t k, int32_t p,
+                           double tol);
+
+/* Copy the last run's results: U (m x k, row-major, leading dimension ldu),
+ * S (k, descending), V (n x k, leading dimension ldv), each in dtype
+ * (DASHSVD_F32 or DASHSVD_F64; S always double).  on_device selects device
+ * or host destination pointers.  Any pointer may be NULL to skip it.  Signs:
+ * the entry of largest magnitude of each V column is positive (lowest row on
+ * ties), U columns flipped alike.  Synchronises the stream. */
+dashsvd_status dashsvd_get_USV(dashsvd_handle *h, void *U, int64_t ldu, double *S, void *V,
+                               int64_t ldv, int32_t dtype, int32_t on_device);
+
+dashsvd_status dashsvd_get_info(dashsvd_handle *h, dashsvd_info *out);
+
+/* Per-pass S (the l singular values of each pass's block C, descending):
+ * writes min(passes, max_passes) rows of l doubles to host memory. */
+dashsvd_status dashsvd_get_trace(dashsvd_handle *h, double *s_hat, int32_t max_passes);
+
+/* Device bytes a run with these arguments needs (workspace of the handle). */
+dashsvd_status dashsvd_workspace_size(const dashsvd_csr *A, int32_t k, int32_t p,
+                                      int32_t precision, size_t *bytes);
+
+const char *dashsvd_status_string(dashsvd_status s);
+/* Detail of the last error on this handle (or of the last failed create when
+ * h is NULL).  Valid until the next call on the handle. */
+const char *dashsvd_last_error(const dashsvd_handle *h);
+
+/* ---------------------------------------------------------------------
+ * Kernel-level entry points.  They run one step of the path on device
+ * buffers the caller owns, on the given stream, and return after the work
+ * is queued (no synchronisation).  They exist so each step can be checked
+ * alone; the solver calls the same kernels.
+ * ------------------------------------------------------------------- */
+
+/* Alg. 5 step 1 (randn): out[i*ld + j] for i < rows, j < cols, element
+ * e = i*cols + j from Philox4x64-10 keyed (seed, 0), counter (b+1, 0, 0, 0)
+ * for block b, raw words 2t, 2t+1 -> Box-Muller pair t = e/2.  dtype F32,
+ * F64 or BF16 (rounded to nearest even from FP64). */
+dashsvd_status dashsvd_k_gaussian(uint64_t seed, int64_t rows, int64_t cols, void *out,
+                                  int64_t ld, int32_t dtype, void *stream);
+
+/* Raw Philox words: out[w] = word w of the stream keyed (seed, 0). */
+dashsvd_status dashsvd_k_philox_raw(uint64_t seed, int64_t nwords, uint64_t *out, void *stream);
+
+/* CSR of A^T (the transposed operand of Alg. 5 steps 2 and 4): rows of A^T
+ * list their columns in increasing order.  All pointers are device memory;
+ * rowT has n+1 entries, colT/valT nnz.  values dtype as given (F32/F64).
+ * Validates A first (status BAD_CSR / NONFINITE).  Synchronises the stream. */
+dashsvd_status dashsvd_k_transpose(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr,
+                                   const int32_t *col, const void *val, int32_t dtype,
+                                   int64_t *rowT, int32_t *colT, void *valT, void *stream);
+
+/* Y = A X or, with alpha != NULL, Y = A X - (*alpha) Q (the shifted block of
+ * Alg. 5 step 4), with the library's row-split + long-row-chunk SpMM.
+ * A: CSR rows x cols on device, values F32 (panel types F32/BF16) or F64
+ * (F64 panels).  X: cols x ldx, Y: rows x ldy, Q: rows x ldq; the first l
+ * columns are used.  xdtype / ydtype: element types of X/Q and Y.  long_row
+ * <= 0 selects the default.  Synchronises the stream (plan sizing). */
+dashsvd_status dashsvd_k_spmm(int64_t rows, int64_t cols, int64_t nnz, const int64_t *row_ptr,
+                              const int32_t *col, const void *val, const void *X, int64_t ldx,
+                              int32_t xdtype, void *Y, int64_t ldy, int32_t ydtype, int32_t l,
+                              const void *Q, int64_t ldq, const double *alpha, int32_t long_row,
+                              void *stream);
+
+/* G (l x l, FP64, row-major, full symmetric) = C^T C for C r x l (ldc),
+ * C dtype F32 or F64; FP64 accumulation (Alg. 3 step 1). */
+dashsvd_status dashsvd_k_gram(int64_t r, int32_t l, const void *C, int64_t ldc, int32_t cdtype,
+                              double *G, void *stream);
+
+/* Symmetric eigendecomposition of G (l x l FP64, device) by the library's
+ * Jacobi kernel: S (l, descending sqrt of the clamped eigenvalues), Vs
+ * (l x l, column i = eigenvector of S_i), W = Vs diag(1/S) with zeroed
+ * columns where S <= S_max*sqrt(l*eps) (Alg. 3 steps 1-4).  sweeps
+ * (optional, device int) receives the sweep count. */
+dashsvd_status dashsvd_k_eig(int32_t l, const double *G, double *S, double *Vs, double *W,
+                             int32_t *sweeps, void *stream);
+
+/* Out (r x c, ldo, odtype) = C (r x l, ldc, cdtype) * W (l x c, FP64,
+ * row-major, leading dimension ldw): the rescale U = C V S^-1 of Alg. 3
+ * step 3 and the final products of Alg. 5.  Columns c..ldo-1 of Out are
+ * written as zero. */
+dashsvd_status dashsvd_k_rescale(int64_t r, int32_t l, const void *C, int64_t ldc, int32_t cdtype,
+                                 const double *W, int64_t ldw, int32_t c, void *Out, int64_t ldo,
+                                 int32_t odtype, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DASHSVD_H */

@@ -1,0 +1,226 @@
+// Internal declarations shared by the HIP sources of the dashSVD library.
+// Target: gfx950 (CDNA4), wave64.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace dsv {
+
+constexpr int kWave = 64;
+constexpr int kMaxL = 160;
+
+// ------------------------------------------------------------------ bf16
+// Storage-only BF16: round to nearest even on the way in, exact on the way out.
+struct bf16 {
+  uint16_t x;
+};
+
+__device__ __forceinline__ float bf2f(bf16 v) { return __uint_as_float((uint32_t)v.x << 16); }
+__device__ __forceinline__ bf16 f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  bf16 r;
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) {
+    r.x = (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+  } else {
+    u += 0x7fffu + ((u >> 16) & 1u);
+    r.x = (uint16_t)(u >> 16);
+  }
+  return r;
+}
+
+// ------------------------------------------------------------------ element I/O
+template <typename T> struct elem;
+template <> struct elem<float> {
+  __device__ static __forceinline__ float ld(const float *p) { return *p; }
+  __device__ static __forceinline__ void st(float *p, float v) { *p = v; }
+};
+template <> struct elem<double> {
+  __device__ static __forceinline__ double ld(const double *p) { return *p; }
+  __device__ static __forceinline__ void st(double *p, double v) { *p = v; }
+};
+template <> struct elem<bf16> {
+  __device__ static __forceinline__ float ld(const bf16 *p) { return bf2f(*p); }
+  __device__ static __forceinline__ void st(bf16 *p, float v) { *p = f2bf(v); }
+};
+
+// Vector of 16 bytes of T, converted to/from the accumulator type A.
+// N = 16 / sizeof(T) elements.
+template <typename T, typename A> struct vec16;
+template <typename A> struct vec16<float, A> {
+  static constexpr int N = 4;
+  __device__ static __forceinline__ void load(const float *p, A *o) {
+    float4 v = *reinterpret_cast<const float4 *>(p);
+    o[0] = (A)v.x; o[1] = (A)v.y; o[2] = (A)v.z; o[3] = (A)v.w;
+  }
+  __device__ static __forceinline__ void store(float *p, const A *o) {
+    float4 v;
+    v.x = (float)o[0]; v.y = (float)o[1]; v.z = (float)o[2]; v.w = (float)o[3];
+    *reinterpret_cast<float4 *>(p) = v;
+  }
+};
+template <typename A> struct vec16<double, A> {
+  static constexpr int N = 2;
+  __device__ static __forceinline__ void load(const double *p, A *o) {
+    double2 v = *reinterpret_cast<const double2 *>(p);
+    o[0] = (A)v.x; o[1] = (A)v.y;
+  }
+  __device__ static __forceinline__ void store(double *p, const A *o) {
+    double2 v;
+    v.x = (double)o[0]; v.y = (double)o[1];
+    *reinterpret_cast<double2 *>(p) = v;
+  }
+};
+template <typename A> struct vec16<bf16, A> {
+  static constexpr int N = 8;
+  __device__ static __forceinline__ void load(const bf16 *p, A *o) {
+    uint4 v = *reinterpret_cast<const uint4 *>(p);
+    uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      o[2 * i] = (A)__uint_as_float(w[i] << 16);
+      o[2 * i + 1] = (A)__uint_as_float(w[i] & 0xffff0000u);
+    }
+  }
+  __device__ static __forceinline__ void store(bf16 *p, const A *o) {
+    uint32_t w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      uint32_t lo = f2bf((float)o[2 * i]).x, hi = f2bf((float)o[2 * i + 1]).x;
+      w[i] = lo | (hi << 16);
+    }
+    *reinterpret_cast<uint4 *>(p) = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+};
+
+// Store N elements of A into a row of T (N = the lane width of the panel
+// type that defined the column mapping; may differ from 16 / sizeof(T)).
+template <typename T, typename A, int N> __device__ __forceinline__ void store_n(T *p, const A *o) {
+  constexpr int M = vec16<T, A>::N;
+  if constexpr (N % M == 0) {
+#pragma unroll
+    for (int i = 0; i < N; i += M) vec16<T, A>::store(p + i, o + i);
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) elem<T>::st(p + i, o[i]);
+  }
+}
+template <typename T, typename A, int N> __device__ __forceinline__ void load_n(const T *p, A *o) {
+  constexpr int M = vec16<T, A>::N;
+  if constexpr (N % M == 0) {
+#pragma unroll
+    for (int i = 0; i < N; i += M) vec16<T, A>::load(p + i, o + i);
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) o[i] = (A)elem<T>::ld(p + i);
+  }
+}
+
+// ------------------------------------------------------------------ plans
+// Row-split SpMM plan: rows longer than long_row nonzeros are cut into
+// chunks of long_row; each chunk writes a partial row, then one task per
+// long row sums its chunks in order (deterministic).
+struct ChunkTask {
+  int64_t begin, end;
+};
+struct LongRow {
+  int64_t row, first;
+  int64_t nch;
+};
+
+// Device-resident solver state (one per solve).
+struct SolverState {
+  double alpha;       // shift used by the next pass
+  double alpha_prev;  // alpha' of the PVE check
+  double prev_ratio;
+  double prev_ek1;
+  double ratio;       // ratio of the last pass
+  int32_t pass;       // passes executed
+  int32_t done;       // set when the PVE check passes
+  int32_t converged;
+  int32_t deficient;
+  int32_t sched_off;  // schedule dropped (guard)
+  int32_t learned_ready;
+  int32_t pad[2];
+};
+
+// ------------------------------------------------------------------ launchers
+// (defined in the .hip files; all asynchronous on `st`)
+hipError_t launch_gaussian(uint64_t seed, int64_t rows, int64_t cols, void *out, int64_t ld,
+                           int dtype, hipStream_t st);
+hipError_t launch_philox_raw(uint64_t seed, int64_t nwords, uint64_t *out, hipStream_t st);
+
+hipError_t launch_scan_i64(const int64_t *in, int64_t n, int64_t *out, int64_t *tmp, hipStream_t st);
+size_t scan_tmp_elems(int64_t n);
+
+hipError_t launch_validate(int64_t m, int64_t n, int64_t nnz, const int64_t *rp, const int32_t *col,
+                           const void *val, int dtype, int64_t *colcnt, int32_t *rowidx,
+                           int32_t *flags, hipStream_t st);
+hipError_t launch_transpose_scatter(int64_t nnz, const int32_t *col, const int32_t *rowidx,
+                                    const int64_t *rowT, int32_t *cursor, int32_t *tmp_row,
+                                    int32_t *tmp_src, hipStream_t st);
+hipError_t launch_transpose_classify(int64_t n, const int64_t *rowT, const int32_t *tmp_row,
+                                     const int32_t *tmp_src, const void *val, int dtype,
+                                     int32_t *colT, void *valT, int32_t *lists, int32_t *counts,
+                                     hipStream_t st);
+hipError_t launch_transpose_sort(int64_t m, int64_t n, const int64_t *rowT, const int32_t *tmp_row,
+                                 const int32_t *tmp_src, const void *val, int dtype, int32_t *colT,
+                                 void *valT, const int32_t *lists, const int32_t *counts_host,
+                                 uint32_t *bitmap_ws, int32_t *prefix_ws, int nblk_large,
+                                 hipStream_t st);
+int64_t transpose_bitmap_words(int64_t m);
+
+hipError_t launch_plan_count(int64_t R, const int64_t *rp, int32_t long_row, int64_t *nch,
+                             hipStream_t st);
+hipError_t launch_plan_fill(int64_t R, const int64_t *rp, int32_t long_row, const int64_t *off,
+                            ChunkTask *tasks, LongRow *longs, int32_t *nlong, hipStream_t st);
+
+// SpMM: Y = A X (- alpha Q).  dtypes: 0 f32, 1 f64, 2 bf16.
+hipError_t launch_spmm(int64_t R, const int64_t *rp, const int32_t *col, const void *val, int vdtype,
+                       const void *X, int64_t ldx, int xdtype, void *Y, int64_t ldy, int ydtype,
+                       int ld_cols, int64_t n_chunks, const ChunkTask *tasks, int64_t n_long,
+                       const LongRow *longs, void *partial, int32_t long_row, const void *Q,
+                       int64_t ldq, const double *alpha, const int32_t *done, hipStream_t st);
+
+hipError_t launch_gram(int64_t r, int l, const void *C, int64_t ldc, int cdtype, double *partial,
+                       int nblocks, double *G, const int32_t *done, hipStream_t st);
+int gram_blocks(int64_t r, int l);
+size_t gram_partial_elems(int nblocks, int l);
+
+// Jacobi eigensolver + eigSVD tail.  mode: 0 = plain eig (kernel entry),
+// 1 = sketch, 2 = power pass (PVE check + shift update), 3 = final.
+struct EigArgs {
+  int l, k;
+  const double *G;
+  double *S;        // l, descending
+  double *Vs;       // l x l, eigenvectors in descending order (may be null)
+  double *W;        // l x l, Vs diag(1/S), zeroed columns below threshold
+  int32_t *sweeps;  // optional
+  SolverState *state;
+  int mode;
+  int pve_mode;     // 0 = R2, 1 = R1
+  int policy;       // shift policy
+  double tol;
+  double *Sprev;    // l
+  double *trace_alpha, *trace_ratio, *trace_s;  // [cap], [cap], [cap*l]
+  int trace_cap;
+  const double *sched;  // device multipliers (SCHEDULE / LEARNED), may be null
+  int sched_len;
+};
+hipError_t launch_eig(const EigArgs &a, hipStream_t st);
+
+hipError_t launch_rescale(int64_t r, int l, const void *C, int64_t ldc, int cdtype, const double *W,
+                          int64_t ldw, int c, void *Out, int64_t ldo, int odtype,
+                          const int32_t *done, hipStream_t st);
+
+// pmax: nblk*k doubles, pidx: nblk*k int64 (workspace)
+hipError_t launch_sign_fix(int64_t rowsV, int64_t rowsU, int k, void *V, int64_t ldv, void *U,
+                           int64_t ldu, int dtype, void *pmax, void *pidx, int nblk,
+                           hipStream_t st);
+hipError_t launch_convert(const void *in, int idtype, void *out, int odtype, int64_t n,
+                          hipStream_t st);
+hipError_t launch_copy2d(const void *in, int64_t ldi, int idtype, void *out, int64_t ldo,
+                         int odtype, int64_t rows, int cols, hipStream_t st);
+hipError_t launch_fill_zero_i32(int32_t *p, int64_t n, hipStream_t st);
+
+}  // namespace dsv

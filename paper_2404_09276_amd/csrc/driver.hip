@@ -1,0 +1,789 @@
+// C ABI and host driver of the dashSVD library (Alg. 5 of the paper, with
+// Alg. 3 for every orthonormalisation and Alg. 4 as the tol = 0 case).
+//
+// The driver is a stream-ordered sequence of the library's kernels:
+//   setup   : CSR validation -> CSR(A^T) -> SpMM plans -> Omega
+//   sketch  : Y0 = M^T Omega -> eigSVD -> Q                 (Alg. 5 step 2)
+//   pass j  : Y = M Q ; C = M^T Y - alpha Q ; G = C^T C ;
+//             eig + PVE check + shift update (device) ; Q = C W   (steps 4-7)
+//   final   : B = M Q ; eigSVD(B) ; U = B W_B(:,1:k) ; V = Q V_B(:,1:k) (9-11)
+// where M = A if m >= n and M = A^T otherwise (Sec. 3.1).  The shift, the
+// previous singular values and the done flag live on the device; the host
+// reads the 4-byte done flag once every check_interval passes, and passes
+// launched after the flag is set return at their first instruction.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dashsvd.h"
+#include "common.h"
+
+using namespace dsv;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr int kDefaultLongRow = 256;
+constexpr int kDefaultPmax = 64;
+
+size_t dsz(int dt) { return dt == DASHSVD_F64 ? 8 : (dt == DASHSVD_BF16 ? 2 : 4); }
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// Bump allocator over one device arena.
+struct Arena {
+  char *base = nullptr;
+  size_t cap = 0, used = 0;
+  bool measuring = false;
+  void reset(bool measure) {
+    used = 0;
+    measuring = measure;
+  }
+  void *take(size_t bytes) {
+    const size_t off = (size_t)round_up((int64_t)used, 256);
+    used = off + (size_t)round_up((int64_t)bytes, 256);
+    if (measuring) return nullptr;
+    return base + off;
+  }
+};
+
+struct Plan {
+  int64_t R = 0;
+  int64_t n_chunks = 0, n_long = 0;
+  int64_t *nch = nullptr, *off = nullptr;
+  ChunkTask *tasks = nullptr;
+  LongRow *longs = nullptr;
+  int32_t *nlong = nullptr;
+  void *partial = nullptr;
+};
+
+}  // namespace
+
+struct dashsvd_handle {
+  dashsvd_options opt;
+  std::vector<double> sched;
+  std::string err;
+  hipStream_t st = nullptr;
+  Arena ar;
+  // results of the last run (device pointers into the arena)
+  bool have = false;
+  int64_t m = 0, n = 0;
+  int k = 0, l = 0;
+  int out_dt = DASHSVD_F32;
+  void *U = nullptr, *V = nullptr;
+  double *S = nullptr;
+  double *trace_s = nullptr;
+  int trace_cap = 0;
+  dashsvd_info info;
+};
+
+namespace {
+
+dashsvd_status fail(dashsvd_handle *h, dashsvd_status s, const std::string &what) {
+  if (h) h->err = what;
+  else g_create_error = what;
+  return s;
+}
+
+#define HIPCHK(x)                                                                              \
+  do {                                                                                         \
+    hipError_t e_ = (x);                                                                       \
+    if (e_ != hipSuccess)                                                                      \
+      return fail(h, DASHSVD_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+void default_options(dashsvd_options *o) {
+  std::memset(o, 0, sizeof(*o));
+  o->precision = DASHSVD_PREC_FP32;
+  o->shift_policy = DASHSVD_SHIFT_PAPER;
+  o->pve_mode = DASHSVD_PVE_R2;
+  o->p_max = -1;
+  o->omega_dtype = DASHSVD_F64;
+}
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+dashsvd_status ensure_arena(dashsvd_handle *h, size_t bytes) {
+  if (bytes <= h->ar.cap) return DASHSVD_OK;
+  if (h->ar.base) {
+    (void)hipStreamSynchronize(h->st);
+    (void)hipFree(h->ar.base);
+    h->ar.base = nullptr;
+    h->ar.cap = 0;
+    h->have = false;
+  }
+  void *p = nullptr;
+  const size_t want = bytes + bytes / 16;
+  if (hipMalloc(&p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(h, DASHSVD_ERR_OOM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+  }
+  h->ar.base = (char *)p;
+  h->ar.cap = want;
+  return DASHSVD_OK;
+}
+
+// Row-split plan of a CSR with R rows (two phases around a host read).
+dashsvd_status plan_alloc(dashsvd_handle *h, Arena &ar, Plan &p, int64_t R, int64_t nnz, int32_t T,
+                          int ld, size_t acc_sz) {
+  p.R = R;
+  const int64_t max_chunks = 2 * (nnz / T) + 1;
+  const int64_t max_long = nnz / T + 1;
+  p.nch = (int64_t *)ar.take(sizeof(int64_t) * (size_t)(R + 1));
+  p.off = (int64_t *)ar.take(sizeof(int64_t) * (size_t)(R + 2));
+  p.tasks = (ChunkTask *)ar.take(sizeof(ChunkTask) * (size_t)max_chunks);
+  p.longs = (LongRow *)ar.take(sizeof(LongRow) * (size_t)max_long);
+  p.nlong = (int32_t *)ar.take(sizeof(int32_t) * 4);
+  p.partial = ar.take(acc_sz * (size_t)ld * (size_t)max_chunks);
+  (void)h;
+  return DASHSVD_OK;
+}
+
+struct RunBufs {
+  // CSR of M and M^T on device (compute value type)
+  const int64_t *rpA = nullptr;
+  const int32_t *colA = nullptr;
+  const void *valA = nullptr;
+  int64_t *rpT = nullptr;
+  int32_t *colT = nullptr;
+  void *valT = nullptr;
+  // transposition temporaries
+  int64_t *colcnt = nullptr;
+  int32_t *rowidx = nullptr, *cursor = nullptr, *tmp_row = nullptr, *tmp_src = nullptr;
+  int32_t *lists = nullptr, *counts = nullptr, *flags = nullptr;
+  uint32_t *bitmap = nullptr;
+  int32_t *prefix = nullptr;
+  int64_t *scan_tmp = nullptr;
+  int nblk_large = 0;
+  Plan planM, planT;
+  // panels
+  void *Y = nullptr;   // M_m x ld, panel type (also Omega)
+  void *Q = nullptr;   // M_n x ld, panel type
+  void *C = nullptr;   // M_n x ld, C type (f32 / f64)
+  void *B = nullptr;   // M_m x ld, C type (final block)
+  double *gpart = nullptr, *G = nullptr, *W = nullptr, *Vs = nullptr, *S = nullptr, *Sprev = nullptr;
+  SolverState *state = nullptr;
+  double *tr_alpha = nullptr, *tr_ratio = nullptr, *tr_s = nullptr;
+  double *sched = nullptr;
+  void *Uo = nullptr, *Vo = nullptr;
+  double *So = nullptr;
+  void *sgn_max = nullptr, *sgn_idx = nullptr;
+  void *omega_dev = nullptr;
+};
+
+}  // namespace
+
+// ===================================================================== C ABI
+extern "C" {
+
+const char *dashsvd_status_string(dashsvd_status s) {
+  switch (s) {
+    case DASHSVD_OK: return "ok";
+    case DASHSVD_NOT_CONVERGED: return "not converged within p_max passes (results valid)";
+    case DASHSVD_RANK_DEFICIENT: return "rank deficient block: some columns zeroed (results valid)";
+    case DASHSVD_ERR_INVALID_ARG: return "invalid argument";
+    case DASHSVD_ERR_BAD_CSR: return "malformed CSR matrix";
+    case DASHSVD_ERR_NONFINITE: return "non-finite value in the matrix";
+    case DASHSVD_ERR_OOM: return "out of device memory";
+    case DASHSVD_ERR_HIP: return "HIP runtime error";
+    case DASHSVD_ERR_STATE: return "call out of order";
+    default: return "unknown status";
+  }
+}
+
+const char *dashsvd_last_error(const dashsvd_handle *h) {
+  return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+dashsvd_status dashsvd_set_options(dashsvd_handle *h, const dashsvd_options *opt) {
+  if (!h) return DASHSVD_ERR_INVALID_ARG;
+  dashsvd_options o;
+  default_options(&o);
+  if (opt) o = *opt;
+  if (o.precision < 0 || o.precision > 2) return fail(h, DASHSVD_ERR_INVALID_ARG, "precision");
+  if (o.shift_policy < 0 || o.shift_policy > 4) return fail(h, DASHSVD_ERR_INVALID_ARG, "shift_policy");
+  if (o.pve_mode < 0 || o.pve_mode > 1) return fail(h, DASHSVD_ERR_INVALID_ARG, "pve_mode");
+  if (o.p_max < 0) o.p_max = kDefaultPmax;
+  if (o.p_max > 100000) return fail(h, DASHSVD_ERR_INVALID_ARG, "p_max too large");
+  h->sched.clear();
+  if (o.shift_policy == DASHSVD_SHIFT_SCHEDULE) {
+    if (!o.schedule) return fail(h, DASHSVD_ERR_INVALID_ARG, "SCHEDULE policy needs options.schedule");
+    h->sched.assign(o.schedule, o.schedule + o.p_max + 1);
+  }
+  o.schedule = nullptr;
+  h->opt = o;
+  h->st = (hipStream_t)o.hip_stream;
+  return DASHSVD_OK;
+}
+
+dashsvd_status dashsvd_create(dashsvd_handle **out, const dashsvd_options *opt) {
+  if (!out) return fail(nullptr, DASHSVD_ERR_INVALID_ARG, "null handle pointer");
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    return fail(nullptr, DASHSVD_ERR_HIP, "no HIP device available");
+  }
+  dashsvd_handle *h = new dashsvd_handle();
+  std::memset(&h->info, 0, sizeof(h->info));
+  dashsvd_status s = dashsvd_set_options(h, opt);
+  if (s != DASHSVD_OK) {
+    g_create_error = h->err;
+    delete h;
+    return s;
+  }
+  *out = h;
+  return DASHSVD_OK;
+}
+
+void dashsvd_destroy(dashsvd_handle *h) {
+  if (!h) return;
+  if (h->ar.base) {
+    (void)hipStreamSynchronize(h->st);
+    (void)hipFree(h->ar.base);
+  }
+  delete h;
+}
+
+static dashsvd_status check_args(dashsvd_handle *h, const dashsvd_csr *A, int32_t k, int32_t p, double tol) {
+  if (!A) return fail(h, DASHSVD_ERR_INVALID_ARG, "null matrix");
+  if (A->m < 1 || A->n < 1 || A->nnz < 0) return fail(h, DASHSVD_ERR_INVALID_ARG, "matrix dimensions");
+  if (A->m > INT32_MAX || A->n > INT32_MAX || A->nnz > INT32_MAX)
+    return fail(h, DASHSVD_ERR_INVALID_ARG, "matrix too large for 32-bit indices");
+  if (A->value_dtype != DASHSVD_F32 && A->value_dtype != DASHSVD_F64)
+    return fail(h, DASHSVD_ERR_INVALID_ARG, "value_dtype");
+  if (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->values)))
+    return fail(h, DASHSVD_ERR_INVALID_ARG, "null CSR array");
+  if (k < 1) return fail(h, DASHSVD_ERR_INVALID_ARG, "k must be >= 1");
+  if (p < 1) return fail(h, DASHSVD_ERR_INVALID_ARG, "oversampling must be >= 1 (the check reads S_{k+1})");
+  const int64_t mn = A->m < A->n ? A->m : A->n;
+  if ((int64_t)k + p > mn) return fail(h, DASHSVD_ERR_INVALID_ARG, "k + oversampling exceeds min(m, n)");
+  if (k + p > DASHSVD_MAX_L) return fail(h, DASHSVD_ERR_INVALID_ARG, "k + oversampling exceeds DASHSVD_MAX_L");
+  if (!(tol >= 0.0) || std::isinf(tol)) return fail(h, DASHSVD_ERR_INVALID_ARG, "tol must be finite and >= 0");
+  return DASHSVD_OK;
+}
+
+dashsvd_status dashsvd_workspace_size(const dashsvd_csr *A, int32_t k, int32_t p, int32_t precision,
+                                      size_t *bytes);
+
+static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t k, int32_t p, double tol,
+                               bool measure_only, size_t *measured) {
+  const double t0 = now_ms();
+  const int prec = h->opt.precision;
+  const int vdt = prec == DASHSVD_PREC_FP64 ? DASHSVD_F64 : DASHSVD_F32;  // compute value type
+  const int pdt = prec == DASHSVD_PREC_FP64 ? DASHSVD_F64 : (prec == DASHSVD_PREC_BF16_PANELS ? DASHSVD_BF16 : DASHSVD_F32);
+  const int cdt = prec == DASHSVD_PREC_FP64 ? DASHSVD_F64 : DASHSVD_F32;  // C, B, U, V type
+  const size_t accsz = prec == DASHSVD_PREC_FP64 ? 8 : 4;
+  const int64_t m = A->m, n = A->n, nnz = A->nnz;
+  const bool wide = m < n;
+  const int64_t Mm = wide ? n : m, Mn = wide ? m : n;
+  const int l = k + p;
+  const int ld = (int)round_up(l, 8);
+  const int32_t T = h->opt.long_row > 0 ? h->opt.long_row : kDefaultLongRow;
+  const int pmax = h->opt.p_max;
+  const int cap = pmax > 0 ? pmax : 1;
+  hipStream_t st = h->st;
+
+  // ---------------------------------------------------------------- arena
+  Arena &ar = h->ar;
+  RunBufs b;
+  ar.reset(measure_only || ar.base == nullptr);
+  if (!measure_only) {
+    size_t need = 0;
+    run_impl(h, A, k, p, tol, true, &need);
+    dashsvd_status s = ensure_arena(h, need);
+    if (s != DASHSVD_OK) return s;
+    ar.reset(false);
+  }
+  h->have = false;
+  const bool need_copy_struct = !A->on_device;
+  const bool need_copy_val = !A->on_device || A->value_dtype != vdt;
+  int64_t *rp_in = need_copy_struct ? (int64_t *)ar.take(8 * (size_t)(m + 1)) : nullptr;
+  int32_t *col_in = need_copy_struct ? (int32_t *)ar.take(4 * (size_t)(nnz + 1)) : nullptr;
+  void *val_raw = !A->on_device ? ar.take(dsz(A->value_dtype) * (size_t)(nnz + 1)) : nullptr;
+  void *val_in = need_copy_val ? ar.take(dsz(vdt) * (size_t)(nnz + 1)) : nullptr;
+  b.rpT = (int64_t *)ar.take(8 * (size_t)(n + 1));
+  b.colT = (int32_t *)ar.take(4 * (size_t)(nnz + 1));
+  b.valT = ar.take(dsz(vdt) * (size_t)(nnz + 1));
+  b.colcnt = (int64_t *)ar.take(8 * (size_t)(n + 1));
+  b.rowidx = (int32_t *)ar.take(4 * (size_t)(nnz + 1));
+  b.cursor = (int32_t *)ar.take(4 * (size_t)(n + 1));
+  b.tmp_row = (int32_t *)ar.take(4 * (size_t)(nnz + 1));
+  b.tmp_src = (int32_t *)ar.take(4 * (size_t)(nnz + 1));
+  b.lists = (int32_t *)ar.take(4 * (size_t)(3 * n + 1));
+  b.counts = (int32_t *)ar.take(4 * 8);
+  b.flags = b.counts + 4;
+  const int64_t words = transpose_bitmap_words(m);
+  b.nblk_large = 256;
+  b.bitmap = (uint32_t *)ar.take(4 * (size_t)words * b.nblk_large);
+  b.prefix = (int32_t *)ar.take(4 * (size_t)words * b.nblk_large);
+  const int64_t scan_n = (m > n ? m : n) + 1;
+  b.scan_tmp = (int64_t *)ar.take(8 * scan_tmp_elems(scan_n));
+  plan_alloc(h, ar, b.planM, Mm, nnz, T, ld, accsz);
+  plan_alloc(h, ar, b.planT, Mn, nnz, T, ld, accsz);
+  b.Y = ar.take(dsz(pdt) * (size_t)Mm * ld);
+  b.Q = ar.take(dsz(pdt) * (size_t)Mn * ld);
+  b.C = ar.take(dsz(cdt) * (size_t)Mn * ld);
+  b.B = pdt == cdt ? b.Y : ar.take(dsz(cdt) * (size_t)Mm * ld);
+  const int nb_n = gram_blocks(Mn, l), nb_m = gram_blocks(Mm, l);
+  b.gpart = (double *)ar.take(8 * gram_partial_elems(nb_n > nb_m ? nb_n : nb_m, l));
+  b.G = (double *)ar.take(8 * (size_t)l * l);
+  b.W = (double *)ar.take(8 * (size_t)l * l);
+  b.Vs = (double *)ar.take(8 * (size_t)l * l);
+  b.S = (double *)ar.take(8 * (size_t)l);
+  b.Sprev = (double *)ar.take(8 * (size_t)l);
+  b.state = (SolverState *)ar.take(sizeof(SolverState));
+  b.tr_alpha = (double *)ar.take(8 * (size_t)cap);
+  b.tr_ratio = (double *)ar.take(8 * (size_t)cap);
+  b.tr_s = (double *)ar.take(8 * (size_t)cap * l);
+  b.sched = (double *)ar.take(8 * (size_t)(pmax + 2));
+  b.Uo = ar.take(dsz(cdt) * (size_t)Mm * k);
+  b.Vo = ar.take(dsz(cdt) * (size_t)Mn * k);
+  const int sgn_blk = 256;
+  b.sgn_max = ar.take(8 * (size_t)sgn_blk * k);
+  b.sgn_idx = ar.take(8 * (size_t)sgn_blk * k);
+  if (h->opt.omega && !h->opt.omega_on_device)
+    b.omega_dev = ar.take(dsz(h->opt.omega_dtype) * (size_t)Mm * l);
+  if (measure_only) {
+    *measured = ar.used;
+    return DASHSVD_OK;
+  }
+
+  // ---------------------------------------------------------------- setup
+  // control buffers start at zero; panels need no clearing (pad columns are
+  // never read into the first l columns)
+  HIPCHK(hipMemsetAsync(b.colcnt, 0, 8 * (size_t)(n + 1), st));
+  HIPCHK(hipMemsetAsync(b.cursor, 0, 4 * (size_t)(n + 1), st));
+  HIPCHK(hipMemsetAsync(b.counts, 0, 4 * 8, st));
+  HIPCHK(hipMemsetAsync(b.planM.nlong, 0, 16, st));
+  HIPCHK(hipMemsetAsync(b.planT.nlong, 0, 16, st));
+  HIPCHK(hipMemsetAsync(b.state, 0, sizeof(SolverState), st));
+  HIPCHK(hipMemsetAsync(b.Sprev, 0, 8 * (size_t)l, st));
+  HIPCHK(hipMemsetAsync(b.tr_alpha, 0, 8 * (size_t)cap, st));
+  HIPCHK(hipMemsetAsync(b.tr_ratio, 0, 8 * (size_t)cap, st));
+  const int64_t *rpA = A->on_device ? A->row_ptr : rp_in;
+  const int32_t *colA = A->on_device ? A->col_idx : col_in;
+  const void *val_src = A->on_device ? A->values : val_raw;
+  if (!A->on_device) {
+    HIPCHK(hipMemcpyAsync(rp_in, A->row_ptr, 8 * (size_t)(m + 1), hipMemcpyHostToDevice, st));
+    if (nnz > 0) {
+      HIPCHK(hipMemcpyAsync(col_in, A->col_idx, 4 * (size_t)nnz, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(val_raw, A->values, dsz(A->value_dtype) * (size_t)nnz, hipMemcpyHostToDevice, st));
+    }
+  }
+  const void *valA = val_src;
+  if (need_copy_val) {
+    HIPCHK(launch_convert(val_src, A->value_dtype, val_in, vdt, nnz, st));
+    valA = val_in;
+  }
+  HIPCHK(launch_validate(m, n, nnz, rpA, colA, valA, vdt, b.colcnt, b.rowidx, b.flags, st));
+  int32_t hflags[4] = {0, 0, 0, 0};
+  HIPCHK(hipMemcpyAsync(hflags, b.flags, sizeof(hflags), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (hflags[0] & 1) return fail(h, DASHSVD_ERR_BAD_CSR, "row_ptr/col_idx malformed");
+  if (hflags[0] & 2) return fail(h, DASHSVD_ERR_NONFINITE, "NaN or Inf among the values");
+  // CSR(A^T)
+  HIPCHK(launch_scan_i64(b.colcnt, n, b.rpT, b.scan_tmp, st));
+  HIPCHK(launch_transpose_scatter(nnz, colA, b.rowidx, b.rpT, b.cursor, b.tmp_row, b.tmp_src, st));
+  HIPCHK(launch_transpose_classify(n, b.rpT, b.tmp_row, b.tmp_src, valA, vdt, b.colT, b.valT, b.lists,
+                                   b.counts, st));
+  int32_t hcounts[4] = {0, 0, 0, 0};
+  HIPCHK(hipMemcpyAsync(hcounts, b.counts, sizeof(hcounts), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(launch_transpose_sort(m, n, b.rpT, b.tmp_row, b.tmp_src, valA, vdt, b.colT, b.valT, b.lists, hcounts,
+                               b.bitmap, b.prefix, b.nblk_large, st));
+  // M and M^T
+  const int64_t *rpM = wide ? b.rpT : rpA;
+  const int32_t *colM = wide ? b.colT : colA;
+  const void *valM = wide ? b.valT : valA;
+  const int64_t *rpMT = wide ? rpA : b.rpT;
+  const int32_t *colMT = wide ? colA : b.colT;
+  const void *valMT = wide ? valA : b.valT;
+  // SpMM plans
+  Plan *plans[2] = {&b.planM, &b.planT};
+  const int64_t *rps[2] = {rpM, rpMT};
+  for (int i = 0; i < 2; ++i) {
+    Plan &pl = *plans[i];
+    HIPCHK(launch_plan_count(pl.R, rps[i], T, pl.nch, st));
+    HIPCHK(launch_scan_i64(pl.nch, pl.R, pl.off, b.scan_tmp, st));
+    HIPCHK(launch_plan_fill(pl.R, rps[i], T, pl.off, pl.tasks, pl.longs, pl.nlong, st));
+  }
+  int64_t totals[2] = {0, 0};
+  int32_t nlongs[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(&totals[0], b.planM.off + b.planM.R, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&totals[1], b.planT.off + b.planT.R, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&nlongs[0], b.planM.nlong, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&nlongs[1], b.planT.nlong, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  b.planM.n_chunks = totals[0];
+  b.planT.n_chunks = totals[1];
+  b.planM.n_long = nlongs[0];
+  b.planT.n_long = nlongs[1];
+  // Omega (Alg. 5 step 1)
+  if (h->opt.omega) {
+    const void *src = h->opt.omega;
+    if (!h->opt.omega_on_device) {
+      HIPCHK(hipMemcpyAsync(b.omega_dev, h->opt.omega, dsz(h->opt.omega_dtype) * (size_t)Mm * l,
+                            hipMemcpyHostToDevice, st));
+      src = b.omega_dev;
+    }
+    HIPCHK(launch_copy2d(src, l, h->opt.omega_dtype, b.Y, ld, pdt, Mm, l, st));
+  } else {
+    HIPCHK(launch_gaussian(h->opt.seed, Mm, l, b.Y, ld, pdt, st));
+  }
+  if (!h->sched.empty())
+    HIPCHK(hipMemcpyAsync(b.sched, h->sched.data(), 8 * h->sched.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const double t_setup = now_ms();
+
+  // ---------------------------------------------------------------- eigSVD helper
+  auto eigsvd = [&](int64_t rows, const void *Cm, int cm_dt, int mode, int nb, void *Qout, int q_dt,
+                    const int32_t *done) -> hipError_t {
+    hipError_t e = launch_gram(rows, l, Cm, ld, cm_dt, b.gpart, nb, b.G, done, st);
+    if (e != hipSuccess) return e;
+    EigArgs ea;
+    std::memset(&ea, 0, sizeof(ea));
+    ea.l = l;
+    ea.k = k;
+    ea.G = b.G;
+    ea.S = b.S;
+    ea.Vs = b.Vs;
+    ea.W = b.W;
+    ea.state = b.state;
+    ea.mode = mode;
+    ea.pve_mode = h->opt.pve_mode;
+    ea.policy = h->opt.shift_policy;
+    ea.tol = tol;
+    ea.Sprev = b.Sprev;
+    ea.trace_alpha = b.tr_alpha;
+    ea.trace_ratio = b.tr_ratio;
+    ea.trace_s = b.tr_s;
+    ea.trace_cap = cap;
+    ea.sched = h->sched.empty() ? nullptr : b.sched;
+    ea.sched_len = (int)h->sched.size();
+    e = launch_eig(ea, st);
+    if (e != hipSuccess) return e;
+    if (Qout) e = launch_rescale(rows, l, Cm, ld, cm_dt, b.W, l, l, Qout, ld, q_dt, done, st);
+    return e;
+  };
+  const int32_t *done = &b.state->done;
+
+  // sketch: Y0 = M^T Omega -> C ; Q = eigSVD(C).U
+  HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ld, b.planT.n_chunks, b.planT.tasks,
+                     b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr, nullptr, st));
+  HIPCHK(eigsvd(Mn, b.C, cdt, 1, nb_n, b.Q, pdt, nullptr));
+  // power passes
+  const int every = h->opt.check_interval > 0 ? h->opt.check_interval : 1;
+  int launched = 0;
+  while (launched < pmax) {
+    const int chunk = (pmax - launched) < every ? (pmax - launched) : every;
+    for (int c = 0; c < chunk; ++c) {
+      HIPCHK(launch_spmm(Mm, rpM, colM, valM, vdt, b.Q, ld, pdt, b.Y, ld, pdt, ld, b.planM.n_chunks,
+                         b.planM.tasks, b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr,
+                         done, st));
+      HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ld, b.planT.n_chunks,
+                         b.planT.tasks, b.planT.n_long, b.planT.longs, b.planT.partial, T, b.Q, ld,
+                         &b.state->alpha, done, st));
+      HIPCHK(eigsvd(Mn, b.C, cdt, 2, nb_n, b.Q, pdt, done));
+    }
+    launched += chunk;
+    if (tol > 0.0 && launched < pmax) {
+      int32_t hd = 0;
+      HIPCHK(hipMemcpyAsync(&hd, done, 4, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (hd) break;
+    }
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  const double t_loop = now_ms();
+  // final Rayleigh-Ritz: B = M Q ; eigSVD(B) ; U = B W(:,1:k) ; V = Q Vs(:,1:k)
+  HIPCHK(launch_spmm(Mm, rpM, colM, valM, vdt, b.Q, ld, pdt, b.B, ld, cdt, ld, b.planM.n_chunks, b.planM.tasks,
+                     b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, nullptr, st));
+  HIPCHK(eigsvd(Mm, b.B, cdt, 3, nb_m, nullptr, cdt, nullptr));
+  HIPCHK(launch_rescale(Mm, l, b.B, ld, cdt, b.W, l, k, b.Uo, k, cdt, nullptr, st));
+  HIPCHK(launch_rescale(Mn, l, b.Q, ld, pdt, b.Vs, l, k, b.Vo, k, cdt, nullptr, st));
+  HIPCHK(launch_sign_fix(Mn, Mm, k, b.Vo, k, b.Uo, k, cdt, b.sgn_max, b.sgn_idx, sgn_blk, st));
+  SolverState hs;
+  HIPCHK(hipMemcpyAsync(&hs, b.state, sizeof(hs), hipMemcpyDeviceToHost, st));
+  dashsvd_info &inf = h->info;
+  std::memset(&inf, 0, sizeof(inf));
+  const int ntr = pmax < DASHSVD_MAX_TRACE ? pmax : DASHSVD_MAX_TRACE;
+  if (ntr > 0) {
+    HIPCHK(hipMemcpyAsync(inf.alpha_used, b.tr_alpha, 8 * (size_t)ntr, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(inf.ratio, b.tr_ratio, 8 * (size_t)ntr, hipMemcpyDeviceToHost, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  const double t_end = now_ms();
+  inf.passes = hs.pass;
+  inf.converged = hs.converged;
+  inf.rank_deficient = hs.deficient;
+  inf.l = l;
+  inf.learned_fallback = hs.sched_off;
+  inf.final_alpha = hs.alpha;
+  inf.time_total_ms = t_end - t0;
+  inf.time_setup_ms = t_setup - t0;
+  inf.time_loop_ms = t_loop - t_setup;
+  inf.time_final_ms = t_end - t_loop;
+  inf.long_chunks_A = wide ? b.planT.n_chunks : b.planM.n_chunks;
+  inf.long_chunks_AT = wide ? b.planM.n_chunks : b.planT.n_chunks;
+  // results in the caller's orientation
+  h->m = m;
+  h->n = n;
+  h->k = k;
+  h->l = l;
+  h->out_dt = cdt;
+  h->U = wide ? b.Vo : b.Uo;
+  h->V = wide ? b.Uo : b.Vo;
+  h->S = b.S;
+  h->trace_s = b.tr_s;
+  h->trace_cap = cap;
+  h->have = true;
+  dashsvd_status s = DASHSVD_OK;
+  if (tol > 0.0 && !hs.converged) s = DASHSVD_NOT_CONVERGED;
+  else if (hs.deficient) s = DASHSVD_RANK_DEFICIENT;
+  inf.status = s;
+  return s;
+}
+
+dashsvd_status dashsvd_run(dashsvd_handle *h, const dashsvd_csr *A, int32_t k, int32_t p, double tol) {
+  if (!h) return DASHSVD_ERR_INVALID_ARG;
+  h->err.clear();
+  dashsvd_status s = check_args(h, A, k, p, tol);
+  if (s != DASHSVD_OK) return s;
+  if (h->opt.shift_policy == DASHSVD_SHIFT_LEARNED)
+    return fail(h, DASHSVD_ERR_INVALID_ARG, "LEARNED policy needs trained weights (dashsvd_mlp_*)");
+  if (h->opt.omega && h->opt.precision == DASHSVD_PREC_BF16_PANELS)
+    return fail(h, DASHSVD_ERR_INVALID_ARG, "a caller-provided Omega is not supported with BF16 panels");
+  s = run_impl(h, A, k, p, tol, false, nullptr);
+  h->info.status = s;
+  return s;
+}
+
+dashsvd_status dashsvd_workspace_size(const dashsvd_csr *A, int32_t k, int32_t p, int32_t precision,
+                                      size_t *bytes) {
+  if (!bytes) return DASHSVD_ERR_INVALID_ARG;
+  dashsvd_handle tmp;
+  dashsvd_options o;
+  default_options(&o);
+  o.precision = precision;
+  dashsvd_status s = dashsvd_set_options(&tmp, &o);
+  if (s != DASHSVD_OK) return s;
+  s = check_args(&tmp, A, k, p, 0.0);
+  if (s != DASHSVD_OK) return s;
+  return run_impl(&tmp, A, k, p, 0.0, true, bytes);
+}
+
+dashsvd_status dashsvd_get_USV(dashsvd_handle *h, void *U, int64_t ldu, double *S, void *V, int64_t ldv,
+                               int32_t dtype, int32_t on_device) {
+  if (!h) return DASHSVD_ERR_INVALID_ARG;
+  if (!h->have) return fail(h, DASHSVD_ERR_STATE, "no results: run first");
+  if (dtype != DASHSVD_F32 && dtype != DASHSVD_F64) return fail(h, DASHSVD_ERR_INVALID_ARG, "dtype");
+  if ((U && ldu < h->k) || (V && ldv < h->k)) return fail(h, DASHSVD_ERR_INVALID_ARG, "leading dimension");
+  hipStream_t st = h->st;
+  const size_t es = dsz(dtype);
+  struct Item {
+    void *dst;
+    int64_t ldd;
+    const void *src;
+    int64_t rows;
+  } items[2] = {{U, ldu, h->U, h->m}, {V, ldv, h->V, h->n}};
+  for (auto &it : items) {
+    if (!it.dst) continue;
+    if (on_device) {
+      HIPCHK(launch_copy2d(it.src, h->k, h->out_dt, it.dst, it.ldd, dtype, it.rows, h->k, st));
+    } else {
+      void *tmp = nullptr;
+      HIPCHK(hipMalloc(&tmp, es * (size_t)it.rows * h->k + 16));
+      hipError_t e = launch_copy2d(it.src, h->k, h->out_dt, tmp, h->k, dtype, it.rows, h->k, st);
+      if (e == hipSuccess)
+        e = hipMemcpy2DAsync(it.dst, es * it.ldd, tmp, es * h->k, es * h->k, it.rows, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      (void)hipFree(tmp);
+      HIPCHK(e);
+    }
+  }
+  if (S) HIPCHK(hipMemcpyAsync(S, h->S, 8 * (size_t)h->k, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return DASHSVD_OK;
+}
+
+dashsvd_status dashsvd_get_info(dashsvd_handle *h, dashsvd_info *out) {
+  if (!h || !out) return DASHSVD_ERR_INVALID_ARG;
+  *out = h->info;
+  return DASHSVD_OK;
+}
+
+dashsvd_status dashsvd_get_trace(dashsvd_handle *h, double *s_hat, int32_t max_passes) {
+  if (!h || !s_hat) return DASHSVD_ERR_INVALID_ARG;
+  if (!h->have) return fail(h, DASHSVD_ERR_STATE, "no results: run first");
+  int np = h->info.passes < max_passes ? h->info.passes : max_passes;
+  if (np > h->trace_cap) np = h->trace_cap;
+  if (np > 0) {
+    HIPCHK(hipMemcpyAsync(s_hat, h->trace_s, 8 * (size_t)np * h->l, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+  }
+  return DASHSVD_OK;
+}
+
+// ------------------------------------------------------------------ kernel-level entries
+dashsvd_status dashsvd_k_gaussian(uint64_t seed, int64_t rows, int64_t cols, void *out, int64_t ld, int32_t dtype,
+                                  void *stream) {
+  dashsvd_handle *h = nullptr;
+  if (rows < 0 || cols < 0 || ld < cols || !out || dtype < 0 || dtype > 2)
+    return fail(h, DASHSVD_ERR_INVALID_ARG, "gaussian arguments");
+  HIPCHK(launch_gaussian(seed, rows, cols, out, ld, dtype, (hipStream_t)stream));
+  return DASHSVD_OK;
+}
+
+dashsvd_status dashsvd_k_philox_raw(uint64_t seed, int64_t nwords, uint64_t *out, void *stream) {
+  dashsvd_handle *h = nullptr;
+  if (nwords < 0 || !out) return fail(h, DASHSVD_ERR_INVALID_ARG, "philox arguments");
+  HIPCHK(launch_philox_raw(seed, nwords, out, (hipStream_t)stream));
+  return DASHSVD_OK;
+}
+
+dashsvd_status dashsvd_k_transpose(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
+                                   const void *val, int32_t dtype, int64_t *rowT, int32_t *colT, void *valT,
+                                   void *stream) {
+  dashsvd_handle *h = nullptr;
+  if (m < 1 || n < 1 || nnz < 0 || nnz > INT32_MAX || (dtype != 0 && dtype != 1))
+    return fail(h, DASHSVD_ERR_INVALID_ARG, "transpose arguments");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t words = transpose_bitmap_words(m);
+  const int nbl = 64;
+  size_t bytes[9] = {8 * (size_t)(n + 1), 4 * (size_t)(nnz + 1), 4 * (size_t)(n + 1), 4 * (size_t)(nnz + 1),
+                     4 * (size_t)(nnz + 1), 4 * (size_t)(3 * n + 1), 64, (size_t)(8 * (words * nbl + 1)),
+                     8 * scan_tmp_elems(n + 1)};
+  void *ptr[9] = {};
+  for (int i = 0; i < 9; ++i) {
+    if (hipMalloc(&ptr[i], bytes[i]) != hipSuccess) {
+      for (int j = 0; j < i; ++j) (void)hipFree(ptr[j]);
+      return fail(h, DASHSVD_ERR_OOM, "transpose workspace");
+    }
+    (void)hipMemsetAsync(ptr[i], 0, bytes[i], st);
+  }
+  int64_t *colcnt = (int64_t *)ptr[0];
+  int32_t *rowidx = (int32_t *)ptr[1], *cursor = (int32_t *)ptr[2], *tmp_row = (int32_t *)ptr[3],
+          *tmp_src = (int32_t *)ptr[4], *lists = (int32_t *)ptr[5], *counts = (int32_t *)ptr[6];
+  uint32_t *bitmap = (uint32_t *)ptr[7];
+  int32_t *prefix = (int32_t *)((uint32_t *)ptr[7] + words * nbl);
+  int64_t *scan_tmp = (int64_t *)ptr[8];
+  dashsvd_status res = DASHSVD_OK;
+  int32_t hc[4] = {0, 0, 0, 0};
+  hipError_t e = launch_validate(m, n, nnz, row_ptr, col, val, dtype, colcnt, rowidx, counts + 4, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(hc, counts + 4, 16, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess && (hc[0] & 1)) res = DASHSVD_ERR_BAD_CSR;
+  else if (e == hipSuccess && (hc[0] & 2)) res = DASHSVD_ERR_NONFINITE;
+  if (e == hipSuccess && res == DASHSVD_OK) {
+    e = launch_scan_i64(colcnt, n, rowT, scan_tmp, st);
+    if (e == hipSuccess) e = launch_transpose_scatter(nnz, col, rowidx, rowT, cursor, tmp_row, tmp_src, st);
+    if (e == hipSuccess)
+      e = launch_transpose_classify(n, rowT, tmp_row, tmp_src, val, dtype, colT, valT, lists, counts, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(hc, counts, 16, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess)
+      e = launch_transpose_sort(m, n, rowT, tmp_row, tmp_src, val, dtype, colT, valT, lists, hc, bitmap, prefix, nbl,
+                                st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  }
+  for (int i = 0; i < 9; ++i) (void)hipFree(ptr[i]);
+  if (e != hipSuccess) return fail(h, DASHSVD_ERR_HIP, hipGetErrorString(e));
+  if (res != DASHSVD_OK) return fail(h, res, "invalid CSR");
+  return DASHSVD_OK;
+}
+
+dashsvd_status dashsvd_k_spmm(int64_t rows, int64_t cols, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
+                              const void *val, const void *X, int64_t ldx, int32_t xdtype, void *Y, int64_t ldy,
+                              int32_t ydtype, int32_t l, const void *Q, int64_t ldq, const double *alpha,
+                              int32_t long_row, void *stream) {
+  dashsvd_handle *h = nullptr;
+  (void)cols;
+  const int ld = (int)round_up(l, 8);
+  if (rows < 1 || l < 1 || l > DASHSVD_MAX_L || ldx % 8 || ldy % 8 || ldx < ld || ldy < ld ||
+      (alpha && (!Q || ldq % 8 || ldq < ld)))
+    return fail(h, DASHSVD_ERR_INVALID_ARG, "spmm arguments (leading dimensions must be multiples of 8 >= l)");
+  const int vdt = xdtype == DASHSVD_F64 ? DASHSVD_F64 : DASHSVD_F32;
+  const size_t accsz = xdtype == DASHSVD_F64 ? 8 : 4;
+  const int32_t T = long_row > 0 ? long_row : kDefaultLongRow;
+  hipStream_t st = (hipStream_t)stream;
+  Arena a;
+  a.reset(true);
+  Plan pl;
+  plan_alloc(h, a, pl, rows, nnz, T, ld, accsz);
+  a.take(8 * scan_tmp_elems(rows + 1));
+  void *base = nullptr;
+  if (hipMalloc(&base, a.used + 256) != hipSuccess) return fail(h, DASHSVD_ERR_OOM, "spmm workspace");
+  (void)hipMemsetAsync(base, 0, a.used + 256, st);
+  a.base = (char *)base;
+  a.cap = a.used + 256;
+  a.reset(false);
+  plan_alloc(h, a, pl, rows, nnz, T, ld, accsz);
+  int64_t *scan_tmp = (int64_t *)a.take(8 * scan_tmp_elems(rows + 1));
+  hipError_t e = launch_plan_count(rows, row_ptr, T, pl.nch, st);
+  if (e == hipSuccess) e = launch_scan_i64(pl.nch, rows, pl.off, scan_tmp, st);
+  if (e == hipSuccess) e = launch_plan_fill(rows, row_ptr, T, pl.off, pl.tasks, pl.longs, pl.nlong, st);
+  int64_t tot = 0;
+  int32_t nl = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&tot, pl.off + rows, 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&nl, pl.nlong, 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess)
+    e = launch_spmm(rows, row_ptr, col, val, vdt, X, ldx, xdtype, Y, ldy, ydtype, ld, tot, pl.tasks, nl, pl.longs,
+                    pl.partial, T, Q, ldq, alpha, nullptr, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(base);
+  if (e != hipSuccess) return fail(h, DASHSVD_ERR_HIP, hipGetErrorString(e));
+  return DASHSVD_OK;
+}
+
+dashsvd_status dashsvd_k_gram(int64_t r, int32_t l, const void *C, int64_t ldc, int32_t cdtype, double *G,
+                              void *stream) {
+  dashsvd_handle *h = nullptr;
+  if (r < 1 || l < 1 || l > DASHSVD_MAX_L || ldc < l || (cdtype != 0 && cdtype != 1))
+    return fail(h, DASHSVD_ERR_INVALID_ARG, "gram arguments");
+  hipStream_t st = (hipStream_t)stream;
+  const int nb = gram_blocks(r, l);
+  double *part = nullptr;
+  HIPCHK(hipMalloc(&part, 8 * gram_partial_elems(nb, l)));
+  hipError_t e = launch_gram(r, l, C, ldc, cdtype, part, nb, G, nullptr, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(part);
+  HIPCHK(e);
+  return DASHSVD_OK;
+}
+
+dashsvd_status dashsvd_k_eig(int32_t l, const double *G, double *S, double *Vs, double *W, int32_t *sweeps,
+                             void *stream) {
+  dashsvd_handle *h = nullptr;
+  if (l < 1 || l > DASHSVD_MAX_L || !G || !S || !W) return fail(h, DASHSVD_ERR_INVALID_ARG, "eig arguments");
+  EigArgs ea;
+  std::memset(&ea, 0, sizeof(ea));
+  ea.l = l;
+  ea.k = 0;
+  ea.G = G;
+  ea.S = S;
+  ea.Vs = Vs;
+  ea.W = W;
+  ea.sweeps = sweeps;
+  ea.mode = 0;
+  HIPCHK(launch_eig(ea, (hipStream_t)stream));
+  return DASHSVD_OK;
+}
+
+dashsvd_status dashsvd_k_rescale(int64_t r, int32_t l, const void *C, int64_t ldc, int32_t cdtype, const double *W,
+                                 int64_t ldw, int32_t c, void *Out, int64_t ldo, int32_t odtype, void *stream) {
+  dashsvd_handle *h = nullptr;
+  if (r < 1 || l < 1 || l > DASHSVD_MAX_L || c < 1 || c > DASHSVD_MAX_L || ldc < l || ldw < c || ldo < c)
+    return fail(h, DASHSVD_ERR_INVALID_ARG, "rescale arguments");
+  HIPCHK(launch_rescale(r, l, C, ldc, cdtype, W, ldw, c, Out, ldo, odtype, nullptr, (hipStream_t)stream));
+  return DASHSVD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,461 @@
+// Dense tall-skinny kernels of eigSVD (Alg. 3) and of the final step of
+// Alg. 5, plus small utilities.
+//
+// Gram G = C^T C (Alg. 3 step 1), FP64 accumulation on the FP64 matrix
+// cores: the l columns are cut into T = ceil(l/16) tiles and only the
+// T(T+1)/2 upper tiles are computed.  A 256-thread block stages 32 rows of C
+// in LDS as FP64 (FP32 inputs convert exactly), and each wavefront owns a
+// fixed set of upper tiles, issuing v_mfma_f64_16x16x4 per tile per 4 rows.
+// Every block writes its partial tiles; a second kernel sums the partials in
+// block order (deterministic) and mirrors the upper triangle.
+//
+// Rescale Out = C W (Alg. 3 step 3, and U = B W_B, V = Q V_B of Alg. 5
+// step 11).  FP32 / BF16 path: W (l x c) is converted to FP32 once per block
+// into LDS; the block walks 64-row strips of C staged in LDS and each
+// wavefront computes a 16-row strip of all output tiles with
+// v_mfma_f32_16x16x4.  FP64 path: plain FP64 FMAs (used for the FP64 form).
+//
+// MFMA operand layout assumed (16x16x4, one block): lane L holds A[L%16][L/16]
+// and B[L/16][L%16]; the accumulator's register q of lane L is
+// D[4*(L/16)+q][L%16].
+#include "common.h"
+
+namespace dsv {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> __device__ __forceinline__ double to_d(T v) { return (double)v; }
+template <> __device__ __forceinline__ double to_d<bf16>(bf16 v) { return (double)bf2f(v); }
+
+// ------------------------------------------------------------------ Gram
+constexpr int kGramRows = 32;
+
+template <typename TC, int LT>
+__global__ __launch_bounds__(256) void k_gram_partial(int64_t r, int l, const TC *__restrict__ C,
+                                                      int64_t ldc, double *__restrict__ partial,
+                                                      int64_t rows_per_block,
+                                                      const int32_t *__restrict__ done) {
+  if (done && *done) return;
+  constexpr int NT = LT * (LT + 1) / 2;
+  constexpr int TPW = (NT + 3) / 4;
+  constexpr int W = LT * 16;
+  constexpr int S = W + 1;  // LDS row stride (doubles), odd to spread banks
+  __shared__ double tile[kGramRows * S];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int tI[TPW], tJ[TPW];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    int t = wave + 4 * i, I = 0;
+    if (t >= NT) t = NT - 1;  // duplicate work is discarded below
+    while (t >= LT - I) {
+      t -= LT - I;
+      ++I;
+    }
+    tI[i] = I;
+    tJ[i] = I + t;
+  }
+  d4 acc[TPW];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+  const int64_t row0 = (int64_t)blockIdx.x * rows_per_block;
+  int64_t row1 = row0 + rows_per_block;
+  if (row1 > r) row1 = r;
+  const int kr = lane >> 4, kc = lane & 15;
+  for (int64_t rb = row0; rb < row1; rb += kGramRows) {
+    for (int idx = threadIdx.x; idx < kGramRows * W; idx += 256) {
+      const int rr = idx / W, cc = idx - rr * W;
+      const int64_t row = rb + rr;
+      tile[rr * S + cc] = (row < row1 && cc < l) ? to_d(C[row * ldc + cc]) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int s = 0; s < kGramRows / 4; ++s) {
+      const double *trow = tile + (s * 4 + kr) * S + kc;
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) {
+        if (wave + 4 * i < NT) {
+          const double a = trow[tI[i] * 16];
+          const double b = trow[tJ[i] * 16];
+          acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[i], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double *out = partial + (int64_t)blockIdx.x * NT * 256;
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    const int t = wave + 4 * i;
+    if (t < NT) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) out[(int64_t)t * 256 + lane * 4 + q] = acc[i][q];
+    }
+  }
+}
+
+// Sum the block partials in block order; write the full symmetric G.
+template <int LT>
+__global__ __launch_bounds__(256) void k_gram_reduce(int l, int nblocks, const double *__restrict__ partial,
+                                                     double *__restrict__ G,
+                                                     const int32_t *__restrict__ done) {
+  if (done && *done) return;
+  constexpr int NT = LT * (LT + 1) / 2;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)NT * 256) return;
+  int t = (int)(e >> 8);
+  const int within = (int)(e & 255);
+  const int lane = within >> 2, q = within & 3;
+  int I = 0;
+  while (t >= LT - I) {
+    t -= LT - I;
+    ++I;
+  }
+  const int J = I + t;
+  const int row = I * 16 + 4 * (lane >> 4) + q;
+  const int col = J * 16 + (lane & 15);
+  if (row >= l || col >= l) return;
+  if (I == J && row > col) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * NT * 256 + e];
+  G[(int64_t)row * l + col] = s;
+  G[(int64_t)col * l + row] = s;
+}
+
+// ------------------------------------------------------------------ rescale
+constexpr int kStrip = 64;
+
+template <typename TC, typename TO, int LTO>
+__global__ __launch_bounds__(256) void k_rescale_mfma(int64_t r, int l, const TC *__restrict__ C,
+                                                      int64_t ldc, const double *__restrict__ W,
+                                                      int64_t ldw, int c, TO *__restrict__ Out,
+                                                      int64_t ldo, const int32_t *__restrict__ done) {
+  if (done && *done) return;
+  constexpr int WC = LTO * 16;
+  constexpr int SW = WC + 4;
+  extern __shared__ float lds[];
+  const int LK = (l + 3) & ~3;
+  const int SC = LK + 1;
+  float *Ws = lds;                 // LK x SW
+  float *Cs = lds + LK * SW;       // kStrip x SC
+  for (int idx = threadIdx.x; idx < LK * WC; idx += 256) {
+    const int kk = idx / WC, cc = idx - kk * WC;
+    Ws[kk * SW + cc] = (kk < l && cc < c) ? (float)W[(int64_t)kk * ldw + cc] : 0.0f;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t nstrips = (r + kStrip - 1) / kStrip;
+  for (int64_t strip = blockIdx.x; strip < nstrips; strip += gridDim.x) {
+    const int64_t rb = strip * kStrip;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kStrip * LK; idx += 256) {
+      const int rr = idx / LK, kk = idx - rr * LK;
+      const int64_t row = rb + rr;
+      Cs[rr * SC + kk] = (row < r && kk < l) ? (float)to_d(C[row * ldc + kk]) : 0.0f;
+    }
+    __syncthreads();
+    f4 acc[LTO];
+#pragma unroll
+    for (int J = 0; J < LTO; ++J) acc[J] = f4{0.f, 0.f, 0.f, 0.f};
+    const float *arow = Cs + (wave * 16 + (lane & 15)) * SC + (lane >> 4);
+    const float *bcol = Ws + (lane >> 4) * SW + (lane & 15);
+    for (int k0 = 0; k0 < LK; k0 += 4) {
+      const float a = arow[k0];
+#pragma unroll
+      for (int J = 0; J < LTO; ++J) {
+        const float b = bcol[k0 * SW + J * 16];
+        acc[J] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[J], 0, 0, 0);
+      }
+    }
+    const int64_t rbase = rb + wave * 16 + 4 * (lane >> 4);
+#pragma unroll
+    for (int J = 0; J < LTO; ++J) {
+      const int col = J * 16 + (lane & 15);
+      if (col < ldo) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t row = rbase + q;
+          if (row < r) elem<TO>::st(Out + row * ldo + col, col < c ? acc[J][q] : 0.0f);
+        }
+      }
+    }
+    // columns beyond the tiles (ldo > LTO*16) are zero
+    for (int idx = threadIdx.x; idx < kStrip * (int)(ldo > WC ? ldo - WC : 0); idx += 256) {
+      const int extra = (int)(ldo - WC);
+      const int rr = idx / extra, cc = WC + idx % extra;
+      const int64_t row = rb + rr;
+      if (row < r) elem<TO>::st(Out + row * ldo + cc, 0.0f);
+    }
+  }
+}
+
+template <typename TC>
+__global__ __launch_bounds__(256) void k_rescale_f64(int64_t r, int l, const TC *__restrict__ C,
+                                                     int64_t ldc, const double *__restrict__ W,
+                                                     int64_t ldw, int c, double *__restrict__ Out,
+                                                     int64_t ldo, const int32_t *__restrict__ done) {
+  if (done && *done) return;
+  const int64_t total = r * ldo;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t row = e / ldo;
+    const int col = (int)(e - row * ldo);
+    double s = 0.0;
+    if (col < c) {
+      const TC *cr = C + row * ldc;
+      for (int k = 0; k < l; ++k) s = fma(to_d(cr[k]), W[(int64_t)k * ldw + col], s);
+    }
+    Out[row * ldo + col] = s;
+  }
+}
+
+// ------------------------------------------------------------------ signs
+// Sign normalisation on output: the entry of largest magnitude of each V
+// column (lowest row on ties) is made positive; the same flip is applied to
+// the matching U column.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sign_partial(int64_t rows, int k, const T *__restrict__ V,
+                                                      int64_t ldv, double *__restrict__ pmax,
+                                                      int64_t *__restrict__ pidx) {
+  __shared__ double smax[256];
+  __shared__ int64_t sidx[256];
+  const int per = blockDim.x / k;  // >= 1 since k <= 256
+  const int t = threadIdx.x, cidx = t % k, sub = t / k;
+  const int64_t chunk = (rows + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  int64_t r1 = r0 + chunk;
+  if (r1 > rows) r1 = rows;
+  double best = -1.0;
+  int64_t bi = INT64_MAX;
+  if (sub < per) {
+    for (int64_t i = r0 + sub; i < r1; i += per) {
+      const double a = fabs(to_d(V[i * ldv + cidx]));
+      if (a > best) {
+        best = a;
+        bi = i;
+      }
+    }
+  }
+  smax[t] = best;
+  sidx[t] = bi;
+  __syncthreads();
+  if (sub == 0) {
+    for (int s = 1; s < per; ++s) {
+      const double a = smax[s * k + cidx];
+      const int64_t ii = sidx[s * k + cidx];
+      if (a > best || (a == best && ii < bi)) {
+        best = a;
+        bi = ii;
+      }
+    }
+    pmax[(int64_t)blockIdx.x * k + cidx] = best;
+    pidx[(int64_t)blockIdx.x * k + cidx] = bi;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sign_apply(int64_t rowsV, int64_t rowsU, int k, T *__restrict__ V,
+                                                    int64_t ldv, T *__restrict__ U, int64_t ldu,
+                                                    const double *__restrict__ pmax,
+                                                    const int64_t *__restrict__ pidx, int nblk) {
+  __shared__ float sgn[256];
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    double best = -1.0;
+    int64_t bi = INT64_MAX;
+    for (int b = 0; b < nblk; ++b) {
+      const double a = pmax[(int64_t)b * k + c];
+      const int64_t ii = pidx[(int64_t)b * k + c];
+      if (a > best || (a == best && ii < bi)) {
+        best = a;
+        bi = ii;
+      }
+    }
+    sgn[c] = (bi != INT64_MAX && to_d(V[bi * ldv + c]) < 0.0) ? -1.0f : 1.0f;
+  }
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tv = rowsV * k, tu = rowsU * k;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tv + tu; e += stride) {
+    if (e < tv) {
+      const int64_t i = e / k;
+      const int c = (int)(e - i * k);
+      if (sgn[c] < 0.f) V[i * ldv + c] = -V[i * ldv + c];
+    } else {
+      const int64_t f = e - tv;
+      const int64_t i = f / k;
+      const int c = (int)(f - i * k);
+      if (sgn[c] < 0.f) U[i * ldu + c] = -U[i * ldu + c];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ conversion
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_copy2d(const TI *__restrict__ in, int64_t ldi, TO *__restrict__ out,
+                                                int64_t ldo, int64_t rows, int cols) {
+  const int64_t total = rows * cols;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t i = e / cols;
+    const int j = (int)(e - i * cols);
+    out[i * ldo + j] = (TO)in[i * ldi + j];
+  }
+}
+
+int grid_for(int64_t work, int block, int64_t cap = 65536) {
+  int64_t g = (work + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+template <typename TC>
+hipError_t gram_dispatch(int64_t r, int l, const TC *C, int64_t ldc, double *partial, int nb,
+                         double *G, const int32_t *done, hipStream_t st) {
+  const int LT = (l + 15) / 16;
+  const int64_t rpb = (r + nb - 1) / nb;
+#define DSV_GRAM(LTV)                                                                          \
+  case LTV: {                                                                                  \
+    hipLaunchKernelGGL((k_gram_partial<TC, LTV>), dim3(nb), dim3(256), 0, st, r, l, C, ldc, partial, \
+                       rpb, done);                                                             \
+    constexpr int NT = LTV * (LTV + 1) / 2;                                                    \
+    hipLaunchKernelGGL((k_gram_reduce<LTV>), dim3((NT * 256 + 255) / 256), dim3(256), 0, st, l, nb, \
+                       partial, G, done);                                                      \
+    break;                                                                                     \
+  }
+  switch (LT) {
+    DSV_GRAM(1) DSV_GRAM(2) DSV_GRAM(3) DSV_GRAM(4) DSV_GRAM(5)
+    DSV_GRAM(6) DSV_GRAM(7) DSV_GRAM(8) DSV_GRAM(9) DSV_GRAM(10)
+    default: return hipErrorInvalidValue;
+  }
+#undef DSV_GRAM
+  return hipGetLastError();
+}
+
+template <typename TC, typename TO>
+hipError_t rescale_dispatch(int64_t r, int l, const TC *C, int64_t ldc, const double *W, int64_t ldw,
+                            int c, TO *Out, int64_t ldo, const int32_t *done, hipStream_t st) {
+  const int LTO = (c + 15) / 16;
+  const int LK = (l + 3) & ~3;
+  const int64_t nstrips = (r + kStrip - 1) / kStrip;
+  int grid = (int)(nstrips < 512 ? nstrips : 512);
+  if (grid < 1) grid = 1;
+#define DSV_RS(LTV)                                                                             \
+  case LTV: {                                                                                   \
+    const size_t shm = sizeof(float) * ((size_t)LK * (LTV * 16 + 4) + (size_t)kStrip * (LK + 1)); \
+    hipLaunchKernelGGL((k_rescale_mfma<TC, TO, LTV>), dim3(grid), dim3(256), shm, st, r, l, C, ldc, W, \
+                       ldw, c, Out, ldo, done);                                                 \
+    break;                                                                                      \
+  }
+  switch (LTO) {
+    DSV_RS(1) DSV_RS(2) DSV_RS(3) DSV_RS(4) DSV_RS(5)
+    DSV_RS(6) DSV_RS(7) DSV_RS(8) DSV_RS(9) DSV_RS(10)
+    default: return hipErrorInvalidValue;
+  }
+#undef DSV_RS
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int gram_blocks(int64_t r, int l) {
+  (void)l;
+  int64_t nb = (r + 63) / 64;
+  if (nb > 512) nb = 512;
+  if (nb < 1) nb = 1;
+  return (int)nb;
+}
+size_t gram_partial_elems(int nblocks, int l) {
+  const int LT = (l + 15) / 16;
+  return (size_t)nblocks * (size_t)(LT * (LT + 1) / 2) * 256;
+}
+
+hipError_t launch_gram(int64_t r, int l, const void *C, int64_t ldc, int cdtype, double *partial,
+                       int nblocks, double *G, const int32_t *done, hipStream_t st) {
+  if (l < 1 || l > kMaxL) return hipErrorInvalidValue;
+  if (cdtype == 0) return gram_dispatch<float>(r, l, (const float *)C, ldc, partial, nblocks, G, done, st);
+  if (cdtype == 1) return gram_dispatch<double>(r, l, (const double *)C, ldc, partial, nblocks, G, done, st);
+  return gram_dispatch<bf16>(r, l, (const bf16 *)C, ldc, partial, nblocks, G, done, st);
+}
+
+hipError_t launch_rescale(int64_t r, int l, const void *C, int64_t ldc, int cdtype, const double *W,
+                          int64_t ldw, int c, void *Out, int64_t ldo, int odtype, const int32_t *done,
+                          hipStream_t st) {
+  if (l < 1 || l > kMaxL || c < 1 || c > kMaxL || r == 0) return r == 0 ? hipSuccess : hipErrorInvalidValue;
+  static bool attr_done = false;
+  if (!attr_done) {
+    // allow the MFMA rescale to use up to 160 KB of LDS
+#define DSV_ATTR(TC, TO, L) \
+  hipFuncSetAttribute((const void *)k_rescale_mfma<TC, TO, L>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+#define DSV_ATTR_ALL(TC, TO) \
+  DSV_ATTR(TC, TO, 1) DSV_ATTR(TC, TO, 2) DSV_ATTR(TC, TO, 3) DSV_ATTR(TC, TO, 4) DSV_ATTR(TC, TO, 5) \
+  DSV_ATTR(TC, TO, 6) DSV_ATTR(TC, TO, 7) DSV_ATTR(TC, TO, 8) DSV_ATTR(TC, TO, 9) DSV_ATTR(TC, TO, 10)
+    DSV_ATTR_ALL(float, float)
+    DSV_ATTR_ALL(float, bf16)
+    DSV_ATTR_ALL(bf16, float)
+#undef DSV_ATTR_ALL
+#undef DSV_ATTR
+    attr_done = true;
+  }
+  if (odtype == 1) {
+    const int g = grid_for(r * ldo, 256, 16384);
+    if (cdtype == 1)
+      hipLaunchKernelGGL(k_rescale_f64<double>, dim3(g), dim3(256), 0, st, r, l, (const double *)C, ldc, W, ldw,
+                         c, (double *)Out, ldo, done);
+    else if (cdtype == 0)
+      hipLaunchKernelGGL(k_rescale_f64<float>, dim3(g), dim3(256), 0, st, r, l, (const float *)C, ldc, W, ldw, c,
+                         (double *)Out, ldo, done);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
+  if (cdtype == 0 && odtype == 0)
+    return rescale_dispatch<float, float>(r, l, (const float *)C, ldc, W, ldw, c, (float *)Out, ldo, done, st);
+  if (cdtype == 0 && odtype == 2)
+    return rescale_dispatch<float, bf16>(r, l, (const float *)C, ldc, W, ldw, c, (bf16 *)Out, ldo, done, st);
+  if (cdtype == 2 && odtype == 0)
+    return rescale_dispatch<bf16, float>(r, l, (const bf16 *)C, ldc, W, ldw, c, (float *)Out, ldo, done, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_sign_fix(int64_t rowsV, int64_t rowsU, int k, void *V, int64_t ldv, void *U,
+                           int64_t ldu, int dtype, void *pmax_v, void *pidx_v, int nblk,
+                           hipStream_t st) {
+  double *pmax = static_cast<double *>(pmax_v);
+  int64_t *pidx = static_cast<int64_t *>(pidx_v);
+  if (k < 1 || k > 256) return hipErrorInvalidValue;
+  if (dtype == 1) {
+    hipLaunchKernelGGL(k_sign_partial<double>, dim3(nblk), dim3(256), 0, st, rowsV, k, (const double *)V, ldv,
+                       pmax, pidx);
+    hipLaunchKernelGGL(k_sign_apply<double>, dim3(grid_for((rowsV + rowsU) * k, 256, 4096)), dim3(256), 0, st,
+                       rowsV, rowsU, k, (double *)V, ldv, (double *)U, ldu, pmax, pidx, nblk);
+  } else {
+    hipLaunchKernelGGL(k_sign_partial<float>, dim3(nblk), dim3(256), 0, st, rowsV, k, (const float *)V, ldv,
+                       pmax, pidx);
+    hipLaunchKernelGGL(k_sign_apply<float>, dim3(grid_for((rowsV + rowsU) * k, 256, 4096)), dim3(256), 0, st,
+                       rowsV, rowsU, k, (float *)V, ldv, (float *)U, ldu, pmax, pidx, nblk);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_copy2d(const void *in, int64_t ldi, int idtype, void *out, int64_t ldo, int odtype,
+                         int64_t rows, int cols, hipStream_t st) {
+  if (rows * cols == 0) return hipSuccess;
+  const int g = grid_for(rows * cols, 256, 16384);
+#define DSV_CP(TI, TO) \
+  hipLaunchKernelGGL((k_copy2d<TI, TO>), dim3(g), dim3(256), 0, st, (const TI *)in, ldi, (TO *)out, ldo, rows, cols)
+  if (idtype == 0 && odtype == 0) DSV_CP(float, float);
+  else if (idtype == 0 && odtype == 1) DSV_CP(float, double);
+  else if (idtype == 1 && odtype == 0) DSV_CP(double, float);
+  else if (idtype == 1 && odtype == 1) DSV_CP(double, double);
+  else return hipErrorInvalidValue;
+#undef DSV_CP
+  return hipGetLastError();
+}
+
+hipError_t launch_convert(const void *in, int idtype, void *out, int odtype, int64_t n, hipStream_t st) {
+  return launch_copy2d(in, 1, idtype, out, 1, odtype, n, 1, st);
+}
+
+}  // namespace dsv

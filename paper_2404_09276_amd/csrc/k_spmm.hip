@@ -1,0 +1,200 @@
+// Sparse x tall-skinny dense products of the power pass (Alg. 5 steps 2, 4
+// and 9): Y = A X and, with the shift fused in the epilogue,
+// C = A^T Y - alpha Q.
+//
+// Layout: the dense panels are row-major with a leading dimension that is a
+// multiple of 8 elements, so each row starts 16-byte aligned.  A group of
+// G = ld / V lanes owns one sparse row, V = 16 / sizeof(panel element) (4
+// FP32, 2 FP64, 8 BF16), and every lane keeps V accumulators: for each
+// nonzero the group gathers one full panel row with one 16-byte load per
+// lane, so a gathered row is a coalesced read of ld elements.  A wavefront
+// holds 64 / G groups.  Four nonzeros are in flight per group (unrolled)
+// to keep enough loads outstanding.
+//
+// Load balance (power-law degrees): rows with more than long_row nonzeros
+// are cut into chunks of long_row; each chunk is an independent task writing
+// a partial row, and a second kernel sums the chunks of each long row in
+// chunk order.  Nothing depends on scheduling order, so results repeat bit
+// for bit.  Tasks are numbered chunks first, then rows, so the heavy chunks
+// start early.
+//
+// The kernels read the solver's done flag first and exit when the PVE check
+// has already stopped the iteration (speculatively launched passes).
+#include "common.h"
+
+namespace dsv {
+
+namespace {
+
+template <typename TX> struct acc_of {
+  using type = float;
+};
+template <> struct acc_of<double> {
+  using type = double;
+};
+
+template <typename TV, typename TX, typename TY, typename TA, bool SHIFT>
+__global__ __launch_bounds__(256) void k_spmm(
+    int64_t R, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+    const TV *__restrict__ val, const TX *__restrict__ X, int64_t ldx, TY *__restrict__ Y,
+    int64_t ldy, int G, int64_t n_chunks, const ChunkTask *__restrict__ tasks,
+    TA *__restrict__ partial, int64_t ldp, int32_t long_row, const TX *__restrict__ Q, int64_t ldq,
+    const double *__restrict__ alpha, const int32_t *__restrict__ done) {
+  if (done && *done) return;
+  constexpr int V = vec16<TX, TA>::N;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rpw = kWave / G;
+  const int sub = lane / G, cl = lane - sub * G;
+  if (sub >= rpw) return;
+  const int64_t g = ((int64_t)blockIdx.x * 4 + wave) * rpw + sub;
+  int64_t b, e, row = -1;
+  if (g < n_chunks) {
+    const ChunkTask t = tasks[g];
+    b = t.begin;
+    e = t.end;
+  } else {
+    row = g - n_chunks;
+    if (row >= R) return;
+    b = rp[row];
+    e = rp[row + 1];
+    if (e - b > long_row) return;  // handled by its chunks
+  }
+  TA acc[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) acc[i] = (TA)0;
+  const TX *xb = X + cl * V;
+  int64_t j = b;
+  for (; j + 4 <= e; j += 4) {
+    const int32_t c0 = col[j], c1 = col[j + 1], c2 = col[j + 2], c3 = col[j + 3];
+    const TA v0 = (TA)val[j], v1 = (TA)val[j + 1], v2 = (TA)val[j + 2], v3 = (TA)val[j + 3];
+    TA x0[V], x1[V], x2[V], x3[V];
+    load_n<TX, TA, V>(xb + (int64_t)c0 * ldx, x0);
+    load_n<TX, TA, V>(xb + (int64_t)c1 * ldx, x1);
+    load_n<TX, TA, V>(xb + (int64_t)c2 * ldx, x2);
+    load_n<TX, TA, V>(xb + (int64_t)c3 * ldx, x3);
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      acc[i] = fma(v0, x0[i], acc[i]);
+      acc[i] = fma(v1, x1[i], acc[i]);
+      acc[i] = fma(v2, x2[i], acc[i]);
+      acc[i] = fma(v3, x3[i], acc[i]);
+    }
+  }
+  for (; j < e; ++j) {
+    const int32_t c0 = col[j];
+    const TA v0 = (TA)val[j];
+    TA x0[V];
+    load_n<TX, TA, V>(xb + (int64_t)c0 * ldx, x0);
+#pragma unroll
+    for (int i = 0; i < V; ++i) acc[i] = fma(v0, x0[i], acc[i]);
+  }
+  if (row < 0) {
+    store_n<TA, TA, V>(partial + g * ldp + cl * V, acc);
+    return;
+  }
+  if constexpr (SHIFT) {
+    const TA a = (TA)(*alpha);
+    TA q[V];
+    load_n<TX, TA, V>(Q + row * ldq + cl * V, q);
+#pragma unroll
+    for (int i = 0; i < V; ++i) acc[i] = acc[i] - a * q[i];
+  }
+  store_n<TY, TA, V>(Y + row * ldy + cl * V, acc);
+}
+
+template <typename TX, typename TY, typename TA, bool SHIFT>
+__global__ __launch_bounds__(256) void k_spmm_long(
+    int64_t n_long, const LongRow *__restrict__ longs, const TA *__restrict__ partial, int64_t ldp,
+    TY *__restrict__ Y, int64_t ldy, int G, const TX *__restrict__ Q, int64_t ldq,
+    const double *__restrict__ alpha, const int32_t *__restrict__ done) {
+  if (done && *done) return;
+  constexpr int V = vec16<TX, TA>::N;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rpw = kWave / G;
+  const int sub = lane / G, cl = lane - sub * G;
+  if (sub >= rpw) return;
+  const int64_t g = ((int64_t)blockIdx.x * 4 + wave) * rpw + sub;
+  if (g >= n_long) return;
+  const LongRow lr = longs[g];
+  TA acc[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) acc[i] = (TA)0;
+  for (int64_t c = 0; c < lr.nch; ++c) {
+    TA p[V];
+    load_n<TA, TA, V>(partial + (lr.first + c) * ldp + cl * V, p);
+#pragma unroll
+    for (int i = 0; i < V; ++i) acc[i] += p[i];
+  }
+  if constexpr (SHIFT) {
+    const TA a = (TA)(*alpha);
+    TA q[V];
+    load_n<TX, TA, V>(Q + lr.row * ldq + cl * V, q);
+#pragma unroll
+    for (int i = 0; i < V; ++i) acc[i] = acc[i] - a * q[i];
+  }
+  store_n<TY, TA, V>(Y + lr.row * ldy + cl * V, acc);
+}
+
+template <typename TV, typename TX, typename TY>
+hipError_t run_spmm(int64_t R, const int64_t *rp, const int32_t *col, const void *val, const void *X,
+                    int64_t ldx, void *Y, int64_t ldy, int ld_cols, int64_t n_chunks,
+                    const ChunkTask *tasks, int64_t n_long, const LongRow *longs, void *partial,
+                    int32_t long_row, const void *Q, int64_t ldq, const double *alpha,
+                    const int32_t *done, hipStream_t st) {
+  using TA = typename acc_of<TX>::type;
+  constexpr int V = vec16<TX, TA>::N;
+  const int G = ld_cols / V;
+  if (G < 1 || G > kWave || ld_cols % V) return hipErrorInvalidValue;
+  const int rpw = kWave / G;
+  const int64_t subs = n_chunks + R;
+  const int64_t blocks = (subs + 4 * rpw - 1) / (4 * rpw);
+  const bool shift = alpha != nullptr;
+  if (blocks > 0) {
+    if (shift)
+      hipLaunchKernelGGL((k_spmm<TV, TX, TY, TA, true>), dim3((unsigned)blocks), dim3(256), 0, st, R, rp, col,
+                         (const TV *)val, (const TX *)X, ldx, (TY *)Y, ldy, G, n_chunks, tasks,
+                         (TA *)partial, (int64_t)ld_cols, long_row, (const TX *)Q, ldq, alpha, done);
+    else
+      hipLaunchKernelGGL((k_spmm<TV, TX, TY, TA, false>), dim3((unsigned)blocks), dim3(256), 0, st, R, rp, col,
+                         (const TV *)val, (const TX *)X, ldx, (TY *)Y, ldy, G, n_chunks, tasks,
+                         (TA *)partial, (int64_t)ld_cols, long_row, (const TX *)Q, ldq, alpha, done);
+  }
+  if (n_long > 0) {
+    const int64_t lb = (n_long + 4 * rpw - 1) / (4 * rpw);
+    if (shift)
+      hipLaunchKernelGGL((k_spmm_long<TX, TY, TA, true>), dim3((unsigned)lb), dim3(256), 0, st, n_long, longs,
+                         (const TA *)partial, (int64_t)ld_cols, (TY *)Y, ldy, G, (const TX *)Q, ldq, alpha,
+                         done);
+    else
+      hipLaunchKernelGGL((k_spmm_long<TX, TY, TA, false>), dim3((unsigned)lb), dim3(256), 0, st, n_long, longs,
+                         (const TA *)partial, (int64_t)ld_cols, (TY *)Y, ldy, G, (const TX *)Q, ldq, alpha,
+                         done);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_spmm(int64_t R, const int64_t *rp, const int32_t *col, const void *val, int vdtype,
+                       const void *X, int64_t ldx, int xdtype, void *Y, int64_t ldy, int ydtype,
+                       int ld_cols, int64_t n_chunks, const ChunkTask *tasks, int64_t n_long,
+                       const LongRow *longs, void *partial, int32_t long_row, const void *Q,
+                       int64_t ldq, const double *alpha, const int32_t *done, hipStream_t st) {
+  // supported combinations: (values, X/Q, Y) = (f32, f32, f32), (f64, f64, f64),
+  // (f32, bf16, bf16), (f32, bf16, f32)
+  if (xdtype == 0 && ydtype == 0 && vdtype == 0)
+    return run_spmm<float, float, float>(R, rp, col, val, X, ldx, Y, ldy, ld_cols, n_chunks, tasks, n_long,
+                                         longs, partial, long_row, Q, ldq, alpha, done, st);
+  if (xdtype == 1 && ydtype == 1 && vdtype == 1)
+    return run_spmm<double, double, double>(R, rp, col, val, X, ldx, Y, ldy, ld_cols, n_chunks, tasks,
+                                            n_long, longs, partial, long_row, Q, ldq, alpha, done, st);
+  if (xdtype == 2 && ydtype == 2 && vdtype == 0)
+    return run_spmm<float, bf16, bf16>(R, rp, col, val, X, ldx, Y, ldy, ld_cols, n_chunks, tasks, n_long,
+                                       longs, partial, long_row, Q, ldq, alpha, done, st);
+  if (xdtype == 2 && ydtype == 0 && vdtype == 0)
+    return run_spmm<float, bf16, float>(R, rp, col, val, X, ldx, Y, ldy, ld_cols, n_chunks, tasks, n_long,
+                                        longs, partial, long_row, Q, ldq, alpha, done, st);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace dsv

@@ -1,0 +1,210 @@
+"""End-to-end parity of dashsvd_run (HIP) with the FP64 CPU oracle (Alg. 5),
+on the same seeded inputs and the same Philox-drawn Omega.
+
+Bars: sigma within 1e-10 relative in the FP64 form and 1e-5 in the FP32
+form at an equal pass count; equal N_p on tolerance-driven runs; per-pass
+shifts and PVE ratios equal to the oracle's within the same bars."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch
+
+
+def _solve(A, k, s, p_max, tol, seed, precision="fp64", **kw):
+    from paper_2404_09276_amd import DashSVD
+    h = DashSVD(precision=precision, p_max=p_max, seed=seed, **kw)
+    U, S, V, st, info = h.solve(A, k, s, tol)
+    tr = h.trace()
+    h.close()
+    return U, S, V, st, info, tr
+
+
+def _vec_close(X, Xref, tol):
+    """Columns equal up to sign (signs are normalised on both sides, but an
+    argmax tie between two near-equal entries could flip one)."""
+    d = np.minimum(np.abs(X - Xref).max(axis=0), np.abs(X + Xref).max(axis=0))
+    return d.max() <= tol
+
+
+def test_small_fp64_fixed_passes(torch_dev):
+    """2000 x 1500 uniform, k=20, s=10, 5 passes (Alg. 4): FP64 parity."""
+    A = synth.config_small(np.float64)
+    ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 20, 10, 5, 0.0, seed=2001)
+    U, S, V, st, info, tr = _solve(A, 20, 10, 5, 0.0, 2001, "fp64")
+    assert st == 0 and info.passes == 5
+    assert np.abs(S - ref.S).max() / ref.S.max() <= 1e-10
+    assert np.abs(S - ref.S).max() <= 1e-10 * np.abs(ref.S).min() * 10
+    assert np.allclose(info.alpha_used, ref.alpha, rtol=1e-10, atol=0)
+    assert np.allclose(info.ratio, ref.ratio, rtol=1e-9, atol=0)
+    assert np.allclose(tr, ref.s_hat, rtol=1e-10, atol=1e-12 * ref.s_hat.max())
+    assert _vec_close(U, ref.U, 1e-8) and _vec_close(V, ref.V, 1e-8)
+
+
+def test_small_fp32_fixed_passes(torch_dev):
+    A = synth.config_small(np.float32)
+    ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 20, 10, 5, 0.0, seed=2001)
+    U, S, V, st, info, tr = _solve(A, 20, 10, 5, 0.0, 2001, "fp32")
+    assert info.passes == 5
+    assert np.all(np.abs(S - ref.S) / ref.S <= 1e-5)
+    assert np.allclose(info.alpha_used, ref.alpha, rtol=1e-5)
+    assert np.abs(U.T @ U - np.eye(20)).max() < 1e-5
+    assert np.abs(V.T @ V - np.eye(20)).max() < 1e-5
+    assert _vec_close(V, ref.V, 2e-3)
+
+
+@pytest.mark.parametrize("mode", ["r2", "r1"])
+def test_small_tolerance_run_equal_passes(torch_dev, mode):
+    A = synth.config_small(np.float64)
+    pm = oracle.PVE_R1 if mode == "r1" else oracle.PVE_R2
+    ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 20, 10, 64, 1e-2, seed=2001, pve_mode=pm)
+    for prec, bar in (("fp64", 1e-10), ("fp32", 1e-5)):
+        U, S, V, st, info, tr = _solve(A, 20, 10, 64, 1e-2, 2001, prec, pve_mode=mode)
+        assert info.converged and st == 0
+        borderline = np.any(np.abs(ref.ratio - 1e-2) < 1e-6 * 1e-2)
+        if not borderline:
+            assert info.passes == ref.passes
+        assert np.all(np.abs(S - ref.S) / ref.S <= bar)
+
+
+@pytest.mark.parametrize("policy", ["none", "fixed"])
+def test_shift_policies(torch_dev, policy):
+    A = synth.config_small(np.float64)
+    pol = {"none": oracle.SHIFT_NONE, "fixed": oracle.SHIFT_FIXED}[policy]
+    ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 20, 10, 6, 0.0, seed=5, shift_policy=pol)
+    U, S, V, st, info, tr = _solve(A, 20, 10, 6, 0.0, 5, "fp64", shift_policy=policy)
+    assert np.allclose(info.alpha_used, ref.alpha, rtol=1e-10, atol=0)
+    assert np.abs(S - ref.S).max() / ref.S.max() <= 1e-10
+
+
+def test_schedule_policy(torch_dev):
+    A = synth.config_small(np.float64)
+    sched = np.r_[0.5, 0.5, 0.7, 0.8, 0.8, 0.9, 0.9, 0.9, 0.9]
+    ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 20, 10, 8, 0.0, seed=6,
+                         shift_policy=oracle.SHIFT_SCHEDULE, sched=sched)
+    U, S, V, st, info, tr = _solve(A, 20, 10, 8, 0.0, 6, "fp64", shift_policy="schedule",
+                                   schedule=sched)
+    assert np.allclose(info.alpha_used, ref.alpha, rtol=1e-10, atol=0)
+    assert np.abs(S - ref.S).max() / ref.S.max() <= 1e-10
+
+
+@pytest.mark.parametrize("mode", ["R2", "R1", "NONE"])
+def test_rank_l_golden_on_gpu(torch_dev, mode):
+    """The hand-derived shift / ratio sequences of a rank-l matrix."""
+    g = json.load(open(os.path.join(GOLDEN, "rank_l_shift_sequence.json")))
+    rng = np.random.default_rng(123)
+    sig = np.array(g["sigma"])
+    Uo, _ = np.linalg.qr(rng.standard_normal((g["m"], len(sig))))
+    Vo, _ = np.linalg.qr(rng.standard_normal((g["n"], len(sig))))
+    A = synth.dense_to_csr((Uo * sig) @ Vo.T)
+    U, S, V, st, info, tr = _solve(A, g["k"], g["s"], 10, g["tol"], 4, "fp64",
+                                   shift_policy="none" if mode == "NONE" else "paper",
+                                   pve_mode="r1" if mode == "R1" else "r2")
+    exp = g[mode]
+    assert info.passes == exp["passes"]
+    assert np.allclose(info.alpha_used, exp["alpha_used"], rtol=1e-11, atol=1e-11)
+    assert np.allclose(info.ratio, exp["ratio"], rtol=1e-11, atol=1e-11)
+    assert np.allclose(S, sig[:g["k"]], rtol=1e-12)
+
+
+def test_wide_matrix(torch_dev):
+    A = synth.uniform_csr(300, 700, 9000, seed=8, dtype=np.float64)
+    ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 8, 8, 6, 0.0, seed=12)
+    U, S, V, st, info, tr = _solve(A, 8, 8, 6, 0.0, 12, "fp64")
+    assert U.shape == (300, 8) and V.shape == (700, 8)
+    assert np.abs(S - ref.S).max() / ref.S.max() <= 1e-10
+    assert _vec_close(U, ref.U, 1e-8) and _vec_close(V, ref.V, 1e-8)
+
+
+def test_zipf_fp32_ragged_and_long_rows(torch_dev):
+    """Power-law rows and columns (long-row chunks on both sides), l = 30."""
+    A = synth.zipf_csr(30000, 12000, 600000, seed=21)
+    ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 20, 10, 4, 0.0, seed=22)
+    U, S, V, st, info, tr = _solve(A, 20, 10, 4, 0.0, 22, "fp32")
+    assert info.long_chunks_A > 0 and info.long_chunks_AT > 0
+    assert np.all(np.abs(S - ref.S) / ref.S <= 1e-5)
+    assert np.allclose(info.alpha_used, ref.alpha, rtol=1e-5)
+
+
+def test_zipf_fp64_l150(torch_dev):
+    A = synth.zipf_csr(8000, 5000, 200000, seed=31)
+    A.val = A.val.astype(np.float64)
+    ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 100, 50, 3, 0.0, seed=32)
+    U, S, V, st, info, tr = _solve(A, 100, 50, 3, 0.0, 32, "fp64")
+    assert np.abs(S - ref.S).max() / ref.S.max() <= 1e-10
+    assert np.allclose(tr, ref.s_hat, rtol=1e-9, atol=1e-11 * ref.s_hat.max())
+
+
+def test_device_resident_input_and_output(torch_dev):
+    torch = torch_dev
+    from paper_2404_09276_amd import DashSVD
+    A = synth.config_small(np.float32)
+
+    class Dev:
+        m, n = A.m, A.n
+        row_ptr = torch.from_numpy(A.row_ptr).cuda()
+        col = torch.from_numpy(A.col).cuda()
+        val = torch.from_numpy(A.val).cuda()
+    h = DashSVD(precision="fp32", p_max=5, seed=2001, stream=torch.cuda.current_stream())
+    h.run(Dev, 20, 10, 0.0)
+    U, S, V = h.get_usv(dtype="float32", device=True)
+    ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 20, 10, 5, 0.0, seed=2001)
+    assert np.all(np.abs(S.cpu().numpy() - ref.S) / ref.S <= 1e-5)
+    assert U.is_cuda and V.dtype == torch.float32
+
+
+def test_deterministic_repeat(torch_dev):
+    A = synth.zipf_csr(20000, 9000, 400000, seed=41)
+    r1 = _solve(A, 16, 8, 5, 0.0, 3, "fp32")
+    r2 = _solve(A, 16, 8, 5, 0.0, 3, "fp32")
+    assert np.array_equal(r1[1], r2[1]) and np.array_equal(r1[0], r2[0])
+
+
+def test_error_paths(torch_dev):
+    from paper_2404_09276_amd import DashSVD, DashSVDError
+    A = synth.uniform_csr(200, 150, 3000, seed=2)
+    h = DashSVD(p_max=3)
+    for k, s in ((20, 0), (100, 60), (0, 5)):
+        with pytest.raises(DashSVDError) as e:
+            h.run(A, k, s, 0.0)
+        assert e.value.status == -1
+    bad = synth.CSR(A.m, A.n, A.row_ptr, A.col.copy(), A.val.copy())
+    bad.col[3] = 10**6
+    with pytest.raises(DashSVDError) as e:
+        h.run(bad, 10, 5, 0.0)
+    assert e.value.status == -2
+    nanv = synth.CSR(A.m, A.n, A.row_ptr, A.col, A.val.copy())
+    nanv.val[0] = np.nan
+    with pytest.raises(DashSVDError) as e:
+        h.run(nanv, 10, 5, 0.0)
+    assert e.value.status == -3
+    # the handle is still usable, and p_max too small reports NOT_CONVERGED
+    st = h.run(A, 10, 5, 1e-12)
+    assert st == 1
+    U, S, V = h.get_usv()
+    assert np.all(np.isfinite(S))
+
+
+def test_rank_deficient_matrix(torch_dev):
+    rng = np.random.default_rng(4)
+    D = rng.standard_normal((300, 3)) @ rng.standard_normal((3, 200))
+    A = synth.dense_to_csr(D)
+    U, S, V, st, info, tr = _solve(A, 4, 4, 3, 0.0, 1, "fp64")
+    assert st == 2 and info.rank_deficient
+    sv = np.linalg.svd(D, compute_uv=False)
+    assert np.allclose(S[:3], sv[:3], rtol=1e-10)
