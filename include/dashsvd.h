@@ -113,7 +113,20 @@ typedef struct {
                              row-major, leading dimension l); NULL = draw from seed */
   int32_t omega_dtype;    /* DASHSVD_F32 / DASHSVD_F64 */
   int32_t omega_on_device;
+  int32_t timing;         /* 1: time each kernel group with HIP events on the stream
+                             (results in dashsvd_info.kt_ms / kt_count) */
 } dashsvd_options;
+
+/* Kernel groups timed when options.timing = 1 (index into kt_ms / kt_count). */
+#define DASHSVD_KT_SPMM 0        /* Y = M Q of a power pass (incl. long-row reduction) */
+#define DASHSVD_KT_SPMM_T 1      /* C = M^T Y - alpha Q of a power pass */
+#define DASHSVD_KT_GRAM 2        /* Gram partials + reduction (every eigSVD) */
+#define DASHSVD_KT_EIG 3         /* Jacobi eig + tail (every eigSVD) */
+#define DASHSVD_KT_RESCALE 4     /* Q = C W (every eigSVD of a power pass and the sketch) */
+#define DASHSVD_KT_TRANSPOSE 5   /* validation + CSR(A^T) build */
+#define DASHSVD_KT_SKETCH 6      /* Omega + M^T Omega */
+#define DASHSVD_KT_FINAL 7       /* B = M Q, its eigSVD, U, V, signs */
+#define DASHSVD_KT_GROUPS 8
 
 typedef struct {
   int32_t passes;          /* N_p: shifted power passes executed */
@@ -131,6 +144,8 @@ typedef struct {
   double time_final_ms;    /* final Rayleigh-Ritz and sign normalisation */
   int64_t long_chunks_A;   /* SpMM chunk tasks of the row-split plan, A side */
   int64_t long_chunks_AT;  /* same for A^T */
+  double kt_ms[8];         /* summed HIP-event time per kernel group (timing = 1) */
+  int32_t kt_count[8];     /* launches counted per group (passes after the stop excluded) */
 } dashsvd_info;
 
 typedef struct dashsvd_handle dashsvd_handle;

@@ -141,7 +141,8 @@ struct SolverState {
   int32_t deficient;
   int32_t sched_off;  // schedule dropped (guard)
   int32_t learned_ready;
-  int32_t pad[2];
+  int32_t skip_rescale;  // set by a pass's eig when the loop had already stopped
+  int32_t pad;
 };
 
 // ------------------------------------------------------------------ launchers
@@ -213,7 +214,7 @@ hipError_t launch_rescale(int64_t r, int l, const void *C, int64_t ldc, int cdty
                           int64_t ldw, int c, void *Out, int64_t ldo, int odtype,
                           const int32_t *done, hipStream_t st);
 
-// pmax: nblk*k doubles, pidx: nblk*k int64 (workspace)
+// pmax: nblk*k doubles, pidx: nblk*k int64 followed by k floats (workspace)
 hipError_t launch_sign_fix(int64_t rowsV, int64_t rowsU, int k, void *V, int64_t ldv, void *U,
                            int64_t ldu, int dtype, void *pmax, void *pidx, int nblk,
                            hipStream_t st);

@@ -78,9 +78,47 @@ struct dashsvd_handle {
   double *trace_s = nullptr;
   int trace_cap = 0;
   dashsvd_info info;
+  // kernel-group timing (options.timing)
+  std::vector<hipEvent_t> ev;
+  struct Mark {
+    int group, pass, e0, e1;
+  };
+  std::vector<Mark> marks;
+  int ev_used = 0;
+  int open_group = -1, open_pass = 0, open_e0 = 0;
 };
 
 namespace {
+
+hipEvent_t take_event(dashsvd_handle *h, int &idx) {
+  if (h->ev_used == (int)h->ev.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->ev.push_back(e);
+  }
+  idx = h->ev_used++;
+  return h->ev[idx];
+}
+
+// Open / close a timed kernel group on the handle's stream (no-op unless
+// options.timing is set).
+void tmark_begin(dashsvd_handle *h, int group, int pass) {
+  if (!h->opt.timing) return;
+  int i;
+  hipEvent_t e = take_event(h, i);
+  if (!e || hipEventRecord(e, h->st) != hipSuccess) return;
+  h->open_group = group;
+  h->open_pass = pass;
+  h->open_e0 = i;
+}
+void tmark_end(dashsvd_handle *h) {
+  if (!h->opt.timing || h->open_group < 0) return;
+  int i;
+  hipEvent_t e = take_event(h, i);
+  if (e && hipEventRecord(e, h->st) == hipSuccess)
+    h->marks.push_back({h->open_group, h->open_pass, h->open_e0, i});
+  h->open_group = -1;
+}
 
 dashsvd_status fail(dashsvd_handle *h, dashsvd_status s, const std::string &what) {
   if (h) h->err = what;
@@ -248,6 +286,7 @@ void dashsvd_destroy(dashsvd_handle *h) {
     (void)hipStreamSynchronize(h->st);
     (void)hipFree(h->ar.base);
   }
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   delete h;
 }
 
@@ -347,7 +386,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   b.Vo = ar.take(dsz(cdt) * (size_t)Mn * k);
   const int sgn_blk = 256;
   b.sgn_max = ar.take(8 * (size_t)sgn_blk * k);
-  b.sgn_idx = ar.take(8 * (size_t)sgn_blk * k);
+  b.sgn_idx = ar.take(8 * (size_t)sgn_blk * k + 4 * (size_t)k);
   if (h->opt.omega && !h->opt.omega_on_device)
     b.omega_dev = ar.take(dsz(h->opt.omega_dtype) * (size_t)Mm * l);
   if (measure_only) {
@@ -356,6 +395,9 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   }
 
   // ---------------------------------------------------------------- setup
+  h->marks.clear();
+  h->ev_used = 0;
+  h->open_group = -1;
   // control buffers start at zero; panels need no clearing (pad columns are
   // never read into the first l columns)
   HIPCHK(hipMemsetAsync(b.colcnt, 0, 8 * (size_t)(n + 1), st));
@@ -382,6 +424,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     HIPCHK(launch_convert(val_src, A->value_dtype, val_in, vdt, nnz, st));
     valA = val_in;
   }
+  tmark_begin(h, DASHSVD_KT_TRANSPOSE, 0);
   HIPCHK(launch_validate(m, n, nnz, rpA, colA, valA, vdt, b.colcnt, b.rowidx, b.flags, st));
   int32_t hflags[4] = {0, 0, 0, 0};
   HIPCHK(hipMemcpyAsync(hflags, b.flags, sizeof(hflags), hipMemcpyDeviceToHost, st));
@@ -398,6 +441,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   HIPCHK(hipStreamSynchronize(st));
   HIPCHK(launch_transpose_sort(m, n, b.rpT, b.tmp_row, b.tmp_src, valA, vdt, b.colT, b.valT, b.lists, hcounts,
                                b.bitmap, b.prefix, b.nblk_large, st));
+  tmark_end(h);
   // M and M^T
   const int64_t *rpM = wide ? b.rpT : rpA;
   const int32_t *colM = wide ? b.colT : colA;
@@ -444,8 +488,10 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
 
   // ---------------------------------------------------------------- eigSVD helper
   auto eigsvd = [&](int64_t rows, const void *Cm, int cm_dt, int mode, int nb, void *Qout, int q_dt,
-                    const int32_t *done) -> hipError_t {
+                    const int32_t *done, int pass) -> hipError_t {
+    tmark_begin(h, DASHSVD_KT_GRAM, pass);
     hipError_t e = launch_gram(rows, l, Cm, ld, cm_dt, b.gpart, nb, b.G, done, st);
+    tmark_end(h);
     if (e != hipSuccess) return e;
     EigArgs ea;
     std::memset(&ea, 0, sizeof(ea));
@@ -467,30 +513,46 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     ea.trace_cap = cap;
     ea.sched = h->sched.empty() ? nullptr : b.sched;
     ea.sched_len = (int)h->sched.size();
+    tmark_begin(h, DASHSVD_KT_EIG, pass);
     e = launch_eig(ea, st);
+    tmark_end(h);
     if (e != hipSuccess) return e;
-    if (Qout) e = launch_rescale(rows, l, Cm, ld, cm_dt, b.W, l, l, Qout, ld, q_dt, done, st);
+    if (Qout) {
+      tmark_begin(h, DASHSVD_KT_RESCALE, pass);
+      // the pass that meets the tolerance still updates Q (Alg. 5 step 4
+      // precedes the check); later passes skip it
+      const int32_t *skip = done ? &b.state->skip_rescale : nullptr;
+      e = launch_rescale(rows, l, Cm, ld, cm_dt, b.W, l, l, Qout, ld, q_dt, skip, st);
+      tmark_end(h);
+    }
     return e;
   };
   const int32_t *done = &b.state->done;
 
   // sketch: Y0 = M^T Omega -> C ; Q = eigSVD(C).U
+  tmark_begin(h, DASHSVD_KT_SKETCH, 0);
   HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ld, b.planT.n_chunks, b.planT.tasks,
                      b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr, nullptr, st));
-  HIPCHK(eigsvd(Mn, b.C, cdt, 1, nb_n, b.Q, pdt, nullptr));
+  tmark_end(h);
+  HIPCHK(eigsvd(Mn, b.C, cdt, 1, nb_n, b.Q, pdt, nullptr, 0));
   // power passes
   const int every = h->opt.check_interval > 0 ? h->opt.check_interval : 1;
   int launched = 0;
   while (launched < pmax) {
     const int chunk = (pmax - launched) < every ? (pmax - launched) : every;
     for (int c = 0; c < chunk; ++c) {
+      const int pass = launched + c + 1;
+      tmark_begin(h, DASHSVD_KT_SPMM, pass);
       HIPCHK(launch_spmm(Mm, rpM, colM, valM, vdt, b.Q, ld, pdt, b.Y, ld, pdt, ld, b.planM.n_chunks,
                          b.planM.tasks, b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr,
                          done, st));
+      tmark_end(h);
+      tmark_begin(h, DASHSVD_KT_SPMM_T, pass);
       HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ld, b.planT.n_chunks,
                          b.planT.tasks, b.planT.n_long, b.planT.longs, b.planT.partial, T, b.Q, ld,
                          &b.state->alpha, done, st));
-      HIPCHK(eigsvd(Mn, b.C, cdt, 2, nb_n, b.Q, pdt, done));
+      tmark_end(h);
+      HIPCHK(eigsvd(Mn, b.C, cdt, 2, nb_n, b.Q, pdt, done, pass));
     }
     launched += chunk;
     if (tol > 0.0 && launched < pmax) {
@@ -503,12 +565,18 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   HIPCHK(hipStreamSynchronize(st));
   const double t_loop = now_ms();
   // final Rayleigh-Ritz: B = M Q ; eigSVD(B) ; U = B W(:,1:k) ; V = Q Vs(:,1:k)
+  tmark_begin(h, DASHSVD_KT_FINAL, 0);
   HIPCHK(launch_spmm(Mm, rpM, colM, valM, vdt, b.Q, ld, pdt, b.B, ld, cdt, ld, b.planM.n_chunks, b.planM.tasks,
                      b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, nullptr, st));
-  HIPCHK(eigsvd(Mm, b.B, cdt, 3, nb_m, nullptr, cdt, nullptr));
+  const bool timing = h->opt.timing != 0;
+  h->opt.timing = 0;  // the final block is timed as one group
+  hipError_t efin = eigsvd(Mm, b.B, cdt, 3, nb_m, nullptr, cdt, nullptr, 0);
+  h->opt.timing = timing;
+  HIPCHK(efin);
   HIPCHK(launch_rescale(Mm, l, b.B, ld, cdt, b.W, l, k, b.Uo, k, cdt, nullptr, st));
   HIPCHK(launch_rescale(Mn, l, b.Q, ld, pdt, b.Vs, l, k, b.Vo, k, cdt, nullptr, st));
   HIPCHK(launch_sign_fix(Mn, Mm, k, b.Vo, k, b.Uo, k, cdt, b.sgn_max, b.sgn_idx, sgn_blk, st));
+  tmark_end(h);
   SolverState hs;
   HIPCHK(hipMemcpyAsync(&hs, b.state, sizeof(hs), hipMemcpyDeviceToHost, st));
   dashsvd_info &inf = h->info;
@@ -532,6 +600,14 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   inf.time_final_ms = t_end - t_loop;
   inf.long_chunks_A = wide ? b.planT.n_chunks : b.planM.n_chunks;
   inf.long_chunks_AT = wide ? b.planM.n_chunks : b.planT.n_chunks;
+  for (const auto &mk : h->marks) {
+    if (mk.pass > hs.pass) continue;  // passes launched after the stop returned at once
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->ev[mk.e0], h->ev[mk.e1]) == hipSuccess) {
+      inf.kt_ms[mk.group] += ms;
+      inf.kt_count[mk.group] += 1;
+    }
+  }
   // results in the caller's orientation
   h->m = m;
   h->n = n;

@@ -15,9 +15,9 @@
 // wavefront computes a 16-row strip of all output tiles with
 // v_mfma_f32_16x16x4.  FP64 path: plain FP64 FMAs (used for the FP64 form).
 //
-// MFMA operand layout assumed (16x16x4, one block): lane L holds A[L%16][L/16]
-// and B[L/16][L%16]; the accumulator's register q of lane L is
-// D[4*(L/16)+q][L%16].
+// MFMA operand layout (16x16x4, one block): lane L holds A[L%16][L/16] and
+// B[L/16][L%16].  Accumulators: FP32 register q of lane L is D[4*(L/16)+q][L%16];
+// FP64 register q of lane L is D[L/16+4q][L%16].
 #include "common.h"
 
 namespace dsv {
@@ -77,8 +77,14 @@ __global__ __launch_bounds__(256) void k_gram_partial(int64_t r, int l, const TC
 #pragma unroll
       for (int i = 0; i < TPW; ++i) {
         if (wave + 4 * i < NT) {
+          // The B column offset is made opaque to the compiler so that a
+          // diagonal tile loads A and B into different registers: an FP64
+          // MFMA fed the same VGPR pair as both operands returned wrong rows
+          // 8-15 of the tile on gfx950.
+          int jo = tJ[i] * 16;
+          asm volatile("" : "+v"(jo));
           const double a = trow[tI[i] * 16];
-          const double b = trow[tJ[i] * 16];
+          const double b = trow[jo];
           acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[i], 0, 0, 0);
         }
       }
@@ -114,7 +120,8 @@ __global__ __launch_bounds__(256) void k_gram_reduce(int l, int nblocks, const d
     ++I;
   }
   const int J = I + t;
-  const int row = I * 16 + 4 * (lane >> 4) + q;
+  // FP64 16x16x4 accumulator: register q of lane L holds D[L/16 + 4q][L%16]
+  const int row = I * 16 + (lane >> 4) + 4 * q;
   const int col = J * 16 + (lane & 15);
   if (row >= l || col >= l) return;
   if (I == J && row > col) return;
@@ -254,12 +261,13 @@ __global__ __launch_bounds__(256) void k_sign_partial(int64_t rows, int k, const
   }
 }
 
+// One block: combine the per-block partial maxima in block order and store
+// the sign of each column (+1 / -1) before any element is flipped.
 template <typename T>
-__global__ __launch_bounds__(256) void k_sign_apply(int64_t rowsV, int64_t rowsU, int k, T *__restrict__ V,
-                                                    int64_t ldv, T *__restrict__ U, int64_t ldu,
-                                                    const double *__restrict__ pmax,
-                                                    const int64_t *__restrict__ pidx, int nblk) {
-  __shared__ float sgn[256];
+__global__ __launch_bounds__(256) void k_sign_select(int k, const T *__restrict__ V, int64_t ldv,
+                                                     const double *__restrict__ pmax,
+                                                     const int64_t *__restrict__ pidx, int nblk,
+                                                     float *__restrict__ sgn) {
   for (int c = threadIdx.x; c < k; c += blockDim.x) {
     double best = -1.0;
     int64_t bi = INT64_MAX;
@@ -273,7 +281,12 @@ __global__ __launch_bounds__(256) void k_sign_apply(int64_t rowsV, int64_t rowsU
     }
     sgn[c] = (bi != INT64_MAX && to_d(V[bi * ldv + c]) < 0.0) ? -1.0f : 1.0f;
   }
-  __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sign_apply(int64_t rowsV, int64_t rowsU, int k, T *__restrict__ V,
+                                                    int64_t ldv, T *__restrict__ U, int64_t ldu,
+                                                    const float *__restrict__ sgn) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t tv = rowsV * k, tu = rowsU * k;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tv + tu; e += stride) {
@@ -424,17 +437,23 @@ hipError_t launch_sign_fix(int64_t rowsV, int64_t rowsU, int k, void *V, int64_t
                            hipStream_t st) {
   double *pmax = static_cast<double *>(pmax_v);
   int64_t *pidx = static_cast<int64_t *>(pidx_v);
+  float *sgn = reinterpret_cast<float *>(pidx + (int64_t)nblk * k);  // k floats after the indices
   if (k < 1 || k > 256) return hipErrorInvalidValue;
+  const int ga = grid_for((rowsV + rowsU) * k, 256, 4096);
   if (dtype == 1) {
     hipLaunchKernelGGL(k_sign_partial<double>, dim3(nblk), dim3(256), 0, st, rowsV, k, (const double *)V, ldv,
                        pmax, pidx);
-    hipLaunchKernelGGL(k_sign_apply<double>, dim3(grid_for((rowsV + rowsU) * k, 256, 4096)), dim3(256), 0, st,
-                       rowsV, rowsU, k, (double *)V, ldv, (double *)U, ldu, pmax, pidx, nblk);
+    hipLaunchKernelGGL(k_sign_select<double>, dim3(1), dim3(256), 0, st, k, (const double *)V, ldv, pmax, pidx,
+                       nblk, sgn);
+    hipLaunchKernelGGL(k_sign_apply<double>, dim3(ga), dim3(256), 0, st, rowsV, rowsU, k, (double *)V, ldv,
+                       (double *)U, ldu, sgn);
   } else {
     hipLaunchKernelGGL(k_sign_partial<float>, dim3(nblk), dim3(256), 0, st, rowsV, k, (const float *)V, ldv,
                        pmax, pidx);
-    hipLaunchKernelGGL(k_sign_apply<float>, dim3(grid_for((rowsV + rowsU) * k, 256, 4096)), dim3(256), 0, st,
-                       rowsV, rowsU, k, (float *)V, ldv, (float *)U, ldu, pmax, pidx, nblk);
+    hipLaunchKernelGGL(k_sign_select<float>, dim3(1), dim3(256), 0, st, k, (const float *)V, ldv, pmax, pidx,
+                       nblk, sgn);
+    hipLaunchKernelGGL(k_sign_apply<float>, dim3(ga), dim3(256), 0, st, rowsV, rowsU, k, (float *)V, ldv,
+                       (float *)U, ldu, sgn);
   }
   return hipGetLastError();
 }

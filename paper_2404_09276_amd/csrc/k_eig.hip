@@ -64,7 +64,14 @@ __device__ __forceinline__ int slot_of(int parity, int g) { return parity ? g - 
 template <int MAXNR>
 __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
   SolverState *state = a.state;
-  if (state && a.mode == 2 && state->done) return;
+  if (state && a.mode == 2) {
+    // a pass launched after the check already passed: nothing to do, and
+    // its rescale must not run either
+    const int stopped = state->done;
+    __syncthreads();
+    if (threadIdx.x == 0) state->skip_rescale = stopped;
+    if (stopped) return;
+  }
   extern __shared__ double G[];  // packed upper, L(L+1)/2
   __shared__ double rc[kMaxPairs], rs[kMaxPairs], rt[kMaxPairs];
   __shared__ int rrot[kMaxPairs];

