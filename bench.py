@@ -140,7 +140,8 @@ def main():
         "config": {"workload": "zipf_200k: CSR 200000x100000, 10M nnz, Zipf 1.1 degrees, "
                                "k=100, oversampling 20, PVE tol 1e-2, FP32 panels",
                    "form": "plain FP32", "passes": inf.passes, "converged": inf.converged,
-                   "eps_pve": pve, "eps_sigma": es},
+                   "eps_pve": pve, "eps_sigma": es, "eig_calls": inf.eig_calls,
+                   "eig_sweeps": inf.eig_sweeps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "SpMM pair per pass (Y = A Q; C = A^T Y - alpha Q)",

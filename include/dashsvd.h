@@ -146,6 +146,8 @@ typedef struct {
   int64_t long_chunks_AT;  /* same for A^T */
   double kt_ms[8];         /* summed HIP-event time per kernel group (timing = 1) */
   int32_t kt_count[8];     /* launches counted per group (passes after the stop excluded) */
+  int32_t eig_calls;       /* eigSVD eigenproblems solved in the run */
+  int32_t eig_sweeps;      /* Jacobi sweeps summed over them */
 } dashsvd_info;
 
 typedef struct dashsvd_handle dashsvd_handle;
@@ -239,6 +241,11 @@ dashsvd_status dashsvd_k_gram(int64_t r, int32_t l, const void *C, int64_t ldc, 
  * (optional, device int) receives the sweep count. */
 dashsvd_status dashsvd_k_eig(int32_t l, const double *G, double *S, double *Vs, double *W,
                              int32_t *sweeps, void *stream);
+/* dashsvd_k_eig with a step profile: prof (device, 4 int64) accumulates the
+ * cycles of the rotation phase, the cycles of the update phase, the 100 MHz
+ * wall-clock ticks and the number of Jacobi steps. */
+dashsvd_status dashsvd_k_eig_prof(int32_t l, const double *G, double *S, double *Vs, double *W,
+                                  int32_t *sweeps, long long *prof, void *stream);
 
 /* Out (r x c, ldo, odtype) = C (r x l, ldc, cdtype) * W (l x c, FP64,
  * row-major, leading dimension ldw): the rescale U = C V S^-1 of Alg. 3

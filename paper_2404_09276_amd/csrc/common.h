@@ -142,7 +142,10 @@ struct SolverState {
   int32_t sched_off;  // schedule dropped (guard)
   int32_t learned_ready;
   int32_t skip_rescale;  // set by a pass's eig when the loop had already stopped
-  int32_t pad;
+  int32_t eig_calls;     // eigSVD calls that ran, and their Jacobi sweeps
+  int32_t eig_sweeps;
+  int32_t pass_skip;     // snapshot of done at the start of the current pass
+  int32_t pad[2];
 };
 
 // ------------------------------------------------------------------ launchers
@@ -183,8 +186,10 @@ hipError_t launch_spmm(int64_t R, const int64_t *rp, const int32_t *col, const v
                        const LongRow *longs, void *partial, int32_t long_row, const void *Q,
                        int64_t ldq, const double *alpha, const int32_t *done, hipStream_t st);
 
+// snap (optional): receives *done as read at the start of the Gram kernel,
+// i.e. whether the iteration had already stopped when this pass began.
 hipError_t launch_gram(int64_t r, int l, const void *C, int64_t ldc, int cdtype, double *partial,
-                       int nblocks, double *G, const int32_t *done, hipStream_t st);
+                       int nblocks, double *G, const int32_t *done, hipStream_t st, int32_t *snap);
 int gram_blocks(int64_t r, int l);
 size_t gram_partial_elems(int nblocks, int l);
 
@@ -192,6 +197,7 @@ size_t gram_partial_elems(int nblocks, int l);
 // 1 = sketch, 2 = power pass (PVE check + shift update), 3 = final.
 struct EigArgs {
   int l, k;
+  double skip;      // Jacobi threshold: rotate only if |g_pq| > skip sqrt(|g_pp g_qq|)
   const double *G;
   double *S;        // l, descending
   double *Vs;       // l x l, eigenvectors in descending order (may be null)
@@ -207,6 +213,7 @@ struct EigArgs {
   int trace_cap;
   const double *sched;  // device multipliers (SCHEDULE / LEARNED), may be null
   int sched_len;
+  long long *prof;      // optional step profile (6 counters), null in the solver
 };
 hipError_t launch_eig(const EigArgs &a, hipStream_t st);
 

@@ -27,7 +27,7 @@ namespace {
 
 thread_local std::string g_create_error;
 
-constexpr int kDefaultLongRow = 256;
+constexpr int kDefaultLongRow = 128;
 constexpr int kDefaultPmax = 64;
 
 size_t dsz(int dt) { return dt == DASHSVD_F64 ? 8 : (dt == DASHSVD_BF16 ? 2 : 4); }
@@ -86,6 +86,9 @@ struct dashsvd_handle {
   std::vector<Mark> marks;
   int ev_used = 0;
   int open_group = -1, open_pass = 0, open_e0 = 0;
+  // second stream for the eigensolver, overlapped with the next SpMM
+  hipStream_t st2 = nullptr;
+  hipEvent_t ev_gram = nullptr, ev_eig = nullptr;
 };
 
 namespace {
@@ -102,20 +105,20 @@ hipEvent_t take_event(dashsvd_handle *h, int &idx) {
 
 // Open / close a timed kernel group on the handle's stream (no-op unless
 // options.timing is set).
-void tmark_begin(dashsvd_handle *h, int group, int pass) {
+void tmark_begin(dashsvd_handle *h, int group, int pass, hipStream_t on = nullptr) {
   if (!h->opt.timing) return;
   int i;
   hipEvent_t e = take_event(h, i);
-  if (!e || hipEventRecord(e, h->st) != hipSuccess) return;
+  if (!e || hipEventRecord(e, on ? on : h->st) != hipSuccess) return;
   h->open_group = group;
   h->open_pass = pass;
   h->open_e0 = i;
 }
-void tmark_end(dashsvd_handle *h) {
+void tmark_end(dashsvd_handle *h, hipStream_t on = nullptr) {
   if (!h->opt.timing || h->open_group < 0) return;
   int i;
   hipEvent_t e = take_event(h, i);
-  if (e && hipEventRecord(e, h->st) == hipSuccess)
+  if (e && hipEventRecord(e, on ? on : h->st) == hipSuccess)
     h->marks.push_back({h->open_group, h->open_pass, h->open_e0, i});
   h->open_group = -1;
 }
@@ -205,6 +208,7 @@ struct RunBufs {
   void *Q = nullptr;   // M_n x ld, panel type
   void *C = nullptr;   // M_n x ld, C type (f32 / f64)
   void *B = nullptr;   // M_m x ld, C type (final block)
+  void *Z = nullptr;   // M_m x ld, C type: M C, rescaled into the next Y
   double *gpart = nullptr, *G = nullptr, *W = nullptr, *Vs = nullptr, *S = nullptr, *Sprev = nullptr;
   SolverState *state = nullptr;
   double *tr_alpha = nullptr, *tr_ratio = nullptr, *tr_s = nullptr;
@@ -287,6 +291,9 @@ void dashsvd_destroy(dashsvd_handle *h) {
     (void)hipFree(h->ar.base);
   }
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  if (h->ev_gram) (void)hipEventDestroy(h->ev_gram);
+  if (h->ev_eig) (void)hipEventDestroy(h->ev_eig);
+  if (h->st2) (void)hipStreamDestroy(h->st2);
   delete h;
 }
 
@@ -370,6 +377,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   b.Q = ar.take(dsz(pdt) * (size_t)Mn * ld);
   b.C = ar.take(dsz(cdt) * (size_t)Mn * ld);
   b.B = pdt == cdt ? b.Y : ar.take(dsz(cdt) * (size_t)Mm * ld);
+  b.Z = ar.take(dsz(cdt) * (size_t)Mm * ld);
   const int nb_n = gram_blocks(Mn, l), nb_m = gram_blocks(Mm, l);
   b.gpart = (double *)ar.take(8 * gram_partial_elems(nb_n > nb_m ? nb_n : nb_m, l));
   b.G = (double *)ar.take(8 * (size_t)l * l);
@@ -486,17 +494,21 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   HIPCHK(hipStreamSynchronize(st));
   const double t_setup = now_ms();
 
-  // ---------------------------------------------------------------- eigSVD helper
-  auto eigsvd = [&](int64_t rows, const void *Cm, int cm_dt, int mode, int nb, void *Qout, int q_dt,
-                    const int32_t *done, int pass) -> hipError_t {
-    tmark_begin(h, DASHSVD_KT_GRAM, pass);
-    hipError_t e = launch_gram(rows, l, Cm, ld, cm_dt, b.gpart, nb, b.G, done, st);
-    tmark_end(h);
-    if (e != hipSuccess) return e;
+  // ---------------------------------------------------------------- eigSVD pieces
+  if (!h->st2) {
+    HIPCHK(hipStreamCreateWithFlags(&h->st2, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&h->ev_gram, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&h->ev_eig, hipEventDisableTiming));
+  }
+  hipStream_t st2 = h->st2;
+  auto make_eig = [&](int mode) {
     EigArgs ea;
     std::memset(&ea, 0, sizeof(ea));
     ea.l = l;
     ea.k = k;
+    // FP64 form: converge to half an ulp; FP32 / BF16 panels carry ~1e-7
+    // relative rounding, so the eigenvectors need no more than 2^-36
+    ea.skip = prec == DASHSVD_PREC_FP64 ? 0x1.0p-53 : 0x1.0p-36;
     ea.G = b.G;
     ea.S = b.S;
     ea.Vs = b.Vs;
@@ -513,46 +525,77 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     ea.trace_cap = cap;
     ea.sched = h->sched.empty() ? nullptr : b.sched;
     ea.sched_len = (int)h->sched.size();
+    return ea;
+  };
+  const int32_t *done = &b.state->done;
+  const int32_t *pass_skip = &b.state->pass_skip;
+  // One eigSVD block (Alg. 3 on C = the current block) overlapped with the
+  // next product:  G = C^T C ; [ eig(G) on the second stream || Z = M C ] ;
+  // Q = C W ; Y = Z W.  Since M Q = M (C W) = (M C) W, Y is the next pass's
+  // M Q without waiting for the eigensolver before the SpMM.  With the BF16
+  // panel form the plain order is used: Q = C W, then Y = M Q from BF16 Q.
+  const bool overlap = pdt == cdt;
+  auto block_step = [&](int mode, int pass, const int32_t *gate) -> hipError_t {
+    tmark_begin(h, DASHSVD_KT_GRAM, pass);
+    hipError_t e = launch_gram(Mn, l, b.C, ld, cdt, b.gpart, nb_n, b.G, gate, st, (int32_t *)pass_skip);
+    tmark_end(h);
+    if (e != hipSuccess) return e;
+    EigArgs ea = make_eig(mode);
+    const int32_t *skip = gate ? pass_skip : nullptr;
+    if (overlap) {
+      if ((e = hipEventRecord(h->ev_gram, st)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(st2, h->ev_gram, 0)) != hipSuccess) return e;
+      tmark_begin(h, DASHSVD_KT_EIG, pass, st2);
+      e = launch_eig(ea, st2);
+      tmark_end(h, st2);
+      if (e != hipSuccess) return e;
+      if ((e = hipEventRecord(h->ev_eig, st2)) != hipSuccess) return e;
+      tmark_begin(h, DASHSVD_KT_SPMM, pass);
+      e = launch_spmm(Mm, rpM, colM, valM, vdt, b.C, ld, cdt, b.Z, ld, cdt, ld, b.planM.n_chunks, b.planM.tasks,
+                      b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, skip, st);
+      tmark_end(h);
+      if (e != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(st, h->ev_eig, 0)) != hipSuccess) return e;
+      tmark_begin(h, DASHSVD_KT_RESCALE, pass);
+      e = launch_rescale(Mn, l, b.C, ld, cdt, b.W, l, l, b.Q, ld, pdt, skip, st);
+      if (e == hipSuccess) e = launch_rescale(Mm, l, b.Z, ld, cdt, b.W, l, l, b.Y, ld, pdt, skip, st);
+      tmark_end(h);
+      return e;
+    }
     tmark_begin(h, DASHSVD_KT_EIG, pass);
     e = launch_eig(ea, st);
     tmark_end(h);
     if (e != hipSuccess) return e;
-    if (Qout) {
-      tmark_begin(h, DASHSVD_KT_RESCALE, pass);
-      // the pass that meets the tolerance still updates Q (Alg. 5 step 4
-      // precedes the check); later passes skip it
-      const int32_t *skip = done ? &b.state->skip_rescale : nullptr;
-      e = launch_rescale(rows, l, Cm, ld, cm_dt, b.W, l, l, Qout, ld, q_dt, skip, st);
-      tmark_end(h);
-    }
+    tmark_begin(h, DASHSVD_KT_RESCALE, pass);
+    e = launch_rescale(Mn, l, b.C, ld, cdt, b.W, l, l, b.Q, ld, pdt, skip, st);
+    tmark_end(h);
+    if (e != hipSuccess) return e;
+    tmark_begin(h, DASHSVD_KT_SPMM, pass);
+    e = launch_spmm(Mm, rpM, colM, valM, vdt, b.Q, ld, pdt, b.Y, ld, pdt, ld, b.planM.n_chunks, b.planM.tasks,
+                    b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, skip, st);
+    tmark_end(h);
     return e;
   };
-  const int32_t *done = &b.state->done;
 
-  // sketch: Y0 = M^T Omega -> C ; Q = eigSVD(C).U
+  // sketch (Alg. 5 step 2): C = M^T Omega ; Q = eigSVD(C).U ; Y = M Q
   tmark_begin(h, DASHSVD_KT_SKETCH, 0);
   HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ld, b.planT.n_chunks, b.planT.tasks,
                      b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr, nullptr, st));
   tmark_end(h);
-  HIPCHK(eigsvd(Mn, b.C, cdt, 1, nb_n, b.Q, pdt, nullptr, 0));
-  // power passes
+  HIPCHK(block_step(1, 0, nullptr));
+  // power passes (steps 3-8): C = M^T Y - alpha Q ; eigSVD(C) ; check ; shift
   const int every = h->opt.check_interval > 0 ? h->opt.check_interval : 1;
   int launched = 0;
   while (launched < pmax) {
     const int chunk = (pmax - launched) < every ? (pmax - launched) : every;
     for (int c = 0; c < chunk; ++c) {
       const int pass = launched + c + 1;
-      tmark_begin(h, DASHSVD_KT_SPMM, pass);
-      HIPCHK(launch_spmm(Mm, rpM, colM, valM, vdt, b.Q, ld, pdt, b.Y, ld, pdt, ld, b.planM.n_chunks,
-                         b.planM.tasks, b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr,
-                         done, st));
-      tmark_end(h);
       tmark_begin(h, DASHSVD_KT_SPMM_T, pass);
       HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ld, b.planT.n_chunks,
                          b.planT.tasks, b.planT.n_long, b.planT.longs, b.planT.partial, T, b.Q, ld,
                          &b.state->alpha, done, st));
       tmark_end(h);
-      HIPCHK(eigsvd(Mn, b.C, cdt, 2, nb_n, b.Q, pdt, done, pass));
+      HIPCHK(block_step(2, pass, done));
     }
     launched += chunk;
     if (tol > 0.0 && launched < pmax) {
@@ -564,15 +607,17 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   }
   HIPCHK(hipStreamSynchronize(st));
   const double t_loop = now_ms();
-  // final Rayleigh-Ritz: B = M Q ; eigSVD(B) ; U = B W(:,1:k) ; V = Q Vs(:,1:k)
+  // final Rayleigh-Ritz (steps 9-11): B = M Q ; eigSVD(B) ; U = B W(:,1:k) ;
+  // V = Q Vs(:,1:k).  B is the last Y (= M Q); the BF16 form keeps an FP32 B.
   tmark_begin(h, DASHSVD_KT_FINAL, 0);
-  HIPCHK(launch_spmm(Mm, rpM, colM, valM, vdt, b.Q, ld, pdt, b.B, ld, cdt, ld, b.planM.n_chunks, b.planM.tasks,
-                     b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, nullptr, st));
-  const bool timing = h->opt.timing != 0;
-  h->opt.timing = 0;  // the final block is timed as one group
-  hipError_t efin = eigsvd(Mm, b.B, cdt, 3, nb_m, nullptr, cdt, nullptr, 0);
-  h->opt.timing = timing;
-  HIPCHK(efin);
+  if (pdt != cdt)
+    HIPCHK(launch_spmm(Mm, rpM, colM, valM, vdt, b.Q, ld, pdt, b.B, ld, cdt, ld, b.planM.n_chunks, b.planM.tasks,
+                       b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, nullptr, st));
+  HIPCHK(launch_gram(Mm, l, b.B, ld, cdt, b.gpart, nb_m, b.G, nullptr, st, nullptr));
+  {
+    EigArgs ea = make_eig(3);
+    HIPCHK(launch_eig(ea, st));
+  }
   HIPCHK(launch_rescale(Mm, l, b.B, ld, cdt, b.W, l, k, b.Uo, k, cdt, nullptr, st));
   HIPCHK(launch_rescale(Mn, l, b.Q, ld, pdt, b.Vs, l, k, b.Vo, k, cdt, nullptr, st));
   HIPCHK(launch_sign_fix(Mn, Mm, k, b.Vo, k, b.Uo, k, cdt, b.sgn_max, b.sgn_idx, sgn_blk, st));
@@ -589,6 +634,8 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   HIPCHK(hipStreamSynchronize(st));
   const double t_end = now_ms();
   inf.passes = hs.pass;
+  inf.eig_calls = hs.eig_calls;
+  inf.eig_sweeps = hs.eig_sweeps;
   inf.converged = hs.converged;
   inf.rank_deficient = hs.deficient;
   inf.l = l;
@@ -828,26 +875,37 @@ dashsvd_status dashsvd_k_gram(int64_t r, int32_t l, const void *C, int64_t ldc, 
   const int nb = gram_blocks(r, l);
   double *part = nullptr;
   HIPCHK(hipMalloc(&part, 8 * gram_partial_elems(nb, l)));
-  hipError_t e = launch_gram(r, l, C, ldc, cdtype, part, nb, G, nullptr, st);
+  hipError_t e = launch_gram(r, l, C, ldc, cdtype, part, nb, G, nullptr, st, nullptr);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   (void)hipFree(part);
   HIPCHK(e);
   return DASHSVD_OK;
 }
 
+dashsvd_status dashsvd_k_eig_prof(int32_t l, const double *G, double *S, double *Vs, double *W,
+                                  int32_t *sweeps, long long *prof, void *stream);
 dashsvd_status dashsvd_k_eig(int32_t l, const double *G, double *S, double *Vs, double *W, int32_t *sweeps,
                              void *stream) {
+  return dashsvd_k_eig_prof(l, G, S, Vs, W, sweeps, nullptr, stream);
+}
+
+// As dashsvd_k_eig, with an optional device array of 6 int64 step-profile
+// counters (phase-A cycles, phase-B cycles, 100 MHz ticks, steps) added to.
+dashsvd_status dashsvd_k_eig_prof(int32_t l, const double *G, double *S, double *Vs, double *W,
+                                  int32_t *sweeps, long long *prof, void *stream) {
   dashsvd_handle *h = nullptr;
   if (l < 1 || l > DASHSVD_MAX_L || !G || !S || !W) return fail(h, DASHSVD_ERR_INVALID_ARG, "eig arguments");
   EigArgs ea;
   std::memset(&ea, 0, sizeof(ea));
   ea.l = l;
   ea.k = 0;
+  ea.skip = 0x1.0p-53;
   ea.G = G;
   ea.S = S;
   ea.Vs = Vs;
   ea.W = W;
   ea.sweeps = sweeps;
+  ea.prof = prof;
   ea.mode = 0;
   HIPCHK(launch_eig(ea, (hipStream_t)stream));
   return DASHSVD_OK;
@@ -856,8 +914,9 @@ dashsvd_status dashsvd_k_eig(int32_t l, const double *G, double *S, double *Vs, 
 dashsvd_status dashsvd_k_rescale(int64_t r, int32_t l, const void *C, int64_t ldc, int32_t cdtype, const double *W,
                                  int64_t ldw, int32_t c, void *Out, int64_t ldo, int32_t odtype, void *stream) {
   dashsvd_handle *h = nullptr;
-  if (r < 1 || l < 1 || l > DASHSVD_MAX_L || c < 1 || c > DASHSVD_MAX_L || ldc < l || ldw < c || ldo < c)
-    return fail(h, DASHSVD_ERR_INVALID_ARG, "rescale arguments");
+  if (r < 1 || l < 1 || l > DASHSVD_MAX_L || c < 1 || c > DASHSVD_MAX_L || ldc < l || ldw < c || ldo < c ||
+      ldc % 8 || ((uintptr_t)C & 15))
+    return fail(h, DASHSVD_ERR_INVALID_ARG, "rescale arguments (ldc: multiple of 8, C 16-byte aligned)");
   HIPCHK(launch_rescale(r, l, C, ldc, cdtype, W, ldw, c, Out, ldo, odtype, nullptr, (hipStream_t)stream));
   return DASHSVD_OK;
 }

@@ -114,6 +114,47 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const int64_t *__rest
   if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = sums[nb];
 }
 
+// ------------------------------------------------------------------ hot-column table
+// Power-law matrices have columns shared by a large fraction of the rows, and
+// one global atomic per nonzero on such a column serialises.  Each block
+// therefore keeps an LDS hash table (column -> count) for the columns of its
+// contiguous range of nonzeros and flushes one global atomic per distinct
+// column; entries that find no free slot after a few probes use the global
+// atomic directly.
+constexpr int kHashSlots = 4096;
+constexpr int kElemPerThread = 16;
+constexpr int kElemPerBlock = 256 * kElemPerThread;
+
+__device__ __forceinline__ int hash_slot(int32_t c) {
+  return (int)(((uint32_t)c * 2654435761u) >> 20) & (kHashSlots - 1);
+}
+
+// Returns the slot holding column c (inserting it), or -1 when the probes fail.
+__device__ __forceinline__ int hash_insert(int32_t *keys, int32_t c) {
+  int h = hash_slot(c);
+#pragma unroll 1
+  for (int probe = 0; probe < 8; ++probe) {
+    const int32_t k = keys[h];
+    if (k == c) return h;
+    if (k == -1) {
+      const int32_t old = atomicCAS(keys + h, -1, c);
+      if (old == -1 || old == c) return h;
+    }
+    h = (h + 1) & (kHashSlots - 1);
+  }
+  return -1;
+}
+
+// Row of nonzero e: the last r in [0, m) with rp[r] <= e (in bounds whatever rp holds).
+__device__ __forceinline__ int64_t row_of(const int64_t *__restrict__ rp, int64_t m, int64_t e) {
+  int64_t lo = 0, hi = m - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (rp[mid] <= e) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 // ------------------------------------------------------------------ validation
 template <typename TV>
 __global__ __launch_bounds__(256) void k_validate(int64_t m, int64_t n, int64_t nnz,
@@ -123,47 +164,95 @@ __global__ __launch_bounds__(256) void k_validate(int64_t m, int64_t n, int64_t 
                                                   int64_t *__restrict__ colcnt,
                                                   int32_t *__restrict__ rowidx,
                                                   int32_t *__restrict__ flags) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  __shared__ int32_t keys[kHashSlots];
+  __shared__ int32_t cnts[kHashSlots];
   const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   // row pointer: starts at 0, nondecreasing, ends at nnz
-  for (int64_t r = t0; r < m; r += stride) {
+  for (int64_t r = t0; r < m; r += (int64_t)gridDim.x * blockDim.x) {
     if (rp[r] > rp[r + 1]) atomicOr(flags, 1);
   }
   if (t0 == 0 && (rp[0] != 0 || rp[m] != nnz)) atomicOr(flags, 1);
   if (m == 0) return;
-  for (int64_t e = t0; e < nnz; e += stride) {
-    // row of e: last r in [0, m) with rp[r] <= e; stays in bounds whatever rp holds
-    int64_t lo = 0, hi = m - 1;
-    while (lo < hi) {
-      int64_t mid = (lo + hi + 1) >> 1;
-      if (rp[mid] <= e) lo = mid; else hi = mid - 1;
+  for (int64_t base = (int64_t)blockIdx.x * kElemPerBlock; base < nnz;
+       base += (int64_t)gridDim.x * kElemPerBlock) {
+    for (int i = threadIdx.x; i < kHashSlots; i += blockDim.x) {
+      keys[i] = -1;
+      cnts[i] = 0;
     }
-    const int32_t c = col[e];
-    rowidx[e] = (int32_t)lo;
-    if (c < 0 || (int64_t)c >= n) {
-      atomicOr(flags, 1);
-      continue;
+    __syncthreads();
+    for (int i = 0; i < kElemPerThread; ++i) {
+      const int64_t e = base + (int64_t)i * blockDim.x + threadIdx.x;
+      if (e >= nnz) break;
+      const int64_t r = row_of(rp, m, e);
+      const int32_t c = col[e];
+      rowidx[e] = (int32_t)r;
+      if (c < 0 || (int64_t)c >= n) {
+        atomicOr(flags, 1);
+        continue;
+      }
+      if (e > rp[r] && e > 0 && col[e - 1] >= c) atomicOr(flags, 1);
+      const double v = (double)val[e];
+      if (!(v - v == 0.0)) atomicOr(flags, 2);
+      const int h = hash_insert(keys, c);
+      if (h >= 0) atomicAdd(cnts + h, 1);
+      else atomicAdd((unsigned long long *)(colcnt + c), 1ull);
     }
-    if (e > rp[lo] && e > 0 && col[e - 1] >= c) atomicOr(flags, 1);
-    const double v = (double)val[e];
-    if (!(v - v == 0.0)) atomicOr(flags, 2);
-    atomicAdd((unsigned long long *)(colcnt + c), 1ull);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kHashSlots; i += blockDim.x) {
+      if (keys[i] >= 0) atomicAdd((unsigned long long *)(colcnt + keys[i]), (unsigned long long)cnts[i]);
+    }
+    __syncthreads();
   }
 }
 
 // ------------------------------------------------------------------ transpose
+// Slot assignment in CSR(A^T): per block, the hot columns reserve one range
+// with a single global atomic and hand out positions inside it from LDS.
 __global__ __launch_bounds__(256) void k_scatter(int64_t nnz, const int32_t *__restrict__ col,
                                                  const int32_t *__restrict__ rowidx,
                                                  const int64_t *__restrict__ rowT,
                                                  int32_t *__restrict__ cursor,
                                                  int32_t *__restrict__ tmp_row,
                                                  int32_t *__restrict__ tmp_src) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride) {
-    const int32_t c = col[e];
-    const int64_t pos = rowT[c] + atomicAdd(cursor + c, 1);
-    tmp_row[pos] = rowidx[e];
-    tmp_src[pos] = (int32_t)e;
+  __shared__ int32_t keys[kHashSlots];
+  __shared__ int32_t cnts[kHashSlots];
+  for (int64_t base = (int64_t)blockIdx.x * kElemPerBlock; base < nnz;
+       base += (int64_t)gridDim.x * kElemPerBlock) {
+    for (int i = threadIdx.x; i < kHashSlots; i += blockDim.x) {
+      keys[i] = -1;
+      cnts[i] = 0;
+    }
+    __syncthreads();
+    int16_t slot[kElemPerThread];
+#pragma unroll
+    for (int i = 0; i < kElemPerThread; ++i) {
+      const int64_t e = base + (int64_t)i * blockDim.x + threadIdx.x;
+      slot[i] = -1;
+      if (e < nnz) {
+        const int h = hash_insert(keys, col[e]);
+        slot[i] = (int16_t)h;
+        if (h >= 0) atomicAdd(cnts + h, 1);
+      }
+    }
+    __syncthreads();
+    // reserve a contiguous range per hot column; the count becomes the range base
+    for (int i = threadIdx.x; i < kHashSlots; i += blockDim.x) {
+      if (keys[i] >= 0) cnts[i] = atomicAdd(cursor + keys[i], cnts[i]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kElemPerThread; ++i) {
+      const int64_t e = base + (int64_t)i * blockDim.x + threadIdx.x;
+      if (e < nnz) {
+        const int32_t c = col[e];
+        const int h = slot[i];
+        const int32_t within = h >= 0 ? atomicAdd(cnts + h, 1) : atomicAdd(cursor + c, 1);
+        const int64_t pos = rowT[c] + within;
+        tmp_row[pos] = rowidx[e];
+        tmp_src[pos] = (int32_t)e;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -179,17 +268,34 @@ __global__ __launch_bounds__(256) void k_classify(int64_t n, const int64_t *__re
                                                   int32_t *__restrict__ lists,
                                                   int32_t *__restrict__ counts) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
-    const int64_t b = rowT[c], L = rowT[c + 1] - b;
-    if (L == 0) continue;
-    if (L == 1) {
-      colT[b] = tmp_row[b];
-      valT[b] = val[tmp_src[b]];
-      continue;
+  const int lane = threadIdx.x & 63;
+  // the loop bound is rounded up to whole waves so every lane joins the ballots
+  const int64_t nr = (n + 63) / 64 * 64;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nr; c += stride) {
+    int cls = -1;
+    if (c < n) {
+      const int64_t b = rowT[c], L = rowT[c + 1] - b;
+      if (L == 1) {
+        colT[b] = tmp_row[b];
+        valT[b] = val[tmp_src[b]];
+      } else if (L > 1) {
+        cls = L <= kSmallSeg ? 0 : (L <= kMedSeg ? 1 : 2);
+      }
     }
-    const int cls = L <= kSmallSeg ? 0 : (L <= kMedSeg ? 1 : 2);
-    const int32_t slot = atomicAdd(counts + cls, 1);
-    lists[(int64_t)cls * n + slot] = (int32_t)c;
+    // one atomic per class per wavefront
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const uint64_t mask = __ballot(cls == k);
+      if (!mask) continue;
+      const int leader = __ffsll((unsigned long long)mask) - 1;
+      int32_t base = 0;
+      if (lane == leader) base = atomicAdd(counts + k, __popcll(mask));
+      base = __shfl(base, leader, 64);
+      if (cls == k) {
+        const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+        lists[(int64_t)k * n + base + rank] = (int32_t)c;
+      }
+    }
   }
 }
 
@@ -264,9 +370,12 @@ __global__ __launch_bounds__(256) void k_sort_medium(int32_t count, const int32_
   }
 }
 
-// Columns with more than 2048 entries: rank each row against a bitmap of
-// the column's rows.  One 1024-thread block per column at a time, with a
-// private bitmap (words = ceil(m/32)) and per-word prefix counts.
+// Columns with more than 2048 entries: rank each row against a bitmap of the
+// column's rows kept in LDS, one window of kWinRows rows at a time
+// (prefix popcounts give the rank inside the window).
+constexpr int kWinWords = 8192;              // 32 KB bitmap + 32 KB prefix
+constexpr int64_t kWinRows = (int64_t)kWinWords * 32;
+
 template <typename TV>
 __global__ __launch_bounds__(1024) void k_sort_large(int32_t count, const int32_t *__restrict__ list,
                                                      int64_t m, const int64_t *__restrict__ rowT,
@@ -275,46 +384,51 @@ __global__ __launch_bounds__(1024) void k_sort_large(int32_t count, const int32_
                                                      const TV *__restrict__ val,
                                                      int32_t *__restrict__ colT,
                                                      TV *__restrict__ valT,
-                                                     uint32_t *__restrict__ bitmap_ws,
-                                                     int32_t *__restrict__ prefix_ws) {
+                                                     uint32_t *__restrict__ unused_ws,
+                                                     int32_t *__restrict__ unused_ws2) {
+  (void)unused_ws;
+  (void)unused_ws2;
+  __shared__ uint32_t bm[kWinWords];
+  __shared__ int32_t pf[kWinWords];
   __shared__ int64_t sh[40];
-  const int64_t words = (m + 31) / 32;
-  uint32_t *bm = bitmap_ws + (int64_t)blockIdx.x * words;
-  int32_t *pf = prefix_ws + (int64_t)blockIdx.x * words;
-  const int64_t per = (words + blockDim.x - 1) / blockDim.x;
+  constexpr int per = kWinWords / 1024;
   for (int64_t w = blockIdx.x; w < count; w += gridDim.x) {
     const int32_t c = list[w];
     const int64_t b = rowT[c];
     const int64_t L = rowT[c + 1] - b;
-    for (int64_t i = threadIdx.x; i < words; i += blockDim.x) bm[i] = 0u;
-    __threadfence();
-    __syncthreads();
-    for (int64_t i = threadIdx.x; i < L; i += blockDim.x) {
-      const int32_t r = tmp_row[b + i];
-      atomicOr(bm + (r >> 5), 1u << (r & 31));
+    int64_t done_rows = 0;  // entries ranked in earlier windows
+    for (int64_t r0 = 0; r0 < m; r0 += kWinRows) {
+      for (int i = threadIdx.x; i < kWinWords; i += 1024) bm[i] = 0u;
+      __syncthreads();
+      for (int64_t i = threadIdx.x; i < L; i += 1024) {
+        const int64_t r = (int64_t)tmp_row[b + i] - r0;
+        if (r >= 0 && r < kWinRows) atomicOr(bm + (r >> 5), 1u << (r & 31));
+      }
+      __syncthreads();
+      const int w0 = threadIdx.x * per;
+      int64_t local = 0;
+#pragma unroll
+      for (int i = 0; i < per; ++i) local += __popc(bm[w0 + i]);
+      int64_t tot;
+      int64_t ex = block_excl_scan(local, sh, tot);
+#pragma unroll
+      for (int i = 0; i < per; ++i) {
+        pf[w0 + i] = (int32_t)ex;
+        ex += __popc(bm[w0 + i]);
+      }
+      __syncthreads();
+      for (int64_t i = threadIdx.x; i < L; i += 1024) {
+        const int64_t r = (int64_t)tmp_row[b + i] - r0;
+        if (r >= 0 && r < kWinRows) {
+          const uint32_t word = bm[r >> 5];
+          const int64_t rank = done_rows + pf[r >> 5] + __popc(word & ((1u << (r & 31)) - 1u));
+          colT[b + rank] = (int32_t)(r + r0);
+          valT[b + rank] = val[tmp_src[b + i]];
+        }
+      }
+      done_rows += tot;
+      __syncthreads();
     }
-    __threadfence();
-    __syncthreads();
-    const int64_t w0 = (int64_t)threadIdx.x * per;
-    int64_t local = 0;
-    for (int64_t i = w0; i < w0 + per && i < words; ++i) local += __popc(bm[i]);
-    int64_t tot;
-    int64_t ex = block_excl_scan(local, sh, tot);
-    for (int64_t i = w0; i < w0 + per && i < words; ++i) {
-      pf[i] = (int32_t)ex;
-      ex += __popc(bm[i]);
-    }
-    __threadfence();
-    __syncthreads();
-    for (int64_t i = threadIdx.x; i < L; i += blockDim.x) {
-      const int32_t r = tmp_row[b + i];
-      const uint32_t word = bm[r >> 5];
-      const int rank = pf[r >> 5] + __popc(word & ((1u << (r & 31)) - 1u));
-      colT[b + rank] = r;
-      valT[b + rank] = val[tmp_src[b + i]];
-    }
-    __threadfence();
-    __syncthreads();
   }
 }
 
@@ -376,7 +490,9 @@ hipError_t launch_scan_i64(const int64_t *in, int64_t n, int64_t *out, int64_t *
 hipError_t launch_validate(int64_t m, int64_t n, int64_t nnz, const int64_t *rp, const int32_t *col,
                            const void *val, int dtype, int64_t *colcnt, int32_t *rowidx,
                            int32_t *flags, hipStream_t st) {
-  const int g = grid_for(nnz > m ? nnz : m, 256, 16384);
+  int64_t gb = (nnz + kElemPerBlock - 1) / kElemPerBlock;
+  if (gb < (m + 255) / 256) gb = (m + 255) / 256;
+  const int g = (int)(gb < 1 ? 1 : (gb > 65536 ? 65536 : gb));
   if (dtype == 1)
     hipLaunchKernelGGL(k_validate<double>, dim3(g), dim3(256), 0, st, m, n, nnz, rp, col,
                        (const double *)val, colcnt, rowidx, flags);
@@ -390,7 +506,8 @@ hipError_t launch_transpose_scatter(int64_t nnz, const int32_t *col, const int32
                                     const int64_t *rowT, int32_t *cursor, int32_t *tmp_row,
                                     int32_t *tmp_src, hipStream_t st) {
   if (nnz == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scatter, dim3(grid_for(nnz, 256, 16384)), dim3(256), 0, st, nnz, col, rowidx,
+  const int64_t gbs = (nnz + kElemPerBlock - 1) / kElemPerBlock;
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)(gbs > 65536 ? 65536 : gbs)), dim3(256), 0, st, nnz, col, rowidx,
                      rowT, cursor, tmp_row, tmp_src);
   return hipGetLastError();
 }

@@ -37,8 +37,13 @@ template <typename TC, int LT>
 __global__ __launch_bounds__(256) void k_gram_partial(int64_t r, int l, const TC *__restrict__ C,
                                                       int64_t ldc, double *__restrict__ partial,
                                                       int64_t rows_per_block,
-                                                      const int32_t *__restrict__ done) {
-  if (done && *done) return;
+                                                      const int32_t *__restrict__ done,
+                                                      int32_t *__restrict__ snap) {
+  if (done) {
+    const int32_t d = *done;
+    if (snap && blockIdx.x == 0 && threadIdx.x == 0) *snap = d;
+    if (d) return;
+  }
   constexpr int NT = LT * (LT + 1) / 2;
   constexpr int TPW = (NT + 3) / 4;
   constexpr int W = LT * 16;
@@ -97,20 +102,51 @@ __global__ __launch_bounds__(256) void k_gram_partial(int64_t r, int l, const TC
     const int t = wave + 4 * i;
     if (t < NT) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) out[(int64_t)t * 256 + lane * 4 + q] = acc[i][q];
+      for (int q = 0; q < 4; ++q) {
+        // Move the accumulator through a VGPR before storing: a store that
+        // read the FP64 MFMA accumulator registers directly returned stale
+        // values for the last rows written by the final MFMA on gfx950.
+        double v = acc[i][q];
+        asm volatile("" : "+v"(v));
+        out[(int64_t)t * 256 + lane * 4 + q] = v;
+      }
     }
   }
 }
 
-// Sum the block partials in block order; write the full symmetric G.
+// Sum the block partials; write the full symmetric G.  Eight threads share
+// an element: thread s sums blocks s, s+8, s+16, ... in order, then the eight
+// partial sums are added in order s = 0..7 (deterministic).
 template <int LT>
 __global__ __launch_bounds__(256) void k_gram_reduce(int l, int nblocks, const double *__restrict__ partial,
                                                      double *__restrict__ G,
                                                      const int32_t *__restrict__ done) {
   if (done && *done) return;
   constexpr int NT = LT * (LT + 1) / 2;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)NT * 256) return;
+  __shared__ double part[256];
+  const int sub = threadIdx.x & 7;
+  const int64_t e = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3);
+  double s = 0.0;
+  if (e < (int64_t)NT * 256) {
+    const int64_t stride = (int64_t)NT * 256;
+    const double *p = partial + e;
+    int b = sub;
+    for (; b + 24 < nblocks; b += 32) {
+      const double x0 = p[(int64_t)b * stride], x1 = p[(int64_t)(b + 8) * stride];
+      const double x2 = p[(int64_t)(b + 16) * stride], x3 = p[(int64_t)(b + 24) * stride];
+      s += x0;
+      s += x1;
+      s += x2;
+      s += x3;
+    }
+    for (; b < nblocks; b += 8) s += p[(int64_t)b * stride];
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (sub != 0 || e >= (int64_t)NT * 256) return;
+  double tot = 0.0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) tot += part[threadIdx.x + i];
   int t = (int)(e >> 8);
   const int within = (int)(e & 255);
   const int lane = within >> 2, q = within & 3;
@@ -125,10 +161,8 @@ __global__ __launch_bounds__(256) void k_gram_reduce(int l, int nblocks, const d
   const int col = J * 16 + (lane & 15);
   if (row >= l || col >= l) return;
   if (I == J && row > col) return;
-  double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * NT * 256 + e];
-  G[(int64_t)row * l + col] = s;
-  G[(int64_t)col * l + row] = s;
+  G[(int64_t)row * l + col] = tot;
+  G[(int64_t)col * l + row] = tot;
 }
 
 // ------------------------------------------------------------------ rescale
@@ -156,10 +190,27 @@ __global__ __launch_bounds__(256) void k_rescale_mfma(int64_t r, int l, const TC
   for (int64_t strip = blockIdx.x; strip < nstrips; strip += gridDim.x) {
     const int64_t rb = strip * kStrip;
     __syncthreads();
-    for (int idx = threadIdx.x; idx < kStrip * LK; idx += 256) {
-      const int rr = idx / LK, kk = idx - rr * LK;
-      const int64_t row = rb + rr;
-      Cs[rr * SC + kk] = (row < r && kk < l) ? (float)to_d(C[row * ldc + kk]) : 0.0f;
+    if constexpr (sizeof(TC) == 4) {
+      // FP32 rows: 16-byte loads (ldc is a multiple of 8, LK of 4); columns
+      // at or beyond l are replaced by zero (pad columns may hold anything)
+      const int LK4 = LK / 4;
+      for (int idx = threadIdx.x; idx < kStrip * LK4; idx += 256) {
+        const int rr = idx / LK4, k4 = (idx - rr * LK4) * 4;
+        const int64_t row = rb + rr;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (row < r) v = *reinterpret_cast<const float4 *>(C + row * ldc + k4);
+        float *dst = Cs + rr * SC + k4;
+        dst[0] = k4 < l ? v.x : 0.0f;
+        dst[1] = k4 + 1 < l ? v.y : 0.0f;
+        dst[2] = k4 + 2 < l ? v.z : 0.0f;
+        dst[3] = k4 + 3 < l ? v.w : 0.0f;
+      }
+    } else {
+      for (int idx = threadIdx.x; idx < kStrip * LK; idx += 256) {
+        const int rr = idx / LK, kk = idx - rr * LK;
+        const int64_t row = rb + rr;
+        Cs[rr * SC + kk] = (row < r && kk < l) ? (float)to_d(C[row * ldc + kk]) : 0.0f;
+      }
     }
     __syncthreads();
     f4 acc[LTO];
@@ -183,7 +234,9 @@ __global__ __launch_bounds__(256) void k_rescale_mfma(int64_t r, int l, const TC
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int64_t row = rbase + q;
-          if (row < r) elem<TO>::st(Out + row * ldo + col, col < c ? acc[J][q] : 0.0f);
+          float v = acc[J][q];
+          asm volatile("" : "+v"(v));
+          if (row < r) elem<TO>::st(Out + row * ldo + col, col < c ? v : 0.0f);
         }
       }
     }
@@ -325,20 +378,23 @@ int grid_for(int64_t work, int block, int64_t cap = 65536) {
 
 template <typename TC>
 hipError_t gram_dispatch(int64_t r, int l, const TC *C, int64_t ldc, double *partial, int nb,
-                         double *G, const int32_t *done, hipStream_t st) {
-  const int LT = (l + 15) / 16;
+                         double *G, const int32_t *done, hipStream_t st, int32_t *snap) {
+  // at least two column tiles: the single-tile instantiation returned wrong
+  // values in the last 4 x 4 corner of the tile once several MFMAs had
+  // accumulated (l = 16, 32+ rows) on gfx950, the two-tile one does not
+  const int LT = (l + 15) / 16 < 2 ? 2 : (l + 15) / 16;
   const int64_t rpb = (r + nb - 1) / nb;
 #define DSV_GRAM(LTV)                                                                          \
   case LTV: {                                                                                  \
     hipLaunchKernelGGL((k_gram_partial<TC, LTV>), dim3(nb), dim3(256), 0, st, r, l, C, ldc, partial, \
-                       rpb, done);                                                             \
+                       rpb, done, snap);                                                       \
     constexpr int NT = LTV * (LTV + 1) / 2;                                                    \
-    hipLaunchKernelGGL((k_gram_reduce<LTV>), dim3((NT * 256 + 255) / 256), dim3(256), 0, st, l, nb, \
+    hipLaunchKernelGGL((k_gram_reduce<LTV>), dim3((NT * 256 + 31) / 32), dim3(256), 0, st, l, nb, \
                        partial, G, done);                                                      \
     break;                                                                                     \
   }
   switch (LT) {
-    DSV_GRAM(1) DSV_GRAM(2) DSV_GRAM(3) DSV_GRAM(4) DSV_GRAM(5)
+    DSV_GRAM(2) DSV_GRAM(3) DSV_GRAM(4) DSV_GRAM(5)
     DSV_GRAM(6) DSV_GRAM(7) DSV_GRAM(8) DSV_GRAM(9) DSV_GRAM(10)
     default: return hipErrorInvalidValue;
   }
@@ -380,16 +436,16 @@ int gram_blocks(int64_t r, int l) {
   return (int)nb;
 }
 size_t gram_partial_elems(int nblocks, int l) {
-  const int LT = (l + 15) / 16;
+  const int LT = (l + 15) / 16 < 2 ? 2 : (l + 15) / 16;
   return (size_t)nblocks * (size_t)(LT * (LT + 1) / 2) * 256;
 }
 
 hipError_t launch_gram(int64_t r, int l, const void *C, int64_t ldc, int cdtype, double *partial,
-                       int nblocks, double *G, const int32_t *done, hipStream_t st) {
+                       int nblocks, double *G, const int32_t *done, hipStream_t st, int32_t *snap) {
   if (l < 1 || l > kMaxL) return hipErrorInvalidValue;
-  if (cdtype == 0) return gram_dispatch<float>(r, l, (const float *)C, ldc, partial, nblocks, G, done, st);
-  if (cdtype == 1) return gram_dispatch<double>(r, l, (const double *)C, ldc, partial, nblocks, G, done, st);
-  return gram_dispatch<bf16>(r, l, (const bf16 *)C, ldc, partial, nblocks, G, done, st);
+  if (cdtype == 0) return gram_dispatch<float>(r, l, (const float *)C, ldc, partial, nblocks, G, done, st, snap);
+  if (cdtype == 1) return gram_dispatch<double>(r, l, (const double *)C, ldc, partial, nblocks, G, done, st, snap);
+  return gram_dispatch<bf16>(r, l, (const bf16 *)C, ldc, partial, nblocks, G, done, st, snap);
 }
 
 hipError_t launch_rescale(int64_t r, int l, const void *C, int64_t ldc, int cdtype, const double *W,

@@ -35,7 +35,6 @@ constexpr int kMaxLP = 160;           // padded size L (multiple of 4)
 constexpr int kMaxPairs = kMaxLP / 2;
 constexpr int kMaxNR = 10;            // register row slots per lane (L=160: 40 lanes/row, 1 row/wave)
 constexpr int kMaxItems = 4;          // block items per thread per parity
-constexpr double kSkip = 1.1102230246251565e-16;  // 2^-53
 
 __device__ __forceinline__ int pk(int i, int j, int L) {  // i <= j
   return i * L - ((i * (i - 1)) >> 1) + (j - i);
@@ -61,6 +60,24 @@ __device__ __forceinline__ void group_of(int parity, int g, int P, int &first, i
 // rotation slot of a size-2 group
 __device__ __forceinline__ int slot_of(int parity, int g) { return parity ? g - 1 : g; }
 
+// Reciprocal and reciprocal square root from the hardware approximations
+// refined by two Newton steps (relative error near 1 ulp); the rotation only
+// needs c^2 + s^2 = 1 to rounding, not correctly rounded quotients.
+__device__ __forceinline__ double frcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ double frsqrt(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
 template <int MAXNR>
 __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
   SolverState *state = a.state;
@@ -73,8 +90,8 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
     if (stopped) return;
   }
   extern __shared__ double G[];  // packed upper, L(L+1)/2
-  __shared__ double rc[kMaxPairs], rs[kMaxPairs], rt[kMaxPairs];
-  __shared__ int rrot[kMaxPairs];
+  __shared__ double2 rot_cs[kMaxPairs];  // (c, s) of each pair's rotation
+  __shared__ double2 rot_tf[kMaxPairs];  // (t = s/c, 1 if rotated else 0)
   __shared__ int label[kMaxLP];
   __shared__ int rank_of[kMaxLP];
   __shared__ double Ssh[kMaxLP];
@@ -83,6 +100,7 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
   __shared__ uint16_t items[2][kMaxItems * kEigThreads];
 
   const int l = a.l;
+  const double kSkip = a.skip;  // rotation / convergence threshold (relative)
   const int L = (l + 3) & ~3;
   const int P = L / 2;
   const int tid = threadIdx.x;
@@ -94,18 +112,22 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
   }
   for (int p = tid; p < L; p += kEigThreads) label[p] = p;
 
-  // block items of both parities, decoded once into LDS: pairs (ga >= gb)
-  // of groups, packed as ga << 8 | gb (0xffff = none)
+  // block items of both parities, decoded once into LDS: pairs of groups
+  // (gb <= ga) enumerated row by row of the packed upper triangle (gb outer,
+  // ga inner), so neighbouring lanes touch neighbouring LDS words; packed as
+  // ga << 8 | gb (0xffff = none)
   for (int par = 0; par < 2; ++par) {
     const int ng = par ? P + 1 : P;
     const int nitems = ng * (ng + 1) / 2;
     for (int t = tid; t < kMaxItems * kEigThreads; t += kEigThreads) {
       uint16_t code = 0xffff;
       if (t < nitems) {
-        int ga = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
-        while (ga * (ga + 1) / 2 > t) --ga;
-        while ((ga + 1) * (ga + 2) / 2 <= t) ++ga;
-        code = (uint16_t)((ga << 8) | (t - ga * (ga + 1) / 2));
+        int gb = 0, rem = t;
+        while (rem >= ng - gb) {
+          rem -= ng - gb;
+          ++gb;
+        }
+        code = (uint16_t)(((gb + rem) << 8) | gb);
       }
       items[par][t] = code;
     }
@@ -136,7 +158,7 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
       const int i = idx / L, j = idx - i * L;
       if (i < j) {
         const double apq = G[pk(i, j, L)];
-        if (apq != 0.0 && !(fabs(apq) <= kSkip * sqrt(fabs(G[pk(i, i, L)] * G[pk(j, j, L)])))) s_flag = 1;
+        if (apq != 0.0 && !(apq * apq <= kSkip * kSkip * fabs(G[pk(i, i, L)] * G[pk(j, j, L)]))) s_flag = 1;
       }
     }
     __syncthreads();
@@ -145,27 +167,36 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
     for (int step = 0; step < L; ++step) {
       const int par = step & 1;
       const int npairs = par ? P - 1 : P;
-      // phase A: rotation of each pair
+      long long c0 = 0, w0 = 0;
+      if (a.prof && tid == 0) {
+        c0 = clock64();
+        w0 = wall_clock64();
+      }
+      // phase A: rotation of each pair (and the index swap that follows it)
       if (tid < npairs) {
         const int p = par ? 2 * tid + 1 : 2 * tid, q = p + 1;
         const double app = G[pk(p, p, L)], aqq = G[pk(q, q, L)], apq = G[pk(p, q, L)];
-        int rot = 0;
-        double c = 1.0, s = 0.0, t = 0.0;
-        if (apq != 0.0 && !(fabs(apq) <= kSkip * sqrt(fabs(app * aqq)))) {
-          const double tau = (aqq - app) / (2.0 * apq);
-          t = tau >= 0.0 ? 1.0 / (tau + sqrt(1.0 + tau * tau)) : -1.0 / (-tau + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + t * t);
+        const int lp = label[p], lq = label[q];
+        double c = 1.0, s = 0.0, t = 0.0, rot = 0.0;
+        if (apq != 0.0 && !(fabs(apq) * fabs(apq) <= kSkip * kSkip * fabs(app * aqq))) {
+          const double tau = (aqq - app) * 0.5 * frcp(apq);
+          const double w = fma(tau, tau, 1.0);
+          const double r = w * frsqrt(w);  // sqrt(1 + tau^2)
+          t = tau >= 0.0 ? frcp(tau + r) : -frcp(r - tau);
+          c = frsqrt(fma(t, t, 1.0));
           s = t * c;
-          rot = 1;
+          rot = 1.0;
         }
-        rc[tid] = c;
-        rs[tid] = s;
-        rt[tid] = t;
-        rrot[tid] = rot;
+        rot_cs[tid] = make_double2(c, s);
+        rot_tf[tid] = make_double2(t, rot);
+        label[p] = lq;
+        label[q] = lp;
       }
       __syncthreads();
-      // phase B: blocks of G
-      const int ng = par ? P + 1 : P;
+      long long c1 = 0;
+      if (a.prof && tid == 0) c1 = clock64();
+      // phase B: 2x2 blocks of G, B <- Ma^T B Mb with M = J P (rotation then
+      // swap): M = [[s, c], [c, -s]] when rotated, [[0, 1], [1, 0]] when not
       for (int s_ = 0; s_ < kMaxItems; ++s_) {
         const uint16_t code = items[par][tid + s_ * kEigThreads];
         if (code == 0xffff) break;
@@ -173,77 +204,68 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
         int fa, na, fb, nb;
         group_of(par, ga, P, fa, na);
         group_of(par, gb, P, fb, nb);
-        (void)ng;
+        int sa = slot_of(par, ga), sb = slot_of(par, gb);
+        sa = sa < 0 ? 0 : (sa >= npairs ? npairs - 1 : sa);
+        sb = sb < 0 ? 0 : (sb >= npairs ? npairs - 1 : sb);
         if (ga == gb) {
           if (na == 2) {
-            const int sl = slot_of(par, ga);
             const int p = fa, q = fa + 1;
-            const double app = G[pk(p, p, L)], aqq = G[pk(q, q, L)];
-            if (rrot[sl]) {
-              const double apq = G[pk(p, q, L)];
-              const double t = rt[sl];
-              G[pk(p, p, L)] = aqq + t * apq;  // swapped
-              G[pk(q, q, L)] = app - t * apq;
+            const double2 tf = rot_tf[sa];
+            const double app = G[pk(p, p, L)], aqq = G[pk(q, q, L)], apq = G[pk(p, q, L)];
+            if (tf.y != 0.0) {
+              G[pk(p, p, L)] = fma(tf.x, apq, aqq);  // swapped
+              G[pk(q, q, L)] = fma(-tf.x, apq, app);
               G[pk(p, q, L)] = 0.0;
             } else {
               G[pk(p, p, L)] = aqq;
               G[pk(q, q, L)] = app;
             }
-            const int lp = label[p];
-            label[p] = label[q];
-            label[q] = lp;
           }
           continue;
         }
-        // off-diagonal block: rows of ga (larger indices), columns of gb
-        double ma00 = 1, ma01 = 0, ma10 = 0, ma11 = 1, mb00 = 1, mb01 = 0, mb10 = 0, mb11 = 1;
-        if (na == 2) {
-          const int sl = slot_of(par, ga);
-          if (rrot[sl]) {
-            ma00 = rs[sl]; ma01 = rc[sl]; ma10 = rc[sl]; ma11 = -rs[sl];
-          } else {
-            ma00 = 0; ma01 = 1; ma10 = 1; ma11 = 0;
-          }
-        }
-        if (nb == 2) {
-          const int sl = slot_of(par, gb);
-          if (rrot[sl]) {
-            mb00 = rs[sl]; mb01 = rc[sl]; mb10 = rc[sl]; mb11 = -rs[sl];
-          } else {
-            mb00 = 0; mb01 = 1; mb10 = 1; mb11 = 0;
-          }
-        }
-        // B[i][j] = G[fa+i][fb+j]; stored at packed (fb+j, fa+i) since fb+j < fa+i
-        double b00 = G[pk(fb, fa, L)];
-        double b01 = nb == 2 ? G[pk(fb + 1, fa, L)] : 0.0;
-        double b10 = na == 2 ? G[pk(fb, fa + 1, L)] : 0.0;
-        double b11 = (na == 2 && nb == 2) ? G[pk(fb + 1, fa + 1, L)] : 0.0;
-        // T = B Mb
-        const double t00 = b00 * mb00 + b01 * mb10, t01 = b00 * mb01 + b01 * mb11;
+        // off-diagonal block: rows of ga (larger indices), columns of gb;
+        // all loads issued before any use.  M = [[s, c], [c, -s]] for both the
+        // rotated case and the plain swap (c = 1, s = 0); a single-index group
+        // has M = [1].
+        const double2 csa = rot_cs[sa], csb = rot_cs[sb];
+        const int i00 = pk(fb, fa, L);
+        const int i01 = nb == 2 ? pk(fb + 1, fa, L) : i00;
+        const int i10 = na == 2 ? pk(fb, fa + 1, L) : i00;
+        const int i11 = (na == 2 && nb == 2) ? pk(fb + 1, fa + 1, L) : i00;
+        const double g00 = G[i00], g01 = G[i01], g10 = G[i10], g11 = G[i11];
+        const double ma00 = na == 2 ? csa.y : 1.0, ma01 = na == 2 ? csa.x : 0.0;
+        const double ma10 = na == 2 ? csa.x : 0.0, ma11 = na == 2 ? -csa.y : 1.0;
+        const double mb00 = nb == 2 ? csb.y : 1.0, mb01 = nb == 2 ? csb.x : 0.0;
+        const double mb10 = nb == 2 ? csb.x : 0.0, mb11 = nb == 2 ? -csb.y : 1.0;
+        const double b01 = nb == 2 ? g01 : 0.0;
+        const double b10 = na == 2 ? g10 : 0.0;
+        const double b11 = (na == 2 && nb == 2) ? g11 : 0.0;
+        // T = B Mb ; B' = Ma^T T
+        const double t00 = g00 * mb00 + b01 * mb10, t01 = g00 * mb01 + b01 * mb11;
         const double t10 = b10 * mb00 + b11 * mb10, t11 = b10 * mb01 + b11 * mb11;
-        // B' = Ma^T T
-        const double n00 = ma00 * t00 + ma10 * t10, n01 = ma00 * t01 + ma10 * t11;
-        const double n10 = ma01 * t00 + ma11 * t10, n11 = ma01 * t01 + ma11 * t11;
-        G[pk(fb, fa, L)] = n00;
-        if (nb == 2) G[pk(fb + 1, fa, L)] = n01;
-        if (na == 2) G[pk(fb, fa + 1, L)] = n10;
-        if (na == 2 && nb == 2) G[pk(fb + 1, fa + 1, L)] = n11;
+        G[i00] = ma00 * t00 + ma10 * t10;
+        if (nb == 2) G[i01] = ma00 * t01 + ma10 * t11;
+        if (na == 2) G[i10] = ma01 * t00 + ma11 * t10;
+        if (na == 2 && nb == 2) G[i11] = ma01 * t01 + ma11 * t11;
       }
-      // V <- V M (column pairs of this parity).  Parameters (8 per lane):
-      //   even: pair (p0, p0+1) -> e[0..3], pair (p0+2, p0+3) -> e[4..7]
-      //   odd : pair (p0-1, p0) -> e[0] = M01, e[1] = M11 (second member here)
-      //         pair (p0+1, p0+2) -> e[2..5]
-      //         pair (p0+3, p0+4) -> e[6] = M00, e[7] = M10 (first member here)
-      {
+      long long cmid = 0;
+      if (a.prof && tid == 0) cmid = clock64();
+      // V <- V M (column pairs of this parity); waves that hold no row skip
+      if (wave * RPW < L) {
+        // Parameters (8 per lane):
+        //   even: pair (p0, p0+1) -> e[0..3], pair (p0+2, p0+3) -> e[4..7]
+        //   odd : pair (p0-1, p0) -> e[0] = M01, e[1] = M11 (second member here)
+        //         pair (p0+1, p0+2) -> e[2..5]
+        //         pair (p0+3, p0+4) -> e[6] = M00, e[7] = M10 (first member here)
         double e[8];
         auto mp = [&](int sl, double &m00, double &m01, double &m10, double &m11) {
-          if (sl < 0 || sl >= npairs) {
-            m00 = 1; m01 = 0; m10 = 0; m11 = 1;
-          } else if (rrot[sl]) {
-            m00 = rs[sl]; m01 = rc[sl]; m10 = rc[sl]; m11 = -rs[sl];
-          } else {
-            m00 = 0; m01 = 1; m10 = 1; m11 = 0;
-          }
+          const int slc = sl < 0 ? 0 : (sl >= npairs ? npairs - 1 : sl);
+          const double2 cs = rot_cs[slc];
+          const bool in = sl >= 0 && sl < npairs;
+          m00 = in ? cs.y : 1.0;
+          m01 = in ? cs.x : 0.0;
+          m10 = in ? cs.x : 0.0;
+          m11 = in ? -cs.y : 1.0;
         };
         if (!par) {
           mp(2 * cl, e[0], e[1], e[2], e[3]);
@@ -276,6 +298,17 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
         }
       }
       __syncthreads();
+      if (a.prof && tid == 0) {
+        // step profile (thread 0): cycles of phase A, cycles of phase B,
+        // wall-clock ticks (100 MHz), steps, G-update cycles, V-update cycles
+        const long long c2 = clock64();
+        a.prof[0] += c1 - c0;
+        a.prof[1] += c2 - c1;
+        a.prof[2] += wall_clock64() - w0;
+        a.prof[3] += 1;
+        a.prof[4] += cmid - c1;
+        a.prof[5] += c2 - cmid;
+      }
     }
   }
 
@@ -317,6 +350,10 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
   }
   if (a.sweeps && tid == 0) *a.sweeps = s_sweeps;
   if (!state) return;
+  if (tid == 0) {
+    state->eig_calls += 1;
+    state->eig_sweeps += s_sweeps;
+  }
   if (tid == 0 && !(Ssh[l - 1] > tau)) state->deficient = 1;
   if (a.mode != 2) return;
 

@@ -8,8 +8,9 @@
 // FP32, 2 FP64, 8 BF16), and every lane keeps V accumulators: for each
 // nonzero the group gathers one full panel row with one 16-byte load per
 // lane, so a gathered row is a coalesced read of ld elements.  A wavefront
-// holds 64 / G groups.  Four nonzeros are in flight per group (unrolled)
-// to keep enough loads outstanding.
+// holds 64 / G groups.  The (column, value) pairs of a row are read
+// cooperatively by the group and broadcast lane to lane, so eight gathers
+// per lane are in flight at once.
 //
 // Load balance (power-law degrees): rows with more than long_row nonzeros
 // are cut into chunks of long_row; each chunk is an independent task writing
@@ -62,30 +63,45 @@ __global__ __launch_bounds__(256) void k_spmm(
 #pragma unroll
   for (int i = 0; i < V; ++i) acc[i] = (TA)0;
   const TX *xb = X + cl * V;
-  int64_t j = b;
-  for (; j + 4 <= e; j += 4) {
-    const int32_t c0 = col[j], c1 = col[j + 1], c2 = col[j + 2], c3 = col[j + 3];
-    const TA v0 = (TA)val[j], v1 = (TA)val[j + 1], v2 = (TA)val[j + 2], v3 = (TA)val[j + 3];
-    TA x0[V], x1[V], x2[V], x3[V];
-    load_n<TX, TA, V>(xb + (int64_t)c0 * ldx, x0);
-    load_n<TX, TA, V>(xb + (int64_t)c1 * ldx, x1);
-    load_n<TX, TA, V>(xb + (int64_t)c2 * ldx, x2);
-    load_n<TX, TA, V>(xb + (int64_t)c3 * ldx, x3);
-#pragma unroll
-    for (int i = 0; i < V; ++i) {
-      acc[i] = fma(v0, x0[i], acc[i]);
-      acc[i] = fma(v1, x1[i], acc[i]);
-      acc[i] = fma(v2, x2[i], acc[i]);
-      acc[i] = fma(v3, x3[i], acc[i]);
+  const int src0 = sub * G;  // first lane of this group
+  // The group reads up to G (column, value) pairs with one coalesced load,
+  // then broadcasts them lane to lane, so the gathers of U consecutive
+  // nonzeros are independent and in flight together.
+  constexpr int U = 8;
+  for (int64_t base = b; base < e; base += G) {
+    const int64_t idx = base + cl;
+    int32_t myc = 0;
+    TA myv = (TA)0;
+    if (idx < e) {
+      myc = col[idx];
+      myv = (TA)val[idx];
     }
-  }
-  for (; j < e; ++j) {
-    const int32_t c0 = col[j];
-    const TA v0 = (TA)val[j];
-    TA x0[V];
-    load_n<TX, TA, V>(xb + (int64_t)c0 * ldx, x0);
+    const int cnt = (int)((e - base) < G ? (e - base) : G);
+    int t = 0;
+    for (; t + U <= cnt; t += U) {
+      int32_t c[U];
+      TA v[U];
 #pragma unroll
-    for (int i = 0; i < V; ++i) acc[i] = fma(v0, x0[i], acc[i]);
+      for (int u = 0; u < U; ++u) {
+        c[u] = __shfl(myc, src0 + t + u, 64);
+        v[u] = __shfl(myv, src0 + t + u, 64);
+      }
+      TA x[U][V];
+#pragma unroll
+      for (int u = 0; u < U; ++u) load_n<TX, TA, V>(xb + (int64_t)c[u] * ldx, x[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int i = 0; i < V; ++i) acc[i] = fma(v[u], x[u][i], acc[i]);
+    }
+    for (; t < cnt; ++t) {
+      const int32_t c0 = __shfl(myc, src0 + t, 64);
+      const TA v0 = __shfl(myv, src0 + t, 64);
+      TA x0[V];
+      load_n<TX, TA, V>(xb + (int64_t)c0 * ldx, x0);
+#pragma unroll
+      for (int i = 0; i < V; ++i) acc[i] = fma(v0, x0[i], acc[i]);
+    }
   }
   if (row < 0) {
     store_n<TA, TA, V>(partial + g * ldp + cl * V, acc);
@@ -117,9 +133,21 @@ __global__ __launch_bounds__(256) void k_spmm_long(
   TA acc[V];
 #pragma unroll
   for (int i = 0; i < V; ++i) acc[i] = (TA)0;
-  for (int64_t c = 0; c < lr.nch; ++c) {
+  // chunk partials summed in chunk order; eight loads in flight
+  const TA *pb = partial + lr.first * ldp + cl * V;
+  int64_t c = 0;
+  for (; c + 8 <= lr.nch; c += 8) {
+    TA p[8][V];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) load_n<TA, TA, V>(pb + (c + u) * ldp, p[u]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int i = 0; i < V; ++i) acc[i] += p[u][i];
+  }
+  for (; c < lr.nch; ++c) {
     TA p[V];
-    load_n<TA, TA, V>(partial + (lr.first + c) * ldp + cl * V, p);
+    load_n<TA, TA, V>(pb + c * ldp, p);
 #pragma unroll
     for (int i = 0; i < V; ++i) acc[i] += p[i];
   }

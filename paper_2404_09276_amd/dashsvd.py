@@ -54,7 +54,8 @@ class _Info(C.Structure):
                 ("ratio", C.c_double * MAX_TRACE), ("time_total_ms", C.c_double),
                 ("time_setup_ms", C.c_double), ("time_loop_ms", C.c_double),
                 ("time_final_ms", C.c_double), ("long_chunks_A", C.c_int64),
-                ("long_chunks_AT", C.c_int64), ("kt_ms", C.c_double * 8), ("kt_count", C.c_int32 * 8)]
+                ("long_chunks_AT", C.c_int64), ("kt_ms", C.c_double * 8), ("kt_count", C.c_int32 * 8),
+                ("eig_calls", C.c_int32), ("eig_sweeps", C.c_int32)]
 
 KT_NAMES = ["spmm", "spmm_t_shift", "gram", "eig", "rescale", "transpose", "sketch", "final"]
 
@@ -65,7 +66,7 @@ EXPORTS = [
     "dashsvd_create", "dashsvd_destroy", "dashsvd_set_options", "dashsvd_run", "dashsvd_get_USV",
     "dashsvd_get_info", "dashsvd_get_trace", "dashsvd_workspace_size", "dashsvd_status_string",
     "dashsvd_last_error", "dashsvd_k_gaussian", "dashsvd_k_philox_raw", "dashsvd_k_transpose",
-    "dashsvd_k_spmm", "dashsvd_k_gram", "dashsvd_k_eig", "dashsvd_k_rescale",
+    "dashsvd_k_spmm", "dashsvd_k_gram", "dashsvd_k_eig", "dashsvd_k_eig_prof", "dashsvd_k_rescale",
 ]
 
 
@@ -98,6 +99,7 @@ def lib():
                                      i32, P]
         L.dashsvd_k_gram.argtypes = [i64, i32, P, i64, i32, P, P]
         L.dashsvd_k_eig.argtypes = [i32, P, P, P, P, P, P]
+        L.dashsvd_k_eig_prof.argtypes = [i32, P, P, P, P, P, P, P]
         L.dashsvd_k_rescale.argtypes = [i64, i32, P, i64, i32, P, i64, i32, P, i64, i32, P]
         for name in EXPORTS:
             if name not in ("dashsvd_destroy", "dashsvd_status_string", "dashsvd_last_error"):
@@ -183,6 +185,8 @@ class Info:
     long_chunks_AT: int
     kt_ms: dict
     kt_count: dict
+    eig_calls: int
+    eig_sweeps: int
 
 
 class DashSVD:
@@ -273,7 +277,7 @@ class DashSVD:
                     np.array(raw.ratio[:min(npass, MAX_TRACE)]), raw.time_total_ms,
                     raw.time_setup_ms, raw.time_loop_ms, raw.time_final_ms, raw.long_chunks_A,
                     raw.long_chunks_AT, dict(zip(KT_NAMES, list(raw.kt_ms))),
-                    dict(zip(KT_NAMES, list(raw.kt_count))))
+                    dict(zip(KT_NAMES, list(raw.kt_count))), raw.eig_calls, raw.eig_sweeps)
 
     def trace(self) -> np.ndarray:
         """Per-pass S (passes x l) of the last run (dashsvd_get_trace)."""
@@ -338,6 +342,13 @@ def k_eig(G, S, Vs, W, sweeps=None, stream=None):
     l = G.shape[0]
     _check(lib().dashsvd_k_eig(l, _ptr(G), _ptr(S), _ptr(Vs), _ptr(W), _ptr(sweeps),
                                _stream_ptr(stream)))
+
+
+def k_eig_prof(G, S, Vs, W, sweeps, prof, stream=None):
+    """k_eig with the step profile (prof: device int64 tensor of 4)."""
+    l = G.shape[0]
+    _check(lib().dashsvd_k_eig_prof(l, _ptr(G), _ptr(S), _ptr(Vs), _ptr(W), _ptr(sweeps),
+                                    _ptr(prof), _stream_ptr(stream)))
 
 
 def k_rescale(Cm, l, W, c, Out, stream=None):
