@@ -507,8 +507,8 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     ea.l = l;
     ea.k = k;
     // FP64 form: converge to half an ulp; FP32 / BF16 panels carry ~1e-7
-    // relative rounding, so the eigenvectors need no more than 2^-36
-    ea.skip = prec == DASHSVD_PREC_FP64 ? 0x1.0p-53 : 0x1.0p-36;
+    // relative rounding, so the eigenvectors need no more than 2^-30
+    ea.skip = prec == DASHSVD_PREC_FP64 ? 0x1.0p-53 : 0x1.0p-30;
     ea.G = b.G;
     ea.S = b.S;
     ea.Vs = b.Vs;
