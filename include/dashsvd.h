@@ -118,11 +118,11 @@ typedef struct {
 } dashsvd_options;
 
 /* Kernel groups timed when options.timing = 1 (index into kt_ms / kt_count). */
-#define DASHSVD_KT_SPMM 0        /* Y = M Q of a power pass (incl. long-row reduction) */
-#define DASHSVD_KT_SPMM_T 1      /* C = M^T Y - alpha Q of a power pass */
+#define DASHSVD_KT_SPMM 0        /* M times a panel: Z = M C (FP32/FP64 forms) or Y = M Q (BF16 form) */
+#define DASHSVD_KT_SPMM_T 1      /* M^T times a panel: X = M^T Z, or C = M^T Y - alpha Q (BF16 form) */
 #define DASHSVD_KT_GRAM 2        /* Gram partials + reduction (every eigSVD) */
 #define DASHSVD_KT_EIG 3         /* Jacobi eig + tail (every eigSVD) */
-#define DASHSVD_KT_RESCALE 4     /* Q = C W (every eigSVD of a power pass and the sketch) */
+#define DASHSVD_KT_RESCALE 4     /* C+ = (X - alpha C) W, or Q = C W (BF16 form) */
 #define DASHSVD_KT_TRANSPOSE 5   /* validation + CSR(A^T) build */
 #define DASHSVD_KT_SKETCH 6      /* Omega + M^T Omega */
 #define DASHSVD_KT_FINAL 7       /* B = M Q, its eigSVD, U, V, signs */

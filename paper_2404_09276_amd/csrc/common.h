@@ -217,9 +217,12 @@ struct EigArgs {
 };
 hipError_t launch_eig(const EigArgs &a, hipStream_t st);
 
+// Out = (C - alpha R) W when R is given (R laid out like C, alpha on the
+// device), else Out = C W.
 hipError_t launch_rescale(int64_t r, int l, const void *C, int64_t ldc, int cdtype, const double *W,
                           int64_t ldw, int c, void *Out, int64_t ldo, int odtype,
-                          const int32_t *done, hipStream_t st);
+                          const int32_t *done, hipStream_t st, const void *R = nullptr,
+                          const double *alpha = nullptr);
 
 // pmax: nblk*k doubles, pidx: nblk*k int64 followed by k floats (workspace)
 hipError_t launch_sign_fix(int64_t rowsV, int64_t rowsU, int k, void *V, int64_t ldv, void *U,

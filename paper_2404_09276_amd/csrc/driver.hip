@@ -208,7 +208,8 @@ struct RunBufs {
   void *Q = nullptr;   // M_n x ld, panel type
   void *C = nullptr;   // M_n x ld, C type (f32 / f64)
   void *B = nullptr;   // M_m x ld, C type (final block)
-  void *Z = nullptr;   // M_m x ld, C type: M C, rescaled into the next Y
+  void *Z = nullptr;   // M_m x ld, C type: M C of the current block
+  void *X = nullptr;   // M_n x ld, C type: M^T M C of the current block (overlapped order)
   double *gpart = nullptr, *G = nullptr, *W = nullptr, *Vs = nullptr, *S = nullptr, *Sprev = nullptr;
   SolverState *state = nullptr;
   double *tr_alpha = nullptr, *tr_ratio = nullptr, *tr_s = nullptr;
@@ -378,6 +379,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   b.C = ar.take(dsz(cdt) * (size_t)Mn * ld);
   b.B = pdt == cdt ? b.Y : ar.take(dsz(cdt) * (size_t)Mm * ld);
   b.Z = ar.take(dsz(cdt) * (size_t)Mm * ld);
+  b.X = pdt == cdt ? ar.take(dsz(cdt) * (size_t)Mn * ld) : nullptr;
   const int nb_n = gram_blocks(Mn, l), nb_m = gram_blocks(Mm, l);
   b.gpart = (double *)ar.take(8 * gram_partial_elems(nb_n > nb_m ? nb_n : nb_m, l));
   b.G = (double *)ar.take(8 * (size_t)l * l);
@@ -529,20 +531,34 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   };
   const int32_t *done = &b.state->done;
   const int32_t *pass_skip = &b.state->pass_skip;
-  // One eigSVD block (Alg. 3 on C = the current block) overlapped with the
-  // next product:  G = C^T C ; [ eig(G) on the second stream || Z = M C ] ;
-  // Q = C W ; Y = Z W.  Since M Q = M (C W) = (M C) W, Y is the next pass's
-  // M Q without waiting for the eigensolver before the SpMM.  With the BF16
-  // panel form the plain order is used: Q = C W, then Y = M Q from BF16 Q.
-  const bool overlap = pdt == cdt;
-  auto block_step = [&](int mode, int pass, const int32_t *gate) -> hipError_t {
-    tmark_begin(h, DASHSVD_KT_GRAM, pass);
-    hipError_t e = launch_gram(Mn, l, b.C, ld, cdt, b.gpart, nb_n, b.G, gate, st, (int32_t *)pass_skip);
-    tmark_end(h);
-    if (e != hipSuccess) return e;
-    EigArgs ea = make_eig(mode);
-    const int32_t *skip = gate ? pass_skip : nullptr;
-    if (overlap) {
+  const int every = h->opt.check_interval > 0 ? h->opt.check_interval : 1;
+  // Host-side stop test after every `every` passes (tolerance runs only).
+  auto stopped = [&](int launched, bool &stop) -> hipError_t {
+    stop = false;
+    if (!(tol > 0.0 && launched < pmax)) return hipSuccess;
+    int32_t hd = 0;
+    hipError_t e = hipMemcpyAsync(&hd, done, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    stop = hd != 0;
+    return e;
+  };
+  int last_pass = 0;  // passes whose eigSVD ran (the final block's C, Z, W)
+  if (pdt == cdt) {
+    // Overlapped order (FP32 and FP64 forms).  With C the current block and
+    // W its eigSVD weights (Q = C W), the next pass is
+    //   Y+ = M Q = (M C) W = Z W,  C+ = M^T Y+ - alpha Q = (M^T Z - alpha C) W,
+    // so both products of the next pass, Z = M C and X = M^T Z, need only C
+    // and run on the main stream while the eigensolver works on the second
+    // one; after it, one rescale forms C+ = (X - alpha C) W with the updated
+    // shift.  Q and Y are formed only for the final Rayleigh-Ritz step.
+    void *Cb[2] = {b.C, b.Q};
+    auto side = [&](int mode, int pass, void *Cin, const int32_t *gate) -> hipError_t {
+      tmark_begin(h, DASHSVD_KT_GRAM, pass);
+      hipError_t e = launch_gram(Mn, l, Cin, ld, cdt, b.gpart, nb_n, b.G, gate, st, (int32_t *)pass_skip);
+      tmark_end(h);
+      if (e != hipSuccess) return e;
+      EigArgs ea = make_eig(mode);
+      const int32_t *skip = gate ? pass_skip : nullptr;
       if ((e = hipEventRecord(h->ev_gram, st)) != hipSuccess) return e;
       if ((e = hipStreamWaitEvent(st2, h->ev_gram, 0)) != hipSuccess) return e;
       tmark_begin(h, DASHSVD_KT_EIG, pass, st2);
@@ -551,75 +567,117 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       if (e != hipSuccess) return e;
       if ((e = hipEventRecord(h->ev_eig, st2)) != hipSuccess) return e;
       tmark_begin(h, DASHSVD_KT_SPMM, pass);
-      e = launch_spmm(Mm, rpM, colM, valM, vdt, b.C, ld, cdt, b.Z, ld, cdt, ld, b.planM.n_chunks, b.planM.tasks,
+      e = launch_spmm(Mm, rpM, colM, valM, vdt, Cin, ld, cdt, b.Z, ld, cdt, ld, b.planM.n_chunks, b.planM.tasks,
                       b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, skip, st);
       tmark_end(h);
       if (e != hipSuccess) return e;
-      if ((e = hipStreamWaitEvent(st, h->ev_eig, 0)) != hipSuccess) return e;
+      tmark_begin(h, DASHSVD_KT_SPMM_T, pass);
+      e = launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Z, ld, cdt, b.X, ld, cdt, ld, b.planT.n_chunks, b.planT.tasks,
+                      b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr, skip, st);
+      tmark_end(h);
+      if (e != hipSuccess) return e;
+      return hipStreamWaitEvent(st, h->ev_eig, 0);
+    };
+    // sketch (Alg. 5 step 2): C = M^T Omega, its eigSVD || M C, M^T M C
+    tmark_begin(h, DASHSVD_KT_SKETCH, 0);
+    HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, Cb[0], ld, cdt, ld, b.planT.n_chunks,
+                       b.planT.tasks, b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr,
+                       nullptr, st));
+    tmark_end(h);
+    HIPCHK(side(1, 0, Cb[0], nullptr));
+    // power passes (steps 3-8)
+    int launched = 0;
+    while (launched < pmax) {
+      const int chunk = (pmax - launched) < every ? (pmax - launched) : every;
+      for (int c = 0; c < chunk; ++c) {
+        const int pass = launched + c + 1;
+        tmark_begin(h, DASHSVD_KT_RESCALE, pass);
+        HIPCHK(launch_rescale(Mn, l, b.X, ld, cdt, b.W, l, l, Cb[pass & 1], ld, cdt, done, st, Cb[(pass - 1) & 1],
+                              &b.state->alpha));
+        tmark_end(h);
+        HIPCHK(side(2, pass, Cb[pass & 1], done));
+      }
+      launched += chunk;
+      bool stop = false;
+      HIPCHK(stopped(launched, stop));
+      if (stop) break;
+    }
+    HIPCHK(hipMemcpyAsync(&last_pass, &b.state->pass, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  } else {
+    // Plain order (BF16 panels): C = M^T Y - alpha Q from the BF16 panels,
+    // G = C^T C, eig, Q = C W, Y = M Q.
+    auto block_step = [&](int mode, int pass, const int32_t *gate) -> hipError_t {
+      tmark_begin(h, DASHSVD_KT_GRAM, pass);
+      hipError_t e = launch_gram(Mn, l, b.C, ld, cdt, b.gpart, nb_n, b.G, gate, st, (int32_t *)pass_skip);
+      tmark_end(h);
+      if (e != hipSuccess) return e;
+      EigArgs ea = make_eig(mode);
+      const int32_t *skip = gate ? pass_skip : nullptr;
+      tmark_begin(h, DASHSVD_KT_EIG, pass);
+      e = launch_eig(ea, st);
+      tmark_end(h);
+      if (e != hipSuccess) return e;
       tmark_begin(h, DASHSVD_KT_RESCALE, pass);
       e = launch_rescale(Mn, l, b.C, ld, cdt, b.W, l, l, b.Q, ld, pdt, skip, st);
-      if (e == hipSuccess) e = launch_rescale(Mm, l, b.Z, ld, cdt, b.W, l, l, b.Y, ld, pdt, skip, st);
+      tmark_end(h);
+      if (e != hipSuccess) return e;
+      tmark_begin(h, DASHSVD_KT_SPMM, pass);
+      e = launch_spmm(Mm, rpM, colM, valM, vdt, b.Q, ld, pdt, b.Y, ld, pdt, ld, b.planM.n_chunks, b.planM.tasks,
+                      b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, skip, st);
       tmark_end(h);
       return e;
-    }
-    tmark_begin(h, DASHSVD_KT_EIG, pass);
-    e = launch_eig(ea, st);
+    };
+    // sketch (Alg. 5 step 2): C = M^T Omega ; Q = eigSVD(C).U ; Y = M Q
+    tmark_begin(h, DASHSVD_KT_SKETCH, 0);
+    HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ld, b.planT.n_chunks, b.planT.tasks,
+                       b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr, nullptr, st));
     tmark_end(h);
-    if (e != hipSuccess) return e;
-    tmark_begin(h, DASHSVD_KT_RESCALE, pass);
-    e = launch_rescale(Mn, l, b.C, ld, cdt, b.W, l, l, b.Q, ld, pdt, skip, st);
-    tmark_end(h);
-    if (e != hipSuccess) return e;
-    tmark_begin(h, DASHSVD_KT_SPMM, pass);
-    e = launch_spmm(Mm, rpM, colM, valM, vdt, b.Q, ld, pdt, b.Y, ld, pdt, ld, b.planM.n_chunks, b.planM.tasks,
-                    b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, skip, st);
-    tmark_end(h);
-    return e;
-  };
-
-  // sketch (Alg. 5 step 2): C = M^T Omega ; Q = eigSVD(C).U ; Y = M Q
-  tmark_begin(h, DASHSVD_KT_SKETCH, 0);
-  HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ld, b.planT.n_chunks, b.planT.tasks,
-                     b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr, nullptr, st));
-  tmark_end(h);
-  HIPCHK(block_step(1, 0, nullptr));
-  // power passes (steps 3-8): C = M^T Y - alpha Q ; eigSVD(C) ; check ; shift
-  const int every = h->opt.check_interval > 0 ? h->opt.check_interval : 1;
-  int launched = 0;
-  while (launched < pmax) {
-    const int chunk = (pmax - launched) < every ? (pmax - launched) : every;
-    for (int c = 0; c < chunk; ++c) {
-      const int pass = launched + c + 1;
-      tmark_begin(h, DASHSVD_KT_SPMM_T, pass);
-      HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ld, b.planT.n_chunks,
-                         b.planT.tasks, b.planT.n_long, b.planT.longs, b.planT.partial, T, b.Q, ld,
-                         &b.state->alpha, done, st));
-      tmark_end(h);
-      HIPCHK(block_step(2, pass, done));
+    HIPCHK(block_step(1, 0, nullptr));
+    // power passes (steps 3-8): C = M^T Y - alpha Q ; eigSVD(C) ; check ; shift
+    int launched = 0;
+    while (launched < pmax) {
+      const int chunk = (pmax - launched) < every ? (pmax - launched) : every;
+      for (int c = 0; c < chunk; ++c) {
+        const int pass = launched + c + 1;
+        tmark_begin(h, DASHSVD_KT_SPMM_T, pass);
+        HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ld, b.planT.n_chunks,
+                           b.planT.tasks, b.planT.n_long, b.planT.longs, b.planT.partial, T, b.Q, ld,
+                           &b.state->alpha, done, st));
+        tmark_end(h);
+        HIPCHK(block_step(2, pass, done));
+      }
+      launched += chunk;
+      bool stop = false;
+      HIPCHK(stopped(launched, stop));
+      if (stop) break;
     }
-    launched += chunk;
-    if (tol > 0.0 && launched < pmax) {
-      int32_t hd = 0;
-      HIPCHK(hipMemcpyAsync(&hd, done, 4, hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      if (hd) break;
-    }
+    HIPCHK(hipStreamSynchronize(st));
   }
-  HIPCHK(hipStreamSynchronize(st));
   const double t_loop = now_ms();
   // final Rayleigh-Ritz (steps 9-11): B = M Q ; eigSVD(B) ; U = B W(:,1:k) ;
-  // V = Q Vs(:,1:k).  B is the last Y (= M Q); the BF16 form keeps an FP32 B.
+  // V = Q Vs(:,1:k).
   tmark_begin(h, DASHSVD_KT_FINAL, 0);
-  if (pdt != cdt)
+  void *Qf = b.Q;
+  if (pdt == cdt) {
+    // the last block: C (its buffer alternates with the pass), Z = M C and
+    // W; Q = C W and B = Z W
+    void *Cl = (last_pass & 1) ? b.Q : b.C;
+    Qf = (last_pass & 1) ? b.C : b.Q;
+    HIPCHK(launch_rescale(Mn, l, Cl, ld, cdt, b.W, l, l, Qf, ld, pdt, nullptr, st));
+    HIPCHK(launch_rescale(Mm, l, b.Z, ld, cdt, b.W, l, l, b.B, ld, cdt, nullptr, st));
+  } else {
+    // the BF16 form keeps an FP32 B
     HIPCHK(launch_spmm(Mm, rpM, colM, valM, vdt, b.Q, ld, pdt, b.B, ld, cdt, ld, b.planM.n_chunks, b.planM.tasks,
                        b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, nullptr, st));
+  }
   HIPCHK(launch_gram(Mm, l, b.B, ld, cdt, b.gpart, nb_m, b.G, nullptr, st, nullptr));
   {
     EigArgs ea = make_eig(3);
     HIPCHK(launch_eig(ea, st));
   }
   HIPCHK(launch_rescale(Mm, l, b.B, ld, cdt, b.W, l, k, b.Uo, k, cdt, nullptr, st));
-  HIPCHK(launch_rescale(Mn, l, b.Q, ld, pdt, b.Vs, l, k, b.Vo, k, cdt, nullptr, st));
+  HIPCHK(launch_rescale(Mn, l, Qf, ld, pdt, b.Vs, l, k, b.Vo, k, cdt, nullptr, st));
   HIPCHK(launch_sign_fix(Mn, Mm, k, b.Vo, k, b.Uo, k, cdt, b.sgn_max, b.sgn_idx, sgn_blk, st));
   tmark_end(h);
   SolverState hs;

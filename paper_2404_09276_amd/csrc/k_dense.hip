@@ -172,8 +172,13 @@ template <typename TC, typename TO, int LTO>
 __global__ __launch_bounds__(256) void k_rescale_mfma(int64_t r, int l, const TC *__restrict__ C,
                                                       int64_t ldc, const double *__restrict__ W,
                                                       int64_t ldw, int c, TO *__restrict__ Out,
-                                                      int64_t ldo, const int32_t *__restrict__ done) {
+                                                      int64_t ldo, const int32_t *__restrict__ done,
+                                                      const TC *__restrict__ R,
+                                                      const double *__restrict__ alpha) {
   if (done && *done) return;
+  // with R: the input rows are C - alpha R (R laid out like C), formed in
+  // FP64 and rounded once
+  const double a_sh = R ? *alpha : 0.0;
   constexpr int WC = LTO * 16;
   constexpr int SW = WC + 4;
   extern __shared__ float lds[];
@@ -199,6 +204,13 @@ __global__ __launch_bounds__(256) void k_rescale_mfma(int64_t r, int l, const TC
         const int64_t row = rb + rr;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         if (row < r) v = *reinterpret_cast<const float4 *>(C + row * ldc + k4);
+        if (R && row < r) {
+          const float4 w = *reinterpret_cast<const float4 *>(R + row * ldc + k4);
+          v.x = (float)((double)v.x - a_sh * (double)w.x);
+          v.y = (float)((double)v.y - a_sh * (double)w.y);
+          v.z = (float)((double)v.z - a_sh * (double)w.z);
+          v.w = (float)((double)v.w - a_sh * (double)w.w);
+        }
         float *dst = Cs + rr * SC + k4;
         dst[0] = k4 < l ? v.x : 0.0f;
         dst[1] = k4 + 1 < l ? v.y : 0.0f;
@@ -209,7 +221,12 @@ __global__ __launch_bounds__(256) void k_rescale_mfma(int64_t r, int l, const TC
       for (int idx = threadIdx.x; idx < kStrip * LK; idx += 256) {
         const int rr = idx / LK, kk = idx - rr * LK;
         const int64_t row = rb + rr;
-        Cs[rr * SC + kk] = (row < r && kk < l) ? (float)to_d(C[row * ldc + kk]) : 0.0f;
+        double x = 0.0;
+        if (row < r && kk < l) {
+          x = to_d(C[row * ldc + kk]);
+          if (R) x -= a_sh * to_d(R[row * ldc + kk]);
+        }
+        Cs[rr * SC + kk] = (float)x;
       }
     }
     __syncthreads();
@@ -254,8 +271,11 @@ template <typename TC>
 __global__ __launch_bounds__(256) void k_rescale_f64(int64_t r, int l, const TC *__restrict__ C,
                                                      int64_t ldc, const double *__restrict__ W,
                                                      int64_t ldw, int c, double *__restrict__ Out,
-                                                     int64_t ldo, const int32_t *__restrict__ done) {
+                                                     int64_t ldo, const int32_t *__restrict__ done,
+                                                     const TC *__restrict__ R,
+                                                     const double *__restrict__ alpha) {
   if (done && *done) return;
+  const double a_sh = R ? *alpha : 0.0;
   const int64_t total = r * ldo;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
@@ -264,7 +284,12 @@ __global__ __launch_bounds__(256) void k_rescale_f64(int64_t r, int l, const TC 
     double s = 0.0;
     if (col < c) {
       const TC *cr = C + row * ldc;
-      for (int k = 0; k < l; ++k) s = fma(to_d(cr[k]), W[(int64_t)k * ldw + col], s);
+      if (R) {
+        const TC *rr = R + row * ldc;
+        for (int k = 0; k < l; ++k) s = fma(fma(-a_sh, to_d(rr[k]), to_d(cr[k])), W[(int64_t)k * ldw + col], s);
+      } else {
+        for (int k = 0; k < l; ++k) s = fma(to_d(cr[k]), W[(int64_t)k * ldw + col], s);
+      }
     }
     Out[row * ldo + col] = s;
   }
@@ -404,7 +429,8 @@ hipError_t gram_dispatch(int64_t r, int l, const TC *C, int64_t ldc, double *par
 
 template <typename TC, typename TO>
 hipError_t rescale_dispatch(int64_t r, int l, const TC *C, int64_t ldc, const double *W, int64_t ldw,
-                            int c, TO *Out, int64_t ldo, const int32_t *done, hipStream_t st) {
+                            int c, TO *Out, int64_t ldo, const int32_t *done, const TC *R,
+                            const double *alpha, hipStream_t st) {
   const int LTO = (c + 15) / 16;
   const int LK = (l + 3) & ~3;
   const int64_t nstrips = (r + kStrip - 1) / kStrip;
@@ -414,7 +440,7 @@ hipError_t rescale_dispatch(int64_t r, int l, const TC *C, int64_t ldc, const do
   case LTV: {                                                                                   \
     const size_t shm = sizeof(float) * ((size_t)LK * (LTV * 16 + 4) + (size_t)kStrip * (LK + 1)); \
     hipLaunchKernelGGL((k_rescale_mfma<TC, TO, LTV>), dim3(grid), dim3(256), shm, st, r, l, C, ldc, W, \
-                       ldw, c, Out, ldo, done);                                                 \
+                       ldw, c, Out, ldo, done, R, alpha);                                       \
     break;                                                                                      \
   }
   switch (LTO) {
@@ -450,7 +476,8 @@ hipError_t launch_gram(int64_t r, int l, const void *C, int64_t ldc, int cdtype,
 
 hipError_t launch_rescale(int64_t r, int l, const void *C, int64_t ldc, int cdtype, const double *W,
                           int64_t ldw, int c, void *Out, int64_t ldo, int odtype, const int32_t *done,
-                          hipStream_t st) {
+                          hipStream_t st, const void *R, const double *alpha) {
+  if (R && !alpha) return hipErrorInvalidValue;
   if (l < 1 || l > kMaxL || c < 1 || c > kMaxL || r == 0) return r == 0 ? hipSuccess : hipErrorInvalidValue;
   static bool attr_done = false;
   if (!attr_done) {
@@ -471,20 +498,23 @@ hipError_t launch_rescale(int64_t r, int l, const void *C, int64_t ldc, int cdty
     const int g = grid_for(r * ldo, 256, 16384);
     if (cdtype == 1)
       hipLaunchKernelGGL(k_rescale_f64<double>, dim3(g), dim3(256), 0, st, r, l, (const double *)C, ldc, W, ldw,
-                         c, (double *)Out, ldo, done);
+                         c, (double *)Out, ldo, done, (const double *)R, alpha);
     else if (cdtype == 0)
       hipLaunchKernelGGL(k_rescale_f64<float>, dim3(g), dim3(256), 0, st, r, l, (const float *)C, ldc, W, ldw, c,
-                         (double *)Out, ldo, done);
+                         (double *)Out, ldo, done, (const float *)R, alpha);
     else
       return hipErrorInvalidValue;
     return hipGetLastError();
   }
   if (cdtype == 0 && odtype == 0)
-    return rescale_dispatch<float, float>(r, l, (const float *)C, ldc, W, ldw, c, (float *)Out, ldo, done, st);
+    return rescale_dispatch<float, float>(r, l, (const float *)C, ldc, W, ldw, c, (float *)Out, ldo, done,
+                                          (const float *)R, alpha, st);
   if (cdtype == 0 && odtype == 2)
-    return rescale_dispatch<float, bf16>(r, l, (const float *)C, ldc, W, ldw, c, (bf16 *)Out, ldo, done, st);
+    return rescale_dispatch<float, bf16>(r, l, (const float *)C, ldc, W, ldw, c, (bf16 *)Out, ldo, done,
+                                         (const float *)R, alpha, st);
   if (cdtype == 2 && odtype == 0)
-    return rescale_dispatch<bf16, float>(r, l, (const bf16 *)C, ldc, W, ldw, c, (float *)Out, ldo, done, st);
+    return rescale_dispatch<bf16, float>(r, l, (const bf16 *)C, ldc, W, ldw, c, (float *)Out, ldo, done,
+                                         (const bf16 *)R, alpha, st);
   return hipErrorInvalidValue;
 }
 

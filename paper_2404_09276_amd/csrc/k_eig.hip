@@ -16,9 +16,11 @@
 //   - the eigenvector matrix V lives in registers: each lane owns four
 //     consecutive columns of some rows, so even-step rotations stay in the
 //     lane and odd steps exchange one value with the neighbouring lane;
-//   - the rotation parameters of a step are published in LDS.
-// A step is: rotations (one thread per pair) | barrier | 2x2 block updates
-// of G (one thread per block pair) and the V update | barrier.
+//   - the rotation parameters of a step are published in LDS, one buffer
+//     per parity.
+// A step is: rotations (one thread per pair) overlapped with the previous
+// step's V update | barrier | 2x2 block updates of G (one thread per block
+// pair, addresses decoded once per launch) | barrier.
 //
 // Tail: S = sqrt(max(lambda, 0)) in descending order (ties by original
 // index, descending), W = V diag(1/S) with columns zeroed where S <=
@@ -34,7 +36,7 @@ constexpr int kEigThreads = 1024;
 constexpr int kMaxLP = 160;           // padded size L (multiple of 4)
 constexpr int kMaxPairs = kMaxLP / 2;
 constexpr int kMaxNR = 10;            // register row slots per lane (L=160: 40 lanes/row, 1 row/wave)
-constexpr int kMaxItems = 4;          // block items per thread per parity
+constexpr int kMaxItems = 4;          // block items per thread per parity (L = 160)
 
 __device__ __forceinline__ int pk(int i, int j, int L) {  // i <= j
   return i * L - ((i * (i - 1)) >> 1) + (j - i);
@@ -78,7 +80,34 @@ __device__ __forceinline__ double frsqrt(double x) {
   return y;
 }
 
-template <int MAXNR>
+// Whole-wave shifts by one lane through DPP (a VALU modifier: no LDS
+// traffic).  wave_shr1: lane i receives lane i-1; wave_shl1: lane i receives
+// lane i+1; the edge lane keeps its own value, which callers never use.
+__device__ __forceinline__ double dpp_move(double x, int ctrl_sel) {
+  const long long b = __double_as_longlong(x);
+  int lo = (int)(b & 0xffffffffll), hi = (int)(b >> 32);
+  if (ctrl_sel) {
+    lo = __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false);
+    hi = __builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false);
+  } else {
+    lo = __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false);
+    hi = __builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false);
+  }
+  return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+__device__ __forceinline__ double wave_shr1(double x) { return dpp_move(x, 1); }
+__device__ __forceinline__ double wave_shl1(double x) { return dpp_move(x, 0); }
+
+template <int N>
+struct IC {
+  static constexpr int value = N;
+};
+
+// MAXNR: register row slots of V per lane; MAXIT: G block items per thread
+// and parity (both upper bounds for the launched size); BATCH: items whose
+// loads are issued together; CPL: consecutive V columns per lane (4 up to
+// L = 128, 8 above, where L is then a multiple of 8)
+template <int MAXNR, int MAXIT, int BATCH, int CPL>
 __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
   SolverState *state = a.state;
   if (state && a.mode == 2) {
@@ -90,18 +119,17 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
     if (stopped) return;
   }
   extern __shared__ double G[];  // packed upper, L(L+1)/2
-  __shared__ double2 rot_cs[kMaxPairs];  // (c, s) of each pair's rotation
-  __shared__ double2 rot_tf[kMaxPairs];  // (t = s/c, 1 if rotated else 0)
+  __shared__ double2 rot_cs[2][kMaxPairs];  // (c, s) of each pair's rotation, by parity
+  __shared__ double2 rot_tf[2][kMaxPairs];  // (t = s/c, 1 if rotated else 0), by parity
   __shared__ int label[kMaxLP];
   __shared__ int rank_of[kMaxLP];
   __shared__ double Ssh[kMaxLP];
   __shared__ int s_flag;
   __shared__ int s_sweeps;
-  __shared__ uint16_t items[2][kMaxItems * kEigThreads];
 
   const int l = a.l;
   const double kSkip = a.skip;  // rotation / convergence threshold (relative)
-  const int L = (l + 3) & ~3;
+  const int L = CPL == 8 ? (l + 7) & ~7 : (l + 3) & ~3;
   const int P = L / 2;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -112,43 +140,136 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
   }
   for (int p = tid; p < L; p += kEigThreads) label[p] = p;
 
-  // block items of both parities, decoded once into LDS: pairs of groups
-  // (gb <= ga) enumerated row by row of the packed upper triangle (gb outer,
-  // ga inner), so neighbouring lanes touch neighbouring LDS words; packed as
-  // ga << 8 | gb (0xffff = none)
+  // Block items of this thread for both parities, decoded once: pairs of
+  // groups (gb <= ga) enumerated row by row of the packed upper triangle (gb
+  // outer, ga inner), so neighbouring lanes touch neighbouring LDS words.
+  // Per item: the packed offsets of the block's two b-rows at its first
+  // a-index (two 16-bit fields; the second a-index is the next word of the
+  // same row) and a meta word: rotation slots of both groups, whether each
+  // group holds two indices, whether the block is diagonal, whether the item
+  // exists.  For a diagonal block the fields are (p,p) and (q,q); (p,q) is
+  // the word after (p,p).
+  constexpr uint32_t kA2 = 1u << 16, kB2 = 1u << 17, kDiag = 1u << 18, kValid = 1u << 19;
+  uint32_t it_o[2][MAXIT], it_m[2][MAXIT];
+#pragma unroll
   for (int par = 0; par < 2; ++par) {
     const int ng = par ? P + 1 : P;
     const int nitems = ng * (ng + 1) / 2;
-    for (int t = tid; t < kMaxItems * kEigThreads; t += kEigThreads) {
-      uint16_t code = 0xffff;
+    const int npairs = par ? P - 1 : P;
+#pragma unroll
+    for (int s_ = 0; s_ < MAXIT; ++s_) {
+      const int t = tid + s_ * kEigThreads;
+      uint32_t o = 0, meta = 0;
       if (t < nitems) {
         int gb = 0, rem = t;
         while (rem >= ng - gb) {
           rem -= ng - gb;
           ++gb;
         }
-        code = (uint16_t)(((gb + rem) << 8) | gb);
+        const int ga = gb + rem;
+        int fa, na, fb, nb;
+        group_of(par, ga, P, fa, na);
+        group_of(par, gb, P, fb, nb);
+        int sa = slot_of(par, ga), sb = slot_of(par, gb);
+        sa = sa < 0 ? 0 : (sa >= npairs ? npairs - 1 : sa);
+        sb = sb < 0 ? 0 : (sb >= npairs ? npairs - 1 : sb);
+        if (ga == gb) {
+          if (na == 2) {
+            o = (uint32_t)pk(fa, fa, L) | ((uint32_t)pk(fa + 1, fa + 1, L) << 16);
+            meta = (uint32_t)sa | kDiag | kValid;
+          }
+        } else {
+          // rows fb and fb+1 of the packed triangle at column fa (a single
+          // b-index reuses row fb; the word after a single a-index is still
+          // inside the array and is loaded but never used or stored)
+          const int i00 = pk(fb, fa, L);
+          const int i01 = nb == 2 ? pk(fb + 1, fa, L) : i00;
+          o = (uint32_t)i00 | ((uint32_t)i01 << 16);
+          meta = (uint32_t)sa | ((uint32_t)sb << 8) | (na == 2 ? kA2 : 0u) | (nb == 2 ? kB2 : 0u) | kValid;
+        }
       }
-      items[par][t] = code;
+      it_o[par][s_] = o;
+      it_m[par][s_] = meta;
     }
   }
 
-  // V in registers: lane column block cl owns columns 4cl..4cl+3 of its rows
-  const int LPR = L / 4;             // lanes per row
+  // V in registers: lane column block cl owns columns CPL cl .. CPL cl +
+  // CPL - 1 of its rows
+  const int LPR = L / CPL;           // lanes per row
   const int RPW = kWave / LPR;       // rows per wave
   const int sub = lane / LPR, cl = lane - sub * LPR;
   const bool active = sub < RPW;
   const int row_stride = (kEigThreads / kWave) * RPW;
   const int NR = (L + row_stride - 1) / row_stride;
-  double v[MAXNR][4];
+  const int c0 = CPL * cl;
+  double v[MAXNR][CPL];
 #pragma unroll
   for (int it = 0; it < MAXNR; ++it) {
     const int row = wave * RPW + sub + it * row_stride;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) v[it][j] = (active && row < L && row == 4 * cl + j) ? 1.0 : 0.0;
+    for (int j = 0; j < CPL; ++j) v[it][j] = (active && row < L && row == c0 + j) ? 1.0 : 0.0;
   }
   if (tid == 0) s_sweeps = 0;
   __syncthreads();
+
+  // V <- V M for the column pairs of one parity, with that parity's
+  // published rotations; waves that hold no row skip.  M = [[s, c], [c, -s]]
+  // (rotation then swap; c = 1, s = 0 is the plain swap), M = I outside the
+  // pairs of the step.  Even steps pair (c0 + 2i, c0 + 2i + 1) inside the
+  // lane (slot c0/2 + i); odd steps pair (c0 + 2i + 1, c0 + 2i + 2) inside
+  // it (slot c0/2 + i) and the two edge columns with the neighbouring lanes
+  // (slots c0/2 - 1 and c0/2 + CPL/2 - 1).
+  auto v_update = [&](int vpar) __attribute__((always_inline)) {
+    if (wave * RPW >= L) return;
+    const int npairs = vpar ? P - 1 : P;
+    const double2 *rcs = rot_cs[vpar];
+    const bool first = cl == 0, last = cl == LPR - 1;
+    if (!vpar) {
+      double2 cs[CPL / 2];
+#pragma unroll
+      for (int i = 0; i < CPL / 2; ++i) {
+        const int sl = c0 / 2 + i;
+        cs[i] = rcs[sl < npairs ? sl : npairs - 1];
+        if (sl >= npairs) cs[i] = make_double2(0.0, 1.0);  // only on idle lanes
+      }
+#pragma unroll
+      for (int it = 0; it < MAXNR; ++it) {
+        if (it < NR) {
+#pragma unroll
+          for (int i = 0; i < CPL / 2; ++i) {
+            const double x = v[it][2 * i], y = v[it][2 * i + 1];
+            v[it][2 * i] = x * cs[i].y + y * cs[i].x;
+            v[it][2 * i + 1] = x * cs[i].x - y * cs[i].y;
+          }
+        }
+      }
+    } else {
+      double2 cs[CPL / 2 + 1];  // [0]: left edge pair, [1..]: inner pairs, [CPL/2]: right edge
+#pragma unroll
+      for (int i = 0; i <= CPL / 2; ++i) {
+        const int sl = c0 / 2 - 1 + i;
+        const int slc = sl < 0 ? 0 : (sl >= npairs ? npairs - 1 : sl);
+        cs[i] = rcs[slc];
+      }
+#pragma unroll
+      for (int it = 0; it < MAXNR; ++it) {
+        if (it < NR) {
+          const double nxt = wave_shl1(v[it][0]);
+          const double prv = wave_shr1(v[it][CPL - 1]);
+#pragma unroll
+          for (int i = 0; i < CPL / 2 - 1; ++i) {
+            const double2 r = cs[i + 1];
+            const double x = v[it][2 * i + 1], y = v[it][2 * i + 2];
+            v[it][2 * i + 1] = x * r.y + y * r.x;
+            v[it][2 * i + 2] = x * r.x - y * r.y;
+          }
+          const double x0 = v[it][0], xl = v[it][CPL - 1];
+          v[it][0] = first ? x0 : prv * cs[0].x - x0 * cs[0].y;
+          v[it][CPL - 1] = last ? xl : xl * cs[CPL / 2].y + nxt * cs[CPL / 2].x;
+        }
+      }
+    }
+  };
 
   for (int sweep = 0; sweep < 60; ++sweep) {
     // convergence test before the sweep: any entry above the skip threshold?
@@ -164,15 +285,21 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
     __syncthreads();
     if (!s_flag) break;
     if (tid == 0) s_sweeps = sweep + 1;
+    // A step has two phases separated by barriers:
+    //   1. one thread per pair computes this step's rotation (and swaps the
+    //      two labels), while every thread applies the previous step's
+    //      rotations to its rows of V (rotations are double-buffered by
+    //      parity; L is even, so parity = step & 1 in every sweep);
+    //   2. the 2x2 blocks of G are updated, B <- Ma^T B Mb, all loads of a
+    //      thread issued before its first store.
     for (int step = 0; step < L; ++step) {
       const int par = step & 1;
       const int npairs = par ? P - 1 : P;
-      long long c0 = 0, w0 = 0;
+      long long c0 = 0, w0 = 0, ca_ = 0, cv = 0;
       if (a.prof && tid == 0) {
         c0 = clock64();
         w0 = wall_clock64();
       }
-      // phase A: rotation of each pair (and the index swap that follows it)
       if (tid < npairs) {
         const int p = par ? 2 * tid + 1 : 2 * tid, q = p + 1;
         const double app = G[pk(p, p, L)], aqq = G[pk(q, q, L)], apq = G[pk(p, q, L)];
@@ -187,129 +314,125 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
           s = t * c;
           rot = 1.0;
         }
-        rot_cs[tid] = make_double2(c, s);
-        rot_tf[tid] = make_double2(t, rot);
+        rot_cs[par][tid] = make_double2(c, s);
+        rot_tf[par][tid] = make_double2(t, rot);
         label[p] = lq;
         label[q] = lp;
       }
+      if (a.prof && tid == 0) ca_ = clock64();
+      if (step > 0) v_update(par ^ 1);
+      if (a.prof && tid == 0) cv = clock64();
       __syncthreads();
       long long c1 = 0;
       if (a.prof && tid == 0) c1 = clock64();
-      // phase B: 2x2 blocks of G, B <- Ma^T B Mb with M = J P (rotation then
-      // swap): M = [[s, c], [c, -s]] when rotated, [[0, 1], [1, 0]] when not
-      for (int s_ = 0; s_ < kMaxItems; ++s_) {
-        const uint16_t code = items[par][tid + s_ * kEigThreads];
-        if (code == 0xffff) break;
-        const int ga = code >> 8, gb = code & 0xff;
-        int fa, na, fb, nb;
-        group_of(par, ga, P, fa, na);
-        group_of(par, gb, P, fb, nb);
-        int sa = slot_of(par, ga), sb = slot_of(par, gb);
-        sa = sa < 0 ? 0 : (sa >= npairs ? npairs - 1 : sa);
-        sb = sb < 0 ? 0 : (sb >= npairs ? npairs - 1 : sb);
-        if (ga == gb) {
-          if (na == 2) {
-            const int p = fa, q = fa + 1;
-            const double2 tf = rot_tf[sa];
-            const double app = G[pk(p, p, L)], aqq = G[pk(q, q, L)], apq = G[pk(p, q, L)];
-            if (tf.y != 0.0) {
-              G[pk(p, p, L)] = fma(tf.x, apq, aqq);  // swapped
-              G[pk(q, q, L)] = fma(-tf.x, apq, app);
-              G[pk(p, q, L)] = 0.0;
-            } else {
-              G[pk(p, p, L)] = aqq;
-              G[pk(q, q, L)] = app;
-            }
-          }
-          continue;
-        }
-        // off-diagonal block: rows of ga (larger indices), columns of gb;
-        // all loads issued before any use.  M = [[s, c], [c, -s]] for both the
-        // rotated case and the plain swap (c = 1, s = 0); a single-index group
-        // has M = [1].
-        const double2 csa = rot_cs[sa], csb = rot_cs[sb];
-        const int i00 = pk(fb, fa, L);
-        const int i01 = nb == 2 ? pk(fb + 1, fa, L) : i00;
-        const int i10 = na == 2 ? pk(fb, fa + 1, L) : i00;
-        const int i11 = (na == 2 && nb == 2) ? pk(fb + 1, fa + 1, L) : i00;
-        const double g00 = G[i00], g01 = G[i01], g10 = G[i10], g11 = G[i11];
-        const double ma00 = na == 2 ? csa.y : 1.0, ma01 = na == 2 ? csa.x : 0.0;
-        const double ma10 = na == 2 ? csa.x : 0.0, ma11 = na == 2 ? -csa.y : 1.0;
-        const double mb00 = nb == 2 ? csb.y : 1.0, mb01 = nb == 2 ? csb.x : 0.0;
-        const double mb10 = nb == 2 ? csb.x : 0.0, mb11 = nb == 2 ? -csb.y : 1.0;
-        const double b01 = nb == 2 ? g01 : 0.0;
-        const double b10 = na == 2 ? g10 : 0.0;
-        const double b11 = (na == 2 && nb == 2) ? g11 : 0.0;
-        // T = B Mb ; B' = Ma^T T
-        const double t00 = g00 * mb00 + b01 * mb10, t01 = g00 * mb01 + b01 * mb11;
-        const double t10 = b10 * mb00 + b11 * mb10, t11 = b10 * mb01 + b11 * mb11;
-        G[i00] = ma00 * t00 + ma10 * t10;
-        if (nb == 2) G[i01] = ma00 * t01 + ma10 * t11;
-        if (na == 2) G[i10] = ma01 * t00 + ma11 * t10;
-        if (na == 2 && nb == 2) G[i11] = ma01 * t01 + ma11 * t11;
-      }
-      long long cmid = 0;
-      if (a.prof && tid == 0) cmid = clock64();
-      // V <- V M (column pairs of this parity); waves that hold no row skip
-      if (wave * RPW < L) {
-        // Parameters (8 per lane):
-        //   even: pair (p0, p0+1) -> e[0..3], pair (p0+2, p0+3) -> e[4..7]
-        //   odd : pair (p0-1, p0) -> e[0] = M01, e[1] = M11 (second member here)
-        //         pair (p0+1, p0+2) -> e[2..5]
-        //         pair (p0+3, p0+4) -> e[6] = M00, e[7] = M10 (first member here)
-        double e[8];
-        auto mp = [&](int sl, double &m00, double &m01, double &m10, double &m11) {
-          const int slc = sl < 0 ? 0 : (sl >= npairs ? npairs - 1 : sl);
-          const double2 cs = rot_cs[slc];
-          const bool in = sl >= 0 && sl < npairs;
-          m00 = in ? cs.y : 1.0;
-          m01 = in ? cs.x : 0.0;
-          m10 = in ? cs.x : 0.0;
-          m11 = in ? -cs.y : 1.0;
-        };
-        if (!par) {
-          mp(2 * cl, e[0], e[1], e[2], e[3]);
-          mp(2 * cl + 1, e[4], e[5], e[6], e[7]);
-        } else {
-          double d0, d1;
-          mp(2 * cl - 1, d0, e[0], d1, e[1]);
-          mp(2 * cl, e[2], e[3], e[4], e[5]);
-          mp(2 * cl + 1, e[6], d0, e[7], d1);
-        }
-        const bool first = cl == 0, last = cl == LPR - 1;
+
+      // the parity is a compile-time index into the item tables, so they stay
+      // in registers
+      auto g_update = [&](auto par_c) __attribute__((always_inline)) {
+        constexpr int PAR = decltype(par_c)::value;
+        const double2 *rcs = rot_cs[PAR];
+        const double2 *rtf = rot_tf[PAR];
+        // items in batches of BATCH (register pressure of the large sizes)
 #pragma unroll
-        for (int it = 0; it < MAXNR; ++it) {
-          if (it < NR) {
-            const double v0 = v[it][0], v1 = v[it][1], v2 = v[it][2], v3 = v[it][3];
-            if (!par) {
-              v[it][0] = v0 * e[0] + v1 * e[2];
-              v[it][1] = v0 * e[1] + v1 * e[3];
-              v[it][2] = v2 * e[4] + v3 * e[6];
-              v[it][3] = v2 * e[5] + v3 * e[7];
+        for (int b0 = 0; b0 < MAXIT; b0 += BATCH) {
+          double g[BATCH][4];
+          double2 pa[BATCH], pb[BATCH];
+          // loads: the two words of each b-row are adjacent, so each row is
+          // one paired 8-byte load and a wave's lanes cover contiguous LDS
+#pragma unroll
+          for (int s_ = b0; s_ < b0 + BATCH; ++s_) {
+            const uint32_t meta = it_m[PAR][s_], o = it_o[PAR][s_];
+            g[s_ - b0][0] = g[s_ - b0][1] = g[s_ - b0][2] = g[s_ - b0][3] = 0.0;
+            pa[s_ - b0] = pb[s_ - b0] = make_double2(0.0, 0.0);
+            if (meta & kValid) {
+              const int r0 = o & 0xffff, r1 = o >> 16;
+              const int sa = meta & 0xff, sb = (meta >> 8) & 0xff;
+              g[s_ - b0][0] = G[r0];
+              g[s_ - b0][1] = G[r0 + 1];
+              g[s_ - b0][2] = G[r1];
+              if (meta & kDiag) {
+                pa[s_ - b0] = rtf[sa];
+              } else {
+                g[s_ - b0][3] = G[r1 + 1];
+                pa[s_ - b0] = rcs[sa];
+                pb[s_ - b0] = rcs[sb];
+              }
+            }
+          }
+#pragma unroll
+          for (int s_ = b0; s_ < b0 + BATCH; ++s_) {
+            const uint32_t meta = it_m[PAR][s_], o = it_o[PAR][s_];
+            if (!(meta & kValid)) continue;
+            const int r0 = o & 0xffff, r1 = o >> 16;
+            if (meta & kDiag) {
+              // (p,p), (p,q), (q,q) of a rotated-and-swapped pair: the diagonal
+              // becomes (a_qq + t a_pq, a_pp - t a_pq) and the coupling vanishes
+              const double app = g[s_ - b0][0], apq = g[s_ - b0][1], aqq = g[s_ - b0][2];
+              const double2 tf = pa[s_ - b0];
+              if (tf.y != 0.0) {
+                G[r0] = fma(tf.x, apq, aqq);
+                G[r0 + 1] = 0.0;
+                G[r1] = fma(-tf.x, apq, app);
+              } else {
+                G[r0] = aqq;
+                G[r1] = app;
+              }
+              continue;
+            }
+            // off-diagonal block B[a][b] at row fb + b, column fa + a; a
+            // single-index group has M = [1]
+            const bool a2 = meta & kA2, b2 = meta & kB2;
+            const double2 csa = pa[s_ - b0], csb = pb[s_ - b0];
+            const double ma00 = a2 ? csa.y : 1.0, ma01 = a2 ? csa.x : 0.0;
+            const double ma10 = a2 ? csa.x : 0.0, ma11 = a2 ? -csa.y : 1.0;
+            const double mb00 = b2 ? csb.y : 1.0, mb01 = b2 ? csb.x : 0.0;
+            const double mb10 = b2 ? csb.x : 0.0, mb11 = b2 ? -csb.y : 1.0;
+            const double g00 = g[s_ - b0][0];
+            const double b10 = a2 ? g[s_ - b0][1] : 0.0;
+            const double b01 = b2 ? g[s_ - b0][2] : 0.0;
+            const double b11 = (a2 && b2) ? g[s_ - b0][3] : 0.0;
+            // T = B Mb ; B' = Ma^T T
+            const double t00 = g00 * mb00 + b01 * mb10, t01 = g00 * mb01 + b01 * mb11;
+            const double t10 = b10 * mb00 + b11 * mb10, t11 = b10 * mb01 + b11 * mb11;
+            const double n00 = ma00 * t00 + ma10 * t10, n10 = ma01 * t00 + ma11 * t10;
+            const double n01 = ma00 * t01 + ma10 * t11, n11 = ma01 * t01 + ma11 * t11;
+            if (a2) {
+              G[r0] = n00;
+              G[r0 + 1] = n10;
             } else {
-              const double nxt0 = __shfl_down(v0, 1, 64);
-              const double prv3 = __shfl_up(v3, 1, 64);
-              v[it][0] = first ? v0 : prv3 * e[0] + v0 * e[1];
-              v[it][1] = v1 * e[2] + v2 * e[4];
-              v[it][2] = v1 * e[3] + v2 * e[5];
-              v[it][3] = last ? v3 : v3 * e[6] + nxt0 * e[7];
+              G[r0] = n00;
+            }
+            if (b2) {
+              if (a2) {
+                G[r1] = n01;
+                G[r1 + 1] = n11;
+              } else {
+                G[r1] = n01;
+              }
             }
           }
         }
-      }
+      };
+      if (par)
+        g_update(IC<1>{});
+      else
+        g_update(IC<0>{});
       __syncthreads();
       if (a.prof && tid == 0) {
-        // step profile (thread 0): cycles of phase A, cycles of phase B,
-        // wall-clock ticks (100 MHz), steps, G-update cycles, V-update cycles
+        // step profile (thread 0): cycles of phase 1 and of phase 2 (each up
+        // to its barrier), wall-clock ticks (100 MHz), steps, cycles of this
+        // thread's rotation work and of its V update in phase 1
         const long long c2 = clock64();
         a.prof[0] += c1 - c0;
         a.prof[1] += c2 - c1;
         a.prof[2] += wall_clock64() - w0;
         a.prof[3] += 1;
-        a.prof[4] += cmid - c1;
-        a.prof[5] += c2 - cmid;
+        a.prof[4] += ca_ - c0;
+        a.prof[5] += cv - ca_;
       }
     }
+    // the sweep's last step is odd: its V update is still pending
+    v_update(1);
   }
 
   // ---------------------------------------------------------------- tail
@@ -337,8 +460,8 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
     const int row = wave * RPW + sub + it * row_stride;
     if (it < NR && active && row < l) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int p = 4 * cl + j;
+      for (int j = 0; j < CPL; ++j) {
+        const int p = c0 + j;
         const int rk = rank_of[p];
         if (rk >= 0) {
           const double sv = Ssh[rk];
@@ -419,26 +542,40 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
 
 hipError_t launch_eig(const EigArgs &a, hipStream_t st) {
   if (a.l < 1 || a.l > kMaxLP) return hipErrorInvalidValue;
+  // the layout rules of the kernel, mirrored: CPL columns of V per lane,
+  // L = l padded to a multiple of CPL
+  const int L4 = (a.l + 3) & ~3;
+  const int CPL = L4 > 128 ? 8 : 4;
+  const int L = CPL == 8 ? (a.l + 7) & ~7 : L4;
+  const int P = L / 2;
+  const int LPR = L / CPL, RPW = kWave / LPR;
+  const int NR = (L + 16 * RPW - 1) / (16 * RPW);
+  const int IT = ((P + 1) * (P + 2) / 2 + kEigThreads - 1) / kEigThreads;  // odd parity has more
+  const size_t shm = sizeof(double) * (size_t)(L * (L + 1) / 2);
+  void (*fn)(EigArgs) = nullptr;
+  if (CPL == 4 && NR <= 1 && IT <= 1)
+    fn = k_eig<1, 1, 1, 4>;
+  else if (CPL == 4 && NR <= 2 && IT <= 2)
+    fn = k_eig<2, 2, 2, 4>;
+  else if (CPL == 4 && NR <= 4 && IT <= 2)
+    fn = k_eig<4, 2, 2, 4>;
+  else if (CPL == 4 && NR <= 4 && IT <= 3)
+    fn = k_eig<4, 3, 1, 4>;
+  else if (CPL == 8 && NR <= 4 && IT <= kMaxItems)
+    fn = k_eig<4, kMaxItems, 1, 8>;
+  else
+    return hipErrorInvalidValue;
   static bool attr = false;
   if (!attr) {
-    hipFuncSetAttribute((const void *)k_eig<1>, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
-    hipFuncSetAttribute((const void *)k_eig<2>, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
-    hipFuncSetAttribute((const void *)k_eig<4>, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
-    hipFuncSetAttribute((const void *)k_eig<kMaxNR>, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+    hipFuncSetAttribute((const void *)k_eig<1, 1, 1, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+    hipFuncSetAttribute((const void *)k_eig<2, 2, 2, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+    hipFuncSetAttribute((const void *)k_eig<4, 2, 2, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+    hipFuncSetAttribute((const void *)k_eig<4, 3, 1, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+    hipFuncSetAttribute((const void *)k_eig<4, kMaxItems, 1, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        128 * 1024);
     attr = true;
   }
-  const int L = (a.l + 3) & ~3;
-  const int LPR = L / 4, RPW = kWave / LPR;
-  const int NR = (L + 16 * RPW - 1) / (16 * RPW);
-  const size_t shm = sizeof(double) * (size_t)(L * (L + 1) / 2);
-  if (NR <= 1)
-    hipLaunchKernelGGL(k_eig<1>, dim3(1), dim3(kEigThreads), shm, st, a);
-  else if (NR <= 2)
-    hipLaunchKernelGGL(k_eig<2>, dim3(1), dim3(kEigThreads), shm, st, a);
-  else if (NR <= 4)
-    hipLaunchKernelGGL(k_eig<4>, dim3(1), dim3(kEigThreads), shm, st, a);
-  else
-    hipLaunchKernelGGL(k_eig<kMaxNR>, dim3(1), dim3(kEigThreads), shm, st, a);
+  hipLaunchKernelGGL(fn, dim3(1), dim3(kEigThreads), shm, st, a);
   return hipGetLastError();
 }
 

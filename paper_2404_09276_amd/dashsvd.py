@@ -57,7 +57,7 @@ class _Info(C.Structure):
                 ("long_chunks_AT", C.c_int64), ("kt_ms", C.c_double * 8), ("kt_count", C.c_int32 * 8),
                 ("eig_calls", C.c_int32), ("eig_sweeps", C.c_int32)]
 
-KT_NAMES = ["spmm", "spmm_t_shift", "gram", "eig", "rescale", "transpose", "sketch", "final"]
+KT_NAMES = ["spmm", "spmm_t", "gram", "eig", "rescale", "transpose", "sketch", "final"]
 
 
 _lib = None
