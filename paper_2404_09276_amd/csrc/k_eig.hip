@@ -32,11 +32,11 @@ namespace dsv {
 
 namespace {
 
-constexpr int kEigThreads = 1024;
+constexpr int kEigThreads = 1024;      // threads up to L = 128
+constexpr int kEigThreadsL = 512;      // threads above
 constexpr int kMaxLP = 160;           // padded size L (multiple of 4)
 constexpr int kMaxPairs = kMaxLP / 2;
-constexpr int kMaxNR = 10;            // register row slots per lane (L=160: 40 lanes/row, 1 row/wave)
-constexpr int kMaxItems = 4;          // block items per thread per parity (L = 160)
+constexpr int kMaxItems = 7;          // block items per thread per parity (L = 160, 512 threads)
 
 __device__ __forceinline__ int pk(int i, int j, int L) {  // i <= j
   return i * L - ((i * (i - 1)) >> 1) + (j - i);
@@ -59,8 +59,6 @@ __device__ __forceinline__ void group_of(int parity, int g, int P, int &first, i
     size = 2;
   }
 }
-// rotation slot of a size-2 group
-__device__ __forceinline__ int slot_of(int parity, int g) { return parity ? g - 1 : g; }
 
 // Reciprocal and reciprocal square root from the hardware approximations
 // refined by two Newton steps (relative error near 1 ulp); the rotation only
@@ -106,9 +104,10 @@ struct IC {
 // MAXNR: register row slots of V per lane; MAXIT: G block items per thread
 // and parity (both upper bounds for the launched size); BATCH: items whose
 // loads are issued together; CPL: consecutive V columns per lane (4 up to
-// L = 128, 8 above, where L is then a multiple of 8)
-template <int MAXNR, int MAXIT, int BATCH, int CPL>
-__global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
+// L = 128, 8 above, where L is then a multiple of 8); NT: threads (1024, or
+// 512 for the largest sizes, so that 2 waves per SIMD leave room for V)
+template <int MAXNR, int MAXIT, int BATCH, int CPL, int NT>
+__global__ __launch_bounds__(NT) void k_eig(EigArgs a) {
   SolverState *state = a.state;
   if (state && a.mode == 2) {
     // a pass launched after the check already passed: nothing to do, and
@@ -118,9 +117,12 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
     if (threadIdx.x == 0) state->skip_rescale = stopped;
     if (stopped) return;
   }
-  extern __shared__ double G[];  // packed upper, L(L+1)/2
-  __shared__ double2 rot_cs[2][kMaxPairs];  // (c, s) of each pair's rotation, by parity
-  __shared__ double2 rot_tf[2][kMaxPairs];  // (t = s/c, 1 if rotated else 0), by parity
+  extern __shared__ double G[];  // packed upper, L(L+1)/2, then 2 zero words
+  // rotation of each index group, by parity: (c, s) with M = [[s, c], [c, -s]]
+  // (rotation then swap); a single-index group holds (0, 1), whose M keeps
+  // its one index and multiplies the absent partner by -1
+  __shared__ double2 rot_cs[2][kMaxPairs + 1];
+  __shared__ double2 rot_tf[2][kMaxPairs + 1];  // (t = s/c, 1 if rotated else 0)
   __shared__ int label[kMaxLP];
   __shared__ int rank_of[kMaxLP];
   __shared__ double Ssh[kMaxLP];
@@ -134,62 +136,98 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
 
-  for (int idx = tid; idx < L * L; idx += kEigThreads) {
+  for (int idx = tid; idx < L * L; idx += NT) {
     const int i = idx / L, j = idx - i * L;
     if (i <= j) G[pk(i, j, L)] = (i < l && j < l) ? a.G[(int64_t)i * l + j] : 0.0;
   }
-  for (int p = tid; p < L; p += kEigThreads) label[p] = p;
+  for (int p = tid; p < L; p += NT) label[p] = p;
+  if (tid == 0) {
+    // the word after (q,q) of the last diagonal block is read (and unused)
+    G[L * (L + 1) / 2] = G[L * (L + 1) / 2 + 1] = 0.0;
+    rot_cs[1][0] = rot_cs[1][P] = make_double2(0.0, 1.0);
+    rot_tf[1][0] = rot_tf[1][P] = make_double2(0.0, 0.0);
+  }
 
-  // Block items of this thread for both parities, decoded once: pairs of
-  // groups (gb <= ga) enumerated row by row of the packed upper triangle (gb
-  // outer, ga inner), so neighbouring lanes touch neighbouring LDS words.
-  // Per item: the packed offsets of the block's two b-rows at its first
-  // a-index (two 16-bit fields; the second a-index is the next word of the
-  // same row) and a meta word: rotation slots of both groups, whether each
-  // group holds two indices, whether the block is diagonal, whether the item
-  // exists.  For a diagonal block the fields are (p,p) and (q,q); (p,q) is
-  // the word after (p,p).
+  // Block items of this thread for both parities, decoded once.  Index
+  // groups: even parity g = {2g, 2g+1} (g < P); odd parity g = {2g-1, 2g}
+  // (0 < g < P) and the single groups {0}, {L-1} (g = 0, P).  An item is a
+  // pair of groups (gb <= ga), i.e. a block of G with b-rows and a-columns.
+  // Items are listed as: blocks of two size-2 groups (row by row of the
+  // packed upper triangle, so neighbouring lanes touch neighbouring LDS
+  // words), then blocks with a single group, then diagonal blocks, so that
+  // waves mostly take one code path.  Per item: the packed offsets of the
+  // block's two b-rows at its first a-index (16-bit fields; the second
+  // a-index is the next word of the row) and a meta word (groups ga, gb,
+  // flags).  A diagonal block stores (p,p) and (q,q); (p,q) follows (p,p).
+  // The tables live in registers, or (CPL = 8, the largest sizes) in LDS
+  // after G with a 16-bit meta (ga | gb << 8, 0xffff = none) whose flags are
+  // derived again when read.
   constexpr uint32_t kA2 = 1u << 16, kB2 = 1u << 17, kDiag = 1u << 18, kValid = 1u << 19;
-  uint32_t it_o[2][MAXIT], it_m[2][MAXIT];
+  constexpr bool kTabLds = CPL == 8;
+  uint32_t it_o[2][kTabLds ? 1 : MAXIT], it_m[2][kTabLds ? 1 : MAXIT];
+  uint32_t *tab_o = reinterpret_cast<uint32_t *>(G + L * (L + 1) / 2 + 2);
+  uint16_t *tab_m = reinterpret_cast<uint16_t *>(tab_o + 2 * MAXIT * NT);
 #pragma unroll
   for (int par = 0; par < 2; ++par) {
-    const int ng = par ? P + 1 : P;
-    const int nitems = ng * (ng + 1) / 2;
-    const int npairs = par ? P - 1 : P;
+    // full groups gf0..gf1 (size 2)
+    const int gf0 = par ? 1 : 0, gf1 = par ? P - 1 : P - 1;
+    const int nf = gf1 - gf0 + 1;
+    const int n_full = nf * (nf - 1) / 2;
+    const int n_part = par ? 2 * P - 1 : 0;
+    const int n_diag = nf;
 #pragma unroll
     for (int s_ = 0; s_ < MAXIT; ++s_) {
-      const int t = tid + s_ * kEigThreads;
+      int t = tid + s_ * NT;
       uint32_t o = 0, meta = 0;
-      if (t < nitems) {
-        int gb = 0, rem = t;
-        while (rem >= ng - gb) {
-          rem -= ng - gb;
-          ++gb;
+      int ga = -1, gb = -1;
+      bool diag = false;
+      if (t < n_full) {
+        int row = 0;
+        while (t >= nf - 1 - row) {
+          t -= nf - 1 - row;
+          ++row;
         }
-        const int ga = gb + rem;
+        gb = gf0 + row;
+        ga = gb + 1 + t;
+      } else if ((t -= n_full) < n_part) {
+        // odd parity only: (0, 1..P), then (1..P-1, P)
+        if (t < P) {
+          gb = 0;
+          ga = t + 1;
+        } else {
+          gb = t - P + 1;
+          ga = P;
+        }
+      } else if ((t -= n_part) < n_diag) {
+        ga = gb = gf0 + t;
+        diag = true;
+      }
+      if (ga >= 0) {
         int fa, na, fb, nb;
         group_of(par, ga, P, fa, na);
         group_of(par, gb, P, fb, nb);
-        int sa = slot_of(par, ga), sb = slot_of(par, gb);
-        sa = sa < 0 ? 0 : (sa >= npairs ? npairs - 1 : sa);
-        sb = sb < 0 ? 0 : (sb >= npairs ? npairs - 1 : sb);
-        if (ga == gb) {
-          if (na == 2) {
-            o = (uint32_t)pk(fa, fa, L) | ((uint32_t)pk(fa + 1, fa + 1, L) << 16);
-            meta = (uint32_t)sa | kDiag | kValid;
-          }
+        if (diag) {
+          o = (uint32_t)pk(fa, fa, L) | ((uint32_t)pk(fa + 1, fa + 1, L) << 16);
+          meta = (uint32_t)ga | ((uint32_t)gb << 8) | kDiag | kValid;
         } else {
           // rows fb and fb+1 of the packed triangle at column fa (a single
-          // b-index reuses row fb; the word after a single a-index is still
-          // inside the array and is loaded but never used or stored)
+          // b-index reads row fb twice; the word after a single a-index is
+          // still inside the array, is finite, and only meets a zero
+          // coefficient; neither is ever stored)
           const int i00 = pk(fb, fa, L);
           const int i01 = nb == 2 ? pk(fb + 1, fa, L) : i00;
           o = (uint32_t)i00 | ((uint32_t)i01 << 16);
-          meta = (uint32_t)sa | ((uint32_t)sb << 8) | (na == 2 ? kA2 : 0u) | (nb == 2 ? kB2 : 0u) | kValid;
+          meta = (uint32_t)ga | ((uint32_t)gb << 8) | (na == 2 ? kA2 : 0u) | (nb == 2 ? kB2 : 0u) | kValid;
         }
       }
-      it_o[par][s_] = o;
-      it_m[par][s_] = meta;
+      if constexpr (kTabLds) {
+        tab_o[(par * MAXIT + s_) * NT + tid] = o;
+        tab_m[(par * MAXIT + s_) * NT + tid] =
+            (meta & kValid) ? (uint16_t)(meta & 0xffff) : (uint16_t)0xffff;
+      } else {
+        it_o[par][s_] = o;
+        it_m[par][s_] = meta;
+      }
     }
   }
 
@@ -199,7 +237,7 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
   const int RPW = kWave / LPR;       // rows per wave
   const int sub = lane / LPR, cl = lane - sub * LPR;
   const bool active = sub < RPW;
-  const int row_stride = (kEigThreads / kWave) * RPW;
+  const int row_stride = (NT / kWave) * RPW;
   const int NR = (L + row_stride - 1) / row_stride;
   const int c0 = CPL * cl;
   double v[MAXNR][CPL];
@@ -212,45 +250,37 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
   if (tid == 0) s_sweeps = 0;
   __syncthreads();
 
-  // V <- V M for the column pairs of one parity, with that parity's
-  // published rotations; waves that hold no row skip.  M = [[s, c], [c, -s]]
-  // (rotation then swap; c = 1, s = 0 is the plain swap), M = I outside the
-  // pairs of the step.  Even steps pair (c0 + 2i, c0 + 2i + 1) inside the
-  // lane (slot c0/2 + i); odd steps pair (c0 + 2i + 1, c0 + 2i + 2) inside
-  // it (slot c0/2 + i) and the two edge columns with the neighbouring lanes
-  // (slots c0/2 - 1 and c0/2 + CPL/2 - 1).
-  auto v_update = [&](int vpar) __attribute__((always_inline)) {
+  // V <- V M for the index groups of one parity; waves that hold no row skip.
+  // Even steps: groups c0/2 + i = (c0 + 2i, c0 + 2i + 1) inside the lane.
+  // Odd steps: groups c0/2 + i + 1 = (c0 + 2i + 1, c0 + 2i + 2) inside the
+  // lane, and the edge groups c0/2 (this lane holds the second member) and
+  // c0/2 + CPL/2 (this lane holds the first member) shared with the
+  // neighbouring lanes.  The first lane of a row holds the single group {0}
+  // alone, which keeps its value.
+  auto v_update = [&](auto vpar_c) __attribute__((always_inline)) {
+    constexpr int VPAR = decltype(vpar_c)::value;
     if (wave * RPW >= L) return;
-    const int npairs = vpar ? P - 1 : P;
-    const double2 *rcs = rot_cs[vpar];
-    const bool first = cl == 0, last = cl == LPR - 1;
-    if (!vpar) {
+    const double2 *rcs = rot_cs[VPAR];
+    if constexpr (VPAR == 0) {
       double2 cs[CPL / 2];
 #pragma unroll
-      for (int i = 0; i < CPL / 2; ++i) {
-        const int sl = c0 / 2 + i;
-        cs[i] = rcs[sl < npairs ? sl : npairs - 1];
-        if (sl >= npairs) cs[i] = make_double2(0.0, 1.0);  // only on idle lanes
-      }
+      for (int i = 0; i < CPL / 2; ++i) cs[i] = rcs[c0 / 2 + i];
 #pragma unroll
       for (int it = 0; it < MAXNR; ++it) {
         if (it < NR) {
 #pragma unroll
           for (int i = 0; i < CPL / 2; ++i) {
             const double x = v[it][2 * i], y = v[it][2 * i + 1];
-            v[it][2 * i] = x * cs[i].y + y * cs[i].x;
-            v[it][2 * i + 1] = x * cs[i].x - y * cs[i].y;
+            v[it][2 * i] = fma(x, cs[i].y, y * cs[i].x);
+            v[it][2 * i + 1] = fma(x, cs[i].x, -(y * cs[i].y));
           }
         }
       }
     } else {
-      double2 cs[CPL / 2 + 1];  // [0]: left edge pair, [1..]: inner pairs, [CPL/2]: right edge
+      double2 cs[CPL / 2 + 1];  // [0]: left edge group, [1..]: inner groups, [CPL/2]: right edge
 #pragma unroll
-      for (int i = 0; i <= CPL / 2; ++i) {
-        const int sl = c0 / 2 - 1 + i;
-        const int slc = sl < 0 ? 0 : (sl >= npairs ? npairs - 1 : sl);
-        cs[i] = rcs[slc];
-      }
+      for (int i = 0; i <= CPL / 2; ++i) cs[i] = rcs[c0 / 2 + i];
+      const bool first = cl == 0;
 #pragma unroll
       for (int it = 0; it < MAXNR; ++it) {
         if (it < NR) {
@@ -260,12 +290,14 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
           for (int i = 0; i < CPL / 2 - 1; ++i) {
             const double2 r = cs[i + 1];
             const double x = v[it][2 * i + 1], y = v[it][2 * i + 2];
-            v[it][2 * i + 1] = x * r.y + y * r.x;
-            v[it][2 * i + 2] = x * r.x - y * r.y;
+            v[it][2 * i + 1] = fma(x, r.y, y * r.x);
+            v[it][2 * i + 2] = fma(x, r.x, -(y * r.y));
           }
           const double x0 = v[it][0], xl = v[it][CPL - 1];
-          v[it][0] = first ? x0 : prv * cs[0].x - x0 * cs[0].y;
-          v[it][CPL - 1] = last ? xl : xl * cs[CPL / 2].y + nxt * cs[CPL / 2].x;
+          const double y0 = fma(prv, cs[0].x, -(x0 * cs[0].y));
+          v[it][0] = first ? x0 : y0;
+          // the last lane's right group is the single {L-1}: (c, s) = (0, 1)
+          v[it][CPL - 1] = fma(xl, cs[CPL / 2].y, nxt * cs[CPL / 2].x);
         }
       }
     }
@@ -275,7 +307,7 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
     // convergence test before the sweep: any entry above the skip threshold?
     if (tid == 0) s_flag = 0;
     __syncthreads();
-    for (int idx = tid; idx < L * L; idx += kEigThreads) {
+    for (int idx = tid; idx < L * L; idx += NT) {
       const int i = idx / L, j = idx - i * L;
       if (i < j) {
         const double apq = G[pk(i, j, L)];
@@ -290,14 +322,14 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
     //      two labels), while every thread applies the previous step's
     //      rotations to its rows of V (rotations are double-buffered by
     //      parity; L is even, so parity = step & 1 in every sweep);
-    //   2. the 2x2 blocks of G are updated, B <- Ma^T B Mb, all loads of a
-    //      thread issued before its first store.
-    for (int step = 0; step < L; ++step) {
-      const int par = step & 1;
+    //   2. the blocks of G are updated, B <- Ma^T B Mb, all loads of a batch
+    //      issued before its first store.
+    auto do_step = [&](auto par_c, int step) __attribute__((always_inline)) {
+      constexpr int par = decltype(par_c)::value;
       const int npairs = par ? P - 1 : P;
-      long long c0 = 0, w0 = 0, ca_ = 0, cv = 0;
+      long long c0_ = 0, w0 = 0, ca_ = 0, cv = 0;
       if (a.prof && tid == 0) {
-        c0 = clock64();
+        c0_ = clock64();
         w0 = wall_clock64();
       }
       if (tid < npairs) {
@@ -314,13 +346,14 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
           s = t * c;
           rot = 1.0;
         }
-        rot_cs[par][tid] = make_double2(c, s);
-        rot_tf[par][tid] = make_double2(t, rot);
+        const int grp = par ? tid + 1 : tid;
+        rot_cs[par][grp] = make_double2(c, s);
+        rot_tf[par][grp] = make_double2(t, rot);
         label[p] = lq;
         label[q] = lp;
       }
       if (a.prof && tid == 0) ca_ = clock64();
-      if (step > 0) v_update(par ^ 1);
+      if (step > 0) v_update(IC<par ^ 1>{});
       if (a.prof && tid == 0) cv = clock64();
       __syncthreads();
       long long c1 = 0;
@@ -332,43 +365,56 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
         constexpr int PAR = decltype(par_c)::value;
         const double2 *rcs = rot_cs[PAR];
         const double2 *rtf = rot_tf[PAR];
-        // items in batches of BATCH (register pressure of the large sizes)
+        auto item = [&](int s_, uint32_t &o, uint32_t &meta) __attribute__((always_inline)) {
+          if constexpr (kTabLds) {
+            o = tab_o[(PAR * MAXIT + s_) * NT + tid];
+            const uint32_t m16 = tab_m[(PAR * MAXIT + s_) * NT + tid];
+            const uint32_t ga = m16 & 0xff, gb = m16 >> 8;
+            const bool a1 = PAR == 1 && (ga == 0 || ga == (uint32_t)P);
+            const bool b1 = PAR == 1 && (gb == 0 || gb == (uint32_t)P);
+            meta = m16 == 0xffff ? 0u
+                                 : (m16 | kValid | (ga == gb ? kDiag : 0u) | (a1 ? 0u : kA2) | (b1 ? 0u : kB2));
+          } else {
+            o = it_o[PAR][s_];
+            meta = it_m[PAR][s_];
+          }
+        };
 #pragma unroll
         for (int b0 = 0; b0 < MAXIT; b0 += BATCH) {
+          uint32_t ob[BATCH], mb[BATCH];
+#pragma unroll
+          for (int s_ = b0; s_ < b0 + BATCH; ++s_) item(s_, ob[s_ - b0], mb[s_ - b0]);
           double g[BATCH][4];
           double2 pa[BATCH], pb[BATCH];
-          // loads: the two words of each b-row are adjacent, so each row is
-          // one paired 8-byte load and a wave's lanes cover contiguous LDS
+          // loads: the two words of each b-row are adjacent (paired loads)
 #pragma unroll
           for (int s_ = b0; s_ < b0 + BATCH; ++s_) {
-            const uint32_t meta = it_m[PAR][s_], o = it_o[PAR][s_];
-            g[s_ - b0][0] = g[s_ - b0][1] = g[s_ - b0][2] = g[s_ - b0][3] = 0.0;
-            pa[s_ - b0] = pb[s_ - b0] = make_double2(0.0, 0.0);
+            const int j = s_ - b0;
+            const uint32_t meta = mb[j], o = ob[j];
+            g[j][0] = g[j][1] = g[j][2] = g[j][3] = 0.0;
+            pa[j] = pb[j] = make_double2(0.0, 0.0);
             if (meta & kValid) {
               const int r0 = o & 0xffff, r1 = o >> 16;
-              const int sa = meta & 0xff, sb = (meta >> 8) & 0xff;
-              g[s_ - b0][0] = G[r0];
-              g[s_ - b0][1] = G[r0 + 1];
-              g[s_ - b0][2] = G[r1];
-              if (meta & kDiag) {
-                pa[s_ - b0] = rtf[sa];
-              } else {
-                g[s_ - b0][3] = G[r1 + 1];
-                pa[s_ - b0] = rcs[sa];
-                pb[s_ - b0] = rcs[sb];
-              }
+              const int ga = meta & 0xff, gb = (meta >> 8) & 0xff;
+              g[j][0] = G[r0];
+              g[j][1] = G[r0 + 1];
+              g[j][2] = G[r1];
+              g[j][3] = G[r1 + 1];
+              pa[j] = (meta & kDiag) ? rtf[ga] : rcs[ga];
+              pb[j] = rcs[gb];
             }
           }
 #pragma unroll
           for (int s_ = b0; s_ < b0 + BATCH; ++s_) {
-            const uint32_t meta = it_m[PAR][s_], o = it_o[PAR][s_];
+            const int j = s_ - b0;
+            const uint32_t meta = mb[j], o = ob[j];
             if (!(meta & kValid)) continue;
             const int r0 = o & 0xffff, r1 = o >> 16;
             if (meta & kDiag) {
               // (p,p), (p,q), (q,q) of a rotated-and-swapped pair: the diagonal
               // becomes (a_qq + t a_pq, a_pp - t a_pq) and the coupling vanishes
-              const double app = g[s_ - b0][0], apq = g[s_ - b0][1], aqq = g[s_ - b0][2];
-              const double2 tf = pa[s_ - b0];
+              const double app = g[j][0], apq = g[j][1], aqq = g[j][2];
+              const double2 tf = pa[j];
               if (tf.y != 0.0) {
                 G[r0] = fma(tf.x, apq, aqq);
                 G[r0 + 1] = 0.0;
@@ -379,65 +425,53 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
               }
               continue;
             }
-            // off-diagonal block B[a][b] at row fb + b, column fa + a; a
-            // single-index group has M = [1]
-            const bool a2 = meta & kA2, b2 = meta & kB2;
-            const double2 csa = pa[s_ - b0], csb = pb[s_ - b0];
-            const double ma00 = a2 ? csa.y : 1.0, ma01 = a2 ? csa.x : 0.0;
-            const double ma10 = a2 ? csa.x : 0.0, ma11 = a2 ? -csa.y : 1.0;
-            const double mb00 = b2 ? csb.y : 1.0, mb01 = b2 ? csb.x : 0.0;
-            const double mb10 = b2 ? csb.x : 0.0, mb11 = b2 ? -csb.y : 1.0;
-            const double g00 = g[s_ - b0][0];
-            const double b10 = a2 ? g[s_ - b0][1] : 0.0;
-            const double b01 = b2 ? g[s_ - b0][2] : 0.0;
-            const double b11 = (a2 && b2) ? g[s_ - b0][3] : 0.0;
-            // T = B Mb ; B' = Ma^T T
-            const double t00 = g00 * mb00 + b01 * mb10, t01 = g00 * mb01 + b01 * mb11;
-            const double t10 = b10 * mb00 + b11 * mb10, t11 = b10 * mb01 + b11 * mb11;
-            const double n00 = ma00 * t00 + ma10 * t10, n10 = ma01 * t00 + ma11 * t10;
-            const double n01 = ma00 * t01 + ma10 * t11, n11 = ma01 * t01 + ma11 * t11;
-            if (a2) {
+            // off-diagonal block B[a][b] at row fb + b, column fa + a:
+            // T = B Mb, B' = Ma^T T with M = [[s, c], [c, -s]]
+            const double ca = pa[j].x, sa = pa[j].y, cb = pb[j].x, sb = pb[j].y;
+            const double g00 = g[j][0], g10 = g[j][1], g01 = g[j][2], g11 = g[j][3];
+            const double t00 = fma(g00, sb, g01 * cb), t01 = fma(g00, cb, -(g01 * sb));
+            const double t10 = fma(g10, sb, g11 * cb), t11 = fma(g10, cb, -(g11 * sb));
+            const double n00 = fma(sa, t00, ca * t10), n10 = fma(ca, t00, -(sa * t10));
+            const double n01 = fma(sa, t01, ca * t11), n11 = fma(ca, t01, -(sa * t11));
+            if ((meta & (kA2 | kB2)) == (kA2 | kB2)) {
               G[r0] = n00;
               G[r0 + 1] = n10;
+              G[r1] = n01;
+              G[r1 + 1] = n11;
             } else {
               G[r0] = n00;
-            }
-            if (b2) {
-              if (a2) {
-                G[r1] = n01;
-                G[r1 + 1] = n11;
-              } else {
-                G[r1] = n01;
-              }
+              if (meta & kA2) G[r0 + 1] = n10;
+              if (meta & kB2) G[r1] = n01;
             }
           }
         }
       };
-      if (par)
-        g_update(IC<1>{});
-      else
-        g_update(IC<0>{});
+      g_update(IC<par>{});
       __syncthreads();
       if (a.prof && tid == 0) {
         // step profile (thread 0): cycles of phase 1 and of phase 2 (each up
         // to its barrier), wall-clock ticks (100 MHz), steps, cycles of this
         // thread's rotation work and of its V update in phase 1
         const long long c2 = clock64();
-        a.prof[0] += c1 - c0;
+        a.prof[0] += c1 - c0_;
         a.prof[1] += c2 - c1;
         a.prof[2] += wall_clock64() - w0;
         a.prof[3] += 1;
-        a.prof[4] += ca_ - c0;
+        a.prof[4] += ca_ - c0_;
         a.prof[5] += cv - ca_;
       }
+    };
+    for (int step = 0; step < L; step += 2) {
+      do_step(IC<0>{}, step);
+      do_step(IC<1>{}, step + 1);
     }
     // the sweep's last step is odd: its V update is still pending
-    v_update(1);
+    v_update(IC<1>{});
   }
 
   // ---------------------------------------------------------------- tail
   // rank the real positions by eigenvalue, descending; ties by label, descending
-  for (int p = tid; p < L; p += kEigThreads) {
+  for (int p = tid; p < L; p += NT) {
     int rk = -1;
     if (label[p] < l) {
       const double lp = G[pk(p, p, L)];
@@ -454,7 +488,7 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
   }
   __syncthreads();
   const double tau = Ssh[0] * sqrt((double)l * 2.220446049250313e-16);
-  for (int i = tid; i < l; i += kEigThreads) a.S[i] = Ssh[i];
+  for (int i = tid; i < l; i += NT) a.S[i] = Ssh[i];
 #pragma unroll
   for (int it = 0; it < MAXNR; ++it) {
     const int row = wave * RPW + sub + it * row_stride;
@@ -499,10 +533,10 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
   }
   __syncthreads();
   if (j - 1 < a.trace_cap) {
-    for (int i = tid; i < l; i += kEigThreads) a.trace_s[(int64_t)(j - 1) * l + i] = Ssh[i];
+    for (int i = tid; i < l; i += NT) a.trace_s[(int64_t)(j - 1) * l + i] = Ssh[i];
   }
   if (!s_stop) {
-    for (int i = tid; i < l; i += kEigThreads) a.Sprev[i] = Ssh[i];
+    for (int i = tid; i < l; i += NT) a.Sprev[i] = Ssh[i];
   }
   if (tid == 0) {
     const double ratio = s_ratio;
@@ -543,39 +577,45 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs a) {
 hipError_t launch_eig(const EigArgs &a, hipStream_t st) {
   if (a.l < 1 || a.l > kMaxLP) return hipErrorInvalidValue;
   // the layout rules of the kernel, mirrored: CPL columns of V per lane,
-  // L = l padded to a multiple of CPL
+  // L = l padded to a multiple of CPL, NT threads
   const int L4 = (a.l + 3) & ~3;
   const int CPL = L4 > 128 ? 8 : 4;
+  const int NT = CPL == 8 ? kEigThreadsL : kEigThreads;
   const int L = CPL == 8 ? (a.l + 7) & ~7 : L4;
   const int P = L / 2;
   const int LPR = L / CPL, RPW = kWave / LPR;
-  const int NR = (L + 16 * RPW - 1) / (16 * RPW);
-  const int IT = ((P + 1) * (P + 2) / 2 + kEigThreads - 1) / kEigThreads;  // odd parity has more
-  const size_t shm = sizeof(double) * (size_t)(L * (L + 1) / 2);
+  const int NR = (L + (NT / kWave) * RPW - 1) / ((NT / kWave) * RPW);
+  const int IT = ((P + 1) * (P + 2) / 2 + NT - 1) / NT;  // odd parity has more
+  size_t shm = sizeof(double) * (size_t)(L * (L + 1) / 2 + 2);
+  if (CPL == 8) shm += (size_t)2 * kMaxItems * NT * (sizeof(uint32_t) + sizeof(uint16_t));
   void (*fn)(EigArgs) = nullptr;
   if (CPL == 4 && NR <= 1 && IT <= 1)
-    fn = k_eig<1, 1, 1, 4>;
+    fn = k_eig<1, 1, 1, 4, kEigThreads>;
   else if (CPL == 4 && NR <= 2 && IT <= 2)
-    fn = k_eig<2, 2, 2, 4>;
+    fn = k_eig<2, 2, 2, 4, kEigThreads>;
   else if (CPL == 4 && NR <= 4 && IT <= 2)
-    fn = k_eig<4, 2, 2, 4>;
+    fn = k_eig<4, 2, 2, 4, kEigThreads>;
   else if (CPL == 4 && NR <= 4 && IT <= 3)
-    fn = k_eig<4, 3, 1, 4>;
-  else if (CPL == 8 && NR <= 4 && IT <= kMaxItems)
-    fn = k_eig<4, kMaxItems, 1, 8>;
+    fn = k_eig<4, 3, 1, 4, kEigThreads>;
+  else if (CPL == 8 && NR <= 7 && IT <= kMaxItems)
+    fn = k_eig<7, kMaxItems, 1, 8, kEigThreadsL>;
   else
     return hipErrorInvalidValue;
   static bool attr = false;
   if (!attr) {
-    hipFuncSetAttribute((const void *)k_eig<1, 1, 1, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
-    hipFuncSetAttribute((const void *)k_eig<2, 2, 2, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
-    hipFuncSetAttribute((const void *)k_eig<4, 2, 2, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
-    hipFuncSetAttribute((const void *)k_eig<4, 3, 1, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
-    hipFuncSetAttribute((const void *)k_eig<4, kMaxItems, 1, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipFuncSetAttribute((const void *)k_eig<1, 1, 1, 4, kEigThreads>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         128 * 1024);
+    hipFuncSetAttribute((const void *)k_eig<2, 2, 2, 4, kEigThreads>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        128 * 1024);
+    hipFuncSetAttribute((const void *)k_eig<4, 2, 2, 4, kEigThreads>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        128 * 1024);
+    hipFuncSetAttribute((const void *)k_eig<4, 3, 1, 4, kEigThreads>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        128 * 1024);
+    hipFuncSetAttribute((const void *)k_eig<7, kMaxItems, 1, 8, kEigThreadsL>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 152 * 1024);
     attr = true;
   }
-  hipLaunchKernelGGL(fn, dim3(1), dim3(kEigThreads), shm, st, a);
+  hipLaunchKernelGGL(fn, dim3(1), dim3(NT), shm, st, a);
   return hipGetLastError();
 }
 
