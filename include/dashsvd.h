@@ -148,6 +148,8 @@ typedef struct {
   int32_t kt_count[8];     /* launches counted per group (passes after the stop excluded) */
   int32_t eig_calls;       /* eigSVD eigenproblems solved in the run */
   int32_t eig_sweeps;      /* Jacobi sweeps summed over them */
+  int32_t sweeps_per_call[DASHSVD_MAX_TRACE + 2]; /* sweeps of eigSVD call c: the sketch (c = 0),
+                                                     the passes, then the final step */
 } dashsvd_info;
 
 typedef struct dashsvd_handle dashsvd_handle;

@@ -214,6 +214,7 @@ struct EigArgs {
   const double *sched;  // device multipliers (SCHEDULE / LEARNED), may be null
   int sched_len;
   long long *prof;      // optional step profile (6 counters), null in the solver
+  int32_t *trace_sweeps;  // sweeps of call c (c = state->eig_calls before this call), [cap + 2]
 };
 hipError_t launch_eig(const EigArgs &a, hipStream_t st);
 

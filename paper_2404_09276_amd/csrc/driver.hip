@@ -213,6 +213,7 @@ struct RunBufs {
   double *gpart = nullptr, *G = nullptr, *W = nullptr, *Vs = nullptr, *S = nullptr, *Sprev = nullptr;
   SolverState *state = nullptr;
   double *tr_alpha = nullptr, *tr_ratio = nullptr, *tr_s = nullptr;
+  int32_t *tr_sweeps = nullptr;
   double *sched = nullptr;
   void *Uo = nullptr, *Vo = nullptr;
   double *So = nullptr;
@@ -391,6 +392,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   b.tr_alpha = (double *)ar.take(8 * (size_t)cap);
   b.tr_ratio = (double *)ar.take(8 * (size_t)cap);
   b.tr_s = (double *)ar.take(8 * (size_t)cap * l);
+  b.tr_sweeps = (int32_t *)ar.take(4 * (size_t)(cap + 2));
   b.sched = (double *)ar.take(8 * (size_t)(pmax + 2));
   b.Uo = ar.take(dsz(cdt) * (size_t)Mm * k);
   b.Vo = ar.take(dsz(cdt) * (size_t)Mn * k);
@@ -419,6 +421,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   HIPCHK(hipMemsetAsync(b.Sprev, 0, 8 * (size_t)l, st));
   HIPCHK(hipMemsetAsync(b.tr_alpha, 0, 8 * (size_t)cap, st));
   HIPCHK(hipMemsetAsync(b.tr_ratio, 0, 8 * (size_t)cap, st));
+  HIPCHK(hipMemsetAsync(b.tr_sweeps, 0, 4 * (size_t)(cap + 2), st));
   const int64_t *rpA = A->on_device ? A->row_ptr : rp_in;
   const int32_t *colA = A->on_device ? A->col_idx : col_in;
   const void *val_src = A->on_device ? A->values : val_raw;
@@ -525,6 +528,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     ea.trace_ratio = b.tr_ratio;
     ea.trace_s = b.tr_s;
     ea.trace_cap = cap;
+    ea.trace_sweeps = b.tr_sweeps;
     ea.sched = h->sched.empty() ? nullptr : b.sched;
     ea.sched_len = (int)h->sched.size();
     return ea;
@@ -688,6 +692,11 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   if (ntr > 0) {
     HIPCHK(hipMemcpyAsync(inf.alpha_used, b.tr_alpha, 8 * (size_t)ntr, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(inf.ratio, b.tr_ratio, 8 * (size_t)ntr, hipMemcpyDeviceToHost, st));
+  }
+  {
+    // entries past the calls that ran are zero (cleared at setup)
+    const int nsw = cap + 2 < DASHSVD_MAX_TRACE + 2 ? cap + 2 : DASHSVD_MAX_TRACE + 2;
+    HIPCHK(hipMemcpyAsync(inf.sweeps_per_call, b.tr_sweeps, 4 * (size_t)nsw, hipMemcpyDeviceToHost, st));
   }
   HIPCHK(hipStreamSynchronize(st));
   const double t_end = now_ms();

@@ -80,16 +80,16 @@ __device__ __forceinline__ double frsqrt(double x) {
 
 // Whole-wave shifts by one lane through DPP (a VALU modifier: no LDS
 // traffic).  wave_shr1: lane i receives lane i-1; wave_shl1: lane i receives
-// lane i+1; the edge lane keeps its own value, which callers never use.
+// lane i+1; the edge lane receives zero, which callers never use.
 __device__ __forceinline__ double dpp_move(double x, int ctrl_sel) {
   const long long b = __double_as_longlong(x);
   int lo = (int)(b & 0xffffffffll), hi = (int)(b >> 32);
   if (ctrl_sel) {
-    lo = __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false);
-    hi = __builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false);
+    lo = __builtin_amdgcn_mov_dpp(lo, 0x138, 0xf, 0xf, true);
+    hi = __builtin_amdgcn_mov_dpp(hi, 0x138, 0xf, 0xf, true);
   } else {
-    lo = __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false);
-    hi = __builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false);
+    lo = __builtin_amdgcn_mov_dpp(lo, 0x130, 0xf, 0xf, true);
+    hi = __builtin_amdgcn_mov_dpp(hi, 0x130, 0xf, 0xf, true);
   }
   return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
 }
@@ -386,23 +386,21 @@ __global__ __launch_bounds__(NT) void k_eig(EigArgs a) {
           for (int s_ = b0; s_ < b0 + BATCH; ++s_) item(s_, ob[s_ - b0], mb[s_ - b0]);
           double g[BATCH][4];
           double2 pa[BATCH], pb[BATCH];
-          // loads: the two words of each b-row are adjacent (paired loads)
+          // loads: the two words of each b-row are adjacent (paired loads).
+          // An absent item (meta 0) reads the first words of G and of the
+          // rotation table and is then skipped, so no load needs a branch.
 #pragma unroll
           for (int s_ = b0; s_ < b0 + BATCH; ++s_) {
             const int j = s_ - b0;
             const uint32_t meta = mb[j], o = ob[j];
-            g[j][0] = g[j][1] = g[j][2] = g[j][3] = 0.0;
-            pa[j] = pb[j] = make_double2(0.0, 0.0);
-            if (meta & kValid) {
-              const int r0 = o & 0xffff, r1 = o >> 16;
-              const int ga = meta & 0xff, gb = (meta >> 8) & 0xff;
-              g[j][0] = G[r0];
-              g[j][1] = G[r0 + 1];
-              g[j][2] = G[r1];
-              g[j][3] = G[r1 + 1];
-              pa[j] = (meta & kDiag) ? rtf[ga] : rcs[ga];
-              pb[j] = rcs[gb];
-            }
+            const int r0 = o & 0xffff, r1 = o >> 16;
+            const int ga = meta & 0xff, gb = (meta >> 8) & 0xff;
+            g[j][0] = G[r0];
+            g[j][1] = G[r0 + 1];
+            g[j][2] = G[r1];
+            g[j][3] = G[r1 + 1];
+            pa[j] = ((meta & kDiag) ? rtf : rcs)[ga];
+            pb[j] = rcs[gb];
           }
 #pragma unroll
           for (int s_ = b0; s_ < b0 + BATCH; ++s_) {
@@ -508,6 +506,7 @@ __global__ __launch_bounds__(NT) void k_eig(EigArgs a) {
   if (a.sweeps && tid == 0) *a.sweeps = s_sweeps;
   if (!state) return;
   if (tid == 0) {
+    if (a.trace_sweeps && state->eig_calls < a.trace_cap + 2) a.trace_sweeps[state->eig_calls] = s_sweeps;
     state->eig_calls += 1;
     state->eig_sweeps += s_sweeps;
   }

@@ -55,7 +55,8 @@ class _Info(C.Structure):
                 ("time_setup_ms", C.c_double), ("time_loop_ms", C.c_double),
                 ("time_final_ms", C.c_double), ("long_chunks_A", C.c_int64),
                 ("long_chunks_AT", C.c_int64), ("kt_ms", C.c_double * 8), ("kt_count", C.c_int32 * 8),
-                ("eig_calls", C.c_int32), ("eig_sweeps", C.c_int32)]
+                ("eig_calls", C.c_int32), ("eig_sweeps", C.c_int32),
+                ("sweeps_per_call", C.c_int32 * (MAX_TRACE + 2))]
 
 KT_NAMES = ["spmm", "spmm_t", "gram", "eig", "rescale", "transpose", "sketch", "final"]
 
@@ -187,6 +188,7 @@ class Info:
     kt_count: dict
     eig_calls: int
     eig_sweeps: int
+    sweeps_per_call: np.ndarray
 
 
 class DashSVD:
@@ -277,7 +279,8 @@ class DashSVD:
                     np.array(raw.ratio[:min(npass, MAX_TRACE)]), raw.time_total_ms,
                     raw.time_setup_ms, raw.time_loop_ms, raw.time_final_ms, raw.long_chunks_A,
                     raw.long_chunks_AT, dict(zip(KT_NAMES, list(raw.kt_ms))),
-                    dict(zip(KT_NAMES, list(raw.kt_count))), raw.eig_calls, raw.eig_sweeps)
+                    dict(zip(KT_NAMES, list(raw.kt_count))), raw.eig_calls, raw.eig_sweeps,
+                    np.array(raw.sweeps_per_call[:min(raw.eig_calls, MAX_TRACE + 2)]))
 
     def trace(self) -> np.ndarray:
         """Per-pass S (passes x l) of the last run (dashsvd_get_trace)."""
