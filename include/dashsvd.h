@@ -150,6 +150,9 @@ typedef struct {
   int32_t eig_sweeps;      /* Jacobi sweeps summed over them */
   int32_t sweeps_per_call[DASHSVD_MAX_TRACE + 2]; /* sweeps of eigSVD call c: the sketch (c = 0),
                                                      the passes, then the final step */
+  int32_t promoted;        /* BF16 panels: 1 if the stagnation guard switched the remaining
+                              passes to FP32 panels (the PVE ratio stayed above tol and above
+                              0.8 x its previous value for two passes) */
 } dashsvd_info;
 
 typedef struct dashsvd_handle dashsvd_handle;
@@ -180,6 +183,19 @@ dashsvd_status dashsvd_get_USV(dashsvd_handle *h, void *U, int64_t ldu, double *
                                int64_t ldv, int32_t dtype, int32_t on_device);
 
 dashsvd_status dashsvd_get_info(dashsvd_handle *h, dashsvd_info *out);
+
+/* Accuracy of the last run (Sec. 4 metrics), computed on the device:
+ *   eps_pve   = max_{i<k} |sigma_i^2 - ||A^T u_i||^2| / sigma_{k+1}^2,
+ *   eps_sigma = max_{i<k} |sigma_i - S_i| / sigma_i,
+ * with u_i the computed left singular vectors, S the computed values and
+ * sigma_ref (host, n_ref >= k + 1 doubles, descending, sigma_ref[k] > 0)
+ * reference singular values of A.  A must be the matrix of the last run
+ * (same sizes; device arrays still valid).  A^T U is formed with the
+ * library's SpMM in the run's compute type and its squared column norms in
+ * FP64.  Either output pointer may be NULL.  Synchronises the stream; the
+ * panels of the last run are overwritten, its results (U, S, V) are not. */
+dashsvd_status dashsvd_evaluate(dashsvd_handle *h, const dashsvd_csr *A, const double *sigma_ref,
+                                int32_t n_ref, double *eps_pve, double *eps_sigma);
 
 /* Per-pass S (the l singular values of each pass's block C, descending):
  * writes min(passes, max_passes) rows of l doubles to host memory. */
@@ -243,9 +259,10 @@ dashsvd_status dashsvd_k_gram(int64_t r, int32_t l, const void *C, int64_t ldc, 
  * (optional, device int) receives the sweep count. */
 dashsvd_status dashsvd_k_eig(int32_t l, const double *G, double *S, double *Vs, double *W,
                              int32_t *sweeps, void *stream);
-/* dashsvd_k_eig with a step profile: prof (device, 4 int64) accumulates the
- * cycles of the rotation phase, the cycles of the update phase, the 100 MHz
- * wall-clock ticks and the number of Jacobi steps. */
+/* dashsvd_k_eig with a step profile: prof (device, 6 int64) accumulates, as
+ * seen by thread 0, the cycles of the rotation phase and of the update
+ * phase, the 100 MHz wall-clock ticks, the number of Jacobi steps, and the
+ * cycles of thread 0's own rotation work and V update. */
 dashsvd_status dashsvd_k_eig_prof(int32_t l, const double *G, double *S, double *Vs, double *W,
                                   int32_t *sweeps, long long *prof, void *stream);
 

@@ -145,7 +145,8 @@ struct SolverState {
   int32_t eig_calls;     // eigSVD calls that ran, and their Jacobi sweeps
   int32_t eig_sweeps;
   int32_t pass_skip;     // snapshot of done at the start of the current pass
-  int32_t pad[2];
+  int32_t stagnant;      // consecutive passes with ratio > tol and > 0.8 x the previous ratio
+  int32_t promote;       // set once stagnant reaches 2 (BF16 panels: switch to FP32)
 };
 
 // ------------------------------------------------------------------ launchers
@@ -213,6 +214,7 @@ struct EigArgs {
   int trace_cap;
   const double *sched;  // device multipliers (SCHEDULE / LEARNED), may be null
   int sched_len;
+  int stagnation_guard;  // track stagnant / promote (BF16 panel form)
   long long *prof;      // optional step profile (6 counters), null in the solver
   int32_t *trace_sweeps;  // sweeps of call c (c = state->eig_calls before this call), [cap + 2]
 };

@@ -89,6 +89,21 @@ struct dashsvd_handle {
   // second stream for the eigensolver, overlapped with the next SpMM
   hipStream_t st2 = nullptr;
   hipEvent_t ev_gram = nullptr, ev_eig = nullptr;
+  // what dashsvd_evaluate needs of the last run: the operator M (A, or A^T
+  // when m < n) and its transpose with their SpMM plans, and free panels
+  struct EvalCtx {
+    bool ok = false;
+    int64_t nnz = 0, Mm = 0, Mn = 0;
+    bool wide = false;
+    int vdt = 0, cdt = 0, ld = 0;
+    int32_t T = 0;
+    const int64_t *rp[2] = {nullptr, nullptr};
+    const int32_t *col[2] = {nullptr, nullptr};
+    const void *val[2] = {nullptr, nullptr};
+    Plan plan[2];
+    void *panel_m = nullptr, *panel_n = nullptr;  // Mm x ld and Mn x ld, cdt
+    double *gpart = nullptr, *G = nullptr;
+  } ev_ctx;
 };
 
 namespace {
@@ -210,6 +225,7 @@ struct RunBufs {
   void *B = nullptr;   // M_m x ld, C type (final block)
   void *Z = nullptr;   // M_m x ld, C type: M C of the current block
   void *X = nullptr;   // M_n x ld, C type: M^T M C of the current block (overlapped order)
+  void *Q32 = nullptr, *Y32 = nullptr;  // FP32 panels after a BF16 promotion
   double *gpart = nullptr, *G = nullptr, *W = nullptr, *Vs = nullptr, *S = nullptr, *Sprev = nullptr;
   SolverState *state = nullptr;
   double *tr_alpha = nullptr, *tr_ratio = nullptr, *tr_s = nullptr;
@@ -381,6 +397,9 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   b.B = pdt == cdt ? b.Y : ar.take(dsz(cdt) * (size_t)Mm * ld);
   b.Z = ar.take(dsz(cdt) * (size_t)Mm * ld);
   b.X = pdt == cdt ? ar.take(dsz(cdt) * (size_t)Mn * ld) : nullptr;
+  // BF16 panels: FP32 panels for the passes after a promotion
+  b.Q32 = pdt != cdt ? ar.take(dsz(cdt) * (size_t)Mn * ld) : nullptr;
+  b.Y32 = pdt != cdt ? ar.take(dsz(cdt) * (size_t)Mm * ld) : nullptr;
   const int nb_n = gram_blocks(Mn, l), nb_m = gram_blocks(Mm, l);
   b.gpart = (double *)ar.take(8 * gram_partial_elems(nb_n > nb_m ? nb_n : nb_m, l));
   b.G = (double *)ar.take(8 * (size_t)l * l);
@@ -547,6 +566,9 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     return e;
   };
   int last_pass = 0;  // passes whose eigSVD ran (the final block's C, Z, W)
+  int promoted = 0;   // BF16 panels switched to FP32 by the stagnation guard
+  void *Qfin = b.Q, *Yfin = b.Y;  // final Q and M Q (plain order)
+  int pfin = pdt;
   if (pdt == cdt) {
     // Overlapped order (FP32 and FP64 forms).  With C the current block and
     // W its eigSVD weights (Q = C W), the next pass is
@@ -610,24 +632,31 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     HIPCHK(hipStreamSynchronize(st));
   } else {
     // Plain order (BF16 panels): C = M^T Y - alpha Q from the BF16 panels,
-    // G = C^T C, eig, Q = C W, Y = M Q.
+    // G = C^T C, eig, Q = C W, Y = M Q.  Stagnation guard: once the PVE
+    // ratio has gained less than 20 % per pass for two passes while above
+    // tol, the BF16 rounding of the panels limits the attainable accuracy, and the
+    // remaining passes run with FP32 panels (Q = C W of the last block,
+    // formed again in FP32, and Y = M Q).
+    void *Qc = b.Q, *Yc = b.Y;
+    int pcur = pdt;
     auto block_step = [&](int mode, int pass, const int32_t *gate) -> hipError_t {
       tmark_begin(h, DASHSVD_KT_GRAM, pass);
       hipError_t e = launch_gram(Mn, l, b.C, ld, cdt, b.gpart, nb_n, b.G, gate, st, (int32_t *)pass_skip);
       tmark_end(h);
       if (e != hipSuccess) return e;
       EigArgs ea = make_eig(mode);
+      ea.stagnation_guard = pcur == DASHSVD_BF16;
       const int32_t *skip = gate ? pass_skip : nullptr;
       tmark_begin(h, DASHSVD_KT_EIG, pass);
       e = launch_eig(ea, st);
       tmark_end(h);
       if (e != hipSuccess) return e;
       tmark_begin(h, DASHSVD_KT_RESCALE, pass);
-      e = launch_rescale(Mn, l, b.C, ld, cdt, b.W, l, l, b.Q, ld, pdt, skip, st);
+      e = launch_rescale(Mn, l, b.C, ld, cdt, b.W, l, l, Qc, ld, pcur, skip, st);
       tmark_end(h);
       if (e != hipSuccess) return e;
       tmark_begin(h, DASHSVD_KT_SPMM, pass);
-      e = launch_spmm(Mm, rpM, colM, valM, vdt, b.Q, ld, pdt, b.Y, ld, pdt, ld, b.planM.n_chunks, b.planM.tasks,
+      e = launch_spmm(Mm, rpM, colM, valM, vdt, Qc, ld, pcur, Yc, ld, pcur, ld, b.planM.n_chunks, b.planM.tasks,
                       b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, skip, st);
       tmark_end(h);
       return e;
@@ -645,24 +674,41 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       for (int c = 0; c < chunk; ++c) {
         const int pass = launched + c + 1;
         tmark_begin(h, DASHSVD_KT_SPMM_T, pass);
-        HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ld, b.planT.n_chunks,
-                           b.planT.tasks, b.planT.n_long, b.planT.longs, b.planT.partial, T, b.Q, ld,
+        HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, Yc, ld, pcur, b.C, ld, cdt, ld, b.planT.n_chunks,
+                           b.planT.tasks, b.planT.n_long, b.planT.longs, b.planT.partial, T, Qc, ld,
                            &b.state->alpha, done, st));
         tmark_end(h);
         HIPCHK(block_step(2, pass, done));
       }
       launched += chunk;
-      bool stop = false;
-      HIPCHK(stopped(launched, stop));
-      if (stop) break;
+      if (tol > 0.0 && launched < pmax) {
+        int32_t flags[2] = {0, 0};  // done, promote
+        HIPCHK(hipMemcpyAsync(&flags[0], done, 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(&flags[1], &b.state->promote, 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (flags[0]) break;
+        if (flags[1] && pcur == DASHSVD_BF16) {
+          pcur = cdt;
+          Qc = b.Q32;
+          Yc = b.Y32;
+          promoted = 1;
+          HIPCHK(launch_rescale(Mn, l, b.C, ld, cdt, b.W, l, l, Qc, ld, pcur, nullptr, st));
+          HIPCHK(launch_spmm(Mm, rpM, colM, valM, vdt, Qc, ld, pcur, Yc, ld, pcur, ld, b.planM.n_chunks,
+                             b.planM.tasks, b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0,
+                             nullptr, nullptr, st));
+        }
+      }
     }
     HIPCHK(hipStreamSynchronize(st));
+    Qfin = Qc;
+    Yfin = Yc;
+    pfin = pcur;
   }
   const double t_loop = now_ms();
   // final Rayleigh-Ritz (steps 9-11): B = M Q ; eigSVD(B) ; U = B W(:,1:k) ;
   // V = Q Vs(:,1:k).
   tmark_begin(h, DASHSVD_KT_FINAL, 0);
-  void *Qf = b.Q;
+  void *Qf = b.Q, *Bf = b.B;
   if (pdt == cdt) {
     // the last block: C (its buffer alternates with the pass), Z = M C and
     // W; Q = C W and B = Z W
@@ -670,18 +716,24 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     Qf = (last_pass & 1) ? b.C : b.Q;
     HIPCHK(launch_rescale(Mn, l, Cl, ld, cdt, b.W, l, l, Qf, ld, pdt, nullptr, st));
     HIPCHK(launch_rescale(Mm, l, b.Z, ld, cdt, b.W, l, l, b.B, ld, cdt, nullptr, st));
-  } else {
+  } else if (pfin != cdt) {
     // the BF16 form keeps an FP32 B
-    HIPCHK(launch_spmm(Mm, rpM, colM, valM, vdt, b.Q, ld, pdt, b.B, ld, cdt, ld, b.planM.n_chunks, b.planM.tasks,
-                       b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, nullptr, st));
+    HIPCHK(launch_spmm(Mm, rpM, colM, valM, vdt, Qfin, ld, pfin, b.B, ld, cdt, ld, b.planM.n_chunks,
+                       b.planM.tasks, b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr,
+                       nullptr, st));
+    Qf = Qfin;
+  } else {
+    // promoted to FP32 panels: B is the last M Q
+    Bf = Yfin;
+    Qf = Qfin;
   }
-  HIPCHK(launch_gram(Mm, l, b.B, ld, cdt, b.gpart, nb_m, b.G, nullptr, st, nullptr));
+  HIPCHK(launch_gram(Mm, l, Bf, ld, cdt, b.gpart, nb_m, b.G, nullptr, st, nullptr));
   {
     EigArgs ea = make_eig(3);
     HIPCHK(launch_eig(ea, st));
   }
-  HIPCHK(launch_rescale(Mm, l, b.B, ld, cdt, b.W, l, k, b.Uo, k, cdt, nullptr, st));
-  HIPCHK(launch_rescale(Mn, l, Qf, ld, pdt, b.Vs, l, k, b.Vo, k, cdt, nullptr, st));
+  HIPCHK(launch_rescale(Mm, l, Bf, ld, cdt, b.W, l, k, b.Uo, k, cdt, nullptr, st));
+  HIPCHK(launch_rescale(Mn, l, Qf, ld, pdt == cdt ? pdt : pfin, b.Vs, l, k, b.Vo, k, cdt, nullptr, st));
   HIPCHK(launch_sign_fix(Mn, Mm, k, b.Vo, k, b.Uo, k, cdt, b.sgn_max, b.sgn_idx, sgn_blk, st));
   tmark_end(h);
   SolverState hs;
@@ -708,6 +760,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   inf.l = l;
   inf.learned_fallback = hs.sched_off;
   inf.final_alpha = hs.alpha;
+  inf.promoted = promoted;
   inf.time_total_ms = t_end - t0;
   inf.time_setup_ms = t_setup - t0;
   inf.time_loop_ms = t_loop - t_setup;
@@ -734,6 +787,31 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   h->trace_s = b.tr_s;
   h->trace_cap = cap;
   h->have = true;
+  {
+    auto &c = h->ev_ctx;
+    c.ok = true;
+    c.nnz = nnz;
+    c.Mm = Mm;
+    c.Mn = Mn;
+    c.wide = wide;
+    c.vdt = vdt;
+    c.cdt = cdt;
+    c.ld = ld;
+    c.T = T;
+    c.rp[0] = rpM;
+    c.rp[1] = rpMT;
+    c.col[0] = colM;
+    c.col[1] = colMT;
+    c.val[0] = valM;
+    c.val[1] = valMT;
+    c.plan[0] = b.planM;
+    c.plan[1] = b.planT;
+    // panels no longer needed once U and V are formed: B and C (C type)
+    c.panel_m = b.B;
+    c.panel_n = b.C;
+    c.gpart = b.gpart;
+    c.G = b.G;
+  }
   dashsvd_status s = DASHSVD_OK;
   if (tol > 0.0 && !hs.converged) s = DASHSVD_NOT_CONVERGED;
   else if (hs.deficient) s = DASHSVD_RANK_DEFICIENT;
@@ -800,6 +878,51 @@ dashsvd_status dashsvd_get_USV(dashsvd_handle *h, void *U, int64_t ldu, double *
   }
   if (S) HIPCHK(hipMemcpyAsync(S, h->S, 8 * (size_t)h->k, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  return DASHSVD_OK;
+}
+
+dashsvd_status dashsvd_evaluate(dashsvd_handle *h, const dashsvd_csr *A, const double *sigma_ref, int32_t n_ref,
+                                double *eps_pve, double *eps_sigma) {
+  if (!h) return DASHSVD_ERR_INVALID_ARG;
+  h->err.clear();
+  if (!h->have || !h->ev_ctx.ok) return fail(h, DASHSVD_ERR_STATE, "no results: run first");
+  auto &c = h->ev_ctx;
+  if (!A || A->m != h->m || A->n != h->n || A->nnz != c.nnz)
+    return fail(h, DASHSVD_ERR_INVALID_ARG, "A is not the matrix of the last run");
+  if (!sigma_ref || n_ref < h->k + 1) return fail(h, DASHSVD_ERR_INVALID_ARG, "sigma_ref needs k + 1 values");
+  if (!(sigma_ref[h->k] > 0.0)) return fail(h, DASHSVD_ERR_INVALID_ARG, "sigma_ref[k] must be positive");
+  hipStream_t st = h->st;
+  const int k = h->k;
+  const int ld8 = (int)round_up(k, 8);
+  // Z = A^T U with U (m x k) in the caller's orientation: A^T is M^T when
+  // A = M, and M itself when M = A^T (m < n)
+  const int side = c.wide ? 0 : 1;
+  const int64_t zrows = c.wide ? c.Mm : c.Mn, urows = h->m;
+  void *Upad = c.wide ? c.panel_n : c.panel_m;  // urows x ld8
+  void *Z = c.wide ? c.panel_m : c.panel_n;     // zrows x ld8
+  HIPCHK(launch_copy2d(h->U, k, h->out_dt, Upad, ld8, c.cdt, urows, k, st));
+  const Plan &pl = c.plan[side];
+  HIPCHK(launch_spmm(zrows, c.rp[side], c.col[side], c.val[side], c.vdt, Upad, ld8, c.cdt, Z, ld8, c.cdt, ld8,
+                     pl.n_chunks, pl.tasks, pl.n_long, pl.longs, pl.partial, c.T, nullptr, 0, nullptr, nullptr,
+                     st));
+  // ||A^T u_i||^2 = (Z^T Z)_ii in FP64
+  HIPCHK(launch_gram(zrows, k, Z, ld8, c.cdt, c.gpart, gram_blocks(zrows, k), c.G, nullptr, st, nullptr));
+  std::vector<double> G((size_t)k * k), S(k);
+  HIPCHK(hipMemcpyAsync(G.data(), c.G, 8 * (size_t)k * k, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(S.data(), h->S, 8 * (size_t)k, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  // eps_PVE = max_i |sigma_i^2 - ||A^T u_i||^2| / sigma_{k+1}^2 and
+  // eps_sigma = max_i |sigma_i - S_i| / sigma_i (Sec. 4 accuracy metrics)
+  const double sk1 = sigma_ref[k] * sigma_ref[k];
+  double pve = 0.0, es = 0.0;
+  for (int i = 0; i < k; ++i) {
+    const double d = std::fabs(sigma_ref[i] * sigma_ref[i] - G[(size_t)i * k + i]) / sk1;
+    if (d > pve || d != d) pve = d;
+    const double e = std::fabs(sigma_ref[i] - S[i]) / sigma_ref[i];
+    if (e > es || e != e) es = e;
+  }
+  if (eps_pve) *eps_pve = pve;
+  if (eps_sigma) *eps_sigma = es;
   return DASHSVD_OK;
 }
 

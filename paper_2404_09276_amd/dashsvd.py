@@ -56,7 +56,7 @@ class _Info(C.Structure):
                 ("time_final_ms", C.c_double), ("long_chunks_A", C.c_int64),
                 ("long_chunks_AT", C.c_int64), ("kt_ms", C.c_double * 8), ("kt_count", C.c_int32 * 8),
                 ("eig_calls", C.c_int32), ("eig_sweeps", C.c_int32),
-                ("sweeps_per_call", C.c_int32 * (MAX_TRACE + 2))]
+                ("sweeps_per_call", C.c_int32 * (MAX_TRACE + 2)), ("promoted", C.c_int32)]
 
 KT_NAMES = ["spmm", "spmm_t", "gram", "eig", "rescale", "transpose", "sketch", "final"]
 
@@ -65,7 +65,8 @@ _lib = None
 
 EXPORTS = [
     "dashsvd_create", "dashsvd_destroy", "dashsvd_set_options", "dashsvd_run", "dashsvd_get_USV",
-    "dashsvd_get_info", "dashsvd_get_trace", "dashsvd_workspace_size", "dashsvd_status_string",
+    "dashsvd_get_info", "dashsvd_get_trace", "dashsvd_evaluate", "dashsvd_workspace_size",
+    "dashsvd_status_string",
     "dashsvd_last_error", "dashsvd_k_gaussian", "dashsvd_k_philox_raw", "dashsvd_k_transpose",
     "dashsvd_k_spmm", "dashsvd_k_gram", "dashsvd_k_eig", "dashsvd_k_eig_prof", "dashsvd_k_rescale",
 ]
@@ -88,6 +89,7 @@ def lib():
         L.dashsvd_get_USV.argtypes = [P, P, i64, P, P, i64, i32, i32]
         L.dashsvd_get_info.argtypes = [P, C.POINTER(_Info)]
         L.dashsvd_get_trace.argtypes = [P, P, i32]
+        L.dashsvd_evaluate.argtypes = [P, C.POINTER(_Csr), P, i32, P, P]
         L.dashsvd_workspace_size.argtypes = [C.POINTER(_Csr), i32, i32, i32, C.POINTER(C.c_size_t)]
         L.dashsvd_status_string.argtypes = [i32]
         L.dashsvd_status_string.restype = C.c_char_p
@@ -189,6 +191,7 @@ class Info:
     eig_calls: int
     eig_sweeps: int
     sweeps_per_call: np.ndarray
+    promoted: bool
 
 
 class DashSVD:
@@ -269,6 +272,18 @@ class DashSVD:
     def _dims(self):
         return self._m, self._n, self._k
 
+    def evaluate(self, A, sigma_ref):
+        """dashsvd_evaluate: (eps_PVE, eps_sigma) of the last run on A (the
+        same matrix) against reference singular values sigma_ref (>= k+1)."""
+        s, keep = make_csr(A.m, A.n, A.row_ptr, A.col, A.val)
+        sr = np.ascontiguousarray(sigma_ref, dtype=np.float64)
+        pve, es = C.c_double(), C.c_double()
+        st = lib().dashsvd_evaluate(self._h, C.byref(s), _ptr(sr), int(sr.shape[0]), C.byref(pve),
+                                    C.byref(es))
+        del keep
+        _check(st, self._h)
+        return pve.value, es.value
+
     def info(self) -> Info:
         raw = _Info()
         _check(lib().dashsvd_get_info(self._h, C.byref(raw)), self._h)
@@ -280,7 +295,8 @@ class DashSVD:
                     raw.time_setup_ms, raw.time_loop_ms, raw.time_final_ms, raw.long_chunks_A,
                     raw.long_chunks_AT, dict(zip(KT_NAMES, list(raw.kt_ms))),
                     dict(zip(KT_NAMES, list(raw.kt_count))), raw.eig_calls, raw.eig_sweeps,
-                    np.array(raw.sweeps_per_call[:min(raw.eig_calls, MAX_TRACE + 2)]))
+                    np.array(raw.sweeps_per_call[:min(raw.eig_calls, MAX_TRACE + 2)]),
+                    bool(raw.promoted))
 
     def trace(self) -> np.ndarray:
         """Per-pass S (passes x l) of the last run (dashsvd_get_trace)."""

@@ -209,3 +209,44 @@ def test_rank_deficient_matrix(torch_dev):
     assert st == 2 and info.rank_deficient
     sv = np.linalg.svd(D, compute_uv=False)
     assert np.allclose(S[:3], sv[:3], rtol=1e-10)
+
+
+@pytest.mark.parametrize("shape,prec,atol", [((2000, 1500), "fp64", 1e-9), ((2000, 1500), "fp32", 2e-5),
+                                             ((700, 1900), "fp64", 1e-9)])
+def test_evaluate_matches_oracle_metrics(torch_dev, shape, prec, atol):
+    """dashsvd_evaluate (Sec. 4 eps_PVE, eps_sigma on the device) against the
+    oracle's metrics of the same U and S, with sigma from a dense SVD."""
+    from paper_2404_09276_amd import DashSVD
+    m, n = shape
+    A = synth.uniform_csr(m, n, 30000, seed=17, dtype=np.float64 if prec == "fp64" else np.float32)
+    sig = np.linalg.svd(A.to_dense().astype(np.float64), compute_uv=False)
+    h = DashSVD(precision=prec, p_max=4, seed=9)
+    h.run(A, 20, 10, 0.0)
+    U, S, V = h.get_usv()
+    pve, es = h.evaluate(A, sig[:21])
+    h.close()
+    rpve, res = oracle.metrics(A.m, A.n, A.row_ptr, A.col, A.val, U, S, sig[:21])
+    assert abs(pve - rpve) <= atol * max(1.0, rpve)
+    assert abs(es - res) <= 1e-12 + 1e-9 * res
+    assert 0.0 <= pve < 1.0
+
+
+def test_bf16_promotion_guard(torch_dev):
+    """BF16 panels with a tolerance below what BF16 rounding allows: the ratio
+    reaches a plateau, the guard switches to FP32 panels, and the run then
+    meets the tolerance with the FP32 form's singular values."""
+    A = synth.config_small(np.float32)
+    U, S, V, st, info, tr = _solve(A, 20, 10, 60, 1e-5, 2001, "bf16")
+    assert info.promoted and info.converged and st == 0
+    r = info.ratio
+    assert r[-1] <= 1e-5
+    U3, S3, V3, st3, info3, tr3 = _solve(A, 20, 10, 60, 1e-5, 2001, "fp32")
+    assert not info3.promoted and info3.converged
+    assert np.all(np.abs(S - S3) / S3 <= 1e-4)
+
+
+def test_bf16_no_promotion_at_loose_tol(torch_dev):
+    """tol above the BF16 plateau (about 2e-2 on this matrix): no promotion."""
+    A = synth.config_small(np.float32)
+    U, S, V, st, info, tr = _solve(A, 20, 10, 60, 5e-2, 2001, "bf16")
+    assert not info.promoted and info.converged
