@@ -7,6 +7,7 @@ Prop. 1 the values are lower bounds that converge from below, so the script
 records the last pass ratio as the convergence evidence.
 
 Usage:  python tests/golden/make_reference_sigma.py zipf_200k
+        python tests/golden/make_reference_sigma.py zipf_2m     (about 10-20 min)
 """
 import json
 import os
@@ -24,6 +25,7 @@ import synth  # noqa: E402
 CASES = {
     # name: (generator, k_needed, block oversampling, p_max)
     "zipf_200k": (synth.config_zipf_200k, 101, 99, 60),
+    "zipf_2m": (synth.config_zipf_2m, 101, 59, 40),
 }
 
 

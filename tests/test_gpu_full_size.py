@@ -1,0 +1,138 @@
+"""The solver at the full sizes of the two large workloads, in the launch
+configuration the benchmark uses (device-resident CSR, default options):
+
+  zipf_200k: 200,000 x 100,000, 10M nonzeros, k = 100, oversampling 20, FP32
+             panels, tol 1e-2;
+  zipf_2m:   2,000,000 x 1,000,000, 100M nonzeros, k = 100, oversampling 50,
+             BF16 panels, tol 1e-2 and 1e-3.
+
+The oracle cannot run Alg. 5 at these sizes inside a test, so the checks are
+ones the oracle can compute one output at a time, or that hold at any size:
+
+  - the final Rayleigh-Ritz step (Alg. 5 steps 9-11) makes A V = B W_B =
+    U diag(S) an identity of the output, so sampled rows of A V, formed by the
+    oracle's SpMM from the GPU's V, must equal U diag(S) up to rounding;
+  - U and V have orthonormal columns (V up to the BF16 rounding of Q);
+  - eps_PVE of Sec. 4 against reference singular values written by the
+    oracle (tests/golden/make_reference_sigma.py) is of the order of tol.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch
+
+
+def _device_csr(torch, A):
+    class Dev:
+        m, n, nnz = A.m, A.n, A.nnz
+        row_ptr = torch.from_numpy(A.row_ptr).cuda()
+        col = torch.from_numpy(A.col).cuda()
+        val = torch.from_numpy(A.val).cuda()
+    return Dev
+
+
+def _sampled_rows_identity(A, U, S, V, rows, rtol):
+    """(A V)[r, :] by the oracle's FP64 SpMM of the sampled rows of A against
+    U[r, :] diag(S)."""
+    rp = A.row_ptr
+    sub_rp = [0]
+    cols, vals = [], []
+    for r in rows:
+        cols.append(A.col[rp[r]:rp[r + 1]])
+        vals.append(A.val[rp[r]:rp[r + 1]])
+        sub_rp.append(sub_rp[-1] + int(rp[r + 1] - rp[r]))
+    AV = oracle.csr_spmm(np.array(sub_rp, dtype=np.int64), np.concatenate(cols),
+                         np.concatenate(vals), V.astype(np.float64))
+    US = U[rows].astype(np.float64) * S[None, :]
+    err = np.abs(AV - US)
+    scale = np.abs(US) + 1e-3 * S[None, :] * np.abs(U).max(axis=0)[None, :]
+    assert np.all(err <= rtol * scale), float((err / scale).max())
+
+
+def _golden_sigma(name):
+    path = os.path.join(GOLDEN, f"sigma_{name}.json")
+    if not os.path.exists(path):
+        return None
+    return np.array(json.load(open(path))["sigma"])
+
+
+def _run(torch, Dev, precision, k, s, tol, seed):
+    from paper_2404_09276_amd import DashSVD
+    h = DashSVD(precision=precision, p_max=64, seed=seed, stream=torch.cuda.current_stream())
+    st = h.run(Dev, k, s, tol)
+    U, S, V = h.get_usv(dtype="float32")
+    info = h.info()
+    return h, st, U, S, V, info
+
+
+def _heavy_and_random_rows(A, count, seed):
+    deg = np.diff(A.row_ptr)
+    heavy = np.argsort(deg)[-8:]
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([heavy, rng.choice(A.m, count, replace=False)]))
+
+
+def test_zipf_200k_fp32_full_size(torch_dev):
+    torch = torch_dev
+    A = synth.config_zipf_200k()
+    Dev = _device_csr(torch, A)
+    h, st, U, S, V, info = _run(torch, Dev, "fp32", 100, 20, 1e-2, synth.OMEGA_SEED["zipf_200k"])
+    try:
+        assert st == 0 and info.converged and 2 <= info.passes <= 20
+        assert np.all(np.diff(S) <= 0) and S[-1] > 0
+        _sampled_rows_identity(A, U, S, V, _heavy_and_random_rows(A, 56, 1), 2e-4)
+        assert np.abs(U.T.astype(np.float64) @ U - np.eye(100)).max() < 1e-4
+        assert np.abs(V.T.astype(np.float64) @ V - np.eye(100)).max() < 1e-4
+        sig = _golden_sigma("zipf_200k")
+        if sig is not None:
+            pve, es = h.evaluate(Dev, sig)
+            assert pve <= 2e-2 and es <= 2e-2
+    finally:
+        h.close()
+
+
+@pytest.fixture(scope="module")
+def zipf_2m(torch_dev):
+    A = synth.config_zipf_2m()
+    return A, _device_csr(torch_dev, A)
+
+
+@pytest.mark.parametrize("tol", [1e-2, 1e-3])
+def test_zipf_2m_bf16_full_size(torch_dev, zipf_2m, tol):
+    torch = torch_dev
+    A, Dev = zipf_2m
+    h, st, U, S, V, info = _run(torch, Dev, "bf16", 100, 50, tol, synth.OMEGA_SEED["zipf_2m"])
+    try:
+        assert st == 0 and info.converged and info.l == 150
+        print(f"zipf_2m bf16 tol={tol}: passes={info.passes} promoted={info.promoted} "
+              f"ratios={np.array2string(info.ratio, precision=2)}", flush=True)
+        assert np.all(np.diff(S) <= 0) and S[-1] > 0
+        # B = A Q and V = Q W_B come from the same BF16 Q: the identity holds
+        # to FP32 rounding
+        _sampled_rows_identity(A, U, S, V, _heavy_and_random_rows(A, 56, 2), 1e-3)
+        assert np.abs(U.T.astype(np.float64) @ U - np.eye(100)).max() < 1e-4
+        # Q is stored in BF16 (8-bit significand): V = Q W_B is orthonormal
+        # to about 2^-8
+        assert np.abs(V.T.astype(np.float64) @ V - np.eye(100)).max() < 2e-2
+        sig = _golden_sigma("zipf_2m")
+        if sig is not None:
+            pve, es = h.evaluate(Dev, sig)
+            assert pve <= 2 * max(tol, 1e-2) and es <= 2e-2
+    finally:
+        h.close()
