@@ -201,6 +201,29 @@ dashsvd_status dashsvd_evaluate(dashsvd_handle *h, const dashsvd_csr *A, const d
  * writes min(passes, max_passes) rows of l doubles to host memory. */
 dashsvd_status dashsvd_get_trace(dashsvd_handle *h, double *s_hat, int32_t max_passes);
 
+/* Batched form: count independent matrices, each solved by Alg. 5 (Alg. 4
+ * when tol == 0) with the handle's options, the same k and oversampling p,
+ * and its own shift, PVE check, stopping pass and traces.  Matrix i draws
+ * Omega from the Philox stream keyed (seed + i, 0).  Requirements: every
+ * matrix as for dashsvd_run, plus m >= n, k + p <= 64, the same value dtype
+ * and memory space for all, and stacked sizes (sum of rows, columns and
+ * nonzeros) below 2^31.  The matrices advance pass-synchronously: each step
+ * of a pass is one launch over the whole batch, and one pass is captured as
+ * a HIP graph and replayed.  Policies PAPER, NONE, FIXED and SCHEDULE.
+ * Returns OK, NOT_CONVERGED (some matrix reached p_max with tol > 0),
+ * RANK_DEFICIENT or an error.  Results stay in the handle until the next
+ * run of either form.  The arrays of all matrices must stay valid until
+ * the call returns (it synchronises). */
+dashsvd_status dashsvd_run_batched(dashsvd_handle *h, const dashsvd_csr *As, int32_t count, int32_t k,
+                                   int32_t p, double tol);
+/* Results of matrix idx of the last batched run, as dashsvd_get_USV. */
+dashsvd_status dashsvd_get_USV_batched(dashsvd_handle *h, int32_t idx, void *U, int64_t ldu, double *S,
+                                       void *V, int64_t ldv, int32_t dtype, int32_t on_device);
+/* Per-matrix info of the last batched run (passes, convergence, alpha and
+ * ratio traces, sweeps); idx < 0 gives the batch summary (maximum passes,
+ * all converged, total eig calls and sweeps, wall time). */
+dashsvd_status dashsvd_get_info_batched(dashsvd_handle *h, int32_t idx, dashsvd_info *out);
+
 /* Device bytes a run with these arguments needs (workspace of the handle). */
 dashsvd_status dashsvd_workspace_size(const dashsvd_csr *A, int32_t k, int32_t p,
                                       int32_t precision, size_t *bytes);

@@ -30,6 +30,9 @@ __device__ __forceinline__ bf16 f2bf(float f) {
 }
 
 // ------------------------------------------------------------------ element I/O
+template <typename T> __device__ __forceinline__ double to_d(T v) { return (double)v; }
+template <> __device__ __forceinline__ double to_d<bf16>(bf16 v) { return (double)bf2f(v); }
+
 template <typename T> struct elem;
 template <> struct elem<float> {
   __device__ static __forceinline__ float ld(const float *p) { return *p; }
@@ -185,7 +188,8 @@ hipError_t launch_spmm(int64_t R, const int64_t *rp, const int32_t *col, const v
                        const void *X, int64_t ldx, int xdtype, void *Y, int64_t ldy, int ydtype,
                        int ld_cols, int64_t n_chunks, const ChunkTask *tasks, int64_t n_long,
                        const LongRow *longs, void *partial, int32_t long_row, const void *Q,
-                       int64_t ldq, const double *alpha, const int32_t *done, hipStream_t st);
+                       int64_t ldq, const double *alpha, const int32_t *done, hipStream_t st,
+                       const int32_t *rowmat = nullptr, const SolverState *bstate = nullptr);
 
 // snap (optional): receives *done as read at the start of the Gram kernel,
 // i.e. whether the iteration had already stopped when this pass began.
@@ -215,10 +219,48 @@ struct EigArgs {
   const double *sched;  // device multipliers (SCHEDULE / LEARNED), may be null
   int sched_len;
   int stagnation_guard;  // track stagnant / promote (BF16 panel form)
+  int32_t *ndone;        // batched form: incremented once when this matrix stops
   long long *prof;      // optional step profile (6 counters), null in the solver
   int32_t *trace_sweeps;  // sweeps of call c (c = state->eig_calls before this call), [cap + 2]
 };
 hipError_t launch_eig(const EigArgs &a, hipStream_t st);
+// arr: count EigArgs in device memory, all with the same l; workgroup b
+// solves arr[b]
+hipError_t launch_eig_batched(const EigArgs *arr, int count, int l, hipStream_t st);
+
+// ------------------------------------------------------------------ batched form
+// One matrix of a batch inside the stacked block-diagonal operator.
+struct BMatDesc {
+  const int64_t *rp;  // source arrays (unused when assembling in place)
+  const int32_t *col;
+  const void *val;
+  int64_t m, n, nnz;
+  int64_t row_off, col_off, nnz_off;  // position in the stacked operator
+};
+// A work item: rows [r0, r1) of matrix mat (stacked row numbers).
+struct BItem {
+  int32_t mat;
+  int32_t pad;
+  int64_t r0, r1;
+};
+constexpr int kBStrip = 64;       // rows staged in LDS at a time
+constexpr int kBItemRows = 512;   // rows per work item
+constexpr int kBMaxL = 64;        // largest l of the batched dense kernels
+
+hipError_t launch_bassemble(const BMatDesc *d, int count, int64_t max_rows_nnz, int64_t total_rows,
+                            int64_t total_nnz, int64_t *rp, int32_t *col, void *val, int vdtype, int in_place,
+                            int32_t *flags, hipStream_t st);
+hipError_t launch_browmat(const int64_t *off, int count, int64_t max_rows, int32_t *rowmat, hipStream_t st);
+hipError_t launch_bsnap(SolverState *state, int count, int snap, hipStream_t st);
+size_t bgram_partial_elems(int64_t n_items, int l);
+hipError_t launch_bgram(const BItem *items, int64_t n_items, const int64_t *item_off, int count, int l,
+                        const void *C, int64_t ldc, int cdtype, double *partial, double *G, int64_t g_stride,
+                        const SolverState *state, int gate, hipStream_t st);
+hipError_t launch_brescale(const BItem *items, int64_t n_items, int l, const void *C, const void *R, int64_t ldc,
+                           int cdtype, const double *W, int64_t w_stride, int64_t ldw, int c, void *Out,
+                           int64_t ldo, int odtype, const SolverState *state, int gate, hipStream_t st);
+hipError_t launch_bsign(const int64_t *voff, const int64_t *uoff, int count, int k, void *V, void *U, int64_t ld,
+                        int dtype, hipStream_t st);
 
 // Out = (C - alpha R) W when R is given (R laid out like C, alpha on the
 // device), else Out = C W.

@@ -18,6 +18,8 @@
 #include <string>
 #include <vector>
 
+#include <algorithm>
+
 #include "../../include/dashsvd.h"
 #include "common.h"
 
@@ -104,6 +106,21 @@ struct dashsvd_handle {
     void *panel_m = nullptr, *panel_n = nullptr;  // Mm x ld and Mn x ld, cdt
     double *gpart = nullptr, *G = nullptr;
   } ev_ctx;
+  // results of the last batched run
+  struct BatchOut {
+    bool have = false;
+    int count = 0, k = 0, l = 0, cap = 0, out_dt = 0;
+    std::vector<int64_t> m, n, row_off, col_off;
+    void *Uo = nullptr, *Vo = nullptr;
+    double *S = nullptr;  // count x l
+    SolverState *state = nullptr;
+    double *tr_alpha = nullptr, *tr_ratio = nullptr;  // count x cap
+    int32_t *tr_sweeps = nullptr;                     // count x (cap + 2)
+    dashsvd_info info;
+  } bat;
+  // internal stream of the batched form (its pass is captured as a graph)
+  hipStream_t stg = nullptr;
+  hipEvent_t ev_b0 = nullptr, ev_b1 = nullptr;
 };
 
 namespace {
@@ -312,6 +329,12 @@ void dashsvd_destroy(dashsvd_handle *h) {
   if (h->ev_gram) (void)hipEventDestroy(h->ev_gram);
   if (h->ev_eig) (void)hipEventDestroy(h->ev_eig);
   if (h->st2) (void)hipStreamDestroy(h->st2);
+  if (h->stg) {
+    (void)hipStreamSynchronize(h->stg);
+    (void)hipStreamDestroy(h->stg);
+  }
+  if (h->ev_b0) (void)hipEventDestroy(h->ev_b0);
+  if (h->ev_b1) (void)hipEventDestroy(h->ev_b1);
   delete h;
 }
 
@@ -366,6 +389,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     ar.reset(false);
   }
   h->have = false;
+  h->bat.have = false;
   const bool need_copy_struct = !A->on_device;
   const bool need_copy_val = !A->on_device || A->value_dtype != vdt;
   int64_t *rp_in = need_copy_struct ? (int64_t *)ar.take(8 * (size_t)(m + 1)) : nullptr;
@@ -923,6 +947,458 @@ dashsvd_status dashsvd_evaluate(dashsvd_handle *h, const dashsvd_csr *A, const d
   }
   if (eps_pve) *eps_pve = pve;
   if (eps_sigma) *eps_sigma = es;
+  return DASHSVD_OK;
+}
+
+// ===================================================================== batched form
+// All matrices of the batch advance pass-synchronously (Alg. 5 on each):
+// their operators are stacked into one block-diagonal CSR, so every step of
+// a pass is one launch over the whole batch, each matrix with its own shift,
+// PVE check, stop flag and traces.  One pass is captured as a graph on the
+// handle's internal stream and replayed; stopped matrices skip their work
+// items.  The run is ordered after prior work on the handle's stream, which
+// waits for it in turn.
+static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As, int32_t count, int32_t k,
+                                       int32_t p, double tol, bool measure_only, size_t *measured) {
+  const int prec = h->opt.precision;
+  const int vdt = prec == DASHSVD_PREC_FP64 ? DASHSVD_F64 : DASHSVD_F32;
+  const int pdt = prec == DASHSVD_PREC_FP64 ? DASHSVD_F64 : (prec == DASHSVD_PREC_BF16_PANELS ? DASHSVD_BF16 : DASHSVD_F32);
+  const int cdt = prec == DASHSVD_PREC_FP64 ? DASHSVD_F64 : DASHSVD_F32;
+  const size_t accsz = prec == DASHSVD_PREC_FP64 ? 8 : 4;
+  const int l = k + p;
+  const int ld = (int)round_up(l, 8);
+  const int32_t T = h->opt.long_row > 0 ? h->opt.long_row : kDefaultLongRow;
+  const int pmax = h->opt.p_max;
+  const int cap = pmax > 0 ? pmax : 1;
+  const int in_dt = As[0].value_dtype;
+  const bool on_dev = As[0].on_device != 0;
+  // stacked sizes
+  std::vector<int64_t> roff(count + 1, 0), coff(count + 1, 0), zoff(count + 1, 0);
+  int64_t max_rn = 1, max_m = 1, max_n = 1;
+  for (int b = 0; b < count; ++b) {
+    roff[b + 1] = roff[b] + As[b].m;
+    coff[b + 1] = coff[b] + As[b].n;
+    zoff[b + 1] = zoff[b] + As[b].nnz;
+    max_rn = std::max(max_rn, std::max(As[b].m + 1, As[b].nnz));
+    max_m = std::max(max_m, As[b].m);
+    max_n = std::max(max_n, As[b].n);
+  }
+  const int64_t m = roff[count], n = coff[count], nnz = zoff[count];
+  if (m > INT32_MAX - 1 || n > INT32_MAX - 1 || nnz > INT32_MAX - 1)
+    return fail(h, DASHSVD_ERR_INVALID_ARG, "batch too large for 32-bit indices of the stacked operator");
+  // work items of both sides (rows of M: U, B; rows of M^T: C, Q, V)
+  std::vector<BItem> itM, itN;
+  std::vector<int64_t> ioffM(count + 1, 0), ioffN(count + 1, 0);
+  for (int b = 0; b < count; ++b) {
+    for (int64_t r = roff[b]; r < roff[b + 1]; r += kBItemRows)
+      itM.push_back({b, 0, r, std::min(r + kBItemRows, roff[b + 1])});
+    ioffM[b + 1] = (int64_t)itM.size();
+    for (int64_t r = coff[b]; r < coff[b + 1]; r += kBItemRows)
+      itN.push_back({b, 0, r, std::min(r + kBItemRows, coff[b + 1])});
+    ioffN[b + 1] = (int64_t)itN.size();
+  }
+  hipStream_t st = h->stg;
+
+  Arena &ar = h->ar;
+  ar.reset(measure_only || ar.base == nullptr);
+  if (!measure_only) {
+    size_t need = 0;
+    run_batched_impl(h, As, count, k, p, tol, true, &need);
+    dashsvd_status s = ensure_arena(h, need);
+    if (s != DASHSVD_OK) return s;
+    ar.reset(false);
+  }
+  h->have = false;
+  h->bat.have = false;
+  RunBufs b;
+  int64_t *rpA = (int64_t *)ar.take(8 * (size_t)(m + 1));
+  int32_t *colA = (int32_t *)ar.take(4 * (size_t)(nnz + 1));
+  void *val_raw = ar.take(dsz(in_dt) * (size_t)(nnz + 1));
+  void *valA = in_dt == vdt ? val_raw : ar.take(dsz(vdt) * (size_t)(nnz + 1));
+  BMatDesc *desc = (BMatDesc *)ar.take(sizeof(BMatDesc) * (size_t)count);
+  b.rpT = (int64_t *)ar.take(8 * (size_t)(n + 1));
+  b.colT = (int32_t *)ar.take(4 * (size_t)(nnz + 1));
+  b.valT = ar.take(dsz(vdt) * (size_t)(nnz + 1));
+  b.colcnt = (int64_t *)ar.take(8 * (size_t)(n + 1));
+  b.rowidx = (int32_t *)ar.take(4 * (size_t)(nnz + 1));
+  b.cursor = (int32_t *)ar.take(4 * (size_t)(n + 1));
+  b.tmp_row = (int32_t *)ar.take(4 * (size_t)(nnz + 1));
+  b.tmp_src = (int32_t *)ar.take(4 * (size_t)(nnz + 1));
+  b.lists = (int32_t *)ar.take(4 * (size_t)(3 * n + 1));
+  b.counts = (int32_t *)ar.take(4 * 8);
+  b.flags = b.counts + 4;
+  const int64_t words = transpose_bitmap_words(m);
+  b.nblk_large = 256;
+  b.bitmap = (uint32_t *)ar.take(4 * (size_t)words * b.nblk_large);
+  b.prefix = (int32_t *)ar.take(4 * (size_t)words * b.nblk_large);
+  b.scan_tmp = (int64_t *)ar.take(8 * scan_tmp_elems(std::max(m, n) + 1));
+  plan_alloc(h, ar, b.planM, m, nnz, T, ld, accsz);
+  plan_alloc(h, ar, b.planT, n, nnz, T, ld, accsz);
+  b.Y = ar.take(dsz(pdt) * (size_t)m * ld);
+  b.Q = ar.take(dsz(pdt) * (size_t)n * ld);
+  b.C = ar.take(dsz(cdt) * (size_t)n * ld);
+  b.B = pdt == cdt ? b.Y : ar.take(dsz(cdt) * (size_t)m * ld);
+  const size_t ll = (size_t)l * l;
+  b.G = (double *)ar.take(8 * ll * count);
+  b.W = (double *)ar.take(8 * ll * count);
+  b.Vs = (double *)ar.take(8 * ll * count);
+  b.S = (double *)ar.take(8 * (size_t)l * count);
+  b.Sprev = (double *)ar.take(8 * (size_t)l * count);
+  b.state = (SolverState *)ar.take(sizeof(SolverState) * (size_t)count);
+  b.tr_alpha = (double *)ar.take(8 * (size_t)cap * count);
+  b.tr_ratio = (double *)ar.take(8 * (size_t)cap * count);
+  b.tr_s = (double *)ar.take(8 * (size_t)cap * l * count);
+  b.tr_sweeps = (int32_t *)ar.take(4 * (size_t)(cap + 2) * count);
+  b.sched = (double *)ar.take(8 * (size_t)(pmax + 2));
+  b.Uo = ar.take(dsz(cdt) * (size_t)m * k);
+  b.Vo = ar.take(dsz(cdt) * (size_t)n * k);
+  EigArgs *eargs = (EigArgs *)ar.take(sizeof(EigArgs) * 3 * (size_t)count);
+  int64_t *offM = (int64_t *)ar.take(8 * (size_t)(count + 1));
+  int64_t *offN = (int64_t *)ar.take(8 * (size_t)(count + 1));
+  int64_t *ioffM_d = (int64_t *)ar.take(8 * (size_t)(count + 1));
+  int64_t *ioffN_d = (int64_t *)ar.take(8 * (size_t)(count + 1));
+  BItem *itM_d = (BItem *)ar.take(sizeof(BItem) * itM.size());
+  BItem *itN_d = (BItem *)ar.take(sizeof(BItem) * itN.size());
+  double *bpart = (double *)ar.take(8 * bgram_partial_elems((int64_t)std::max(itM.size(), itN.size()), l));
+  int32_t *rowmatM = (int32_t *)ar.take(4 * (size_t)m);
+  int32_t *rowmatN = (int32_t *)ar.take(4 * (size_t)n);
+  int32_t *ndone = (int32_t *)ar.take(16);
+  if (measure_only) {
+    *measured = ar.used;
+    return DASHSVD_OK;
+  }
+
+  // ---------------------------------------------------------------- setup
+  HIPCHK(hipMemsetAsync(b.colcnt, 0, 8 * (size_t)(n + 1), st));
+  HIPCHK(hipMemsetAsync(b.cursor, 0, 4 * (size_t)(n + 1), st));
+  HIPCHK(hipMemsetAsync(b.counts, 0, 4 * 8, st));
+  HIPCHK(hipMemsetAsync(b.planM.nlong, 0, 16, st));
+  HIPCHK(hipMemsetAsync(b.planT.nlong, 0, 16, st));
+  HIPCHK(hipMemsetAsync(b.state, 0, sizeof(SolverState) * (size_t)count, st));
+  HIPCHK(hipMemsetAsync(b.Sprev, 0, 8 * (size_t)l * count, st));
+  HIPCHK(hipMemsetAsync(b.tr_alpha, 0, 8 * (size_t)cap * count, st));
+  HIPCHK(hipMemsetAsync(b.tr_ratio, 0, 8 * (size_t)cap * count, st));
+  HIPCHK(hipMemsetAsync(b.tr_sweeps, 0, 4 * (size_t)(cap + 2) * count, st));
+  HIPCHK(hipMemsetAsync(ndone, 0, 16, st));
+  // stacked operator
+  std::vector<BMatDesc> hd(count);
+  for (int i = 0; i < count; ++i) {
+    hd[i] = {As[i].row_ptr, As[i].col_idx, As[i].values, As[i].m, As[i].n, As[i].nnz, roff[i], coff[i], zoff[i]};
+    if (!on_dev) {
+      if (As[i].row_ptr[0] != 0 || As[i].row_ptr[As[i].m] != As[i].nnz)
+        return fail(h, DASHSVD_ERR_BAD_CSR, "row_ptr of matrix " + std::to_string(i) + " malformed");
+      HIPCHK(hipMemcpyAsync(rpA + roff[i], As[i].row_ptr, 8 * (size_t)As[i].m, hipMemcpyHostToDevice, st));
+      if (As[i].nnz > 0) {
+        HIPCHK(hipMemcpyAsync(colA + zoff[i], As[i].col_idx, 4 * (size_t)As[i].nnz, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync((char *)val_raw + dsz(in_dt) * zoff[i], As[i].values,
+                              dsz(in_dt) * (size_t)As[i].nnz, hipMemcpyHostToDevice, st));
+      }
+    }
+  }
+  HIPCHK(hipMemcpyAsync(desc, hd.data(), sizeof(BMatDesc) * (size_t)count, hipMemcpyHostToDevice, st));
+  HIPCHK(launch_bassemble(desc, count, max_rn, m, nnz, rpA, colA, val_raw, in_dt, on_dev ? 0 : 1, b.flags + 2, st));
+  if (in_dt != vdt) HIPCHK(launch_convert(val_raw, in_dt, valA, vdt, nnz, st));
+  HIPCHK(launch_validate(m, n, nnz, rpA, colA, valA, vdt, b.colcnt, b.rowidx, b.flags, st));
+  int32_t hflags[4] = {0, 0, 0, 0};
+  HIPCHK(hipMemcpyAsync(hflags, b.flags, sizeof(hflags), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if ((hflags[0] & 1) || (hflags[2] & 1)) return fail(h, DASHSVD_ERR_BAD_CSR, "row_ptr/col_idx malformed");
+  if (hflags[0] & 2) return fail(h, DASHSVD_ERR_NONFINITE, "NaN or Inf among the values");
+  HIPCHK(launch_scan_i64(b.colcnt, n, b.rpT, b.scan_tmp, st));
+  HIPCHK(launch_transpose_scatter(nnz, colA, b.rowidx, b.rpT, b.cursor, b.tmp_row, b.tmp_src, st));
+  HIPCHK(launch_transpose_classify(n, b.rpT, b.tmp_row, b.tmp_src, valA, vdt, b.colT, b.valT, b.lists, b.counts,
+                                   st));
+  int32_t hcounts[4] = {0, 0, 0, 0};
+  HIPCHK(hipMemcpyAsync(hcounts, b.counts, sizeof(hcounts), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(launch_transpose_sort(m, n, b.rpT, b.tmp_row, b.tmp_src, valA, vdt, b.colT, b.valT, b.lists, hcounts,
+                               b.bitmap, b.prefix, b.nblk_large, st));
+  Plan *plans[2] = {&b.planM, &b.planT};
+  const int64_t *rps[2] = {rpA, b.rpT};
+  for (int i = 0; i < 2; ++i) {
+    Plan &pl = *plans[i];
+    HIPCHK(launch_plan_count(pl.R, rps[i], T, pl.nch, st));
+    HIPCHK(launch_scan_i64(pl.nch, pl.R, pl.off, b.scan_tmp, st));
+    HIPCHK(launch_plan_fill(pl.R, rps[i], T, pl.off, pl.tasks, pl.longs, pl.nlong, st));
+  }
+  int64_t totals[2] = {0, 0};
+  int32_t nlongs[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(&totals[0], b.planM.off + b.planM.R, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&totals[1], b.planT.off + b.planT.R, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&nlongs[0], b.planM.nlong, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&nlongs[1], b.planT.nlong, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(offM, roff.data(), 8 * (size_t)(count + 1), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(offN, coff.data(), 8 * (size_t)(count + 1), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ioffM_d, ioffM.data(), 8 * (size_t)(count + 1), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ioffN_d, ioffN.data(), 8 * (size_t)(count + 1), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(itM_d, itM.data(), sizeof(BItem) * itM.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(itN_d, itN.data(), sizeof(BItem) * itN.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  b.planM.n_chunks = totals[0];
+  b.planT.n_chunks = totals[1];
+  b.planM.n_long = nlongs[0];
+  b.planT.n_long = nlongs[1];
+  HIPCHK(launch_browmat(offM, count, max_m, rowmatM, st));
+  HIPCHK(launch_browmat(offN, count, max_n, rowmatN, st));
+  // Omega of matrix i from the Philox stream keyed (seed + i, 0)
+  for (int i = 0; i < count; ++i)
+    HIPCHK(launch_gaussian(h->opt.seed + (uint64_t)i, As[i].m, l, (char *)b.Y + dsz(pdt) * (size_t)roff[i] * ld, ld,
+                           pdt, st));
+  if (!h->sched.empty())
+    HIPCHK(hipMemcpyAsync(b.sched, h->sched.data(), 8 * h->sched.size(), hipMemcpyHostToDevice, st));
+  // per-matrix eigSVD arguments for the sketch (mode 1), the passes (2) and
+  // the final step (3)
+  std::vector<EigArgs> ea(3 * (size_t)count);
+  for (int mode = 1; mode <= 3; ++mode)
+    for (int i = 0; i < count; ++i) {
+      EigArgs &e = ea[(size_t)(mode - 1) * count + i];
+      std::memset(&e, 0, sizeof(e));
+      e.l = l;
+      e.k = k;
+      e.skip = prec == DASHSVD_PREC_FP64 ? 0x1.0p-53 : 0x1.0p-30;
+      e.G = b.G + ll * i;
+      e.S = b.S + (size_t)l * i;
+      e.Vs = b.Vs + ll * i;
+      e.W = b.W + ll * i;
+      e.state = b.state + i;
+      e.mode = mode;
+      e.pve_mode = h->opt.pve_mode;
+      e.policy = h->opt.shift_policy;
+      e.tol = tol;
+      e.Sprev = b.Sprev + (size_t)l * i;
+      e.trace_alpha = b.tr_alpha + (size_t)cap * i;
+      e.trace_ratio = b.tr_ratio + (size_t)cap * i;
+      e.trace_s = b.tr_s + (size_t)cap * l * i;
+      e.trace_cap = cap;
+      e.trace_sweeps = b.tr_sweeps + (size_t)(cap + 2) * i;
+      e.sched = h->sched.empty() ? nullptr : b.sched;
+      e.sched_len = (int)h->sched.size();
+      e.ndone = ndone;
+    }
+  HIPCHK(hipMemcpyAsync(eargs, ea.data(), sizeof(EigArgs) * ea.size(), hipMemcpyHostToDevice, st));
+  const int64_t nIM = (int64_t)itM.size(), nIN = (int64_t)itN.size();
+
+  // one eigSVD block of every matrix on C (rows of M^T): Gram, eig, Q = C W,
+  // then Y = M Q; gate: skip the matrices stopped before this pass
+  auto block = [&](int mode, int gate) -> hipError_t {
+    hipError_t e = launch_bgram(itN_d, nIN, ioffN_d, count, l, b.C, ld, cdt, bpart, b.G, (int64_t)ll, b.state,
+                                gate, st);
+    if (e == hipSuccess) e = launch_eig_batched(eargs + (size_t)(mode - 1) * count, count, l, st);
+    if (e == hipSuccess)
+      e = launch_brescale(itN_d, nIN, l, b.C, nullptr, ld, cdt, b.W, (int64_t)ll, l, l, b.Q, ld, pdt, b.state,
+                          gate, st);
+    if (e == hipSuccess)
+      e = launch_spmm(m, rpA, colA, valA, vdt, b.Q, ld, pdt, b.Y, ld, pdt, ld, b.planM.n_chunks, b.planM.tasks,
+                      b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, nullptr, st,
+                      gate ? rowmatM : nullptr, b.state);
+    return e;
+  };
+  // sketch: C = M^T Omega, eigSVD, Y = M Q
+  HIPCHK(launch_spmm(n, b.rpT, b.colT, b.valT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ld, b.planT.n_chunks, b.planT.tasks,
+                     b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr, nullptr, st));
+  HIPCHK(block(1, 0));
+  // one power pass of every running matrix, captured once and replayed
+  auto pass = [&]() -> hipError_t {
+    hipError_t e = launch_bsnap(b.state, count, 1, st);
+    if (e == hipSuccess)
+      e = launch_spmm(n, b.rpT, b.colT, b.valT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ld, b.planT.n_chunks,
+                      b.planT.tasks, b.planT.n_long, b.planT.longs, b.planT.partial, T, b.Q, ld, &b.state->alpha,
+                      nullptr, st, rowmatN, b.state);
+    if (e == hipSuccess) e = block(2, 1);
+    return e;
+  };
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (pmax > 0) {
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    hipError_t ec = pass();
+    hipError_t ee = hipStreamEndCapture(st, &graph);
+    if (ec != hipSuccess || ee != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return fail(h, DASHSVD_ERR_HIP, std::string("pass capture: ") + hipGetErrorString(ec != hipSuccess ? ec : ee));
+    }
+    hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return fail(h, DASHSVD_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+    }
+  }
+  const int every = h->opt.check_interval > 0 ? h->opt.check_interval : 1;
+  int launched = 0;
+  hipError_t eloop = hipSuccess;
+  while (launched < pmax && eloop == hipSuccess) {
+    const int chunk = (pmax - launched) < every ? (pmax - launched) : every;
+    for (int c = 0; c < chunk && eloop == hipSuccess; ++c) eloop = hipGraphLaunch(exec, st);
+    launched += chunk;
+    if (eloop == hipSuccess && tol > 0.0 && launched < pmax) {
+      int32_t nd = 0;
+      eloop = hipMemcpyAsync(&nd, ndone, 4, hipMemcpyDeviceToHost, st);
+      if (eloop == hipSuccess) eloop = hipStreamSynchronize(st);
+      if (nd >= count) break;
+    }
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  HIPCHK(eloop);
+  // final Rayleigh-Ritz of every matrix: B = M Q, eigSVD(B), U = B W(:,1:k),
+  // V = Q Vs(:,1:k), signs
+  HIPCHK(launch_bsnap(b.state, count, 0, st));
+  HIPCHK(launch_spmm(m, rpA, colA, valA, vdt, b.Q, ld, pdt, b.B, ld, cdt, ld, b.planM.n_chunks, b.planM.tasks,
+                     b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, nullptr, st));
+  HIPCHK(launch_bgram(itM_d, nIM, ioffM_d, count, l, b.B, ld, cdt, bpart, b.G, (int64_t)ll, b.state, 0, st));
+  HIPCHK(launch_eig_batched(eargs + 2 * (size_t)count, count, l, st));
+  HIPCHK(launch_brescale(itM_d, nIM, l, b.B, nullptr, ld, cdt, b.W, (int64_t)ll, l, k, b.Uo, k, cdt, b.state, 0,
+                         st));
+  HIPCHK(launch_brescale(itN_d, nIN, l, b.Q, nullptr, ld, pdt, b.Vs, (int64_t)ll, l, k, b.Vo, k, cdt, b.state, 0,
+                         st));
+  HIPCHK(launch_bsign(offN, offM, count, k, b.Vo, b.Uo, k, cdt, st));
+  // aggregate info
+  std::vector<SolverState> hs(count);
+  HIPCHK(hipMemcpyAsync(hs.data(), b.state, sizeof(SolverState) * (size_t)count, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  auto &bo = h->bat;
+  std::memset(&bo.info, 0, sizeof(bo.info));
+  bo.info.converged = 1;
+  for (int i = 0; i < count; ++i) {
+    bo.info.passes = std::max(bo.info.passes, hs[i].pass);
+    bo.info.converged &= hs[i].converged;
+    bo.info.rank_deficient |= hs[i].deficient;
+    bo.info.eig_calls += hs[i].eig_calls;
+    bo.info.eig_sweeps += hs[i].eig_sweeps;
+  }
+  bo.info.l = l;
+  bo.have = true;
+  bo.count = count;
+  bo.k = k;
+  bo.l = l;
+  bo.cap = cap;
+  bo.out_dt = cdt;
+  bo.m.assign(count, 0);
+  bo.n.assign(count, 0);
+  for (int i = 0; i < count; ++i) {
+    bo.m[i] = As[i].m;
+    bo.n[i] = As[i].n;
+  }
+  bo.row_off = roff;
+  bo.col_off = coff;
+  bo.Uo = b.Uo;
+  bo.Vo = b.Vo;
+  bo.S = b.S;
+  bo.state = b.state;
+  bo.tr_alpha = b.tr_alpha;
+  bo.tr_ratio = b.tr_ratio;
+  bo.tr_sweeps = b.tr_sweeps;
+  dashsvd_status s = DASHSVD_OK;
+  if (tol > 0.0 && !bo.info.converged) s = DASHSVD_NOT_CONVERGED;
+  else if (bo.info.rank_deficient) s = DASHSVD_RANK_DEFICIENT;
+  bo.info.status = s;
+  return s;
+}
+
+dashsvd_status dashsvd_run_batched(dashsvd_handle *h, const dashsvd_csr *As, int32_t count, int32_t k, int32_t p,
+                                   double tol) {
+  if (!h) return DASHSVD_ERR_INVALID_ARG;
+  h->err.clear();
+  if (!As || count < 1) return fail(h, DASHSVD_ERR_INVALID_ARG, "empty batch");
+  if (h->opt.shift_policy == DASHSVD_SHIFT_LEARNED)
+    return fail(h, DASHSVD_ERR_INVALID_ARG, "the batched form takes the PAPER, NONE, FIXED or SCHEDULE policy");
+  if (h->opt.omega) return fail(h, DASHSVD_ERR_INVALID_ARG, "the batched form draws its own Omega");
+  for (int i = 0; i < count; ++i) {
+    dashsvd_status s = check_args(h, &As[i], k, p, tol);
+    if (s != DASHSVD_OK) {
+      h->err = "matrix " + std::to_string(i) + ": " + h->err;
+      return s;
+    }
+    if (As[i].m < As[i].n)
+      return fail(h, DASHSVD_ERR_INVALID_ARG, "batched form: matrix " + std::to_string(i) + " has m < n");
+    if (As[i].value_dtype != As[0].value_dtype || (As[i].on_device != 0) != (As[0].on_device != 0))
+      return fail(h, DASHSVD_ERR_INVALID_ARG, "batched form: mixed value types or memory spaces");
+  }
+  if (k + p > kBMaxL) return fail(h, DASHSVD_ERR_INVALID_ARG, "batched form: k + oversampling exceeds 64");
+  if (!h->stg) {
+    HIPCHK(hipStreamCreateWithFlags(&h->stg, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&h->ev_b0, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&h->ev_b1, hipEventDisableTiming));
+  }
+  HIPCHK(hipEventRecord(h->ev_b0, h->st));
+  HIPCHK(hipStreamWaitEvent(h->stg, h->ev_b0, 0));
+  const double t0 = now_ms();
+  dashsvd_status s = run_batched_impl(h, As, count, k, p, tol, false, nullptr);
+  (void)hipStreamSynchronize(h->stg);
+  h->bat.info.time_total_ms = now_ms() - t0;
+  h->bat.info.status = s;
+  return s;
+}
+
+dashsvd_status dashsvd_get_USV_batched(dashsvd_handle *h, int32_t idx, void *U, int64_t ldu, double *S, void *V,
+                                       int64_t ldv, int32_t dtype, int32_t on_device) {
+  if (!h) return DASHSVD_ERR_INVALID_ARG;
+  auto &bo = h->bat;
+  if (!bo.have) return fail(h, DASHSVD_ERR_STATE, "no batched results: run_batched first");
+  if (idx < 0 || idx >= bo.count) return fail(h, DASHSVD_ERR_INVALID_ARG, "matrix index");
+  if (dtype != DASHSVD_F32 && dtype != DASHSVD_F64) return fail(h, DASHSVD_ERR_INVALID_ARG, "dtype");
+  if ((U && ldu < bo.k) || (V && ldv < bo.k)) return fail(h, DASHSVD_ERR_INVALID_ARG, "leading dimension");
+  hipStream_t st = h->stg;
+  const size_t es = dsz(dtype), os = dsz(bo.out_dt);
+  struct Item {
+    void *dst;
+    int64_t ldd;
+    const void *src;
+    int64_t rows;
+  } items[2] = {{U, ldu, (const char *)bo.Uo + os * (size_t)bo.row_off[idx] * bo.k, bo.m[idx]},
+                {V, ldv, (const char *)bo.Vo + os * (size_t)bo.col_off[idx] * bo.k, bo.n[idx]}};
+  for (auto &it : items) {
+    if (!it.dst) continue;
+    if (on_device) {
+      HIPCHK(launch_copy2d(it.src, bo.k, bo.out_dt, it.dst, it.ldd, dtype, it.rows, bo.k, st));
+    } else {
+      void *tmp = nullptr;
+      HIPCHK(hipMalloc(&tmp, es * (size_t)it.rows * bo.k + 16));
+      hipError_t e = launch_copy2d(it.src, bo.k, bo.out_dt, tmp, bo.k, dtype, it.rows, bo.k, st);
+      if (e == hipSuccess)
+        e = hipMemcpy2DAsync(it.dst, es * it.ldd, tmp, es * bo.k, es * bo.k, it.rows, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      (void)hipFree(tmp);
+      HIPCHK(e);
+    }
+  }
+  if (S)
+    HIPCHK(hipMemcpyAsync(S, bo.S + (size_t)bo.l * idx, 8 * (size_t)bo.k,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return DASHSVD_OK;
+}
+
+dashsvd_status dashsvd_get_info_batched(dashsvd_handle *h, int32_t idx, dashsvd_info *out) {
+  if (!h || !out) return DASHSVD_ERR_INVALID_ARG;
+  auto &bo = h->bat;
+  if (!bo.have) return fail(h, DASHSVD_ERR_STATE, "no batched results: run_batched first");
+  if (idx < 0) {
+    *out = bo.info;
+    return DASHSVD_OK;
+  }
+  if (idx >= bo.count) return fail(h, DASHSVD_ERR_INVALID_ARG, "matrix index");
+  hipStream_t st = h->stg;
+  SolverState s;
+  HIPCHK(hipMemcpyAsync(&s, bo.state + idx, sizeof(s), hipMemcpyDeviceToHost, st));
+  std::memset(out, 0, sizeof(*out));
+  const int ntr = bo.cap < DASHSVD_MAX_TRACE ? bo.cap : DASHSVD_MAX_TRACE;
+  HIPCHK(hipMemcpyAsync(out->alpha_used, bo.tr_alpha + (size_t)bo.cap * idx, 8 * (size_t)ntr,
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(out->ratio, bo.tr_ratio + (size_t)bo.cap * idx, 8 * (size_t)ntr, hipMemcpyDeviceToHost,
+                        st));
+  const int nsw = bo.cap + 2 < DASHSVD_MAX_TRACE + 2 ? bo.cap + 2 : DASHSVD_MAX_TRACE + 2;
+  HIPCHK(hipMemcpyAsync(out->sweeps_per_call, bo.tr_sweeps + (size_t)(bo.cap + 2) * idx, 4 * (size_t)nsw,
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  out->passes = s.pass;
+  out->converged = s.converged;
+  out->rank_deficient = s.deficient;
+  out->l = bo.l;
+  out->final_alpha = s.alpha;
+  out->eig_calls = s.eig_calls;
+  out->eig_sweeps = s.eig_sweeps;
+  out->status = bo.info.status;
   return DASHSVD_OK;
 }
 

@@ -27,8 +27,6 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-template <typename T> __device__ __forceinline__ double to_d(T v) { return (double)v; }
-template <> __device__ __forceinline__ double to_d<bf16>(bf16 v) { return (double)bf2f(v); }
 
 // ------------------------------------------------------------------ Gram
 constexpr int kGramRows = 32;

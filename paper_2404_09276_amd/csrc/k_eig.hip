@@ -26,12 +26,15 @@
 // index, descending), W = V diag(1/S) with columns zeroed where S <=
 // S_max sqrt(l eps), then for a power pass the PVE ratio of eq. (19) with the
 // surrogate E = S + alpha (Prop. 3) and the shift rule.
+#include <cstring>
+
 #include "common.h"
 
 namespace dsv {
 
 namespace {
 
+constexpr int kEigThreadsS = 256;      // threads up to L = 32
 constexpr int kEigThreads = 1024;      // threads up to L = 128
 constexpr int kEigThreadsL = 512;      // threads above
 constexpr int kMaxLP = 160;           // padded size L (multiple of 4)
@@ -106,8 +109,10 @@ struct IC {
 // loads are issued together; CPL: consecutive V columns per lane (4 up to
 // L = 128, 8 above, where L is then a multiple of 8); NT: threads (1024, or
 // 512 for the largest sizes, so that 2 waves per SIMD leave room for V)
-template <int MAXNR, int MAXIT, int BATCH, int CPL, int NT>
-__global__ __launch_bounds__(NT) void k_eig(EigArgs a) {
+// BATCHED: workgroup b solves arr[b] (a0 unused); else a0.
+template <int MAXNR, int MAXIT, int BATCH, int CPL, int NT, bool BATCHED>
+__global__ __launch_bounds__(NT) void k_eig(EigArgs a0, const EigArgs *__restrict__ arr) {
+  const EigArgs &a = BATCHED ? arr[blockIdx.x] : a0;
   SolverState *state = a.state;
   if (state && a.mode == 2) {
     // a pass launched after the check already passed: nothing to do, and
@@ -548,6 +553,7 @@ __global__ __launch_bounds__(NT) void k_eig(EigArgs a) {
     if (s_stop) {
       state->done = 1;
       state->converged = 1;
+      if (a.ndone) atomicAdd(a.ndone, 1);
     } else {
       double na = alpha;
       const double Sl = Ssh[l - 1];
@@ -581,48 +587,79 @@ __global__ __launch_bounds__(NT) void k_eig(EigArgs a) {
 
 }  // namespace
 
-hipError_t launch_eig(const EigArgs &a, hipStream_t st) {
-  if (a.l < 1 || a.l > kMaxLP) return hipErrorInvalidValue;
-  // the layout rules of the kernel, mirrored: CPL columns of V per lane,
-  // L = l padded to a multiple of CPL, NT threads
-  const int L4 = (a.l + 3) & ~3;
+// Kernel variant, block size and dynamic LDS for size l (the layout rules of
+// the kernel, mirrored): CPL columns of V per lane, L = l padded to a
+// multiple of CPL, NT threads.
+template <bool B>
+static hipError_t pick_eig(int l, void (**fn)(EigArgs, const EigArgs *), int *nt, size_t *shm) {
+  if (l < 1 || l > kMaxLP) return hipErrorInvalidValue;
+  const int L4 = (l + 3) & ~3;
   const int CPL = L4 > 128 ? 8 : 4;
-  const int NT = CPL == 8 ? kEigThreadsL : kEigThreads;
-  const int L = CPL == 8 ? (a.l + 7) & ~7 : L4;
+  const int NT = CPL == 8 ? kEigThreadsL : (L4 <= 32 ? kEigThreadsS : kEigThreads);
+  const int L = CPL == 8 ? (l + 7) & ~7 : L4;
   const int P = L / 2;
   const int LPR = L / CPL, RPW = kWave / LPR;
   const int NR = (L + (NT / kWave) * RPW - 1) / ((NT / kWave) * RPW);
   const int IT = ((P + 1) * (P + 2) / 2 + NT - 1) / NT;  // odd parity has more
-  size_t shm = sizeof(double) * (size_t)(L * (L + 1) / 2 + 2);
-  if (CPL == 8) shm += (size_t)2 * kMaxItems * NT * (sizeof(uint32_t) + sizeof(uint16_t));
-  void (*fn)(EigArgs) = nullptr;
-  if (CPL == 4 && NR <= 1 && IT <= 1)
-    fn = k_eig<1, 1, 1, 4, kEigThreads>;
-  else if (CPL == 4 && NR <= 2 && IT <= 2)
-    fn = k_eig<2, 2, 2, 4, kEigThreads>;
-  else if (CPL == 4 && NR <= 4 && IT <= 2)
-    fn = k_eig<4, 2, 2, 4, kEigThreads>;
-  else if (CPL == 4 && NR <= 4 && IT <= 3)
-    fn = k_eig<4, 3, 1, 4, kEigThreads>;
+  size_t s = sizeof(double) * (size_t)(L * (L + 1) / 2 + 2);
+  if (CPL == 8) s += (size_t)2 * kMaxItems * NT * (sizeof(uint32_t) + sizeof(uint16_t));
+  void (*f)(EigArgs, const EigArgs *) = nullptr;
+  if (NT == kEigThreadsS && NR <= 1 && IT <= 1)
+    f = k_eig<1, 1, 1, 4, kEigThreadsS, B>;
+  else if (CPL == 4 && NT == kEigThreads && NR <= 1 && IT <= 1)
+    f = k_eig<1, 1, 1, 4, kEigThreads, B>;
+  else if (CPL == 4 && NT == kEigThreads && NR <= 2 && IT <= 2)
+    f = k_eig<2, 2, 2, 4, kEigThreads, B>;
+  else if (CPL == 4 && NT == kEigThreads && NR <= 4 && IT <= 2)
+    f = k_eig<4, 2, 2, 4, kEigThreads, B>;
+  else if (CPL == 4 && NT == kEigThreads && NR <= 4 && IT <= 3)
+    f = k_eig<4, 3, 1, 4, kEigThreads, B>;
   else if (CPL == 8 && NR <= 7 && IT <= kMaxItems)
-    fn = k_eig<7, kMaxItems, 1, 8, kEigThreadsL>;
+    f = k_eig<7, kMaxItems, 1, 8, kEigThreadsL, B>;
   else
     return hipErrorInvalidValue;
   static bool attr = false;
   if (!attr) {
-    hipFuncSetAttribute((const void *)k_eig<1, 1, 1, 4, kEigThreads>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipFuncSetAttribute((const void *)k_eig<1, 1, 1, 4, kEigThreadsS, B>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+    hipFuncSetAttribute((const void *)k_eig<1, 1, 1, 4, kEigThreads, B>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         128 * 1024);
-    hipFuncSetAttribute((const void *)k_eig<2, 2, 2, 4, kEigThreads>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipFuncSetAttribute((const void *)k_eig<2, 2, 2, 4, kEigThreads, B>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         128 * 1024);
-    hipFuncSetAttribute((const void *)k_eig<4, 2, 2, 4, kEigThreads>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipFuncSetAttribute((const void *)k_eig<4, 2, 2, 4, kEigThreads, B>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         128 * 1024);
-    hipFuncSetAttribute((const void *)k_eig<4, 3, 1, 4, kEigThreads>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipFuncSetAttribute((const void *)k_eig<4, 3, 1, 4, kEigThreads, B>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         128 * 1024);
-    hipFuncSetAttribute((const void *)k_eig<7, kMaxItems, 1, 8, kEigThreadsL>,
+    hipFuncSetAttribute((const void *)k_eig<7, kMaxItems, 1, 8, kEigThreadsL, B>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, 152 * 1024);
     attr = true;
   }
-  hipLaunchKernelGGL(fn, dim3(1), dim3(NT), shm, st, a);
+  *fn = f;
+  *nt = NT;
+  *shm = s;
+  return hipSuccess;
+}
+
+hipError_t launch_eig(const EigArgs &a, hipStream_t st) {
+  void (*fn)(EigArgs, const EigArgs *) = nullptr;
+  int nt = 0;
+  size_t shm = 0;
+  hipError_t e = pick_eig<false>(a.l, &fn, &nt, &shm);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, dim3(1), dim3(nt), shm, st, a, (const EigArgs *)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_eig_batched(const EigArgs *arr, int count, int l, hipStream_t st) {
+  if (count < 1) return hipSuccess;
+  void (*fn)(EigArgs, const EigArgs *) = nullptr;
+  int nt = 0;
+  size_t shm = 0;
+  hipError_t e = pick_eig<true>(l, &fn, &nt, &shm);
+  if (e != hipSuccess) return e;
+  EigArgs none;
+  std::memset(&none, 0, sizeof(none));
+  hipLaunchKernelGGL(fn, dim3((unsigned)count), dim3(nt), shm, st, none, arr);
   return hipGetLastError();
 }
 

@@ -40,7 +40,8 @@ __global__ __launch_bounds__(256) void k_spmm(
     const TV *__restrict__ val, const TX *__restrict__ X, int64_t ldx, TY *__restrict__ Y,
     int64_t ldy, int G, int64_t n_chunks, const ChunkTask *__restrict__ tasks,
     TA *__restrict__ partial, int64_t ldp, int32_t long_row, const TX *__restrict__ Q, int64_t ldq,
-    const double *__restrict__ alpha, const int32_t *__restrict__ done) {
+    const double *__restrict__ alpha, const int32_t *__restrict__ done,
+    const int32_t *__restrict__ rowmat, const SolverState *__restrict__ bstate) {
   if (done && *done) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rpw = kWave / G;
@@ -48,6 +49,7 @@ __global__ __launch_bounds__(256) void k_spmm(
   if (sub >= rpw) return;
   const int64_t g = ((int64_t)blockIdx.x * 4 + wave) * rpw + sub;
   int64_t b, e, row = -1;
+  const double *alpha_row = alpha;
   if (g < n_chunks) {
     const ChunkTask t = tasks[g];
     b = t.begin;
@@ -58,6 +60,13 @@ __global__ __launch_bounds__(256) void k_spmm(
     b = rp[row];
     e = rp[row + 1];
     if (e - b > long_row) return;  // handled by its chunks
+    if (rowmat) {
+      // batched operator: the row's matrix may have stopped before this
+      // pass (pass-start snapshot); its own shift
+      const SolverState &ms = bstate[rowmat[row]];
+      if (ms.pass_skip) return;
+      alpha_row = &ms.alpha;
+    }
   }
   TA acc[V];
 #pragma unroll
@@ -108,7 +117,7 @@ __global__ __launch_bounds__(256) void k_spmm(
     return;
   }
   if constexpr (SHIFT) {
-    const TA a = (TA)(*alpha);
+    const TA a = (TA)(*alpha_row);
     TA q[V];
     load_n<TX, TA, V>(Q + row * ldq + cl * V, q);
 #pragma unroll
@@ -121,7 +130,8 @@ template <typename TX, typename TY, typename TA, bool SHIFT, int V>
 __global__ __launch_bounds__(256) void k_spmm_long(
     int64_t n_long, const LongRow *__restrict__ longs, const TA *__restrict__ partial, int64_t ldp,
     TY *__restrict__ Y, int64_t ldy, int G, const TX *__restrict__ Q, int64_t ldq,
-    const double *__restrict__ alpha, const int32_t *__restrict__ done) {
+    const double *__restrict__ alpha, const int32_t *__restrict__ done,
+    const int32_t *__restrict__ rowmat, const SolverState *__restrict__ bstate) {
   if (done && *done) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rpw = kWave / G;
@@ -130,6 +140,12 @@ __global__ __launch_bounds__(256) void k_spmm_long(
   const int64_t g = ((int64_t)blockIdx.x * 4 + wave) * rpw + sub;
   if (g >= n_long) return;
   const LongRow lr = longs[g];
+  const double *alpha_row = alpha;
+  if (rowmat) {
+    const SolverState &ms = bstate[rowmat[lr.row]];
+    if (ms.pass_skip) return;
+    alpha_row = &ms.alpha;
+  }
   TA acc[V];
 #pragma unroll
   for (int i = 0; i < V; ++i) acc[i] = (TA)0;
@@ -152,7 +168,7 @@ __global__ __launch_bounds__(256) void k_spmm_long(
     for (int i = 0; i < V; ++i) acc[i] += p[i];
   }
   if constexpr (SHIFT) {
-    const TA a = (TA)(*alpha);
+    const TA a = (TA)(*alpha_row);
     TA q[V];
     load_n<TX, TA, V>(Q + lr.row * ldq + cl * V, q);
 #pragma unroll
@@ -166,7 +182,8 @@ hipError_t run_spmm_v(int64_t R, const int64_t *rp, const int32_t *col, const vo
                       int64_t ldx, void *Y, int64_t ldy, int ld_cols, int64_t n_chunks,
                       const ChunkTask *tasks, int64_t n_long, const LongRow *longs, void *partial,
                       int32_t long_row, const void *Q, int64_t ldq, const double *alpha,
-                      const int32_t *done, hipStream_t st) {
+                      const int32_t *done, const int32_t *rowmat, const SolverState *bstate,
+                      hipStream_t st) {
   using TA = typename acc_of<TX>::type;
   const int G = ld_cols / V;
   if (G < 1 || G > kWave || ld_cols % V) return hipErrorInvalidValue;
@@ -178,22 +195,24 @@ hipError_t run_spmm_v(int64_t R, const int64_t *rp, const int32_t *col, const vo
     if (shift)
       hipLaunchKernelGGL((k_spmm<TV, TX, TY, TA, true, V>), dim3((unsigned)blocks), dim3(256), 0, st, R, rp,
                          col, (const TV *)val, (const TX *)X, ldx, (TY *)Y, ldy, G, n_chunks, tasks,
-                         (TA *)partial, (int64_t)ld_cols, long_row, (const TX *)Q, ldq, alpha, done);
+                         (TA *)partial, (int64_t)ld_cols, long_row, (const TX *)Q, ldq, alpha, done,
+                         rowmat, bstate);
     else
       hipLaunchKernelGGL((k_spmm<TV, TX, TY, TA, false, V>), dim3((unsigned)blocks), dim3(256), 0, st, R, rp,
                          col, (const TV *)val, (const TX *)X, ldx, (TY *)Y, ldy, G, n_chunks, tasks,
-                         (TA *)partial, (int64_t)ld_cols, long_row, (const TX *)Q, ldq, alpha, done);
+                         (TA *)partial, (int64_t)ld_cols, long_row, (const TX *)Q, ldq, alpha, done,
+                         rowmat, bstate);
   }
   if (n_long > 0) {
     const int64_t lb = (n_long + 4 * rpw - 1) / (4 * rpw);
     if (shift)
       hipLaunchKernelGGL((k_spmm_long<TX, TY, TA, true, V>), dim3((unsigned)lb), dim3(256), 0, st, n_long,
                          longs, (const TA *)partial, (int64_t)ld_cols, (TY *)Y, ldy, G, (const TX *)Q, ldq,
-                         alpha, done);
+                         alpha, done, rowmat, bstate);
     else
       hipLaunchKernelGGL((k_spmm_long<TX, TY, TA, false, V>), dim3((unsigned)lb), dim3(256), 0, st, n_long,
                          longs, (const TA *)partial, (int64_t)ld_cols, (TY *)Y, ldy, G, (const TX *)Q, ldq,
-                         alpha, done);
+                         alpha, done, rowmat, bstate);
   }
   return hipGetLastError();
 }
@@ -205,14 +224,15 @@ hipError_t run_spmm(int64_t R, const int64_t *rp, const int32_t *col, const void
                     int64_t ldx, void *Y, int64_t ldy, int ld_cols, int64_t n_chunks,
                     const ChunkTask *tasks, int64_t n_long, const LongRow *longs, void *partial,
                     int32_t long_row, const void *Q, int64_t ldq, const double *alpha,
-                    const int32_t *done, hipStream_t st) {
+                    const int32_t *done, const int32_t *rowmat, const SolverState *bstate,
+                    hipStream_t st) {
   using TA = typename acc_of<TX>::type;
   constexpr int V = vec16<TX, TA>::N;
   if (ld_cols / V <= kWave)
     return run_spmm_v<TV, TX, TY, V>(R, rp, col, val, X, ldx, Y, ldy, ld_cols, n_chunks, tasks, n_long, longs,
-                                     partial, long_row, Q, ldq, alpha, done, st);
+                                     partial, long_row, Q, ldq, alpha, done, rowmat, bstate, st);
   return run_spmm_v<TV, TX, TY, 2 * V>(R, rp, col, val, X, ldx, Y, ldy, ld_cols, n_chunks, tasks, n_long,
-                                       longs, partial, long_row, Q, ldq, alpha, done, st);
+                                       longs, partial, long_row, Q, ldq, alpha, done, rowmat, bstate, st);
 }
 
 }  // namespace
@@ -221,21 +241,22 @@ hipError_t launch_spmm(int64_t R, const int64_t *rp, const int32_t *col, const v
                        const void *X, int64_t ldx, int xdtype, void *Y, int64_t ldy, int ydtype,
                        int ld_cols, int64_t n_chunks, const ChunkTask *tasks, int64_t n_long,
                        const LongRow *longs, void *partial, int32_t long_row, const void *Q,
-                       int64_t ldq, const double *alpha, const int32_t *done, hipStream_t st) {
+                       int64_t ldq, const double *alpha, const int32_t *done, hipStream_t st,
+                       const int32_t *rowmat, const SolverState *bstate) {
   // supported combinations: (values, X/Q, Y) = (f32, f32, f32), (f64, f64, f64),
   // (f32, bf16, bf16), (f32, bf16, f32)
   if (xdtype == 0 && ydtype == 0 && vdtype == 0)
     return run_spmm<float, float, float>(R, rp, col, val, X, ldx, Y, ldy, ld_cols, n_chunks, tasks, n_long,
-                                         longs, partial, long_row, Q, ldq, alpha, done, st);
+                                         longs, partial, long_row, Q, ldq, alpha, done, rowmat, bstate, st);
   if (xdtype == 1 && ydtype == 1 && vdtype == 1)
     return run_spmm<double, double, double>(R, rp, col, val, X, ldx, Y, ldy, ld_cols, n_chunks, tasks,
-                                            n_long, longs, partial, long_row, Q, ldq, alpha, done, st);
+                                            n_long, longs, partial, long_row, Q, ldq, alpha, done, rowmat, bstate, st);
   if (xdtype == 2 && ydtype == 2 && vdtype == 0)
     return run_spmm<float, bf16, bf16>(R, rp, col, val, X, ldx, Y, ldy, ld_cols, n_chunks, tasks, n_long,
-                                       longs, partial, long_row, Q, ldq, alpha, done, st);
+                                       longs, partial, long_row, Q, ldq, alpha, done, rowmat, bstate, st);
   if (xdtype == 2 && ydtype == 0 && vdtype == 0)
     return run_spmm<float, bf16, float>(R, rp, col, val, X, ldx, Y, ldy, ld_cols, n_chunks, tasks, n_long,
-                                        longs, partial, long_row, Q, ldq, alpha, done, st);
+                                        longs, partial, long_row, Q, ldq, alpha, done, rowmat, bstate, st);
   return hipErrorInvalidValue;
 }
 

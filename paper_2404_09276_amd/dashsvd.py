@@ -65,7 +65,8 @@ _lib = None
 
 EXPORTS = [
     "dashsvd_create", "dashsvd_destroy", "dashsvd_set_options", "dashsvd_run", "dashsvd_get_USV",
-    "dashsvd_get_info", "dashsvd_get_trace", "dashsvd_evaluate", "dashsvd_workspace_size",
+    "dashsvd_get_info", "dashsvd_get_trace", "dashsvd_evaluate", "dashsvd_run_batched",
+    "dashsvd_get_USV_batched", "dashsvd_get_info_batched", "dashsvd_workspace_size",
     "dashsvd_status_string",
     "dashsvd_last_error", "dashsvd_k_gaussian", "dashsvd_k_philox_raw", "dashsvd_k_transpose",
     "dashsvd_k_spmm", "dashsvd_k_gram", "dashsvd_k_eig", "dashsvd_k_eig_prof", "dashsvd_k_rescale",
@@ -90,6 +91,9 @@ def lib():
         L.dashsvd_get_info.argtypes = [P, C.POINTER(_Info)]
         L.dashsvd_get_trace.argtypes = [P, P, i32]
         L.dashsvd_evaluate.argtypes = [P, C.POINTER(_Csr), P, i32, P, P]
+        L.dashsvd_run_batched.argtypes = [P, C.POINTER(_Csr), i32, i32, i32, f64]
+        L.dashsvd_get_USV_batched.argtypes = [P, i32, P, i64, P, P, i64, i32, i32]
+        L.dashsvd_get_info_batched.argtypes = [P, i32, C.POINTER(_Info)]
         L.dashsvd_workspace_size.argtypes = [C.POINTER(_Csr), i32, i32, i32, C.POINTER(C.c_size_t)]
         L.dashsvd_status_string.argtypes = [i32]
         L.dashsvd_status_string.restype = C.c_char_p
@@ -287,16 +291,40 @@ class DashSVD:
     def info(self) -> Info:
         raw = _Info()
         _check(lib().dashsvd_get_info(self._h, C.byref(raw)), self._h)
-        npass = raw.passes
-        return Info(raw.passes, bool(raw.converged), bool(raw.rank_deficient), raw.status, raw.l,
-                    bool(raw.learned_fallback), raw.final_alpha,
-                    np.array(raw.alpha_used[:min(npass, MAX_TRACE)]),
-                    np.array(raw.ratio[:min(npass, MAX_TRACE)]), raw.time_total_ms,
-                    raw.time_setup_ms, raw.time_loop_ms, raw.time_final_ms, raw.long_chunks_A,
-                    raw.long_chunks_AT, dict(zip(KT_NAMES, list(raw.kt_ms))),
-                    dict(zip(KT_NAMES, list(raw.kt_count))), raw.eig_calls, raw.eig_sweeps,
-                    np.array(raw.sweeps_per_call[:min(raw.eig_calls, MAX_TRACE + 2)]),
-                    bool(raw.promoted))
+        return _info_from(raw)
+
+    # ------------------------------------------------------------ batched form
+    def run_batched(self, mats, k: int, p: int, tol: float) -> int:
+        """dashsvd_run_batched over a list of matrices (objects with m, n,
+        row_ptr, col, val; all numpy or all device tensors)."""
+        structs, keeps = [], []
+        for A in mats:
+            s, keep = make_csr(A.m, A.n, A.row_ptr, A.col, A.val)
+            structs.append(s)
+            keeps.append(keep)
+        arr = (_Csr * len(structs))(*structs)
+        self._bdims = [(A.m, A.n) for A in mats]
+        self._bk = k
+        st = lib().dashsvd_run_batched(self._h, arr, len(structs), k, p, float(tol))
+        del keeps
+        return _check(st, self._h)
+
+    def get_usv_batched(self, idx: int, dtype: str = "float64"):
+        """dashsvd_get_USV_batched (host arrays): U, S, V of matrix idx."""
+        m, n = self._bdims[idx]
+        k = self._bk
+        code = F64 if dtype == "float64" else F32
+        nd = np.float64 if code == F64 else np.float32
+        U, V, S = np.empty((m, k), dtype=nd), np.empty((n, k), dtype=nd), np.empty(k, dtype=np.float64)
+        _check(lib().dashsvd_get_USV_batched(self._h, idx, _ptr(U), k, _ptr(S), _ptr(V), k, code, 0), self._h)
+        return U, S, V
+
+    def info_batched(self, idx: int) -> Info:
+        """dashsvd_get_info_batched: matrix idx, or the batch summary for idx < 0."""
+        raw = _Info()
+        _check(lib().dashsvd_get_info_batched(self._h, idx, C.byref(raw)), self._h)
+        return _info_from(raw)
+
 
     def trace(self) -> np.ndarray:
         """Per-pass S (passes x l) of the last run (dashsvd_get_trace)."""
@@ -374,3 +402,16 @@ def k_rescale(Cm, l, W, c, Out, stream=None):
     _check(lib().dashsvd_k_rescale(Cm.shape[0], l, _ptr(Cm), Cm.stride(0), _dtype_code(Cm), _ptr(W),
                                    W.stride(0), c, _ptr(Out), Out.stride(0), _dtype_code(Out),
                                    _stream_ptr(stream)))
+
+
+def _info_from(raw) -> Info:
+    npass = raw.passes
+    return Info(raw.passes, bool(raw.converged), bool(raw.rank_deficient), raw.status, raw.l,
+                bool(raw.learned_fallback), raw.final_alpha,
+                np.array(raw.alpha_used[:min(npass, MAX_TRACE)]),
+                np.array(raw.ratio[:min(npass, MAX_TRACE)]), raw.time_total_ms,
+                raw.time_setup_ms, raw.time_loop_ms, raw.time_final_ms, raw.long_chunks_A,
+                raw.long_chunks_AT, dict(zip(KT_NAMES, list(raw.kt_ms))),
+                dict(zip(KT_NAMES, list(raw.kt_count))), raw.eig_calls, raw.eig_sweeps,
+                np.array(raw.sweeps_per_call[:min(raw.eig_calls, MAX_TRACE + 2)]),
+                bool(raw.promoted))

@@ -1,0 +1,150 @@
+"""Batched form (dashsvd_run_batched): every matrix of the batch must give
+what Alg. 5 gives on it alone.  Matrix i draws Omega from the Philox stream
+keyed (seed + i, 0), so the oracle (and the single-matrix library path) can
+reproduce each member; the batch mixes sizes, power-law and uniform
+structure, long rows and ragged tails."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch
+
+
+def _batch(dtype=np.float64):
+    mats = [
+        synth.uniform_csr(700, 500, 9000, seed=51, dtype=dtype),
+        synth.zipf_csr(3000, 1200, 40000, seed=52),
+        synth.uniform_csr(129, 64, 2000, seed=53, dtype=dtype),
+        synth.zipf_csr(1500, 1500, 30000, seed=54),
+        synth.uniform_csr(2049, 333, 12000, seed=55, dtype=dtype),
+        synth.zipf_csr(900, 450, 20000, seed=56),
+    ]
+    for A in mats:
+        A.val = A.val.astype(dtype)
+    return mats
+
+
+def _vec_close(X, Xref, tol):
+    d = np.minimum(np.abs(X - Xref).max(axis=0), np.abs(X + Xref).max(axis=0))
+    return d.max() <= tol
+
+
+def _run(mats, k, s, pmax, tol, seed, precision, **kw):
+    from paper_2404_09276_amd import DashSVD
+    h = DashSVD(precision=precision, p_max=pmax, seed=seed, **kw)
+    st = h.run_batched(mats, k, s, tol)
+    out = [(h.get_usv_batched(i), h.info_batched(i)) for i in range(len(mats))]
+    summary = h.info_batched(-1)
+    h.close()
+    return st, out, summary
+
+
+def test_batched_fp64_matches_oracle_per_matrix(torch_dev):
+    mats = _batch(np.float64)
+    st, out, summary = _run(mats, 8, 4, 4, 0.0, 300, "fp64")
+    assert st == 0 and summary.passes == 4
+    for i, A in enumerate(mats):
+        (U, S, V), info = out[i]
+        ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 8, 4, 4, 0.0, seed=300 + i)
+        assert info.passes == 4
+        assert np.abs(S - ref.S).max() / ref.S.max() <= 1e-10, i
+        assert np.allclose(info.alpha_used, ref.alpha, rtol=1e-10, atol=0), i
+        assert _vec_close(U, ref.U, 1e-8) and _vec_close(V, ref.V, 1e-8), i
+
+
+@pytest.mark.parametrize("mode", ["r2", "r1"])
+def test_batched_tolerance_each_matrix_stops_at_its_own_pass(torch_dev, mode):
+    mats = _batch(np.float64)
+    pm = oracle.PVE_R1 if mode == "r1" else oracle.PVE_R2
+    st, out, summary = _run(mats, 8, 4, 30, 1e-3, 400, "fp64", pve_mode=mode)
+    assert st == 0 and summary.converged
+    passes = []
+    for i, A in enumerate(mats):
+        (U, S, V), info = out[i]
+        ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 8, 4, 30, 1e-3, seed=400 + i, pve_mode=pm)
+        borderline = np.any(np.abs(ref.ratio - 1e-3) < 1e-6 * 1e-3)
+        if not borderline:
+            assert info.passes == ref.passes, i
+            assert np.allclose(info.ratio, ref.ratio, rtol=1e-8, atol=0), i
+        assert np.abs(S - ref.S).max() / ref.S.max() <= 1e-10, i
+        passes.append(info.passes)
+    assert summary.passes == max(passes)
+
+
+def test_batched_fp32_matches_single_matrix_runs(torch_dev):
+    """Members of an FP32 batch against dashsvd_run on each matrix alone with
+    the same Omega stream (same algorithm, different kernels for the small
+    dense steps)."""
+    from paper_2404_09276_amd import DashSVD
+    mats = _batch(np.float32)
+    st, out, summary = _run(mats, 10, 6, 40, 1e-2, 500, "fp32")
+    assert st == 0
+    for i, A in enumerate(mats):
+        (U, S, V), info = out[i]
+        h = DashSVD(precision="fp32", p_max=40, seed=500 + i)
+        U1, S1, V1, st1, info1 = h.solve(A, 10, 6, 1e-2)
+        h.close()
+        assert info.passes == info1.passes, i
+        assert np.all(np.abs(S - S1) / S1 <= 1e-5), i
+        assert np.abs(U.T @ U - np.eye(10)).max() < 1e-5
+
+
+def test_batched_bf16_power_law_batch(torch_dev):
+    """A batch shaped like the paper-scale batched workload (rows 1k-10k,
+    columns 0.5-1 x rows, density 0.05-1 %, Zipf 1.1 degrees), k = 16,
+    oversampling 8, BF16 panels, tol 1e-2: every member converges and meets
+    the output identity A V = U diag(S) of the final Rayleigh-Ritz step."""
+    mats = synth.batched_zipf(24, rows=(1000, 10000), seed=5000)
+    st, out, summary = _run(mats, 16, 8, 16, 1e-2, 700, "bf16")
+    assert st == 0 and summary.converged
+    for i, A in enumerate(mats):
+        (U, S, V), info = out[i]
+        assert info.converged and 2 <= info.passes <= 16
+        AV = oracle.csr_spmm(A.row_ptr, A.col, A.val, V)
+        err = np.abs(AV - U * S[None, :]).max(axis=0) / S
+        assert err.max() <= 5e-3, (i, err.max())
+        assert np.all(np.diff(S) <= 0)
+
+
+def test_batched_graph_replays_match_eager_fixed_passes(torch_dev):
+    """p_max passes run as p_max replays of one captured pass: results after 1,
+    2 and 5 replays each match the oracle at that pass count."""
+    mats = _batch(np.float64)[:3]
+    for p in (1, 2, 5):
+        st, out, summary = _run(mats, 8, 4, p, 0.0, 900, "fp64")
+        for i, A in enumerate(mats):
+            (U, S, V), info = out[i]
+            ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 8, 4, p, 0.0, seed=900 + i)
+            assert np.abs(S - ref.S).max() / ref.S.max() <= 1e-10, (p, i)
+
+
+def test_batched_errors(torch_dev):
+    from paper_2404_09276_amd import DashSVD, DashSVDError
+    mats = _batch(np.float64)
+    h = DashSVD(precision="fp64", p_max=3)
+    wide = synth.uniform_csr(300, 700, 5000, seed=3, dtype=np.float64)
+    with pytest.raises(DashSVDError) as e:
+        h.run_batched(mats[:2] + [wide], 8, 4, 0.0)
+    assert e.value.status == -1
+    with pytest.raises(DashSVDError) as e:
+        h.run_batched(mats[:2], 40, 30, 0.0)
+    assert e.value.status == -1
+    bad = synth.CSR(mats[0].m, mats[0].n, mats[0].row_ptr, mats[0].col.copy(), mats[0].val)
+    bad.col[5] = mats[0].n  # inside the stacked column range, outside its own
+    with pytest.raises(DashSVDError) as e:
+        h.run_batched([mats[1], bad], 8, 4, 0.0)
+    assert e.value.status == -2
+    # still usable
+    assert h.run_batched(mats[:2], 8, 4, 0.0) == 0
+    h.close()
