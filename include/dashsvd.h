@@ -115,6 +115,10 @@ typedef struct {
   int32_t omega_on_device;
   int32_t timing;         /* 1: time each kernel group with HIP events on the stream
                              (results in dashsvd_info.kt_ms / kt_count) */
+  const char *tuning_db;  /* optional path of a tuning database written by dashsvd_autotune;
+                             runs with long_row <= 0 take the SpMM chunk length stored for
+                             their shape bucket (else the built-in default).  Read when the
+                             options are set. */
 } dashsvd_options;
 
 /* Kernel groups timed when options.timing = 1 (index into kt_ms / kt_count). */
@@ -150,6 +154,7 @@ typedef struct {
   int32_t eig_sweeps;      /* Jacobi sweeps summed over them */
   int32_t sweeps_per_call[DASHSVD_MAX_TRACE + 2]; /* sweeps of eigSVD call c: the sketch (c = 0),
                                                      the passes, then the final step */
+  int32_t long_row_used;   /* SpMM chunk length of the run (option, tuning database or default) */
   int32_t promoted;        /* BF16 panels: 1 if the stagnation guard switched the remaining
                               passes to FP32 panels (the PVE ratio stayed above tol and above
                               0.8 x its previous value for two passes) */
@@ -223,6 +228,19 @@ dashsvd_status dashsvd_get_USV_batched(dashsvd_handle *h, int32_t idx, void *U, 
  * ratio traces, sweeps); idx < 0 gives the batch summary (maximum passes,
  * all converged, total eig calls and sweeps, wall time). */
 dashsvd_status dashsvd_get_info_batched(dashsvd_handle *h, int32_t idx, dashsvd_info *out);
+
+/* Autotuner of the SpMM work split: times short runs (2 passes, tol 0) of
+ * the given matrix (count == 1, dashsvd_run) or batch (count > 1,
+ * dashsvd_run_batched) for each candidate long-row chunk length
+ * (32 ... 1024 nonzeros), keeps the fastest by the SpMM kernel time (single
+ * matrix) or the pass-loop time (batch), appends "key chunk_length" to the
+ * text file db_path (if not NULL) and to the handle's table, and returns it
+ * in *best.  The key is the shape bucket: precision, l rounded up to 8,
+ * log2 of the rows and of the mean nonzeros per row of the operator, and
+ * the form (single / batched).  The handle's other options are used and
+ * left unchanged; the results of the tuning runs are discarded. */
+dashsvd_status dashsvd_autotune(dashsvd_handle *h, const dashsvd_csr *As, int32_t count, int32_t k,
+                                int32_t p, const char *db_path, int32_t *best);
 
 /* Device bytes a run with these arguments needs (workspace of the handle). */
 dashsvd_status dashsvd_workspace_size(const dashsvd_csr *A, int32_t k, int32_t p,

@@ -118,6 +118,8 @@ struct dashsvd_handle {
     int32_t *tr_sweeps = nullptr;                     // count x (cap + 2)
     dashsvd_info info;
   } bat;
+  // SpMM chunk lengths by shape bucket (tuning database)
+  std::vector<std::pair<std::string, int>> tune;
   // internal stream of the batched form (its pass is captured as a graph)
   hipStream_t stg = nullptr;
   hipEvent_t ev_b0 = nullptr, ev_b1 = nullptr;
@@ -175,6 +177,13 @@ void default_options(dashsvd_options *o) {
   o->pve_mode = DASHSVD_PVE_R2;
   o->p_max = -1;
   o->omega_dtype = DASHSVD_F64;
+}
+
+// Shape bucket of the tuning database.
+std::string tune_key(int prec, int ld, int64_t rows, int64_t nnz, bool batched) {
+  auto lg = [](double x) { return (int)std::lround(std::log2(x > 1.0 ? x : 1.0)); };
+  return "p" + std::to_string(prec) + "_ld" + std::to_string(ld) + "_r" + std::to_string(lg((double)rows)) +
+         "_d" + std::to_string(lg((double)nnz / (double)(rows > 0 ? rows : 1))) + (batched ? "_b" : "_s");
 }
 
 double now_ms() {
@@ -294,6 +303,17 @@ dashsvd_status dashsvd_set_options(dashsvd_handle *h, const dashsvd_options *opt
     h->sched.assign(o.schedule, o.schedule + o.p_max + 1);
   }
   o.schedule = nullptr;
+  h->tune.clear();
+  if (o.tuning_db) {
+    if (FILE *f = std::fopen(o.tuning_db, "r")) {
+      char key[256];
+      int v = 0;
+      while (std::fscanf(f, "%255s %d", key, &v) == 2)
+        if (v > 0) h->tune.emplace_back(key, v);
+      std::fclose(f);
+    }
+  }
+  o.tuning_db = nullptr;
   h->opt = o;
   h->st = (hipStream_t)o.hip_stream;
   return DASHSVD_OK;
@@ -338,6 +358,15 @@ void dashsvd_destroy(dashsvd_handle *h) {
   delete h;
 }
 
+// SpMM chunk length of a run: the option, else the tuned value of the
+// bucket (last entry wins), else the default.
+static int32_t chunk_length(const dashsvd_handle *h, const std::string &key) {
+  if (h->opt.long_row > 0) return h->opt.long_row;
+  for (auto it = h->tune.rbegin(); it != h->tune.rend(); ++it)
+    if (it->first == key) return it->second;
+  return kDefaultLongRow;
+}
+
 static dashsvd_status check_args(dashsvd_handle *h, const dashsvd_csr *A, int32_t k, int32_t p, double tol) {
   if (!A) return fail(h, DASHSVD_ERR_INVALID_ARG, "null matrix");
   if (A->m < 1 || A->n < 1 || A->nnz < 0) return fail(h, DASHSVD_ERR_INVALID_ARG, "matrix dimensions");
@@ -372,7 +401,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   const int64_t Mm = wide ? n : m, Mn = wide ? m : n;
   const int l = k + p;
   const int ld = (int)round_up(l, 8);
-  const int32_t T = h->opt.long_row > 0 ? h->opt.long_row : kDefaultLongRow;
+  const int32_t T = chunk_length(h, tune_key(prec, ld, Mm, nnz, false));
   const int pmax = h->opt.p_max;
   const int cap = pmax > 0 ? pmax : 1;
   hipStream_t st = h->st;
@@ -785,6 +814,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   inf.learned_fallback = hs.sched_off;
   inf.final_alpha = hs.alpha;
   inf.promoted = promoted;
+  inf.long_row_used = T;
   inf.time_total_ms = t_end - t0;
   inf.time_setup_ms = t_setup - t0;
   inf.time_loop_ms = t_loop - t_setup;
@@ -967,7 +997,6 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
   const size_t accsz = prec == DASHSVD_PREC_FP64 ? 8 : 4;
   const int l = k + p;
   const int ld = (int)round_up(l, 8);
-  const int32_t T = h->opt.long_row > 0 ? h->opt.long_row : kDefaultLongRow;
   const int pmax = h->opt.p_max;
   const int cap = pmax > 0 ? pmax : 1;
   const int in_dt = As[0].value_dtype;
@@ -984,6 +1013,7 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
     max_n = std::max(max_n, As[b].n);
   }
   const int64_t m = roff[count], n = coff[count], nnz = zoff[count];
+  const int32_t T = chunk_length(h, tune_key(prec, ld, m, nnz, true));
   if (m > INT32_MAX - 1 || n > INT32_MAX - 1 || nnz > INT32_MAX - 1)
     return fail(h, DASHSVD_ERR_INVALID_ARG, "batch too large for 32-bit indices of the stacked operator");
   // work items of both sides (rows of M: U, B; rows of M^T: C, Q, V)
@@ -1225,6 +1255,8 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
   }
   const int every = h->opt.check_interval > 0 ? h->opt.check_interval : 1;
   int launched = 0;
+  HIPCHK(hipStreamSynchronize(st));
+  const double t_loop0 = now_ms();
   hipError_t eloop = hipSuccess;
   while (launched < pmax && eloop == hipSuccess) {
     const int chunk = (pmax - launched) < every ? (pmax - launched) : every;
@@ -1237,6 +1269,8 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
       if (nd >= count) break;
     }
   }
+  if (eloop == hipSuccess) eloop = hipStreamSynchronize(st);
+  const double t_loop1 = now_ms();
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
   HIPCHK(eloop);
@@ -1267,6 +1301,8 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
     bo.info.eig_sweeps += hs[i].eig_sweeps;
   }
   bo.info.l = l;
+  bo.info.time_loop_ms = t_loop1 - t_loop0;
+  bo.info.long_row_used = T;
   bo.have = true;
   bo.count = count;
   bo.k = k;
@@ -1328,6 +1364,68 @@ dashsvd_status dashsvd_run_batched(dashsvd_handle *h, const dashsvd_csr *As, int
   h->bat.info.time_total_ms = now_ms() - t0;
   h->bat.info.status = s;
   return s;
+}
+
+dashsvd_status dashsvd_autotune(dashsvd_handle *h, const dashsvd_csr *As, int32_t count, int32_t k, int32_t p,
+                                const char *db_path, int32_t *best) {
+  if (!h) return DASHSVD_ERR_INVALID_ARG;
+  h->err.clear();
+  if (!As || count < 1) return fail(h, DASHSVD_ERR_INVALID_ARG, "empty input");
+  const dashsvd_options saved = h->opt;
+  const std::vector<double> saved_sched = h->sched;
+  const int ld = (int)round_up(k + p, 8);
+  int64_t rows = 0, nnz = 0;
+  for (int i = 0; i < count; ++i) {
+    const bool wide = As[i].m < As[i].n;
+    rows += wide ? As[i].n : As[i].m;
+    nnz += As[i].nnz;
+  }
+  const std::string key = tune_key(saved.precision, ld, rows, nnz, count > 1);
+  static const int32_t kCand[] = {32, 64, 128, 256, 512, 1024};
+  double best_t = 0.0;
+  int32_t best_T = 0;
+  dashsvd_status s = DASHSVD_OK;
+  for (int32_t T : kCand) {
+    h->opt.long_row = T;
+    h->opt.p_max = 2;
+    h->opt.timing = count == 1 ? 1 : 0;
+    h->opt.shift_policy = saved.shift_policy == DASHSVD_SHIFT_LEARNED ? DASHSVD_SHIFT_PAPER : saved.shift_policy;
+    double t = 0.0;
+    for (int rep = 0; rep < 3 && s >= 0; ++rep) {
+      double tr = 0.0;
+      if (count == 1) {
+        s = dashsvd_run(h, As, k, p, 0.0);
+        tr = h->info.kt_ms[DASHSVD_KT_SPMM] + h->info.kt_ms[DASHSVD_KT_SPMM_T];
+      } else {
+        s = dashsvd_run_batched(h, As, count, k, p, 0.0);
+        tr = h->bat.info.time_loop_ms;
+      }
+      if (rep == 0 || tr < t) t = tr;
+    }
+    if (s < 0) break;
+    if (best_T == 0 || t < best_t) {
+      best_t = t;
+      best_T = T;
+    }
+  }
+  const std::string err = h->err;
+  h->opt = saved;
+  h->sched = saved_sched;
+  h->have = false;
+  h->bat.have = false;
+  if (s < 0) {
+    h->err = err;
+    return s;
+  }
+  h->tune.emplace_back(key, best_T);
+  if (db_path) {
+    FILE *f = std::fopen(db_path, "a");
+    if (!f) return fail(h, DASHSVD_ERR_INVALID_ARG, std::string("cannot append to ") + db_path);
+    std::fprintf(f, "%s %d\n", key.c_str(), best_T);
+    std::fclose(f);
+  }
+  if (best) *best = best_T;
+  return DASHSVD_OK;
 }
 
 dashsvd_status dashsvd_get_USV_batched(dashsvd_handle *h, int32_t idx, void *U, int64_t ldu, double *S, void *V,

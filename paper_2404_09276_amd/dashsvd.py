@@ -44,7 +44,7 @@ class _Options(C.Structure):
                 ("p_max", C.c_int32), ("seed", C.c_uint64), ("hip_stream", C.c_void_p),
                 ("long_row", C.c_int32), ("check_interval", C.c_int32), ("schedule", C.c_void_p),
                 ("omega", C.c_void_p), ("omega_dtype", C.c_int32), ("omega_on_device", C.c_int32),
-                ("timing", C.c_int32)]
+                ("timing", C.c_int32), ("tuning_db", C.c_char_p)]
 
 
 class _Info(C.Structure):
@@ -56,7 +56,8 @@ class _Info(C.Structure):
                 ("time_final_ms", C.c_double), ("long_chunks_A", C.c_int64),
                 ("long_chunks_AT", C.c_int64), ("kt_ms", C.c_double * 8), ("kt_count", C.c_int32 * 8),
                 ("eig_calls", C.c_int32), ("eig_sweeps", C.c_int32),
-                ("sweeps_per_call", C.c_int32 * (MAX_TRACE + 2)), ("promoted", C.c_int32)]
+                ("sweeps_per_call", C.c_int32 * (MAX_TRACE + 2)), ("long_row_used", C.c_int32),
+                ("promoted", C.c_int32)]
 
 KT_NAMES = ["spmm", "spmm_t", "gram", "eig", "rescale", "transpose", "sketch", "final"]
 
@@ -66,7 +67,7 @@ _lib = None
 EXPORTS = [
     "dashsvd_create", "dashsvd_destroy", "dashsvd_set_options", "dashsvd_run", "dashsvd_get_USV",
     "dashsvd_get_info", "dashsvd_get_trace", "dashsvd_evaluate", "dashsvd_run_batched",
-    "dashsvd_get_USV_batched", "dashsvd_get_info_batched", "dashsvd_workspace_size",
+    "dashsvd_get_USV_batched", "dashsvd_get_info_batched", "dashsvd_autotune", "dashsvd_workspace_size",
     "dashsvd_status_string",
     "dashsvd_last_error", "dashsvd_k_gaussian", "dashsvd_k_philox_raw", "dashsvd_k_transpose",
     "dashsvd_k_spmm", "dashsvd_k_gram", "dashsvd_k_eig", "dashsvd_k_eig_prof", "dashsvd_k_rescale",
@@ -94,6 +95,7 @@ def lib():
         L.dashsvd_run_batched.argtypes = [P, C.POINTER(_Csr), i32, i32, i32, f64]
         L.dashsvd_get_USV_batched.argtypes = [P, i32, P, i64, P, P, i64, i32, i32]
         L.dashsvd_get_info_batched.argtypes = [P, i32, C.POINTER(_Info)]
+        L.dashsvd_autotune.argtypes = [P, C.POINTER(_Csr), i32, i32, i32, C.c_char_p, C.POINTER(C.c_int32)]
         L.dashsvd_workspace_size.argtypes = [C.POINTER(_Csr), i32, i32, i32, C.POINTER(C.c_size_t)]
         L.dashsvd_status_string.argtypes = [i32]
         L.dashsvd_status_string.restype = C.c_char_p
@@ -196,6 +198,7 @@ class Info:
     eig_sweeps: int
     sweeps_per_call: np.ndarray
     promoted: bool
+    long_row_used: int
 
 
 class DashSVD:
@@ -203,17 +206,18 @@ class DashSVD:
 
     def __init__(self, precision: str = "fp32", shift_policy: str = "paper", pve_mode: str = "r2",
                  p_max: int = -1, seed: int = 0, stream=None, long_row: int = 0,
-                 check_interval: int = 1, schedule=None, omega=None, timing: bool = False):
+                 check_interval: int = 1, schedule=None, omega=None, timing: bool = False,
+                 tuning_db=None):
         self._h = C.c_void_p()
         self._keep = []
         opt = self._options(precision, shift_policy, pve_mode, p_max, seed, stream, long_row,
-                            check_interval, schedule, omega, timing)
+                            check_interval, schedule, omega, timing, tuning_db)
         st = lib().dashsvd_create(C.byref(self._h), C.byref(opt))
         _check(st, None)
 
     def _options(self, precision="fp32", shift_policy="paper", pve_mode="r2", p_max=-1, seed=0,
                  stream=None, long_row=0, check_interval=1, schedule=None, omega=None,
-                 timing=False):
+                 timing=False, tuning_db=None):
         sched_arr = None
         if schedule is not None:
             sched_arr = np.ascontiguousarray(schedule, dtype=np.float64)
@@ -228,7 +232,8 @@ class DashSVD:
         return _Options(PREC[precision], SHIFT[shift_policy], PVE[pve_mode], p_max, seed,
                         stream or None, long_row, check_interval,
                         _ptr(sched_arr).value if sched_arr is not None else None,
-                        om_ptr, om_dt, om_dev, int(bool(timing)))
+                        om_ptr, om_dt, om_dev, int(bool(timing)),
+                        tuning_db.encode() if tuning_db else None)
 
     def set_options(self, **kw):
         opt = self._options(**kw)
@@ -318,6 +323,24 @@ class DashSVD:
         U, V, S = np.empty((m, k), dtype=nd), np.empty((n, k), dtype=nd), np.empty(k, dtype=np.float64)
         _check(lib().dashsvd_get_USV_batched(self._h, idx, _ptr(U), k, _ptr(S), _ptr(V), k, code, 0), self._h)
         return U, S, V
+
+    def autotune(self, mats, k: int, p: int, db_path=None) -> int:
+        """dashsvd_autotune on one matrix (a single object) or a batch (a
+        list); returns the chosen SpMM chunk length."""
+        if not isinstance(mats, (list, tuple)):
+            mats = [mats]
+        structs, keeps = [], []
+        for A in mats:
+            s, keep = make_csr(A.m, A.n, A.row_ptr, A.col, A.val)
+            structs.append(s)
+            keeps.append(keep)
+        arr = (_Csr * len(structs))(*structs)
+        best = C.c_int32()
+        st = lib().dashsvd_autotune(self._h, arr, len(structs), k, p,
+                                    db_path.encode() if db_path else None, C.byref(best))
+        del keeps
+        _check(st, self._h)
+        return best.value
 
     def info_batched(self, idx: int) -> Info:
         """dashsvd_get_info_batched: matrix idx, or the batch summary for idx < 0."""
@@ -414,4 +437,4 @@ def _info_from(raw) -> Info:
                 raw.long_chunks_AT, dict(zip(KT_NAMES, list(raw.kt_ms))),
                 dict(zip(KT_NAMES, list(raw.kt_count))), raw.eig_calls, raw.eig_sweeps,
                 np.array(raw.sweeps_per_call[:min(raw.eig_calls, MAX_TRACE + 2)]),
-                bool(raw.promoted))
+                bool(raw.promoted), raw.long_row_used)

@@ -148,3 +148,33 @@ def test_batched_errors(torch_dev):
     # still usable
     assert h.run_batched(mats[:2], 8, 4, 0.0) == 0
     h.close()
+
+
+def test_autotune_writes_and_applies_database(torch_dev, tmp_path):
+    """dashsvd_autotune picks one of its candidate chunk lengths for a single
+    matrix and for a batch, appends them to the database, and a handle that
+    reads the database runs with them; results stay within rounding of the
+    default chunking."""
+    from paper_2404_09276_amd import DashSVD
+    db = str(tmp_path / "tune.txt")
+    A = synth.zipf_csr(20000, 9000, 400000, seed=61)
+    mats = synth.batched_zipf(8, rows=(1000, 4000), seed=6100)
+    h = DashSVD(precision="fp32", p_max=6, seed=3)
+    t1 = h.autotune(A, 16, 8, db)
+    t2 = h.autotune(mats, 16, 8, db)
+    h.close()
+    cands = {32, 64, 128, 256, 512, 1024}
+    assert t1 in cands and t2 in cands
+    lines = open(db).read().split("\n")
+    assert lines[0].endswith(f"_s {t1}") and lines[1].endswith(f"_b {t2}")
+    h = DashSVD(precision="fp32", p_max=6, seed=3, tuning_db=db)
+    U, S, V, st, info = h.solve(A, 16, 8, 0.0)
+    assert info.long_row_used == t1
+    h.run_batched(mats, 16, 8, 0.0)
+    assert h.info_batched(-1).long_row_used == t2
+    h.close()
+    h = DashSVD(precision="fp32", p_max=6, seed=3)
+    U0, S0, V0, st0, info0 = h.solve(A, 16, 8, 0.0)
+    h.close()
+    assert info0.long_row_used == 128
+    assert np.all(np.abs(S - S0) / S0 <= 1e-5)
