@@ -155,6 +155,7 @@ typedef struct {
   int32_t sweeps_per_call[DASHSVD_MAX_TRACE + 2]; /* sweeps of eigSVD call c: the sketch (c = 0),
                                                      the passes, then the final step */
   int32_t long_row_used;   /* SpMM chunk length of the run (option, tuning database or default) */
+  int32_t learned_n;       /* LEARNED policy: pass count predicted after pass 2 (0 if none) */
   int32_t promoted;        /* BF16 panels: 1 if the stagnation guard switched the remaining
                               passes to FP32 panels (the PVE ratio stayed above tol and above
                               0.8 x its previous value for two passes) */
@@ -241,6 +242,42 @@ dashsvd_status dashsvd_get_info_batched(dashsvd_handle *h, int32_t idx, dashsvd_
  * left unchanged; the results of the tuning runs are discarded. */
 dashsvd_status dashsvd_autotune(dashsvd_handle *h, const dashsvd_csr *As, int32_t count, int32_t k,
                                 int32_t p, const char *db_path, int32_t *best);
+
+/* ---------------------------------------------------------------------
+ * Learned shift (policy DASHSVD_SHIFT_LEARNED).  The paper's rule sets the
+ * shift of Alg. 5 step 6 from S_l; this policy lets an MLP propose the
+ * multiplier c in alpha_j = c E_l(j-1) for passes 3, 4, ... (E = S + the
+ * shift that produced S) from the E of passes 1 and 2, with the PVE check of
+ * step 5 still deciding termination and a guard that returns to c = 1/2 once
+ * E_{k+1} decreases or the PVE ratio increases.
+ *   features (3 l + 3): E_i(1)/E_1(1), E_i(2)/E_1(2), E_i(2)/E_i(1) for
+ *     i < l, then log m, log n, log(nnz/m) of the operator (m >= n);
+ *   network: relu(W1 x + b1) -> relu(W2 . + b2) -> W3 . + b3, hidden width
+ *     128, FP32; outputs o: c = 1/2 + (c_max - 1/2) sigmoid(o_0), log N = o_1;
+ *   loss: mean of (c - c*)^2 + 0.1 (o_1 - log N*)^2.
+ * Inference runs inside the eigensolver of pass 2.  All buffers of these
+ * calls are host memory; the parameters stay on the device in the handle.
+ * ------------------------------------------------------------------- */
+/* New MLP for blocks of l = k + oversampling columns; weights He-uniform from
+ * seed, Adam state cleared.  c_max in (0.5, 1). */
+dashsvd_status dashsvd_mlp_init(dashsvd_handle *h, int32_t l, uint64_t seed, double c_max);
+dashsvd_status dashsvd_mlp_num_params(dashsvd_handle *h, int64_t *n);
+/* Parameters as one FP32 vector: W1 (128 x D), b1, W2 (128 x 128), b2,
+ * W3 (2 x 128), b3, row-major; set also clears the Adam state. */
+dashsvd_status dashsvd_mlp_set_params(dashsvd_handle *h, const float *params, int64_t n);
+dashsvd_status dashsvd_mlp_get_params(dashsvd_handle *h, float *params, int64_t n);
+/* out (batch x 2) = (c, log N) for features X (batch x D). */
+dashsvd_status dashsvd_mlp_forward(dashsvd_handle *h, const float *X, int32_t batch, float *out);
+/* Gradient of the loss (same layout as the parameters) and the loss, for
+ * targets Y (batch x 2: c*, log N*). */
+dashsvd_status dashsvd_mlp_grad(dashsvd_handle *h, const float *X, const float *Y, int32_t batch,
+                                float *grad, float *loss);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) of learning rate lr on a batch. */
+dashsvd_status dashsvd_mlp_train_step(dashsvd_handle *h, const float *X, const float *Y,
+                                      int32_t batch, float lr, float *loss);
+/* Features of the last dashsvd_run (it must have run two passes), exactly as
+ * the LEARNED policy forms them; n = 3 l + 3. */
+dashsvd_status dashsvd_learned_features(dashsvd_handle *h, float *feat, int32_t n);
 
 /* Device bytes a run with these arguments needs (workspace of the handle). */
 dashsvd_status dashsvd_workspace_size(const dashsvd_csr *A, int32_t k, int32_t p,

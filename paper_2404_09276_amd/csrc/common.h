@@ -143,7 +143,8 @@ struct SolverState {
   int32_t converged;
   int32_t deficient;
   int32_t sched_off;  // schedule dropped (guard)
-  int32_t learned_ready;
+  int32_t learned_ready;  // the learned schedule has been written (pass 2)
+  int32_t learned_n;      // predicted pass count of the learned model
   int32_t skip_rescale;  // set by a pass's eig when the loop had already stopped
   int32_t eig_calls;     // eigSVD calls that ran, and their Jacobi sweeps
   int32_t eig_sweeps;
@@ -220,9 +221,30 @@ struct EigArgs {
   int sched_len;
   int stagnation_guard;  // track stagnant / promote (BF16 panel form)
   int32_t *ndone;        // batched form: incremented once when this matrix stops
+  // learned shift (policy LEARNED): MLP parameters (see k_mlp.hip), its
+  // input width D = 3 l + 3 and hidden width H, the cap of c, and the three
+  // shape features log m, log n, log(nnz / m) of the operator
+  const float *mlp;
+  int mlp_D, mlp_H;
+  double mlp_cmax;
+  double shape_feat[3];
   long long *prof;      // optional step profile (6 counters), null in the solver
   int32_t *trace_sweeps;  // sweeps of call c (c = state->eig_calls before this call), [cap + 2]
 };
+// MLP of the learned shift (k_mlp.hip)
+struct MlpDims {
+  int D, H;
+};
+constexpr int kMlpH = 128;
+constexpr float kMlpLambda = 0.1f;  // weight of the log pass-count term of the loss
+inline int64_t mlp_num_params(int D, int H) { return (int64_t)H * D + H + (int64_t)H * H + H + 2 * H + 2; }
+hipError_t mlp_forward(const MlpDims &d, const float *P, const float *X, int B, float *A1, float *A2, float *O,
+                       hipStream_t st);
+hipError_t mlp_backward(const MlpDims &d, const float *P, const float *X, const float *T, int B, float cmax,
+                        float lambda, float *A1, float *A2, float *O, float *dO, float *dA2, float *dA1, float *G,
+                        float *loss, hipStream_t st);
+hipError_t mlp_adam(float *P, const float *G, float *m, float *v, int64_t n, float lr, int t, hipStream_t st);
+
 hipError_t launch_eig(const EigArgs &a, hipStream_t st);
 // arr: count EigArgs in device memory, all with the same l; workgroup b
 // solves arr[b]

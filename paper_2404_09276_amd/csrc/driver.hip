@@ -118,6 +118,17 @@ struct dashsvd_handle {
     int32_t *tr_sweeps = nullptr;                     // count x (cap + 2)
     dashsvd_info info;
   } bat;
+  // learned-shift MLP (its own device memory, kept across runs)
+  struct Mlp {
+    bool ok = false;
+    int l = 0, D = 0, H = 0;
+    double cmax = 0.9;
+    int64_t np = 0;
+    float *P = nullptr, *G = nullptr, *m = nullptr, *v = nullptr;
+    int step = 0;
+    float *buf = nullptr;  // batch buffers of forward / backward
+    int buf_batch = 0;
+  } mlp;
   // SpMM chunk lengths by shape bucket (tuning database)
   std::vector<std::pair<std::string, int>> tune;
   // internal stream of the batched form (its pass is captured as a graph)
@@ -298,6 +309,7 @@ dashsvd_status dashsvd_set_options(dashsvd_handle *h, const dashsvd_options *opt
   if (o.p_max < 0) o.p_max = kDefaultPmax;
   if (o.p_max > 100000) return fail(h, DASHSVD_ERR_INVALID_ARG, "p_max too large");
   h->sched.clear();
+  if (o.shift_policy == DASHSVD_SHIFT_LEARNED) h->sched.assign((size_t)o.p_max + 1, 0.5);
   if (o.shift_policy == DASHSVD_SHIFT_SCHEDULE) {
     if (!o.schedule) return fail(h, DASHSVD_ERR_INVALID_ARG, "SCHEDULE policy needs options.schedule");
     h->sched.assign(o.schedule, o.schedule + o.p_max + 1);
@@ -355,6 +367,8 @@ void dashsvd_destroy(dashsvd_handle *h) {
   }
   if (h->ev_b0) (void)hipEventDestroy(h->ev_b0);
   if (h->ev_b1) (void)hipEventDestroy(h->ev_b1);
+  if (h->mlp.P) (void)hipFree(h->mlp.P);
+  if (h->mlp.buf) (void)hipFree(h->mlp.buf);
   delete h;
 }
 
@@ -603,6 +617,15 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     ea.trace_sweeps = b.tr_sweeps;
     ea.sched = h->sched.empty() ? nullptr : b.sched;
     ea.sched_len = (int)h->sched.size();
+    if (h->opt.shift_policy == DASHSVD_SHIFT_LEARNED && h->mlp.ok) {
+      ea.mlp = h->mlp.P;
+      ea.mlp_D = h->mlp.D;
+      ea.mlp_H = h->mlp.H;
+      ea.mlp_cmax = h->mlp.cmax;
+      ea.shape_feat[0] = std::log((double)Mm);
+      ea.shape_feat[1] = std::log((double)Mn);
+      ea.shape_feat[2] = std::log((double)(nnz > 0 ? nnz : 1) / (double)Mm);
+    }
     return ea;
   };
   const int32_t *done = &b.state->done;
@@ -814,6 +837,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   inf.learned_fallback = hs.sched_off;
   inf.final_alpha = hs.alpha;
   inf.promoted = promoted;
+  inf.learned_n = hs.learned_ready ? hs.learned_n : 0;
   inf.long_row_used = T;
   inf.time_total_ms = t_end - t0;
   inf.time_setup_ms = t_setup - t0;
@@ -878,8 +902,9 @@ dashsvd_status dashsvd_run(dashsvd_handle *h, const dashsvd_csr *A, int32_t k, i
   h->err.clear();
   dashsvd_status s = check_args(h, A, k, p, tol);
   if (s != DASHSVD_OK) return s;
-  if (h->opt.shift_policy == DASHSVD_SHIFT_LEARNED)
-    return fail(h, DASHSVD_ERR_INVALID_ARG, "LEARNED policy needs trained weights (dashsvd_mlp_*)");
+  if (h->opt.shift_policy == DASHSVD_SHIFT_LEARNED && (!h->mlp.ok || h->mlp.l != k + p))
+    return fail(h, DASHSVD_ERR_INVALID_ARG,
+                "LEARNED policy needs an MLP for l = k + oversampling (dashsvd_mlp_init / set_params)");
   if (h->opt.omega && h->opt.precision == DASHSVD_PREC_BF16_PANELS)
     return fail(h, DASHSVD_ERR_INVALID_ARG, "a caller-provided Omega is not supported with BF16 panels");
   s = run_impl(h, A, k, p, tol, false, nullptr);
@@ -1497,6 +1522,195 @@ dashsvd_status dashsvd_get_info_batched(dashsvd_handle *h, int32_t idx, dashsvd_
   out->eig_calls = s.eig_calls;
   out->eig_sweeps = s.eig_sweeps;
   out->status = bo.info.status;
+  return DASHSVD_OK;
+}
+
+// ===================================================================== learned shift
+// The MLP of the learned shift policy (kernels in k_mlp.hip): parameters,
+// gradients and Adam moments live in one device allocation of the handle.
+static dashsvd_status mlp_buffers(dashsvd_handle *h, int B) {
+  auto &M = h->mlp;
+  if (B <= M.buf_batch) return DASHSVD_OK;
+  if (M.buf) (void)hipFree(M.buf);
+  M.buf = nullptr;
+  M.buf_batch = 0;
+  const size_t n = (size_t)B * (M.D + 4 * M.H + 6) + 4;
+  if (hipMalloc(&M.buf, 4 * n) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(h, DASHSVD_ERR_OOM, "MLP batch buffers");
+  }
+  M.buf_batch = B;
+  return DASHSVD_OK;
+}
+
+struct MlpBufs {
+  float *X, *T, *A1, *A2, *O, *dO, *dA2, *dA1, *loss;
+};
+static MlpBufs mlp_view(dashsvd_handle *h, int B) {
+  auto &M = h->mlp;
+  MlpBufs v;
+  v.X = M.buf;
+  v.T = v.X + (size_t)B * M.D;
+  v.A1 = v.T + 2 * (size_t)B;
+  v.A2 = v.A1 + (size_t)B * M.H;
+  v.O = v.A2 + (size_t)B * M.H;
+  v.dO = v.O + 2 * (size_t)B;
+  v.dA2 = v.dO + 2 * (size_t)B;
+  v.dA1 = v.dA2 + (size_t)B * M.H;
+  v.loss = v.dA1 + (size_t)B * M.H;
+  return v;
+}
+
+dashsvd_status dashsvd_mlp_init(dashsvd_handle *h, int32_t l, uint64_t seed, double c_max) {
+  if (!h) return DASHSVD_ERR_INVALID_ARG;
+  h->err.clear();
+  if (l < 2 || l > DASHSVD_MAX_L) return fail(h, DASHSVD_ERR_INVALID_ARG, "l");
+  if (!(c_max > 0.5 && c_max < 1.0)) return fail(h, DASHSVD_ERR_INVALID_ARG, "c_max must be in (0.5, 1)");
+  auto &M = h->mlp;
+  if (M.P) (void)hipFree(M.P);
+  M = dashsvd_handle::Mlp();
+  M.l = l;
+  M.D = 3 * l + 3;
+  M.H = kMlpH;
+  M.cmax = c_max;
+  M.np = mlp_num_params(M.D, M.H);
+  void *p = nullptr;
+  if (hipMalloc(&p, 4 * 4 * (size_t)M.np) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(h, DASHSVD_ERR_OOM, "MLP parameters");
+  }
+  M.P = (float *)p;
+  M.G = M.P + M.np;
+  M.m = M.G + M.np;
+  M.v = M.m + M.np;
+  // He-uniform weights from a splitmix64 stream, zero biases, a small output
+  // layer
+  std::vector<float> host((size_t)M.np, 0.0f);
+  uint64_t z = seed;
+  auto uni = [&]() {
+    z += 0x9E3779B97F4A7C15ULL;
+    uint64_t x = z;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBULL;
+    x ^= x >> 31;
+    return (double)(x >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+  };
+  size_t o = 0;
+  const double r1 = std::sqrt(6.0 / M.D), r2 = std::sqrt(6.0 / M.H);
+  for (int64_t i = 0; i < (int64_t)M.H * M.D; ++i) host[o++] = (float)(r1 * uni());
+  o += M.H;
+  for (int64_t i = 0; i < (int64_t)M.H * M.H; ++i) host[o++] = (float)(r2 * uni());
+  o += M.H;
+  for (int64_t i = 0; i < 2 * (int64_t)M.H; ++i) host[o++] = (float)(0.1 * r2 * uni());
+  HIPCHK(hipMemcpy(M.P, host.data(), 4 * (size_t)M.np, hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(M.m, 0, 4 * 2 * (size_t)M.np));
+  M.ok = true;
+  return DASHSVD_OK;
+}
+
+dashsvd_status dashsvd_mlp_num_params(dashsvd_handle *h, int64_t *n) {
+  if (!h || !n) return DASHSVD_ERR_INVALID_ARG;
+  if (!h->mlp.ok) return fail(h, DASHSVD_ERR_STATE, "no MLP: dashsvd_mlp_init first");
+  *n = h->mlp.np;
+  return DASHSVD_OK;
+}
+
+dashsvd_status dashsvd_mlp_set_params(dashsvd_handle *h, const float *params, int64_t n) {
+  if (!h || !params) return DASHSVD_ERR_INVALID_ARG;
+  if (!h->mlp.ok) return fail(h, DASHSVD_ERR_STATE, "no MLP: dashsvd_mlp_init first");
+  if (n != h->mlp.np) return fail(h, DASHSVD_ERR_INVALID_ARG, "parameter count");
+  HIPCHK(hipMemcpy(h->mlp.P, params, 4 * (size_t)n, hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(h->mlp.m, 0, 4 * 2 * (size_t)n));
+  h->mlp.step = 0;
+  return DASHSVD_OK;
+}
+
+dashsvd_status dashsvd_mlp_get_params(dashsvd_handle *h, float *params, int64_t n) {
+  if (!h || !params) return DASHSVD_ERR_INVALID_ARG;
+  if (!h->mlp.ok) return fail(h, DASHSVD_ERR_STATE, "no MLP: dashsvd_mlp_init first");
+  if (n != h->mlp.np) return fail(h, DASHSVD_ERR_INVALID_ARG, "parameter count");
+  HIPCHK(hipMemcpy(params, h->mlp.P, 4 * (size_t)n, hipMemcpyDeviceToHost));
+  return DASHSVD_OK;
+}
+
+dashsvd_status dashsvd_mlp_forward(dashsvd_handle *h, const float *X, int32_t batch, float *out) {
+  if (!h || !X || !out || batch < 1) return DASHSVD_ERR_INVALID_ARG;
+  if (!h->mlp.ok) return fail(h, DASHSVD_ERR_STATE, "no MLP: dashsvd_mlp_init first");
+  auto &M = h->mlp;
+  dashsvd_status s = mlp_buffers(h, batch);
+  if (s != DASHSVD_OK) return s;
+  MlpBufs v = mlp_view(h, batch);
+  HIPCHK(hipMemcpy(v.X, X, 4 * (size_t)batch * M.D, hipMemcpyHostToDevice));
+  HIPCHK(mlp_forward({M.D, M.H}, M.P, v.X, batch, v.A1, v.A2, v.O, nullptr));
+  std::vector<float> o(2 * (size_t)batch);
+  HIPCHK(hipMemcpy(o.data(), v.O, 4 * o.size(), hipMemcpyDeviceToHost));
+  for (int b = 0; b < batch; ++b) {
+    const double sg = 1.0 / (1.0 + std::exp(-(double)o[2 * b]));
+    out[2 * b] = (float)(0.5 + (M.cmax - 0.5) * sg);
+    out[2 * b + 1] = o[2 * b + 1];
+  }
+  return DASHSVD_OK;
+}
+
+static dashsvd_status mlp_grad_impl(dashsvd_handle *h, const float *X, const float *Y, int32_t batch,
+                                    float *loss) {
+  auto &M = h->mlp;
+  dashsvd_status s = mlp_buffers(h, batch);
+  if (s != DASHSVD_OK) return s;
+  MlpBufs v = mlp_view(h, batch);
+  HIPCHK(hipMemcpy(v.X, X, 4 * (size_t)batch * M.D, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(v.T, Y, 4 * 2 * (size_t)batch, hipMemcpyHostToDevice));
+  HIPCHK(mlp_backward({M.D, M.H}, M.P, v.X, v.T, batch, (float)M.cmax, kMlpLambda, v.A1, v.A2, v.O, v.dO, v.dA2,
+                      v.dA1, M.G, v.loss, nullptr));
+  if (loss) HIPCHK(hipMemcpy(loss, v.loss, 4, hipMemcpyDeviceToHost));
+  return DASHSVD_OK;
+}
+
+dashsvd_status dashsvd_mlp_grad(dashsvd_handle *h, const float *X, const float *Y, int32_t batch, float *grad,
+                                float *loss) {
+  if (!h || !X || !Y || batch < 1) return DASHSVD_ERR_INVALID_ARG;
+  if (!h->mlp.ok) return fail(h, DASHSVD_ERR_STATE, "no MLP: dashsvd_mlp_init first");
+  dashsvd_status s = mlp_grad_impl(h, X, Y, batch, loss);
+  if (s != DASHSVD_OK) return s;
+  if (grad) HIPCHK(hipMemcpy(grad, h->mlp.G, 4 * (size_t)h->mlp.np, hipMemcpyDeviceToHost));
+  return DASHSVD_OK;
+}
+
+dashsvd_status dashsvd_mlp_train_step(dashsvd_handle *h, const float *X, const float *Y, int32_t batch, float lr,
+                                      float *loss) {
+  if (!h || !X || !Y || batch < 1 || !(lr > 0.0f)) return DASHSVD_ERR_INVALID_ARG;
+  if (!h->mlp.ok) return fail(h, DASHSVD_ERR_STATE, "no MLP: dashsvd_mlp_init first");
+  dashsvd_status s = mlp_grad_impl(h, X, Y, batch, loss);
+  if (s != DASHSVD_OK) return s;
+  auto &M = h->mlp;
+  M.step += 1;
+  HIPCHK(mlp_adam(M.P, M.G, M.m, M.v, M.np, lr, M.step, nullptr));
+  HIPCHK(hipDeviceSynchronize());
+  return DASHSVD_OK;
+}
+
+dashsvd_status dashsvd_learned_features(dashsvd_handle *h, float *feat, int32_t n) {
+  if (!h || !feat) return DASHSVD_ERR_INVALID_ARG;
+  if (!h->have) return fail(h, DASHSVD_ERR_STATE, "no results: run first");
+  const int l = h->l;
+  if (n != 3 * l + 3) return fail(h, DASHSVD_ERR_INVALID_ARG, "feature count must be 3 l + 3");
+  if (h->info.passes < 2 || h->trace_cap < 2) return fail(h, DASHSVD_ERR_STATE, "features need two passes");
+  std::vector<double> s((size_t)2 * l);
+  HIPCHK(hipMemcpyAsync(s.data(), h->trace_s, 8 * s.size(), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  const double a1 = h->info.alpha_used[0], a2 = h->info.alpha_used[1];
+  const double e11 = s[0] + a1, e21 = s[l] + a2;
+  for (int i = 0; i < l; ++i) {
+    const double e1 = s[i] + a1, e2 = s[l + i] + a2;
+    feat[i] = e11 > 0.0 ? (float)(e1 / e11) : 0.0f;
+    feat[l + i] = e21 > 0.0 ? (float)(e2 / e21) : 0.0f;
+    feat[2 * l + i] = e1 > 0.0 ? (float)(e2 / e1) : 0.0f;
+  }
+  const int64_t Mm = h->m > h->n ? h->m : h->n, Mn = h->m > h->n ? h->n : h->m;
+  const int64_t nnz = h->ev_ctx.nnz;
+  feat[3 * l] = (float)std::log((double)Mm);
+  feat[3 * l + 1] = (float)std::log((double)Mn);
+  feat[3 * l + 2] = (float)std::log((double)(nnz > 0 ? nnz : 1) / (double)Mm);
   return DASHSVD_OK;
 }
 

@@ -536,6 +536,54 @@ __global__ __launch_bounds__(NT) void k_eig(EigArgs a0, const EigArgs *__restric
     s_stop = (a.tol > 0.0 && worst <= a.tol) ? 1 : 0;
   }
   __syncthreads();
+  if (a.policy == 4 && a.mlp && j == 2 && a.sched && !s_stop) {
+    // Learned shift: features of passes 1 and 2 (E_i = S_i + the shift that
+    // produced them), the MLP forward pass, then the multiplier c for the
+    // shifts of passes 3, 4, ... into the schedule read below.
+    __shared__ float mf[3 * kMaxLP + 3];
+    __shared__ float mh1[kMlpH], mh2[kMlpH];
+    __shared__ float mo[2];
+    const int D = a.mlp_D, H = a.mlp_H;
+    const double a1 = a.trace_alpha[0];
+    const double e11 = a.trace_s[0] + a1, e21 = Ssh[0] + alpha;
+    for (int i = tid; i < l; i += NT) {
+      const double e1 = a.trace_s[i] + a1, e2 = Ssh[i] + alpha;
+      mf[i] = e11 > 0.0 ? (float)(e1 / e11) : 0.0f;
+      mf[l + i] = e21 > 0.0 ? (float)(e2 / e21) : 0.0f;
+      mf[2 * l + i] = e1 > 0.0 ? (float)(e2 / e1) : 0.0f;
+    }
+    if (tid < 3) mf[3 * l + tid] = (float)a.shape_feat[tid];
+    __syncthreads();
+    const float *W1 = a.mlp, *b1 = W1 + (int64_t)H * D, *W2 = b1 + H, *b2 = W2 + (int64_t)H * H;
+    const float *W3 = b2 + H, *b3 = W3 + 2 * H;
+    for (int o = tid; o < H; o += NT) {
+      float s = b1[o];
+      for (int i = 0; i < D; ++i) s = fmaf(mf[i], W1[(int64_t)o * D + i], s);
+      mh1[o] = s > 0.0f ? s : 0.0f;
+    }
+    __syncthreads();
+    for (int o = tid; o < H; o += NT) {
+      float s = b2[o];
+      for (int i = 0; i < H; ++i) s = fmaf(mh1[i], W2[(int64_t)o * H + i], s);
+      mh2[o] = s > 0.0f ? s : 0.0f;
+    }
+    __syncthreads();
+    if (tid < 2) {
+      float s = b3[tid];
+      for (int i = 0; i < H; ++i) s = fmaf(mh2[i], W3[(int64_t)tid * H + i], s);
+      mo[tid] = s;
+    }
+    __syncthreads();
+    const float sg = 1.0f / (1.0f + expf(-mo[0]));
+    const double c = 0.5 + (a.mlp_cmax - 0.5) * (double)sg;
+    for (int t = 2 + tid; t < a.sched_len; t += NT) const_cast<double *>(a.sched)[t] = c;
+    if (tid == 0) {
+      state->learned_ready = 1;
+      const float ln = mo[1];
+      state->learned_n = ln > 0.0f && ln < 10.0f ? (int32_t)lrintf(expf(ln)) : 0;
+    }
+    __syncthreads();
+  }
   if (j - 1 < a.trace_cap) {
     for (int i = tid; i < l; i += NT) a.trace_s[(int64_t)(j - 1) * l + i] = Ssh[i];
   }
@@ -618,21 +666,10 @@ static hipError_t pick_eig(int l, void (**fn)(EigArgs, const EigArgs *), int *nt
     f = k_eig<7, kMaxItems, 1, 8, kEigThreadsL, B>;
   else
     return hipErrorInvalidValue;
-  static bool attr = false;
-  if (!attr) {
-    hipFuncSetAttribute((const void *)k_eig<1, 1, 1, 4, kEigThreadsS, B>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
-    hipFuncSetAttribute((const void *)k_eig<1, 1, 1, 4, kEigThreads, B>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        128 * 1024);
-    hipFuncSetAttribute((const void *)k_eig<2, 2, 2, 4, kEigThreads, B>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        128 * 1024);
-    hipFuncSetAttribute((const void *)k_eig<4, 2, 2, 4, kEigThreads, B>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        128 * 1024);
-    hipFuncSetAttribute((const void *)k_eig<4, 3, 1, 4, kEigThreads, B>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        128 * 1024);
-    hipFuncSetAttribute((const void *)k_eig<7, kMaxItems, 1, 8, kEigThreadsL, B>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 152 * 1024);
-    attr = true;
+  // dynamic LDS above the default limit: allow exactly what this size needs
+  if (s > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s);
+    if (e != hipSuccess) return e;
   }
   *fn = f;
   *nt = NT;

@@ -57,6 +57,7 @@ class _Info(C.Structure):
                 ("long_chunks_AT", C.c_int64), ("kt_ms", C.c_double * 8), ("kt_count", C.c_int32 * 8),
                 ("eig_calls", C.c_int32), ("eig_sweeps", C.c_int32),
                 ("sweeps_per_call", C.c_int32 * (MAX_TRACE + 2)), ("long_row_used", C.c_int32),
+                ("learned_n", C.c_int32),
                 ("promoted", C.c_int32)]
 
 KT_NAMES = ["spmm", "spmm_t", "gram", "eig", "rescale", "transpose", "sketch", "final"]
@@ -67,7 +68,9 @@ _lib = None
 EXPORTS = [
     "dashsvd_create", "dashsvd_destroy", "dashsvd_set_options", "dashsvd_run", "dashsvd_get_USV",
     "dashsvd_get_info", "dashsvd_get_trace", "dashsvd_evaluate", "dashsvd_run_batched",
-    "dashsvd_get_USV_batched", "dashsvd_get_info_batched", "dashsvd_autotune", "dashsvd_workspace_size",
+    "dashsvd_get_USV_batched", "dashsvd_get_info_batched", "dashsvd_autotune", "dashsvd_mlp_init",
+    "dashsvd_mlp_num_params", "dashsvd_mlp_set_params", "dashsvd_mlp_get_params", "dashsvd_mlp_forward",
+    "dashsvd_mlp_grad", "dashsvd_mlp_train_step", "dashsvd_learned_features", "dashsvd_workspace_size",
     "dashsvd_status_string",
     "dashsvd_last_error", "dashsvd_k_gaussian", "dashsvd_k_philox_raw", "dashsvd_k_transpose",
     "dashsvd_k_spmm", "dashsvd_k_gram", "dashsvd_k_eig", "dashsvd_k_eig_prof", "dashsvd_k_rescale",
@@ -96,6 +99,14 @@ def lib():
         L.dashsvd_get_USV_batched.argtypes = [P, i32, P, i64, P, P, i64, i32, i32]
         L.dashsvd_get_info_batched.argtypes = [P, i32, C.POINTER(_Info)]
         L.dashsvd_autotune.argtypes = [P, C.POINTER(_Csr), i32, i32, i32, C.c_char_p, C.POINTER(C.c_int32)]
+        L.dashsvd_mlp_init.argtypes = [P, i32, u64, f64]
+        L.dashsvd_mlp_num_params.argtypes = [P, C.POINTER(C.c_int64)]
+        L.dashsvd_mlp_set_params.argtypes = [P, P, i64]
+        L.dashsvd_mlp_get_params.argtypes = [P, P, i64]
+        L.dashsvd_mlp_forward.argtypes = [P, P, i32, P]
+        L.dashsvd_mlp_grad.argtypes = [P, P, P, i32, P, P]
+        L.dashsvd_mlp_train_step.argtypes = [P, P, P, i32, C.c_float, P]
+        L.dashsvd_learned_features.argtypes = [P, P, i32]
         L.dashsvd_workspace_size.argtypes = [C.POINTER(_Csr), i32, i32, i32, C.POINTER(C.c_size_t)]
         L.dashsvd_status_string.argtypes = [i32]
         L.dashsvd_status_string.restype = C.c_char_p
@@ -199,6 +210,7 @@ class Info:
     sweeps_per_call: np.ndarray
     promoted: bool
     long_row_used: int
+    learned_n: int
 
 
 class DashSVD:
@@ -342,6 +354,57 @@ class DashSVD:
         _check(st, self._h)
         return best.value
 
+    # ------------------------------------------------------------ learned shift
+    def mlp_init(self, l: int, seed: int = 0, c_max: float = 0.9):
+        _check(lib().dashsvd_mlp_init(self._h, l, seed, c_max), self._h)
+        self._mlp_l = l
+        self._mlp_cmax = c_max
+
+    def mlp_num_params(self) -> int:
+        n = C.c_int64()
+        _check(lib().dashsvd_mlp_num_params(self._h, C.byref(n)), self._h)
+        return n.value
+
+    def mlp_params(self) -> np.ndarray:
+        out = np.empty(self.mlp_num_params(), dtype=np.float32)
+        _check(lib().dashsvd_mlp_get_params(self._h, _ptr(out), out.shape[0]), self._h)
+        return out
+
+    def mlp_set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        _check(lib().dashsvd_mlp_set_params(self._h, _ptr(p), p.shape[0]), self._h)
+
+    def mlp_forward(self, X) -> np.ndarray:
+        """(batch x 2): the multiplier c in [0.5, c_max] and log N."""
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        out = np.empty((X.shape[0], 2), dtype=np.float32)
+        _check(lib().dashsvd_mlp_forward(self._h, _ptr(X), X.shape[0], _ptr(out)), self._h)
+        return out
+
+    def mlp_grad(self, X, Y):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        Y = np.ascontiguousarray(Y, dtype=np.float32)
+        g = np.empty(self.mlp_num_params(), dtype=np.float32)
+        loss = C.c_float()
+        _check(lib().dashsvd_mlp_grad(self._h, _ptr(X), _ptr(Y), X.shape[0], _ptr(g), C.byref(loss)), self._h)
+        return g, loss.value
+
+    def mlp_train_step(self, X, Y, lr: float) -> float:
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        Y = np.ascontiguousarray(Y, dtype=np.float32)
+        loss = C.c_float()
+        _check(lib().dashsvd_mlp_train_step(self._h, _ptr(X), _ptr(Y), X.shape[0], lr, C.byref(loss)),
+               self._h)
+        return loss.value
+
+    def learned_features(self) -> np.ndarray:
+        """Features of the last run (passes 1 and 2), as the LEARNED policy
+        computes them on the device."""
+        l = self.info().l
+        f = np.empty(3 * l + 3, dtype=np.float32)
+        _check(lib().dashsvd_learned_features(self._h, _ptr(f), f.shape[0]), self._h)
+        return f
+
     def info_batched(self, idx: int) -> Info:
         """dashsvd_get_info_batched: matrix idx, or the batch summary for idx < 0."""
         raw = _Info()
@@ -437,4 +500,4 @@ def _info_from(raw) -> Info:
                 raw.long_chunks_AT, dict(zip(KT_NAMES, list(raw.kt_ms))),
                 dict(zip(KT_NAMES, list(raw.kt_count))), raw.eig_calls, raw.eig_sweeps,
                 np.array(raw.sweeps_per_call[:min(raw.eig_calls, MAX_TRACE + 2)]),
-                bool(raw.promoted), raw.long_row_used)
+                bool(raw.promoted), raw.long_row_used, raw.learned_n)

@@ -414,3 +414,23 @@ def test_invalid_arguments_rejected():
         oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 20, 0, 5, 0.0)
     with pytest.raises(ValueError):
         oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 1000, 1000, 5, 0.0)
+
+
+def test_mlp_reference_gradient_matches_finite_differences():
+    """The FP64 MLP reference used to check the HIP learned-shift kernels:
+    its analytic gradient against central differences of its own loss."""
+    from oracle import mlp_ref
+    rng = np.random.default_rng(3)
+    D, H = 9, 128
+    n = H * D + H + H * H + H + 2 * H + 2
+    P = rng.standard_normal(n) * 0.2
+    X = rng.standard_normal((5, D))
+    Y = np.stack([rng.uniform(0.5, 0.9, 5), rng.uniform(1.0, 3.0, 5)], axis=1)
+    g = mlp_ref.grad(P, X, Y, D, H, 0.9)
+    idx = rng.choice(n, 40, replace=False)
+    h = 1e-6
+    for i in idx:
+        e = np.zeros(n)
+        e[i] = h
+        fd = (mlp_ref.loss(P + e, X, Y, D, H, 0.9) - mlp_ref.loss(P - e, X, Y, D, H, 0.9)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
