@@ -1,20 +1,25 @@
 """Benchmark: time-to-PVE <= 1e-2 of dashSVD on one MI355X.
 
-Workload: the 200,000 x 100,000 power-law CSR matrix (10M nonzeros, Zipf 1.1
-row and column degrees, values in (0, 1]), k = 100, oversampling 20,
-tol = 1e-2 on the PVE check, FP32 panels.  The matrix is generated on the
-host from a fixed seed, copied to device memory before the timed region, and
-every timed step is one full dashsvd_run: validation, CSR(A^T), SpMM plans,
-Omega, the sketch, the shifted power passes until the check passes, and the
-final Rayleigh-Ritz step.
+Workload (zipf_200k): the 200,000 x 100,000 power-law CSR matrix (10M
+nonzeros, Zipf 1.1 row and column degrees, values in (0, 1]), k = 100,
+oversampling 20, tol = 1e-2 on the PVE check, FP32 panels.  The matrix is
+generated on the host from a fixed seed and copied to device memory before
+the timed region; every timed step is one full dashsvd_run: validation,
+CSR(A^T), SpMM plans, Omega, the sketch, the shifted power passes until the
+check passes, and the final Rayleigh-Ritz step.
 
 Printed: one JSON line with the metric, the roofline of the dominant kernel
-(HIP-event durations measured inside the timed region on the library's
-stream) and the CPU oracle timed on a bounded sample of the same workload.
+(the Jacobi eigensolver, whose time is measured with HIP events on the
+library's streams inside the timed region), the SpMM pair against HBM, the
+other forms of the metric (BF16 panels, learned shift, batched), and the CPU
+oracle timed on the host cores.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-forms]
+  python bench.py --copy-probe   (a plain 1 GiB device copy, three times: the
+                                  reference that calibrates the HBM counters)
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,16 +32,24 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time-to-PVE≤1e-2 (s) + SpMM HBM GB/s, plain FP32 vs BF16/learned-α"
 HBM_PEAK_GBS = 8000.0
+# FP64 vector peak of one compute unit: 64 FMA lanes x 2 flops x 2.4 GHz
+# (the 78.6 TFLOP/s chip peak over 256 CUs); the eigensolver is one workgroup
+CU_FP64_TFLOPS = 78.6 / 256
 K, P, TOL, OMEGA_SEED = 100, 20, 1e-2, 2002
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_zipf_200k_fp32.txt")
 
 
-def spmm_bytes(m, n, nnz, l, b_val=4, b_idx=4, b_ptr=8, b_x=4, b_y=4, shift=False, b_q=4):
+def spmm_bytes(m, n, nnz, l, b_val=4, b_idx=4, b_ptr=8, b_x=4, b_y=4):
     """Algorithmic bytes of Y = A X (A m x n CSR, X n x l, Y m x l), each
-    array counted once; with the shift epilogue Q (m x l) is read once more."""
-    b = nnz * (b_val + b_idx) + (m + 1) * b_ptr + n * l * b_x + m * l * b_y
-    if shift:
-        b += m * l * b_q
-    return b
+    array counted once."""
+    return nnz * (b_val + b_idx) + (m + 1) * b_ptr + n * l * b_x + m * l * b_y
+
+
+def jacobi_flops(l, sweeps):
+    """Algorithmic flops of cyclic Jacobi sweeps on an l x l symmetric matrix
+    with eigenvector accumulation: l(l-1)/2 rotations a sweep, each 6l flops
+    on the matrix (symmetric two-sided update) and 6l on the vectors."""
+    return 6.0 * l * l * (l - 1) * sweeps
 
 
 def load_workload(torch):
@@ -51,24 +64,18 @@ def load_workload(torch):
     return A, Dev
 
 
-def eps_metrics(A, U, S):
-    """eps_PVE and eps_sigma of Sec. 4 against the stored reference sigma."""
+def reference_sigma():
     path = os.path.join(ROOT, "tests", "golden", "sigma_zipf_200k.json")
-    if not os.path.exists(path):
-        return None, None
-    ref = np.array(json.load(open(path))["sigma"])
-    At = A.to_scipy().T.tocsr()
-    Z = At @ U.astype(np.float64)
-    nrm = (Z * Z).sum(axis=0)
-    k = U.shape[1]
-    pve = float(np.max(np.abs(ref[:k] ** 2 - nrm)) / ref[k] ** 2)
-    es = float(np.max(np.abs(ref[:k] - S) / ref[:k]))
-    return pve, es
+    return np.array(json.load(open(path))["sigma"]) if os.path.exists(path) else None
 
 
-def run_form(torch, Dev, precision, steps, warmup, stream, **kw):
-    from paper_2404_09276_amd import DashSVD
-    h = DashSVD(precision=precision, p_max=64, seed=OMEGA_SEED, stream=stream, timing=True, **kw)
+def run_form(torch, Dev, steps, warmup, stream, model=None, **kw):
+    """Time `steps` solves; returns (seconds, infos, eps_PVE, eps_sigma)."""
+    from paper_2404_09276_amd import DashSVD, learned
+    h = DashSVD(p_max=64, seed=OMEGA_SEED, stream=stream, timing=True, **kw)
+    if model:
+        learned.attach(h, model)
+        h.set_options(p_max=64, seed=OMEGA_SEED, stream=stream, timing=True, **kw)
     for _ in range(warmup):
         h.run(Dev, K, P, TOL)
     torch.cuda.synchronize()
@@ -79,24 +86,82 @@ def run_form(torch, Dev, precision, steps, warmup, stream, **kw):
         infos.append(h.info())
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    U, S, V = h.get_usv(dtype="float32")
+    sig = reference_sigma()
+    pve, es = h.evaluate(Dev, sig) if sig is not None else (None, None)
     h.close()
-    return el, infos, U, S
+    return el, infos, pve, es
 
 
-def cpu_baseline(A, passes_gpu):
-    """The oracle as it stands on the host cores, on a bounded sample of the
-    same workload: the sketch, 2 shifted passes and the final Rayleigh-Ritz
-    step on the full matrix (4 eigSVD blocks); scaled to the GPU run's
-    N_p + 2 blocks to give seconds per solve."""
-    import oracle
+def batched_form(torch, steps):
+    """The batched form on 512 power-law matrices (rows 1k-10k, columns
+    0.5-1 x rows, density 0.05-1 %, Zipf 1.1), k = 16, oversampling 8, BF16
+    panels, tol 1e-2: seconds per batch and matrices per second."""
+    import synth
+    from paper_2404_09276_amd import DashSVD
+
+    mats = synth.batched_zipf(512, rows=(1000, 10000), seed=5000)
+    dev = []
+    for A in mats:
+        class D:
+            pass
+        d = D()
+        d.m, d.n, d.nnz = A.m, A.n, A.nnz
+        d.row_ptr = torch.from_numpy(A.row_ptr).cuda()
+        d.col = torch.from_numpy(A.col).cuda()
+        d.val = torch.from_numpy(A.val).cuda()
+        dev.append(d)
+    h = DashSVD(precision="bf16", p_max=16, seed=5000, stream=torch.cuda.current_stream())
+    h.run_batched(dev, 16, 8, 1e-2)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, K, P, 2, 0.0, seed=OMEGA_SEED)
-    t = time.perf_counter() - t0
-    scale = (passes_gpu + 2) / 4.0
-    return {"value": t * scale, "unit": "s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"sketch + 2 passes + final RR on the full matrix took {t:.2f} s; "
-                      f"scaled by (N_p+2)/4 with N_p={passes_gpu}"}
+    for _ in range(steps):
+        h.run_batched(dev, 16, 8, 1e-2)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    s = h.info_batched(-1)
+    h.close()
+    return {"value": el, "unit": "s per batch", "matrices_per_s": 512 / el, "matrices": 512,
+            "nnz_total": int(sum(A.nnz for A in mats)), "max_passes": s.passes,
+            "all_converged": bool(s.converged), "pass_loop_ms": s.time_loop_ms,
+            "workload": "512 Zipf 1.1 matrices, rows U[1k,10k], k=16, oversampling 8, BF16 panels, "
+                        "tol 1e-2, p_max 16"}
+
+
+def cpu_baseline(A, min_seconds=10.0):
+    """The oracle as it stands on the host cores: full FP64 solves of the same
+    workload (tol 1e-2, same Omega seed), repeated until min_seconds of CPU
+    work, seconds per solve."""
+    import oracle
+    runs, t0 = 0, time.perf_counter()
+    passes = None
+    while True:
+        r = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, K, P, 64, TOL, seed=OMEGA_SEED)
+        passes = r.passes
+        runs += 1
+        if time.perf_counter() - t0 >= min_seconds:
+            break
+    t = (time.perf_counter() - t0) / runs
+    return {"value": t, "unit": "s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{runs} full solves of the workload (tol 1e-2, {passes} passes each), "
+                      f"mean seconds per solve"}
+
+
+def traffic():
+    """HBM bytes per launch of the eigensolver from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, calibrated on a copy kernel),
+    or None when it is missing or the kernel source changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    t = {}
+    for line in open(TRAFFIC_FILE):
+        parts = line.split()
+        if len(parts) == 2 and not line.startswith("#"):
+            t[parts[0]] = parts[1]
+    src = os.path.join(ROOT, "paper_2404_09276_amd", "csrc", "k_eig.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if t.get("k_eig_sha256") != digest or "k_eig_bytes_per_launch" not in t:
+        return None
+    return float(t["k_eig_bytes_per_launch"])
 
 
 def main():
@@ -106,33 +171,45 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": src.numel() * 4, "launches": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the single-matrix path has no multi-GPU form in this library)", file=sys.stderr)
+              "(this library has no multi-GPU form)", file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     A, Dev = load_workload(torch)
     stream = torch.cuda.current_stream()
-    el, infos, U, S = run_form(torch, Dev, "fp32", args.steps, args.warmup, stream)
+    el, infos, pve, es = run_form(torch, Dev, args.steps, args.warmup, stream, precision="fp32")
     ms = el / args.steps * 1e3
     inf = infos[-1]
     l = K + P
-    # per-group averages over the timed region
     tot = {g: sum(i.kt_ms[g] for i in infos) for g in infos[0].kt_ms}
     cnt = {g: sum(i.kt_count[g] for i in infos) for g in infos[0].kt_count}
     avg = {g: (tot[g] / cnt[g] if cnt[g] else 0.0) for g in tot}
+    dom = max(("spmm", "spmm_t", "gram", "eig", "rescale", "transpose", "final"), key=lambda g: tot[g])
+    # eigensolver: algorithmic FP64 flops of its sweeps over its event time
+    sweeps = sum(i.eig_sweeps for i in infos)
+    eig_ms = sum(i.kt_ms["eig"] for i in infos)
+    eig_tf = jacobi_flops(l, sweeps) / (eig_ms * 1e-3) / 1e12 if eig_ms else 0.0
+    # SpMM pair against HBM
     b1 = spmm_bytes(A.m, A.n, A.nnz, l)
     b2 = spmm_bytes(A.n, A.m, A.nnz, l)
     gbs1 = b1 / (avg["spmm"] * 1e-3) / 1e9 if avg["spmm"] else 0.0
     gbs2 = b2 / (avg["spmm_t"] * 1e-3) / 1e9 if avg["spmm_t"] else 0.0
-    # dominant kernel group by time in the timed region
-    dom = max(("spmm", "spmm_t", "gram", "eig", "rescale"), key=lambda g: tot[g])
-    spmm_total_ms = avg["spmm"] + avg["spmm_t"]
-    achieved = (b1 + b2) / (spmm_total_ms * 1e-3) / 1e9 if spmm_total_ms else 0.0
-    pve, es = eps_metrics(A, U, S)
+    pair_ms = avg["spmm"] + avg["spmm_t"]
+    achieved_pair = (b1 + b2) / (pair_ms * 1e-3) / 1e9 if pair_ms else 0.0
     out = {
         "metric": METRIC, "value": ms / 1e3, "unit": "s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": False, "scaling": "weak",
@@ -141,24 +218,39 @@ def main():
                                "k=100, oversampling 20, PVE tol 1e-2, FP32 panels",
                    "form": "plain FP32", "passes": inf.passes, "converged": inf.converged,
                    "eps_pve": pve, "eps_sigma": es, "eig_calls": inf.eig_calls,
-                   "eig_sweeps": inf.eig_sweeps},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "SpMM pair per pass (Z = A C; X = A^T Z)",
-                     "bytes_per_launch": {"spmm": b1, "spmm_t": b2},
-                     "avg_ms": {"spmm": avg["spmm"], "spmm_t": avg["spmm_t"]},
-                     "gbs": {"spmm": gbs1, "spmm_t": gbs2}},
+                   "eig_sweeps": inf.eig_sweeps,
+                   "sweeps_per_call": [int(x) for x in inf.sweeps_per_call]},
+        "roofline": {"bound": "alu", "kernel": "k_eig (Jacobi eigensolver of eigSVD, one workgroup)",
+                     "achieved": eig_tf, "peak": CU_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": eig_tf / CU_FP64_TFLOPS, "traffic": traffic(),
+                     "flops_per_sweep": jacobi_flops(l, 1), "sweeps_timed": sweeps,
+                     "avg_ms_per_launch": avg["eig"],
+                     "peak_basis": "FP64 vector peak of the one CU the kernel runs on (78.6 TFLOP/s / 256)"},
+        "roofline_spmm": {"bound": "hbm", "kernel": "SpMM pair per pass (Z = A C; X = A^T Z)",
+                          "achieved": achieved_pair, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": achieved_pair / HBM_PEAK_GBS,
+                          "bytes_per_launch": {"spmm": b1, "spmm_t": b2},
+                          "avg_ms": {"spmm": avg["spmm"], "spmm_t": avg["spmm_t"]},
+                          "gbs": {"spmm": gbs1, "spmm_t": gbs2}},
         "kernel_groups_ms_per_step": {g: tot[g] / args.steps for g in tot},
         "dominant_group": dom,
     }
     if not args.no_forms:
-        elb, infb, Ub, Sb = run_form(torch, Dev, "bf16", max(2, args.steps // 3), 1, stream)
-        pveb, esb = eps_metrics(A, Ub, Sb)
-        out["forms"] = {"bf16_panels": {"value": elb / max(2, args.steps // 3), "unit": "s",
-                                        "passes": infb[-1].passes, "eps_pve": pveb,
-                                        "eps_sigma": esb}}
+        nf = max(2, args.steps // 3)
+        elb, infb, pveb, esb = run_form(torch, Dev, nf, 1, stream, precision="bf16")
+        out["forms"] = {"bf16_panels": {"value": elb / nf, "unit": "s", "passes": infb[-1].passes,
+                                        "promoted": infb[-1].promoted, "eps_pve": pveb, "eps_sigma": esb}}
+        model = os.path.join(ROOT, "paper_2404_09276_amd", "learned_alpha_l120.npz")
+        if os.path.exists(model):
+            ell, infl, pvel, esl = run_form(torch, Dev, nf, 1, stream, model=model, precision="fp32",
+                                            shift_policy="learned")
+            out["forms"]["learned_alpha"] = {"value": ell / nf, "unit": "s", "passes": infl[-1].passes,
+                                             "fell_back": infl[-1].learned_fallback,
+                                             "predicted_passes": infl[-1].learned_n,
+                                             "eps_pve": pvel, "eps_sigma": esl}
+        out["forms"]["batched"] = batched_form(torch, 3)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(A, inf.passes)
+        out["cpu_baseline"] = cpu_baseline(A)
     print(json.dumps(out), flush=True)
 
 
