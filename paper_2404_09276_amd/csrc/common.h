@@ -220,7 +220,8 @@ struct EigArgs {
   const double *sched;  // device multipliers (SCHEDULE / LEARNED), may be null
   int sched_len;
   int stagnation_guard;  // track stagnant / promote (BF16 panel form)
-  int32_t *ndone;        // batched form: incremented once when this matrix stops
+  int32_t *ndone;        // batched form: [0] incremented once when this matrix stops,
+                         // [1] once when it asks for FP32 panels
   // learned shift (policy LEARNED): MLP parameters (see k_mlp.hip), its
   // input width D = 3 l + 3 and hidden width H, the cap of c, and the three
   // shape features log m, log n, log(nnz / m) of the operator

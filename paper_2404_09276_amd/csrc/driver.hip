@@ -1107,6 +1107,9 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
   b.sched = (double *)ar.take(8 * (size_t)(pmax + 2));
   b.Uo = ar.take(dsz(cdt) * (size_t)m * k);
   b.Vo = ar.take(dsz(cdt) * (size_t)n * k);
+  // BF16 panels: FP32 panels for the passes after a promotion
+  b.Q32 = pdt != cdt ? ar.take(dsz(cdt) * (size_t)n * ld) : nullptr;
+  b.Y32 = pdt != cdt ? ar.take(dsz(cdt) * (size_t)m * ld) : nullptr;
   EigArgs *eargs = (EigArgs *)ar.take(sizeof(EigArgs) * 3 * (size_t)count);
   int64_t *offM = (int64_t *)ar.take(8 * (size_t)(count + 1));
   int64_t *offN = (int64_t *)ar.take(8 * (size_t)(count + 1));
@@ -1229,10 +1232,17 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
       e.sched = h->sched.empty() ? nullptr : b.sched;
       e.sched_len = (int)h->sched.size();
       e.ndone = ndone;
+      e.stagnation_guard = mode == 2 && pdt == DASHSVD_BF16;
     }
   HIPCHK(hipMemcpyAsync(eargs, ea.data(), sizeof(EigArgs) * ea.size(), hipMemcpyHostToDevice, st));
   const int64_t nIM = (int64_t)itM.size(), nIN = (int64_t)itN.size();
 
+  // Panels of the passes: BF16 (or the form's type) until a matrix's PVE
+  // ratio reaches a plateau above tol (the stagnation guard of the single
+  // form), then FP32 for the whole batch: Q = C W of the last block is formed
+  // again in FP32 and the pass is captured again.
+  void *Qc = b.Q, *Yc = b.Y;
+  int pc = pdt;
   // one eigSVD block of every matrix on C (rows of M^T): Gram, eig, Q = C W,
   // then Y = M Q; gate: skip the matrices stopped before this pass
   auto block = [&](int mode, int gate) -> hipError_t {
@@ -1240,10 +1250,10 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
                                 gate, st);
     if (e == hipSuccess) e = launch_eig_batched(eargs + (size_t)(mode - 1) * count, count, l, st);
     if (e == hipSuccess)
-      e = launch_brescale(itN_d, nIN, l, b.C, nullptr, ld, cdt, b.W, (int64_t)ll, l, l, b.Q, ld, pdt, b.state,
+      e = launch_brescale(itN_d, nIN, l, b.C, nullptr, ld, cdt, b.W, (int64_t)ll, l, l, Qc, ld, pc, b.state,
                           gate, st);
     if (e == hipSuccess)
-      e = launch_spmm(m, rpA, colA, valA, vdt, b.Q, ld, pdt, b.Y, ld, pdt, ld, b.planM.n_chunks, b.planM.tasks,
+      e = launch_spmm(m, rpA, colA, valA, vdt, Qc, ld, pc, Yc, ld, pc, ld, b.planM.n_chunks, b.planM.tasks,
                       b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, nullptr, st,
                       gate ? rowmatM : nullptr, b.state);
     return e;
@@ -1256,59 +1266,86 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
   auto pass = [&]() -> hipError_t {
     hipError_t e = launch_bsnap(b.state, count, 1, st);
     if (e == hipSuccess)
-      e = launch_spmm(n, b.rpT, b.colT, b.valT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ld, b.planT.n_chunks,
-                      b.planT.tasks, b.planT.n_long, b.planT.longs, b.planT.partial, T, b.Q, ld, &b.state->alpha,
+      e = launch_spmm(n, b.rpT, b.colT, b.valT, vdt, Yc, ld, pc, b.C, ld, cdt, ld, b.planT.n_chunks,
+                      b.planT.tasks, b.planT.n_long, b.planT.longs, b.planT.partial, T, Qc, ld, &b.state->alpha,
                       nullptr, st, rowmatN, b.state);
     if (e == hipSuccess) e = block(2, 1);
     return e;
   };
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  if (pmax > 0) {
+  auto capture = [&]() -> dashsvd_status {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     hipError_t ec = pass();
     hipError_t ee = hipStreamEndCapture(st, &graph);
     if (ec != hipSuccess || ee != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
+      graph = nullptr;
       return fail(h, DASHSVD_ERR_HIP, std::string("pass capture: ") + hipGetErrorString(ec != hipSuccess ? ec : ee));
     }
     hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (ei != hipSuccess) {
       (void)hipGraphDestroy(graph);
+      graph = nullptr;
       return fail(h, DASHSVD_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
     }
+    return DASHSVD_OK;
+  };
+  if (pmax > 0) {
+    dashsvd_status sc = capture();
+    if (sc != DASHSVD_OK) return sc;
   }
   const int every = h->opt.check_interval > 0 ? h->opt.check_interval : 1;
   int launched = 0;
+  int promoted = 0;
   HIPCHK(hipStreamSynchronize(st));
   const double t_loop0 = now_ms();
   hipError_t eloop = hipSuccess;
-  while (launched < pmax && eloop == hipSuccess) {
+  dashsvd_status sloop = DASHSVD_OK;
+  while (launched < pmax && eloop == hipSuccess && sloop == DASHSVD_OK) {
     const int chunk = (pmax - launched) < every ? (pmax - launched) : every;
     for (int c = 0; c < chunk && eloop == hipSuccess; ++c) eloop = hipGraphLaunch(exec, st);
     launched += chunk;
     if (eloop == hipSuccess && tol > 0.0 && launched < pmax) {
-      int32_t nd = 0;
-      eloop = hipMemcpyAsync(&nd, ndone, 4, hipMemcpyDeviceToHost, st);
+      int32_t nd[2] = {0, 0};
+      eloop = hipMemcpyAsync(nd, ndone, 8, hipMemcpyDeviceToHost, st);
       if (eloop == hipSuccess) eloop = hipStreamSynchronize(st);
-      if (nd >= count) break;
+      if (eloop != hipSuccess || nd[0] >= count) break;
+      if (nd[1] > 0 && pc == DASHSVD_BF16) {
+        Qc = b.Q32;
+        Yc = b.Y32;
+        pc = cdt;
+        promoted = 1;
+        eloop = launch_brescale(itN_d, nIN, l, b.C, nullptr, ld, cdt, b.W, (int64_t)ll, l, l, Qc, ld, pc, b.state,
+                                1, st);
+        if (eloop == hipSuccess)
+          eloop = launch_spmm(m, rpA, colA, valA, vdt, Qc, ld, pc, Yc, ld, pc, ld, b.planM.n_chunks,
+                              b.planM.tasks, b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0,
+                              nullptr, nullptr, st, rowmatM, b.state);
+        if (eloop == hipSuccess) sloop = capture();
+      }
     }
   }
   if (eloop == hipSuccess) eloop = hipStreamSynchronize(st);
   const double t_loop1 = now_ms();
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
+  if (sloop != DASHSVD_OK) return sloop;
   HIPCHK(eloop);
   // final Rayleigh-Ritz of every matrix: B = M Q, eigSVD(B), U = B W(:,1:k),
   // V = Q Vs(:,1:k), signs
   HIPCHK(launch_bsnap(b.state, count, 0, st));
-  HIPCHK(launch_spmm(m, rpA, colA, valA, vdt, b.Q, ld, pdt, b.B, ld, cdt, ld, b.planM.n_chunks, b.planM.tasks,
+  HIPCHK(launch_spmm(m, rpA, colA, valA, vdt, Qc, ld, pc, b.B, ld, cdt, ld, b.planM.n_chunks, b.planM.tasks,
                      b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, nullptr, st));
   HIPCHK(launch_bgram(itM_d, nIM, ioffM_d, count, l, b.B, ld, cdt, bpart, b.G, (int64_t)ll, b.state, 0, st));
   HIPCHK(launch_eig_batched(eargs + 2 * (size_t)count, count, l, st));
   HIPCHK(launch_brescale(itM_d, nIM, l, b.B, nullptr, ld, cdt, b.W, (int64_t)ll, l, k, b.Uo, k, cdt, b.state, 0,
                          st));
-  HIPCHK(launch_brescale(itN_d, nIN, l, b.Q, nullptr, ld, pdt, b.Vs, (int64_t)ll, l, k, b.Vo, k, cdt, b.state, 0,
+  HIPCHK(launch_brescale(itN_d, nIN, l, Qc, nullptr, ld, pc, b.Vs, (int64_t)ll, l, k, b.Vo, k, cdt, b.state, 0,
                          st));
   HIPCHK(launch_bsign(offN, offM, count, k, b.Vo, b.Uo, k, cdt, st));
   // aggregate info
@@ -1328,6 +1365,7 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
   bo.info.l = l;
   bo.info.time_loop_ms = t_loop1 - t_loop0;
   bo.info.long_row_used = T;
+  bo.info.promoted = promoted;
   bo.have = true;
   bo.count = count;
   bo.k = k;

@@ -624,7 +624,10 @@ __global__ __launch_bounds__(NT) void k_eig(EigArgs a0, const EigArgs *__restric
         // accuracy.  Ordinary convergence gains ~45 % per pass or more.
         const bool stag = j >= 2 && ratio > 0.8 * state->prev_ratio;
         state->stagnant = stag ? state->stagnant + 1 : 0;
-        if (state->stagnant >= 2) state->promote = 1;
+        if (state->stagnant >= 2 && !state->promote) {
+          state->promote = 1;
+          if (a.ndone) atomicAdd(a.ndone + 1, 1);  // batched form: promotions so far
+        }
       }
       state->prev_ratio = ratio;
       state->alpha_prev = a.pve_mode == 1 ? na : alpha;
