@@ -597,9 +597,12 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     std::memset(&ea, 0, sizeof(ea));
     ea.l = l;
     ea.k = k;
-    // FP64 form: converge to half an ulp; FP32 / BF16 panels carry ~1e-7
-    // relative rounding, so the eigenvectors need no more than 2^-30
-    ea.skip = prec == DASHSVD_PREC_FP64 ? 0x1.0p-53 : 0x1.0p-30;
+    // Jacobi stops when every |g_pq| <= skip sqrt(g_pp g_qq).  V is a
+    // product of rotations, so Q = C V S^-1 then has Q^T Q = I + E with
+    // |E_pq| <= skip whatever the eigenvalue gaps, and the eigenvalues are
+    // off by O(skip^2).  FP64 form: half an ulp; FP32 / BF16 panels store Q
+    // with 2^-24 relative rounding, so 2^-23 is below what they hold.
+    ea.skip = prec == DASHSVD_PREC_FP64 ? 0x1.0p-53 : 0x1.0p-23;
     ea.G = b.G;
     ea.S = b.S;
     ea.Vs = b.Vs;
@@ -1213,7 +1216,7 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
       std::memset(&e, 0, sizeof(e));
       e.l = l;
       e.k = k;
-      e.skip = prec == DASHSVD_PREC_FP64 ? 0x1.0p-53 : 0x1.0p-30;
+      e.skip = prec == DASHSVD_PREC_FP64 ? 0x1.0p-53 : 0x1.0p-23;
       e.G = b.G + ll * i;
       e.S = b.S + (size_t)l * i;
       e.Vs = b.Vs + ll * i;
