@@ -110,7 +110,7 @@ struct IC {
 // L = 128, 8 above, where L is then a multiple of 8); NT: threads (1024, or
 // 512 for the largest sizes, so that 2 waves per SIMD leave room for V)
 // BATCHED: workgroup b solves arr[b] (a0 unused); else a0.
-template <int MAXNR, int MAXIT, int BATCH, int CPL, int NT, bool BATCHED>
+template <int MAXNR, int MAXIT, int BATCH, int CPL, int NT, bool BATCHED, bool RSV>
 __global__ __launch_bounds__(NT) void k_eig(EigArgs a0, const EigArgs *__restrict__ arr) {
   const EigArgs &a = BATCHED ? arr[blockIdx.x] : a0;
   SolverState *state = a.state;
@@ -242,15 +242,18 @@ __global__ __launch_bounds__(NT) void k_eig(EigArgs a0, const EigArgs *__restric
   const int RPW = kWave / LPR;       // rows per wave
   const int sub = lane / LPR, cl = lane - sub * LPR;
   const bool active = sub < RPW;
-  const int row_stride = (NT / kWave) * RPW;
+  // RSV: wave 0 holds no rows of V (it computes the rotations while the
+  // other waves update V)
+  const int vwave = RSV ? wave - 1 : wave;
+  const int row_stride = (NT / kWave - (RSV ? 1 : 0)) * RPW;
   const int NR = (L + row_stride - 1) / row_stride;
   const int c0 = CPL * cl;
   double v[MAXNR][CPL];
 #pragma unroll
   for (int it = 0; it < MAXNR; ++it) {
-    const int row = wave * RPW + sub + it * row_stride;
+    const int row = vwave * RPW + sub + it * row_stride;
 #pragma unroll
-    for (int j = 0; j < CPL; ++j) v[it][j] = (active && row < L && row == c0 + j) ? 1.0 : 0.0;
+    for (int j = 0; j < CPL; ++j) v[it][j] = (vwave >= 0 && active && row < L && row == c0 + j) ? 1.0 : 0.0;
   }
   if (tid == 0) s_sweeps = 0;
   __syncthreads();
@@ -264,7 +267,7 @@ __global__ __launch_bounds__(NT) void k_eig(EigArgs a0, const EigArgs *__restric
   // alone, which keeps its value.
   auto v_update = [&](auto vpar_c) __attribute__((always_inline)) {
     constexpr int VPAR = decltype(vpar_c)::value;
-    if (wave * RPW >= L) return;
+    if (vwave < 0 || vwave * RPW >= L) return;
     const double2 *rcs = rot_cs[VPAR];
     if constexpr (VPAR == 0) {
       double2 cs[CPL / 2];
@@ -494,8 +497,8 @@ __global__ __launch_bounds__(NT) void k_eig(EigArgs a0, const EigArgs *__restric
   for (int i = tid; i < l; i += NT) a.S[i] = Ssh[i];
 #pragma unroll
   for (int it = 0; it < MAXNR; ++it) {
-    const int row = wave * RPW + sub + it * row_stride;
-    if (it < NR && active && row < l) {
+    const int row = vwave * RPW + sub + it * row_stride;
+    if (vwave >= 0 && it < NR && active && row < l) {
 #pragma unroll
       for (int j = 0; j < CPL; ++j) {
         const int p = c0 + j;
@@ -651,22 +654,26 @@ static hipError_t pick_eig(int l, void (**fn)(EigArgs, const EigArgs *), int *nt
   const int P = L / 2;
   const int LPR = L / CPL, RPW = kWave / LPR;
   const int NR = (L + (NT / kWave) * RPW - 1) / ((NT / kWave) * RPW);
+  // with wave 0 kept free of V rows (its lanes compute the P <= 64 rotations)
+  const int NRr = (L + (NT / kWave - 1) * RPW - 1) / ((NT / kWave - 1) * RPW);
   const int IT = ((P + 1) * (P + 2) / 2 + NT - 1) / NT;  // odd parity has more
   size_t s = sizeof(double) * (size_t)(L * (L + 1) / 2 + 2);
   if (CPL == 8) s += (size_t)2 * kMaxItems * NT * (sizeof(uint32_t) + sizeof(uint16_t));
   void (*f)(EigArgs, const EigArgs *) = nullptr;
   if (NT == kEigThreadsS && NR <= 1 && IT <= 1)
-    f = k_eig<1, 1, 1, 4, kEigThreadsS, B>;
-  else if (CPL == 4 && NT == kEigThreads && NR <= 1 && IT <= 1)
-    f = k_eig<1, 1, 1, 4, kEigThreads, B>;
-  else if (CPL == 4 && NT == kEigThreads && NR <= 2 && IT <= 2)
-    f = k_eig<2, 2, 2, 4, kEigThreads, B>;
+    f = k_eig<1, 1, 1, 4, kEigThreadsS, B, false>;
+  else if (CPL == 4 && NT == kEigThreads && NRr <= 1 && IT <= 1)
+    f = k_eig<1, 1, 1, 4, kEigThreads, B, true>;
+  else if (CPL == 4 && NT == kEigThreads && NRr <= 2 && IT <= 2)
+    f = k_eig<2, 2, 2, 4, kEigThreads, B, true>;
+  else if (CPL == 4 && NT == kEigThreads && NRr <= 4 && IT <= 2)
+    f = k_eig<4, 2, 2, 4, kEigThreads, B, true>;
   else if (CPL == 4 && NT == kEigThreads && NR <= 4 && IT <= 2)
-    f = k_eig<4, 2, 2, 4, kEigThreads, B>;
+    f = k_eig<4, 2, 2, 4, kEigThreads, B, false>;
   else if (CPL == 4 && NT == kEigThreads && NR <= 4 && IT <= 3)
-    f = k_eig<4, 3, 1, 4, kEigThreads, B>;
+    f = k_eig<4, 3, 1, 4, kEigThreads, B, false>;
   else if (CPL == 8 && NR <= 7 && IT <= kMaxItems)
-    f = k_eig<7, kMaxItems, 1, 8, kEigThreadsL, B>;
+    f = k_eig<7, kMaxItems, 1, 8, kEigThreadsL, B, false>;
   else
     return hipErrorInvalidValue;
   // dynamic LDS above the default limit: allow exactly what this size needs
