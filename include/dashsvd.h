@@ -80,6 +80,19 @@ typedef int32_t dashsvd_status;
 #define DASHSVD_PVE_R2 0
 #define DASHSVD_PVE_R1 1
 
+/* Orthonormalisation of the sketch and pass blocks (Alg. 3 inside Alg. 5).
+ *   AUTO (default): Cholesky-QR.  W = R^-1 from G = C^T C = R^T R, so that
+ *       Q = C W is orthonormal with the span of eigSVD's Q, and S from the
+ *       eigenvalues of G (Householder tridiagonalisation and Sturm-count
+ *       bisection, FP64).  The passes use only S and span(Q), which both
+ *       bases share; the final Rayleigh-Ritz step always uses eigSVD with
+ *       eigenvectors.  A block whose G is not safely positive definite
+ *       (lambda_min <= 2^-32 lambda_max, or a failed factorisation) falls
+ *       back to JACOBI for that call.
+ *   JACOBI: eigSVD itself (Jacobi eigenvectors of G) for every block. */
+#define DASHSVD_EIG_AUTO 0
+#define DASHSVD_EIG_JACOBI 1
+
 #define DASHSVD_MAX_L 160     /* largest supported l = k + oversampling */
 #define DASHSVD_MAX_TRACE 256 /* passes recorded in dashsvd_info */
 
@@ -119,13 +132,15 @@ typedef struct {
                              runs with long_row <= 0 take the SpMM chunk length stored for
                              their shape bucket (else the built-in default).  Read when the
                              options are set. */
+  int32_t eig_method;     /* DASHSVD_EIG_* (default AUTO): how the sketch and the power passes
+                             orthonormalise their block */
 } dashsvd_options;
 
 /* Kernel groups timed when options.timing = 1 (index into kt_ms / kt_count). */
 #define DASHSVD_KT_SPMM 0        /* M times a panel: Z = M C (FP32/FP64 forms) or Y = M Q (BF16 form) */
 #define DASHSVD_KT_SPMM_T 1      /* M^T times a panel: X = M^T Z, or C = M^T Y - alpha Q (BF16 form) */
 #define DASHSVD_KT_GRAM 2        /* Gram partials + reduction (every eigSVD) */
-#define DASHSVD_KT_EIG 3         /* Jacobi eig + tail (every eigSVD) */
+#define DASHSVD_KT_EIG 3         /* eigensolver + tail (every eigSVD or Cholesky-QR block) */
 #define DASHSVD_KT_RESCALE 4     /* C+ = (X - alpha C) W, or Q = C W (BF16 form) */
 #define DASHSVD_KT_TRANSPOSE 5   /* validation + CSR(A^T) build */
 #define DASHSVD_KT_SKETCH 6      /* Omega + M^T Omega */
@@ -151,7 +166,7 @@ typedef struct {
   double kt_ms[8];         /* summed HIP-event time per kernel group (timing = 1) */
   int32_t kt_count[8];     /* launches counted per group (passes after the stop excluded) */
   int32_t eig_calls;       /* eigSVD eigenproblems solved in the run */
-  int32_t eig_sweeps;      /* Jacobi sweeps summed over them */
+  int32_t eig_sweeps;      /* Jacobi sweeps summed over them (Cholesky-QR calls count 0) */
   int32_t sweeps_per_call[DASHSVD_MAX_TRACE + 2]; /* sweeps of eigSVD call c: the sketch (c = 0),
                                                      the passes, then the final step */
   int32_t long_row_used;   /* SpMM chunk length of the run (option, tuning database or default) */
@@ -159,6 +174,7 @@ typedef struct {
   int32_t promoted;        /* BF16 panels: 1 if the stagnation guard switched the remaining
                               passes to FP32 panels (the PVE ratio stayed above tol and above
                               0.8 x its previous value for two passes) */
+  int32_t cholqr_calls;    /* eig_calls solved by Cholesky-QR (eig_method AUTO) */
 } dashsvd_info;
 
 typedef struct dashsvd_handle dashsvd_handle;
@@ -343,6 +359,18 @@ dashsvd_status dashsvd_k_eig(int32_t l, const double *G, double *S, double *Vs, 
  * cycles of thread 0's own rotation work and V update. */
 dashsvd_status dashsvd_k_eig_prof(int32_t l, const double *G, double *S, double *Vs, double *W,
                                   int32_t *sweeps, long long *prof, void *stream);
+
+/* Orthonormalisation of a pass block without eigenvectors (the solver of
+ * the sketch and power passes under eig_method AUTO): from G (device, l x l
+ * symmetric, FP64, row-major) the Cholesky-QR weights W = R^-1 (device,
+ * l x l, upper triangular, zeros below the diagonal; G = R^T R) and S
+ * (device, l, descending) = sqrt of the eigenvalues of G, from Householder
+ * tridiagonalisation and Sturm-count bisection.  *accepted (host) is 1 when
+ * the factorisation completed and lambda_min > 2^-32 lambda_max; when 0,
+ * W and S are unspecified (the solver then runs the Jacobi eigSVD).
+ * Synchronises the stream. */
+dashsvd_status dashsvd_k_cholqr(int32_t l, const double *G, double *S, double *W, int32_t *accepted,
+                                void *stream);
 
 /* Out (r x c, ldo, odtype) = C (r x l, ldc, cdtype) * W (l x c, FP64,
  * row-major, leading dimension ldw): the rescale U = C V S^-1 of Alg. 3

@@ -151,6 +151,16 @@ struct SolverState {
   int32_t pass_skip;     // snapshot of done at the start of the current pass
   int32_t stagnant;      // consecutive passes with ratio > tol and > 0.8 x the previous ratio
   int32_t promote;       // set once stagnant reaches 2 (BF16 panels: switch to FP32)
+  // Cholesky-QR pass solver (k_cholqr.hip): 1 when it declined the current
+  // call and the Jacobi eigensolver must run; arrivals of its two
+  // workgroups (the second one runs the tail, then clears it); 1 when the
+  // Cholesky factorisation of the current call completed
+  int32_t cq_fallback;
+  int32_t cq_arrive;
+  int32_t cq_chol_ok;
+  int32_t cq_calls;  // calls it accepted
+  int32_t cq_off;    // set by a pass tail once the PVE ratio reached cq_switch x tol:
+                     // later blocks are orthonormalised by Jacobi eigSVD
 };
 
 // ------------------------------------------------------------------ launchers
@@ -231,6 +241,8 @@ struct EigArgs {
   double shape_feat[3];
   long long *prof;      // optional step profile (6 counters), null in the solver
   int32_t *trace_sweeps;  // sweeps of call c (c = state->eig_calls before this call), [cap + 2]
+  const int32_t *run_if;  // Jacobi only: when set, the call does nothing unless *run_if != 0
+  double cq_switch;       // pass tail: set state->cq_off once ratio <= cq_switch x tol (0: never)
 };
 // MLP of the learned shift (k_mlp.hip)
 struct MlpDims {
@@ -247,6 +259,15 @@ hipError_t mlp_backward(const MlpDims &d, const float *P, const float *X, const 
 hipError_t mlp_adam(float *P, const float *G, float *m, float *v, int64_t n, float lr, int t, hipStream_t st);
 
 hipError_t launch_eig(const EigArgs &a, hipStream_t st);
+// Orthonormalisation of a pass block (modes 1 and 2) without eigenvectors:
+// the Cholesky-QR weights W = R^-1 (G = R^T R) and S from the eigenvalues
+// of G, then the Jacobi eigensolver on the same arguments, which runs only
+// where the first one declined (G not safely positive definite).  Needs
+// a.state.
+hipError_t launch_eig_pass(const EigArgs &a, hipStream_t st);
+// the first kernel of launch_eig_pass alone (state->cq_fallback tells
+// whether it declined)
+hipError_t launch_cholqr(const EigArgs &a, hipStream_t st);
 // arr: count EigArgs in device memory, all with the same l; workgroup b
 // solves arr[b]
 hipError_t launch_eig_batched(const EigArgs *arr, int count, int l, hipStream_t st);

@@ -306,6 +306,7 @@ dashsvd_status dashsvd_set_options(dashsvd_handle *h, const dashsvd_options *opt
   if (o.precision < 0 || o.precision > 2) return fail(h, DASHSVD_ERR_INVALID_ARG, "precision");
   if (o.shift_policy < 0 || o.shift_policy > 4) return fail(h, DASHSVD_ERR_INVALID_ARG, "shift_policy");
   if (o.pve_mode < 0 || o.pve_mode > 1) return fail(h, DASHSVD_ERR_INVALID_ARG, "pve_mode");
+  if (o.eig_method < 0 || o.eig_method > 1) return fail(h, DASHSVD_ERR_INVALID_ARG, "eig_method");
   if (o.p_max < 0) o.p_max = kDefaultPmax;
   if (o.p_max > 100000) return fail(h, DASHSVD_ERR_INVALID_ARG, "p_max too large");
   h->sched.clear();
@@ -592,6 +593,17 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     HIPCHK(hipEventCreateWithFlags(&h->ev_eig, hipEventDisableTiming));
   }
   hipStream_t st2 = h->st2;
+  // Sketch and pass blocks: Cholesky-QR with eigenvalues (Jacobi where it
+  // declines), or Jacobi throughout.  Cholesky-QR keeps the span but not
+  // the principal (Ritz) basis, and the next block C = A Q of a
+  // non-principal Q has nearly collinear columns whose FP32 storage loses
+  // the small directions by about eps kappa(C).  The last two blocks before
+  // the final step fix the accuracy of its products, so they are always
+  // Jacobi: AUTO switches to Jacobi after the first pass whose PVE ratio is
+  // within kCqSwitch x tol (set on the device by the pass tail), and for
+  // the blocks of passes p_max - 1 and p_max.
+  const bool cholqr = h->opt.eig_method == DASHSVD_EIG_AUTO;
+  constexpr double kCqSwitch = 100.0;
   auto make_eig = [&](int mode) {
     EigArgs ea;
     std::memset(&ea, 0, sizeof(ea));
@@ -618,6 +630,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     ea.trace_s = b.tr_s;
     ea.trace_cap = cap;
     ea.trace_sweeps = b.tr_sweeps;
+    ea.cq_switch = cholqr ? kCqSwitch : 0.0;
     ea.sched = h->sched.empty() ? nullptr : b.sched;
     ea.sched_len = (int)h->sched.size();
     if (h->opt.shift_policy == DASHSVD_SHIFT_LEARNED && h->mlp.ok) {
@@ -667,7 +680,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       if ((e = hipEventRecord(h->ev_gram, st)) != hipSuccess) return e;
       if ((e = hipStreamWaitEvent(st2, h->ev_gram, 0)) != hipSuccess) return e;
       tmark_begin(h, DASHSVD_KT_EIG, pass, st2);
-      e = launch_eig(ea, st2);
+      e = cholqr && pass + 1 < pmax ? launch_eig_pass(ea, st2) : launch_eig(ea, st2);
       tmark_end(h, st2);
       if (e != hipSuccess) return e;
       if ((e = hipEventRecord(h->ev_eig, st2)) != hipSuccess) return e;
@@ -727,7 +740,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       ea.stagnation_guard = pcur == DASHSVD_BF16;
       const int32_t *skip = gate ? pass_skip : nullptr;
       tmark_begin(h, DASHSVD_KT_EIG, pass);
-      e = launch_eig(ea, st);
+      e = cholqr && pass + 1 < pmax ? launch_eig_pass(ea, st) : launch_eig(ea, st);
       tmark_end(h);
       if (e != hipSuccess) return e;
       tmark_begin(h, DASHSVD_KT_RESCALE, pass);
@@ -840,6 +853,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   inf.learned_fallback = hs.sched_off;
   inf.final_alpha = hs.alpha;
   inf.promoted = promoted;
+  inf.cholqr_calls = hs.cq_calls;
   inf.learned_n = hs.learned_ready ? hs.learned_n : 0;
   inf.long_row_used = T;
   inf.time_total_ms = t_end - t0;
@@ -1927,6 +1941,33 @@ dashsvd_status dashsvd_k_eig_prof(int32_t l, const double *G, double *S, double 
   ea.prof = prof;
   ea.mode = 0;
   HIPCHK(launch_eig(ea, (hipStream_t)stream));
+  return DASHSVD_OK;
+}
+
+dashsvd_status dashsvd_k_cholqr(int32_t l, const double *G, double *S, double *W, int32_t *accepted,
+                                void *stream) {
+  dashsvd_handle *h = nullptr;
+  if (l < 1 || l > DASHSVD_MAX_L || !G || !S || !W || !accepted)
+    return fail(h, DASHSVD_ERR_INVALID_ARG, "cholqr arguments");
+  hipStream_t st = (hipStream_t)stream;
+  SolverState *state = nullptr;
+  HIPCHK(hipMalloc(&state, sizeof(SolverState)));
+  EigArgs ea;
+  std::memset(&ea, 0, sizeof(ea));
+  ea.l = l;
+  ea.G = G;
+  ea.S = S;
+  ea.W = W;
+  ea.state = state;
+  ea.mode = 1;
+  int32_t fallback = 1;
+  hipError_t e = hipMemsetAsync(state, 0, sizeof(SolverState), st);
+  if (e == hipSuccess) e = launch_cholqr(ea, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&fallback, &state->cq_fallback, 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(state);
+  HIPCHK(e);
+  *accepted = fallback ? 0 : 1;
   return DASHSVD_OK;
 }
 

@@ -23,6 +23,7 @@ F32, F64, BF16 = 0, 1, 2
 PREC = {"fp32": 0, "fp64": 1, "bf16": 2}
 SHIFT = {"paper": 0, "none": 1, "fixed": 2, "schedule": 3, "learned": 4}
 PVE = {"r2": 0, "r1": 1}
+EIG = {"auto": 0, "jacobi": 1}
 MAX_L = 160
 MAX_TRACE = 256
 
@@ -44,7 +45,7 @@ class _Options(C.Structure):
                 ("p_max", C.c_int32), ("seed", C.c_uint64), ("hip_stream", C.c_void_p),
                 ("long_row", C.c_int32), ("check_interval", C.c_int32), ("schedule", C.c_void_p),
                 ("omega", C.c_void_p), ("omega_dtype", C.c_int32), ("omega_on_device", C.c_int32),
-                ("timing", C.c_int32), ("tuning_db", C.c_char_p)]
+                ("timing", C.c_int32), ("tuning_db", C.c_char_p), ("eig_method", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -58,7 +59,7 @@ class _Info(C.Structure):
                 ("eig_calls", C.c_int32), ("eig_sweeps", C.c_int32),
                 ("sweeps_per_call", C.c_int32 * (MAX_TRACE + 2)), ("long_row_used", C.c_int32),
                 ("learned_n", C.c_int32),
-                ("promoted", C.c_int32)]
+                ("promoted", C.c_int32), ("cholqr_calls", C.c_int32)]
 
 KT_NAMES = ["spmm", "spmm_t", "gram", "eig", "rescale", "transpose", "sketch", "final"]
 
@@ -73,7 +74,7 @@ EXPORTS = [
     "dashsvd_mlp_grad", "dashsvd_mlp_train_step", "dashsvd_learned_features", "dashsvd_workspace_size",
     "dashsvd_status_string",
     "dashsvd_last_error", "dashsvd_k_gaussian", "dashsvd_k_philox_raw", "dashsvd_k_transpose",
-    "dashsvd_k_spmm", "dashsvd_k_gram", "dashsvd_k_eig", "dashsvd_k_eig_prof", "dashsvd_k_rescale",
+    "dashsvd_k_spmm", "dashsvd_k_gram", "dashsvd_k_eig", "dashsvd_k_eig_prof", "dashsvd_k_cholqr", "dashsvd_k_rescale",
 ]
 
 
@@ -211,6 +212,7 @@ class Info:
     promoted: bool
     long_row_used: int
     learned_n: int
+    cholqr_calls: int
 
 
 class DashSVD:
@@ -219,17 +221,17 @@ class DashSVD:
     def __init__(self, precision: str = "fp32", shift_policy: str = "paper", pve_mode: str = "r2",
                  p_max: int = -1, seed: int = 0, stream=None, long_row: int = 0,
                  check_interval: int = 1, schedule=None, omega=None, timing: bool = False,
-                 tuning_db=None):
+                 tuning_db=None, eig_method: str = "auto"):
         self._h = C.c_void_p()
         self._keep = []
         opt = self._options(precision, shift_policy, pve_mode, p_max, seed, stream, long_row,
-                            check_interval, schedule, omega, timing, tuning_db)
+                            check_interval, schedule, omega, timing, tuning_db, eig_method)
         st = lib().dashsvd_create(C.byref(self._h), C.byref(opt))
         _check(st, None)
 
     def _options(self, precision="fp32", shift_policy="paper", pve_mode="r2", p_max=-1, seed=0,
                  stream=None, long_row=0, check_interval=1, schedule=None, omega=None,
-                 timing=False, tuning_db=None):
+                 timing=False, tuning_db=None, eig_method="auto"):
         sched_arr = None
         if schedule is not None:
             sched_arr = np.ascontiguousarray(schedule, dtype=np.float64)
@@ -245,7 +247,7 @@ class DashSVD:
                         stream or None, long_row, check_interval,
                         _ptr(sched_arr).value if sched_arr is not None else None,
                         om_ptr, om_dt, om_dev, int(bool(timing)),
-                        tuning_db.encode() if tuning_db else None)
+                        tuning_db.encode() if tuning_db else None, EIG[eig_method])
 
     def set_options(self, **kw):
         opt = self._options(**kw)
@@ -477,6 +479,15 @@ def k_eig(G, S, Vs, W, sweeps=None, stream=None):
                                _stream_ptr(stream)))
 
 
+def k_cholqr(G, S, W, stream=None) -> bool:
+    """Cholesky-QR weights W = R^-1 and S from the eigenvalues of G; True if
+    the kernel accepted G (else W and S are unspecified)."""
+    l = G.shape[0]
+    acc = C.c_int32(0)
+    _check(lib().dashsvd_k_cholqr(l, _ptr(G), _ptr(S), _ptr(W), C.byref(acc), _stream_ptr(stream)))
+    return bool(acc.value)
+
+
 def k_eig_prof(G, S, Vs, W, sweeps, prof, stream=None):
     """k_eig with the step profile (prof: device int64 tensor of 4)."""
     l = G.shape[0]
@@ -500,4 +511,4 @@ def _info_from(raw) -> Info:
                 raw.long_chunks_AT, dict(zip(KT_NAMES, list(raw.kt_ms))),
                 dict(zip(KT_NAMES, list(raw.kt_count))), raw.eig_calls, raw.eig_sweeps,
                 np.array(raw.sweeps_per_call[:min(raw.eig_calls, MAX_TRACE + 2)]),
-                bool(raw.promoted), raw.long_row_used, raw.learned_n)
+                bool(raw.promoted), raw.long_row_used, raw.learned_n, raw.cholqr_calls)

@@ -296,6 +296,74 @@ def test_eig_rank_deficient_zeroes_w(torch_dev):
     assert np.allclose(S.cpu().numpy()[:3], So[:3], rtol=1e-12)
 
 
+# ------------------------------------------------------------------ Cholesky-QR pass solver
+def _cholqr(torch, G):
+    from paper_2404_09276_amd import k_cholqr
+    l = G.shape[0]
+    S = torch.full((l,), -1.0, dtype=torch.float64, device="cuda")
+    W = torch.full((l, l), -1.0, dtype=torch.float64, device="cuda")
+    acc = k_cholqr(_dev(torch, G), S, W)
+    return acc, S.cpu().numpy(), W.cpu().numpy()
+
+
+@pytest.mark.parametrize("l", [1, 2, 3, 5, 16, 24, 30, 75, 120, 129, 150, 160])
+def test_cholqr_weights_and_values(torch_dev, l):
+    """W = R^-1 with G = R^T R (upper triangular, W^T G W = I) and S against
+    the oracle's Jacobi eigenvalues, on graded Gram matrices."""
+    rng = np.random.default_rng(300 + l)
+    B = rng.standard_normal((l + 7, l)) @ np.diag(np.logspace(0, -2, l))
+    G = B.T @ B
+    acc, s, Wm = _cholqr(torch_dev, G)
+    assert acc
+    assert np.all(np.tril(Wm, -1) == 0.0)
+    assert np.abs(Wm.T @ G @ Wm - np.eye(l)).max() <= 1e-10
+    # R = W^-1 is the Cholesky factor: its diagonal is positive
+    assert np.all(np.diag(Wm) > 0)
+    ev, _, _ = oracle.jacobi_eig(G)
+    ref = np.sqrt(np.maximum(ev[::-1], 0))
+    assert np.all(np.diff(s) <= 0)
+    assert np.abs(s**2 - ref**2).max() <= 100 * l * 2.2e-16 * ref[0] ** 2
+
+
+def test_cholqr_reduced_and_block_structure(torch_dev):
+    """Columns already reduced (diagonal and block-diagonal G) take the
+    reflector-free step; clustered eigenvalues keep their multiplicity."""
+    Gs = [np.diag([4.0, 9.0, 1.0, 16.0, 25.0]),
+          np.diag(np.r_[np.full(6, 2.0), np.full(6, 2.0 + 1e-9), [5.0]]),
+          np.kron(np.eye(4), np.array([[2.0, 1.0], [1.0, 3.0]]))]
+    for G in Gs:
+        l = G.shape[0]
+        acc, s, Wm = _cholqr(torch_dev, G)
+        assert acc
+        ev, _, _ = oracle.jacobi_eig(G)
+        assert np.allclose(s**2, ev[::-1], rtol=1e-14, atol=1e-15 * ev.max())
+        assert np.abs(Wm.T @ G @ Wm - np.eye(l)).max() <= 1e-13
+
+
+def test_cholqr_declines_ill_conditioned_and_singular(torch_dev):
+    """The kernel declines G with lambda_min <= 2^-32 lambda_max, singular G,
+    and G with a non-finite entry (the solver then runs Jacobi)."""
+    rng = np.random.default_rng(9)
+    Q, _ = np.linalg.qr(rng.standard_normal((20, 20)))
+    for lam_min in (1e-10, 0.0):
+        G = (Q * np.r_[np.ones(19), lam_min]) @ Q.T
+        G = 0.5 * (G + G.T)
+        acc, _, _ = _cholqr(torch_dev, G)
+        assert not acc
+    B = rng.standard_normal((40, 3)) @ rng.standard_normal((3, 8))
+    acc, _, _ = _cholqr(torch_dev, B.T @ B)
+    assert not acc
+    G = np.eye(6)
+    G[2, 2] = np.nan
+    acc, _, _ = _cholqr(torch_dev, G)
+    assert not acc
+    # just inside the accepted range: kappa = 2^30
+    G = (Q * np.r_[np.ones(19), 2.0**-30]) @ Q.T
+    acc, s, Wm = _cholqr(torch_dev, 0.5 * (G + G.T))
+    assert acc
+    assert abs(s[-1] ** 2 - 2.0**-30) <= 1e3 * 2.2e-16
+
+
 @pytest.mark.parametrize("r,l,c,odt", [(1000, 30, 30, "f32"), (777, 120, 120, "f32"), (300, 150, 100, "f32"),
                                        (5000, 150, 150, "bf16"), (500, 30, 20, "f64"), (65, 7, 3, "f32")])
 def test_rescale_matches_numpy(torch_dev, r, l, c, odt):

@@ -207,6 +207,8 @@ def test_rank_deficient_matrix(torch_dev):
     A = synth.dense_to_csr(D)
     U, S, V, st, info, tr = _solve(A, 4, 4, 3, 0.0, 1, "fp64")
     assert st == 2 and info.rank_deficient
+    # every pass block is singular: the Cholesky-QR solver declines them all
+    assert info.cholqr_calls == 0
     sv = np.linalg.svd(D, compute_uv=False)
     assert np.allclose(S[:3], sv[:3], rtol=1e-10)
 
@@ -250,3 +252,45 @@ def test_bf16_no_promotion_at_loose_tol(torch_dev):
     A = synth.config_small(np.float32)
     U, S, V, st, info, tr = _solve(A, 20, 10, 60, 5e-2, 2001, "bf16")
     assert not info.promoted and info.converged
+
+
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_eig_methods_agree(torch_dev, prec, bar):
+    """Pass blocks orthonormalised by Cholesky-QR with eigenvalues (AUTO) and
+    by the Jacobi eigSVD (JACOBI) give the same shifts, ratios, pass count
+    and singular values, both equal to the oracle's."""
+    A = synth.config_small(np.float64 if prec == "fp64" else np.float32)
+    ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 20, 10, 64, 1e-2, seed=2001)
+    out = {}
+    for meth in ("auto", "jacobi"):
+        U, S, V, st, info, tr = _solve(A, 20, 10, 64, 1e-2, 2001, prec, eig_method=meth)
+        assert st == 0 and info.converged
+        assert np.all(np.abs(S - ref.S) / ref.S <= bar)
+        out[meth] = (S, V, info)
+    Sa, Va, ia = out["auto"]
+    Sj, Vj, ij = out["jacobi"]
+    # Cholesky-QR from the sketch on; Jacobi for the last two pass blocks
+    # (the PVE ratio reached 100 tol two passes before the end) and the
+    # final step
+    assert 2 <= ia.cholqr_calls <= ia.eig_calls - 3 and ij.cholqr_calls == 0
+    assert list(ia.sweeps_per_call[:ia.cholqr_calls]) == [0] * ia.cholqr_calls
+    assert np.all(ia.sweeps_per_call[ia.cholqr_calls:] > 0)
+    assert ia.passes == ij.passes == ref.passes
+    assert np.allclose(ia.alpha_used, ij.alpha_used, rtol=bar)
+    assert np.allclose(ia.ratio, ij.ratio, rtol=100 * bar)
+    assert np.all(np.abs(Sa - Sj) / Sj <= bar)
+    assert _vec_close(Va, Vj, 1e-7 if prec == "fp64" else 2e-3)
+
+
+def test_eig_methods_zipf_fp32(torch_dev):
+    """Power-law matrix, FP32 form, k = 40, s = 20: both methods reach the
+    oracle's singular values within the FP32 bar in the same passes."""
+    A = synth.zipf_csr(20000, 12000, 300000, seed=31)
+    ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 40, 20, 64, 1e-2, seed=7)
+    passes = {}
+    for meth in ("auto", "jacobi"):
+        U, S, V, st, info, tr = _solve(A, 40, 20, 64, 1e-2, 7, "fp32", eig_method=meth)
+        assert st == 0
+        assert np.all(np.abs(S - ref.S) / ref.S <= 1e-5)
+        passes[meth] = info.passes
+    assert passes["auto"] == passes["jacobi"] == ref.passes
