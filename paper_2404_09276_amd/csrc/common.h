@@ -140,6 +140,9 @@ struct SolverState {
   double ratio;       // ratio of the last pass
   int32_t pass;       // passes executed
   int32_t done;       // set when the PVE check passes
+  int32_t cq_off;     // set by a pass tail once the PVE ratio reached cq_switch x tol:
+                      // later blocks are orthonormalised by Jacobi eigSVD (read by the
+                      // host together with done)
   int32_t converged;
   int32_t deficient;
   int32_t sched_off;  // schedule dropped (guard)
@@ -159,8 +162,9 @@ struct SolverState {
   int32_t cq_arrive;
   int32_t cq_chol_ok;
   int32_t cq_calls;  // calls it accepted
-  int32_t cq_off;    // set by a pass tail once the PVE ratio reached cq_switch x tol:
-                     // later blocks are orthonormalised by Jacobi eigSVD
+  // index of the last eigensolver call that has started on the device (the
+  // main stream holds its SpMMs back until the call is resident on its CU)
+  int32_t eig_started;
 };
 
 // ------------------------------------------------------------------ launchers
@@ -172,22 +176,16 @@ hipError_t launch_philox_raw(uint64_t seed, int64_t nwords, uint64_t *out, hipSt
 hipError_t launch_scan_i64(const int64_t *in, int64_t n, int64_t *out, int64_t *tmp, hipStream_t st);
 size_t scan_tmp_elems(int64_t n);
 
+// Validation of a CSR (flags[0] |= 1: malformed structure, |= 2: non-finite
+// value) with the row index of every nonzero.
 hipError_t launch_validate(int64_t m, int64_t n, int64_t nnz, const int64_t *rp, const int32_t *col,
-                           const void *val, int dtype, int64_t *colcnt, int32_t *rowidx,
-                           int32_t *flags, hipStream_t st);
-hipError_t launch_transpose_scatter(int64_t nnz, const int32_t *col, const int32_t *rowidx,
-                                    const int64_t *rowT, int32_t *cursor, int32_t *tmp_row,
-                                    int32_t *tmp_src, hipStream_t st);
-hipError_t launch_transpose_classify(int64_t n, const int64_t *rowT, const int32_t *tmp_row,
-                                     const int32_t *tmp_src, const void *val, int dtype,
-                                     int32_t *colT, void *valT, int32_t *lists, int32_t *counts,
-                                     hipStream_t st);
-hipError_t launch_transpose_sort(int64_t m, int64_t n, const int64_t *rowT, const int32_t *tmp_row,
-                                 const int32_t *tmp_src, const void *val, int dtype, int32_t *colT,
-                                 void *valT, const int32_t *lists, const int32_t *counts_host,
-                                 uint32_t *bitmap_ws, int32_t *prefix_ws, int nblk_large,
-                                 hipStream_t st);
-int64_t transpose_bitmap_words(int64_t m);
+                           const void *val, int dtype, int32_t *rowidx, int32_t *flags, hipStream_t st);
+// CSR(A^T) of a validated CSR (rowidx from launch_validate): workspace bytes
+// (sort keys, indices and the sort's own storage) and the build.
+size_t transpose_ws_bytes(int64_t n, int64_t nnz);
+hipError_t launch_transpose(int64_t n, int64_t nnz, const int32_t *col, const int32_t *rowidx, const void *val,
+                            int dtype, int64_t *rowT, int32_t *colT, void *valT, void *ws, size_t ws_bytes,
+                            hipStream_t st);
 
 hipError_t launch_plan_count(int64_t R, const int64_t *rp, int32_t long_row, int64_t *nch,
                              hipStream_t st);
@@ -243,7 +241,15 @@ struct EigArgs {
   int32_t *trace_sweeps;  // sweeps of call c (c = state->eig_calls before this call), [cap + 2]
   const int32_t *run_if;  // Jacobi only: when set, the call does nothing unless *run_if != 0
   double cq_switch;       // pass tail: set state->cq_off once ratio <= cq_switch x tol (0: never)
+  int32_t call_idx;       // > 0: store it to state->eig_started when the call starts working
 };
+// Store idx to *flag (agent scope): an eigensolver call has started.
+__device__ __forceinline__ void signal_started(int32_t *flag, int32_t idx) {
+  __hip_atomic_store(flag, idx, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+// One wave that returns once *flag >= expect, or after about 200 us (the
+// wait only orders dispatch; it never blocks the stream for longer).
+hipError_t launch_wait_started(const int32_t *flag, int32_t expect, hipStream_t st);
 // MLP of the learned shift (k_mlp.hip)
 struct MlpDims {
   int D, H;

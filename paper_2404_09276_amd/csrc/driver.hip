@@ -247,13 +247,10 @@ struct RunBufs {
   int32_t *colT = nullptr;
   void *valT = nullptr;
   // transposition temporaries
-  int64_t *colcnt = nullptr;
-  int32_t *rowidx = nullptr, *cursor = nullptr, *tmp_row = nullptr, *tmp_src = nullptr;
-  int32_t *lists = nullptr, *counts = nullptr, *flags = nullptr;
-  uint32_t *bitmap = nullptr;
-  int32_t *prefix = nullptr;
+  int32_t *rowidx = nullptr, *flags = nullptr;
+  void *tws = nullptr;  // CSR(A^T) build workspace
+  size_t tws_bytes = 0;
   int64_t *scan_tmp = nullptr;
-  int nblk_large = 0;
   Plan planM, planT;
   // panels
   void *Y = nullptr;   // M_m x ld, panel type (also Omega)
@@ -443,18 +440,10 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   b.rpT = (int64_t *)ar.take(8 * (size_t)(n + 1));
   b.colT = (int32_t *)ar.take(4 * (size_t)(nnz + 1));
   b.valT = ar.take(dsz(vdt) * (size_t)(nnz + 1));
-  b.colcnt = (int64_t *)ar.take(8 * (size_t)(n + 1));
   b.rowidx = (int32_t *)ar.take(4 * (size_t)(nnz + 1));
-  b.cursor = (int32_t *)ar.take(4 * (size_t)(n + 1));
-  b.tmp_row = (int32_t *)ar.take(4 * (size_t)(nnz + 1));
-  b.tmp_src = (int32_t *)ar.take(4 * (size_t)(nnz + 1));
-  b.lists = (int32_t *)ar.take(4 * (size_t)(3 * n + 1));
-  b.counts = (int32_t *)ar.take(4 * 8);
-  b.flags = b.counts + 4;
-  const int64_t words = transpose_bitmap_words(m);
-  b.nblk_large = 256;
-  b.bitmap = (uint32_t *)ar.take(4 * (size_t)words * b.nblk_large);
-  b.prefix = (int32_t *)ar.take(4 * (size_t)words * b.nblk_large);
+  b.flags = (int32_t *)ar.take(4 * 8);
+  b.tws_bytes = transpose_ws_bytes(n, nnz);
+  b.tws = ar.take(b.tws_bytes);
   const int64_t scan_n = (m > n ? m : n) + 1;
   b.scan_tmp = (int64_t *)ar.take(8 * scan_tmp_elems(scan_n));
   plan_alloc(h, ar, b.planM, Mm, nnz, T, ld, accsz);
@@ -499,9 +488,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   h->open_group = -1;
   // control buffers start at zero; panels need no clearing (pad columns are
   // never read into the first l columns)
-  HIPCHK(hipMemsetAsync(b.colcnt, 0, 8 * (size_t)(n + 1), st));
-  HIPCHK(hipMemsetAsync(b.cursor, 0, 4 * (size_t)(n + 1), st));
-  HIPCHK(hipMemsetAsync(b.counts, 0, 4 * 8, st));
+  HIPCHK(hipMemsetAsync(b.flags, 0, 4 * 8, st));
   HIPCHK(hipMemsetAsync(b.planM.nlong, 0, 16, st));
   HIPCHK(hipMemsetAsync(b.planT.nlong, 0, 16, st));
   HIPCHK(hipMemsetAsync(b.state, 0, sizeof(SolverState), st));
@@ -525,22 +512,14 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     valA = val_in;
   }
   tmark_begin(h, DASHSVD_KT_TRANSPOSE, 0);
-  HIPCHK(launch_validate(m, n, nnz, rpA, colA, valA, vdt, b.colcnt, b.rowidx, b.flags, st));
+  HIPCHK(launch_validate(m, n, nnz, rpA, colA, valA, vdt, b.rowidx, b.flags, st));
   int32_t hflags[4] = {0, 0, 0, 0};
   HIPCHK(hipMemcpyAsync(hflags, b.flags, sizeof(hflags), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (hflags[0] & 1) return fail(h, DASHSVD_ERR_BAD_CSR, "row_ptr/col_idx malformed");
   if (hflags[0] & 2) return fail(h, DASHSVD_ERR_NONFINITE, "NaN or Inf among the values");
   // CSR(A^T)
-  HIPCHK(launch_scan_i64(b.colcnt, n, b.rpT, b.scan_tmp, st));
-  HIPCHK(launch_transpose_scatter(nnz, colA, b.rowidx, b.rpT, b.cursor, b.tmp_row, b.tmp_src, st));
-  HIPCHK(launch_transpose_classify(n, b.rpT, b.tmp_row, b.tmp_src, valA, vdt, b.colT, b.valT, b.lists,
-                                   b.counts, st));
-  int32_t hcounts[4] = {0, 0, 0, 0};
-  HIPCHK(hipMemcpyAsync(hcounts, b.counts, sizeof(hcounts), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  HIPCHK(launch_transpose_sort(m, n, b.rpT, b.tmp_row, b.tmp_src, valA, vdt, b.colT, b.valT, b.lists, hcounts,
-                               b.bitmap, b.prefix, b.nblk_large, st));
+  HIPCHK(launch_transpose(n, nnz, colA, b.rowidx, valA, vdt, b.rpT, b.colT, b.valT, b.tws, b.tws_bytes, st));
   tmark_end(h);
   // M and M^T
   const int64_t *rpM = wide ? b.rpT : rpA;
@@ -648,15 +627,24 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   const int32_t *pass_skip = &b.state->pass_skip;
   const int every = h->opt.check_interval > 0 ? h->opt.check_interval : 1;
   // Host-side stop test after every `every` passes (tolerance runs only).
+  // Host copy of state->cq_off (read with done at each stop test): once set,
+  // the pass blocks go straight to the Jacobi eigensolver.
+  int32_t host_cq_off = 0;
   auto stopped = [&](int launched, bool &stop) -> hipError_t {
     stop = false;
     if (!(tol > 0.0 && launched < pmax)) return hipSuccess;
-    int32_t hd = 0;
-    hipError_t e = hipMemcpyAsync(&hd, done, 4, hipMemcpyDeviceToHost, st);
+    int32_t hd[2] = {0, 0};  // done, cq_off (adjacent)
+    hipError_t e = hipMemcpyAsync(hd, done, 8, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    stop = hd != 0;
+    stop = hd[0] != 0;
+    host_cq_off = hd[1];
     return e;
   };
+  auto launch_block_eig = [&](EigArgs &ea, int pass, hipStream_t s) -> hipError_t {
+    const bool cq = cholqr && !host_cq_off && pass + 1 < pmax;
+    return cq ? launch_eig_pass(ea, s) : launch_eig(ea, s);
+  };
+  int32_t eig_launches = 0;  // eigensolver calls launched beside the SpMMs (signal index)
   int last_pass = 0;  // passes whose eigSVD ran (the final block's C, Z, W)
   int promoted = 0;   // BF16 panels switched to FP32 by the stagnation guard
   void *Qfin = b.Q, *Yfin = b.Y;  // final Q and M Q (plain order)
@@ -676,14 +664,18 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       tmark_end(h);
       if (e != hipSuccess) return e;
       EigArgs ea = make_eig(mode);
+      ea.call_idx = ++eig_launches;
       const int32_t *skip = gate ? pass_skip : nullptr;
       if ((e = hipEventRecord(h->ev_gram, st)) != hipSuccess) return e;
       if ((e = hipStreamWaitEvent(st2, h->ev_gram, 0)) != hipSuccess) return e;
       tmark_begin(h, DASHSVD_KT_EIG, pass, st2);
-      e = cholqr && pass + 1 < pmax ? launch_eig_pass(ea, st2) : launch_eig(ea, st2);
+      e = launch_block_eig(ea, pass, st2);
       tmark_end(h, st2);
       if (e != hipSuccess) return e;
       if ((e = hipEventRecord(h->ev_eig, st2)) != hipSuccess) return e;
+      // The eigensolver needs whole CUs (1024 threads); the SpMMs would take
+      // every CU first, so they wait (bounded) until it is resident.
+      if ((e = launch_wait_started(&b.state->eig_started, ea.call_idx, st)) != hipSuccess) return e;
       tmark_begin(h, DASHSVD_KT_SPMM, pass);
       e = launch_spmm(Mm, rpM, colM, valM, vdt, Cin, ld, cdt, b.Z, ld, cdt, ld, b.planM.n_chunks, b.planM.tasks,
                       b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, skip, st);
@@ -740,7 +732,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       ea.stagnation_guard = pcur == DASHSVD_BF16;
       const int32_t *skip = gate ? pass_skip : nullptr;
       tmark_begin(h, DASHSVD_KT_EIG, pass);
-      e = cholqr && pass + 1 < pmax ? launch_eig_pass(ea, st) : launch_eig(ea, st);
+      e = launch_block_eig(ea, pass, st);
       tmark_end(h);
       if (e != hipSuccess) return e;
       tmark_begin(h, DASHSVD_KT_RESCALE, pass);
@@ -774,12 +766,13 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       }
       launched += chunk;
       if (tol > 0.0 && launched < pmax) {
-        int32_t flags[2] = {0, 0};  // done, promote
-        HIPCHK(hipMemcpyAsync(&flags[0], done, 4, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(&flags[1], &b.state->promote, 4, hipMemcpyDeviceToHost, st));
+        int32_t flags[3] = {0, 0, 0};  // done, cq_off, promote
+        HIPCHK(hipMemcpyAsync(&flags[0], done, 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(&flags[2], &b.state->promote, 4, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
+        host_cq_off = flags[1];
         if (flags[0]) break;
-        if (flags[1] && pcur == DASHSVD_BF16) {
+        if (flags[2] && pcur == DASHSVD_BF16) {
           pcur = cdt;
           Qc = b.Q32;
           Yc = b.Y32;
@@ -1091,18 +1084,10 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
   b.rpT = (int64_t *)ar.take(8 * (size_t)(n + 1));
   b.colT = (int32_t *)ar.take(4 * (size_t)(nnz + 1));
   b.valT = ar.take(dsz(vdt) * (size_t)(nnz + 1));
-  b.colcnt = (int64_t *)ar.take(8 * (size_t)(n + 1));
   b.rowidx = (int32_t *)ar.take(4 * (size_t)(nnz + 1));
-  b.cursor = (int32_t *)ar.take(4 * (size_t)(n + 1));
-  b.tmp_row = (int32_t *)ar.take(4 * (size_t)(nnz + 1));
-  b.tmp_src = (int32_t *)ar.take(4 * (size_t)(nnz + 1));
-  b.lists = (int32_t *)ar.take(4 * (size_t)(3 * n + 1));
-  b.counts = (int32_t *)ar.take(4 * 8);
-  b.flags = b.counts + 4;
-  const int64_t words = transpose_bitmap_words(m);
-  b.nblk_large = 256;
-  b.bitmap = (uint32_t *)ar.take(4 * (size_t)words * b.nblk_large);
-  b.prefix = (int32_t *)ar.take(4 * (size_t)words * b.nblk_large);
+  b.flags = (int32_t *)ar.take(4 * 8);
+  b.tws_bytes = transpose_ws_bytes(n, nnz);
+  b.tws = ar.take(b.tws_bytes);
   b.scan_tmp = (int64_t *)ar.take(8 * scan_tmp_elems(std::max(m, n) + 1));
   plan_alloc(h, ar, b.planM, m, nnz, T, ld, accsz);
   plan_alloc(h, ar, b.planT, n, nnz, T, ld, accsz);
@@ -1144,9 +1129,7 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
   }
 
   // ---------------------------------------------------------------- setup
-  HIPCHK(hipMemsetAsync(b.colcnt, 0, 8 * (size_t)(n + 1), st));
-  HIPCHK(hipMemsetAsync(b.cursor, 0, 4 * (size_t)(n + 1), st));
-  HIPCHK(hipMemsetAsync(b.counts, 0, 4 * 8, st));
+  HIPCHK(hipMemsetAsync(b.flags, 0, 4 * 8, st));
   HIPCHK(hipMemsetAsync(b.planM.nlong, 0, 16, st));
   HIPCHK(hipMemsetAsync(b.planT.nlong, 0, 16, st));
   HIPCHK(hipMemsetAsync(b.state, 0, sizeof(SolverState) * (size_t)count, st));
@@ -1173,21 +1156,13 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
   HIPCHK(hipMemcpyAsync(desc, hd.data(), sizeof(BMatDesc) * (size_t)count, hipMemcpyHostToDevice, st));
   HIPCHK(launch_bassemble(desc, count, max_rn, m, nnz, rpA, colA, val_raw, in_dt, on_dev ? 0 : 1, b.flags + 2, st));
   if (in_dt != vdt) HIPCHK(launch_convert(val_raw, in_dt, valA, vdt, nnz, st));
-  HIPCHK(launch_validate(m, n, nnz, rpA, colA, valA, vdt, b.colcnt, b.rowidx, b.flags, st));
+  HIPCHK(launch_validate(m, n, nnz, rpA, colA, valA, vdt, b.rowidx, b.flags, st));
   int32_t hflags[4] = {0, 0, 0, 0};
   HIPCHK(hipMemcpyAsync(hflags, b.flags, sizeof(hflags), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if ((hflags[0] & 1) || (hflags[2] & 1)) return fail(h, DASHSVD_ERR_BAD_CSR, "row_ptr/col_idx malformed");
   if (hflags[0] & 2) return fail(h, DASHSVD_ERR_NONFINITE, "NaN or Inf among the values");
-  HIPCHK(launch_scan_i64(b.colcnt, n, b.rpT, b.scan_tmp, st));
-  HIPCHK(launch_transpose_scatter(nnz, colA, b.rowidx, b.rpT, b.cursor, b.tmp_row, b.tmp_src, st));
-  HIPCHK(launch_transpose_classify(n, b.rpT, b.tmp_row, b.tmp_src, valA, vdt, b.colT, b.valT, b.lists, b.counts,
-                                   st));
-  int32_t hcounts[4] = {0, 0, 0, 0};
-  HIPCHK(hipMemcpyAsync(hcounts, b.counts, sizeof(hcounts), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  HIPCHK(launch_transpose_sort(m, n, b.rpT, b.tmp_row, b.tmp_src, valA, vdt, b.colT, b.valT, b.lists, hcounts,
-                               b.bitmap, b.prefix, b.nblk_large, st));
+  HIPCHK(launch_transpose(n, nnz, colA, b.rowidx, valA, vdt, b.rpT, b.colT, b.valT, b.tws, b.tws_bytes, st));
   Plan *plans[2] = {&b.planM, &b.planT};
   const int64_t *rps[2] = {rpA, b.rpT};
   for (int i = 0; i < 2; ++i) {
@@ -1811,45 +1786,29 @@ dashsvd_status dashsvd_k_transpose(int64_t m, int64_t n, int64_t nnz, const int6
   if (m < 1 || n < 1 || nnz < 0 || nnz > INT32_MAX || (dtype != 0 && dtype != 1))
     return fail(h, DASHSVD_ERR_INVALID_ARG, "transpose arguments");
   hipStream_t st = (hipStream_t)stream;
-  const int64_t words = transpose_bitmap_words(m);
-  const int nbl = 64;
-  size_t bytes[9] = {8 * (size_t)(n + 1), 4 * (size_t)(nnz + 1), 4 * (size_t)(n + 1), 4 * (size_t)(nnz + 1),
-                     4 * (size_t)(nnz + 1), 4 * (size_t)(3 * n + 1), 64, (size_t)(8 * (words * nbl + 1)),
-                     8 * scan_tmp_elems(n + 1)};
-  void *ptr[9] = {};
-  for (int i = 0; i < 9; ++i) {
+  const size_t tws_bytes = transpose_ws_bytes(n, nnz);
+  size_t bytes[3] = {4 * (size_t)(nnz + 1), 64, tws_bytes};
+  void *ptr[3] = {};
+  for (int i = 0; i < 3; ++i) {
     if (hipMalloc(&ptr[i], bytes[i]) != hipSuccess) {
       for (int j = 0; j < i; ++j) (void)hipFree(ptr[j]);
       return fail(h, DASHSVD_ERR_OOM, "transpose workspace");
     }
-    (void)hipMemsetAsync(ptr[i], 0, bytes[i], st);
   }
-  int64_t *colcnt = (int64_t *)ptr[0];
-  int32_t *rowidx = (int32_t *)ptr[1], *cursor = (int32_t *)ptr[2], *tmp_row = (int32_t *)ptr[3],
-          *tmp_src = (int32_t *)ptr[4], *lists = (int32_t *)ptr[5], *counts = (int32_t *)ptr[6];
-  uint32_t *bitmap = (uint32_t *)ptr[7];
-  int32_t *prefix = (int32_t *)((uint32_t *)ptr[7] + words * nbl);
-  int64_t *scan_tmp = (int64_t *)ptr[8];
+  int32_t *rowidx = (int32_t *)ptr[0], *flags = (int32_t *)ptr[1];
   dashsvd_status res = DASHSVD_OK;
   int32_t hc[4] = {0, 0, 0, 0};
-  hipError_t e = launch_validate(m, n, nnz, row_ptr, col, val, dtype, colcnt, rowidx, counts + 4, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(hc, counts + 4, 16, hipMemcpyDeviceToHost, st);
+  hipError_t e = hipMemsetAsync(flags, 0, 64, st);
+  if (e == hipSuccess) e = launch_validate(m, n, nnz, row_ptr, col, val, dtype, rowidx, flags, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(hc, flags, 16, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e == hipSuccess && (hc[0] & 1)) res = DASHSVD_ERR_BAD_CSR;
   else if (e == hipSuccess && (hc[0] & 2)) res = DASHSVD_ERR_NONFINITE;
   if (e == hipSuccess && res == DASHSVD_OK) {
-    e = launch_scan_i64(colcnt, n, rowT, scan_tmp, st);
-    if (e == hipSuccess) e = launch_transpose_scatter(nnz, col, rowidx, rowT, cursor, tmp_row, tmp_src, st);
-    if (e == hipSuccess)
-      e = launch_transpose_classify(n, rowT, tmp_row, tmp_src, val, dtype, colT, valT, lists, counts, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(hc, counts, 16, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e == hipSuccess)
-      e = launch_transpose_sort(m, n, rowT, tmp_row, tmp_src, val, dtype, colT, valT, lists, hc, bitmap, prefix, nbl,
-                                st);
+    e = launch_transpose(n, nnz, col, rowidx, val, dtype, rowT, colT, valT, ptr[2], tws_bytes, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
   }
-  for (int i = 0; i < 9; ++i) (void)hipFree(ptr[i]);
+  for (int i = 0; i < 3; ++i) (void)hipFree(ptr[i]);
   if (e != hipSuccess) return fail(h, DASHSVD_ERR_HIP, hipGetErrorString(e));
   if (res != DASHSVD_OK) return fail(h, res, "invalid CSR");
   return DASHSVD_OK;

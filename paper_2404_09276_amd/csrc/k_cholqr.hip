@@ -95,6 +95,8 @@ __global__ __launch_bounds__(kCqThreads) void k_cholqr(EigArgs a) {
   SolverState *state = a.state;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int l = a.l;
+  const bool handover = a.mode == 2 && !state->done && state->cq_off;
+  if (!handover && a.call_idx > 0 && blockIdx.x == 0 && tid == 0) signal_started(&state->eig_started, a.call_idx);
   if (a.mode == 2) {
     // a pass launched after the check already passed: nothing to do
     const int stopped = state->done;
@@ -103,8 +105,9 @@ __global__ __launch_bounds__(kCqThreads) void k_cholqr(EigArgs a) {
       if (stopped) state->cq_fallback = 0;
     }
     if (stopped) return;
-    // near the end of the run: the Jacobi eigensolver takes over
-    if (state->cq_off) {
+    // near the end of the run: the Jacobi eigensolver takes over (and
+    // signals its own start)
+    if (handover) {
       if (blockIdx.x == 0 && tid == 0) state->cq_fallback = 1;
       return;
     }
@@ -390,7 +393,21 @@ __global__ __launch_bounds__(kCqThreads) void k_cholqr(EigArgs a) {
   pass_tail(a, state, Ssh);
 }
 
+__global__ __launch_bounds__(kWave) void k_wait_started(const int32_t *flag, int32_t expect) {
+  // wall clock at 100 MHz: give up after 200 us
+  const long long t0 = wall_clock64();
+  while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < expect) {
+    if (wall_clock64() - t0 > 20000) break;
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_wait_started(const int32_t *flag, int32_t expect, hipStream_t st) {
+  hipLaunchKernelGGL(k_wait_started, dim3(1), dim3(kWave), 0, st, flag, expect);
+  return hipGetLastError();
+}
 
 hipError_t launch_cholqr(const EigArgs &a, hipStream_t st) {
   if (!a.state || a.l < 1 || a.l > kCqMaxL || (a.mode != 1 && a.mode != 2)) return hipErrorInvalidValue;

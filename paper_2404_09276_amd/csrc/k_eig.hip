@@ -116,6 +116,7 @@ __global__ __launch_bounds__(NT) void k_eig(EigArgs a0, const EigArgs *__restric
   const EigArgs &a = BATCHED ? arr[blockIdx.x] : a0;
   if (a.run_if && *a.run_if == 0) return;
   SolverState *state = a.state;
+  if (!BATCHED && state && a.call_idx > 0 && threadIdx.x == 0) signal_started(&state->eig_started, a.call_idx);
   if (state && a.mode == 2) {
     // a pass launched after the check already passed: nothing to do, and
     // its rescale must not run either
