@@ -9,14 +9,19 @@ CSR(A^T), SpMM plans, Omega, the sketch, the shifted power passes until the
 check passes, and the final Rayleigh-Ritz step.
 
 Printed: one JSON line with the metric, the roofline of the dominant kernel
-(the Jacobi eigensolver, whose time is measured with HIP events on the
-library's streams inside the timed region), the SpMM pair against HBM, the
-other forms of the metric (BF16 panels, learned shift, batched), and the CPU
-oracle timed on the host cores.
+(the SpMM, the two sparse products of every pass, timed with HIP events on
+the stream it runs on inside the timed region) with its counter traffic, the
+Jacobi eigensolver against the FP64 ALU of its one CU, the Cholesky-QR pass
+solver's time, the other forms of the metric (BF16 panels, learned shift,
+batched), and the CPU oracle timed on the host cores.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-forms]
   python bench.py --copy-probe   (a plain 1 GiB device copy, three times: the
                                   reference that calibrates the HBM counters)
+  python bench.py --summarize-trace STATS_CSV COMMAND > kernel_stats.md
+  python bench.py --summarize-pmc FETCH_CSV WRITE_CSV COPY_FETCH_CSV COPY_WRITE_CSV COMMANDS > traffic.txt
+                                 (the committed profile summaries, from the
+                                  rocprofv3 outputs of the commands given)
 """
 import argparse
 import hashlib
@@ -37,6 +42,7 @@ HBM_PEAK_GBS = 8000.0
 CU_FP64_TFLOPS = 78.6 / 256
 K, P, TOL, OMEGA_SEED = 100, 20, 1e-2, 2002
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_zipf_200k_fp32.txt")
+CSRC = os.path.join(ROOT, "paper_2404_09276_amd", "csrc")
 
 
 def spmm_bytes(m, n, nnz, l, b_val=4, b_idx=4, b_ptr=8, b_x=4, b_y=4):
@@ -146,8 +152,13 @@ def cpu_baseline(A, min_seconds=10.0):
                       f"mean seconds per solve"}
 
 
-def traffic():
-    """HBM bytes per launch of the eigensolver from the committed rocprofv3
+def source_digest(name):
+    return hashlib.sha256(open(os.path.join(CSRC, name), "rb").read()).hexdigest()
+
+
+def traffic(kind):
+    """HBM bytes per launch of a kernel ("spmm": one SpMM, k_spmm and its
+    long-row kernel; "eig": one Jacobi call) from the committed rocprofv3
     counter summary (FETCH_SIZE + WRITE_SIZE, calibrated on a copy kernel),
     or None when it is missing or the kernel source changed since."""
     if not os.path.exists(TRAFFIC_FILE):
@@ -157,11 +168,103 @@ def traffic():
         parts = line.split()
         if len(parts) == 2 and not line.startswith("#"):
             t[parts[0]] = parts[1]
-    src = os.path.join(ROOT, "paper_2404_09276_amd", "csrc", "k_eig.hip")
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if t.get("k_eig_sha256") != digest or "k_eig_bytes_per_launch" not in t:
+    src = {"spmm": "k_spmm.hip", "eig": "k_eig.hip"}[kind]
+    if t.get(f"{kind}_sha256") != source_digest(src) or f"{kind}_bytes_per_launch" not in t:
         return None
-    return float(t["k_eig_bytes_per_launch"])
+    return float(t[f"{kind}_bytes_per_launch"])
+
+
+def short_name(name):
+    """Kernel name without namespaces and argument list."""
+    base = name[5:] if name.startswith("void ") else name
+    for ns in ("dsv::(anonymous namespace)::", "dsv::"):
+        base = base.replace(ns, "")
+    return base.split("(")[0].strip()
+
+
+def summarize_trace(stats_csv, command):
+    """Markdown table of a rocprofv3 --stats kernel summary."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    out = ["| kernel | calls | total ms | average us | % of GPU time |", "|---|---:|---:|---:|---:|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        if float(r["TotalDurationNs"]) < 1e-3 * tot:
+            continue
+        out.append(f"| `{short_name(r['Name'])[:80]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                   f"{float(r['AverageNs']) / 1e3:.1f} | {100 * float(r['TotalDurationNs']) / tot:.2f} |")
+    print(f"Command (from /tmp; R = repository root):\n\n    {command}\n")
+    print("\n".join(out))
+
+
+def summarize_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, commands):
+    """Per-kernel HBM traffic per dispatch from FETCH_SIZE and WRITE_SIZE
+    runs, each calibrated by what the counter reads for a plain copy of known
+    size; the lines the benchmark reads (per-launch bytes and the source
+    digests they belong to) come last."""
+    import csv
+
+    def per_kernel(path):
+        acc = {}
+        for r in csv.DictReader(open(path)):
+            acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return acc
+
+    def copy_kib(path):
+        vals = [v for k, vs in per_kernel(path).items() if "copyBuffer" in k for v in vs]
+        return max(vals)
+
+    probe_bytes = (1 << 28) * 4
+    fcal = probe_bytes / 1024.0 / copy_kib(copy_fetch_csv)
+    wcal = probe_bytes / 1024.0 / copy_kib(copy_write_csv)
+    fk, wk = per_kernel(fetch_csv), per_kernel(write_csv)
+    rows = []
+    for name in fk:
+        if name not in wk or "rocclr" in name:
+            continue
+        f, w = np.mean(fk[name]), np.mean(wk[name])
+        rows.append((short_name(name), len(fk[name]), f, w, (fcal * f + wcal * w) * 1024 / 1e6, fk[name], wk[name]))
+    rows.sort(key=lambda r: -r[4] * r[1])
+    print("# HBM traffic per dispatch, zipf_200k workload (200000 x 100000, 10M nnz, k=100, oversampling 20,")
+    print("# FP32 panels, tol 1e-2), one bench step; MI355X, rocprofv3 counter collection.")
+    print("# Commands (run from /tmp; R = repository root):")
+    for c in commands:
+        print(f"#   {c}")
+    print(f"# Calibration: a plain 1 GiB device copy reads FETCH_SIZE = {probe_bytes / 1024 / fcal:.1f} KiB and")
+    print(f"# WRITE_SIZE = {probe_bytes / 1024 / wcal:.1f} KiB per launch, so bytes = {fcal:.4f} x FETCH_SIZE x 1024"
+          f" + {wcal:.4f} x WRITE_SIZE x 1024.")
+    print("# FETCH_SIZE counts L2 misses, which the 256 MB last-level cache may still serve: an upper bound on HBM reads.")
+    print("#")
+    print(f"# {'kernel':56s} {'dispatches':>10s} {'FETCH_KiB':>11s} {'WRITE_KiB':>11s} {'calibrated_MB':>14s}")
+    for name, cnt, f, w, mb, _, _ in rows:
+        print(f"# {name[:56]:56s} {cnt:10d} {f:11.1f} {w:11.1f} {mb:14.2f}")
+    print("#")
+    spmm = [r for r in rows if r[0].startswith("k_spmm<")]
+    spmm_long = [r for r in rows if r[0].startswith("k_spmm_long<")]
+    # one SpMM launch = k_spmm + its long-row kernel (mean over the dispatches)
+    spmm_b = sum(r[4] * r[1] for r in spmm) / max(1, sum(r[1] for r in spmm))
+    spmm_b += sum(r[4] * r[1] for r in spmm_long) / max(1, sum(r[1] for r in spmm))
+    # Jacobi calls: dispatches that did work (the gated launches behind an
+    # accepted Cholesky-QR call return at once and read almost nothing)
+    eig_f, eig_w = [], []
+    for name, cnt, f, w, mb, fl, wl in rows:
+        if name.startswith("k_eig<"):
+            for a, b in zip(fl, wl):
+                if a > 16.0:
+                    eig_f.append(a)
+                    eig_w.append(b)
+    eig_b = (fcal * np.mean(eig_f) + wcal * np.mean(eig_w)) * 1024 if eig_f else 0.0
+    print("# One SpMM launch = k_spmm + k_spmm_long (means over their dispatches); one Jacobi call = the k_eig")
+    print("# dispatches that read more than 16 KiB (the others are gated launches that returned at once).")
+    print(f"# Algorithmic bytes per launch for comparison: SpMM (A C) {spmm_bytes(200000, 100000, 10**7, 120) / 1e6:.1f} MB,"
+          f" SpMM (A^T Z) {spmm_bytes(100000, 200000, 10**7, 120) / 1e6:.1f} MB.")
+    print(f"fetch_calibration {fcal:.6f}")
+    print(f"write_calibration {wcal:.6f}")
+    print(f"spmm_sha256 {source_digest('k_spmm.hip')}")
+    print(f"spmm_bytes_per_launch {spmm_b * 1e6:.0f}")
+    print(f"eig_sha256 {source_digest('k_eig.hip')}")
+    print(f"eig_bytes_per_launch {eig_b:.0f}")
+    print(f"eig_calls_counted {len(eig_f)}")
 
 
 def main():
@@ -172,7 +275,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("STATS_CSV", "COMMAND"))
+    ap.add_argument("--summarize-pmc", nargs="+", metavar="ARG")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_pmc:
+        a = args.summarize_pmc
+        summarize_pmc(a[0], a[1], a[2], a[3], a[4:])
+        return
     if args.copy_probe:
         import torch
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -198,18 +310,20 @@ def main():
     tot = {g: sum(i.kt_ms[g] for i in infos) for g in infos[0].kt_ms}
     cnt = {g: sum(i.kt_count[g] for i in infos) for g in infos[0].kt_count}
     avg = {g: (tot[g] / cnt[g] if cnt[g] else 0.0) for g in tot}
-    dom = max(("spmm", "spmm_t", "gram", "eig", "rescale", "transpose", "final"), key=lambda g: tot[g])
-    # eigensolver: algorithmic FP64 flops of its sweeps over its event time
-    sweeps = sum(i.eig_sweeps for i in infos)
-    eig_ms = sum(i.kt_ms["eig"] for i in infos)
-    eig_tf = jacobi_flops(l, sweeps) / (eig_ms * 1e-3) / 1e12 if eig_ms else 0.0
-    # SpMM pair against HBM
+    dom = max(("spmm", "spmm_t", "gram", "eig", "cholqr", "rescale", "transpose", "final"), key=lambda g: tot[g])
+    # dominant kernel, the SpMM: algorithmic bytes of the two products of a
+    # pass over their event time (one launch = k_spmm and its long-row kernel)
     b1 = spmm_bytes(A.m, A.n, A.nnz, l)
     b2 = spmm_bytes(A.n, A.m, A.nnz, l)
     gbs1 = b1 / (avg["spmm"] * 1e-3) / 1e9 if avg["spmm"] else 0.0
     gbs2 = b2 / (avg["spmm_t"] * 1e-3) / 1e9 if avg["spmm_t"] else 0.0
     pair_ms = avg["spmm"] + avg["spmm_t"]
-    achieved_pair = (b1 + b2) / (pair_ms * 1e-3) / 1e9 if pair_ms else 0.0
+    achieved = (b1 + b2) / (pair_ms * 1e-3) / 1e9 if pair_ms else 0.0
+    # Jacobi eigensolver calls (the last pass blocks and the final step):
+    # algorithmic FP64 flops of their sweeps over their event time
+    sweeps = sum(i.eig_sweeps for i in infos)
+    eig_ms = tot["eig"]
+    eig_tf = jacobi_flops(l, sweeps) / (eig_ms * 1e-3) / 1e12 if eig_ms else 0.0
     out = {
         "metric": METRIC, "value": ms / 1e3, "unit": "s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": False, "scaling": "weak",
@@ -218,20 +332,22 @@ def main():
                                "k=100, oversampling 20, PVE tol 1e-2, FP32 panels",
                    "form": "plain FP32", "passes": inf.passes, "converged": inf.converged,
                    "eps_pve": pve, "eps_sigma": es, "eig_calls": inf.eig_calls,
-                   "eig_sweeps": inf.eig_sweeps,
+                   "cholqr_calls": inf.cholqr_calls, "eig_sweeps": inf.eig_sweeps,
                    "sweeps_per_call": [int(x) for x in inf.sweeps_per_call]},
-        "roofline": {"bound": "alu", "kernel": "k_eig (Jacobi eigensolver of eigSVD, one workgroup)",
-                     "achieved": eig_tf, "peak": CU_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": eig_tf / CU_FP64_TFLOPS, "traffic": traffic(),
-                     "flops_per_sweep": jacobi_flops(l, 1), "sweeps_timed": sweeps,
-                     "avg_ms_per_launch": avg["eig"],
-                     "peak_basis": "FP64 vector peak of the one CU the kernel runs on (78.6 TFLOP/s / 256)"},
-        "roofline_spmm": {"bound": "hbm", "kernel": "SpMM pair per pass (Z = A C; X = A^T Z)",
-                          "achieved": achieved_pair, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": achieved_pair / HBM_PEAK_GBS,
-                          "bytes_per_launch": {"spmm": b1, "spmm_t": b2},
-                          "avg_ms": {"spmm": avg["spmm"], "spmm_t": avg["spmm_t"]},
-                          "gbs": {"spmm": gbs1, "spmm_t": gbs2}},
+        "roofline": {"bound": "hbm", "kernel": "SpMM (k_spmm + k_spmm_long), the two products of a pass",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic("spmm"),
+                     "bytes_per_launch": {"spmm": b1, "spmm_t": b2},
+                     "avg_ms": {"spmm": avg["spmm"], "spmm_t": avg["spmm_t"]},
+                     "gbs": {"spmm": gbs1, "spmm_t": gbs2}},
+        "roofline_eig": {"bound": "alu", "kernel": "k_eig (Jacobi eigSVD, one workgroup)",
+                         "achieved": eig_tf, "peak": CU_FP64_TFLOPS, "unit": "TFLOP/s",
+                         "frac": eig_tf / CU_FP64_TFLOPS, "traffic": traffic("eig"),
+                         "flops_per_sweep": jacobi_flops(l, 1), "sweeps_timed": sweeps,
+                         "avg_ms_per_launch": avg["eig"],
+                         "peak_basis": "FP64 vector peak of the one CU the kernel runs on (78.6 TFLOP/s / 256)"},
+        "cholqr": {"kernel": "k_cholqr (Cholesky-QR weights and Sturm-bisection eigenvalues, two workgroups)",
+                   "calls_per_step": cnt["cholqr"] / args.steps, "avg_ms_per_launch": avg["cholqr"]},
         "kernel_groups_ms_per_step": {g: tot[g] / args.steps for g in tot},
         "dominant_group": dom,
     }

@@ -140,12 +140,13 @@ typedef struct {
 #define DASHSVD_KT_SPMM 0        /* M times a panel: Z = M C (FP32/FP64 forms) or Y = M Q (BF16 form) */
 #define DASHSVD_KT_SPMM_T 1      /* M^T times a panel: X = M^T Z, or C = M^T Y - alpha Q (BF16 form) */
 #define DASHSVD_KT_GRAM 2        /* Gram partials + reduction (every eigSVD) */
-#define DASHSVD_KT_EIG 3         /* eigensolver + tail (every eigSVD or Cholesky-QR block) */
+#define DASHSVD_KT_EIG 3         /* Jacobi eigSVD + tail */
 #define DASHSVD_KT_RESCALE 4     /* C+ = (X - alpha C) W, or Q = C W (BF16 form) */
 #define DASHSVD_KT_TRANSPOSE 5   /* validation + CSR(A^T) build */
 #define DASHSVD_KT_SKETCH 6      /* Omega + M^T Omega */
 #define DASHSVD_KT_FINAL 7       /* B = M Q, its eigSVD, U, V, signs */
-#define DASHSVD_KT_GROUPS 8
+#define DASHSVD_KT_CHOLQR 8      /* Cholesky-QR + eigenvalue blocks (eig_method AUTO) */
+#define DASHSVD_KT_GROUPS 9
 
 typedef struct {
   int32_t passes;          /* N_p: shifted power passes executed */
@@ -163,8 +164,9 @@ typedef struct {
   double time_final_ms;    /* final Rayleigh-Ritz and sign normalisation */
   int64_t long_chunks_A;   /* SpMM chunk tasks of the row-split plan, A side */
   int64_t long_chunks_AT;  /* same for A^T */
-  double kt_ms[8];         /* summed HIP-event time per kernel group (timing = 1) */
-  int32_t kt_count[8];     /* launches counted per group (passes after the stop excluded) */
+  double kt_ms[DASHSVD_KT_GROUPS];     /* summed HIP-event time per kernel group (timing = 1) */
+  int32_t kt_count[DASHSVD_KT_GROUPS]; /* launches counted per group (passes after the stop
+                                          excluded) */
   int32_t eig_calls;       /* eigSVD eigenproblems solved in the run */
   int32_t eig_sweeps;      /* Jacobi sweeps summed over them (Cholesky-QR calls count 0) */
   int32_t sweeps_per_call[DASHSVD_MAX_TRACE + 2]; /* sweeps of eigSVD call c: the sketch (c = 0),

@@ -642,7 +642,10 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   };
   auto launch_block_eig = [&](EigArgs &ea, int pass, hipStream_t s) -> hipError_t {
     const bool cq = cholqr && !host_cq_off && pass + 1 < pmax;
-    return cq ? launch_eig_pass(ea, s) : launch_eig(ea, s);
+    tmark_begin(h, cq ? DASHSVD_KT_CHOLQR : DASHSVD_KT_EIG, pass, s);
+    const hipError_t e = cq ? launch_eig_pass(ea, s) : launch_eig(ea, s);
+    tmark_end(h, s);
+    return e;
   };
   int32_t eig_launches = 0;  // eigensolver calls launched beside the SpMMs (signal index)
   int last_pass = 0;  // passes whose eigSVD ran (the final block's C, Z, W)
@@ -668,9 +671,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       const int32_t *skip = gate ? pass_skip : nullptr;
       if ((e = hipEventRecord(h->ev_gram, st)) != hipSuccess) return e;
       if ((e = hipStreamWaitEvent(st2, h->ev_gram, 0)) != hipSuccess) return e;
-      tmark_begin(h, DASHSVD_KT_EIG, pass, st2);
       e = launch_block_eig(ea, pass, st2);
-      tmark_end(h, st2);
       if (e != hipSuccess) return e;
       if ((e = hipEventRecord(h->ev_eig, st2)) != hipSuccess) return e;
       // The eigensolver needs whole CUs (1024 threads); the SpMMs would take
@@ -731,9 +732,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       EigArgs ea = make_eig(mode);
       ea.stagnation_guard = pcur == DASHSVD_BF16;
       const int32_t *skip = gate ? pass_skip : nullptr;
-      tmark_begin(h, DASHSVD_KT_EIG, pass);
       e = launch_block_eig(ea, pass, st);
-      tmark_end(h);
       if (e != hipSuccess) return e;
       tmark_begin(h, DASHSVD_KT_RESCALE, pass);
       e = launch_rescale(Mn, l, b.C, ld, cdt, b.W, l, l, Qc, ld, pcur, skip, st);

@@ -55,13 +55,13 @@ class _Info(C.Structure):
                 ("ratio", C.c_double * MAX_TRACE), ("time_total_ms", C.c_double),
                 ("time_setup_ms", C.c_double), ("time_loop_ms", C.c_double),
                 ("time_final_ms", C.c_double), ("long_chunks_A", C.c_int64),
-                ("long_chunks_AT", C.c_int64), ("kt_ms", C.c_double * 8), ("kt_count", C.c_int32 * 8),
+                ("long_chunks_AT", C.c_int64), ("kt_ms", C.c_double * 9), ("kt_count", C.c_int32 * 9),
                 ("eig_calls", C.c_int32), ("eig_sweeps", C.c_int32),
                 ("sweeps_per_call", C.c_int32 * (MAX_TRACE + 2)), ("long_row_used", C.c_int32),
                 ("learned_n", C.c_int32),
                 ("promoted", C.c_int32), ("cholqr_calls", C.c_int32)]
 
-KT_NAMES = ["spmm", "spmm_t", "gram", "eig", "rescale", "transpose", "sketch", "final"]
+KT_NAMES = ["spmm", "spmm_t", "gram", "eig", "rescale", "transpose", "sketch", "final", "cholqr"]
 
 
 _lib = None
