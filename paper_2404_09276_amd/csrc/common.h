@@ -320,6 +320,9 @@ hipError_t launch_rescale(int64_t r, int l, const void *C, int64_t ldc, int cdty
                           const double *alpha = nullptr);
 
 // pmax: nblk*k doubles, pidx: nblk*k int64 followed by k floats (workspace)
+// C (m x n) = op(A) B for small FP64 matrices (op(A) = A^T if transA)
+hipError_t launch_small_gemm(int m, int n, int kk, const double *A, int lda, int transA, const double *B, int ldb,
+                             double *C, int ldc, hipStream_t st);
 hipError_t launch_sign_fix(int64_t rowsV, int64_t rowsU, int k, void *V, int64_t ldv, void *U,
                            int64_t ldu, int dtype, void *pmax, void *pidx, int nblk,
                            hipStream_t st);

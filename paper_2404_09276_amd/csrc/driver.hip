@@ -261,6 +261,7 @@ struct RunBufs {
   void *X = nullptr;   // M_n x ld, C type: M^T M C of the current block (overlapped order)
   void *Q32 = nullptr, *Y32 = nullptr;  // FP32 panels after a BF16 promotion
   double *gpart = nullptr, *G = nullptr, *W = nullptr, *Vs = nullptr, *S = nullptr, *Sprev = nullptr;
+  double *G2 = nullptr, *T2 = nullptr, *W2 = nullptr, *PU = nullptr, *PV = nullptr;  // final step
   SolverState *state = nullptr;
   double *tr_alpha = nullptr, *tr_ratio = nullptr, *tr_s = nullptr;
   int32_t *tr_sweeps = nullptr;
@@ -462,6 +463,11 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   b.G = (double *)ar.take(8 * (size_t)l * l);
   b.W = (double *)ar.take(8 * (size_t)l * l);
   b.Vs = (double *)ar.take(8 * (size_t)l * l);
+  b.G2 = (double *)ar.take(8 * (size_t)l * l);
+  b.T2 = (double *)ar.take(8 * (size_t)l * l);
+  b.W2 = (double *)ar.take(8 * (size_t)l * l);
+  b.PU = (double *)ar.take(8 * (size_t)l * l);
+  b.PV = (double *)ar.take(8 * (size_t)l * l);
   b.S = (double *)ar.take(8 * (size_t)l);
   b.Sprev = (double *)ar.take(8 * (size_t)l);
   b.state = (SolverState *)ar.take(sizeof(SolverState));
@@ -792,32 +798,44 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   // final Rayleigh-Ritz (steps 9-11): B = M Q ; eigSVD(B) ; U = B W(:,1:k) ;
   // V = Q Vs(:,1:k).
   tmark_begin(h, DASHSVD_KT_FINAL, 0);
-  void *Qf = b.Q, *Bf = b.B;
   if (pdt == cdt) {
-    // the last block: C (its buffer alternates with the pass), Z = M C and
-    // W; Q = C W and B = Z W
+    // Overlapped order: the last block C (its buffer alternates with the
+    // pass), Z = M C and W, with Q = C W and B = M Q = Z W never formed:
+    //   B^T B = W^T (Z^T Z) W,  U = B W_B = Z (W W_B),  V = Q V_B = C (W V_B)
+    // (W_B, V_B the final eigSVD's weights and eigenvectors): one Gram of Z,
+    // l x l FP64 products, and one rescale each for U and V.
     void *Cl = (last_pass & 1) ? b.Q : b.C;
-    Qf = (last_pass & 1) ? b.C : b.Q;
-    HIPCHK(launch_rescale(Mn, l, Cl, ld, cdt, b.W, l, l, Qf, ld, pdt, nullptr, st));
-    HIPCHK(launch_rescale(Mm, l, b.Z, ld, cdt, b.W, l, l, b.B, ld, cdt, nullptr, st));
-  } else if (pfin != cdt) {
-    // the BF16 form keeps an FP32 B
-    HIPCHK(launch_spmm(Mm, rpM, colM, valM, vdt, Qfin, ld, pfin, b.B, ld, cdt, ld, b.planM.n_chunks,
-                       b.planM.tasks, b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr,
-                       nullptr, st));
-    Qf = Qfin;
+    HIPCHK(launch_gram(Mm, l, b.Z, ld, cdt, b.gpart, nb_m, b.G2, nullptr, st, nullptr));
+    HIPCHK(launch_small_gemm(l, l, l, b.G2, l, 0, b.W, l, b.T2, l, st));
+    HIPCHK(launch_small_gemm(l, l, l, b.W, l, 1, b.T2, l, b.G, l, st));
+    {
+      EigArgs ea = make_eig(3);
+      ea.W = b.W2;
+      HIPCHK(launch_eig(ea, st));
+    }
+    HIPCHK(launch_small_gemm(l, k, l, b.W, l, 0, b.W2, l, b.PU, k, st));
+    HIPCHK(launch_small_gemm(l, k, l, b.W, l, 0, b.Vs, l, b.PV, k, st));
+    HIPCHK(launch_rescale(Mm, l, b.Z, ld, cdt, b.PU, k, k, b.Uo, k, cdt, nullptr, st));
+    HIPCHK(launch_rescale(Mn, l, Cl, ld, cdt, b.PV, k, k, b.Vo, k, cdt, nullptr, st));
   } else {
-    // promoted to FP32 panels: B is the last M Q
-    Bf = Yfin;
-    Qf = Qfin;
+    void *Qf = Qfin, *Bf = b.B;
+    if (pfin != cdt) {
+      // the BF16 form keeps an FP32 B
+      HIPCHK(launch_spmm(Mm, rpM, colM, valM, vdt, Qfin, ld, pfin, b.B, ld, cdt, ld, b.planM.n_chunks,
+                         b.planM.tasks, b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr,
+                         nullptr, st));
+    } else {
+      // promoted to FP32 panels: B is the last M Q
+      Bf = Yfin;
+    }
+    HIPCHK(launch_gram(Mm, l, Bf, ld, cdt, b.gpart, nb_m, b.G, nullptr, st, nullptr));
+    {
+      EigArgs ea = make_eig(3);
+      HIPCHK(launch_eig(ea, st));
+    }
+    HIPCHK(launch_rescale(Mm, l, Bf, ld, cdt, b.W, l, k, b.Uo, k, cdt, nullptr, st));
+    HIPCHK(launch_rescale(Mn, l, Qf, ld, pfin, b.Vs, l, k, b.Vo, k, cdt, nullptr, st));
   }
-  HIPCHK(launch_gram(Mm, l, Bf, ld, cdt, b.gpart, nb_m, b.G, nullptr, st, nullptr));
-  {
-    EigArgs ea = make_eig(3);
-    HIPCHK(launch_eig(ea, st));
-  }
-  HIPCHK(launch_rescale(Mm, l, Bf, ld, cdt, b.W, l, k, b.Uo, k, cdt, nullptr, st));
-  HIPCHK(launch_rescale(Mn, l, Qf, ld, pdt == cdt ? pdt : pfin, b.Vs, l, k, b.Vo, k, cdt, nullptr, st));
   HIPCHK(launch_sign_fix(Mn, Mm, k, b.Vo, k, b.Uo, k, cdt, b.sgn_max, b.sgn_idx, sgn_blk, st));
   tmark_end(h);
   SolverState hs;

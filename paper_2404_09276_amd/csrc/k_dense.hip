@@ -561,4 +561,29 @@ hipError_t launch_convert(const void *in, int idtype, void *out, int odtype, int
   return launch_copy2d(in, 1, idtype, out, 1, odtype, n, 1, st);
 }
 
+// ------------------------------------------------------------------ small FP64 products
+// C (m x n) = op(A) B with op(A) = A (m x kk, lda) or A^T (A kk x m, lda),
+// B kk x n (ldb); one thread per entry, sums in index order.
+__global__ __launch_bounds__(256) void k_small_gemm(int m, int n, int kk, const double *__restrict__ A, int lda,
+                                                    int transA, const double *__restrict__ B, int ldb,
+                                                    double *__restrict__ C, int ldc) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * n) return;
+  const int i = idx / n, j = idx - i * n;
+  double s = 0.0;
+  if (transA)
+    for (int t = 0; t < kk; ++t) s = fma(A[(int64_t)t * lda + i], B[(int64_t)t * ldb + j], s);
+  else
+    for (int t = 0; t < kk; ++t) s = fma(A[(int64_t)i * lda + t], B[(int64_t)t * ldb + j], s);
+  C[(int64_t)i * ldc + j] = s;
+}
+
+hipError_t launch_small_gemm(int m, int n, int kk, const double *A, int lda, int transA, const double *B, int ldb,
+                             double *C, int ldc, hipStream_t st) {
+  if (m < 1 || n < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_small_gemm, dim3((m * n + 255) / 256), dim3(256), 0, st, m, n, kk, A, lda, transA, B, ldb,
+                     C, ldc);
+  return hipGetLastError();
+}
+
 }  // namespace dsv
