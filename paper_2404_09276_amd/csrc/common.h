@@ -323,6 +323,11 @@ hipError_t launch_rescale(int64_t r, int l, const void *C, int64_t ldc, int cdty
 // C (m x n) = op(A) B for small FP64 matrices (op(A) = A^T if transA)
 hipError_t launch_small_gemm(int m, int n, int kk, const double *A, int lda, int transA, const double *B, int ldb,
                              double *C, int ldc, hipStream_t st);
+// Sign normalisation of V (entry of largest magnitude positive per column,
+// lowest row on ties) with the same flips applied to the columns of P
+// (prow x k, FP64), the weights that form U afterwards.
+hipError_t launch_sign_fold(int64_t rowsV, int k, void *V, int64_t ldv, int dtype, double *P, int prow, int ldp,
+                            void *pmax, void *pidx, int nblk, hipStream_t st);
 hipError_t launch_sign_fix(int64_t rowsV, int64_t rowsU, int k, void *V, int64_t ldv, void *U,
                            int64_t ldu, int dtype, void *pmax, void *pidx, int nblk,
                            hipStream_t st);

@@ -815,8 +815,11 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     }
     HIPCHK(launch_small_gemm(l, k, l, b.W, l, 0, b.W2, l, b.PU, k, st));
     HIPCHK(launch_small_gemm(l, k, l, b.W, l, 0, b.Vs, l, b.PV, k, st));
-    HIPCHK(launch_rescale(Mm, l, b.Z, ld, cdt, b.PU, k, k, b.Uo, k, cdt, nullptr, st));
+    // V first; its sign normalisation flips V and the columns of W W_B, so
+    // U comes out with the matching signs
     HIPCHK(launch_rescale(Mn, l, Cl, ld, cdt, b.PV, k, k, b.Vo, k, cdt, nullptr, st));
+    HIPCHK(launch_sign_fold(Mn, k, b.Vo, k, cdt, b.PU, l, k, b.sgn_max, b.sgn_idx, sgn_blk, st));
+    HIPCHK(launch_rescale(Mm, l, b.Z, ld, cdt, b.PU, k, k, b.Uo, k, cdt, nullptr, st));
   } else {
     void *Qf = Qfin, *Bf = b.B;
     if (pfin != cdt) {
@@ -835,8 +838,8 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     }
     HIPCHK(launch_rescale(Mm, l, Bf, ld, cdt, b.W, l, k, b.Uo, k, cdt, nullptr, st));
     HIPCHK(launch_rescale(Mn, l, Qf, ld, pfin, b.Vs, l, k, b.Vo, k, cdt, nullptr, st));
+    HIPCHK(launch_sign_fix(Mn, Mm, k, b.Vo, k, b.Uo, k, cdt, b.sgn_max, b.sgn_idx, sgn_blk, st));
   }
-  HIPCHK(launch_sign_fix(Mn, Mm, k, b.Vo, k, b.Uo, k, cdt, b.sgn_max, b.sgn_idx, sgn_blk, st));
   tmark_end(h);
   SolverState hs;
   HIPCHK(hipMemcpyAsync(&hs, b.state, sizeof(hs), hipMemcpyDeviceToHost, st));

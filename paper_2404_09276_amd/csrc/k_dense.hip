@@ -339,24 +339,62 @@ __global__ __launch_bounds__(256) void k_sign_partial(int64_t rows, int k, const
 
 // One block: combine the per-block partial maxima in block order and store
 // the sign of each column (+1 / -1) before any element is flipped.
+// Column c = blockIdx.x: the largest |V| over the nblk partial maxima
+// (lowest row on ties) by a tree in LDS, then the sign of that entry.
 template <typename T>
 __global__ __launch_bounds__(256) void k_sign_select(int k, const T *__restrict__ V, int64_t ldv,
                                                      const double *__restrict__ pmax,
                                                      const int64_t *__restrict__ pidx, int nblk,
                                                      float *__restrict__ sgn) {
-  for (int c = threadIdx.x; c < k; c += blockDim.x) {
-    double best = -1.0;
-    int64_t bi = INT64_MAX;
-    for (int b = 0; b < nblk; ++b) {
-      const double a = pmax[(int64_t)b * k + c];
-      const int64_t ii = pidx[(int64_t)b * k + c];
-      if (a > best || (a == best && ii < bi)) {
-        best = a;
-        bi = ii;
+  __shared__ double sm[256];
+  __shared__ int64_t si[256];
+  const int c = blockIdx.x, t = threadIdx.x;
+  double best = -1.0;
+  int64_t bi = INT64_MAX;
+  for (int b = t; b < nblk; b += blockDim.x) {
+    const double a = pmax[(int64_t)b * k + c];
+    const int64_t ii = pidx[(int64_t)b * k + c];
+    if (a > best || (a == best && ii < bi)) {
+      best = a;
+      bi = ii;
+    }
+  }
+  sm[t] = best;
+  si[t] = bi;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (t < h) {
+      const double a = sm[t + h];
+      const int64_t ii = si[t + h];
+      if (a > sm[t] || (a == sm[t] && ii < si[t])) {
+        sm[t] = a;
+        si[t] = ii;
       }
     }
-    sgn[c] = (bi != INT64_MAX && to_d(V[bi * ldv + c]) < 0.0) ? -1.0f : 1.0f;
+    __syncthreads();
   }
+  if (t == 0) sgn[c] = (si[0] != INT64_MAX && to_d(V[si[0] * ldv + c]) < 0.0) ? -1.0f : 1.0f;
+}
+
+// Columns of one matrix times the signs.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sign_cols(int64_t rows, int k, T *__restrict__ V, int64_t ldv,
+                                                   const float *__restrict__ sgn) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < rows * k; e += stride) {
+    const int64_t i = e / k;
+    const int c = (int)(e - i * k);
+    if (sgn[c] < 0.f) V[i * ldv + c] = -V[i * ldv + c];
+  }
+}
+
+// Columns of a small FP64 matrix times the signs.
+__global__ __launch_bounds__(256) void k_sign_small(int rows, int k, double *__restrict__ P, int ldp,
+                                                    const float *__restrict__ sgn) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * k) return;
+  const int i = e / k, c = e - i * k;
+  if (sgn[c] < 0.f) P[(int64_t)i * ldp + c] = -P[(int64_t)i * ldp + c];
 }
 
 template <typename T>
@@ -527,14 +565,14 @@ hipError_t launch_sign_fix(int64_t rowsV, int64_t rowsU, int k, void *V, int64_t
   if (dtype == 1) {
     hipLaunchKernelGGL(k_sign_partial<double>, dim3(nblk), dim3(256), 0, st, rowsV, k, (const double *)V, ldv,
                        pmax, pidx);
-    hipLaunchKernelGGL(k_sign_select<double>, dim3(1), dim3(256), 0, st, k, (const double *)V, ldv, pmax, pidx,
+    hipLaunchKernelGGL(k_sign_select<double>, dim3(k), dim3(256), 0, st, k, (const double *)V, ldv, pmax, pidx,
                        nblk, sgn);
     hipLaunchKernelGGL(k_sign_apply<double>, dim3(ga), dim3(256), 0, st, rowsV, rowsU, k, (double *)V, ldv,
                        (double *)U, ldu, sgn);
   } else {
     hipLaunchKernelGGL(k_sign_partial<float>, dim3(nblk), dim3(256), 0, st, rowsV, k, (const float *)V, ldv,
                        pmax, pidx);
-    hipLaunchKernelGGL(k_sign_select<float>, dim3(1), dim3(256), 0, st, k, (const float *)V, ldv, pmax, pidx,
+    hipLaunchKernelGGL(k_sign_select<float>, dim3(k), dim3(256), 0, st, k, (const float *)V, ldv, pmax, pidx,
                        nblk, sgn);
     hipLaunchKernelGGL(k_sign_apply<float>, dim3(ga), dim3(256), 0, st, rowsV, rowsU, k, (float *)V, ldv,
                        (float *)U, ldu, sgn);
@@ -564,25 +602,62 @@ hipError_t launch_convert(const void *in, int idtype, void *out, int odtype, int
 // ------------------------------------------------------------------ small FP64 products
 // C (m x n) = op(A) B with op(A) = A (m x kk, lda) or A^T (A kk x m, lda),
 // B kk x n (ldb); one thread per entry, sums in index order.
+// 16 x 16 output tiles, the inner dimension staged through LDS in tiles of 16.
 __global__ __launch_bounds__(256) void k_small_gemm(int m, int n, int kk, const double *__restrict__ A, int lda,
                                                     int transA, const double *__restrict__ B, int ldb,
                                                     double *__restrict__ C, int ldc) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= m * n) return;
-  const int i = idx / n, j = idx - i * n;
+  __shared__ double As[16][17], Bs[16][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int i = blockIdx.y * 16 + ty, j = blockIdx.x * 16 + tx;
   double s = 0.0;
-  if (transA)
-    for (int t = 0; t < kk; ++t) s = fma(A[(int64_t)t * lda + i], B[(int64_t)t * ldb + j], s);
-  else
-    for (int t = 0; t < kk; ++t) s = fma(A[(int64_t)i * lda + t], B[(int64_t)t * ldb + j], s);
-  C[(int64_t)i * ldc + j] = s;
+  for (int t0 = 0; t0 < kk; t0 += 16) {
+    // As[ty][tx] = op(A)(blockIdx.y*16 + ty, t0 + tx); Bs[ty][tx] = B(t0 + ty, j)
+    const int ai = blockIdx.y * 16 + ty, at = t0 + tx;
+    double av = 0.0;
+    if (ai < m && at < kk) av = transA ? A[(int64_t)at * lda + ai] : A[(int64_t)ai * lda + at];
+    As[ty][tx] = av;
+    const int bt = t0 + ty;
+    Bs[ty][tx] = (bt < kk && j < n) ? B[(int64_t)bt * ldb + j] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 16; ++t) s = fma(As[ty][t], Bs[t][tx], s);
+    __syncthreads();
+  }
+  if (i < m && j < n) C[(int64_t)i * ldc + j] = s;
 }
 
 hipError_t launch_small_gemm(int m, int n, int kk, const double *A, int lda, int transA, const double *B, int ldb,
                              double *C, int ldc, hipStream_t st) {
   if (m < 1 || n < 1) return hipSuccess;
-  hipLaunchKernelGGL(k_small_gemm, dim3((m * n + 255) / 256), dim3(256), 0, st, m, n, kk, A, lda, transA, B, ldb,
-                     C, ldc);
+  hipLaunchKernelGGL(k_small_gemm, dim3((n + 15) / 16, (m + 15) / 16), dim3(256), 0, st, m, n, kk, A, lda, transA, B,
+                     ldb, C, ldc);
+  return hipGetLastError();
+}
+
+// Signs of the columns of V (the entry of largest magnitude made positive,
+// lowest row on ties), applied to V and to the columns of the small FP64
+// matrix P (the weights that form U from its block).
+hipError_t launch_sign_fold(int64_t rowsV, int k, void *V, int64_t ldv, int dtype, double *P, int prow, int ldp,
+                            void *pmax_v, void *pidx_v, int nblk, hipStream_t st) {
+  double *pmax = static_cast<double *>(pmax_v);
+  int64_t *pidx = static_cast<int64_t *>(pidx_v);
+  float *sgn = reinterpret_cast<float *>(pidx + (int64_t)nblk * k);
+  if (k < 1 || k > 256) return hipErrorInvalidValue;
+  const int ga = grid_for(rowsV * k, 256, 4096);
+  if (dtype == 1) {
+    hipLaunchKernelGGL(k_sign_partial<double>, dim3(nblk), dim3(256), 0, st, rowsV, k, (const double *)V, ldv,
+                       pmax, pidx);
+    hipLaunchKernelGGL(k_sign_select<double>, dim3(k), dim3(256), 0, st, k, (const double *)V, ldv, pmax, pidx,
+                       nblk, sgn);
+    hipLaunchKernelGGL(k_sign_cols<double>, dim3(ga), dim3(256), 0, st, rowsV, k, (double *)V, ldv, sgn);
+  } else {
+    hipLaunchKernelGGL(k_sign_partial<float>, dim3(nblk), dim3(256), 0, st, rowsV, k, (const float *)V, ldv,
+                       pmax, pidx);
+    hipLaunchKernelGGL(k_sign_select<float>, dim3(k), dim3(256), 0, st, k, (const float *)V, ldv, pmax, pidx,
+                       nblk, sgn);
+    hipLaunchKernelGGL(k_sign_cols<float>, dim3(ga), dim3(256), 0, st, rowsV, k, (float *)V, ldv, sgn);
+  }
+  hipLaunchKernelGGL(k_sign_small, dim3((prow * k + 255) / 256), dim3(256), 0, st, prow, k, P, ldp, sgn);
   return hipGetLastError();
 }
 
