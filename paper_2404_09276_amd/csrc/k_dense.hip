@@ -11,8 +11,8 @@
 //
 // Rescale Out = C W (Alg. 3 step 3, and U = B W_B, V = Q V_B of Alg. 5
 // step 11).  FP32 / BF16 path: W (l x c) is converted to FP32 once per block
-// into LDS; the block walks 64-row strips of C staged in LDS and each
-// wavefront computes a 16-row strip of all output tiles with
+// into LDS; each wavefront walks 16-row tiles of C, loading its A operand
+// straight from memory, and computes all output tiles of its rows with
 // v_mfma_f32_16x16x4.  FP64 path: plain FP64 FMAs (used for the FP64 form).
 //
 // MFMA operand layout (16x16x4, one block): lane L holds A[L%16][L/16] and
@@ -164,8 +164,24 @@ __global__ __launch_bounds__(256) void k_gram_reduce(int l, int nblocks, const d
 }
 
 // ------------------------------------------------------------------ rescale
-constexpr int kStrip = 64;
+// Four consecutive elements of an FP32 or BF16 row (one 16- or 8-byte load).
+__device__ __forceinline__ float4 load4f(const float *p) { return *reinterpret_cast<const float4 *>(p); }
+__device__ __forceinline__ float4 load4f(const bf16 *p) {
+  const uint2 u = *reinterpret_cast<const uint2 *>(p);
+  return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u), __uint_as_float(u.y << 16),
+                     __uint_as_float(u.y & 0xffff0000u));
+}
 
+// FP32 MFMA rescale.  W (LK x WC, FP32) is staged once per block in LDS;
+// each wavefront then walks 16-row tiles of C on its own (no block
+// barriers after the staging).  For a k-slab of 16, lane L loads the four
+// consecutive elements k0 + 4(L/16) .. +3 of row L%16 with one vector load
+// and feeds them to four MFMA steps; step s uses k = k0 + 4(L/16) + s in
+// both operands (a permutation of the k order inside the slab), so the A
+// operand never goes through LDS.  The next slab's loads are issued before
+// the current slab's MFMAs.  Columns k >= l of C are masked to zero (pad
+// columns may hold anything); with R, the input is C - alpha R, formed in
+// FP64 and rounded once.
 template <typename TC, typename TO, int LTO>
 __global__ __launch_bounds__(256) void k_rescale_mfma(int64_t r, int l, const TC *__restrict__ C,
                                                       int64_t ldc, const double *__restrict__ W,
@@ -174,93 +190,80 @@ __global__ __launch_bounds__(256) void k_rescale_mfma(int64_t r, int l, const TC
                                                       const TC *__restrict__ R,
                                                       const double *__restrict__ alpha) {
   if (done && *done) return;
-  // with R: the input rows are C - alpha R (R laid out like C), formed in
-  // FP64 and rounded once
   const double a_sh = R ? *alpha : 0.0;
   constexpr int WC = LTO * 16;
   constexpr int SW = WC + 4;
   extern __shared__ float lds[];
-  const int LK = (l + 3) & ~3;
-  const int SC = LK + 1;
-  float *Ws = lds;                 // LK x SW
-  float *Cs = lds + LK * SW;       // kStrip x SC
+  const int LK = (l + 15) & ~15;  // k-slabs of 16
+  float *Ws = lds;                // LK x SW
   for (int idx = threadIdx.x; idx < LK * WC; idx += 256) {
     const int kk = idx / WC, cc = idx - kk * WC;
     Ws[kk * SW + cc] = (kk < l && cc < c) ? (float)W[(int64_t)kk * ldw + cc] : 0.0f;
   }
+  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t nstrips = (r + kStrip - 1) / kStrip;
-  for (int64_t strip = blockIdx.x; strip < nstrips; strip += gridDim.x) {
-    const int64_t rb = strip * kStrip;
-    __syncthreads();
-    if constexpr (sizeof(TC) == 4) {
-      // FP32 rows: 16-byte loads (ldc is a multiple of 8, LK of 4); columns
-      // at or beyond l are replaced by zero (pad columns may hold anything)
-      const int LK4 = LK / 4;
-      for (int idx = threadIdx.x; idx < kStrip * LK4; idx += 256) {
-        const int rr = idx / LK4, k4 = (idx - rr * LK4) * 4;
-        const int64_t row = rb + rr;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (row < r) v = *reinterpret_cast<const float4 *>(C + row * ldc + k4);
-        if (R && row < r) {
-          const float4 w = *reinterpret_cast<const float4 *>(R + row * ldc + k4);
-          v.x = (float)((double)v.x - a_sh * (double)w.x);
-          v.y = (float)((double)v.y - a_sh * (double)w.y);
-          v.z = (float)((double)v.z - a_sh * (double)w.z);
-          v.w = (float)((double)v.w - a_sh * (double)w.w);
-        }
-        float *dst = Cs + rr * SC + k4;
-        dst[0] = k4 < l ? v.x : 0.0f;
-        dst[1] = k4 + 1 < l ? v.y : 0.0f;
-        dst[2] = k4 + 2 < l ? v.z : 0.0f;
-        dst[3] = k4 + 3 < l ? v.w : 0.0f;
+  const int lr = lane & 15, kq = lane >> 4;  // A row, k quad
+  const int64_t ntiles = (r + 15) / 16;
+  const int nslab = LK / 16;
+  auto load_slab = [&](int64_t row, int k0) -> float4 {
+    const int kb = k0 + 4 * kq;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (row < r && kb < l) {
+      // ld is a multiple of 8 and kb of 4: the vector stays inside the row
+      v = load4f(C + row * ldc + kb);
+      if (R) {
+        const float4 w = load4f(R + row * ldc + kb);
+        v.x = (float)((double)v.x - a_sh * (double)w.x);
+        v.y = (float)((double)v.y - a_sh * (double)w.y);
+        v.z = (float)((double)v.z - a_sh * (double)w.z);
+        v.w = (float)((double)v.w - a_sh * (double)w.w);
       }
-    } else {
-      for (int idx = threadIdx.x; idx < kStrip * LK; idx += 256) {
-        const int rr = idx / LK, kk = idx - rr * LK;
-        const int64_t row = rb + rr;
-        double x = 0.0;
-        if (row < r && kk < l) {
-          x = to_d(C[row * ldc + kk]);
-          if (R) x -= a_sh * to_d(R[row * ldc + kk]);
-        }
-        Cs[rr * SC + kk] = (float)x;
-      }
+      if (kb + 1 >= l) v.y = 0.f;
+      if (kb + 2 >= l) v.z = 0.f;
+      if (kb + 3 >= l) v.w = 0.f;
     }
-    __syncthreads();
+    return v;
+  };
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
+    const int64_t row = tile * 16 + lr;
     f4 acc[LTO];
 #pragma unroll
     for (int J = 0; J < LTO; ++J) acc[J] = f4{0.f, 0.f, 0.f, 0.f};
-    const float *arow = Cs + (wave * 16 + (lane & 15)) * SC + (lane >> 4);
-    const float *bcol = Ws + (lane >> 4) * SW + (lane & 15);
-    for (int k0 = 0; k0 < LK; k0 += 4) {
-      const float a = arow[k0];
+    float4 cur = load_slab(row, 0);
+    for (int sl = 0; sl < nslab; ++sl) {
+      const int k0 = sl * 16;
+      const float4 nxt = sl + 1 < nslab ? load_slab(row, k0 + 16) : make_float4(0.f, 0.f, 0.f, 0.f);
+      const float av[4] = {cur.x, cur.y, cur.z, cur.w};
 #pragma unroll
-      for (int J = 0; J < LTO; ++J) {
-        const float b = bcol[k0 * SW + J * 16];
-        acc[J] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[J], 0, 0, 0);
+      for (int s_ = 0; s_ < 4; ++s_) {
+        const float *bw = Ws + (k0 + 4 * kq + s_) * SW + lr;
+#pragma unroll
+        for (int J = 0; J < LTO; ++J)
+          acc[J] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s_], bw[J * 16], acc[J], 0, 0, 0);
       }
+      cur = nxt;
     }
-    const int64_t rbase = rb + wave * 16 + 4 * (lane >> 4);
+    const int64_t rbase = tile * 16 + 4 * kq;
 #pragma unroll
     for (int J = 0; J < LTO; ++J) {
-      const int col = J * 16 + (lane & 15);
+      const int col = J * 16 + lr;
       if (col < ldo) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int64_t row = rbase + q;
+          const int64_t orow = rbase + q;
           float v = acc[J][q];
           asm volatile("" : "+v"(v));
-          if (row < r) elem<TO>::st(Out + row * ldo + col, col < c ? v : 0.0f);
+          if (orow < r) elem<TO>::st(Out + orow * ldo + col, col < c ? v : 0.0f);
         }
       }
     }
-    // columns beyond the tiles (ldo > LTO*16) are zero
-    for (int idx = threadIdx.x; idx < kStrip * (int)(ldo > WC ? ldo - WC : 0); idx += 256) {
-      const int extra = (int)(ldo - WC);
-      const int rr = idx / extra, cc = WC + idx % extra;
-      const int64_t row = rb + rr;
-      if (row < r) elem<TO>::st(Out + row * ldo + cc, 0.0f);
+    // columns beyond the tiles (ldo > WC) are zero
+    if (ldo > WC) {
+      for (int q = 0; q < 4; ++q) {
+        const int64_t orow = rbase + q;
+        if (orow < r)
+          for (int64_t cc = WC + lr; cc < ldo; cc += 16) elem<TO>::st(Out + orow * ldo + cc, 0.0f);
+      }
     }
   }
 }
@@ -468,16 +471,18 @@ hipError_t rescale_dispatch(int64_t r, int l, const TC *C, int64_t ldc, const do
                             int c, TO *Out, int64_t ldo, const int32_t *done, const TC *R,
                             const double *alpha, hipStream_t st) {
   const int LTO = (c + 15) / 16;
-  const int LK = (l + 3) & ~3;
-  const int64_t nstrips = (r + kStrip - 1) / kStrip;
-  int grid = (int)(nstrips < 512 ? nstrips : 512);
-  if (grid < 1) grid = 1;
-#define DSV_RS(LTV)                                                                             \
-  case LTV: {                                                                                   \
-    const size_t shm = sizeof(float) * ((size_t)LK * (LTV * 16 + 4) + (size_t)kStrip * (LK + 1)); \
+  const int LK = (l + 15) & ~15;
+  const int64_t ntiles = (r + 15) / 16;
+  // blocks of four wavefronts, each wavefront on its own 16-row tiles
+  int64_t g = (ntiles + 3) / 4;
+  if (g > 512) g = 512;
+  const int grid = (int)(g < 1 ? 1 : g);
+#define DSV_RS(LTV)                                                                         \
+  case LTV: {                                                                               \
+    const size_t shm = sizeof(float) * (size_t)LK * (LTV * 16 + 4);                         \
     hipLaunchKernelGGL((k_rescale_mfma<TC, TO, LTV>), dim3(grid), dim3(256), shm, st, r, l, C, ldc, W, \
-                       ldw, c, Out, ldo, done, R, alpha);                                       \
-    break;                                                                                      \
+                       ldw, c, Out, ldo, done, R, alpha);                                   \
+    break;                                                                                  \
   }
   switch (LTO) {
     DSV_RS(1) DSV_RS(2) DSV_RS(3) DSV_RS(4) DSV_RS(5)
