@@ -3,11 +3,13 @@
 //
 // Gram G = C^T C (Alg. 3 step 1), FP64 accumulation on the FP64 matrix
 // cores: the l columns are cut into T = ceil(l/16) tiles and only the
-// T(T+1)/2 upper tiles are computed.  A 256-thread block stages 32 rows of C
-// in LDS as FP64 (FP32 inputs convert exactly), and each wavefront owns a
-// fixed set of upper tiles, issuing v_mfma_f64_16x16x4 per tile per 4 rows.
-// Every block writes its partial tiles; a second kernel sums the partials in
-// block order (deterministic) and mirrors the upper triangle.
+// T(T+1)/2 upper tiles are computed.  The four wavefronts of a block walk the
+// same rows of C four at a time, each owning a fixed set of upper tiles: a
+// lane loads its element of every column tile straight into a register
+// (FP32 and BF16 inputs convert to FP64 exactly), and that register is the A
+// or B operand of v_mfma_f64_16x16x4 for every tile in that tile row or
+// column.  Every block writes its partial tiles; a second kernel sums the
+// partials in block order (deterministic) and mirrors the upper triangle.
 //
 // Rescale Out = C W (Alg. 3 step 3, and U = B W_B, V = Q V_B of Alg. 5
 // step 11).  FP32 / BF16 path: W (l x c) is converted to FP32 once per block
@@ -29,8 +31,112 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 
 // ------------------------------------------------------------------ Gram
-constexpr int kGramRows = 32;
+// Tile t of the upper triangle, numbered row by row: (tile_i, tile_j), i <= j.
+constexpr int tile_i(int LT, int t) {
+  int I = 0;
+  while (t >= LT - I) {
+    t -= LT - I;
+    ++I;
+  }
+  return I;
+}
+constexpr int tile_j(int LT, int t) { return t - (tile_i(LT, t) * (2 * LT - tile_i(LT, t) + 1)) / 2 + tile_i(LT, t); }
 
+// One k-step (4 rows) of the tiles owned by wavefront WV: tiles WV, WV+4, ...
+// v[c] holds this lane's element of column tile c (row L/16, column L%16),
+// which is its A operand for a tile in row c and its B operand for a tile in
+// column c.  Unrolled at compile time so that v and acc stay in registers.
+template <int LT, int WV, int I, int TPW>
+__device__ __forceinline__ void gram_step(const double (&v)[LT], d4 (&acc)[TPW]) {
+  constexpr int t = WV + 4 * I;
+  if constexpr (I < TPW && t < LT * (LT + 1) / 2) {
+    constexpr int a = tile_i(LT, t), b = tile_j(LT, t);
+    double y = v[b];
+    // A diagonal tile must not feed the same VGPR pair as both operands (an
+    // FP64 MFMA given that returned wrong rows 8-15 on gfx950): make the B
+    // copy opaque so it lives in a register of its own.
+    if constexpr (a == b) asm volatile("" : "+v"(y));
+    acc[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[a], y, acc[I], 0, 0, 0);
+    gram_step<LT, WV, I + 1, TPW>(v, acc);
+  }
+}
+
+// Raw buffer loads over the block's rows: an offset at or past the end of
+// the range reads zero (the hardware range check), so rows past the block
+// need no mask.  Word 3 of the descriptor is the gfx9 raw-buffer format.
+constexpr int kBufWord3 = 0x00020000;
+__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, int off, const float *) {
+  return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, int off, const double *) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, int off, const bf16 *) {
+  return (double)__uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0) << 16);
+}
+
+// Rows [row0, row1) of the block, k-steps of 4 rows, loads kept
+// kGramPrefetch steps ahead in registers.  Columns past l are zeroed after
+// the load (pad columns may hold anything).
+constexpr int kGramPrefetch = 4;
+
+template <typename TC, int LT, int WV>
+__device__ __forceinline__ void gram_wave(int64_t row0, int64_t row1, int l, const TC *__restrict__ C,
+                                          int64_t ldc, double *__restrict__ out) {
+  constexpr int NT = LT * (LT + 1) / 2;
+  constexpr int TPW = (NT + 3) / 4;
+  const int lane = threadIdx.x & 63;
+  const int kr = lane >> 4, kc = lane & 15;
+  d4 acc[TPW];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+  // the range ends at the last element of the block: column l-1 of row row1-1
+  const int64_t nbytes = ((row1 - row0 - 1) * ldc + l) * (int64_t)sizeof(TC);
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)(C + row0 * ldc), 0, (int)nbytes, kBufWord3);
+  bool colok[LT];
+#pragma unroll
+  for (int c = 0; c < LT; ++c) colok[c] = c * 16 + kc < l;
+  const int step_bytes = (int)(4 * ldc * (int64_t)sizeof(TC));
+  int off = (int)((kr * ldc + kc) * (int64_t)sizeof(TC));
+  double buf[kGramPrefetch][LT];
+#pragma unroll
+  for (int s = 0; s < kGramPrefetch; ++s) {
+#pragma unroll
+    for (int c = 0; c < LT; ++c) buf[s][c] = buf_ld(rs, off + c * 16 * (int)sizeof(TC), C);
+    off += step_bytes;
+  }
+  for (int64_t rb = row0; rb < row1; rb += 4 * kGramPrefetch) {
+#pragma unroll
+    for (int s = 0; s < kGramPrefetch; ++s) {
+      double v[LT];
+#pragma unroll
+      for (int c = 0; c < LT; ++c) v[c] = colok[c] ? buf[s][c] : 0.0;
+#pragma unroll
+      for (int c = 0; c < LT; ++c) buf[s][c] = buf_ld(rs, off + c * 16 * (int)sizeof(TC), C);
+      off += step_bytes;
+      gram_step<LT, WV, 0, TPW>(v, acc);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    const int t = WV + 4 * i;
+    if (t < NT) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        // Move the accumulator through a VGPR before storing: a store that
+        // read the FP64 MFMA accumulator registers directly returned stale
+        // values for the last rows written by the final MFMA on gfx950.
+        double x = acc[i][q];
+        asm volatile("" : "+v"(x));
+        out[(int64_t)t * 256 + lane * 4 + q] = x;
+      }
+    }
+  }
+}
+
+// Block partial of G = C^T C over rows [b * rows_per_block, ...): the four
+// wavefronts walk the same rows, each on its own upper tiles, with the MFMA
+// operands loaded straight from memory (no LDS, no block barrier).
 template <typename TC, int LT>
 __global__ __launch_bounds__(256) void k_gram_partial(int64_t r, int l, const TC *__restrict__ C,
                                                       int64_t ldc, double *__restrict__ partial,
@@ -43,72 +149,20 @@ __global__ __launch_bounds__(256) void k_gram_partial(int64_t r, int l, const TC
     if (d) return;
   }
   constexpr int NT = LT * (LT + 1) / 2;
-  constexpr int TPW = (NT + 3) / 4;
-  constexpr int W = LT * 16;
-  constexpr int S = W + 1;  // LDS row stride (doubles), odd to spread banks
-  __shared__ double tile[kGramRows * S];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int tI[TPW], tJ[TPW];
-#pragma unroll
-  for (int i = 0; i < TPW; ++i) {
-    int t = wave + 4 * i, I = 0;
-    if (t >= NT) t = NT - 1;  // duplicate work is discarded below
-    while (t >= LT - I) {
-      t -= LT - I;
-      ++I;
-    }
-    tI[i] = I;
-    tJ[i] = I + t;
-  }
-  d4 acc[TPW];
-#pragma unroll
-  for (int i = 0; i < TPW; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
   const int64_t row0 = (int64_t)blockIdx.x * rows_per_block;
   int64_t row1 = row0 + rows_per_block;
   if (row1 > r) row1 = r;
-  const int kr = lane >> 4, kc = lane & 15;
-  for (int64_t rb = row0; rb < row1; rb += kGramRows) {
-    for (int idx = threadIdx.x; idx < kGramRows * W; idx += 256) {
-      const int rr = idx / W, cc = idx - rr * W;
-      const int64_t row = rb + rr;
-      tile[rr * S + cc] = (row < row1 && cc < l) ? to_d(C[row * ldc + cc]) : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 2
-    for (int s = 0; s < kGramRows / 4; ++s) {
-      const double *trow = tile + (s * 4 + kr) * S + kc;
-#pragma unroll
-      for (int i = 0; i < TPW; ++i) {
-        if (wave + 4 * i < NT) {
-          // The B column offset is made opaque to the compiler so that a
-          // diagonal tile loads A and B into different registers: an FP64
-          // MFMA fed the same VGPR pair as both operands returned wrong rows
-          // 8-15 of the tile on gfx950.
-          int jo = tJ[i] * 16;
-          asm volatile("" : "+v"(jo));
-          const double a = trow[tI[i] * 16];
-          const double b = trow[jo];
-          acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[i], 0, 0, 0);
-        }
-      }
-    }
-    __syncthreads();
-  }
   double *out = partial + (int64_t)blockIdx.x * NT * 256;
-#pragma unroll
-  for (int i = 0; i < TPW; ++i) {
-    const int t = wave + 4 * i;
-    if (t < NT) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        // Move the accumulator through a VGPR before storing: a store that
-        // read the FP64 MFMA accumulator registers directly returned stale
-        // values for the last rows written by the final MFMA on gfx950.
-        double v = acc[i][q];
-        asm volatile("" : "+v"(v));
-        out[(int64_t)t * 256 + lane * 4 + q] = v;
-      }
-    }
+  const int wave = threadIdx.x >> 6;
+  if (row0 >= row1) {
+    for (int i = threadIdx.x; i < NT * 256; i += 256) out[i] = 0.0;
+    return;
+  }
+  switch (wave) {
+    case 0: gram_wave<TC, LT, 0>(row0, row1, l, C, ldc, out); break;
+    case 1: gram_wave<TC, LT, 1>(row0, row1, l, C, ldc, out); break;
+    case 2: gram_wave<TC, LT, 2>(row0, row1, l, C, ldc, out); break;
+    default: gram_wave<TC, LT, 3>(row0, row1, l, C, ldc, out); break;
   }
 }
 
@@ -178,93 +232,153 @@ __device__ __forceinline__ float4 load4f(const bf16 *p) {
 // consecutive elements k0 + 4(L/16) .. +3 of row L%16 with one vector load
 // and feeds them to four MFMA steps; step s uses k = k0 + 4(L/16) + s in
 // both operands (a permutation of the k order inside the slab), so the A
-// operand never goes through LDS.  The next slab's loads are issued before
-// the current slab's MFMAs.  Columns k >= l of C are masked to zero (pad
-// columns may hold anything); with R, the input is C - alpha R, formed in
-// FP64 and rounded once.
+// operand never goes through LDS.  A wavefront's (tile, slab) sequence is
+// walked as one stream with the loads two slabs ahead, across tile ends.
+// Columns k >= l of C are masked to zero (pad columns may hold anything);
+// with R, the input is C - alpha R, formed in FP64 and rounded once.
+constexpr int kRescaleThreads = 1024;  // 16 wavefronts share one copy of W
+
 template <typename TC, typename TO, int LTO>
-__global__ __launch_bounds__(256) void k_rescale_mfma(int64_t r, int l, const TC *__restrict__ C,
-                                                      int64_t ldc, const double *__restrict__ W,
-                                                      int64_t ldw, int c, TO *__restrict__ Out,
-                                                      int64_t ldo, const int32_t *__restrict__ done,
-                                                      const TC *__restrict__ R,
-                                                      const double *__restrict__ alpha) {
+__global__ __launch_bounds__(kRescaleThreads) void k_rescale_mfma(int64_t r, int l, const TC *__restrict__ C,
+                                                                  int64_t ldc, const double *__restrict__ W,
+                                                                  int64_t ldw, int c, TO *__restrict__ Out,
+                                                                  int64_t ldo, const int32_t *__restrict__ done,
+                                                                  const TC *__restrict__ R,
+                                                                  const double *__restrict__ alpha) {
   if (done && *done) return;
+  constexpr int NW = kRescaleThreads / 64;
   const double a_sh = R ? *alpha : 0.0;
   constexpr int WC = LTO * 16;
   constexpr int SW = WC + 4;
   extern __shared__ float lds[];
   const int LK = (l + 15) & ~15;  // k-slabs of 16
   float *Ws = lds;                // LK x SW
-  for (int idx = threadIdx.x; idx < LK * WC; idx += 256) {
-    const int kk = idx / WC, cc = idx - kk * WC;
-    Ws[kk * SW + cc] = (kk < l && cc < c) ? (float)W[(int64_t)kk * ldw + cc] : 0.0f;
+  {
+    // Eight independent loads in flight per thread: every load reads a
+    // clamped (valid) address unconditionally, and the values pass an
+    // opaque copy before the mask, so the compiler cannot sink a load into
+    // a branch (which would wait for each load in turn).
+    constexpr int kU = 8;
+    const int total = LK * WC;
+    for (int base = threadIdx.x; base < total; base += kRescaleThreads * kU) {
+      double v[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int idx = base + u * kRescaleThreads;
+        const int kk = idx / WC, cc = idx - kk * WC;
+        v[u] = W[(int64_t)(kk < l ? kk : l - 1) * ldw + (cc < c ? cc : c - 1)];
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int idx = base + u * kRescaleThreads;
+        const int kk = idx / WC, cc = idx - kk * WC;
+        double x = v[u];
+        asm volatile("" : "+v"(x));
+        if (idx < total) Ws[kk * SW + cc] = (kk < l && cc < c) ? (float)x : 0.0f;
+      }
+    }
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // the wavefront index is uniform: keep the tile walk in scalar registers
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lr = lane & 15, kq = lane >> 4;  // A row, k quad
   const int64_t ntiles = (r + 15) / 16;
   const int nslab = LK / 16;
-  auto load_slab = [&](int64_t row, int k0) -> float4 {
-    const int kb = k0 + 4 * kq;
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (row < r && kb < l) {
-      // ld is a multiple of 8 and kb of 4: the vector stays inside the row
-      v = load4f(C + row * ldc + kb);
-      if (R) {
-        const float4 w = load4f(R + row * ldc + kb);
-        v.x = (float)((double)v.x - a_sh * (double)w.x);
-        v.y = (float)((double)v.y - a_sh * (double)w.y);
-        v.z = (float)((double)v.z - a_sh * (double)w.z);
-        v.w = (float)((double)v.w - a_sh * (double)w.w);
-      }
-      if (kb + 1 >= l) v.y = 0.f;
-      if (kb + 2 >= l) v.z = 0.f;
-      if (kb + 3 >= l) v.w = 0.f;
-    }
-    return v;
+  const int64_t tstride = (int64_t)gridDim.x * NW;
+  // Raw slab loads, issued ahead of use: the addresses are clamped to valid
+  // ones (rows past r are never stored; k >= l is masked at use), and no
+  // arithmetic touches the loaded values until they are used, so nothing
+  // waits for a load at the point where it is issued.
+  struct Slab {
+    float4 c, r;
   };
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
-    const int64_t row = tile * 16 + lr;
-    f4 acc[LTO];
-#pragma unroll
-    for (int J = 0; J < LTO; ++J) acc[J] = f4{0.f, 0.f, 0.f, 0.f};
-    float4 cur = load_slab(row, 0);
-    for (int sl = 0; sl < nslab; ++sl) {
-      const int k0 = sl * 16;
-      const float4 nxt = sl + 1 < nslab ? load_slab(row, k0 + 16) : make_float4(0.f, 0.f, 0.f, 0.f);
-      const float av[4] = {cur.x, cur.y, cur.z, cur.w};
-#pragma unroll
-      for (int s_ = 0; s_ < 4; ++s_) {
-        const float *bw = Ws + (k0 + 4 * kq + s_) * SW + lr;
-#pragma unroll
-        for (int J = 0; J < LTO; ++J)
-          acc[J] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s_], bw[J * 16], acc[J], 0, 0, 0);
-      }
-      cur = nxt;
+  const TC *Rl = R ? R : C;
+  auto load_slab = [&](int64_t tile, int sl) -> Slab {
+    int64_t row = tile * 16 + lr;
+    if (row >= r) row = r - 1;
+    int kb = sl * 16 + 4 * kq;
+    if (kb >= l) kb = 0;  // ld is a multiple of 8 and kb of 4: the vector stays inside the row
+    Slab x;
+    x.c = load4f(C + row * ldc + kb);
+    x.r = load4f(Rl + row * ldc + kb);  // without R: a second read of C, ignored
+    return x;
+  };
+  auto advance = [&](int64_t &tile, int &sl) {
+    if (++sl == nslab) {
+      sl = 0;
+      tile += tstride;
     }
-    const int64_t rbase = tile * 16 + 4 * kq;
+  };
+  int64_t tile = (int64_t)blockIdx.x * NW + wave;  // slab in use
+  int sl = 0;
+  int64_t tl = tile;  // next slab to load
+  int sll = 0;
+  f4 acc[LTO];
 #pragma unroll
-    for (int J = 0; J < LTO; ++J) {
-      const int col = J * 16 + lr;
-      if (col < ldo) {
+  for (int J = 0; J < LTO; ++J) acc[J] = f4{0.f, 0.f, 0.f, 0.f};
+  // One slab: take the values of b, reload b with the slab three ahead,
+  // then the MFMAs; at the end of a tile, store it.  Three buffers used in
+  // turn, each reloaded unconditionally (clamped addresses), so no register
+  // copy has to wait for a load in flight; past the last tile a step only
+  // reloads.
+  auto step = [&](Slab &b) {
+    const bool live = tile < ntiles;
+    const int k0 = sl * 16;
+    const float cv[4] = {b.c.x, b.c.y, b.c.z, b.c.w};
+    const float rv[4] = {b.r.x, b.r.y, b.r.z, b.r.w};
+    float av[4];
 #pragma unroll
+    for (int s_ = 0; s_ < 4; ++s_) {
+      const float v = R ? (float)((double)cv[s_] - a_sh * (double)rv[s_]) : cv[s_];
+      av[s_] = k0 + 4 * kq + s_ < l ? v : 0.0f;
+    }
+    b = load_slab(tl, sll);
+    advance(tl, sll);
+    if (!live) return;
+#pragma unroll
+    for (int s_ = 0; s_ < 4; ++s_) {
+      const float *bw = Ws + (k0 + 4 * kq + s_) * SW + lr;
+#pragma unroll
+      for (int J = 0; J < LTO; ++J)
+        acc[J] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s_], bw[J * 16], acc[J], 0, 0, 0);
+    }
+    if (sl == nslab - 1) {
+      const int64_t rbase = tile * 16 + 4 * kq;
+#pragma unroll
+      for (int J = 0; J < LTO; ++J) {
+        const int col = J * 16 + lr;
+        if (col < ldo) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int64_t orow = rbase + q;
+            float v = acc[J][q];
+            asm volatile("" : "+v"(v));
+            if (orow < r) elem<TO>::st(Out + orow * ldo + col, col < c ? v : 0.0f);
+          }
+        }
+        acc[J] = f4{0.f, 0.f, 0.f, 0.f};
+      }
+      // columns beyond the tiles (ldo > WC) are zero
+      if (ldo > WC) {
         for (int q = 0; q < 4; ++q) {
           const int64_t orow = rbase + q;
-          float v = acc[J][q];
-          asm volatile("" : "+v"(v));
-          if (orow < r) elem<TO>::st(Out + orow * ldo + col, col < c ? v : 0.0f);
+          if (orow < r)
+            for (int64_t cc = WC + lr; cc < ldo; cc += 16) elem<TO>::st(Out + orow * ldo + cc, 0.0f);
         }
       }
     }
-    // columns beyond the tiles (ldo > WC) are zero
-    if (ldo > WC) {
-      for (int q = 0; q < 4; ++q) {
-        const int64_t orow = rbase + q;
-        if (orow < r)
-          for (int64_t cc = WC + lr; cc < ldo; cc += 16) elem<TO>::st(Out + orow * ldo + cc, 0.0f);
-      }
-    }
+    advance(tile, sl);
+  };
+  Slab b0 = load_slab(tl, sll);
+  advance(tl, sll);
+  Slab b1 = load_slab(tl, sll);
+  advance(tl, sll);
+  Slab b2 = load_slab(tl, sll);
+  advance(tl, sll);
+  while (tile < ntiles) {
+    step(b0);
+    step(b1);
+    step(b2);
   }
 }
 
@@ -447,7 +561,10 @@ hipError_t gram_dispatch(int64_t r, int l, const TC *C, int64_t ldc, double *par
   // values in the last 4 x 4 corner of the tile once several MFMAs had
   // accumulated (l = 16, 32+ rows) on gfx950, the two-tile one does not
   const int LT = (l + 15) / 16 < 2 ? 2 : (l + 15) / 16;
-  const int64_t rpb = (r + nb - 1) / nb;
+  constexpr int64_t kStep = 4 * kGramPrefetch;  // rows of one unrolled iteration
+  const int64_t rpb = ((r + nb - 1) / nb + kStep - 1) / kStep * kStep;
+  // byte offsets inside one block's rows (prefetch included) are 32-bit
+  if ((rpb + kStep) * ldc * (int64_t)sizeof(TC) >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
 #define DSV_GRAM(LTV)                                                                          \
   case LTV: {                                                                                  \
     hipLaunchKernelGGL((k_gram_partial<TC, LTV>), dim3(nb), dim3(256), 0, st, r, l, C, ldc, partial, \
@@ -473,14 +590,16 @@ hipError_t rescale_dispatch(int64_t r, int l, const TC *C, int64_t ldc, const do
   const int LTO = (c + 15) / 16;
   const int LK = (l + 15) & ~15;
   const int64_t ntiles = (r + 15) / 16;
-  // blocks of four wavefronts, each wavefront on its own 16-row tiles
-  int64_t g = (ntiles + 3) / 4;
-  if (g > 512) g = 512;
+  // blocks of 16 wavefronts, each wavefront on its own 16-row tiles; one
+  // block per CU (the W copy fills most of the LDS)
+  constexpr int NW = kRescaleThreads / 64;
+  int64_t g = (ntiles + NW - 1) / NW;
+  if (g > 256) g = 256;
   const int grid = (int)(g < 1 ? 1 : g);
 #define DSV_RS(LTV)                                                                         \
   case LTV: {                                                                               \
     const size_t shm = sizeof(float) * (size_t)LK * (LTV * 16 + 4);                         \
-    hipLaunchKernelGGL((k_rescale_mfma<TC, TO, LTV>), dim3(grid), dim3(256), shm, st, r, l, C, ldc, W, \
+    hipLaunchKernelGGL((k_rescale_mfma<TC, TO, LTV>), dim3(grid), dim3(kRescaleThreads), shm, st, r, l, C, ldc, W, \
                        ldw, c, Out, ldo, done, R, alpha);                                   \
     break;                                                                                  \
   }

@@ -236,6 +236,22 @@ def test_gram_integer_exact_f64(torch_dev):
     assert np.array_equal(G.cpu().numpy(), Cm[:, :45].T @ Cm[:, :45])
 
 
+@pytest.mark.parametrize("r,l,pad", [(1001, 120, 8), (77, 10, 6), (4099, 33, 15)])
+def test_gram_ignores_pad_columns(torch_dev, r, l, pad):
+    """Pad columns past l may hold anything, NaN included: G must not see them."""
+    torch = torch_dev
+    from paper_2404_09276_amd import k_gram
+    Cm = np.random.default_rng(r + l).standard_normal((r, l + pad)).astype(np.float32)
+    Cm[:, l:] = np.nan
+    G = torch.zeros((l, l), dtype=torch.float64, device="cuda")
+    k_gram(_dev(torch, Cm), l, G)
+    torch.cuda.synchronize()
+    ref = oracle.gram(Cm[:, :l].astype(np.float64))
+    g = G.cpu().numpy()
+    assert np.all(np.isfinite(g))
+    assert np.allclose(g, ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+
+
 @pytest.mark.parametrize("l", [1, 2, 3, 5, 16, 24, 30, 75, 120, 150, 160])
 def test_eig_matches_lapack(torch_dev, l):
     torch = torch_dev
@@ -362,6 +378,28 @@ def test_cholqr_declines_ill_conditioned_and_singular(torch_dev):
     acc, s, Wm = _cholqr(torch_dev, 0.5 * (G + G.T))
     assert acc
     assert abs(s[-1] ** 2 - 2.0**-30) <= 1e3 * 2.2e-16
+
+
+@pytest.mark.parametrize("r,l,c", [(70001, 120, 120), (4099, 33, 20), (17, 150, 160)])
+def test_rescale_pad_columns_and_many_tiles(torch_dev, r, l, c):
+    """Pad columns of C past l may hold anything (NaN here); row counts that
+    leave wavefronts with several 16-row tiles and a ragged last tile."""
+    torch = torch_dev
+    from paper_2404_09276_amd import k_rescale
+    ld = (l + 7) // 8 * 8 + 8
+    ldo = (c + 7) // 8 * 8
+    rng = np.random.default_rng(r + l)
+    Cm = rng.standard_normal((r, ld)).astype(np.float32)
+    Cm[:, l:] = np.nan
+    W = rng.standard_normal((l, c))
+    Out = torch.full((r, ldo), 3.0, dtype=torch.float32, device="cuda")
+    k_rescale(_dev(torch, Cm), l, _dev(torch, W), c, Out)
+    torch.cuda.synchronize()
+    ref = Cm[:, :l].astype(np.float64) @ W
+    got = Out.cpu().numpy()
+    scale = np.abs(Cm[:, :l]).astype(np.float64) @ np.abs(W)
+    assert np.all(np.abs(got[:, :c] - ref) <= 4 * l * 2.0**-24 * scale + 1e-300)
+    assert np.all(got[:, c:] == 0.0)
 
 
 @pytest.mark.parametrize("r,l,c,odt", [(1000, 30, 30, "f32"), (777, 120, 120, "f32"), (300, 150, 100, "f32"),
