@@ -126,8 +126,10 @@ typedef struct {
                              row-major, leading dimension l); NULL = draw from seed */
   int32_t omega_dtype;    /* DASHSVD_F32 / DASHSVD_F64 */
   int32_t omega_on_device;
-  int32_t timing;         /* 1: time each kernel group with HIP events on the stream
-                             (results in dashsvd_info.kt_ms / kt_count) */
+  int32_t timing;         /* DASHSVD_TIMING_ALL (1): time each kernel group with HIP events
+                             on its stream (results in dashsvd_info.kt_ms / kt_count);
+                             DASHSVD_TIMING_SPMM (2): only the two SpMM groups, so that
+                             the events barely slow the run; 0: none */
   const char *tuning_db;  /* optional path of a tuning database written by dashsvd_autotune;
                              runs with long_row <= 0 take the SpMM chunk length stored for
                              their shape bucket (else the built-in default).  Read when the
@@ -136,7 +138,10 @@ typedef struct {
                              orthonormalise their block */
 } dashsvd_options;
 
-/* Kernel groups timed when options.timing = 1 (index into kt_ms / kt_count). */
+#define DASHSVD_TIMING_ALL 1
+#define DASHSVD_TIMING_SPMM 2
+
+/* Kernel groups timed when options.timing is set (index into kt_ms / kt_count). */
 #define DASHSVD_KT_SPMM 0        /* M times a panel: Z = M C (FP32/FP64 forms) or Y = M Q (BF16 form) */
 #define DASHSVD_KT_SPMM_T 1      /* M^T times a panel: X = M^T Z, or C = M^T Y - alpha Q (BF16 form) */
 #define DASHSVD_KT_GRAM 2        /* Gram partials + reduction (every eigSVD) */

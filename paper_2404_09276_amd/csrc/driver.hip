@@ -9,8 +9,9 @@
 //   final   : B = M Q ; eigSVD(B) ; U = B W_B(:,1:k) ; V = Q V_B(:,1:k) (9-11)
 // where M = A if m >= n and M = A^T otherwise (Sec. 3.1).  The shift, the
 // previous singular values and the done flag live on the device; the host
-// reads the 4-byte done flag once every check_interval passes, and passes
-// launched after the flag is set return at their first instruction.
+// reads the done flag once every check_interval passes (in the overlapped
+// order, one chunk behind, while the next chunk runs), and passes launched
+// after the flag is set return at their first instruction.
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -91,6 +92,10 @@ struct dashsvd_handle {
   // second stream for the eigensolver, overlapped with the next SpMM
   hipStream_t st2 = nullptr;
   hipEvent_t ev_gram = nullptr, ev_eig = nullptr;
+  // stop test one chunk behind: two slots of (done, cq_off) in pinned host
+  // memory, each filled by a copy queued behind a chunk of passes
+  int32_t *hflags = nullptr;
+  hipEvent_t ev_flag[2] = {nullptr, nullptr};
   // what dashsvd_evaluate needs of the last run: the operator M (A, or A^T
   // when m < n) and its transpose with their SpMM plans, and free panels
   struct EvalCtx {
@@ -149,9 +154,13 @@ hipEvent_t take_event(dashsvd_handle *h, int &idx) {
 }
 
 // Open / close a timed kernel group on the handle's stream (no-op unless
-// options.timing is set).
+// options.timing is set; with DASHSVD_TIMING_SPMM only the SpMM groups).
 void tmark_begin(dashsvd_handle *h, int group, int pass, hipStream_t on = nullptr) {
   if (!h->opt.timing) return;
+  if (h->opt.timing == DASHSVD_TIMING_SPMM && group != DASHSVD_KT_SPMM && group != DASHSVD_KT_SPMM_T) {
+    h->open_group = -1;
+    return;
+  }
   int i;
   hipEvent_t e = take_event(h, i);
   if (!e || hipEventRecord(e, on ? on : h->st) != hipSuccess) return;
@@ -206,6 +215,7 @@ dashsvd_status ensure_arena(dashsvd_handle *h, size_t bytes) {
   if (bytes <= h->ar.cap) return DASHSVD_OK;
   if (h->ar.base) {
     (void)hipStreamSynchronize(h->st);
+    if (h->st2) (void)hipStreamSynchronize(h->st2);
     (void)hipFree(h->ar.base);
     h->ar.base = nullptr;
     h->ar.cap = 0;
@@ -354,11 +364,15 @@ void dashsvd_destroy(dashsvd_handle *h) {
   if (!h) return;
   if (h->ar.base) {
     (void)hipStreamSynchronize(h->st);
+    if (h->st2) (void)hipStreamSynchronize(h->st2);
     (void)hipFree(h->ar.base);
   }
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   if (h->ev_gram) (void)hipEventDestroy(h->ev_gram);
   if (h->ev_eig) (void)hipEventDestroy(h->ev_eig);
+  for (hipEvent_t e : h->ev_flag)
+    if (e) (void)hipEventDestroy(e);
+  if (h->hflags) (void)hipHostFree(h->hflags);
   if (h->st2) (void)hipStreamDestroy(h->st2);
   if (h->stg) {
     (void)hipStreamSynchronize(h->stg);
@@ -492,6 +506,33 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   h->marks.clear();
   h->ev_used = 0;
   h->open_group = -1;
+  if (!h->st2) {
+    HIPCHK(hipStreamCreateWithFlags(&h->st2, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&h->ev_gram, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&h->ev_eig, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&h->ev_flag[0], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&h->ev_flag[1], hipEventDisableTiming));
+    HIPCHK(hipHostMalloc((void **)&h->hflags, 64, hipHostMallocDefault));
+  }
+  hipStream_t st2 = h->st2;
+  // Omega (Alg. 5 step 1) depends on nothing else: it is formed on the
+  // second stream while the main stream validates and transposes the CSR
+  // (the second stream first waits for the main stream's work so far, which
+  // may still read the panel Omega is written to).
+  HIPCHK(hipEventRecord(h->ev_gram, st));
+  HIPCHK(hipStreamWaitEvent(st2, h->ev_gram, 0));
+  if (h->opt.omega) {
+    const void *src = h->opt.omega;
+    if (!h->opt.omega_on_device) {
+      HIPCHK(hipMemcpyAsync(b.omega_dev, h->opt.omega, dsz(h->opt.omega_dtype) * (size_t)Mm * l,
+                            hipMemcpyHostToDevice, st2));
+      src = b.omega_dev;
+    }
+    HIPCHK(launch_copy2d(src, l, h->opt.omega_dtype, b.Y, ld, pdt, Mm, l, st2));
+  } else {
+    HIPCHK(launch_gaussian(h->opt.seed, Mm, l, b.Y, ld, pdt, st2));
+  }
+  HIPCHK(hipEventRecord(h->ev_eig, st2));
   // control buffers start at zero; panels need no clearing (pad columns are
   // never read into the first l columns)
   HIPCHK(hipMemsetAsync(b.flags, 0, 4 * 8, st));
@@ -522,6 +563,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   int32_t hflags[4] = {0, 0, 0, 0};
   HIPCHK(hipMemcpyAsync(hflags, b.flags, sizeof(hflags), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  if (hflags[0] & 3) (void)hipStreamSynchronize(st2);  // Omega's writes end before the arena is reused
   if (hflags[0] & 1) return fail(h, DASHSVD_ERR_BAD_CSR, "row_ptr/col_idx malformed");
   if (hflags[0] & 2) return fail(h, DASHSVD_ERR_NONFINITE, "NaN or Inf among the values");
   // CSR(A^T)
@@ -554,30 +596,12 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   b.planT.n_chunks = totals[1];
   b.planM.n_long = nlongs[0];
   b.planT.n_long = nlongs[1];
-  // Omega (Alg. 5 step 1)
-  if (h->opt.omega) {
-    const void *src = h->opt.omega;
-    if (!h->opt.omega_on_device) {
-      HIPCHK(hipMemcpyAsync(b.omega_dev, h->opt.omega, dsz(h->opt.omega_dtype) * (size_t)Mm * l,
-                            hipMemcpyHostToDevice, st));
-      src = b.omega_dev;
-    }
-    HIPCHK(launch_copy2d(src, l, h->opt.omega_dtype, b.Y, ld, pdt, Mm, l, st));
-  } else {
-    HIPCHK(launch_gaussian(h->opt.seed, Mm, l, b.Y, ld, pdt, st));
-  }
   if (!h->sched.empty())
     HIPCHK(hipMemcpyAsync(b.sched, h->sched.data(), 8 * h->sched.size(), hipMemcpyHostToDevice, st));
-  HIPCHK(hipStreamSynchronize(st));
-  const double t_setup = now_ms();
+  HIPCHK(hipStreamWaitEvent(st, h->ev_eig, 0));  // Omega is ready
+  const double t_setup = now_ms();  // host time: the setup kernels may still run
 
   // ---------------------------------------------------------------- eigSVD pieces
-  if (!h->st2) {
-    HIPCHK(hipStreamCreateWithFlags(&h->st2, hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&h->ev_gram, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&h->ev_eig, hipEventDisableTiming));
-  }
-  hipStream_t st2 = h->st2;
   // Sketch and pass blocks: Cholesky-QR with eigenvalues (Jacobi where it
   // declines), or Jacobi throughout.  Cholesky-QR keeps the span but not
   // the principal (Ritz) basis, and the next block C = A Q of a
@@ -632,20 +656,9 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   const int32_t *done = &b.state->done;
   const int32_t *pass_skip = &b.state->pass_skip;
   const int every = h->opt.check_interval > 0 ? h->opt.check_interval : 1;
-  // Host-side stop test after every `every` passes (tolerance runs only).
   // Host copy of state->cq_off (read with done at each stop test): once set,
   // the pass blocks go straight to the Jacobi eigensolver.
   int32_t host_cq_off = 0;
-  auto stopped = [&](int launched, bool &stop) -> hipError_t {
-    stop = false;
-    if (!(tol > 0.0 && launched < pmax)) return hipSuccess;
-    int32_t hd[2] = {0, 0};  // done, cq_off (adjacent)
-    hipError_t e = hipMemcpyAsync(hd, done, 8, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    stop = hd[0] != 0;
-    host_cq_off = hd[1];
-    return e;
-  };
   auto launch_block_eig = [&](EigArgs &ea, int pass, hipStream_t s) -> hipError_t {
     const bool cq = cholqr && !host_cq_off && pass + 1 < pmax;
     tmark_begin(h, cq ? DASHSVD_KT_CHOLQR : DASHSVD_KT_EIG, pass, s);
@@ -702,8 +715,13 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
                        nullptr, st));
     tmark_end(h);
     HIPCHK(side(1, 0, Cb[0], nullptr));
-    // power passes (steps 3-8)
+    // power passes (steps 3-8).  Stop test one chunk behind: the flags of
+    // a chunk are copied to pinned host memory behind its work, and the host
+    // reads them only once the next chunk is queued, so the GPU does not
+    // idle while the host decides; a chunk queued after the stop returns at
+    // the first instruction of each kernel.
     int launched = 0;
+    int pending = -1;  // flag slot copied but not read yet
     while (launched < pmax) {
       const int chunk = (pmax - launched) < every ? (pmax - launched) : every;
       for (int c = 0; c < chunk; ++c) {
@@ -715,9 +733,16 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
         HIPCHK(side(2, pass, Cb[pass & 1], done));
       }
       launched += chunk;
-      bool stop = false;
-      HIPCHK(stopped(launched, stop));
-      if (stop) break;
+      if (!(tol > 0.0 && launched < pmax)) continue;
+      const int slot = pending == 0 ? 1 : 0;
+      HIPCHK(hipMemcpyAsync(h->hflags + 2 * slot, done, 8, hipMemcpyDeviceToHost, st));  // done, cq_off
+      HIPCHK(hipEventRecord(h->ev_flag[slot], st));
+      if (pending >= 0) {
+        HIPCHK(hipEventSynchronize(h->ev_flag[pending]));
+        host_cq_off = h->hflags[2 * pending + 1];
+        if (h->hflags[2 * pending] != 0) break;
+      }
+      pending = slot;
     }
     HIPCHK(hipMemcpyAsync(&last_pass, &b.state->pass, 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));

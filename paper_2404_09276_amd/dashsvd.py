@@ -24,6 +24,8 @@ PREC = {"fp32": 0, "fp64": 1, "bf16": 2}
 SHIFT = {"paper": 0, "none": 1, "fixed": 2, "schedule": 3, "learned": 4}
 PVE = {"r2": 0, "r1": 1}
 EIG = {"auto": 0, "jacobi": 1}
+# timing: False / True (every kernel group) / "spmm" (the two SpMM groups only)
+TIMING = {False: 0, True: 1, "spmm": 2}
 MAX_L = 160
 MAX_TRACE = 256
 
@@ -220,7 +222,7 @@ class DashSVD:
 
     def __init__(self, precision: str = "fp32", shift_policy: str = "paper", pve_mode: str = "r2",
                  p_max: int = -1, seed: int = 0, stream=None, long_row: int = 0,
-                 check_interval: int = 1, schedule=None, omega=None, timing: bool = False,
+                 check_interval: int = 1, schedule=None, omega=None, timing=False,
                  tuning_db=None, eig_method: str = "auto"):
         self._h = C.c_void_p()
         self._keep = []
@@ -246,7 +248,7 @@ class DashSVD:
         return _Options(PREC[precision], SHIFT[shift_policy], PVE[pve_mode], p_max, seed,
                         stream or None, long_row, check_interval,
                         _ptr(sched_arr).value if sched_arr is not None else None,
-                        om_ptr, om_dt, om_dev, int(bool(timing)),
+                        om_ptr, om_dt, om_dev, TIMING[timing],
                         tuning_db.encode() if tuning_db else None, EIG[eig_method])
 
     def set_options(self, **kw):

@@ -176,6 +176,25 @@ def test_deterministic_repeat(torch_dev):
     assert np.array_equal(r1[1], r2[1]) and np.array_equal(r1[0], r2[0])
 
 
+@pytest.mark.parametrize("timing", [True, "spmm"])
+def test_timing_levels_and_stop_test(torch_dev, timing):
+    """Kernel-group events: every group, or the two SpMM groups only.  The
+    tolerance run stops at the same pass with the stop test one chunk behind,
+    and the chunk queued after the stop adds no timed launches."""
+    A = synth.config_small(np.float32)
+    ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 20, 10, 64, 1e-2, seed=2001)
+    U, S, V, st, info, tr = _solve(A, 20, 10, 64, 1e-2, 2001, "fp32", timing=timing)
+    assert st == 0 and info.converged and info.passes == len(ref.alpha)
+    timed = {g for g in info.kt_count if info.kt_count[g] > 0}
+    if timing == "spmm":
+        assert timed == {"spmm", "spmm_t"}
+    else:
+        assert {"spmm", "spmm_t", "gram", "rescale", "final"} <= timed
+    # overlapped order: the sketch's products and those of each pass whose
+    # eigSVD ran (the last one's products are computed beside it)
+    assert info.kt_count["spmm"] == info.passes + 1
+
+
 def test_error_paths(torch_dev):
     from paper_2404_09276_amd import DashSVD, DashSVDError
     A = synth.uniform_csr(200, 150, 3000, seed=2)
