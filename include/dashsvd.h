@@ -136,7 +136,16 @@ typedef struct {
                              options are set. */
   int32_t eig_method;     /* DASHSVD_EIG_* (default AUTO): how the sketch and the power passes
                              orthonormalise their block */
+  int32_t reorder;        /* DASHSVD_REORDER_*: solve P_r A P_c^T with rows and columns
+                             by non-increasing nonzero count (memory locality of the
+                             products); U and V are returned in the caller's order.
+                             AUTO (0): on from DASHSVD_REORDER_MIN_NNZ nonzeros */
 } dashsvd_options;
+
+#define DASHSVD_REORDER_AUTO 0
+#define DASHSVD_REORDER_ON 1
+#define DASHSVD_REORDER_OFF (-1)
+#define DASHSVD_REORDER_MIN_NNZ (1 << 22)
 
 #define DASHSVD_TIMING_ALL 1
 #define DASHSVD_TIMING_SPMM 2

@@ -170,7 +170,7 @@ struct SolverState {
 // ------------------------------------------------------------------ launchers
 // (defined in the .hip files; all asynchronous on `st`)
 hipError_t launch_gaussian(uint64_t seed, int64_t rows, int64_t cols, void *out, int64_t ld,
-                           int dtype, hipStream_t st);
+                           int dtype, hipStream_t st, const int32_t *row_to = nullptr);
 hipError_t launch_philox_raw(uint64_t seed, int64_t nwords, uint64_t *out, hipStream_t st);
 
 hipError_t launch_scan_i64(const int64_t *in, int64_t n, int64_t *out, int64_t *tmp, hipStream_t st);
@@ -187,6 +187,31 @@ hipError_t launch_transpose(int64_t n, int64_t nnz, const int32_t *col, const in
                             int dtype, int64_t *rowT, int32_t *colT, void *valT, void *ws, size_t ws_bytes,
                             hipStream_t st);
 
+// Degree order of a CSR structure with R rows: perm (new -> old, rows by
+// non-increasing length, ties by index), inv (old -> new) and the row
+// pointer of the permuted structure.  ws: degree_order_ws_bytes(R).
+size_t degree_order_ws_bytes(int64_t R);
+hipError_t launch_degree_order(int64_t R, const int64_t *rp, int64_t max_len, int32_t *perm, int32_t *inv,
+                               int64_t *rp_new, void *ws, size_t ws_bytes, int64_t *scan_tmp, hipStream_t st);
+// Entries of a CSR structure moved to the permuted one: entry e of row
+// row_of[e] goes to row inv_r[row], column col[e] becomes inv_c[col[e]].
+hipError_t launch_permute_entries(int64_t nnz, const int64_t *rp, const int32_t *row_of, int row_of_unsigned,
+                                  const int32_t *col, const void *val, int dtype, const int32_t *inv_r,
+                                  const int32_t *inv_c, const int64_t *rp_new, int32_t *col_new, void *val_new,
+                                  hipStream_t st);
+// The two halves of launch_transpose: the sort of the column keys with the
+// row pointer of A^T, then the gather of rows and values (into the degree
+// order when inv_r, inv_c and rp_new, the permuted row pointer, are given).
+hipError_t launch_transpose_keys(int64_t n, int64_t nnz, const int32_t *col, int64_t *rowT, void *ws,
+                                 size_t ws_bytes, hipStream_t st);
+hipError_t launch_transpose_gather(int64_t nnz, const int32_t *rowidx, const void *val, int dtype, const void *ws,
+                                   int32_t *colT, void *valT, hipStream_t st, const int64_t *rowT = nullptr,
+                                   const int32_t *inv_r = nullptr, const int32_t *inv_c = nullptr,
+                                   const int64_t *rp_new = nullptr);
+// out[0..3] = *endM, *endT, *nlM, *nlT (chunk totals and long-row counts of
+// the two SpMM plans), so that the host reads them with one copy.
+hipError_t launch_plan_sizes(const int64_t *endM, const int64_t *endT, const int32_t *nlM, const int32_t *nlT,
+                             int64_t *out, hipStream_t st);
 hipError_t launch_plan_count(int64_t R, const int64_t *rp, int32_t long_row, int64_t *nch,
                              hipStream_t st);
 hipError_t launch_plan_fill(int64_t R, const int64_t *rp, int32_t long_row, const int64_t *off,
@@ -314,10 +339,12 @@ hipError_t launch_bsign(const int64_t *voff, const int64_t *uoff, int count, int
 
 // Out = (C - alpha R) W when R is given (R laid out like C, alpha on the
 // device), else Out = C W.
+// Out = (C - alpha R) W; row_to (optional): row i of the product is stored
+// in row row_to[i] of Out.
 hipError_t launch_rescale(int64_t r, int l, const void *C, int64_t ldc, int cdtype, const double *W,
                           int64_t ldw, int c, void *Out, int64_t ldo, int odtype,
                           const int32_t *done, hipStream_t st, const void *R = nullptr,
-                          const double *alpha = nullptr);
+                          const double *alpha = nullptr, const int32_t *row_to = nullptr);
 
 // pmax: nblk*k doubles, pidx: nblk*k int64 followed by k floats (workspace)
 // C (m x n) = op(A) B for small FP64 matrices (op(A) = A^T if transA)
@@ -334,7 +361,7 @@ hipError_t launch_sign_fix(int64_t rowsV, int64_t rowsU, int k, void *V, int64_t
 hipError_t launch_convert(const void *in, int idtype, void *out, int odtype, int64_t n,
                           hipStream_t st);
 hipError_t launch_copy2d(const void *in, int64_t ldi, int idtype, void *out, int64_t ldo,
-                         int odtype, int64_t rows, int cols, hipStream_t st);
+                         int odtype, int64_t rows, int cols, hipStream_t st, const int32_t *row_to = nullptr);
 hipError_t launch_fill_zero_i32(int32_t *p, int64_t n, hipStream_t st);
 
 }  // namespace dsv

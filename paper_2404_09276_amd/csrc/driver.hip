@@ -92,8 +92,10 @@ struct dashsvd_handle {
   // second stream for the eigensolver, overlapped with the next SpMM
   hipStream_t st2 = nullptr;
   hipEvent_t ev_gram = nullptr, ev_eig = nullptr;
-  // stop test one chunk behind: two slots of (done, cq_off) in pinned host
-  // memory, each filled by a copy queued behind a chunk of passes
+  // pinned host memory for the reads the host waits on: [0, 16) the stop
+  // test one chunk behind (two slots of done, cq_off, each filled by a copy
+  // queued behind a chunk of passes); [64, 96) the SpMM plan sizes;
+  // [128, 144) the CSR validation flags
   int32_t *hflags = nullptr;
   hipEvent_t ev_flag[2] = {nullptr, nullptr};
   // what dashsvd_evaluate needs of the last run: the operator M (A, or A^T
@@ -110,6 +112,7 @@ struct dashsvd_handle {
     Plan plan[2];
     void *panel_m = nullptr, *panel_n = nullptr;  // Mm x ld and Mn x ld, cdt
     double *gpart = nullptr, *G = nullptr;
+    const int32_t *u_row_to = nullptr;  // degree order: row r of U goes to row u_row_to[r] of the panel
   } ev_ctx;
   // results of the last batched run
   struct BatchOut {
@@ -258,6 +261,7 @@ struct RunBufs {
   void *valT = nullptr;
   // transposition temporaries
   int32_t *rowidx = nullptr, *flags = nullptr;
+  int64_t *sizes = nullptr;  // 4 plan sizes for the host
   void *tws = nullptr;  // CSR(A^T) build workspace
   size_t tws_bytes = 0;
   int64_t *scan_tmp = nullptr;
@@ -279,6 +283,14 @@ struct RunBufs {
   void *Uo = nullptr, *Vo = nullptr;
   double *So = nullptr;
   void *sgn_max = nullptr, *sgn_idx = nullptr;
+  // degree order (options.reorder): perm new -> old, inv old -> new, for the
+  // rows (r, m of them) and columns (c, n) of A; the permuted A and A^T
+  int32_t *perm_r = nullptr, *inv_r = nullptr, *perm_c = nullptr, *inv_c = nullptr;
+  int64_t *rpP = nullptr, *rpPT = nullptr;
+  int32_t *colP = nullptr;  // the permuted A^T takes colT and valT
+  void *valP = nullptr;
+  void *dws = nullptr;
+  size_t dws_bytes = 0;
   void *omega_dev = nullptr;
 };
 
@@ -315,6 +327,7 @@ dashsvd_status dashsvd_set_options(dashsvd_handle *h, const dashsvd_options *opt
   if (o.shift_policy < 0 || o.shift_policy > 4) return fail(h, DASHSVD_ERR_INVALID_ARG, "shift_policy");
   if (o.pve_mode < 0 || o.pve_mode > 1) return fail(h, DASHSVD_ERR_INVALID_ARG, "pve_mode");
   if (o.eig_method < 0 || o.eig_method > 1) return fail(h, DASHSVD_ERR_INVALID_ARG, "eig_method");
+  if (o.reorder < -1 || o.reorder > 1) return fail(h, DASHSVD_ERR_INVALID_ARG, "reorder");
   if (o.p_max < 0) o.p_max = kDefaultPmax;
   if (o.p_max > 100000) return fail(h, DASHSVD_ERR_INVALID_ARG, "p_max too large");
   h->sched.clear();
@@ -457,6 +470,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   b.valT = ar.take(dsz(vdt) * (size_t)(nnz + 1));
   b.rowidx = (int32_t *)ar.take(4 * (size_t)(nnz + 1));
   b.flags = (int32_t *)ar.take(4 * 8);
+  b.sizes = (int64_t *)ar.take(8 * 4);
   b.tws_bytes = transpose_ws_bytes(n, nnz);
   b.tws = ar.take(b.tws_bytes);
   const int64_t scan_n = (m > n ? m : n) + 1;
@@ -497,6 +511,20 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   b.sgn_idx = ar.take(8 * (size_t)sgn_blk * k + 4 * (size_t)k);
   if (h->opt.omega && !h->opt.omega_on_device)
     b.omega_dev = ar.take(dsz(h->opt.omega_dtype) * (size_t)Mm * l);
+  const bool reorder = h->opt.reorder == DASHSVD_REORDER_ON ||
+                       (h->opt.reorder == DASHSVD_REORDER_AUTO && nnz >= DASHSVD_REORDER_MIN_NNZ);
+  if (reorder) {
+    b.perm_r = (int32_t *)ar.take(4 * (size_t)(m + 1));
+    b.inv_r = (int32_t *)ar.take(4 * (size_t)(m + 1));
+    b.perm_c = (int32_t *)ar.take(4 * (size_t)(n + 1));
+    b.inv_c = (int32_t *)ar.take(4 * (size_t)(n + 1));
+    b.rpP = (int64_t *)ar.take(8 * (size_t)(m + 1));
+    b.rpPT = (int64_t *)ar.take(8 * (size_t)(n + 1));
+    b.colP = (int32_t *)ar.take(4 * (size_t)(nnz + 1));
+    b.valP = ar.take(dsz(vdt) * (size_t)(nnz + 1));
+    b.dws_bytes = degree_order_ws_bytes(m > n ? m : n);
+    b.dws = ar.take(b.dws_bytes);
+  }
   if (measure_only) {
     *measured = ar.used;
     return DASHSVD_OK;
@@ -512,27 +540,35 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     HIPCHK(hipEventCreateWithFlags(&h->ev_eig, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&h->ev_flag[0], hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&h->ev_flag[1], hipEventDisableTiming));
-    HIPCHK(hipHostMalloc((void **)&h->hflags, 64, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&h->hflags, 256, hipHostMallocDefault));
   }
   hipStream_t st2 = h->st2;
-  // Omega (Alg. 5 step 1) depends on nothing else: it is formed on the
-  // second stream while the main stream validates and transposes the CSR
-  // (the second stream first waits for the main stream's work so far, which
-  // may still read the panel Omega is written to).
-  HIPCHK(hipEventRecord(h->ev_gram, st));
-  HIPCHK(hipStreamWaitEvent(st2, h->ev_gram, 0));
-  if (h->opt.omega) {
-    const void *src = h->opt.omega;
-    if (!h->opt.omega_on_device) {
-      HIPCHK(hipMemcpyAsync(b.omega_dev, h->opt.omega, dsz(h->opt.omega_dtype) * (size_t)Mm * l,
-                            hipMemcpyHostToDevice, st2));
-      src = b.omega_dev;
+  // Omega (Alg. 5 step 1) depends on nothing but the row order: it is
+  // formed on the second stream while the main stream validates, transposes
+  // and reorders the CSR (the second stream first waits for the main
+  // stream's work so far, which may still read the panel Omega is written
+  // to).  With the degree order, Omega is drawn in the caller's row order
+  // and row r is stored in row row_to[r] of the panel.
+  auto launch_omega = [&](const int32_t *row_to) -> hipError_t {
+    hipError_t e = hipEventRecord(h->ev_gram, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st2, h->ev_gram, 0);
+    if (e != hipSuccess) return e;
+    if (h->opt.omega) {
+      const void *src = h->opt.omega;
+      if (!h->opt.omega_on_device) {
+        e = hipMemcpyAsync(b.omega_dev, h->opt.omega, dsz(h->opt.omega_dtype) * (size_t)Mm * l,
+                           hipMemcpyHostToDevice, st2);
+        if (e != hipSuccess) return e;
+        src = b.omega_dev;
+      }
+      e = launch_copy2d(src, l, h->opt.omega_dtype, b.Y, ld, pdt, Mm, l, st2, row_to);
+    } else {
+      e = launch_gaussian(h->opt.seed, Mm, l, b.Y, ld, pdt, st2, row_to);
     }
-    HIPCHK(launch_copy2d(src, l, h->opt.omega_dtype, b.Y, ld, pdt, Mm, l, st2));
-  } else {
-    HIPCHK(launch_gaussian(h->opt.seed, Mm, l, b.Y, ld, pdt, st2));
-  }
-  HIPCHK(hipEventRecord(h->ev_eig, st2));
+    if (e == hipSuccess) e = hipEventRecord(h->ev_eig, st2);
+    return e;
+  };
+  if (!reorder) HIPCHK(launch_omega(nullptr));
   // control buffers start at zero; panels need no clearing (pad columns are
   // never read into the first l columns)
   HIPCHK(hipMemsetAsync(b.flags, 0, 4 * 8, st));
@@ -545,6 +581,9 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   HIPCHK(hipMemsetAsync(b.tr_sweeps, 0, 4 * (size_t)(cap + 2), st));
   const int64_t *rpA = A->on_device ? A->row_ptr : rp_in;
   const int32_t *colA = A->on_device ? A->col_idx : col_in;
+  const int64_t *rpAT = b.rpT;
+  const int32_t *colAT = b.colT;
+  const void *valAT = b.valT;
   const void *val_src = A->on_device ? A->values : val_raw;
   if (!A->on_device) {
     HIPCHK(hipMemcpyAsync(rp_in, A->row_ptr, 8 * (size_t)(m + 1), hipMemcpyHostToDevice, st));
@@ -560,22 +599,44 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   }
   tmark_begin(h, DASHSVD_KT_TRANSPOSE, 0);
   HIPCHK(launch_validate(m, n, nnz, rpA, colA, valA, vdt, b.rowidx, b.flags, st));
-  int32_t hflags[4] = {0, 0, 0, 0};
-  HIPCHK(hipMemcpyAsync(hflags, b.flags, sizeof(hflags), hipMemcpyDeviceToHost, st));
+  int32_t *hflags = h->hflags + 32;  // pinned
+  HIPCHK(hipMemcpyAsync(hflags, b.flags, 16, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (hflags[0] & 3) (void)hipStreamSynchronize(st2);  // Omega's writes end before the arena is reused
   if (hflags[0] & 1) return fail(h, DASHSVD_ERR_BAD_CSR, "row_ptr/col_idx malformed");
   if (hflags[0] & 2) return fail(h, DASHSVD_ERR_NONFINITE, "NaN or Inf among the values");
-  // CSR(A^T)
-  HIPCHK(launch_transpose(n, nnz, colA, b.rowidx, valA, vdt, b.rpT, b.colT, b.valT, b.tws, b.tws_bytes, st));
+  // CSR(A^T): the sort of the column keys gives its row pointer
+  HIPCHK(launch_transpose_keys(n, nnz, colA, b.rpT, b.tws, b.tws_bytes, st));
+  if (reorder) {
+    // degree order of the rows (from the row pointer of A) and of the
+    // columns (from that of A^T); the transposed entries are gathered
+    // straight into the permuted A^T, and A's entries move to the permuted A
+    HIPCHK(launch_degree_order(m, rpA, n, b.perm_r, b.inv_r, b.rpP, b.dws, b.dws_bytes, b.scan_tmp, st));
+    HIPCHK(launch_degree_order(n, b.rpT, m, b.perm_c, b.inv_c, b.rpPT, b.dws, b.dws_bytes, b.scan_tmp, st));
+    HIPCHK(launch_omega(wide ? b.inv_c : b.inv_r));
+    HIPCHK(launch_transpose_gather(nnz, b.rowidx, valA, vdt, b.tws, b.colT, b.valT, st, b.rpT, b.inv_r, b.inv_c,
+                                   b.rpPT));
+    HIPCHK(launch_permute_entries(nnz, rpA, b.rowidx, 0, colA, valA, vdt, b.inv_r, b.inv_c, b.rpP, b.colP, b.valP,
+                                  st));
+    rpA = b.rpP;
+    colA = b.colP;
+    valA = b.valP;
+    rpAT = b.rpPT;
+  } else {
+    HIPCHK(launch_transpose_gather(nnz, b.rowidx, valA, vdt, b.tws, b.colT, b.valT, st));
+  }
   tmark_end(h);
   // M and M^T
-  const int64_t *rpM = wide ? b.rpT : rpA;
-  const int32_t *colM = wide ? b.colT : colA;
-  const void *valM = wide ? b.valT : valA;
-  const int64_t *rpMT = wide ? rpA : b.rpT;
-  const int32_t *colMT = wide ? colA : b.colT;
-  const void *valMT = wide ? valA : b.valT;
+  const int64_t *rpM = wide ? rpAT : rpA;
+  const int32_t *colM = wide ? colAT : colA;
+  const void *valM = wide ? valAT : valA;
+  const int64_t *rpMT = wide ? rpA : rpAT;
+  const int32_t *colMT = wide ? colA : colAT;
+  const void *valMT = wide ? valA : valAT;
+  // rows of M and of M^T: where row i of the solver's U and V goes in the
+  // caller's order (null without the degree order)
+  const int32_t *mapM = reorder ? (wide ? b.perm_c : b.perm_r) : nullptr;
+  const int32_t *mapN = reorder ? (wide ? b.perm_r : b.perm_c) : nullptr;
   // SpMM plans
   Plan *plans[2] = {&b.planM, &b.planT};
   const int64_t *rps[2] = {rpM, rpMT};
@@ -585,17 +646,18 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     HIPCHK(launch_scan_i64(pl.nch, pl.R, pl.off, b.scan_tmp, st));
     HIPCHK(launch_plan_fill(pl.R, rps[i], T, pl.off, pl.tasks, pl.longs, pl.nlong, st));
   }
-  int64_t totals[2] = {0, 0};
-  int32_t nlongs[2] = {0, 0};
-  HIPCHK(hipMemcpyAsync(&totals[0], b.planM.off + b.planM.R, 8, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(&totals[1], b.planT.off + b.planT.R, 8, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(&nlongs[0], b.planM.nlong, 4, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(&nlongs[1], b.planT.nlong, 4, hipMemcpyDeviceToHost, st));
+  // the four plan sizes in one device buffer (the scan workspace is free
+  // again), one copy to pinned memory, one wait
+  int64_t *sizes_d = b.sizes;
+  int64_t *sizes_h = (int64_t *)(h->hflags + 16);
+  HIPCHK(launch_plan_sizes(b.planM.off + b.planM.R, b.planT.off + b.planT.R, b.planM.nlong, b.planT.nlong, sizes_d,
+                           st));
+  HIPCHK(hipMemcpyAsync(sizes_h, sizes_d, 32, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  b.planM.n_chunks = totals[0];
-  b.planT.n_chunks = totals[1];
-  b.planM.n_long = nlongs[0];
-  b.planT.n_long = nlongs[1];
+  b.planM.n_chunks = sizes_h[0];
+  b.planT.n_chunks = sizes_h[1];
+  b.planM.n_long = (int32_t)sizes_h[2];
+  b.planT.n_long = (int32_t)sizes_h[3];
   if (!h->sched.empty())
     HIPCHK(hipMemcpyAsync(b.sched, h->sched.data(), 8 * h->sched.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamWaitEvent(st, h->ev_eig, 0));  // Omega is ready
@@ -842,9 +904,9 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     HIPCHK(launch_small_gemm(l, k, l, b.W, l, 0, b.Vs, l, b.PV, k, st));
     // V first; its sign normalisation flips V and the columns of W W_B, so
     // U comes out with the matching signs
-    HIPCHK(launch_rescale(Mn, l, Cl, ld, cdt, b.PV, k, k, b.Vo, k, cdt, nullptr, st));
+    HIPCHK(launch_rescale(Mn, l, Cl, ld, cdt, b.PV, k, k, b.Vo, k, cdt, nullptr, st, nullptr, nullptr, mapN));
     HIPCHK(launch_sign_fold(Mn, k, b.Vo, k, cdt, b.PU, l, k, b.sgn_max, b.sgn_idx, sgn_blk, st));
-    HIPCHK(launch_rescale(Mm, l, b.Z, ld, cdt, b.PU, k, k, b.Uo, k, cdt, nullptr, st));
+    HIPCHK(launch_rescale(Mm, l, b.Z, ld, cdt, b.PU, k, k, b.Uo, k, cdt, nullptr, st, nullptr, nullptr, mapM));
   } else {
     void *Qf = Qfin, *Bf = b.B;
     if (pfin != cdt) {
@@ -861,8 +923,8 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       EigArgs ea = make_eig(3);
       HIPCHK(launch_eig(ea, st));
     }
-    HIPCHK(launch_rescale(Mm, l, Bf, ld, cdt, b.W, l, k, b.Uo, k, cdt, nullptr, st));
-    HIPCHK(launch_rescale(Mn, l, Qf, ld, pfin, b.Vs, l, k, b.Vo, k, cdt, nullptr, st));
+    HIPCHK(launch_rescale(Mm, l, Bf, ld, cdt, b.W, l, k, b.Uo, k, cdt, nullptr, st, nullptr, nullptr, mapM));
+    HIPCHK(launch_rescale(Mn, l, Qf, ld, pfin, b.Vs, l, k, b.Vo, k, cdt, nullptr, st, nullptr, nullptr, mapN));
     HIPCHK(launch_sign_fix(Mn, Mm, k, b.Vo, k, b.Uo, k, cdt, b.sgn_max, b.sgn_idx, sgn_blk, st));
   }
   tmark_end(h);
@@ -944,6 +1006,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     c.panel_n = b.C;
     c.gpart = b.gpart;
     c.G = b.G;
+    c.u_row_to = reorder ? b.inv_r : nullptr;
   }
   dashsvd_status s = DASHSVD_OK;
   if (tol > 0.0 && !hs.converged) s = DASHSVD_NOT_CONVERGED;
@@ -1034,7 +1097,8 @@ dashsvd_status dashsvd_evaluate(dashsvd_handle *h, const dashsvd_csr *A, const d
   const int64_t zrows = c.wide ? c.Mm : c.Mn, urows = h->m;
   void *Upad = c.wide ? c.panel_n : c.panel_m;  // urows x ld8
   void *Z = c.wide ? c.panel_m : c.panel_n;     // zrows x ld8
-  HIPCHK(launch_copy2d(h->U, k, h->out_dt, Upad, ld8, c.cdt, urows, k, st));
+  // with the degree order, U (rows of A) enters in the permuted row order
+  HIPCHK(launch_copy2d(h->U, k, h->out_dt, Upad, ld8, c.cdt, urows, k, st, c.u_row_to));
   const Plan &pl = c.plan[side];
   HIPCHK(launch_spmm(zrows, c.rp[side], c.col[side], c.val[side], c.vdt, Upad, ld8, c.cdt, Z, ld8, c.cdt, ld8,
                      pl.n_chunks, pl.tasks, pl.n_long, pl.longs, pl.partial, c.T, nullptr, 0, nullptr, nullptr,

@@ -127,6 +127,8 @@ __device__ __forceinline__ int64_t row_of(const int64_t *__restrict__ rp, int64_
 }
 
 // ------------------------------------------------------------------ validation
+constexpr int kValChunk = 8;  // consecutive nonzeros per thread
+
 template <typename TV>
 __global__ __launch_bounds__(256) void k_validate(int64_t m, int64_t n, int64_t nnz,
                                                   const int64_t *__restrict__ rp,
@@ -141,16 +143,39 @@ __global__ __launch_bounds__(256) void k_validate(int64_t m, int64_t n, int64_t 
   for (int64_t r = t0; r < m; r += stride) bad |= rp[r] > rp[r + 1];
   if (t0 == 0 && (rp[0] != 0 || rp[m] != nnz)) bad = 1;
   if (m > 0) {
-    for (int64_t e = t0; e < nnz; e += stride) {
-      const int64_t r = row_of(rp, m, e);
-      const int32_t c = col[e];
-      rowidx[e] = (int32_t)r;
-      if (c < 0 || (int64_t)c >= n)
-        bad = 1;
-      else if (e > 0 && e > rp[r] && col[e - 1] >= c)
-        bad = 1;
-      const double v = (double)val[e];
-      if (!(v - v == 0.0)) nonfinite = 1;
+    // each thread takes kValChunk consecutive nonzeros: one binary search for
+    // the first, then a short walk along the row pointer (a binary search
+    // again after more than 8 rows, so runs of empty rows stay cheap); with a
+    // malformed row pointer the rows found may be wrong, but the flag above
+    // is then set and they are never used
+    for (int64_t cbeg = t0 * kValChunk; cbeg < nnz; cbeg += stride * kValChunk) {
+      int64_t r = row_of(rp, m, cbeg);
+      int64_t rbeg = rp[r], rend = rp[r + 1];
+#pragma unroll
+      for (int k = 0; k < kValChunk; ++k) {
+        const int64_t e = cbeg + k;
+        if (e >= nnz) break;
+        int steps = 0;
+        while (e >= rend && r + 1 < m && steps < 8) {
+          ++r;
+          rbeg = rend;
+          rend = rp[r + 1];
+          ++steps;
+        }
+        if (e >= rend) {
+          r = row_of(rp, m, e);
+          rbeg = rp[r];
+          rend = rp[r + 1];
+        }
+        const int32_t c = col[e];
+        rowidx[e] = (int32_t)r;
+        if (c < 0 || (int64_t)c >= n)
+          bad = 1;
+        else if (e > 0 && e > rbeg && col[e - 1] >= c)
+          bad = 1;
+        const double v = (double)val[e];
+        if (!(v - v == 0.0)) nonfinite = 1;
+      }
     }
   }
   // one atomic per wavefront and flag
@@ -173,6 +198,29 @@ __global__ __launch_bounds__(256) void k_tgather(int64_t nnz, const int32_t *__r
   }
 }
 
+// The same gather straight into the degree-ordered structure: sorted entry p
+// (column j = keys[p] of A, source nonzero src[p]) goes to row inv_c[j] of
+// the permuted A^T at its offset inside column j, with its row r of A
+// renumbered inv_r[r].
+template <typename TV>
+__global__ __launch_bounds__(256) void k_tgather_perm(int64_t nnz, const int32_t *__restrict__ src,
+                                                      const uint32_t *__restrict__ keys,
+                                                      const int32_t *__restrict__ rowidx,
+                                                      const TV *__restrict__ val, const int64_t *__restrict__ rowT,
+                                                      const int32_t *__restrict__ inv_r,
+                                                      const int32_t *__restrict__ inv_c,
+                                                      const int64_t *__restrict__ rp_new,
+                                                      int32_t *__restrict__ colT, TV *__restrict__ valT) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += stride) {
+    const int64_t j = (int64_t)keys[p];
+    const int32_t s = src[p];
+    const int64_t pos = rp_new[inv_c[j]] + (p - rowT[j]);
+    colT[pos] = inv_r[rowidx[s]];
+    valT[pos] = val[s];
+  }
+}
+
 // Row pointer of A^T: rowT[c] = first position whose sorted column key is
 // >= c (c = 0..n; rowT[n] = nnz).
 __global__ __launch_bounds__(256) void k_tbounds(int64_t n, int64_t nnz, const uint32_t *__restrict__ keys,
@@ -185,6 +233,66 @@ __global__ __launch_bounds__(256) void k_tbounds(int64_t n, int64_t nnz, const u
       if ((int64_t)keys[mid] < c) lo = mid + 1; else hi = mid;
     }
     rowT[c] = lo;
+  }
+}
+
+// ------------------------------------------------------------------ degree order
+// Locality order of the operator: rows (and, on the transposed structure,
+// columns) by non-increasing number of nonzeros, ties by index.  Solving
+// P_r A P_c^T instead of A leaves the singular values unchanged and permutes
+// U and V by P_r and P_c; the products then gather the panel rows of the
+// dense columns from one compact region of memory.
+
+// Sort key of row i: its length (a stable descending sort lists long rows
+// first and keeps index order in ties).
+__global__ __launch_bounds__(256) void k_degree_keys(int64_t R, const int64_t *__restrict__ rp,
+                                                     uint32_t *__restrict__ key) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < R; i += stride)
+    key[i] = (uint32_t)(rp[i + 1] - rp[i]);
+}
+
+// inv[perm[i]] = i, and the row lengths in the new order.
+__global__ __launch_bounds__(256) void k_perm_invert(int64_t R, const int64_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ perm, int32_t *__restrict__ inv,
+                                                     int64_t *__restrict__ len) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < R; i += stride) {
+    const int32_t o = perm[i];
+    inv[o] = (int32_t)i;
+    len[i] = rp[o + 1] - rp[o];
+  }
+}
+
+// Entry e of row r moves to row inv_r[r] of the permuted structure, at the
+// same offset inside the row; its column c becomes inv_c[c].
+template <typename TV, typename TR>
+__global__ __launch_bounds__(256) void k_permute_entries(int64_t nnz, const int64_t *__restrict__ rp,
+                                                         const TR *__restrict__ row_of,
+                                                         const int32_t *__restrict__ col,
+                                                         const TV *__restrict__ val,
+                                                         const int32_t *__restrict__ inv_r,
+                                                         const int32_t *__restrict__ inv_c,
+                                                         const int64_t *__restrict__ rp_new,
+                                                         int32_t *__restrict__ col_new, TV *__restrict__ val_new) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride) {
+    const int64_t r = (int64_t)row_of[e];
+    const int64_t pos = rp_new[inv_r[r]] + (e - rp[r]);
+    col_new[pos] = inv_c[col[e]];
+    val_new[pos] = val[e];
+  }
+}
+
+// The sizes the host needs to launch the products, in one place for one copy.
+__global__ void k_plan_sizes(const int64_t *__restrict__ endM, const int64_t *__restrict__ endT,
+                             const int32_t *__restrict__ nlM, const int32_t *__restrict__ nlT,
+                             int64_t *__restrict__ out) {
+  if (threadIdx.x == 0) {
+    out[0] = *endM;
+    out[1] = *endT;
+    out[2] = *nlM;
+    out[3] = *nlT;
   }
 }
 
@@ -251,7 +359,8 @@ hipError_t launch_scan_i64(const int64_t *in, int64_t n, int64_t *out, int64_t *
 
 hipError_t launch_validate(int64_t m, int64_t n, int64_t nnz, const int64_t *rp, const int32_t *col,
                            const void *val, int dtype, int32_t *rowidx, int32_t *flags, hipStream_t st) {
-  const int64_t work = nnz > m ? nnz : m;
+  const int64_t chunks = (nnz + kValChunk - 1) / kValChunk;
+  const int64_t work = chunks > m ? chunks : m;
   const int g = grid_for(work, 256, 16384);
   if (dtype == 1)
     hipLaunchKernelGGL(k_validate<double>, dim3(g), dim3(256), 0, st, m, n, nnz, rp, col,
@@ -271,9 +380,8 @@ size_t transpose_ws_bytes(int64_t n, int64_t nnz) {
   return 2 * 4 * (cnt + 64) + sort_bytes + 256;
 }
 
-hipError_t launch_transpose(int64_t n, int64_t nnz, const int32_t *col, const int32_t *rowidx, const void *val,
-                            int dtype, int64_t *rowT, int32_t *colT, void *valT, void *ws, size_t ws_bytes,
-                            hipStream_t st) {
+hipError_t launch_transpose_keys(int64_t n, int64_t nnz, const int32_t *col, int64_t *rowT, void *ws,
+                                 size_t ws_bytes, hipStream_t st) {
   const size_t cnt = nnz > 0 ? (size_t)nnz : 1;
   uint32_t *keys = (uint32_t *)ws;
   int32_t *src = (int32_t *)(keys + cnt + 64);
@@ -285,7 +393,27 @@ hipError_t launch_transpose(int64_t n, int64_t nnz, const int32_t *col, const in
                                                    rocprim::counting_iterator<int32_t>(0), src, (size_t)nnz, 0u,
                                                    key_bits(n), st);
     if (e != hipSuccess) return e;
-    const int g = grid_for(nnz, 256, 16384);
+  }
+  hipLaunchKernelGGL(k_tbounds, dim3(grid_for(n + 1, 256, 16384)), dim3(256), 0, st, n, nnz, keys, rowT);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_gather(int64_t nnz, const int32_t *rowidx, const void *val, int dtype, const void *ws,
+                                   int32_t *colT, void *valT, hipStream_t st, const int64_t *rowT,
+                                   const int32_t *inv_r, const int32_t *inv_c, const int64_t *rp_new) {
+  if (nnz == 0) return hipSuccess;
+  const size_t cnt = (size_t)nnz;
+  const uint32_t *keys = (const uint32_t *)ws;
+  const int32_t *src = (const int32_t *)(keys + cnt + 64);
+  const int g = grid_for(nnz, 256, 16384);
+  if (inv_r) {
+    if (dtype == 1)
+      hipLaunchKernelGGL(k_tgather_perm<double>, dim3(g), dim3(256), 0, st, nnz, src, keys, rowidx,
+                         (const double *)val, rowT, inv_r, inv_c, rp_new, colT, (double *)valT);
+    else
+      hipLaunchKernelGGL(k_tgather_perm<float>, dim3(g), dim3(256), 0, st, nnz, src, keys, rowidx,
+                         (const float *)val, rowT, inv_r, inv_c, rp_new, colT, (float *)valT);
+  } else {
     if (dtype == 1)
       hipLaunchKernelGGL(k_tgather<double>, dim3(g), dim3(256), 0, st, nnz, src, rowidx, (const double *)val,
                          colT, (double *)valT);
@@ -293,7 +421,66 @@ hipError_t launch_transpose(int64_t n, int64_t nnz, const int32_t *col, const in
       hipLaunchKernelGGL(k_tgather<float>, dim3(g), dim3(256), 0, st, nnz, src, rowidx, (const float *)val,
                          colT, (float *)valT);
   }
-  hipLaunchKernelGGL(k_tbounds, dim3(grid_for(n + 1, 256, 16384)), dim3(256), 0, st, n, nnz, keys, rowT);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose(int64_t n, int64_t nnz, const int32_t *col, const int32_t *rowidx, const void *val,
+                            int dtype, int64_t *rowT, int32_t *colT, void *valT, void *ws, size_t ws_bytes,
+                            hipStream_t st) {
+  const hipError_t e = launch_transpose_keys(n, nnz, col, rowT, ws, ws_bytes, st);
+  if (e != hipSuccess) return e;
+  return launch_transpose_gather(nnz, rowidx, val, dtype, ws, colT, valT, st);
+}
+
+size_t degree_order_ws_bytes(int64_t R) {
+  size_t sort_bytes = 0;
+  const size_t cnt = R > 0 ? (size_t)R : 1;
+  (void)rocprim::radix_sort_pairs_desc(nullptr, sort_bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                                       rocprim::counting_iterator<int32_t>(0), (int32_t *)nullptr, cnt, 0u, 32u);
+  return 2 * 4 * (cnt + 64) + 8 * (cnt + 64) + sort_bytes + 256;
+}
+
+hipError_t launch_degree_order(int64_t R, const int64_t *rp, int64_t max_len, int32_t *perm, int32_t *inv,
+                               int64_t *rp_new, void *ws, size_t ws_bytes, int64_t *scan_tmp, hipStream_t st) {
+  if (R == 0) return hipMemsetAsync(rp_new, 0, sizeof(int64_t), st);
+  const size_t cnt = (size_t)R;
+  uint32_t *keys = (uint32_t *)ws;
+  uint32_t *keys_sorted = keys + cnt + 64;
+  int64_t *len = (int64_t *)(keys_sorted + cnt + 64);
+  void *tmp = (void *)(len + cnt + 64);
+  size_t tmp_bytes = ws_bytes - 2 * 4 * (cnt + 64) - 8 * (cnt + 64);
+  const int g = grid_for(R, 256, 16384);
+  hipLaunchKernelGGL(k_degree_keys, dim3(g), dim3(256), 0, st, R, rp, keys);
+  // lengths are at most max_len: sort on the bits that can be set
+  hipError_t e = rocprim::radix_sort_pairs_desc(tmp, tmp_bytes, (const uint32_t *)keys, keys_sorted,
+                                                rocprim::counting_iterator<int32_t>(0), perm, cnt, 0u,
+                                                key_bits(max_len + 1), st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_perm_invert, dim3(g), dim3(256), 0, st, R, rp, perm, inv, len);
+  return launch_scan_i64(len, R, rp_new, scan_tmp, st);
+}
+
+hipError_t launch_permute_entries(int64_t nnz, const int64_t *rp, const int32_t *row_of, int row_of_unsigned,
+                                  const int32_t *col, const void *val, int dtype, const int32_t *inv_r,
+                                  const int32_t *inv_c, const int64_t *rp_new, int32_t *col_new, void *val_new,
+                                  hipStream_t st) {
+  if (nnz == 0) return hipSuccess;
+  const int g = grid_for(nnz, 256, 16384);
+#define DSV_PERM(TV, TR)                                                                                   \
+  hipLaunchKernelGGL((k_permute_entries<TV, TR>), dim3(g), dim3(256), 0, st, nnz, rp, (const TR *)row_of, \
+                     col, (const TV *)val, inv_r, inv_c, rp_new, col_new, (TV *)val_new)
+  if (dtype == 1) {
+    if (row_of_unsigned) DSV_PERM(double, uint32_t); else DSV_PERM(double, int32_t);
+  } else {
+    if (row_of_unsigned) DSV_PERM(float, uint32_t); else DSV_PERM(float, int32_t);
+  }
+#undef DSV_PERM
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_sizes(const int64_t *endM, const int64_t *endT, const int32_t *nlM, const int32_t *nlT,
+                             int64_t *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_plan_sizes, dim3(1), dim3(64), 0, st, endM, endT, nlM, nlT, out);
   return hipGetLastError();
 }
 

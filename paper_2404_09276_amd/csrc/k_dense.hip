@@ -244,7 +244,8 @@ __global__ __launch_bounds__(kRescaleThreads) void k_rescale_mfma(int64_t r, int
                                                                   int64_t ldw, int c, TO *__restrict__ Out,
                                                                   int64_t ldo, const int32_t *__restrict__ done,
                                                                   const TC *__restrict__ R,
-                                                                  const double *__restrict__ alpha) {
+                                                                  const double *__restrict__ alpha,
+                                                                  const int32_t *__restrict__ row_to) {
   if (done && *done) return;
   constexpr int NW = kRescaleThreads / 64;
   const double a_sh = R ? *alpha : 0.0;
@@ -344,27 +345,30 @@ __global__ __launch_bounds__(kRescaleThreads) void k_rescale_mfma(int64_t r, int
     }
     if (sl == nslab - 1) {
       const int64_t rbase = tile * 16 + 4 * kq;
+      int64_t dst[4];  // output rows of this lane's four accumulator rows
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t orow = rbase + q;
+        dst[q] = orow < r ? (row_to ? (int64_t)row_to[orow] : orow) : -1;
+      }
 #pragma unroll
       for (int J = 0; J < LTO; ++J) {
         const int col = J * 16 + lr;
         if (col < ldo) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const int64_t orow = rbase + q;
             float v = acc[J][q];
             asm volatile("" : "+v"(v));
-            if (orow < r) elem<TO>::st(Out + orow * ldo + col, col < c ? v : 0.0f);
+            if (dst[q] >= 0) elem<TO>::st(Out + dst[q] * ldo + col, col < c ? v : 0.0f);
           }
         }
         acc[J] = f4{0.f, 0.f, 0.f, 0.f};
       }
       // columns beyond the tiles (ldo > WC) are zero
       if (ldo > WC) {
-        for (int q = 0; q < 4; ++q) {
-          const int64_t orow = rbase + q;
-          if (orow < r)
-            for (int64_t cc = WC + lr; cc < ldo; cc += 16) elem<TO>::st(Out + orow * ldo + cc, 0.0f);
-        }
+        for (int q = 0; q < 4; ++q)
+          if (dst[q] >= 0)
+            for (int64_t cc = WC + lr; cc < ldo; cc += 16) elem<TO>::st(Out + dst[q] * ldo + cc, 0.0f);
       }
     }
     advance(tile, sl);
@@ -388,7 +392,8 @@ __global__ __launch_bounds__(256) void k_rescale_f64(int64_t r, int l, const TC 
                                                      int64_t ldw, int c, double *__restrict__ Out,
                                                      int64_t ldo, const int32_t *__restrict__ done,
                                                      const TC *__restrict__ R,
-                                                     const double *__restrict__ alpha) {
+                                                     const double *__restrict__ alpha,
+                                                     const int32_t *__restrict__ row_to) {
   if (done && *done) return;
   const double a_sh = R ? *alpha : 0.0;
   const int64_t total = r * ldo;
@@ -406,7 +411,7 @@ __global__ __launch_bounds__(256) void k_rescale_f64(int64_t r, int l, const TC 
         for (int k = 0; k < l; ++k) s = fma(to_d(cr[k]), W[(int64_t)k * ldw + col], s);
       }
     }
-    Out[row * ldo + col] = s;
+    Out[(row_to ? (int64_t)row_to[row] : row) * ldo + col] = s;
   }
 }
 
@@ -535,15 +540,18 @@ __global__ __launch_bounds__(256) void k_sign_apply(int64_t rowsV, int64_t rowsU
 }
 
 // ------------------------------------------------------------------ conversion
+// row_to (optional): input row i goes to output row row_to[i].
 template <typename TI, typename TO>
 __global__ __launch_bounds__(256) void k_copy2d(const TI *__restrict__ in, int64_t ldi, TO *__restrict__ out,
-                                                int64_t ldo, int64_t rows, int cols) {
+                                                int64_t ldo, int64_t rows, int cols,
+                                                const int32_t *__restrict__ row_to) {
   const int64_t total = rows * cols;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
     const int64_t i = e / cols;
     const int j = (int)(e - i * cols);
-    out[i * ldo + j] = (TO)in[i * ldi + j];
+    const int64_t io = row_to ? (int64_t)row_to[i] : i;
+    elem<TO>::st(out + io * ldo + j, (decltype(elem<TO>::ld(out)))to_d(in[i * ldi + j]));
   }
 }
 
@@ -586,7 +594,7 @@ hipError_t gram_dispatch(int64_t r, int l, const TC *C, int64_t ldc, double *par
 template <typename TC, typename TO>
 hipError_t rescale_dispatch(int64_t r, int l, const TC *C, int64_t ldc, const double *W, int64_t ldw,
                             int c, TO *Out, int64_t ldo, const int32_t *done, const TC *R,
-                            const double *alpha, hipStream_t st) {
+                            const double *alpha, hipStream_t st, const int32_t *row_to) {
   const int LTO = (c + 15) / 16;
   const int LK = (l + 15) & ~15;
   const int64_t ntiles = (r + 15) / 16;
@@ -600,7 +608,7 @@ hipError_t rescale_dispatch(int64_t r, int l, const TC *C, int64_t ldc, const do
   case LTV: {                                                                               \
     const size_t shm = sizeof(float) * (size_t)LK * (LTV * 16 + 4);                         \
     hipLaunchKernelGGL((k_rescale_mfma<TC, TO, LTV>), dim3(grid), dim3(kRescaleThreads), shm, st, r, l, C, ldc, W, \
-                       ldw, c, Out, ldo, done, R, alpha);                                   \
+                       ldw, c, Out, ldo, done, R, alpha, row_to);                           \
     break;                                                                                  \
   }
   switch (LTO) {
@@ -636,7 +644,7 @@ hipError_t launch_gram(int64_t r, int l, const void *C, int64_t ldc, int cdtype,
 
 hipError_t launch_rescale(int64_t r, int l, const void *C, int64_t ldc, int cdtype, const double *W,
                           int64_t ldw, int c, void *Out, int64_t ldo, int odtype, const int32_t *done,
-                          hipStream_t st, const void *R, const double *alpha) {
+                          hipStream_t st, const void *R, const double *alpha, const int32_t *row_to) {
   if (R && !alpha) return hipErrorInvalidValue;
   if (l < 1 || l > kMaxL || c < 1 || c > kMaxL || r == 0) return r == 0 ? hipSuccess : hipErrorInvalidValue;
   static bool attr_done = false;
@@ -658,23 +666,23 @@ hipError_t launch_rescale(int64_t r, int l, const void *C, int64_t ldc, int cdty
     const int g = grid_for(r * ldo, 256, 16384);
     if (cdtype == 1)
       hipLaunchKernelGGL(k_rescale_f64<double>, dim3(g), dim3(256), 0, st, r, l, (const double *)C, ldc, W, ldw,
-                         c, (double *)Out, ldo, done, (const double *)R, alpha);
+                         c, (double *)Out, ldo, done, (const double *)R, alpha, row_to);
     else if (cdtype == 0)
       hipLaunchKernelGGL(k_rescale_f64<float>, dim3(g), dim3(256), 0, st, r, l, (const float *)C, ldc, W, ldw, c,
-                         (double *)Out, ldo, done, (const float *)R, alpha);
+                         (double *)Out, ldo, done, (const float *)R, alpha, row_to);
     else
       return hipErrorInvalidValue;
     return hipGetLastError();
   }
   if (cdtype == 0 && odtype == 0)
     return rescale_dispatch<float, float>(r, l, (const float *)C, ldc, W, ldw, c, (float *)Out, ldo, done,
-                                          (const float *)R, alpha, st);
+                                          (const float *)R, alpha, st, row_to);
   if (cdtype == 0 && odtype == 2)
     return rescale_dispatch<float, bf16>(r, l, (const float *)C, ldc, W, ldw, c, (bf16 *)Out, ldo, done,
-                                         (const float *)R, alpha, st);
+                                         (const float *)R, alpha, st, row_to);
   if (cdtype == 2 && odtype == 0)
     return rescale_dispatch<bf16, float>(r, l, (const bf16 *)C, ldc, W, ldw, c, (float *)Out, ldo, done,
-                                         (const bf16 *)R, alpha, st);
+                                         (const bf16 *)R, alpha, st, row_to);
   return hipErrorInvalidValue;
 }
 
@@ -704,16 +712,19 @@ hipError_t launch_sign_fix(int64_t rowsV, int64_t rowsU, int k, void *V, int64_t
   return hipGetLastError();
 }
 
-hipError_t launch_copy2d(const void *in, int64_t ldi, int idtype, void *out, int64_t ldo, int odtype,
-                         int64_t rows, int cols, hipStream_t st) {
+hipError_t launch_copy2d(const void *in, int64_t ldi, int idtype, void *out, int64_t ldo, int odtype, int64_t rows,
+                         int cols, hipStream_t st, const int32_t *row_to) {
   if (rows * cols == 0) return hipSuccess;
   const int g = grid_for(rows * cols, 256, 16384);
 #define DSV_CP(TI, TO) \
-  hipLaunchKernelGGL((k_copy2d<TI, TO>), dim3(g), dim3(256), 0, st, (const TI *)in, ldi, (TO *)out, ldo, rows, cols)
+  hipLaunchKernelGGL((k_copy2d<TI, TO>), dim3(g), dim3(256), 0, st, (const TI *)in, ldi, (TO *)out, ldo, rows, cols, \
+                     row_to)
   if (idtype == 0 && odtype == 0) DSV_CP(float, float);
   else if (idtype == 0 && odtype == 1) DSV_CP(float, double);
   else if (idtype == 1 && odtype == 0) DSV_CP(double, float);
   else if (idtype == 1 && odtype == 1) DSV_CP(double, double);
+  else if (idtype == 0 && odtype == 2) DSV_CP(float, bf16);
+  else if (idtype == 1 && odtype == 2) DSV_CP(double, bf16);
   else return hipErrorInvalidValue;
 #undef DSV_CP
   return hipGetLastError();

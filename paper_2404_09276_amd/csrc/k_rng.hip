@@ -49,9 +49,12 @@ __device__ __forceinline__ void box_muller(uint64_t w0, uint64_t w1, double &z0,
   z1 = r * s;
 }
 
+// row_to (optional): element (r, c) of the block is stored in row row_to[r]
+// of out (the block drawn in one row order, stored in another).
 template <typename TO>
 __global__ __launch_bounds__(256) void k_gaussian(uint64_t seed, int64_t rows, int64_t cols,
-                                                  TO *__restrict__ out, int64_t ld) {
+                                                  TO *__restrict__ out, int64_t ld,
+                                                  const int32_t *__restrict__ row_to) {
   const int64_t total = rows * cols;
   const int64_t nblk = (total + 3) / 4;
   for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nblk;
@@ -66,7 +69,8 @@ __global__ __launch_bounds__(256) void k_gaussian(uint64_t seed, int64_t rows, i
       const int64_t e = 4 * b + i;
       if (e < total) {
         const int64_t r = e / cols, c = e - r * cols;
-        elem<TO>::st(out + r * ld + c, (decltype(elem<TO>::ld(out)))z[i]);
+        const int64_t ro = row_to ? (int64_t)row_to[r] : r;
+        elem<TO>::st(out + ro * ld + c, (decltype(elem<TO>::ld(out)))z[i]);
       }
     }
   }
@@ -95,16 +99,16 @@ int grid_for(int64_t work, int block) {
 }  // namespace
 
 hipError_t launch_gaussian(uint64_t seed, int64_t rows, int64_t cols, void *out, int64_t ld,
-                           int dtype, hipStream_t st) {
+                           int dtype, hipStream_t st, const int32_t *row_to) {
   const int64_t nblk = (rows * cols + 3) / 4;
   if (nblk == 0) return hipSuccess;
   const int g = grid_for(nblk, 256);
   if (dtype == 0)
-    hipLaunchKernelGGL(k_gaussian<float>, dim3(g), dim3(256), 0, st, seed, rows, cols, (float *)out, ld);
+    hipLaunchKernelGGL(k_gaussian<float>, dim3(g), dim3(256), 0, st, seed, rows, cols, (float *)out, ld, row_to);
   else if (dtype == 1)
-    hipLaunchKernelGGL(k_gaussian<double>, dim3(g), dim3(256), 0, st, seed, rows, cols, (double *)out, ld);
+    hipLaunchKernelGGL(k_gaussian<double>, dim3(g), dim3(256), 0, st, seed, rows, cols, (double *)out, ld, row_to);
   else
-    hipLaunchKernelGGL(k_gaussian<bf16>, dim3(g), dim3(256), 0, st, seed, rows, cols, (bf16 *)out, ld);
+    hipLaunchKernelGGL(k_gaussian<bf16>, dim3(g), dim3(256), 0, st, seed, rows, cols, (bf16 *)out, ld, row_to);
   return hipGetLastError();
 }
 

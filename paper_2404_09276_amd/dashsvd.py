@@ -26,6 +26,8 @@ PVE = {"r2": 0, "r1": 1}
 EIG = {"auto": 0, "jacobi": 1}
 # timing: False / True (every kernel group) / "spmm" (the two SpMM groups only)
 TIMING = {False: 0, True: 1, "spmm": 2}
+# reorder: "auto" (from 2^22 nonzeros), True, False
+REORDER = {"auto": 0, True: 1, False: -1}
 MAX_L = 160
 MAX_TRACE = 256
 
@@ -47,7 +49,8 @@ class _Options(C.Structure):
                 ("p_max", C.c_int32), ("seed", C.c_uint64), ("hip_stream", C.c_void_p),
                 ("long_row", C.c_int32), ("check_interval", C.c_int32), ("schedule", C.c_void_p),
                 ("omega", C.c_void_p), ("omega_dtype", C.c_int32), ("omega_on_device", C.c_int32),
-                ("timing", C.c_int32), ("tuning_db", C.c_char_p), ("eig_method", C.c_int32)]
+                ("timing", C.c_int32), ("tuning_db", C.c_char_p), ("eig_method", C.c_int32),
+                ("reorder", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -223,17 +226,17 @@ class DashSVD:
     def __init__(self, precision: str = "fp32", shift_policy: str = "paper", pve_mode: str = "r2",
                  p_max: int = -1, seed: int = 0, stream=None, long_row: int = 0,
                  check_interval: int = 1, schedule=None, omega=None, timing=False,
-                 tuning_db=None, eig_method: str = "auto"):
+                 tuning_db=None, eig_method: str = "auto", reorder="auto"):
         self._h = C.c_void_p()
         self._keep = []
         opt = self._options(precision, shift_policy, pve_mode, p_max, seed, stream, long_row,
-                            check_interval, schedule, omega, timing, tuning_db, eig_method)
+                            check_interval, schedule, omega, timing, tuning_db, eig_method, reorder)
         st = lib().dashsvd_create(C.byref(self._h), C.byref(opt))
         _check(st, None)
 
     def _options(self, precision="fp32", shift_policy="paper", pve_mode="r2", p_max=-1, seed=0,
                  stream=None, long_row=0, check_interval=1, schedule=None, omega=None,
-                 timing=False, tuning_db=None, eig_method="auto"):
+                 timing=False, tuning_db=None, eig_method="auto", reorder="auto"):
         sched_arr = None
         if schedule is not None:
             sched_arr = np.ascontiguousarray(schedule, dtype=np.float64)
@@ -249,7 +252,7 @@ class DashSVD:
                         stream or None, long_row, check_interval,
                         _ptr(sched_arr).value if sched_arr is not None else None,
                         om_ptr, om_dt, om_dev, TIMING[timing],
-                        tuning_db.encode() if tuning_db else None, EIG[eig_method])
+                        tuning_db.encode() if tuning_db else None, EIG[eig_method], REORDER[reorder])
 
     def set_options(self, **kw):
         opt = self._options(**kw)

@@ -195,6 +195,68 @@ def test_timing_levels_and_stop_test(torch_dev, timing):
     assert info.kt_count["spmm"] == info.passes + 1
 
 
+@pytest.mark.parametrize("shape,prec", [((30000, 12000), "fp32"), ((9000, 21000), "fp32"),
+                                        ((8000, 5000), "fp64")])
+def test_degree_order_matches_oracle(torch_dev, shape, prec):
+    """The solver on P_r A P_c^T (rows and columns by non-increasing degree):
+    same singular values and shifts as the oracle on A, and U, V returned in
+    A's own row orders (tall and wide)."""
+    m, n = shape
+    A = synth.zipf_csr(m, n, 500000, seed=m + n)
+    if prec == "fp64":
+        A.val = A.val.astype(np.float64)
+    ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 20, 10, 4, 0.0, seed=23)
+    U, S, V, st, info, tr = _solve(A, 20, 10, 4, 0.0, 23, prec, reorder=True)
+    assert st == 0 and U.shape == (m, 20) and V.shape == (n, 20)
+    bar = 1e-10 if prec == "fp64" else 1e-5
+    assert np.all(np.abs(S - ref.S) / ref.S <= bar)
+    assert np.allclose(info.alpha_used, ref.alpha, rtol=bar)
+    # leading vectors (well separated): equal up to the normalised sign
+    vb = 1e-7 if prec == "fp64" else 2e-3
+    assert _vec_close(U[:, :5], ref.U[:, :5], vb) and _vec_close(V[:, :5], ref.V[:, :5], vb)
+    # every column, in the caller's row order: the residual |A v - sigma u|
+    # of the approximation is the oracle's (4 passes leave the trailing
+    # triplets unconverged by the same amount)
+    D = A.to_dense().astype(np.float64)
+    res = np.abs(D @ V.astype(np.float64) - U.astype(np.float64) * S).max(axis=0) / S
+    rref = np.abs(D @ ref.V - ref.U * ref.S).max(axis=0) / ref.S
+    assert np.all(res <= rref + (1e-9 if prec == "fp64" else 1e-4))
+
+
+def test_degree_order_same_result_as_plain_order(torch_dev):
+    """Reordering changes only the summation order: with and without it the
+    singular values agree to FP32 rounding, the vectors to the sign, and the
+    on-device accuracy metrics agree."""
+    from paper_2404_09276_amd import DashSVD
+    A = synth.zipf_csr(20000, 9000, 400000, seed=41)
+    out = {}
+    for ro in (False, True):
+        h = DashSVD(precision="fp32", p_max=64, seed=3, reorder=ro)
+        st = h.run(A, 16, 8, 1e-2)
+        U, S, V = h.get_usv()
+        sig = np.linalg.svd(A.to_dense().astype(np.float64), compute_uv=False)[:17]
+        out[ro] = (U, S, V, h.info().passes, h.evaluate(A, sig))
+        h.close()
+    (U0, S0, V0, p0, e0), (U1, S1, V1, p1, e1) = out[False], out[True]
+    assert p0 == p1
+    assert np.all(np.abs(S0 - S1) / S0 <= 1e-5)
+    assert _vec_close(U0[:, :4], U1[:, :4], 1e-3) and _vec_close(V0[:, :4], V1[:, :4], 1e-3)
+    assert abs(e0[0] - e1[0]) <= 1e-4 and abs(e0[1] - e1[1]) <= 1e-5
+
+
+def test_degree_order_bf16_and_given_omega(torch_dev):
+    """A caller-provided Omega (in A's row order) and BF16 panels under the
+    degree order: same singular values as the oracle."""
+    A = synth.zipf_csr(12000, 7000, 300000, seed=55)
+    om = np.random.default_rng(9).standard_normal((A.m, 24))
+    ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 16, 8, 4, 0.0, seed=0, omega=om)
+    U, S, V, st, info, tr = _solve(A, 16, 8, 4, 0.0, 0, "fp32", reorder=True, omega=om)
+    assert np.all(np.abs(S - ref.S) / ref.S <= 1e-5)
+    ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 16, 8, 4, 0.0, seed=7)
+    U, S, V, st, info, tr = _solve(A, 16, 8, 4, 0.0, 7, "bf16", reorder=True)
+    assert np.all(np.abs(S - ref.S) / ref.S <= 2e-2)
+
+
 def test_error_paths(torch_dev):
     from paper_2404_09276_amd import DashSVD, DashSVDError
     A = synth.uniform_csr(200, 150, 3000, seed=2)
