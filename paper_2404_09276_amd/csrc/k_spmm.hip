@@ -126,6 +126,11 @@ __global__ __launch_bounds__(256) void k_spmm(
   store_n<TY, TA, V>(Y + row * ldy + cl * V, acc);
 }
 
+// One workgroup per long row: its NG = 256 / G lane groups split the chunk
+// partials round-robin (group k takes chunks k, k + NG, ...), each summing
+// its share in chunk order with eight loads in flight, and the group sums are
+// then added in group order (fixed, so results repeat bit for bit).  A row
+// with hundreds of chunks no longer waits on one group's chain of loads.
 template <typename TX, typename TY, typename TA, bool SHIFT, int V>
 __global__ __launch_bounds__(256) void k_spmm_long(
     int64_t n_long, const LongRow *__restrict__ longs, const TA *__restrict__ partial, int64_t ldp,
@@ -133,11 +138,13 @@ __global__ __launch_bounds__(256) void k_spmm_long(
     const double *__restrict__ alpha, const int32_t *__restrict__ done,
     const int32_t *__restrict__ rowmat, const SolverState *__restrict__ bstate) {
   if (done && *done) return;
+  __shared__ TA red[256 * V];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rpw = kWave / G;
   const int sub = lane / G, cl = lane - sub * G;
-  if (sub >= rpw) return;
-  const int64_t g = ((int64_t)blockIdx.x * 4 + wave) * rpw + sub;
+  const int NG = 4 * rpw;                // lane groups in the workgroup
+  const int k = wave * rpw + sub;        // this lane's group
+  const int64_t g = blockIdx.x;
   if (g >= n_long) return;
   const LongRow lr = longs[g];
   const double *alpha_row = alpha;
@@ -149,30 +156,41 @@ __global__ __launch_bounds__(256) void k_spmm_long(
   TA acc[V];
 #pragma unroll
   for (int i = 0; i < V; ++i) acc[i] = (TA)0;
-  // chunk partials summed in chunk order; eight loads in flight
-  const TA *pb = partial + lr.first * ldp + cl * V;
-  int64_t c = 0;
-  for (; c + 8 <= lr.nch; c += 8) {
-    TA p[8][V];
+  if (sub < rpw) {
+    const TA *pb = partial + lr.first * ldp + cl * V;
+    int64_t c = k;
+    for (; c + 7 * (int64_t)NG < lr.nch; c += 8 * (int64_t)NG) {
+      TA p[8][V];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) load_n<TA, TA, V>(pb + (c + u) * ldp, p[u]);
+      for (int u = 0; u < 8; ++u) load_n<TA, TA, V>(pb + (c + u * (int64_t)NG) * ldp, p[u]);
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+      for (int u = 0; u < 8; ++u)
 #pragma unroll
-      for (int i = 0; i < V; ++i) acc[i] += p[u][i];
+        for (int i = 0; i < V; ++i) acc[i] += p[u][i];
+    }
+    for (; c < lr.nch; c += NG) {
+      TA p[V];
+      load_n<TA, TA, V>(pb + c * ldp, p);
+#pragma unroll
+      for (int i = 0; i < V; ++i) acc[i] += p[i];
+    }
+#pragma unroll
+    for (int i = 0; i < V; ++i) red[(k * G + cl) * V + i] = acc[i];
   }
-  for (; c < lr.nch; ++c) {
-    TA p[V];
-    load_n<TA, TA, V>(pb + c * ldp, p);
+  __syncthreads();
+  if (wave != 0 || sub != 0) return;
+  // group 0's lanes add the group sums in group order
 #pragma unroll
-    for (int i = 0; i < V; ++i) acc[i] += p[i];
-  }
+  for (int i = 0; i < V; ++i) acc[i] = red[cl * V + i];
+  for (int q = 1; q < NG; ++q)
+#pragma unroll
+    for (int i = 0; i < V; ++i) acc[i] += red[(q * G + cl) * V + i];
   if constexpr (SHIFT) {
     const TA a = (TA)(*alpha_row);
-    TA q[V];
-    load_n<TX, TA, V>(Q + lr.row * ldq + cl * V, q);
+    TA qv[V];
+    load_n<TX, TA, V>(Q + lr.row * ldq + cl * V, qv);
 #pragma unroll
-    for (int i = 0; i < V; ++i) acc[i] = acc[i] - a * q[i];
+    for (int i = 0; i < V; ++i) acc[i] = acc[i] - a * qv[i];
   }
   store_n<TY, TA, V>(Y + lr.row * ldy + cl * V, acc);
 }
@@ -204,7 +222,7 @@ hipError_t run_spmm_v(int64_t R, const int64_t *rp, const int32_t *col, const vo
                          rowmat, bstate);
   }
   if (n_long > 0) {
-    const int64_t lb = (n_long + 4 * rpw - 1) / (4 * rpw);
+    const int64_t lb = n_long;  // one workgroup per long row
     if (shift)
       hipLaunchKernelGGL((k_spmm_long<TX, TY, TA, true, V>), dim3((unsigned)lb), dim3(256), 0, st, n_long,
                          longs, (const TA *)partial, (int64_t)ld_cols, (TY *)Y, ldy, G, (const TX *)Q, ldq,
