@@ -163,8 +163,17 @@ def cpu_baseline(A, min_seconds=10.0):
                       f"mean seconds per solve"}
 
 
-def source_digest(name):
-    return hashlib.sha256(open(os.path.join(CSRC, name), "rb").read()).hexdigest()
+def source_digest(*names):
+    """SHA-256 over the named sources, in order."""
+    h = hashlib.sha256()
+    for name in names:
+        h.update(open(os.path.join(CSRC, name), "rb").read())
+    return h.hexdigest()
+
+
+# The SpMM's counter traffic depends on the kernel and on the order of the
+# operator's rows and columns (the degree order is built in k_csr.hip).
+TRAFFIC_SOURCES = {"spmm": ("k_spmm.hip", "k_csr.hip"), "eig": ("k_eig.hip",)}
 
 
 def traffic(kind):
@@ -179,8 +188,7 @@ def traffic(kind):
         parts = line.split()
         if len(parts) == 2 and not line.startswith("#"):
             t[parts[0]] = parts[1]
-    src = {"spmm": "k_spmm.hip", "eig": "k_eig.hip"}[kind]
-    if t.get(f"{kind}_sha256") != source_digest(src) or f"{kind}_bytes_per_launch" not in t:
+    if t.get(f"{kind}_sha256") != source_digest(*TRAFFIC_SOURCES[kind]) or f"{kind}_bytes_per_launch" not in t:
         return None
     return float(t[f"{kind}_bytes_per_launch"])
 
@@ -271,9 +279,9 @@ def summarize_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, commands
           f" SpMM (A^T Z) {spmm_bytes(100000, 200000, 10**7, 120) / 1e6:.1f} MB.")
     print(f"fetch_calibration {fcal:.6f}")
     print(f"write_calibration {wcal:.6f}")
-    print(f"spmm_sha256 {source_digest('k_spmm.hip')}")
+    print(f"spmm_sha256 {source_digest(*TRAFFIC_SOURCES['spmm'])}")
     print(f"spmm_bytes_per_launch {spmm_b * 1e6:.0f}")
-    print(f"eig_sha256 {source_digest('k_eig.hip')}")
+    print(f"eig_sha256 {source_digest(*TRAFFIC_SOURCES['eig'])}")
     print(f"eig_bytes_per_launch {eig_b:.0f}")
     print(f"eig_calls_counted {len(eig_f)}")
 

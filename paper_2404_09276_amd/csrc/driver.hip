@@ -506,7 +506,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   b.sched = (double *)ar.take(8 * (size_t)(pmax + 2));
   b.Uo = ar.take(dsz(cdt) * (size_t)Mm * k);
   b.Vo = ar.take(dsz(cdt) * (size_t)Mn * k);
-  const int sgn_blk = 256;
+  const int sgn_blk = 1024;  // blocks of the column-maximum search of the sign step
   b.sgn_max = ar.take(8 * (size_t)sgn_blk * k);
   b.sgn_idx = ar.take(8 * (size_t)sgn_blk * k + 4 * (size_t)k);
   if (h->opt.omega && !h->opt.omega_on_device)

@@ -143,20 +143,25 @@ __global__ __launch_bounds__(256) void k_validate(int64_t m, int64_t n, int64_t 
   for (int64_t r = t0; r < m; r += stride) bad |= rp[r] > rp[r + 1];
   if (t0 == 0 && (rp[0] != 0 || rp[m] != nnz)) bad = 1;
   if (m > 0) {
-    // each thread takes kValChunk consecutive nonzeros: one binary search for
-    // the first, then a short walk along the row pointer (a binary search
-    // again after more than 8 rows, so runs of empty rows stay cheap); with a
+    // a wavefront takes 64 kValChunk consecutive nonzeros, lane L the ones at
+    // L, L + 64, ... (coalesced reads and writes): one binary search for its
+    // first, then a walk along the row pointer (a binary search again after
+    // more than 64 rows, so runs of empty rows stay cheap); with a
     // malformed row pointer the rows found may be wrong, but the flag above
     // is then set and they are never used
-    for (int64_t cbeg = t0 * kValChunk; cbeg < nnz; cbeg += stride * kValChunk) {
-      int64_t r = row_of(rp, m, cbeg);
+    const int lane = threadIdx.x & 63;
+    const int64_t wave0 = t0 - lane;  // first thread of this wavefront
+    for (int64_t cbeg = wave0 * kValChunk; cbeg < nnz; cbeg += stride * kValChunk) {
+      const int64_t efirst = cbeg + lane;
+      if (efirst >= nnz) break;
+      int64_t r = row_of(rp, m, efirst);
       int64_t rbeg = rp[r], rend = rp[r + 1];
 #pragma unroll
       for (int k = 0; k < kValChunk; ++k) {
-        const int64_t e = cbeg + k;
+        const int64_t e = efirst + 64 * k;
         if (e >= nnz) break;
         int steps = 0;
-        while (e >= rend && r + 1 < m && steps < 8) {
+        while (e >= rend && r + 1 < m && steps < 64) {
           ++r;
           rbeg = rend;
           rend = rp[r + 1];
