@@ -13,6 +13,7 @@
 // order, one chunk behind, while the next chunk runs), and passes launched
 // after the flag is set return at their first instruction.
 #include <chrono>
+#include <cstddef>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -787,6 +788,29 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     // reads them only once the next chunk is queued, so the GPU does not
     // idle while the host decides; a chunk queued after the stop returns at
     // the first instruction of each kernel.
+    // When the ratios read so far predict that the chunk just queued meets
+    // tol, the host waits for that chunk's flags instead (one host round
+    // trip, against a whole chunk of launches that would return at once).
+    struct Flags {  // copy of SolverState from `ratio` to `cq_off`
+      double ratio;
+      int32_t pass, done, cq_off, pad;
+    };
+    static_assert(offsetof(SolverState, pass) == offsetof(SolverState, ratio) + 8 &&
+                      offsetof(SolverState, done) == offsetof(SolverState, ratio) + 12 &&
+                      offsetof(SolverState, cq_off) == offsetof(SolverState, ratio) + 16,
+                  "flag copy layout");
+    Flags *hf = reinterpret_cast<Flags *>(h->hflags);  // two slots
+    double r_old = 0.0, r_new = 0.0;  // the last two ratios read
+    bool stop = false;
+    auto read_slot = [&](int slot) -> hipError_t {
+      const hipError_t e = hipEventSynchronize(h->ev_flag[slot]);
+      if (e != hipSuccess) return e;
+      host_cq_off = hf[slot].cq_off;
+      stop = hf[slot].done != 0;
+      r_old = r_new;
+      r_new = hf[slot].ratio;
+      return hipSuccess;
+    };
     int launched = 0;
     int pending = -1;  // flag slot copied but not read yet
     while (launched < pmax) {
@@ -802,14 +826,24 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       launched += chunk;
       if (!(tol > 0.0 && launched < pmax)) continue;
       const int slot = pending == 0 ? 1 : 0;
-      HIPCHK(hipMemcpyAsync(h->hflags + 2 * slot, done, 8, hipMemcpyDeviceToHost, st));  // done, cq_off
+      HIPCHK(hipMemcpyAsync(&hf[slot], &b.state->ratio, sizeof(Flags) - 4, hipMemcpyDeviceToHost, st));
       HIPCHK(hipEventRecord(h->ev_flag[slot], st));
       if (pending >= 0) {
-        HIPCHK(hipEventSynchronize(h->ev_flag[pending]));
-        host_cq_off = h->hflags[2 * pending + 1];
-        if (h->hflags[2 * pending] != 0) break;
+        HIPCHK(read_slot(pending));
+        if (stop) break;
       }
       pending = slot;
+      // geometric extrapolation of the ratio over the chunk just queued
+      if (r_old > 0.0 && r_new > 0.0 && r_new < r_old) {
+        const double q = r_new / r_old;
+        double pred = r_new;
+        for (int c = 0; c < chunk; ++c) pred *= q;
+        if (pred <= 1.5 * tol) {
+          HIPCHK(read_slot(slot));
+          pending = -1;
+          if (stop) break;
+        }
+      }
     }
     HIPCHK(hipMemcpyAsync(&last_pass, &b.state->pass, 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
