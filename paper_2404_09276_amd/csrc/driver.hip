@@ -802,11 +802,13 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     Flags *hf = reinterpret_cast<Flags *>(h->hflags);  // two slots
     double r_old = 0.0, r_new = 0.0;  // the last two ratios read
     bool stop = false;
+    int stop_pass = 0;  // passes executed, as read with the stop flag
     auto read_slot = [&](int slot) -> hipError_t {
       const hipError_t e = hipEventSynchronize(h->ev_flag[slot]);
       if (e != hipSuccess) return e;
       host_cq_off = hf[slot].cq_off;
       stop = hf[slot].done != 0;
+      stop_pass = hf[slot].pass;
       r_old = r_new;
       r_new = hf[slot].ratio;
       return hipSuccess;
@@ -845,8 +847,13 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
         }
       }
     }
-    HIPCHK(hipMemcpyAsync(&last_pass, &b.state->pass, 4, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    if (stop) {
+      // no pass runs after the flag is set: the count read with it is final
+      last_pass = stop_pass;
+    } else {
+      HIPCHK(hipMemcpyAsync(&last_pass, &b.state->pass, 4, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
   } else {
     // Plain order (BF16 panels): C = M^T Y - alpha Q from the BF16 panels,
     // G = C^T C, eig, Q = C W, Y = M Q.  Stagnation guard: once the PVE
