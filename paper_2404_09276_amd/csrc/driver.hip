@@ -729,8 +729,22 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   int32_t host_cq_off = 0;
   auto launch_block_eig = [&](EigArgs &ea, int pass, hipStream_t s) -> hipError_t {
     const bool cq = cholqr && !host_cq_off && pass + 1 < pmax;
-    tmark_begin(h, cq ? DASHSVD_KT_CHOLQR : DASHSVD_KT_EIG, pass, s);
-    const hipError_t e = cq ? launch_eig_pass(ea, s) : launch_eig(ea, s);
+    if (!cq) {
+      tmark_begin(h, DASHSVD_KT_EIG, pass, s);
+      const hipError_t e = launch_eig(ea, s);
+      tmark_end(h, s);
+      return e;
+    }
+    // Cholesky-QR, then the Jacobi eigensolver gated on its hand-over or
+    // decline (each timed in its own group)
+    tmark_begin(h, DASHSVD_KT_CHOLQR, pass, s);
+    hipError_t e = launch_cholqr(ea, s);
+    tmark_end(h, s);
+    if (e != hipSuccess) return e;
+    EigArgs gated = ea;
+    gated.run_if = &b.state->cq_fallback;
+    tmark_begin(h, DASHSVD_KT_EIG, pass, s);
+    e = launch_eig(gated, s);
     tmark_end(h, s);
     return e;
   };
