@@ -166,39 +166,44 @@ __global__ __launch_bounds__(256) void k_gram_partial(int64_t r, int l, const TC
   }
 }
 
-// Sum the block partials; write the full symmetric G.  Eight threads share
-// an element: thread s sums blocks s, s+8, s+16, ... in order, then the eight
-// partial sums are added in order s = 0..7 (deterministic).
+// Sum the block partials; write the full symmetric G.  A workgroup owns 32
+// consecutive partial elements and eight segments of the blocks: thread
+// (s, e) sums blocks [s nb/8, (s+1) nb/8) of element e in block order (the
+// 32 elements of a segment are one coalesced read per block), then the
+// eight segment sums are added in order s = 0..7 (deterministic).
 template <int LT>
 __global__ __launch_bounds__(256) void k_gram_reduce(int l, int nblocks, const double *__restrict__ partial,
                                                      double *__restrict__ G,
                                                      const int32_t *__restrict__ done) {
   if (done && *done) return;
   constexpr int NT = LT * (LT + 1) / 2;
-  __shared__ double part[256];
-  const int sub = threadIdx.x & 7;
-  const int64_t e = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3);
+  __shared__ double part[8][32];
+  const int el = threadIdx.x & 31, seg = threadIdx.x >> 5;
+  const int64_t e = (int64_t)blockIdx.x * 32 + el;
   double s = 0.0;
   if (e < (int64_t)NT * 256) {
     const int64_t stride = (int64_t)NT * 256;
     const double *p = partial + e;
-    int b = sub;
-    for (; b + 24 < nblocks; b += 32) {
-      const double x0 = p[(int64_t)b * stride], x1 = p[(int64_t)(b + 8) * stride];
-      const double x2 = p[(int64_t)(b + 16) * stride], x3 = p[(int64_t)(b + 24) * stride];
+    const int per = (nblocks + 7) / 8;
+    const int b0 = seg * per;
+    const int b1 = b0 + per < nblocks ? b0 + per : nblocks;
+    int b = b0;
+    for (; b + 3 < b1; b += 4) {
+      const double x0 = p[(int64_t)b * stride], x1 = p[(int64_t)(b + 1) * stride];
+      const double x2 = p[(int64_t)(b + 2) * stride], x3 = p[(int64_t)(b + 3) * stride];
       s += x0;
       s += x1;
       s += x2;
       s += x3;
     }
-    for (; b < nblocks; b += 8) s += p[(int64_t)b * stride];
+    for (; b < b1; ++b) s += p[(int64_t)b * stride];
   }
-  part[threadIdx.x] = s;
+  part[seg][el] = s;
   __syncthreads();
-  if (sub != 0 || e >= (int64_t)NT * 256) return;
+  if (seg != 0 || e >= (int64_t)NT * 256) return;
   double tot = 0.0;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) tot += part[threadIdx.x + i];
+  for (int i = 0; i < 8; ++i) tot += part[i][el];
   int t = (int)(e >> 8);
   const int within = (int)(e & 255);
   const int lane = within >> 2, q = within & 3;
