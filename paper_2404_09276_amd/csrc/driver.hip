@@ -446,8 +446,15 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   const bool wide = m < n;
   const int64_t Mm = wide ? n : m, Mn = wide ? m : n;
   const int l = k + p;
-  const int ld = (int)round_up(l, 8);
-  const int32_t T = chunk_length(h, tune_key(prec, ld, Mm, nnz, false), nnz);
+  // Panel rows: the SpMM's lanes cover ldc = l rounded up to 8 columns.  The
+  // leading dimension ld starts every row on a 128-byte boundary where that
+  // costs at most 1/8 more memory, so a gathered row touches fewer cache
+  // lines (480-byte FP32 rows at l = 120: 4 lines each instead of 4.5 on
+  // average; 240-byte BF16 rows: 2 instead of 2.75).
+  const int ldc = (int)round_up(l, 8);
+  const int64_t line_elems = (int64_t)(128 / (dsz(pdt) < dsz(cdt) ? dsz(pdt) : dsz(cdt)));
+  const int ld = round_up(l, line_elems) * 8 <= (int64_t)ldc * 9 ? (int)round_up(l, line_elems) : ldc;
+  const int32_t T = chunk_length(h, tune_key(prec, ldc, Mm, nnz, false), nnz);
   const int pmax = h->opt.p_max;
   const int cap = pmax > 0 ? pmax : 1;
   hipStream_t st = h->st;
@@ -481,8 +488,8 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   b.tws = ar.take(b.tws_bytes);
   const int64_t scan_n = (m > n ? m : n) + 1;
   b.scan_tmp = (int64_t *)ar.take(8 * scan_tmp_elems(scan_n));
-  plan_alloc(h, ar, b.planM, Mm, nnz, T, ld, accsz);
-  plan_alloc(h, ar, b.planT, Mn, nnz, T, ld, accsz);
+  plan_alloc(h, ar, b.planM, Mm, nnz, T, ldc, accsz);
+  plan_alloc(h, ar, b.planT, Mn, nnz, T, ldc, accsz);
   b.Y = ar.take(dsz(pdt) * (size_t)Mm * ld);
   b.Q = ar.take(dsz(pdt) * (size_t)Mn * ld);
   b.C = ar.take(dsz(cdt) * (size_t)Mn * ld);
@@ -779,12 +786,12 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       // every CU first, so they wait (bounded) until it is resident.
       if ((e = launch_wait_started(&b.state->eig_started, ea.call_idx, st)) != hipSuccess) return e;
       tmark_begin(h, DASHSVD_KT_SPMM, pass);
-      e = launch_spmm(Mm, rpM, colM, valM, vdt, Cin, ld, cdt, b.Z, ld, cdt, ld, b.planM.n_chunks, b.planM.tasks,
+      e = launch_spmm(Mm, rpM, colM, valM, vdt, Cin, ld, cdt, b.Z, ld, cdt, ldc, b.planM.n_chunks, b.planM.tasks,
                       b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, skip, st);
       tmark_end(h);
       if (e != hipSuccess) return e;
       tmark_begin(h, DASHSVD_KT_SPMM_T, pass);
-      e = launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Z, ld, cdt, b.X, ld, cdt, ld, b.planT.n_chunks, b.planT.tasks,
+      e = launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Z, ld, cdt, b.X, ld, cdt, ldc, b.planT.n_chunks, b.planT.tasks,
                       b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr, skip, st);
       tmark_end(h);
       if (e != hipSuccess) return e;
@@ -792,7 +799,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     };
     // sketch (Alg. 5 step 2): C = M^T Omega, its eigSVD || M C, M^T M C
     tmark_begin(h, DASHSVD_KT_SKETCH, 0);
-    HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, Cb[0], ld, cdt, ld, b.planT.n_chunks,
+    HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, Cb[0], ld, cdt, ldc, b.planT.n_chunks,
                        b.planT.tasks, b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr,
                        nullptr, st));
     tmark_end(h);
@@ -892,14 +899,14 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       tmark_end(h);
       if (e != hipSuccess) return e;
       tmark_begin(h, DASHSVD_KT_SPMM, pass);
-      e = launch_spmm(Mm, rpM, colM, valM, vdt, Qc, ld, pcur, Yc, ld, pcur, ld, b.planM.n_chunks, b.planM.tasks,
+      e = launch_spmm(Mm, rpM, colM, valM, vdt, Qc, ld, pcur, Yc, ld, pcur, ldc, b.planM.n_chunks, b.planM.tasks,
                       b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, skip, st);
       tmark_end(h);
       return e;
     };
     // sketch (Alg. 5 step 2): C = M^T Omega ; Q = eigSVD(C).U ; Y = M Q
     tmark_begin(h, DASHSVD_KT_SKETCH, 0);
-    HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ld, b.planT.n_chunks, b.planT.tasks,
+    HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ldc, b.planT.n_chunks, b.planT.tasks,
                        b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr, nullptr, st));
     tmark_end(h);
     HIPCHK(block_step(1, 0, nullptr));
@@ -910,7 +917,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       for (int c = 0; c < chunk; ++c) {
         const int pass = launched + c + 1;
         tmark_begin(h, DASHSVD_KT_SPMM_T, pass);
-        HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, Yc, ld, pcur, b.C, ld, cdt, ld, b.planT.n_chunks,
+        HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, Yc, ld, pcur, b.C, ld, cdt, ldc, b.planT.n_chunks,
                            b.planT.tasks, b.planT.n_long, b.planT.longs, b.planT.partial, T, Qc, ld,
                            &b.state->alpha, done, st));
         tmark_end(h);
@@ -930,7 +937,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
           Yc = b.Y32;
           promoted = 1;
           HIPCHK(launch_rescale(Mn, l, b.C, ld, cdt, b.W, l, l, Qc, ld, pcur, nullptr, st));
-          HIPCHK(launch_spmm(Mm, rpM, colM, valM, vdt, Qc, ld, pcur, Yc, ld, pcur, ld, b.planM.n_chunks,
+          HIPCHK(launch_spmm(Mm, rpM, colM, valM, vdt, Qc, ld, pcur, Yc, ld, pcur, ldc, b.planM.n_chunks,
                              b.planM.tasks, b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0,
                              nullptr, nullptr, st));
         }
@@ -971,7 +978,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     void *Qf = Qfin, *Bf = b.B;
     if (pfin != cdt) {
       // the BF16 form keeps an FP32 B
-      HIPCHK(launch_spmm(Mm, rpM, colM, valM, vdt, Qfin, ld, pfin, b.B, ld, cdt, ld, b.planM.n_chunks,
+      HIPCHK(launch_spmm(Mm, rpM, colM, valM, vdt, Qfin, ld, pfin, b.B, ld, cdt, ldc, b.planM.n_chunks,
                          b.planM.tasks, b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr,
                          nullptr, st));
     } else {
