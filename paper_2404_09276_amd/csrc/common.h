@@ -56,6 +56,10 @@ template <typename A> struct vec16<float, A> {
     float4 v = *reinterpret_cast<const float4 *>(p);
     o[0] = (A)v.x; o[1] = (A)v.y; o[2] = (A)v.z; o[3] = (A)v.w;
   }
+  __device__ static __forceinline__ void unpack(const uint32_t *w, A *o) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o[i] = (A)__uint_as_float(w[i]);
+  }
   __device__ static __forceinline__ void store(float *p, const A *o) {
     float4 v;
     v.x = (float)o[0]; v.y = (float)o[1]; v.z = (float)o[2]; v.w = (float)o[3];
@@ -68,6 +72,11 @@ template <typename A> struct vec16<double, A> {
     double2 v = *reinterpret_cast<const double2 *>(p);
     o[0] = (A)v.x; o[1] = (A)v.y;
   }
+  __device__ static __forceinline__ void unpack(const uint32_t *w, A *o) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      o[i] = (A)__longlong_as_double((long long)(((uint64_t)w[2 * i + 1] << 32) | w[2 * i]));
+  }
   __device__ static __forceinline__ void store(double *p, const A *o) {
     double2 v;
     v.x = (double)o[0]; v.y = (double)o[1];
@@ -79,6 +88,13 @@ template <typename A> struct vec16<bf16, A> {
   __device__ static __forceinline__ void load(const bf16 *p, A *o) {
     uint4 v = *reinterpret_cast<const uint4 *>(p);
     uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      o[2 * i] = (A)__uint_as_float(w[i] << 16);
+      o[2 * i + 1] = (A)__uint_as_float(w[i] & 0xffff0000u);
+    }
+  }
+  __device__ static __forceinline__ void unpack(const uint32_t *w, A *o) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       o[2 * i] = (A)__uint_as_float(w[i] << 16);
@@ -199,11 +215,14 @@ hipError_t launch_permute_entries(int64_t nnz, const int64_t *rp, const int32_t 
                                   const int32_t *col, const void *val, int dtype, const int32_t *inv_r,
                                   const int32_t *inv_c, const int64_t *rp_new, int32_t *col_new, void *val_new,
                                   hipStream_t st);
-// The two halves of launch_transpose: the sort of the column keys with the
-// row pointer of A^T, then the gather of rows and values (into the degree
-// order when inv_r, inv_c and rp_new, the permuted row pointer, are given).
+// The two halves of launch_transpose: the sort of the column keys (carrying
+// each nonzero's row and value when dtype is F32, its index otherwise) with
+// the row pointer of A^T, then the scatter or gather of rows and values (into
+// the degree order when inv_r, inv_c and rp_new, the permuted row pointer,
+// are given).  Both halves take the same rowidx, val and dtype.
 hipError_t launch_transpose_keys(int64_t n, int64_t nnz, const int32_t *col, int64_t *rowT, void *ws,
-                                 size_t ws_bytes, hipStream_t st);
+                                 size_t ws_bytes, hipStream_t st, const int32_t *rowidx, const void *val,
+                                 int dtype);
 hipError_t launch_transpose_gather(int64_t nnz, const int32_t *rowidx, const void *val, int dtype, const void *ws,
                                    int32_t *colT, void *valT, hipStream_t st, const int64_t *rowT = nullptr,
                                    const int32_t *inv_r = nullptr, const int32_t *inv_c = nullptr,
@@ -223,7 +242,8 @@ hipError_t launch_spmm(int64_t R, const int64_t *rp, const int32_t *col, const v
                        int ld_cols, int64_t n_chunks, const ChunkTask *tasks, int64_t n_long,
                        const LongRow *longs, void *partial, int32_t long_row, const void *Q,
                        int64_t ldq, const double *alpha, const int32_t *done, hipStream_t st,
-                       const int32_t *rowmat = nullptr, const SolverState *bstate = nullptr);
+                       const int32_t *rowmat = nullptr, const SolverState *bstate = nullptr,
+                       int64_t xrows = 0);
 
 // snap (optional): receives *done as read at the start of the Gram kernel,
 // i.e. whether the iteration had already stopped when this pass began.
@@ -363,5 +383,18 @@ hipError_t launch_convert(const void *in, int idtype, void *out, int odtype, int
 hipError_t launch_copy2d(const void *in, int64_t ldi, int idtype, void *out, int64_t ldo,
                          int odtype, int64_t rows, int cols, hipStream_t st, const int32_t *row_to = nullptr);
 hipError_t launch_fill_zero_i32(int32_t *p, int64_t n, hipStream_t st);
+// Zero several small buffers (sizes in 4-byte words) with one launch.
+constexpr int kMaxZeroRanges = 12;
+struct ZeroRanges {
+  int32_t *p[kMaxZeroRanges];
+  int64_t n[kMaxZeroRanges];
+  int count;
+  void add(void *ptr, size_t bytes) {
+    p[count] = (int32_t *)ptr;
+    n[count] = (int64_t)(bytes / 4);
+    ++count;
+  }
+};
+hipError_t launch_zero_ranges(const ZeroRanges &z, hipStream_t st);
 
 }  // namespace dsv

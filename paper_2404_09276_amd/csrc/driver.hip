@@ -42,6 +42,14 @@ constexpr int kDefaultPmax = 64;
 size_t dsz(int dt) { return dt == DASHSVD_F64 ? 8 : (dt == DASHSVD_BF16 ? 2 : 4); }
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
+// Pinned host staging area of a handle: flag slots and plan sizes in the
+// first 256 bytes, then the solver state and the per-pass traces copied back
+// at the end of a solve.
+constexpr size_t kPinState = 256, kPinAlpha = 1024, kPinRatio = kPinAlpha + 8 * DASHSVD_MAX_TRACE,
+                 kPinSweeps = kPinRatio + 8 * DASHSVD_MAX_TRACE, kPinBytes = 8192;
+static_assert(sizeof(SolverState) <= kPinAlpha - kPinState, "solver state fits its staging slot");
+static_assert(kPinSweeps + 4 * (DASHSVD_MAX_TRACE + 2) <= kPinBytes, "traces fit the staging area");
+
 // Bump allocator over one device arena.
 struct Arena {
   char *base = nullptr;
@@ -553,7 +561,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     HIPCHK(hipEventCreateWithFlags(&h->ev_eig, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&h->ev_flag[0], hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&h->ev_flag[1], hipEventDisableTiming));
-    HIPCHK(hipHostMalloc((void **)&h->hflags, 256, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&h->hflags, kPinBytes, hipHostMallocDefault));
   }
   hipStream_t st2 = h->st2;
   // Omega (Alg. 5 step 1) depends on nothing but the row order: it is
@@ -584,14 +592,18 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   if (!reorder) HIPCHK(launch_omega(nullptr));
   // control buffers start at zero; panels need no clearing (pad columns are
   // never read into the first l columns)
-  HIPCHK(hipMemsetAsync(b.flags, 0, 4 * 8, st));
-  HIPCHK(hipMemsetAsync(b.planM.nlong, 0, 16, st));
-  HIPCHK(hipMemsetAsync(b.planT.nlong, 0, 16, st));
-  HIPCHK(hipMemsetAsync(b.state, 0, sizeof(SolverState), st));
-  HIPCHK(hipMemsetAsync(b.Sprev, 0, 8 * (size_t)l, st));
-  HIPCHK(hipMemsetAsync(b.tr_alpha, 0, 8 * (size_t)cap, st));
-  HIPCHK(hipMemsetAsync(b.tr_ratio, 0, 8 * (size_t)cap, st));
-  HIPCHK(hipMemsetAsync(b.tr_sweeps, 0, 4 * (size_t)(cap + 2), st));
+  {
+    ZeroRanges z{};
+    z.add(b.flags, 4 * 8);
+    z.add(b.planM.nlong, 16);
+    z.add(b.planT.nlong, 16);
+    z.add(b.state, sizeof(SolverState));
+    z.add(b.Sprev, 8 * (size_t)l);
+    z.add(b.tr_alpha, 8 * (size_t)cap);
+    z.add(b.tr_ratio, 8 * (size_t)cap);
+    z.add(b.tr_sweeps, 4 * (size_t)(cap + 2));
+    HIPCHK(launch_zero_ranges(z, st));
+  }
   const int64_t *rpA = A->on_device ? A->row_ptr : rp_in;
   const int32_t *colA = A->on_device ? A->col_idx : col_in;
   const int64_t *rpAT = b.rpT;
@@ -619,7 +631,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   if (hflags[0] & 1) return fail(h, DASHSVD_ERR_BAD_CSR, "row_ptr/col_idx malformed");
   if (hflags[0] & 2) return fail(h, DASHSVD_ERR_NONFINITE, "NaN or Inf among the values");
   // CSR(A^T): the sort of the column keys gives its row pointer
-  HIPCHK(launch_transpose_keys(n, nnz, colA, b.rpT, b.tws, b.tws_bytes, st));
+  HIPCHK(launch_transpose_keys(n, nnz, colA, b.rpT, b.tws, b.tws_bytes, st, b.rowidx, valA, vdt));
   if (reorder) {
     // degree order of the rows (from the row pointer of A) and of the
     // columns (from that of A^T); the transposed entries are gathered
@@ -787,12 +799,14 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       if ((e = launch_wait_started(&b.state->eig_started, ea.call_idx, st)) != hipSuccess) return e;
       tmark_begin(h, DASHSVD_KT_SPMM, pass);
       e = launch_spmm(Mm, rpM, colM, valM, vdt, Cin, ld, cdt, b.Z, ld, cdt, ldc, b.planM.n_chunks, b.planM.tasks,
-                      b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, skip, st);
+                      b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, skip, st, nullptr,
+                      nullptr, Mn);
       tmark_end(h);
       if (e != hipSuccess) return e;
       tmark_begin(h, DASHSVD_KT_SPMM_T, pass);
       e = launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Z, ld, cdt, b.X, ld, cdt, ldc, b.planT.n_chunks, b.planT.tasks,
-                      b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr, skip, st);
+                      b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr, skip, st, nullptr,
+                      nullptr, Mm);
       tmark_end(h);
       if (e != hipSuccess) return e;
       return hipStreamWaitEvent(st, h->ev_eig, 0);
@@ -801,7 +815,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     tmark_begin(h, DASHSVD_KT_SKETCH, 0);
     HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, Cb[0], ld, cdt, ldc, b.planT.n_chunks,
                        b.planT.tasks, b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr,
-                       nullptr, st));
+                       nullptr, st, nullptr, nullptr, Mm));
     tmark_end(h);
     HIPCHK(side(1, 0, Cb[0], nullptr));
     // power passes (steps 3-8).  Stop test one chunk behind: the flags of
@@ -900,14 +914,16 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       if (e != hipSuccess) return e;
       tmark_begin(h, DASHSVD_KT_SPMM, pass);
       e = launch_spmm(Mm, rpM, colM, valM, vdt, Qc, ld, pcur, Yc, ld, pcur, ldc, b.planM.n_chunks, b.planM.tasks,
-                      b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, skip, st);
+                      b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, skip, st, nullptr,
+                      nullptr, Mn);
       tmark_end(h);
       return e;
     };
     // sketch (Alg. 5 step 2): C = M^T Omega ; Q = eigSVD(C).U ; Y = M Q
     tmark_begin(h, DASHSVD_KT_SKETCH, 0);
     HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ldc, b.planT.n_chunks, b.planT.tasks,
-                       b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr, nullptr, st));
+                       b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr, nullptr, st,
+                       nullptr, nullptr, Mm));
     tmark_end(h);
     HIPCHK(block_step(1, 0, nullptr));
     // power passes (steps 3-8): C = M^T Y - alpha Q ; eigSVD(C) ; check ; shift
@@ -919,7 +935,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
         tmark_begin(h, DASHSVD_KT_SPMM_T, pass);
         HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, Yc, ld, pcur, b.C, ld, cdt, ldc, b.planT.n_chunks,
                            b.planT.tasks, b.planT.n_long, b.planT.longs, b.planT.partial, T, Qc, ld,
-                           &b.state->alpha, done, st));
+                           &b.state->alpha, done, st, nullptr, nullptr, Mm));
         tmark_end(h);
         HIPCHK(block_step(2, pass, done));
       }
@@ -939,7 +955,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
           HIPCHK(launch_rescale(Mn, l, b.C, ld, cdt, b.W, l, l, Qc, ld, pcur, nullptr, st));
           HIPCHK(launch_spmm(Mm, rpM, colM, valM, vdt, Qc, ld, pcur, Yc, ld, pcur, ldc, b.planM.n_chunks,
                              b.planM.tasks, b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0,
-                             nullptr, nullptr, st));
+                             nullptr, nullptr, st, nullptr, nullptr, Mn));
         }
       }
     }
@@ -980,7 +996,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       // the BF16 form keeps an FP32 B
       HIPCHK(launch_spmm(Mm, rpM, colM, valM, vdt, Qfin, ld, pfin, b.B, ld, cdt, ldc, b.planM.n_chunks,
                          b.planM.tasks, b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr,
-                         nullptr, st));
+                         nullptr, st, nullptr, nullptr, Mn));
     } else {
       // promoted to FP32 panels: B is the last M Q
       Bf = Yfin;
@@ -995,21 +1011,28 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     HIPCHK(launch_sign_fix(Mn, Mm, k, b.Vo, k, b.Uo, k, cdt, b.sgn_max, b.sgn_idx, sgn_blk, st));
   }
   tmark_end(h);
+  // solver state and traces through the pinned staging area (asynchronous
+  // copies, one wait)
+  char *pin = reinterpret_cast<char *>(h->hflags);
   SolverState hs;
-  HIPCHK(hipMemcpyAsync(&hs, b.state, sizeof(hs), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(pin + kPinState, b.state, sizeof(hs), hipMemcpyDeviceToHost, st));
   dashsvd_info &inf = h->info;
   std::memset(&inf, 0, sizeof(inf));
   const int ntr = pmax < DASHSVD_MAX_TRACE ? pmax : DASHSVD_MAX_TRACE;
   if (ntr > 0) {
-    HIPCHK(hipMemcpyAsync(inf.alpha_used, b.tr_alpha, 8 * (size_t)ntr, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(inf.ratio, b.tr_ratio, 8 * (size_t)ntr, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(pin + kPinAlpha, b.tr_alpha, 8 * (size_t)ntr, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(pin + kPinRatio, b.tr_ratio, 8 * (size_t)ntr, hipMemcpyDeviceToHost, st));
   }
-  {
-    // entries past the calls that ran are zero (cleared at setup)
-    const int nsw = cap + 2 < DASHSVD_MAX_TRACE + 2 ? cap + 2 : DASHSVD_MAX_TRACE + 2;
-    HIPCHK(hipMemcpyAsync(inf.sweeps_per_call, b.tr_sweeps, 4 * (size_t)nsw, hipMemcpyDeviceToHost, st));
-  }
+  // entries past the calls that ran are zero (cleared at setup)
+  const int nsw = cap + 2 < DASHSVD_MAX_TRACE + 2 ? cap + 2 : DASHSVD_MAX_TRACE + 2;
+  HIPCHK(hipMemcpyAsync(pin + kPinSweeps, b.tr_sweeps, 4 * (size_t)nsw, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  std::memcpy(&hs, pin + kPinState, sizeof(hs));
+  if (ntr > 0) {
+    std::memcpy(inf.alpha_used, pin + kPinAlpha, 8 * (size_t)ntr);
+    std::memcpy(inf.ratio, pin + kPinRatio, 8 * (size_t)ntr);
+  }
+  std::memcpy(inf.sweeps_per_call, pin + kPinSweeps, 4 * (size_t)nsw);
   const double t_end = now_ms();
   inf.passes = hs.pass;
   inf.eig_calls = hs.eig_calls;
@@ -1169,7 +1192,7 @@ dashsvd_status dashsvd_evaluate(dashsvd_handle *h, const dashsvd_csr *A, const d
   const Plan &pl = c.plan[side];
   HIPCHK(launch_spmm(zrows, c.rp[side], c.col[side], c.val[side], c.vdt, Upad, ld8, c.cdt, Z, ld8, c.cdt, ld8,
                      pl.n_chunks, pl.tasks, pl.n_long, pl.longs, pl.partial, c.T, nullptr, 0, nullptr, nullptr,
-                     st));
+                     st, nullptr, nullptr, urows));
   // ||A^T u_i||^2 = (Z^T Z)_ii in FP64
   HIPCHK(launch_gram(zrows, k, Z, ld8, c.cdt, c.gpart, gram_blocks(zrows, k), c.G, nullptr, st, nullptr));
   std::vector<double> G((size_t)k * k), S(k);
@@ -1423,12 +1446,13 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
     if (e == hipSuccess)
       e = launch_spmm(m, rpA, colA, valA, vdt, Qc, ld, pc, Yc, ld, pc, ld, b.planM.n_chunks, b.planM.tasks,
                       b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, nullptr, st,
-                      gate ? rowmatM : nullptr, b.state);
+                      gate ? rowmatM : nullptr, b.state, n);
     return e;
   };
   // sketch: C = M^T Omega, eigSVD, Y = M Q
   HIPCHK(launch_spmm(n, b.rpT, b.colT, b.valT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ld, b.planT.n_chunks, b.planT.tasks,
-                     b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr, nullptr, st));
+                     b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr, nullptr, st, nullptr,
+                     nullptr, m));
   HIPCHK(block(1, 0));
   // one power pass of every running matrix, captured once and replayed
   auto pass = [&]() -> hipError_t {
@@ -1436,7 +1460,7 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
     if (e == hipSuccess)
       e = launch_spmm(n, b.rpT, b.colT, b.valT, vdt, Yc, ld, pc, b.C, ld, cdt, ld, b.planT.n_chunks,
                       b.planT.tasks, b.planT.n_long, b.planT.longs, b.planT.partial, T, Qc, ld, &b.state->alpha,
-                      nullptr, st, rowmatN, b.state);
+                      nullptr, st, rowmatN, b.state, m);
     if (e == hipSuccess) e = block(2, 1);
     return e;
   };
@@ -1493,7 +1517,7 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
         if (eloop == hipSuccess)
           eloop = launch_spmm(m, rpA, colA, valA, vdt, Qc, ld, pc, Yc, ld, pc, ld, b.planM.n_chunks,
                               b.planM.tasks, b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0,
-                              nullptr, nullptr, st, rowmatM, b.state);
+                              nullptr, nullptr, st, rowmatM, b.state, n);
         if (eloop == hipSuccess) sloop = capture();
       }
     }
@@ -1508,7 +1532,8 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
   // V = Q Vs(:,1:k), signs
   HIPCHK(launch_bsnap(b.state, count, 0, st));
   HIPCHK(launch_spmm(m, rpA, colA, valA, vdt, Qc, ld, pc, b.B, ld, cdt, ld, b.planM.n_chunks, b.planM.tasks,
-                     b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, nullptr, st));
+                     b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, nullptr, st, nullptr,
+                     nullptr, n));
   HIPCHK(launch_bgram(itM_d, nIM, ioffM_d, count, l, b.B, ld, cdt, bpart, b.G, (int64_t)ll, b.state, 0, st));
   HIPCHK(launch_eig_batched(eargs + 2 * (size_t)count, count, l, st));
   HIPCHK(launch_brescale(itM_d, nIM, l, b.B, nullptr, ld, cdt, b.W, (int64_t)ll, l, k, b.Uo, k, cdt, b.state, 0,
@@ -1995,7 +2020,6 @@ dashsvd_status dashsvd_k_spmm(int64_t rows, int64_t cols, int64_t nnz, const int
                               int32_t ydtype, int32_t l, const void *Q, int64_t ldq, const double *alpha,
                               int32_t long_row, void *stream) {
   dashsvd_handle *h = nullptr;
-  (void)cols;
   const int ld = (int)round_up(l, 8);
   if (rows < 1 || l < 1 || l > DASHSVD_MAX_L || ldx % 8 || ldy % 8 || ldx < ld || ldy < ld ||
       (alpha && (!Q || ldq % 8 || ldq < ld)))
@@ -2027,7 +2051,7 @@ dashsvd_status dashsvd_k_spmm(int64_t rows, int64_t cols, int64_t nnz, const int
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e == hipSuccess)
     e = launch_spmm(rows, row_ptr, col, val, vdt, X, ldx, xdtype, Y, ldy, ydtype, ld, tot, pl.tasks, nl, pl.longs,
-                    pl.partial, T, Q, ldq, alpha, nullptr, st);
+                    pl.partial, T, Q, ldq, alpha, nullptr, st, nullptr, nullptr, cols);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   (void)hipFree(base);
   if (e != hipSuccess) return fail(h, DASHSVD_ERR_HIP, hipGetErrorString(e));

@@ -7,14 +7,17 @@
 //      the row pointer, checks the column (range, strictly increasing in the
 //      row) and the value (finite), and records its row;
 //   2. a stable LSD radix sort of the column indices (only the bits that
-//      column numbers below n use) carrying the nonzero index: every column
-//      of A then lists its nonzeros in their CSR order, i.e. by increasing
-//      row, with no per-column sort and no atomics on the columns (a Zipf
-//      matrix sends a tenth of its nonzeros to its first column);
-//   3. one thread per entry gathers its row and value, one thread per
-//      column finds where the column starts in the sorted keys.
+//      column numbers below n use) carrying, for FP32 values, the entry's
+//      row and value packed in 8 bytes (for FP64 values, the nonzero index):
+//      every column of A then lists its nonzeros in their CSR order, i.e. by
+//      increasing row, with no per-column sort and no atomics on the columns
+//      (a Zipf matrix sends a tenth of its nonzeros to its first column);
+//   3. one thread per entry writes its row and value (FP64: gathers them by
+//      the nonzero index), one thread per column finds where the column
+//      starts in the sorted keys.
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/iterator/counting_iterator.hpp>
+#include <rocprim/iterator/transform_iterator.hpp>
 
 #include "common.h"
 
@@ -144,7 +147,7 @@ __global__ __launch_bounds__(256) void k_validate(int64_t m, int64_t n, int64_t 
   if (t0 == 0 && (rp[0] != 0 || rp[m] != nnz)) bad = 1;
   if (m > 0) {
     // a wavefront takes 64 kValChunk consecutive nonzeros, lane L the ones at
-    // L, L + 64, ... (coalesced reads and writes): one binary search for its
+    // L, L + 64, ... (coalesced reads and writes): one binary search for the
     // first, then a walk along the row pointer (a binary search again after
     // more than 64 rows, so runs of empty rows stay cheap); with a
     // malformed row pointer the rows found may be wrong, but the flag above
@@ -154,7 +157,25 @@ __global__ __launch_bounds__(256) void k_validate(int64_t m, int64_t n, int64_t 
     for (int64_t cbeg = wave0 * kValChunk; cbeg < nnz; cbeg += stride * kValChunk) {
       const int64_t efirst = cbeg + lane;
       if (efirst >= nnz) break;
-      int64_t r = row_of(rp, m, efirst);
+      // the columns (and each one's predecessor) and values of the lane's
+      // nonzeros: all loads issued before any is used (clamped indices,
+      // unconditional), then one wait
+      int32_t cc[kValChunk], cp[kValChunk];
+      double vv[kValChunk];
+#pragma unroll
+      for (int k = 0; k < kValChunk; ++k) {
+        const int64_t e = efirst + 64 * k < nnz ? efirst + 64 * k : nnz - 1;
+        cc[k] = col[e];
+        cp[k] = col[e > 0 ? e - 1 : 0];
+        vv[k] = (double)val[e];
+      }
+#pragma unroll
+      for (int k = 0; k < kValChunk; ++k) asm volatile("" : "+v"(cc[k]), "+v"(cp[k]), "+v"(vv[k]));
+      // one binary search per wavefront (its first nonzero, a uniform
+      // value: scalar loads); each lane then walks to its own row
+      const int64_t cb = ((int64_t)__builtin_amdgcn_readfirstlane((int)(cbeg >> 32)) << 32) |
+                         (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)cbeg);
+      int64_t r = row_of(rp, m, cb);
       int64_t rbeg = rp[r], rend = rp[r + 1];
 #pragma unroll
       for (int k = 0; k < kValChunk; ++k) {
@@ -172,14 +193,13 @@ __global__ __launch_bounds__(256) void k_validate(int64_t m, int64_t n, int64_t 
           rbeg = rp[r];
           rend = rp[r + 1];
         }
-        const int32_t c = col[e];
+        const int32_t c = cc[k];
         rowidx[e] = (int32_t)r;
         if (c < 0 || (int64_t)c >= n)
           bad = 1;
-        else if (e > 0 && e > rbeg && col[e - 1] >= c)
+        else if (e > 0 && e > rbeg && cp[k] >= c)
           bad = 1;
-        const double v = (double)val[e];
-        if (!(v - v == 0.0)) nonfinite = 1;
+        if (!(vv[k] - vv[k] == 0.0)) nonfinite = 1;
       }
     }
   }
@@ -223,6 +243,42 @@ __global__ __launch_bounds__(256) void k_tgather_perm(int64_t nnz, const int32_t
     const int64_t pos = rp_new[inv_c[j]] + (p - rowT[j]);
     colT[pos] = inv_r[rowidx[s]];
     valT[pos] = val[s];
+  }
+}
+
+// Sort payload of nonzero i with an FP32 value: its row in the low word, the
+// value's bits in the high word.
+struct PackRowVal {
+  const int32_t *rowidx;
+  const float *val;
+  __device__ uint64_t operator()(int32_t i) const {
+    return (uint64_t)(uint32_t)rowidx[i] | ((uint64_t)__float_as_uint(val[i]) << 32);
+  }
+};
+
+// Sorted entry p with its packed (row, value): straight to position p of
+// CSR(A^T), or, with the degree order, to row inv_c[j] of the permuted A^T
+// at its offset inside column j = keys[p], the row renumbered inv_r[r].
+__global__ __launch_bounds__(256) void k_tscatter_packed(int64_t nnz, const uint64_t *__restrict__ rv,
+                                                         const uint32_t *__restrict__ keys,
+                                                         const int64_t *__restrict__ rowT,
+                                                         const int32_t *__restrict__ inv_r,
+                                                         const int32_t *__restrict__ inv_c,
+                                                         const int64_t *__restrict__ rp_new,
+                                                         int32_t *__restrict__ colT, float *__restrict__ valT) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += stride) {
+    const uint64_t w = rv[p];
+    const int32_t r = (int32_t)(uint32_t)w;
+    int64_t pos = p;
+    int32_t c = r;
+    if (inv_r) {
+      const int64_t j = (int64_t)keys[p];
+      pos = rp_new[inv_c[j]] + (p - rowT[j]);
+      c = inv_r[r];
+    }
+    colT[pos] = c;
+    valT[pos] = __uint_as_float((uint32_t)(w >> 32));
   }
 }
 
@@ -342,6 +398,14 @@ __global__ __launch_bounds__(256) void k_plan_fill(int64_t R, const int64_t *__r
   }
 }
 
+// one grid row per range
+__global__ __launch_bounds__(256) void k_zero_ranges(ZeroRanges z) {
+  const int r = blockIdx.y;
+  int32_t *p = z.p[r];
+  const int64_t n = z.n[r];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0;
+}
+
 __global__ void k_fill_zero_i32(int32_t *p, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0;
@@ -376,27 +440,44 @@ hipError_t launch_validate(int64_t m, int64_t n, int64_t nnz, const int64_t *rp,
   return hipGetLastError();
 }
 
+// Workspace: sorted keys, the sorted payload (8 bytes per entry: packed row
+// and FP32 value, or the FP64 path's 4-byte nonzero index), the sort's
+// temporary storage.
+size_t tws_keys_bytes(size_t cnt) { return (4 * (cnt + 64) + 255) / 256 * 256; }
+size_t tws_payload_bytes(size_t cnt) { return (8 * (cnt + 64) + 255) / 256 * 256; }
+
+auto packed_input(const int32_t *rowidx, const float *val) {
+  return rocprim::make_transform_iterator(rocprim::counting_iterator<int32_t>(0), PackRowVal{rowidx, val});
+}
+
 size_t transpose_ws_bytes(int64_t n, int64_t nnz) {
-  size_t sort_bytes = 0;
+  size_t sort_idx = 0, sort_packed = 0;
   const size_t cnt = nnz > 0 ? (size_t)nnz : 1;
-  (void)rocprim::radix_sort_pairs(nullptr, sort_bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+  (void)rocprim::radix_sort_pairs(nullptr, sort_idx, (const uint32_t *)nullptr, (uint32_t *)nullptr,
                                   rocprim::counting_iterator<int32_t>(0), (int32_t *)nullptr, cnt, 0u,
                                   key_bits(n));
-  return 2 * 4 * (cnt + 64) + sort_bytes + 256;
+  (void)rocprim::radix_sort_pairs(nullptr, sort_packed, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                                  packed_input(nullptr, nullptr), (uint64_t *)nullptr, cnt, 0u, key_bits(n));
+  return tws_keys_bytes(cnt) + tws_payload_bytes(cnt) + (sort_idx > sort_packed ? sort_idx : sort_packed) + 256;
 }
 
 hipError_t launch_transpose_keys(int64_t n, int64_t nnz, const int32_t *col, int64_t *rowT, void *ws,
-                                 size_t ws_bytes, hipStream_t st) {
+                                 size_t ws_bytes, hipStream_t st, const int32_t *rowidx, const void *val,
+                                 int dtype) {
   const size_t cnt = nnz > 0 ? (size_t)nnz : 1;
   uint32_t *keys = (uint32_t *)ws;
-  int32_t *src = (int32_t *)(keys + cnt + 64);
-  void *tmp = (void *)(src + cnt + 64);
-  size_t tmp_bytes = ws_bytes - 2 * 4 * (cnt + 64);
+  char *payload = (char *)ws + tws_keys_bytes(cnt);
+  void *tmp = (void *)(payload + tws_payload_bytes(cnt));
+  size_t tmp_bytes = ws_bytes - tws_keys_bytes(cnt) - tws_payload_bytes(cnt);
   if (nnz > 0) {
     // validated columns are in [0, n): sort on their low bits only
-    const hipError_t e = rocprim::radix_sort_pairs(tmp, tmp_bytes, (const uint32_t *)col, keys,
-                                                   rocprim::counting_iterator<int32_t>(0), src, (size_t)nnz, 0u,
-                                                   key_bits(n), st);
+    const hipError_t e =
+        dtype == 0 ? rocprim::radix_sort_pairs(tmp, tmp_bytes, (const uint32_t *)col, keys,
+                                               packed_input(rowidx, (const float *)val), (uint64_t *)payload,
+                                               (size_t)nnz, 0u, key_bits(n), st)
+                   : rocprim::radix_sort_pairs(tmp, tmp_bytes, (const uint32_t *)col, keys,
+                                               rocprim::counting_iterator<int32_t>(0), (int32_t *)payload,
+                                               (size_t)nnz, 0u, key_bits(n), st);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_tbounds, dim3(grid_for(n + 1, 256, 16384)), dim3(256), 0, st, n, nnz, keys, rowT);
@@ -409,9 +490,13 @@ hipError_t launch_transpose_gather(int64_t nnz, const int32_t *rowidx, const voi
   if (nnz == 0) return hipSuccess;
   const size_t cnt = (size_t)nnz;
   const uint32_t *keys = (const uint32_t *)ws;
-  const int32_t *src = (const int32_t *)(keys + cnt + 64);
+  const char *payload = (const char *)ws + tws_keys_bytes(cnt);
+  const int32_t *src = (const int32_t *)payload;
   const int g = grid_for(nnz, 256, 16384);
-  if (inv_r) {
+  if (dtype == 0) {
+    hipLaunchKernelGGL(k_tscatter_packed, dim3(g), dim3(256), 0, st, nnz, (const uint64_t *)payload, keys, rowT,
+                       inv_r, inv_c, rp_new, colT, (float *)valT);
+  } else if (inv_r) {
     if (dtype == 1)
       hipLaunchKernelGGL(k_tgather_perm<double>, dim3(g), dim3(256), 0, st, nnz, src, keys, rowidx,
                          (const double *)val, rowT, inv_r, inv_c, rp_new, colT, (double *)valT);
@@ -432,7 +517,7 @@ hipError_t launch_transpose_gather(int64_t nnz, const int32_t *rowidx, const voi
 hipError_t launch_transpose(int64_t n, int64_t nnz, const int32_t *col, const int32_t *rowidx, const void *val,
                             int dtype, int64_t *rowT, int32_t *colT, void *valT, void *ws, size_t ws_bytes,
                             hipStream_t st) {
-  const hipError_t e = launch_transpose_keys(n, nnz, col, rowT, ws, ws_bytes, st);
+  const hipError_t e = launch_transpose_keys(n, nnz, col, rowT, ws, ws_bytes, st, rowidx, val, dtype);
   if (e != hipSuccess) return e;
   return launch_transpose_gather(nnz, rowidx, val, dtype, ws, colT, valT, st);
 }
@@ -501,6 +586,19 @@ hipError_t launch_plan_fill(int64_t R, const int64_t *rp, int32_t long_row, cons
   if (R == 0) return hipSuccess;
   hipLaunchKernelGGL(k_plan_fill, dim3(grid_for(R, 256, 16384)), dim3(256), 0, st, R, rp, long_row, off,
                      tasks, longs, nlong);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_ranges(const ZeroRanges &z, hipStream_t st) {
+  if (z.count < 0 || z.count > kMaxZeroRanges) return hipErrorInvalidValue;
+  if (z.count == 0) return hipSuccess;
+  int64_t most = 1;
+  for (int i = 0; i < z.count; ++i) {
+    if (z.n[i] < 0 || (z.n[i] > 0 && !z.p[i])) return hipErrorInvalidValue;
+    if (z.n[i] > most) most = z.n[i];
+  }
+  const int64_t gx = grid_for(most, 256, 64);
+  hipLaunchKernelGGL(k_zero_ranges, dim3((unsigned)gx, (unsigned)z.count), dim3(256), 0, st, z);
   return hipGetLastError();
 }
 

@@ -19,6 +19,14 @@
 // for bit.  Tasks are numbered chunks first, then rows, so the heavy chunks
 // start early.
 //
+// Gathers in flight: when the panel X is known to span less than 2 GB, the
+// gathers are raw buffer loads whose range check returns zero for offsets
+// past the panel.  Every step then issues U gathers unconditionally, the
+// slots past the row's end pointing out of range (no memory traffic, value
+// zero), so short rows and the last nonzeros of a row keep U gathers in
+// flight instead of one at a time, and the (column, value) pairs of the next
+// G nonzeros are fetched while the current ones are gathered.
+//
 // The kernels read the solver's done flag first and exit when the PVE check
 // has already stopped the iteration (speculatively launched passes).
 #include "common.h"
@@ -26,6 +34,28 @@
 namespace dsv {
 
 namespace {
+
+// Raw buffer resource (word 3 of the descriptor for gfx950 raw buffers) and
+// an offset past any panel of at most kBufMaxBytes (plus up to 3 words per
+// lane, still below 2^31): such loads return zero.
+constexpr int kBufRsrcWord3 = 0x00020000;
+constexpr uint32_t kBufPastEnd = 0x7FFFFF00u;
+constexpr int64_t kBufMaxBytes = 0x7FFFF000;
+
+// One lane's V panel elements (V * sizeof(TX) bytes, whole 16-byte words)
+// at byte offset off of the buffer, converted to the accumulator type.
+template <typename TX, typename TA, int V>
+__device__ __forceinline__ void buf_gather(__amdgpu_buffer_rsrc_t r, uint32_t off, TA *o) {
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  constexpr int W = 16 / (int)sizeof(TX);  // elements per 16-byte word
+  static_assert(V % W == 0, "whole 16-byte words per lane");
+#pragma unroll
+  for (int j = 0; j < V / W; ++j) {
+    const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(r, (int)(off + 16u * j), 0, 0);
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+    vec16<TX, TA>::unpack(w, o + j * W);
+  }
+}
 
 template <typename TX> struct acc_of {
   using type = float;
@@ -41,7 +71,7 @@ __global__ __launch_bounds__(256) void k_spmm(
     int64_t ldy, int G, int64_t n_chunks, const ChunkTask *__restrict__ tasks,
     TA *__restrict__ partial, int64_t ldp, int32_t long_row, const TX *__restrict__ Q, int64_t ldq,
     const double *__restrict__ alpha, const int32_t *__restrict__ done,
-    const int32_t *__restrict__ rowmat, const SolverState *__restrict__ bstate) {
+    const int32_t *__restrict__ rowmat, const SolverState *__restrict__ bstate, int32_t xbytes) {
   if (done && *done) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rpw = kWave / G;
@@ -77,6 +107,48 @@ __global__ __launch_bounds__(256) void k_spmm(
   // then broadcasts them lane to lane, so the gathers of U consecutive
   // nonzeros are independent and in flight together.
   constexpr int U = 8;
+  if (xbytes > 0) {
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)X, 0, xbytes, kBufRsrcWord3);
+    const uint32_t row_b = (uint32_t)(ldx * (int64_t)sizeof(TX));
+    const uint32_t lane_b = (uint32_t)(cl * V * (int)sizeof(TX));
+    // clamped (valid) pair index: the loads are unconditional, the slots past
+    // the end are masked where the pairs are used
+    auto pair_at = [&](int64_t i) -> int64_t { return i < e ? i : e - 1; };
+    int32_t myc = 0;
+    TA myv = (TA)0;
+    if (b < e) {
+      const int64_t i0 = pair_at(b + cl);
+      myc = col[i0];
+      myv = (TA)val[i0];
+    }
+    for (int64_t base = b; base < e; base += G) {
+      const int64_t inext = pair_at(base + G + cl);
+      const int32_t nc = col[inext];
+      const TV nv = val[inext];
+      const int cnt = (int)((e - base) < G ? (e - base) : G);
+      for (int t = 0; t < cnt; t += U) {
+        uint32_t off[U];
+        TA v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int32_t c = __shfl(myc, src0 + t + u, 64);
+          const TA w = __shfl(myv, src0 + t + u, 64);
+          const bool ok = t + u < cnt;
+          off[u] = ok ? (uint32_t)c * row_b + lane_b : kBufPastEnd;
+          v[u] = ok ? w : (TA)0;
+        }
+        TA x[U][V];
+#pragma unroll
+        for (int u = 0; u < U; ++u) buf_gather<TX, TA, V>(rs, off[u], x[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int i = 0; i < V; ++i) acc[i] = fma(v[u], x[u][i], acc[i]);
+      }
+      myc = nc;
+      myv = (TA)nv;
+    }
+  } else
   for (int64_t base = b; base < e; base += G) {
     const int64_t idx = base + cl;
     int32_t myc = 0;
@@ -201,9 +273,11 @@ hipError_t run_spmm_v(int64_t R, const int64_t *rp, const int32_t *col, const vo
                       const ChunkTask *tasks, int64_t n_long, const LongRow *longs, void *partial,
                       int32_t long_row, const void *Q, int64_t ldq, const double *alpha,
                       const int32_t *done, const int32_t *rowmat, const SolverState *bstate,
-                      hipStream_t st) {
+                      hipStream_t st, int64_t xrows) {
   using TA = typename acc_of<TX>::type;
   const int G = ld_cols / V;
+  const int64_t xb = xrows * ldx * (int64_t)sizeof(TX);
+  const int32_t xbytes = (xrows > 0 && xb <= kBufMaxBytes) ? (int32_t)xb : 0;
   if (G < 1 || G > kWave || ld_cols % V) return hipErrorInvalidValue;
   const int rpw = kWave / G;
   const int64_t subs = n_chunks + R;
@@ -214,12 +288,12 @@ hipError_t run_spmm_v(int64_t R, const int64_t *rp, const int32_t *col, const vo
       hipLaunchKernelGGL((k_spmm<TV, TX, TY, TA, true, V>), dim3((unsigned)blocks), dim3(256), 0, st, R, rp,
                          col, (const TV *)val, (const TX *)X, ldx, (TY *)Y, ldy, G, n_chunks, tasks,
                          (TA *)partial, (int64_t)ld_cols, long_row, (const TX *)Q, ldq, alpha, done,
-                         rowmat, bstate);
+                         rowmat, bstate, xbytes);
     else
       hipLaunchKernelGGL((k_spmm<TV, TX, TY, TA, false, V>), dim3((unsigned)blocks), dim3(256), 0, st, R, rp,
                          col, (const TV *)val, (const TX *)X, ldx, (TY *)Y, ldy, G, n_chunks, tasks,
                          (TA *)partial, (int64_t)ld_cols, long_row, (const TX *)Q, ldq, alpha, done,
-                         rowmat, bstate);
+                         rowmat, bstate, xbytes);
   }
   if (n_long > 0) {
     const int64_t lb = n_long;  // one workgroup per long row
@@ -243,14 +317,14 @@ hipError_t run_spmm(int64_t R, const int64_t *rp, const int32_t *col, const void
                     const ChunkTask *tasks, int64_t n_long, const LongRow *longs, void *partial,
                     int32_t long_row, const void *Q, int64_t ldq, const double *alpha,
                     const int32_t *done, const int32_t *rowmat, const SolverState *bstate,
-                    hipStream_t st) {
+                    hipStream_t st, int64_t xrows) {
   using TA = typename acc_of<TX>::type;
   constexpr int V = vec16<TX, TA>::N;
   if (ld_cols / V <= kWave)
     return run_spmm_v<TV, TX, TY, V>(R, rp, col, val, X, ldx, Y, ldy, ld_cols, n_chunks, tasks, n_long, longs,
-                                     partial, long_row, Q, ldq, alpha, done, rowmat, bstate, st);
+                                     partial, long_row, Q, ldq, alpha, done, rowmat, bstate, st, xrows);
   return run_spmm_v<TV, TX, TY, 2 * V>(R, rp, col, val, X, ldx, Y, ldy, ld_cols, n_chunks, tasks, n_long,
-                                       longs, partial, long_row, Q, ldq, alpha, done, rowmat, bstate, st);
+                                       longs, partial, long_row, Q, ldq, alpha, done, rowmat, bstate, st, xrows);
 }
 
 }  // namespace
@@ -260,21 +334,21 @@ hipError_t launch_spmm(int64_t R, const int64_t *rp, const int32_t *col, const v
                        int ld_cols, int64_t n_chunks, const ChunkTask *tasks, int64_t n_long,
                        const LongRow *longs, void *partial, int32_t long_row, const void *Q,
                        int64_t ldq, const double *alpha, const int32_t *done, hipStream_t st,
-                       const int32_t *rowmat, const SolverState *bstate) {
+                       const int32_t *rowmat, const SolverState *bstate, int64_t xrows) {
   // supported combinations: (values, X/Q, Y) = (f32, f32, f32), (f64, f64, f64),
   // (f32, bf16, bf16), (f32, bf16, f32)
   if (xdtype == 0 && ydtype == 0 && vdtype == 0)
     return run_spmm<float, float, float>(R, rp, col, val, X, ldx, Y, ldy, ld_cols, n_chunks, tasks, n_long,
-                                         longs, partial, long_row, Q, ldq, alpha, done, rowmat, bstate, st);
+                                         longs, partial, long_row, Q, ldq, alpha, done, rowmat, bstate, st, xrows);
   if (xdtype == 1 && ydtype == 1 && vdtype == 1)
     return run_spmm<double, double, double>(R, rp, col, val, X, ldx, Y, ldy, ld_cols, n_chunks, tasks,
-                                            n_long, longs, partial, long_row, Q, ldq, alpha, done, rowmat, bstate, st);
+                                            n_long, longs, partial, long_row, Q, ldq, alpha, done, rowmat, bstate, st, xrows);
   if (xdtype == 2 && ydtype == 2 && vdtype == 0)
     return run_spmm<float, bf16, bf16>(R, rp, col, val, X, ldx, Y, ldy, ld_cols, n_chunks, tasks, n_long,
-                                       longs, partial, long_row, Q, ldq, alpha, done, rowmat, bstate, st);
+                                       longs, partial, long_row, Q, ldq, alpha, done, rowmat, bstate, st, xrows);
   if (xdtype == 2 && ydtype == 0 && vdtype == 0)
     return run_spmm<float, bf16, float>(R, rp, col, val, X, ldx, Y, ldy, ld_cols, n_chunks, tasks, n_long,
-                                        longs, partial, long_row, Q, ldq, alpha, done, rowmat, bstate, st);
+                                        longs, partial, long_row, Q, ldq, alpha, done, rowmat, bstate, st, xrows);
   return hipErrorInvalidValue;
 }
 
