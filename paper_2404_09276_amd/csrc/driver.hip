@@ -804,8 +804,12 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       tmark_end(h);
       if (e != hipSuccess) return e;
       tmark_begin(h, DASHSVD_KT_SPMM_T, pass);
+      // X = M^T Z feeds only the next pass: when the eigensolver of this
+      // block stops the iteration before the product's workgroups start,
+      // they return at once (the live flag, not the pass-start snapshot;
+      // Z above is kept, the final step uses it)
       e = launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Z, ld, cdt, b.X, ld, cdt, ldc, b.planT.n_chunks, b.planT.tasks,
-                      b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr, skip, st, nullptr,
+                      b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr, gate, st, nullptr,
                       nullptr, Mm);
       tmark_end(h);
       if (e != hipSuccess) return e;
@@ -1054,6 +1058,8 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   inf.long_chunks_AT = wide ? b.planM.n_chunks : b.planT.n_chunks;
   for (const auto &mk : h->marks) {
     if (mk.pass > hs.pass) continue;  // passes launched after the stop returned at once
+    // the transposed product of the stopping pass may have returned early
+    if (hs.done && pdt == cdt && mk.group == DASHSVD_KT_SPMM_T && mk.pass == hs.pass) continue;
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, h->ev[mk.e0], h->ev[mk.e1]) == hipSuccess) {
       inf.kt_ms[mk.group] += ms;

@@ -27,8 +27,10 @@
 // flight instead of one at a time, and the (column, value) pairs of the next
 // G nonzeros are fetched while the current ones are gathered.
 //
-// The kernels read the solver's done flag first and exit when the PVE check
-// has already stopped the iteration (speculatively launched passes).
+// The kernels read the solver's done flag first (a device-scope load: the
+// flag may be set by the eigensolver running beside them) and exit when the
+// PVE check has already stopped the iteration (speculatively launched
+// passes, and the transposed product of the last pass).
 #include "common.h"
 
 namespace dsv {
@@ -72,7 +74,7 @@ __global__ __launch_bounds__(256) void k_spmm(
     TA *__restrict__ partial, int64_t ldp, int32_t long_row, const TX *__restrict__ Q, int64_t ldq,
     const double *__restrict__ alpha, const int32_t *__restrict__ done,
     const int32_t *__restrict__ rowmat, const SolverState *__restrict__ bstate, int32_t xbytes) {
-  if (done && *done) return;
+  if (done && __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rpw = kWave / G;
   const int sub = lane / G, cl = lane - sub * G;
@@ -209,7 +211,7 @@ __global__ __launch_bounds__(256) void k_spmm_long(
     TY *__restrict__ Y, int64_t ldy, int G, const TX *__restrict__ Q, int64_t ldq,
     const double *__restrict__ alpha, const int32_t *__restrict__ done,
     const int32_t *__restrict__ rowmat, const SolverState *__restrict__ bstate) {
-  if (done && *done) return;
+  if (done && __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
   __shared__ TA red[256 * V];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rpw = kWave / G;

@@ -98,7 +98,9 @@ __device__ __forceinline__ void pass_tail(const EigArgs &a, SolverState *state, 
     state->ratio = ratio;
     if (a.cq_switch > 0.0 && a.tol > 0.0 && ratio <= a.cq_switch * a.tol) state->cq_off = 1;
     if (s_stop) {
-      state->done = 1;
+      // published at device scope: the transposed product of this pass,
+      // running beside the eigensolver, stops early once it sees the flag
+      __hip_atomic_store(&state->done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       state->converged = 1;
       if (a.ndone) atomicAdd(a.ndone, 1);
     } else {
