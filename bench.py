@@ -171,9 +171,10 @@ def source_digest(*names):
     return h.hexdigest()
 
 
-# The SpMM's counter traffic depends on the kernel and on the order of the
-# operator's rows and columns (the degree order is built in k_csr.hip).
-TRAFFIC_SOURCES = {"spmm": ("k_spmm.hip", "k_csr.hip"), "eig": ("k_eig.hip",)}
+# The SpMM's counter traffic depends on the kernel, on the order of the
+# operator's rows and columns (the degree order is built in k_csr.hip) and on
+# the panel layout (the leading dimension is chosen in driver.hip).
+TRAFFIC_SOURCES = {"spmm": ("k_spmm.hip", "k_csr.hip", "driver.hip"), "eig": ("k_eig.hip",)}
 
 
 def traffic(kind):
