@@ -33,10 +33,11 @@ thread_local std::string g_create_error;
 
 constexpr int kDefaultLongRow = 128;
 // Default chunk length from DASHSVD_REORDER_MIN_NNZ nonzeros: on the
-// degree-ordered power-law operators of that size, chunks of 512 nonzeros
-// gave the fastest products (fewer partial rows; 128 and 2048 were 11 % and
-// 18 % slower on the 10M-nonzero benchmark matrix).
-constexpr int kDefaultLongRowLarge = 512;
+// degree-ordered power-law operators of that size, chunks of 768 nonzeros
+// gave the fastest products (fewer partial rows; on the 10M-nonzero
+// benchmark matrix the solve took 9.89 ms against 10.06, 9.99 and 9.90 ms
+// with 384, 512 and 1024, timed in one process).
+constexpr int kDefaultLongRowLarge = 768;
 constexpr int kDefaultPmax = 64;
 
 size_t dsz(int dt) { return dt == DASHSVD_F64 ? 8 : (dt == DASHSVD_BF16 ? 2 : 4); }
@@ -1643,7 +1644,7 @@ dashsvd_status dashsvd_autotune(dashsvd_handle *h, const dashsvd_csr *As, int32_
     nnz += As[i].nnz;
   }
   const std::string key = tune_key(saved.precision, ld, rows, nnz, count > 1);
-  static const int32_t kCand[] = {32, 64, 128, 256, 512, 1024};
+  static const int32_t kCand[] = {32, 64, 128, 256, 512, 768, 1024};
   double best_t = 0.0;
   int32_t best_T = 0;
   dashsvd_status s = DASHSVD_OK;
