@@ -351,8 +351,11 @@ dashsvd_status dashsvd_k_transpose(int64_t m, int64_t n, int64_t nnz, const int6
  * Alg. 5 step 4), with the library's row-split + long-row-chunk SpMM.
  * A: CSR rows x cols on device, values F32 (panel types F32/BF16) or F64
  * (F64 panels).  X: cols x ldx, Y: rows x ldy, Q: rows x ldq; the first l
- * columns are used.  xdtype / ydtype: element types of X/Q and Y.  long_row
- * <= 0 selects the default.  Synchronises the stream (plan sizing). */
+ * columns are used.  xdtype / ydtype: element types of X/Q and Y.  cols <= 0
+ * means the rows of X are not given: the gathers then use plain loads
+ * instead of range-checked buffer loads (the path panels of 2 GB and more
+ * take; same results).  long_row <= 0 selects the default.  Synchronises
+ * the stream (plan sizing). */
 dashsvd_status dashsvd_k_spmm(int64_t rows, int64_t cols, int64_t nnz, const int64_t *row_ptr,
                               const int32_t *col, const void *val, const void *X, int64_t ldx,
                               int32_t xdtype, void *Y, int64_t ldy, int32_t ydtype, int32_t l,

@@ -162,11 +162,12 @@ def test_spmm_integer_bitwise(torch_dev, l, dt):
     Qd = _dev(torch, Q, tdt)
     ydt = torch.float64 if dt == "f64" else torch.float32
     alpha = torch.tensor([2.0], dtype=torch.float64, device="cuda")
-    for long_row in (0, 64, 7):
+    # cols = 0: rows of X not given, plain loads instead of buffer loads
+    for long_row, xrows in ((0, A.n), (64, A.n), (7, A.n), (0, 0), (7, 0)):
         Y = torch.zeros((A.m, ld), dtype=ydt, device="cuda")
-        k_spmm(A.m, A.n, rp, col, val, Xd, Y, l, long_row=long_row)
+        k_spmm(A.m, xrows, rp, col, val, Xd, Y, l, long_row=long_row)
         Cs = torch.zeros((A.m, ld), dtype=ydt, device="cuda")
-        k_spmm(A.m, A.n, rp, col, val, Xd, Cs, l, Q=Qd, alpha=alpha, long_row=long_row)
+        k_spmm(A.m, xrows, rp, col, val, Xd, Cs, l, Q=Qd, alpha=alpha, long_row=long_row)
         torch.cuda.synchronize()
         ref = oracle.csr_spmm(A.row_ptr, A.col, A.val, X[:, :l])
         assert np.array_equal(Y.cpu().numpy()[:, :l].astype(np.float64), ref)
