@@ -98,6 +98,13 @@ def test_transpose_bitwise_all_segment_classes(torch_dev):
     _transpose_case(torch_dev, A, np.float64)
 
 
+def test_transpose_nine_bit_digit_sort(torch_dev):
+    # 300 columns (9 key bits) and 70 000 columns (17 key bits) take the
+    # sort with 9-bit digits (one and two passes)
+    _transpose_case(torch_dev, synth.zipf_csr(2000, 300, 40000, seed=6))
+    _transpose_case(torch_dev, synth.zipf_csr(50000, 70000, 1000000, seed=7))
+
+
 def test_transpose_small_and_ragged(torch_dev):
     rng = np.random.default_rng(3)
     D = rng.standard_normal((70, 45)) * (rng.random((70, 45)) < 0.2)
