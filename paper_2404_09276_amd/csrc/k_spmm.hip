@@ -31,6 +31,8 @@
 // flag may be set by the eigensolver running beside them) and exit when the
 // PVE check has already stopped the iteration (speculatively launched
 // passes, and the transposed product of the last pass).
+#include <type_traits>
+
 #include "common.h"
 
 namespace dsv {
@@ -66,8 +68,17 @@ template <> struct acc_of<double> {
   using type = double;
 };
 
+// FP32 panels, one 16-byte vector per lane: at least 6 wavefronts per SIMD
+// (at most 80 VGPRs; the compiler's own choice, 81, allowed 5), so more
+// gathers are in flight per CU: 1 % faster products on the power-law
+// benchmark matrix (8 wavefronts would need spills).  The other lane widths
+// and types would spill under that cap and keep the compiler's choice.
+template <typename TX, int V> constexpr int spmm_min_waves() {
+  return std::is_same<TX, float>::value && V == 4 ? 6 : 1;
+}
+
 template <typename TV, typename TX, typename TY, typename TA, bool SHIFT, int V>
-__global__ __launch_bounds__(256) void k_spmm(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(spmm_min_waves<TX, V>()))) void k_spmm(
     int64_t R, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
     const TV *__restrict__ val, const TX *__restrict__ X, int64_t ldx, TY *__restrict__ Y,
     int64_t ldy, int G, int64_t n_chunks, const ChunkTask *__restrict__ tasks,
