@@ -63,6 +63,8 @@ def lib():
         L.orc_pve_ratio.restype = f64
         L.orc_shift_update.argtypes = [i64, P, f64]
         L.orc_shift_update.restype = f64
+        L.orc_schedule_shift.argtypes = [i64, f64, f64, f64, f64, f64, f64, f64, P]
+        L.orc_schedule_shift.restype = f64
         L.orc_dashsvd.argtypes = [i64, i64, P, P, P, i64, i64, i64, f64, u64, P, i32, i32, P,
                                   P, P, P, P, P]
         L.orc_dashsvd.restype = C.c_int
@@ -164,6 +166,15 @@ def shift_update(S, alpha: float) -> float:
     """Alg. 5 step 6: if S_l > alpha then alpha = (S_l + alpha)/2."""
     S = np.ascontiguousarray(S, dtype=np.float64)
     return float(lib().orc_shift_update(S.shape[0], _p(S), alpha))
+
+
+def schedule_shift(j: int, ratio: float, prev_ratio: float, ek1: float, prev_ek1: float,
+                   el: float, alpha: float, c: float, off: bool):
+    """Proposed-multiplier shift (our extension of Alg. 5 step 6) with its
+    guard; returns (next shift, guard state)."""
+    o = C.c_int32(1 if off else 0)
+    a = lib().orc_schedule_shift(j, ratio, prev_ratio, ek1, prev_ek1, el, alpha, c, C.byref(o))
+    return float(a), bool(o.value)
 
 
 # ---------------------------------------------------------------- dashSVD

@@ -335,6 +335,24 @@ double orc_shift_update(int64_t l, const double *S, double alpha) {
   return alpha;
 }
 
+/* Proposed-multiplier form of the shift rule (the learned shift's policy;
+ * our extension of Alg. 5 step 6).  The paper's update alpha <- (S_l +
+ * alpha)/2 equals max(alpha, 0.5 * E_l) with E_l = S_l + alpha the surrogate
+ * of sigma_l^2 (Prop. 3); a schedule replaces 0.5 by c for the shift set
+ * after pass j.  Guard: from the second pass on, once the PVE ratio grows or
+ * E_{k+1} shrinks between consecutive passes, *off is set and 0.5 is used
+ * for the rest of the run.  Arguments: pass number j (1-based), its ratio
+ * and E_{k+1}, the previous pass's ratio and E_{k+1}, E_l, the shift used in
+ * pass j, and the proposed multiplier c.  Returns the next shift. */
+double orc_schedule_shift(int64_t j, double ratio, double prev_ratio, double ek1,
+                          double prev_ek1, double el, double alpha, double c,
+                          int32_t *off) {
+  if (j >= 2 && (ratio > prev_ratio || ek1 < prev_ek1)) *off = 1;
+  const double mult = *off ? 0.5 : c;
+  const double cand = mult * el;
+  return cand > alpha ? cand : alpha;
+}
+
 /* ------------------------------------------------------------------ */
 /* dashSVD, Alg. 5 (Alg. 4 when tol == 0). */
 
@@ -411,7 +429,7 @@ int orc_dashsvd(int64_t m, int64_t n, const int64_t *row_ptr,
   deficient |= orc_eigsvd(M_n, l, Cb, Q, Sv, Vl);
   double alpha = 0.0, alpha_prev = 0.0;
   double prev_ratio = 0.0, prev_ek1 = 0.0;
-  int sched_off = 0;
+  int32_t sched_off = 0;
   int32_t passes = 0, converged = 0;
 
   for (int64_t j = 1; j <= p_max; ++j) {
@@ -439,18 +457,11 @@ int orc_dashsvd(int64_t m, int64_t n, const int64_t *row_ptr,
     } else if (shift_policy == ORC_SHIFT_FIXED) {
       if (j == 1) alpha = orc_shift_update(l, Sv, alpha);
     } else if (shift_policy == ORC_SHIFT_SCHEDULE) {
-      /* Proposed-multiplier form of the shift rule: the paper's update
-       * alpha <- (S_l + alpha)/2 equals max(alpha, 0.5 * E_l) with
-       * E_l = S_l + alpha the surrogate of sigma_l^2 (Prop. 3).  A schedule
-       * replaces 0.5 by sched[j] for the shift set after pass j.  Guard: once
-       * the PVE ratio grows or E_{k+1} shrinks between passes, the schedule
-       * is dropped and 0.5 is used for the rest of the run. */
+      /* schedule sched[j] for the shift set after pass j (0.5 without one) */
       const double El = Sv[l - 1] + a_used;
       const double Ek1 = Sv[k] + a_used;
-      if (j >= 2 && (ratio > prev_ratio || Ek1 < prev_ek1)) sched_off = 1;
-      const double c = (sched && !sched_off) ? sched[j] : 0.5;
-      const double cand = c * El;
-      alpha = cand > alpha ? cand : alpha;
+      alpha = orc_schedule_shift(j, ratio, prev_ratio, Ek1, prev_ek1, El, alpha,
+                                 sched ? sched[j] : 0.5, &sched_off);
       prev_ek1 = Ek1;
     }
     prev_ratio = ratio;

@@ -100,6 +100,35 @@ def test_batched_fp32_matches_single_matrix_runs(torch_dev):
         assert np.abs(U.T @ U - np.eye(10)).max() < 1e-5
 
 
+@pytest.mark.parametrize("prec,bar", [("fp32", 1e-5), ("bf16", 2e-2)])
+def test_batched_members_match_oracle(torch_dev, prec, bar):
+    """Every member of an FP32 or BF16 batch against the FP64 oracle on that
+    matrix alone with the member's Omega stream (seed + i).  FP32: the same
+    pass count as the oracle's tolerance run and sigma within 1e-5 relative.
+    BF16 panels (8-bit significand, relative rounding 2^-9 on every panel
+    entry): sigma within 2e-2 relative of the oracle run for the member's own
+    pass count, and every member converged."""
+    mats = _batch(np.float32) + synth.batched_zipf(6, rows=(1000, 6000), seed=5100)
+    st, out, summary = _run(mats, 10, 6, 40, 1e-2, 500, prec)
+    assert st in (0, 2) and summary.converged
+    worst = 0.0
+    for i, A in enumerate(mats):
+        (U, S, V), info = out[i]
+        assert info.converged, i
+        if prec == "fp32":
+            ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 10, 6, 40, 1e-2, seed=500 + i)
+            borderline = np.any(np.abs(ref.ratio - 1e-2) < 1e-6 * 1e-2)
+            if not borderline:
+                assert info.passes == ref.passes, i
+        else:
+            ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 10, 6, info.passes, 0.0,
+                                 seed=500 + i)
+        rel = np.abs(S - ref.S) / ref.S
+        worst = max(worst, float(rel.max()))
+        assert np.all(rel <= bar), (i, rel.max())
+    print(f"batched {prec}: worst member sigma rel err vs oracle {worst:.2e}", flush=True)
+
+
 def test_batched_bf16_power_law_batch(torch_dev):
     """A batch shaped like the paper-scale batched workload (rows 1k-10k,
     columns 0.5-1 x rows, density 0.05-1 %, Zipf 1.1 degrees), k = 16,

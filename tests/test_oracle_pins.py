@@ -434,3 +434,176 @@ def test_mlp_reference_gradient_matches_finite_differences():
         e[i] = h
         fd = (mlp_ref.loss(P + e, X, Y, D, H, 0.9) - mlp_ref.loss(P - e, X, Y, D, H, 0.9)) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
+
+
+# ------------------------------------------------------------------ error metrics
+
+def test_metrics_hand_rotated_vector():
+    """Sec. 4 error metrics on a diagonal matrix with hand-known answers.
+    A = diag(5, 4, 3, 2, 1) padded to 7 x 5, k = 2.  u_1 is the exact left
+    vector e_1 rotated by theta towards e_4 (sigma 2), u_2 = e_2 exactly, so
+    ||A^T u_1||^2 = 25 cos^2 + 4 sin^2 and eps_PVE = 21 sin^2 / sigma_3^2.
+    Catches a denominator of sigma_k^2 (gives /16), a missing square, or the
+    norm of A u instead of A^T u; eps_sigma divides by the exact sigma."""
+    sig = np.array([5.0, 4.0, 3.0, 2.0, 1.0])
+    D = np.zeros((7, 5))
+    for i in range(5):
+        D[i, i] = sig[i]
+    A = synth.dense_to_csr(D)
+    th = 0.3
+    U = np.zeros((7, 2))
+    U[0, 0], U[3, 0] = math.cos(th), math.sin(th)
+    U[1, 1] = 1.0
+    S = np.array([4.9, 4.1])
+    pve, es = oracle.metrics(7, 5, A.row_ptr, A.col, A.val, U, S, sig)
+    assert pve == pytest.approx(21.0 * math.sin(th) ** 2 / 9.0, rel=1e-14)
+    assert es == pytest.approx(max(0.1 / 5.0, 0.1 / 4.0), rel=1e-13)
+
+
+def test_metrics_match_dense_numpy():
+    """The metrics against a direct dense computation: sigma from LAPACK svd,
+    ||A^T u_i||^2 formed with a dense product, denominator sigma_{k+1}^2."""
+    A, D = _csr_small(seed=90, m=60, n=45, density=0.3)
+    sv = np.linalg.svd(D, compute_uv=False)
+    k = 6
+    rng = np.random.default_rng(91)
+    U, _ = np.linalg.qr(np.linalg.svd(D)[0][:, :k] + 1e-3 * rng.standard_normal((60, k)))
+    S = sv[:k] * (1 - 1e-4 * rng.random(k))
+    pve, es = oracle.metrics(A.m, A.n, A.row_ptr, A.col, A.val, U, S, sv)
+    nrm = np.linalg.norm(D.T @ U, axis=0) ** 2
+    assert pve == pytest.approx(np.max(np.abs(sv[:k] ** 2 - nrm)) / sv[k] ** 2, rel=1e-10)
+    assert es == pytest.approx(np.max(np.abs(sv[:k] - S) / sv[:k]), rel=1e-10)
+
+
+# ------------------------------------------------------------------ shift policies
+
+def _mirror(D, om, k, s, P, next_alpha):
+    """NumPy/LAPACK route to the pass loop of Alg. 5 (tol = 0, reading R2);
+    next_alpha(j, S, alpha, ratio) gives the shift set after pass j."""
+    l = k + s
+
+    def eig_svd(Cm):
+        w, V = np.linalg.eigh(Cm.T @ Cm)
+        w, V = np.maximum(w[::-1], 0.0), V[:, ::-1]
+        Sv = np.sqrt(w)
+        return Cm @ V / Sv, Sv
+
+    Q, _ = eig_svd(D.T @ om)
+    alpha, a_prev, Sp = 0.0, 0.0, np.zeros(l)
+    al, ra = [], []
+    for j in range(1, P + 1):
+        Q, S = eig_svd(D.T @ (D @ Q) - alpha * Q)
+        ratio = np.max(np.abs((Sp[:k] + a_prev) - (S[:k] + alpha))) / (S[k] + alpha)
+        al.append(alpha)
+        ra.append(ratio)
+        a_prev, Sp = alpha, S
+        alpha = next_alpha(j, S, alpha, ratio)
+    return np.array(al), np.array(ra)
+
+
+def test_fixed_policy_lapack_mirror():
+    """Alg. 2* of Sec. 4.1: the shift is set by the rule after the first pass
+    and then frozen.  The oracle's FIXED trace against a LAPACK mirror, and
+    the trace differs from the paper's rule (which keeps moving the shift),
+    so a FIXED branch that fell through to the paper's rule fails here."""
+    A = synth.uniform_csr(300, 200, 6000, seed=77, dtype=np.float64)
+    D = A.to_dense()
+    k, s, P = 8, 4, 6
+    om = oracle.gaussian(55, A.m, k + s)
+    r = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, k, s, P, 0.0, omega=om,
+                       shift_policy=oracle.SHIFT_FIXED)
+
+    def nxt(j, S, a, ratio):
+        return (S[-1] + a) / 2 if (j == 1 and S[-1] > a) else a
+    al, ra = _mirror(D, om, k, s, P, nxt)
+    assert np.allclose(r.alpha, al, rtol=1e-10, atol=1e-14)
+    assert np.allclose(r.ratio, ra, rtol=1e-8)
+    assert r.alpha[1] > 0 and np.all(r.alpha[1:] == r.alpha[1])
+    rp = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, k, s, P, 0.0, omega=om)
+    assert rp.alpha[-1] > r.alpha[-1] * 1.1
+
+
+def test_schedule_lapack_mirror_with_guard_trip():
+    """The schedule policy with c = 0.9 from the second pass on, against a
+    LAPACK mirror that applies the guard written out independently.  The
+    ratio grows at pass 6 (0.007 -> 0.15) so the guard drops the schedule
+    there; without the guard the shift would keep rising."""
+    A = synth.uniform_csr(300, 200, 6000, seed=77, dtype=np.float64)
+    D = A.to_dense()
+    k, s, P = 8, 4, 8
+    l = k + s
+    om = oracle.gaussian(55, A.m, l)
+    sched = np.array([0.5] + [0.9] * P)
+    r = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, k, s, P, 0.0, omega=om,
+                       shift_policy=oracle.SHIFT_SCHEDULE, sched=sched)
+    st = {"off": False, "pr": None, "pe": None, "trip": None}
+
+    def nxt(j, S, a, ratio):
+        ek1 = S[k] + a
+        if j >= 2 and (ratio > st["pr"] or ek1 < st["pe"]) and not st["off"]:
+            st["off"], st["trip"] = True, j
+        st["pr"], st["pe"] = ratio, ek1
+        c = 0.5 if st["off"] else sched[j]
+        return max(a, c * (S[-1] + a))
+    al, ra = _mirror(D, om, k, s, P, nxt)
+    assert st["trip"] == 6
+    assert np.allclose(r.alpha, al, rtol=1e-10, atol=1e-14)
+    assert np.allclose(r.ratio, ra, rtol=1e-7)
+    # after the trip 0.5 * E_l stays under the shift, which then stays put;
+    # the unguarded rule would have moved it to 0.9 * E_l
+    assert r.alpha[7] == r.alpha[6] == r.alpha[5]
+    E_l6 = r.s_hat[5][-1] + r.alpha[5]
+    assert 0.9 * E_l6 > r.alpha[6] * 1.01
+
+
+def test_schedule_rank_l_hand_derived():
+    """Rank exactly l (the golden matrix): every pass's block has singular
+    values sigma_i^2 - alpha (Prop. 2).  With c_1 = 0.8 the shift set after
+    pass 1 is 0.8 * E_l = 0.8 * 9 = 7.2, not the paper's 4.5, and pass 2's
+    S is sigma^2 - 7.2 = [92.8, 56.8, 28.8, 17.8, 8.8, 1.8]."""
+    g = json.load(open(os.path.join(GOLDEN, "rank_l_shift_sequence.json")))
+    A, D, sig = _rank_l_matrix(g)
+    sched = np.array([0.5, 0.8, 0.8])
+    r = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, g["k"], g["s"], 2, 0.0, seed=4,
+                       shift_policy=oracle.SHIFT_SCHEDULE, sched=sched)
+    assert r.passes == 2
+    assert np.allclose(r.alpha, [0.0, 7.2], rtol=1e-12, atol=1e-13)
+    assert np.allclose(r.s_hat[1], [92.8, 56.8, 28.8, 17.8, 8.8, 1.8], rtol=1e-11)
+    assert r.ratio[0] == pytest.approx(6.25, rel=1e-12)
+    assert np.allclose(r.S, sig[:g["k"]], rtol=1e-13)
+
+
+def test_schedule_shift_hand_trajectories():
+    """The schedule step on fabricated scalar trajectories: each guard
+    criterion fires alone, the guard never fires at pass 1, and once off it
+    stays off.  Values computed by hand."""
+    f = oracle.schedule_shift
+    # pass 1: no guard; 0.8 * 10 = 8 > 1
+    assert f(1, 5.0, 0.0, 3.0, 0.0, 10.0, 1.0, 0.8, False) == (8.0, False)
+    # pass 2, ratio down and E_{k+1} up: schedule kept, 0.7 * 12 = 8.4
+    assert f(2, 0.5, 5.0, 3.5, 3.0, 12.0, 8.0, 0.7, False) == (pytest.approx(8.4), False)
+    # candidate below the shift: the shift never decreases
+    assert f(2, 0.5, 5.0, 3.5, 3.0, 12.0, 9.0, 0.7, False) == (9.0, False)
+    # ratio grows: guard fires, 0.5 * 20 = 10
+    assert f(3, 0.6, 0.5, 3.6, 3.5, 20.0, 8.4, 0.9, False) == (10.0, True)
+    # E_{k+1} shrinks alone: guard fires, 0.5 * 20 = 10
+    assert f(3, 0.4, 0.5, 3.4, 3.5, 20.0, 8.4, 0.9, False) == (10.0, True)
+    # once off it stays off even when both criteria are fine
+    assert f(4, 0.1, 0.4, 3.7, 3.4, 30.0, 10.0, 0.9, True) == (15.0, True)
+    # equal values do not fire the guard (strict comparisons)
+    assert f(3, 0.5, 0.5, 3.5, 3.5, 20.0, 8.4, 0.9, False) == (18.0, False)
+
+
+def test_mlp_reference_forward_hand_values():
+    """The MLP reference's forward pass on weights chosen so every layer can
+    be done by hand (D = 2, H = 2): W1 = [[1, -1], [2, 0]], b1 = [0, -1],
+    W2 = I, b2 = [0.5, 0], W3 = [[1, 1], [0, 2]], b3 = [0, 0.25].  For
+    x = (3, 1): h1 = relu(2, 5) = (2, 5); h2 = (2.5, 5); o = (7.5, 10.25).
+    For x = (0, 1): h1 = relu(-1, -1) = 0; h2 = (0.5, 0); o = (0.5, 0.25)."""
+    from oracle import mlp_ref
+    P = np.array([1, -1, 2, 0, 0, -1, 1, 0, 0, 1, 0.5, 0, 1, 1, 0, 2, 0, 0.25], dtype=float)
+    X = np.array([[3.0, 1.0], [0.0, 1.0]])
+    o = mlp_ref.forward(P, X, 2, 2)[2]
+    assert np.array_equal(o, [[7.5, 10.25], [0.5, 0.25]])
+    c = mlp_ref.outputs(P, X, 2, 2, 0.9)[:, 0]
+    assert np.allclose(c, 0.5 + 0.4 / (1 + np.exp(-np.array([7.5, 0.5]))), rtol=1e-15)
