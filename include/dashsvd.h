@@ -313,9 +313,34 @@ dashsvd_status dashsvd_mlp_train_step(dashsvd_handle *h, const float *X, const f
  * the LEARNED policy forms them; n = 3 l + 3. */
 dashsvd_status dashsvd_learned_features(dashsvd_handle *h, float *feat, int32_t n);
 
-/* Device bytes a run with these arguments needs (workspace of the handle). */
+/* Device bytes a run with these arguments needs (workspace of the handle),
+ * under the default options with the given precision.  Host only: no HIP
+ * call is made. */
 dashsvd_status dashsvd_workspace_size(const dashsvd_csr *A, int32_t k, int32_t p,
                                       int32_t precision, size_t *bytes);
+/* The same for dashsvd_run_batched over the count matrices As. */
+dashsvd_status dashsvd_workspace_size_batched(const dashsvd_csr *As, int32_t count, int32_t k,
+                                              int32_t p, int32_t precision, size_t *bytes);
+/* The same under the options of handle h (its precision, degree order,
+ * caller Omega, schedule, tuning database ...): batched = 0 sizes
+ * dashsvd_run on As[0], batched = 1 sizes dashsvd_run_batched on the count
+ * matrices.  Host only. */
+dashsvd_status dashsvd_handle_workspace_size(const dashsvd_handle *h, const dashsvd_csr *As,
+                                             int32_t count, int32_t batched, int32_t k, int32_t p,
+                                             size_t *bytes);
+
+/* Caller-owned workspace (for instance a torch allocation), used in place of
+ * the arena the handle would allocate itself: every device buffer of
+ * dashsvd_run, dashsvd_run_batched and dashsvd_evaluate is carved out of
+ * [dev_ptr, dev_ptr + bytes).  dev_ptr must be device memory of the current
+ * GPU, 256-byte aligned; it stays owned by the caller, who must keep it
+ * valid, and not use it, until the handle is destroyed or given another
+ * workspace.  A run that needs more than bytes (dashsvd_handle_workspace_size)
+ * fails with DASHSVD_ERR_OOM and allocates nothing.  dev_ptr = NULL returns
+ * the handle to its own arena, allocated on the next run.  The call waits
+ * for the handle's queued work and discards the results of earlier runs,
+ * which lived in the old workspace. */
+dashsvd_status dashsvd_set_workspace(dashsvd_handle *h, void *dev_ptr, size_t bytes);
 
 const char *dashsvd_status_string(dashsvd_status s);
 /* Detail of the last error on this handle (or of the last failed create when

@@ -86,6 +86,7 @@ struct dashsvd_handle {
   std::string err;
   hipStream_t st = nullptr;
   Arena ar;
+  bool ar_external = false;  // the arena is a caller buffer (dashsvd_set_workspace)
   // results of the last run (device pointers into the arena)
   bool have = false;
   int64_t m = 0, n = 0;
@@ -231,6 +232,9 @@ double now_ms() {
 
 dashsvd_status ensure_arena(dashsvd_handle *h, size_t bytes) {
   if (bytes <= h->ar.cap) return DASHSVD_OK;
+  if (h->ar_external)
+    return fail(h, DASHSVD_ERR_OOM, "the caller's workspace holds " + std::to_string(h->ar.cap) +
+                                        " bytes; this run needs " + std::to_string(bytes));
   if (h->ar.base) {
     (void)hipStreamSynchronize(h->st);
     if (h->st2) (void)hipStreamSynchronize(h->st2);
@@ -393,7 +397,8 @@ void dashsvd_destroy(dashsvd_handle *h) {
   if (h->ar.base) {
     (void)hipStreamSynchronize(h->st);
     if (h->st2) (void)hipStreamSynchronize(h->st2);
-    (void)hipFree(h->ar.base);
+    if (h->stg) (void)hipStreamSynchronize(h->stg);
+    if (!h->ar_external) (void)hipFree(h->ar.base);
   }
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   if (h->ev_gram) (void)hipEventDestroy(h->ev_gram);
@@ -411,6 +416,29 @@ void dashsvd_destroy(dashsvd_handle *h) {
   if (h->mlp.P) (void)hipFree(h->mlp.P);
   if (h->mlp.buf) (void)hipFree(h->mlp.buf);
   delete h;
+}
+
+dashsvd_status dashsvd_set_workspace(dashsvd_handle *h, void *dev_ptr, size_t bytes) {
+  if (!h) return DASHSVD_ERR_INVALID_ARG;
+  h->err.clear();
+  if (dev_ptr && ((uintptr_t)dev_ptr & 255))
+    return fail(h, DASHSVD_ERR_INVALID_ARG, "workspace must start on a 256-byte boundary");
+  if (dev_ptr && bytes == 0) return fail(h, DASHSVD_ERR_INVALID_ARG, "workspace of 0 bytes");
+  // work still queued may use the current arena
+  if (h->ar.base) {
+    (void)hipStreamSynchronize(h->st);
+    if (h->st2) (void)hipStreamSynchronize(h->st2);
+    if (h->stg) (void)hipStreamSynchronize(h->stg);
+    if (!h->ar_external) (void)hipFree(h->ar.base);
+  }
+  h->ar.base = (char *)dev_ptr;
+  h->ar.cap = dev_ptr ? bytes : 0;
+  h->ar_external = dev_ptr != nullptr;
+  // results and evaluation buffers of earlier runs lived in the old arena
+  h->have = false;
+  h->bat.have = false;
+  h->ev_ctx.ok = false;
+  return DASHSVD_OK;
 }
 
 // SpMM chunk length of a run: the option, else the tuned value of the
@@ -1141,6 +1169,39 @@ dashsvd_status dashsvd_workspace_size(const dashsvd_csr *A, int32_t k, int32_t p
   return run_impl(&tmp, A, k, p, 0.0, true, bytes);
 }
 
+static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As, int32_t count, int32_t k,
+                                       int32_t p, double tol, bool measure_only, size_t *measured);
+static dashsvd_status check_batch(dashsvd_handle *h, const dashsvd_csr *As, int32_t count, int32_t k, int32_t p,
+                                  double tol);
+
+dashsvd_status dashsvd_workspace_size_batched(const dashsvd_csr *As, int32_t count, int32_t k, int32_t p,
+                                              int32_t precision, size_t *bytes) {
+  if (!bytes) return DASHSVD_ERR_INVALID_ARG;
+  dashsvd_handle tmp;
+  dashsvd_options o;
+  default_options(&o);
+  o.precision = precision;
+  dashsvd_status s = dashsvd_set_options(&tmp, &o);
+  if (s == DASHSVD_OK) s = check_batch(&tmp, As, count, k, p, 0.0);
+  if (s != DASHSVD_OK) return s;
+  return run_batched_impl(&tmp, As, count, k, p, 0.0, true, bytes);
+}
+
+dashsvd_status dashsvd_handle_workspace_size(const dashsvd_handle *h, const dashsvd_csr *As, int32_t count,
+                                             int32_t batched, int32_t k, int32_t p, size_t *bytes) {
+  if (!h || !bytes) return DASHSVD_ERR_INVALID_ARG;
+  // the sizing pass reads only the options, the schedule and the tuning
+  // table, so it runs on a copy that owns no HIP resources
+  dashsvd_handle tmp;
+  tmp.opt = h->opt;
+  tmp.sched = h->sched;
+  tmp.tune = h->tune;
+  dashsvd_status s = batched ? check_batch(&tmp, As, count, k, p, 0.0) : check_args(&tmp, As, k, p, 0.0);
+  if (s != DASHSVD_OK) return s;
+  return batched ? run_batched_impl(&tmp, As, count, k, p, 0.0, true, bytes)
+                 : run_impl(&tmp, As, k, p, 0.0, true, bytes);
+}
+
 dashsvd_status dashsvd_get_USV(dashsvd_handle *h, void *U, int64_t ldu, double *S, void *V, int64_t ldv,
                                int32_t dtype, int32_t on_device) {
   if (!h) return DASHSVD_ERR_INVALID_ARG;
@@ -1594,10 +1655,10 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
   return s;
 }
 
-dashsvd_status dashsvd_run_batched(dashsvd_handle *h, const dashsvd_csr *As, int32_t count, int32_t k, int32_t p,
-                                   double tol) {
-  if (!h) return DASHSVD_ERR_INVALID_ARG;
-  h->err.clear();
+// Arguments of a batched run (as dashsvd_run for each matrix, plus the
+// batched form's own requirements).
+static dashsvd_status check_batch(dashsvd_handle *h, const dashsvd_csr *As, int32_t count, int32_t k, int32_t p,
+                                  double tol) {
   if (!As || count < 1) return fail(h, DASHSVD_ERR_INVALID_ARG, "empty batch");
   if (h->opt.shift_policy == DASHSVD_SHIFT_LEARNED)
     return fail(h, DASHSVD_ERR_INVALID_ARG, "the batched form takes the PAPER, NONE, FIXED or SCHEDULE policy");
@@ -1614,6 +1675,17 @@ dashsvd_status dashsvd_run_batched(dashsvd_handle *h, const dashsvd_csr *As, int
       return fail(h, DASHSVD_ERR_INVALID_ARG, "batched form: mixed value types or memory spaces");
   }
   if (k + p > kBMaxL) return fail(h, DASHSVD_ERR_INVALID_ARG, "batched form: k + oversampling exceeds 64");
+  return DASHSVD_OK;
+}
+
+dashsvd_status dashsvd_run_batched(dashsvd_handle *h, const dashsvd_csr *As, int32_t count, int32_t k, int32_t p,
+                                   double tol) {
+  if (!h) return DASHSVD_ERR_INVALID_ARG;
+  h->err.clear();
+  {
+    dashsvd_status s = check_batch(h, As, count, k, p, tol);
+    if (s != DASHSVD_OK) return s;
+  }
   if (!h->stg) {
     HIPCHK(hipStreamCreateWithFlags(&h->stg, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&h->ev_b0, hipEventDisableTiming));

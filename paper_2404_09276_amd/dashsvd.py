@@ -77,6 +77,7 @@ EXPORTS = [
     "dashsvd_get_USV_batched", "dashsvd_get_info_batched", "dashsvd_autotune", "dashsvd_mlp_init",
     "dashsvd_mlp_num_params", "dashsvd_mlp_set_params", "dashsvd_mlp_get_params", "dashsvd_mlp_forward",
     "dashsvd_mlp_grad", "dashsvd_mlp_train_step", "dashsvd_learned_features", "dashsvd_workspace_size",
+    "dashsvd_workspace_size_batched", "dashsvd_handle_workspace_size", "dashsvd_set_workspace",
     "dashsvd_status_string",
     "dashsvd_last_error", "dashsvd_k_gaussian", "dashsvd_k_philox_raw", "dashsvd_k_transpose",
     "dashsvd_k_spmm", "dashsvd_k_gram", "dashsvd_k_eig", "dashsvd_k_eig_prof", "dashsvd_k_cholqr", "dashsvd_k_rescale",
@@ -114,6 +115,11 @@ def lib():
         L.dashsvd_mlp_train_step.argtypes = [P, P, P, i32, C.c_float, P]
         L.dashsvd_learned_features.argtypes = [P, P, i32]
         L.dashsvd_workspace_size.argtypes = [C.POINTER(_Csr), i32, i32, i32, C.POINTER(C.c_size_t)]
+        L.dashsvd_workspace_size_batched.argtypes = [C.POINTER(_Csr), i32, i32, i32, i32,
+                                                     C.POINTER(C.c_size_t)]
+        L.dashsvd_handle_workspace_size.argtypes = [P, C.POINTER(_Csr), i32, i32, i32, i32,
+                                                    C.POINTER(C.c_size_t)]
+        L.dashsvd_set_workspace.argtypes = [P, P, C.c_size_t]
         L.dashsvd_status_string.argtypes = [i32]
         L.dashsvd_status_string.restype = C.c_char_p
         L.dashsvd_last_error.argtypes = [P]
@@ -253,6 +259,39 @@ class DashSVD:
                         _ptr(sched_arr).value if sched_arr is not None else None,
                         om_ptr, om_dt, om_dev, TIMING[timing],
                         tuning_db.encode() if tuning_db else None, EIG[eig_method], REORDER[reorder])
+
+    def set_workspace(self, buf):
+        """dashsvd_set_workspace: run inside the caller's device buffer (a
+        torch tensor on the GPU, e.g. torch.empty(n, dtype=torch.uint8,
+        device="cuda")), or back in the handle's own arena with None.  The
+        tensor is kept referenced while the handle uses it."""
+        if buf is None:
+            _check(lib().dashsvd_set_workspace(self._h, None, 0), self._h)
+            self._ws = None
+            return
+        if not _on_device(buf):
+            raise ValueError("the workspace must be a device tensor")
+        nbytes = buf.numel() * buf.element_size()
+        _check(lib().dashsvd_set_workspace(self._h, C.c_void_p(buf.data_ptr()), nbytes), self._h)
+        self._ws = buf
+
+    def workspace_bytes(self, A, k: int, p: int) -> int:
+        """dashsvd_handle_workspace_size under this handle's options: A is one
+        matrix (dashsvd_run) or a list of matrices (dashsvd_run_batched)."""
+        batched = isinstance(A, (list, tuple))
+        mats = A if batched else [A]
+        structs, keeps = [], []
+        for M in mats:
+            sct, keep = make_csr(M.m, M.n, M.row_ptr, M.col, M.val)
+            structs.append(sct)
+            keeps.append(keep)
+        arr = (_Csr * len(structs))(*structs)
+        out = C.c_size_t()
+        st = lib().dashsvd_handle_workspace_size(self._h, arr, len(structs), int(batched), k, p,
+                                                 C.byref(out))
+        del keeps
+        _check(st, self._h)
+        return int(out.value)
 
     def set_options(self, **kw):
         opt = self._options(**kw)
@@ -517,3 +556,17 @@ def _info_from(raw) -> Info:
                 dict(zip(KT_NAMES, list(raw.kt_count))), raw.eig_calls, raw.eig_sweeps,
                 np.array(raw.sweeps_per_call[:min(raw.eig_calls, MAX_TRACE + 2)]),
                 bool(raw.promoted), raw.long_row_used, raw.learned_n, raw.cholqr_calls)
+
+
+def workspace_size_batched(mats, k: int, p: int, precision: str = "fp32") -> int:
+    structs, keeps = [], []
+    for A in mats:
+        sct, keep = make_csr(A.m, A.n, A.row_ptr, A.col, A.val)
+        structs.append(sct)
+        keeps.append(keep)
+    arr = (_Csr * len(structs))(*structs)
+    out = C.c_size_t()
+    st = lib().dashsvd_workspace_size_batched(arr, len(structs), k, p, PREC[precision], C.byref(out))
+    del keeps
+    _check(st)
+    return int(out.value)

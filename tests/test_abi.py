@@ -77,3 +77,63 @@ def test_binding_refuses_missing_library(tmp_path, monkeypatch):
     monkeypatch.setattr(d, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(RuntimeError):
         d.lib()
+
+
+def test_workspace_size_batched_host_only():
+    """The batched form's sizing pass (the layout its run carves out of the
+    workspace) runs host-only, grows with the batch, and rejects what the
+    batched form does not take."""
+    import synth
+    from paper_2404_09276_amd import dashsvd as d
+    mats = synth.batched_zipf(6, rows=(1000, 3000), seed=77)
+    w6 = d.workspace_size_batched(mats, 8, 4, "fp32")
+    w3 = d.workspace_size_batched(mats[:3], 8, 4, "fp32")
+    assert w6 > w3 > 0
+    assert d.workspace_size_batched(mats, 8, 4, "bf16") != w6
+    with pytest.raises(d.DashSVDError) as e:
+        d.workspace_size_batched(mats, 40, 30, "fp32")  # l above the batched limit
+    assert e.value.status == d.ERR_INVALID_ARG
+    wide = synth.uniform_csr(300, 700, 5000, seed=3)
+    with pytest.raises(d.DashSVDError):
+        d.workspace_size_batched(mats[:2] + [wide], 8, 4, "fp32")
+
+
+_LAYOUT_C = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "dashsvd.h"
+#define F(T, f) printf("%s.%s %zu %zu\n", #T, #f, offsetof(T, f), sizeof(((T *)0)->f));
+#define S(T) printf("%s %zu\n", #T, sizeof(T));
+int main(void) {
+  S(dashsvd_csr) S(dashsvd_options) S(dashsvd_info)
+  %FIELDS%
+  return 0;
+}
+"""
+
+
+def test_struct_layout_matches_header(tmp_path):
+    """The ctypes structures of the binding have the size and the field
+    offsets of the C structures in include/dashsvd.h, as gcc lays them out:
+    a field added, moved or resized on one side of the ABI only fails here
+    instead of corrupting a run."""
+    import ctypes as C
+    import subprocess
+    from paper_2404_09276_amd import dashsvd as d
+    structs = {"dashsvd_csr": d._Csr, "dashsvd_options": d._Options, "dashsvd_info": d._Info}
+    fields = "\n  ".join(f"F({cn}, {f[0]})" for cn, py in structs.items() for f in py._fields_)
+    src = tmp_path / "layout.c"
+    src.write_text(_LAYOUT_C.replace("%FIELDS%", fields))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    out = subprocess.check_output([str(exe)]).decode().split("\n")
+    got = {}
+    for line in out:
+        if line:
+            parts = line.split()
+            got[parts[0]] = tuple(int(x) for x in parts[1:])
+    for cn, py in structs.items():
+        assert got[cn] == (C.sizeof(py),), cn
+        for f in py._fields_:
+            desc = getattr(py, f[0])
+            assert got[f"{cn}.{f[0]}"] == (desc.offset, desc.size), (cn, f[0])

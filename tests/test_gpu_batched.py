@@ -100,13 +100,13 @@ def test_batched_fp32_matches_single_matrix_runs(torch_dev):
         assert np.abs(U.T @ U - np.eye(10)).max() < 1e-5
 
 
-@pytest.mark.parametrize("prec,bar", [("fp32", 1e-5), ("bf16", 2e-2)])
+@pytest.mark.parametrize("prec,bar", [("fp32", 1e-5), ("bf16", 5e-3)])
 def test_batched_members_match_oracle(torch_dev, prec, bar):
     """Every member of an FP32 or BF16 batch against the FP64 oracle on that
     matrix alone with the member's Omega stream (seed + i).  FP32: the same
     pass count as the oracle's tolerance run and sigma within 1e-5 relative.
     BF16 panels (8-bit significand, relative rounding 2^-9 on every panel
-    entry): sigma within 2e-2 relative of the oracle run for the member's own
+    entry): sigma within 5e-3 (2.5 x 2^-9) relative of the oracle run for the member's own
     pass count, and every member converged."""
     mats = _batch(np.float32) + synth.batched_zipf(6, rows=(1000, 6000), seed=5100)
     st, out, summary = _run(mats, 10, 6, 40, 1e-2, 500, prec)

@@ -378,3 +378,48 @@ def test_eig_methods_zipf_fp32(torch_dev):
         assert np.all(np.abs(S - ref.S) / ref.S <= 1e-5)
         passes[meth] = info.passes
     assert passes["auto"] == passes["jacobi"] == ref.passes
+
+
+def test_caller_workspace(torch_dev):
+    """dashsvd_set_workspace: a run inside a torch-allocated buffer of exactly
+    dashsvd_handle_workspace_size bytes gives bitwise the results of a run in
+    the handle's own arena (same layout, same kernels); a buffer one byte
+    short fails with ERR_OOM and leaves the handle usable; None returns the
+    handle to its own arena."""
+    torch = torch_dev
+    from paper_2404_09276_amd import DashSVD, DashSVDError
+    from paper_2404_09276_amd.dashsvd import ERR_OOM
+    A = synth.zipf_csr(20000, 9000, 400000, seed=41)
+    h0 = DashSVD(precision="fp32", p_max=5, seed=3)
+    U0, S0, V0, st0, info0 = h0.solve(A, 16, 8, 0.0)
+    h0.close()
+    h = DashSVD(precision="fp32", p_max=5, seed=3)
+    need = h.workspace_bytes(A, 16, 8)
+    buf = torch.empty(need, dtype=torch.uint8, device="cuda")
+    h.set_workspace(buf)
+    U1, S1, V1, st1, info1 = h.solve(A, 16, 8, 0.0)
+    assert np.array_equal(S0, S1) and np.array_equal(U0, U1) and np.array_equal(V0, V1)
+    small = torch.empty(need - 1, dtype=torch.uint8, device="cuda")
+    h.set_workspace(small)
+    with pytest.raises(DashSVDError) as e:
+        h.run(A, 16, 8, 0.0)
+    assert e.value.status == ERR_OOM
+    h.set_workspace(buf)
+    U2, S2, V2, st2, info2 = h.solve(A, 16, 8, 0.0)
+    assert np.array_equal(S0, S2)
+    h.set_workspace(None)
+    U3, S3, V3, st3, info3 = h.solve(A, 16, 8, 0.0)
+    assert np.array_equal(S0, S3)
+    # the batched form in a caller workspace
+    mats = synth.batched_zipf(4, rows=(1000, 3000), seed=78)
+    hb = DashSVD(precision="fp32", p_max=4, seed=9)
+    needb = hb.workspace_bytes(mats, 8, 4)
+    bufb = torch.empty(needb, dtype=torch.uint8, device="cuda")
+    hb.set_workspace(bufb)
+    assert hb.run_batched(mats, 8, 4, 0.0) == 0
+    Sb = hb.get_usv_batched(2)[1]
+    hb.close()
+    ref = oracle.dashsvd(mats[2].m, mats[2].n, mats[2].row_ptr, mats[2].col, mats[2].val, 8, 4, 4, 0.0,
+                         seed=11)
+    assert np.all(np.abs(Sb - ref.S) / ref.S <= 1e-5)
+    h.close()
