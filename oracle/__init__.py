@@ -24,7 +24,7 @@ _SRC = os.path.join(_HERE, "dashsvd_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 SHIFT_PAPER, SHIFT_NONE, SHIFT_FIXED, SHIFT_SCHEDULE = 0, 1, 2, 3
-PVE_R2, PVE_R1 = 0, 1
+PVE_R2, PVE_R1, PVE_NOSURR = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
@@ -69,6 +69,7 @@ def lib():
                                   P, P, P, P, P]
         L.orc_dashsvd.restype = C.c_int
         L.orc_metrics.argtypes = [i64, i64, P, P, P, i64, P, P, P, P, P]
+        L.orc_residual_metrics.argtypes = [i64, i64, P, P, P, i64, P, P, P, P, i64, u64, P, P, P, P]
         L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -248,6 +249,24 @@ def metrics(m: int, n: int, row_ptr, col, val, U, S, sigma_ref):
     lib().orc_metrics(m, n, _p(rp), _p(c), _p(v), k, _p(U), _p(S), _p(sr), C.byref(pve),
                       C.byref(es))
     return pve.value, es.value
+
+
+def residual_metrics(m: int, n: int, row_ptr, col, val, U, S, V, sigma_ref, steps: int = 200,
+                     seed: int = 7):
+    """eps_res and eps_spec of Sec. 4 (and ||A - U S V^T||_2 with the Lanczos
+    steps taken) against exact sigma_1..sigma_{k+1}."""
+    rp, c, v = _csr64(row_ptr, col, val)
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    sr = np.ascontiguousarray(sigma_ref, dtype=np.float64)
+    k = U.shape[1]
+    assert sr.shape[0] >= k + 1 and V.shape == (n, k) and U.shape == (m, k)
+    er, es, en = C.c_double(), C.c_double(), C.c_double()
+    st = C.c_int64()
+    lib().orc_residual_metrics(m, n, _p(rp), _p(c), _p(v), k, _p(U), _p(S), _p(V), _p(sr), steps, seed,
+                               C.byref(er), C.byref(es), C.byref(en), C.byref(st))
+    return er.value, es.value, en.value, st.value
 
 
 def num_threads() -> int:

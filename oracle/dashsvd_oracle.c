@@ -357,7 +357,7 @@ double orc_schedule_shift(int64_t j, double ratio, double prev_ratio, double ek1
 /* dashSVD, Alg. 5 (Alg. 4 when tol == 0). */
 
 enum { ORC_SHIFT_PAPER = 0, ORC_SHIFT_NONE = 1, ORC_SHIFT_FIXED = 2, ORC_SHIFT_SCHEDULE = 3 };
-enum { ORC_PVE_R2 = 0, ORC_PVE_R1 = 1 };
+enum { ORC_PVE_R2 = 0, ORC_PVE_R1 = 1, ORC_PVE_NOSURR = 2 };
 
 typedef struct {
   int32_t passes;      /* N_p: passes executed */
@@ -380,7 +380,15 @@ typedef struct {
  *          after the first pass, then frozen), SCHEDULE (after pass j the
  *          shift becomes max(alpha, sched[j] * (S_l + alpha)), with the
  *          guard described at the update; sched has p_max + 1 entries).
- *   pve_mode: R2 (default) or R1.
+ *   pve_mode: R2 (default) or R1 (readings of the surrogate check), or
+ *          NOSURR: the accuracy control without the surrogate that Sec. 4.3
+ *          (Table 3) compares against, checking eq. (18) on the computed
+ *          singular values themselves: after each pass the singular values
+ *          of B = A Q (eigSVD of B, Alg. 3) are formed, E_i = sigma_i(B)^2,
+ *          and the pass stops when max_{i<=k} |E'_i - E_i| / E_{k+1} <= tol,
+ *          E' being the previous pass's values (zeros before the first
+ *          pass, as S' in Alg. 5 step 2).  The shift rule still reads the S
+ *          of eigSVD(A^T A Q - alpha Q); the trace's ratio is this ratio.
  * Outputs: U (m x k), S (k), V (n x k), row-major, signs normalised so the
  * entry of largest magnitude in each V column is positive (lowest index on
  * ties).  Q_out (optional) receives the final orthonormal basis Q in the
@@ -422,6 +430,10 @@ int orc_dashsvd(int64_t m, int64_t n, const int64_t *row_ptr,
   double *Sv = (double *)malloc(sizeof(double) * (size_t)l);
   double *Sp = (double *)calloc((size_t)l, sizeof(double));
   double *Vl = (double *)malloc(sizeof(double) * (size_t)(l * l));
+  /* NOSURR: squared singular values of B = A Q, this pass and the last */
+  double *Eb = (double *)malloc(sizeof(double) * (size_t)l);
+  double *Ebp = (double *)calloc((size_t)l, sizeof(double));
+  double *Zb = (double *)malloc(sizeof(double) * (size_t)l);
   int deficient = 0;
 
   /* Step 2: Q = eigSVD(A^T Omega).U, alpha = alpha' = 0, S' = zeros(l). */
@@ -439,9 +451,20 @@ int orc_dashsvd(int64_t m, int64_t n, const int64_t *row_ptr,
     for (int64_t i = 0; i < M_n * l; ++i) Cb[i] -= alpha * Q[i];
     deficient |= orc_eigsvd(M_n, l, Cb, Q, Sv, Vl);
     passes = (int32_t)j;
-    /* Step 5: the PVE surrogate check. */
+    /* Step 5: the PVE surrogate check, or eq. (18) on sigma(A Q). */
     const double a_used = alpha;
-    const double ratio = orc_pve_ratio(k, Sv, Sp, a_used, alpha_prev);
+    double ratio;
+    if (pve_mode == ORC_PVE_NOSURR) {
+      double *Vb = (double *)malloc(sizeof(double) * (size_t)(l * l));
+      orc_csr_spmm(M_m, M_rp, M_c, M_v, Q, l, Y);
+      orc_eigsvd(M_m, l, Y, NULL, Zb, Vb);
+      free(Vb);
+      for (int64_t i = 0; i < l; ++i) Eb[i] = Zb[i] * Zb[i];
+      ratio = orc_pve_ratio(k, Eb, Ebp, 0.0, 0.0);
+      memcpy(Ebp, Eb, sizeof(double) * (size_t)l);
+    } else {
+      ratio = orc_pve_ratio(k, Sv, Sp, a_used, alpha_prev);
+    }
     if (info && j - 1 < info->trace_cap) {
       if (info->alpha_used) info->alpha_used[j - 1] = a_used;
       if (info->ratio) info->ratio[j - 1] = ratio;
@@ -509,7 +532,7 @@ int orc_dashsvd(int64_t m, int64_t n, const int64_t *row_ptr,
     info->final_alpha = alpha;
   }
   free(rT); free(cT); free(vT); free(Om); free(Q); free(Y); free(Cb);
-  free(Sv); free(Sp); free(Vl); free(Ub); free(Vk);
+  free(Sv); free(Sp); free(Vl); free(Ub); free(Vk); free(Eb); free(Ebp); free(Zb);
   if (tol > 0.0 && !converged) return 1;
   return 0;
 }
@@ -541,6 +564,145 @@ void orc_metrics(int64_t m, int64_t n, const int64_t *row_ptr,
   free(Z);
   *eps_pve = pve;
   *eps_sigma = es;
+}
+
+/* The other two error metrics of Sec. 4, for a computed triplet (U m x k,
+ * S k, V n x k, row-major) against the exact sigma_1..sigma_{k+1}:
+ *   eps_res  = max_{i<=k} ||A^T u_i - s_i v_i||_2 / sigma_i,
+ *   eps_spec = (||A - U diag(S) V^T||_2 - sigma_{k+1}) / sigma_{k+1}
+ * (||A - A_k||_2 = sigma_{k+1}).  The spectral norm of E = A - U S V^T is
+ * the square root of the largest eigenvalue of E^T E, estimated by the
+ * Lanczos process with full reorthogonalisation (Golub & Van Loan,
+ * Sec. 10.1; every new vector is orthogonalised twice against all earlier
+ * ones) started from a Gaussian vector of the Philox stream keyed by
+ * `seed`.  The largest eigenvalue of the tridiagonal T_j (by orc_jacobi_eig)
+ * is a lower bound of ||E||_2^2 that does not decrease with j; the process
+ * stops after `steps` steps (at most n), at an invariant subspace, or once
+ * the estimate has changed by at most 1e-14 relative over 5 steps.  Outputs
+ * the two metrics, ||E||_2 and the steps taken. */
+static void orc_apply_ete(int64_t m, int64_t n, const int64_t *rp, const int32_t *c,
+                          const double *v, const int64_t *rpT, const int32_t *cT,
+                          const double *vT, int64_t k, const double *U, const double *S,
+                          const double *V, const double *x, double *y, double *z,
+                          double *tk) {
+  /* y = A x - U (S .* (V^T x)) */
+  orc_csr_spmm(m, rp, c, v, x, 1, y);
+  for (int64_t i = 0; i < k; ++i) {
+    double d = 0.0;
+    for (int64_t r = 0; r < n; ++r) d += V[r * k + i] * x[r];
+    tk[i] = S[i] * d;
+  }
+  for (int64_t r = 0; r < m; ++r) {
+    double d = 0.0;
+    for (int64_t i = 0; i < k; ++i) d += U[r * k + i] * tk[i];
+    y[r] -= d;
+  }
+  /* z = A^T y - V (S .* (U^T y)) */
+  orc_csr_spmm(n, rpT, cT, vT, y, 1, z);
+  for (int64_t i = 0; i < k; ++i) {
+    double d = 0.0;
+    for (int64_t r = 0; r < m; ++r) d += U[r * k + i] * y[r];
+    tk[i] = S[i] * d;
+  }
+  for (int64_t r = 0; r < n; ++r) {
+    double d = 0.0;
+    for (int64_t i = 0; i < k; ++i) d += V[r * k + i] * tk[i];
+    z[r] -= d;
+  }
+}
+
+static double orc_tridiag_max_eig(int64_t j, const double *al, const double *be) {
+  double *T = (double *)calloc((size_t)(j * j), sizeof(double));
+  double *ev = (double *)malloc(sizeof(double) * (size_t)j);
+  double *Vt = (double *)malloc(sizeof(double) * (size_t)(j * j));
+  for (int64_t i = 0; i < j; ++i) {
+    T[i * j + i] = al[i];
+    if (i + 1 < j) T[i * j + i + 1] = T[(i + 1) * j + i] = be[i];
+  }
+  orc_jacobi_eig(j, T, ev, Vt);
+  const double lam = ev[j - 1];
+  free(T); free(ev); free(Vt);
+  return lam;
+}
+
+void orc_residual_metrics(int64_t m, int64_t n, const int64_t *row_ptr,
+                          const int32_t *col, const double *val, int64_t k,
+                          const double *U, const double *S, const double *V,
+                          const double *sigma_ref, int64_t steps, uint64_t seed,
+                          double *eps_res, double *eps_spec, double *enorm,
+                          int64_t *steps_taken) {
+  const int64_t nnz = row_ptr[m];
+  int64_t *rT = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+  int32_t *cT = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+  double *vT = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+  orc_csr_transpose(m, n, row_ptr, col, val, rT, cT, vT);
+  /* eps_res: Z = A^T U (n x k), then the column norms of Z - V diag(S) */
+  double *Z = (double *)malloc(sizeof(double) * (size_t)(n * k));
+  orc_csr_spmm(n, rT, cT, vT, U, k, Z);
+  double res = 0.0;
+  for (int64_t i = 0; i < k; ++i) {
+    double s2 = 0.0;
+    for (int64_t r = 0; r < n; ++r) {
+      const double d = Z[r * k + i] - S[i] * V[r * k + i];
+      s2 += d * d;
+    }
+    const double e = sqrt(s2) / sigma_ref[i];
+    if (e > res || e != e) res = e;
+  }
+  free(Z);
+  /* ||E||_2 by Lanczos on E^T E */
+  if (steps > n) steps = n;
+  if (steps < 1) steps = 1;
+  double *Qv = (double *)malloc(sizeof(double) * (size_t)((steps + 1) * n));
+  double *al = (double *)malloc(sizeof(double) * (size_t)steps);
+  double *be = (double *)malloc(sizeof(double) * (size_t)steps);
+  double *y = (double *)malloc(sizeof(double) * (size_t)m);
+  double *w = (double *)malloc(sizeof(double) * (size_t)n);
+  double *tk = (double *)malloc(sizeof(double) * (size_t)(k > 0 ? k : 1));
+  orc_gaussian(seed, n, 1, Qv);
+  double nrm = 0.0;
+  for (int64_t r = 0; r < n; ++r) nrm += Qv[r] * Qv[r];
+  nrm = sqrt(nrm);
+  for (int64_t r = 0; r < n; ++r) Qv[r] /= nrm;
+  double lam = 0.0, lam_old = -1.0;
+  int64_t j = 0;
+  for (; j < steps; ++j) {
+    const double *q = Qv + j * n;
+    orc_apply_ete(m, n, row_ptr, col, val, rT, cT, vT, k, U, S, V, q, y, w, tk);
+    double a = 0.0;
+    for (int64_t r = 0; r < n; ++r) a += q[r] * w[r];
+    al[j] = a;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int64_t i = 0; i <= j; ++i) {
+        const double *qi = Qv + i * n;
+        double d = 0.0;
+        for (int64_t r = 0; r < n; ++r) d += qi[r] * w[r];
+        for (int64_t r = 0; r < n; ++r) w[r] -= d * qi[r];
+      }
+    }
+    double b = 0.0;
+    for (int64_t r = 0; r < n; ++r) b += w[r] * w[r];
+    b = sqrt(b);
+    be[j] = b;
+    const int last = j + 1 == steps || !(b > 1e-14 * fabs(a));
+    if (last || (j + 1) % 5 == 0) {
+      lam = orc_tridiag_max_eig(j + 1, al, be);
+      if (last || fabs(lam - lam_old) <= 1e-14 * lam) {
+        ++j;
+        break;
+      }
+      lam_old = lam;
+    }
+    double *qn = Qv + (j + 1) * n;
+    for (int64_t r = 0; r < n; ++r) qn[r] = w[r] / b;
+  }
+  const double en = sqrt(lam > 0.0 ? lam : 0.0);
+  *eps_res = res;
+  *enorm = en;
+  *eps_spec = (en - sigma_ref[k]) / sigma_ref[k];
+  *steps_taken = j;
+  free(Qv); free(al); free(be); free(y); free(w); free(tk);
+  free(rT); free(cT); free(vT);
 }
 
 int orc_num_threads(void) {

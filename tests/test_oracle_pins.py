@@ -607,3 +607,154 @@ def test_mlp_reference_forward_hand_values():
     assert np.array_equal(o, [[7.5, 10.25], [0.5, 0.25]])
     c = mlp_ref.outputs(P, X, 2, 2, 0.9)[:, 0]
     assert np.allclose(c, 0.5 + 0.4 / (1 + np.exp(-np.array([7.5, 0.5]))), rtol=1e-15)
+
+
+# ------------------------------------------------------------------ control without the surrogate
+
+def test_nosurr_lapack_mirror():
+    """Accuracy control without the surrogate (Sec. 4.3, Table 3): after
+    each pass the singular values of B = A Q are computed and eq. (18) is
+    checked on their squares, E' starting at zero.  A NumPy mirror that takes
+    sigma(B) from LAPACK's SVD of B itself (not from the eig of its Gram)
+    must give the same per-pass ratios, stopping pass and final sigma.  A
+    ratio on sigma instead of sigma^2, on the surrogate S + alpha, with
+    E_k in place of E_{k+1} in the denominator, or with B formed from the
+    Q before the pass instead of after it, fails here."""
+    A = synth.uniform_csr(300, 200, 6000, seed=77, dtype=np.float64)
+    D = A.to_dense()
+    k, s, tol = 8, 4, 1e-3
+    l = k + s
+    om = oracle.gaussian(55, A.m, l)
+    r = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, k, s, 30, tol, omega=om,
+                       pve_mode=oracle.PVE_NOSURR)
+
+    def eig_svd(Cm):
+        w, V = np.linalg.eigh(Cm.T @ Cm)
+        w, V = np.maximum(w[::-1], 0.0), V[:, ::-1]
+        Sv = np.sqrt(w)
+        return Cm @ V / Sv, Sv
+
+    Q, _ = eig_svd(D.T @ om)
+    alpha, Ep, ratios = 0.0, np.zeros(l), []
+    for j in range(1, 31):
+        Q, S = eig_svd(D.T @ (D @ Q) - alpha * Q)
+        E = np.linalg.svd(D @ Q, compute_uv=False) ** 2
+        ratio = np.max(np.abs(Ep[:k] - E[:k])) / E[k]
+        ratios.append(ratio)
+        assert r.alpha[j - 1] == pytest.approx(alpha, rel=1e-10, abs=1e-14)
+        if ratio <= tol:
+            break
+        Ep = E
+        if S[-1] > alpha:
+            alpha = (S[-1] + alpha) / 2
+    assert r.converged and r.passes == len(ratios) >= 3
+    assert np.allclose(r.ratio, ratios, rtol=1e-7, atol=1e-15)
+    assert min(abs(np.log(np.array(ratios) / tol))) > 0.05  # no borderline pass
+    sb = np.linalg.svd(D @ Q, compute_uv=False)
+    assert np.allclose(r.S, sb[:k], rtol=1e-11)
+
+
+def test_nosurr_rank_l_closed_form():
+    """rank(A) = l: the sketch already spans the row space, so sigma(A Q) =
+    sigma(A) from the first pass on.  The first check compares with E' = 0:
+    ratio_1 = sigma_1^2 / sigma_{k+1}^2 exactly; the second finds no change
+    (ratio_2 ~ 0) and stops, N_p = 2 at any tol."""
+    g = json.load(open(os.path.join(GOLDEN, "rank_l_shift_sequence.json")))
+    A, D, sig = _rank_l_matrix(g)
+    k, s = g["k"], g["s"]
+    for tol in (1e-2, 1e-8):
+        r = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, k, s, 10, tol, seed=4,
+                           pve_mode=oracle.PVE_NOSURR)
+        assert r.passes == 2 and r.converged
+        assert r.ratio[0] == pytest.approx(sig[0] ** 2 / sig[k] ** 2, rel=1e-12)
+        assert r.ratio[1] <= 1e-11
+        assert np.allclose(r.S, sig[:k], rtol=1e-13)
+
+
+def test_nosurr_stops_at_or_one_before_the_surrogate():
+    """Table 3's observation: without the surrogate, N_p is the same or one
+    smaller (the surrogate lags sigma(A Q)^2 by about a pass, Prop. 3).
+    Checked on the 2000 x 1500 workload and a power-law matrix at three
+    tolerances."""
+    cases = [(synth.config_small(np.float64), 20, 10, 2001),
+             (synth.zipf_csr(20000, 12000, 400000, seed=21), 50, 25, 3)]
+    for A, k, s, seed in cases:
+        for tol in (1e-1, 1e-2, 1e-3):
+            r2 = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, k, s, 30, tol, seed=seed)
+            rn = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, k, s, 30, tol, seed=seed,
+                                pve_mode=oracle.PVE_NOSURR)
+            assert r2.converged and rn.converged
+            assert r2.passes - 1 <= rn.passes <= r2.passes, (tol, r2.passes, rn.passes)
+
+
+# ------------------------------------------------------------------ residual and spectral metrics
+
+def test_residual_metrics_hand_diagonal():
+    """A = diag(5, 4, 3, 2, 1) padded to 7 x 5, k = 2, v_1 = e_1, v_2 = e_2,
+    u_1 = e_1 rotated by theta towards e_4, u_2 = e_2, s = (4.9, 4):
+      A^T u_1 - s_1 v_1 = (5 cos - 4.9) e_1 + 2 sin e_4, so
+      eps_res = sqrt((5 cos - 4.9)^2 + 4 sin^2) / 5;
+    with theta = 0 the rank-2 part is exact but for s_1: E = diag(0.1, 0, 3,
+    2, 1) and ||E||_2 = 3 = sigma_3, eps_spec = 0.  Catches a residual
+    divided by s_i instead of sigma_i, A u in place of A^T u, and a norm
+    of the wrong residual."""
+    sig = np.array([5.0, 4.0, 3.0, 2.0, 1.0])
+    D = np.zeros((7, 5))
+    for i in range(5):
+        D[i, i] = sig[i]
+    A = synth.dense_to_csr(D)
+    V = np.zeros((5, 2))
+    V[0, 0] = V[1, 1] = 1.0
+    S = np.array([4.9, 4.0])
+    for th in (0.0, 0.3):
+        U = np.zeros((7, 2))
+        U[0, 0], U[3, 0] = math.cos(th), math.sin(th)
+        U[1, 1] = 1.0
+        er, es, en, _ = oracle.residual_metrics(7, 5, A.row_ptr, A.col, A.val, U, S, V, sig)
+        assert er == pytest.approx(math.sqrt((5 * math.cos(th) - 4.9) ** 2 + 4 * math.sin(th) ** 2) / 5.0,
+                                   rel=1e-13)
+        E = D - (U * S) @ V.T
+        assert en == pytest.approx(np.linalg.norm(E, 2), rel=1e-12)
+        if th == 0.0:
+            assert en == pytest.approx(3.0, rel=1e-14) and abs(es) <= 1e-14
+
+
+@pytest.mark.parametrize("shape", [(60, 45), (45, 60), (300, 200)])
+def test_residual_metrics_match_dense_numpy(shape):
+    """Both metrics against a direct dense computation: ||A^T u_i - s_i v_i||
+    from dense products, ||A - U S V^T||_2 from LAPACK's SVD of the dense
+    residual, sigma from LAPACK."""
+    m, n = shape
+    A, D = _csr_small(seed=m + n, m=m, n=n, density=0.3)
+    Uf, sv, Vt = np.linalg.svd(D)
+    k = 6
+    rng = np.random.default_rng(92)
+    U, _ = np.linalg.qr(Uf[:, :k] + 1e-3 * rng.standard_normal((m, k)))
+    V, _ = np.linalg.qr(Vt[:k].T + 1e-3 * rng.standard_normal((n, k)))
+    S = sv[:k] * (1 - 1e-4 * rng.random(k))
+    er, es, en, steps = oracle.residual_metrics(m, n, A.row_ptr, A.col, A.val, U, S, V, sv)
+    res = np.linalg.norm(D.T @ U - V * S, axis=0) / sv[:k]
+    assert er == pytest.approx(res.max(), rel=1e-10)
+    ref = np.linalg.norm(D - (U * S) @ V.T, 2)
+    assert en == pytest.approx(ref, rel=1e-11)
+    assert es == pytest.approx((ref - sv[k]) / sv[k], rel=1e-8, abs=1e-12)
+    assert es > 0 and steps <= min(m, n)
+
+
+def test_spectral_norm_lanczos_clustered_spectrum():
+    """Lanczos on E^T E when the top of the residual's spectrum is a tight
+    cluster (sigma_{k+1} and sigma_{k+2} 1e-6 apart): the estimate is a
+    lower bound and reaches ||E||_2 to 1e-12 within the step budget."""
+    rng = np.random.default_rng(31)
+    m, n = 120, 90
+    sig = np.concatenate([[9.0, 8.0, 7.0], [3.0, 3.0 - 3e-6], np.linspace(2.5, 0.1, n - 5)])
+    Uo, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    Vo, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    D = (Uo * sig) @ Vo.T
+    A = synth.dense_to_csr(D)
+    k = 3
+    er, es, en, steps = oracle.residual_metrics(m, n, A.row_ptr, A.col, A.val, Uo[:, :k], sig[:k],
+                                                Vo[:, :k], sig, steps=90)
+    assert en <= 3.0 * (1 + 1e-13)
+    assert en == pytest.approx(3.0, rel=1e-12)
+    assert abs(es) <= 1e-12 and er <= 1e-13
