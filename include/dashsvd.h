@@ -387,6 +387,28 @@ dashsvd_status dashsvd_k_spmm(int64_t rows, int64_t cols, int64_t nnz, const int
                               const void *Q, int64_t ldq, const double *alpha, int32_t long_row,
                               void *stream);
 
+/* dashsvd_k_spmm without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture that builds around it, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, kernels
+ * and results (bit for bit) as dashsvd_k_spmm; the row-split plan and the
+ * partial rows of long-row chunks live in a static device array of 32 MiB
+ * (33554432 bytes) that each device holds until the process ends.  The plan
+ * takes about 16 bytes per row plus, for each of the 2 * nnz / long_row + 1
+ * chunks it may hold, 16 + ld * 4 bytes (ld * 8 with F64 panels; ld = l
+ * rounded up to 8) and 24 bytes per nnz / long_row + 1 long rows.  A call
+ * whose plan needs more than the array fails with DASHSVD_ERR_INVALID_ARG and
+ * a message giving the size, before any work is queued; a larger long_row
+ * needs less.  All calls on one device share the array, which keeps the last
+ * call's contents: calls that overlap on one device (several host threads or
+ * streams) race and give wrong results.  Each call synchronises the stream
+ * before returning, so calls made one after another from one thread are
+ * safe. */
+dashsvd_status dashsvd_k_spmm_static(int64_t rows, int64_t cols, int64_t nnz, const int64_t *row_ptr,
+                                     const int32_t *col, const void *val, const void *X, int64_t ldx,
+                                     int32_t xdtype, void *Y, int64_t ldy, int32_t ydtype, int32_t l,
+                                     const void *Q, int64_t ldq, const double *alpha, int32_t long_row,
+                                     void *stream);
+
 /* G (l x l, FP64, row-major, full symmetric) = C^T C for C r x l (ldc),
  * C dtype F32 or F64; FP64 accumulation (Alg. 3 step 1). */
 dashsvd_status dashsvd_k_gram(int64_t r, int32_t l, const void *C, int64_t ldc, int32_t cdtype,

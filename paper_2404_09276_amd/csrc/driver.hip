@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -2094,45 +2095,164 @@ dashsvd_status dashsvd_k_transpose(int64_t m, int64_t n, int64_t nnz, const int6
   return DASHSVD_OK;
 }
 
+}  // extern "C"
+
+// Scratch of dashsvd_k_spmm_static (32 MiB per device; see below).
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+namespace {
+
+// Plan and product of the kernel-level SpMM entries over a workspace at
+// `base` (measured by spmm_ws_bytes): the row-split plan, a host read of its
+// two sizes, then the product.  Synchronises the stream before returning.
+struct SpmmCall {
+  int64_t rows, cols, nnz;
+  const int64_t *row_ptr;
+  const int32_t *col;
+  const void *val;
+  const void *X;
+  int64_t ldx;
+  int32_t xdtype;
+  void *Y;
+  int64_t ldy;
+  int32_t ydtype;
+  int32_t l;
+  const void *Q;
+  int64_t ldq;
+  const double *alpha;
+  int32_t long_row;
+  hipStream_t st;
+};
+
+dashsvd_status spmm_call_check(const SpmmCall &c) {
+  dashsvd_handle *h = nullptr;
+  const int ld = (int)round_up(c.l, 8);
+  if (c.rows < 1 || c.l < 1 || c.l > DASHSVD_MAX_L || c.ldx % 8 || c.ldy % 8 || c.ldx < ld || c.ldy < ld ||
+      (c.alpha && (!c.Q || c.ldq % 8 || c.ldq < ld)))
+    return fail(h, DASHSVD_ERR_INVALID_ARG, "spmm arguments (leading dimensions must be multiples of 8 >= l)");
+  return DASHSVD_OK;
+}
+
+// Lays the plan out in `a` (a measuring arena takes no memory).
+void spmm_layout(const SpmmCall &c, Arena &a, Plan &pl, int64_t **scan_tmp) {
+  const int ld = (int)round_up(c.l, 8);
+  const size_t accsz = c.xdtype == DASHSVD_F64 ? 8 : 4;
+  const int32_t T = c.long_row > 0 ? c.long_row : kDefaultLongRow;
+  plan_alloc(nullptr, a, pl, c.rows, c.nnz, T, ld, accsz);
+  *scan_tmp = (int64_t *)a.take(8 * scan_tmp_elems(c.rows + 1));
+}
+
+size_t spmm_ws_bytes(const SpmmCall &c) {
+  Arena a;
+  a.reset(true);
+  Plan pl;
+  int64_t *scan_tmp = nullptr;
+  spmm_layout(c, a, pl, &scan_tmp);
+  return a.used;
+}
+
+// The plan's atomic long-row counter must start at zero; every other word of
+// the workspace is written before it is read.
+hipError_t spmm_run_on(const SpmmCall &c, char *base, size_t cap) {
+  const int ld = (int)round_up(c.l, 8);
+  const int vdt = c.xdtype == DASHSVD_F64 ? DASHSVD_F64 : DASHSVD_F32;
+  const int32_t T = c.long_row > 0 ? c.long_row : kDefaultLongRow;
+  Arena a;
+  a.base = base;
+  a.cap = cap;
+  a.reset(false);
+  Plan pl;
+  int64_t *scan_tmp = nullptr;
+  spmm_layout(c, a, pl, &scan_tmp);
+  ZeroRanges z{};
+  z.add(pl.nlong, 16);
+  hipError_t e = launch_zero_ranges(z, c.st);
+  if (e == hipSuccess) e = launch_plan_count(c.rows, c.row_ptr, T, pl.nch, c.st);
+  if (e == hipSuccess) e = launch_scan_i64(pl.nch, c.rows, pl.off, scan_tmp, c.st);
+  if (e == hipSuccess) e = launch_plan_fill(c.rows, c.row_ptr, T, pl.off, pl.tasks, pl.longs, pl.nlong, c.st);
+  int64_t tot = 0;
+  int32_t nl = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&tot, pl.off + c.rows, 8, hipMemcpyDeviceToHost, c.st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&nl, pl.nlong, 4, hipMemcpyDeviceToHost, c.st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c.st);
+  if (e == hipSuccess)
+    e = launch_spmm(c.rows, c.row_ptr, c.col, c.val, vdt, c.X, c.ldx, c.xdtype, c.Y, c.ldy, c.ydtype, ld, tot,
+                    pl.tasks, nl, pl.longs, pl.partial, T, c.Q, c.ldq, c.alpha, nullptr, c.st, nullptr, nullptr,
+                    c.cols);
+  if (e == hipSuccess) e = hipStreamSynchronize(c.st);
+  return e;
+}
+
+// Scratch of dashsvd_k_spmm_static: the plan and long-row partials of one
+// call.  Every device holds its own copy for the life of the process.  In
+// host code the array's name is not a device address: the kernels get the
+// address hipGetSymbolAddress returns for the current device, resolved once
+// per device and kept in g_scratch_dev.
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxScratchDevices] = {};
+
+hipError_t static_scratch_address(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
 dashsvd_status dashsvd_k_spmm(int64_t rows, int64_t cols, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
                               const void *val, const void *X, int64_t ldx, int32_t xdtype, void *Y, int64_t ldy,
                               int32_t ydtype, int32_t l, const void *Q, int64_t ldq, const double *alpha,
                               int32_t long_row, void *stream) {
   dashsvd_handle *h = nullptr;
-  const int ld = (int)round_up(l, 8);
-  if (rows < 1 || l < 1 || l > DASHSVD_MAX_L || ldx % 8 || ldy % 8 || ldx < ld || ldy < ld ||
-      (alpha && (!Q || ldq % 8 || ldq < ld)))
-    return fail(h, DASHSVD_ERR_INVALID_ARG, "spmm arguments (leading dimensions must be multiples of 8 >= l)");
-  const int vdt = xdtype == DASHSVD_F64 ? DASHSVD_F64 : DASHSVD_F32;
-  const size_t accsz = xdtype == DASHSVD_F64 ? 8 : 4;
-  const int32_t T = long_row > 0 ? long_row : kDefaultLongRow;
-  hipStream_t st = (hipStream_t)stream;
-  Arena a;
-  a.reset(true);
-  Plan pl;
-  plan_alloc(h, a, pl, rows, nnz, T, ld, accsz);
-  a.take(8 * scan_tmp_elems(rows + 1));
+  const SpmmCall c{rows, cols, nnz, row_ptr, col, val, X, ldx, xdtype, Y, ldy, ydtype, l, Q, ldq, alpha,
+                   long_row, (hipStream_t)stream};
+  dashsvd_status s = spmm_call_check(c);
+  if (s != DASHSVD_OK) return s;
+  const size_t bytes = spmm_ws_bytes(c) + 256;
   void *base = nullptr;
-  if (hipMalloc(&base, a.used + 256) != hipSuccess) return fail(h, DASHSVD_ERR_OOM, "spmm workspace");
-  (void)hipMemsetAsync(base, 0, a.used + 256, st);
-  a.base = (char *)base;
-  a.cap = a.used + 256;
-  a.reset(false);
-  plan_alloc(h, a, pl, rows, nnz, T, ld, accsz);
-  int64_t *scan_tmp = (int64_t *)a.take(8 * scan_tmp_elems(rows + 1));
-  hipError_t e = launch_plan_count(rows, row_ptr, T, pl.nch, st);
-  if (e == hipSuccess) e = launch_scan_i64(pl.nch, rows, pl.off, scan_tmp, st);
-  if (e == hipSuccess) e = launch_plan_fill(rows, row_ptr, T, pl.off, pl.tasks, pl.longs, pl.nlong, st);
-  int64_t tot = 0;
-  int32_t nl = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(&tot, pl.off + rows, 8, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(&nl, pl.nlong, 4, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e == hipSuccess)
-    e = launch_spmm(rows, row_ptr, col, val, vdt, X, ldx, xdtype, Y, ldy, ydtype, ld, tot, pl.tasks, nl, pl.longs,
-                    pl.partial, T, Q, ldq, alpha, nullptr, st, nullptr, nullptr, cols);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (hipMalloc(&base, bytes) != hipSuccess) return fail(h, DASHSVD_ERR_OOM, "spmm workspace");
+  hipError_t e = hipMemsetAsync(base, 0, bytes, c.st);
+  if (e == hipSuccess) e = spmm_run_on(c, (char *)base, bytes);
   (void)hipFree(base);
+  if (e != hipSuccess) return fail(h, DASHSVD_ERR_HIP, hipGetErrorString(e));
+  return DASHSVD_OK;
+}
+
+dashsvd_status dashsvd_k_spmm_static(int64_t rows, int64_t cols, int64_t nnz, const int64_t *row_ptr,
+                                     const int32_t *col, const void *val, const void *X, int64_t ldx,
+                                     int32_t xdtype, void *Y, int64_t ldy, int32_t ydtype, int32_t l,
+                                     const void *Q, int64_t ldq, const double *alpha, int32_t long_row,
+                                     void *stream) {
+  dashsvd_handle *h = nullptr;
+  const SpmmCall c{rows, cols, nnz, row_ptr, col, val, X, ldx, xdtype, Y, ldy, ydtype, l, Q, ldq, alpha,
+                   long_row, (hipStream_t)stream};
+  dashsvd_status s = spmm_call_check(c);
+  if (s != DASHSVD_OK) return s;
+  const size_t bytes = spmm_ws_bytes(c);
+  if (bytes > kStaticScratchBytes)
+    return fail(h, DASHSVD_ERR_INVALID_ARG,
+                "k_spmm_static: this call's plan needs " + std::to_string(bytes) +
+                    " bytes of scratch, the static scratch holds " + std::to_string(kStaticScratchBytes) +
+                    " (a larger long_row needs fewer partial rows; dashsvd_k_spmm has no limit)");
+  void *base = nullptr;
+  hipError_t e = static_scratch_address(&base);
+  if (e != hipSuccess) return fail(h, DASHSVD_ERR_HIP, std::string("static scratch: ") + hipGetErrorString(e));
+  e = spmm_run_on(c, (char *)base, kStaticScratchBytes);
   if (e != hipSuccess) return fail(h, DASHSVD_ERR_HIP, hipGetErrorString(e));
   return DASHSVD_OK;
 }

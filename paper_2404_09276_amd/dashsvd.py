@@ -80,7 +80,7 @@ EXPORTS = [
     "dashsvd_workspace_size_batched", "dashsvd_handle_workspace_size", "dashsvd_set_workspace",
     "dashsvd_status_string",
     "dashsvd_last_error", "dashsvd_k_gaussian", "dashsvd_k_philox_raw", "dashsvd_k_transpose",
-    "dashsvd_k_spmm", "dashsvd_k_gram", "dashsvd_k_eig", "dashsvd_k_eig_prof", "dashsvd_k_cholqr", "dashsvd_k_rescale",
+    "dashsvd_k_spmm", "dashsvd_k_spmm_static", "dashsvd_k_gram", "dashsvd_k_eig", "dashsvd_k_eig_prof", "dashsvd_k_cholqr", "dashsvd_k_rescale",
 ]
 
 
@@ -129,6 +129,7 @@ def lib():
         L.dashsvd_k_transpose.argtypes = [i64, i64, i64, P, P, P, i32, P, P, P, P]
         L.dashsvd_k_spmm.argtypes = [i64, i64, i64, P, P, P, P, i64, i32, P, i64, i32, i32, P, i64, P,
                                      i32, P]
+        L.dashsvd_k_spmm_static.argtypes = L.dashsvd_k_spmm.argtypes
         L.dashsvd_k_gram.argtypes = [i64, i32, P, i64, i32, P, P]
         L.dashsvd_k_eig.argtypes = [i32, P, P, P, P, P, P]
         L.dashsvd_k_eig_prof.argtypes = [i32, P, P, P, P, P, P, P]
@@ -510,6 +511,15 @@ def k_spmm(rows, cols, row_ptr, col, val, X, Y, l, Q=None, alpha=None, long_row=
                                 _ptr(X), X.stride(0), _dtype_code(X), _ptr(Y), Y.stride(0),
                                 _dtype_code(Y), l, _ptr(Q), Q.stride(0) if Q is not None else 0,
                                 _ptr(alpha), long_row, _stream_ptr(stream)))
+
+
+def k_spmm_static(rows, cols, row_ptr, col, val, X, Y, l, Q=None, alpha=None, long_row=0, stream=None):
+    """As k_spmm, through the entry point that allocates nothing (its plan
+    lives in the library's static device scratch)."""
+    _check(lib().dashsvd_k_spmm_static(rows, cols, col.numel(), _ptr(row_ptr), _ptr(col), _ptr(val),
+                                       _ptr(X), X.stride(0), _dtype_code(X), _ptr(Y), Y.stride(0),
+                                       _dtype_code(Y), l, _ptr(Q), Q.stride(0) if Q is not None else 0,
+                                       _ptr(alpha), long_row, _stream_ptr(stream)))
 
 
 def k_gram(Cm, l, G, stream=None):
