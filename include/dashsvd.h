@@ -72,13 +72,21 @@ typedef int32_t dashsvd_status;
 #define DASHSVD_SHIFT_SCHEDULE 3
 #define DASHSVD_SHIFT_LEARNED 4
 
-/* Readings of the PVE check (Alg. 5 step 5 with eq. (19)).
+/* Readings of the PVE check (Alg. 5 step 5 with eq. (19)), and the check
+ * without the surrogate.
  *   R2 (default): E_i = S_i + alpha with the alpha that produced S_i, for
  *       both the current and the previous pass.
  *   R1: the literal step order, where the stored previous shift is the one
- *       after its update. */
+ *       after its update.
+ *   NOSURR: the accuracy control that Sec. 4.3 (Table 3) compares the
+ *       surrogate against: after every pass, the singular values of
+ *       B = A Q (Alg. 3 on B) and eq. (18) on their squares, E' = 0 before
+ *       the first pass.  The shift rule is unchanged.  Costs a Gram of an
+ *       m x l block and an l x l eigensolve per pass; FP32 and FP64 panels
+ *       only (BF16 panels: DASHSVD_ERR_INVALID_ARG), single solves only. */
 #define DASHSVD_PVE_R2 0
 #define DASHSVD_PVE_R1 1
+#define DASHSVD_PVE_NOSURR 2
 
 /* Orthonormalisation of the sketch and pass blocks (Alg. 3 inside Alg. 5).
  *   AUTO (default): Cholesky-QR.  W = R^-1 from G = C^T C = R^T R, so that
@@ -162,7 +170,8 @@ typedef struct {
 #define DASHSVD_KT_SKETCH 6      /* Omega + M^T Omega */
 #define DASHSVD_KT_FINAL 7       /* B = M Q, its eigSVD, U, V, signs */
 #define DASHSVD_KT_CHOLQR 8      /* Cholesky-QR + eigenvalue blocks (eig_method AUTO) */
-#define DASHSVD_KT_GROUPS 9
+#define DASHSVD_KT_CHECK 9       /* pve_mode NOSURR: Gram of B, its eigenvalues, eq. (18) */
+#define DASHSVD_KT_GROUPS 10
 
 typedef struct {
   int32_t passes;          /* N_p: shifted power passes executed */
@@ -236,6 +245,34 @@ dashsvd_status dashsvd_get_info(dashsvd_handle *h, dashsvd_info *out);
  * panels of the last run are overwritten, its results (U, S, V) are not. */
 dashsvd_status dashsvd_evaluate(dashsvd_handle *h, const dashsvd_csr *A, const double *sigma_ref,
                                 int32_t n_ref, double *eps_pve, double *eps_sigma);
+
+/* All four error metrics of Sec. 4 for the last run, on the device. */
+typedef struct {
+  double eps_pve;    /* max_{i<k} |sigma_i^2 - ||A^T u_i||^2| / sigma_{k+1}^2 */
+  double eps_sigma;  /* max_{i<k} |sigma_i - S_i| / sigma_i */
+  double eps_res;    /* max_{i<k} ||A^T u_i - S_i v_i||_2 / sigma_i */
+  double eps_spec;   /* (||A - U diag(S) V^T||_2 - sigma_{k+1}) / sigma_{k+1} */
+  double spec_norm;  /* the estimate of ||A - U diag(S) V^T||_2 used (a lower bound) */
+  int32_t lanczos_steps;  /* Lanczos steps taken for spec_norm */
+  int32_t pad;
+} dashsvd_metrics;
+
+/* As dashsvd_evaluate, plus eps_res and eps_spec (Sec. 4).  eps_res forms
+ * A^T U with the library's SpMM and the column norms of A^T U - V diag(S) in
+ * FP64.  ||A - U diag(S) V^T||_2 is the square root of the largest
+ * eigenvalue of E^T E (E = A - U S V^T), estimated by the Lanczos process
+ * with full reorthogonalisation (two rounds of Gram-Schmidt per step)
+ * started from the Gaussian vector of the Philox stream keyed by seed
+ * (Omega's generator, one column), with the products by A and A^T in the
+ * run's compute type and the vectors in FP64.  The estimate never exceeds
+ * the norm and grows with the steps; it stops after max_steps steps (at
+ * most n), at an invariant subspace, or when it has changed by at most
+ * 1e-14 (FP64 runs; 1e-9 otherwise) relative over 5 steps.  Allocates
+ * FP64 buffers of (m + n) k + n max(k, max_steps + 1) doubles for the call
+ * and frees them.  Synchronises the stream; errors as dashsvd_evaluate. */
+dashsvd_status dashsvd_evaluate_all(dashsvd_handle *h, const dashsvd_csr *A, const double *sigma_ref,
+                                    int32_t n_ref, int32_t max_steps, uint64_t seed,
+                                    dashsvd_metrics *out);
 
 /* Per-pass S (the l singular values of each pass's block C, descending):
  * writes min(passes, max_passes) rows of l doubles to host memory. */
@@ -363,6 +400,15 @@ dashsvd_status dashsvd_k_gaussian(uint64_t seed, int64_t rows, int64_t cols, voi
 
 /* Raw Philox words: out[w] = word w of the stream keyed (seed, 0). */
 dashsvd_status dashsvd_k_philox_raw(uint64_t seed, int64_t nwords, uint64_t *out, void *stream);
+
+/* The library's stable LSD radix sort (used for CSR(A^T) and the degree
+ * order): keys_out = keys_in sorted on their low `bits` bits (1..32),
+ * ascending, or descending when descending != 0 (non-increasing keys); equal
+ * keys keep their input order, and idx_out[p] is the input position of
+ * keys_out[p].  All pointers device memory, n entries each.  Synchronises
+ * the stream. */
+dashsvd_status dashsvd_k_sort_index(int64_t n, const uint32_t *keys_in, uint32_t *keys_out, int32_t *idx_out,
+                                    int32_t bits, int32_t descending, void *stream);
 
 /* CSR of A^T (the transposed operand of Alg. 5 steps 2 and 4): rows of A^T
  * list their columns in increasing order.  All pointers are device memory;

@@ -190,6 +190,17 @@ hipError_t launch_gaussian(uint64_t seed, int64_t rows, int64_t cols, void *out,
 hipError_t launch_philox_raw(uint64_t seed, int64_t nwords, uint64_t *out, hipStream_t st);
 
 hipError_t launch_scan_i64(const int64_t *in, int64_t n, int64_t *out, int64_t *tmp, hipStream_t st);
+// Stable LSD radix sort (k_sort.hip) on the low `bits` bits of 32-bit keys.
+// Workspace: sort_ws_bytes(n, bits, payload bytes).  keys_out / the payload
+// output receive the sorted keys and payloads; the inputs are not modified.
+size_t sort_ws_bytes(int64_t n, unsigned bits, int payload_bytes);
+// payload of input i: row[i] | (bits of val[i]) << 32
+hipError_t sort_keys_packed(int64_t n, const uint32_t *keys_in, const int32_t *row, const float *val,
+                            uint32_t *keys_out, uint64_t *pay_out, unsigned bits, void *ws, size_t ws_bytes,
+                            hipStream_t st);
+// payload of input i: i; descending = non-increasing keys, ties in input order
+hipError_t sort_keys_index(int64_t n, const uint32_t *keys_in, uint32_t *keys_out, int32_t *idx_out, unsigned bits,
+                           bool descending, void *ws, size_t ws_bytes, hipStream_t st);
 size_t scan_tmp_elems(int64_t n);
 
 // Validation of a CSR (flags[0] |= 1: malformed structure, |= 2: non-finite
@@ -285,6 +296,7 @@ struct EigArgs {
   long long *prof;      // optional step profile (6 counters), null in the solver
   int32_t *trace_sweeps;  // sweeps of call c (c = state->eig_calls before this call), [cap + 2]
   const int32_t *run_if;  // Jacobi only: when set, the call does nothing unless *run_if != 0
+  const int32_t *skip_if; // Jacobi only: when set, the call does nothing if *skip_if != 0
   double cq_switch;       // pass tail: set state->cq_off once ratio <= cq_switch x tol (0: never)
   int32_t call_idx;       // > 0: store it to state->eig_started when the call starts working
 };
@@ -309,7 +321,34 @@ hipError_t mlp_backward(const MlpDims &d, const float *P, const float *X, const 
                         float *loss, hipStream_t st);
 hipError_t mlp_adam(float *P, const float *G, float *m, float *v, int64_t n, float lr, int t, hipStream_t st);
 
+// Evaluation vector kernels (k_eval.hip).  X, V, Z: FP64 column-major, one
+// vector of n entries every ld.  partial: eval_partial_elems(J) doubles.
+size_t eval_partial_elems(int J);
+// out[j] = sum_r X[j ldx + r] y[r], j < J
+hipError_t launch_dots(int64_t n, int J, const double *X, int64_t ldx, const double *y, double *partial,
+                       double *out, hipStream_t st);
+// out[i] = sum_r (Z[i ld + r] - S[i] V[i ld + r])^2, i < k
+hipError_t launch_resid_norms(int64_t n, int k, const double *Z, const double *V, int64_t ld, const double *S,
+                              double *partial, double *out, hipStream_t st);
+// y[r] -= sum_j X[j ldx + r] c[j] (scale[j] c[j] when scale is given)
+hipError_t launch_combo(int64_t n, int J, const double *X, int64_t ldx, const double *c, const double *scale,
+                        double *y, hipStream_t st);
+// out[r] = w[r] / sqrt(*nrm2)
+hipError_t launch_scale_by_norm(int64_t n, const double *w, const double *nrm2, double *out, hipStream_t st);
+// out[j ldo + row_to(r)] = in[r ldi + j] (in F32 or F64, row-major)
+hipError_t launch_to_colmajor(int64_t rows, int cols, const void *in, int64_t ldi, int idtype, double *out,
+                              int64_t ldo, const int32_t *row_to, hipStream_t st);
 hipError_t launch_eig(const EigArgs &a, hipStream_t st);
+// Accuracy control without the surrogate (Sec. 4.3): eq. (18) on the
+// squared singular values Sb (l, descending) of B = M Q of the pass just
+// run against those of the previous pass (Ebp, zero before the first pass;
+// updated unless the check stops the loop).  Writes the ratio to the solver
+// state and the pass's trace slot, sets done / converged when it is <= tol
+// and cq_off when it is <= cq_switch x tol.  Nothing happens when *gate is
+// set (the pass was launched after the stop).  One workgroup.
+hipError_t launch_pve_nosurr(int k, int l, const double *Sb, double *Ebp, double tol, double cq_switch,
+                             SolverState *state, double *trace_ratio, int trace_cap, const int32_t *gate,
+                             hipStream_t st);
 // Orthonormalisation of a pass block (modes 1 and 2) without eigenvectors:
 // the Cholesky-QR weights W = R^-1 (G = R^T R) and S from the eigenvalues
 // of G, then the Jacobi eigensolver on the same arguments, which runs only

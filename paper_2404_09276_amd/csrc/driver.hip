@@ -130,6 +130,7 @@ struct dashsvd_handle {
     void *panel_m = nullptr, *panel_n = nullptr;  // Mm x ld and Mn x ld, cdt
     double *gpart = nullptr, *G = nullptr;
     const int32_t *u_row_to = nullptr;  // degree order: row r of U goes to row u_row_to[r] of the panel
+    const int32_t *v_row_to = nullptr;  // and row r of V to row v_row_to[r]
   } ev_ctx;
   // results of the last batched run
   struct BatchOut {
@@ -296,6 +297,7 @@ struct RunBufs {
   void *Q32 = nullptr, *Y32 = nullptr;  // FP32 panels after a BF16 promotion
   double *gpart = nullptr, *G = nullptr, *W = nullptr, *Vs = nullptr, *S = nullptr, *Sprev = nullptr;
   double *G2 = nullptr, *T2 = nullptr, *W2 = nullptr, *PU = nullptr, *PV = nullptr;  // final step
+  double *Sb = nullptr, *Ebp = nullptr;  // check without the surrogate: sigma(M Q), previous sigma(M Q)^2
   SolverState *state = nullptr;
   double *tr_alpha = nullptr, *tr_ratio = nullptr, *tr_s = nullptr;
   int32_t *tr_sweeps = nullptr;
@@ -345,7 +347,7 @@ dashsvd_status dashsvd_set_options(dashsvd_handle *h, const dashsvd_options *opt
   if (opt) o = *opt;
   if (o.precision < 0 || o.precision > 2) return fail(h, DASHSVD_ERR_INVALID_ARG, "precision");
   if (o.shift_policy < 0 || o.shift_policy > 4) return fail(h, DASHSVD_ERR_INVALID_ARG, "shift_policy");
-  if (o.pve_mode < 0 || o.pve_mode > 1) return fail(h, DASHSVD_ERR_INVALID_ARG, "pve_mode");
+  if (o.pve_mode < 0 || o.pve_mode > 2) return fail(h, DASHSVD_ERR_INVALID_ARG, "pve_mode");
   if (o.eig_method < 0 || o.eig_method > 1) return fail(h, DASHSVD_ERR_INVALID_ARG, "eig_method");
   if (o.reorder < -1 || o.reorder > 1) return fail(h, DASHSVD_ERR_INVALID_ARG, "reorder");
   if (o.p_max < 0) o.p_max = kDefaultPmax;
@@ -549,6 +551,8 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   b.PV = (double *)ar.take(8 * (size_t)l * l);
   b.S = (double *)ar.take(8 * (size_t)l);
   b.Sprev = (double *)ar.take(8 * (size_t)l);
+  b.Sb = (double *)ar.take(8 * (size_t)l);
+  b.Ebp = (double *)ar.take(8 * (size_t)l);
   b.state = (SolverState *)ar.take(sizeof(SolverState));
   b.tr_alpha = (double *)ar.take(8 * (size_t)cap);
   b.tr_ratio = (double *)ar.take(8 * (size_t)cap);
@@ -629,6 +633,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     z.add(b.planT.nlong, 16);
     z.add(b.state, sizeof(SolverState));
     z.add(b.Sprev, 8 * (size_t)l);
+    z.add(b.Ebp, 8 * (size_t)l);
     z.add(b.tr_alpha, 8 * (size_t)cap);
     z.add(b.tr_ratio, 8 * (size_t)cap);
     z.add(b.tr_sweeps, 4 * (size_t)(cap + 2));
@@ -730,6 +735,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   // the blocks of passes p_max - 1 and p_max.
   const bool cholqr = h->opt.eig_method == DASHSVD_EIG_AUTO;
   constexpr double kCqSwitch = 100.0;
+  const bool nosurr = h->opt.pve_mode == DASHSVD_PVE_NOSURR;
   auto make_eig = [&](int mode) {
     EigArgs ea;
     std::memset(&ea, 0, sizeof(ea));
@@ -749,7 +755,9 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     ea.mode = mode;
     ea.pve_mode = h->opt.pve_mode;
     ea.policy = h->opt.shift_policy;
-    ea.tol = tol;
+    // without the surrogate, the pass tail only updates the shift; the
+    // check of sigma(M Q) decides termination
+    ea.tol = nosurr ? 0.0 : tol;
     ea.Sprev = b.Sprev;
     ea.trace_alpha = b.tr_alpha;
     ea.trace_ratio = b.tr_ratio;
@@ -845,6 +853,34 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       if (e != hipSuccess) return e;
       return hipStreamWaitEvent(st, h->ev_eig, 0);
     };
+    // Accuracy control without the surrogate (Sec. 4.3): sigma(B) of
+    // B = M Q = Z W after the pass, from B^T B = W^T (Z^T Z) W (the final
+    // step's identity), its eigenvalues by the Jacobi kernel, then eq. (18)
+    // on their squares.  On the main stream after the pass's eigensolver,
+    // so a stop leaves C, Z and W of the stopping pass for the final step.
+    auto check_nosurr = [&](int pass) -> hipError_t {
+      tmark_begin(h, DASHSVD_KT_CHECK, pass);
+      hipError_t e = launch_gram(Mm, l, b.Z, ld, cdt, b.gpart, nb_m, b.G2, pass_skip, st, nullptr);
+      if (e == hipSuccess) e = launch_small_gemm(l, l, l, b.G2, l, 0, b.W, l, b.T2, l, st);
+      if (e == hipSuccess) e = launch_small_gemm(l, l, l, b.W, l, 1, b.T2, l, b.PU, l, st);
+      if (e == hipSuccess) {
+        EigArgs ev;
+        std::memset(&ev, 0, sizeof(ev));
+        ev.l = l;
+        ev.k = k;
+        ev.skip = prec == DASHSVD_PREC_FP64 ? 0x1.0p-53 : 0x1.0p-23;
+        ev.G = b.PU;
+        ev.S = b.Sb;
+        ev.W = b.W2;
+        ev.skip_if = pass_skip;
+        e = launch_eig(ev, st);
+      }
+      if (e == hipSuccess)
+        e = launch_pve_nosurr(k, l, b.Sb, b.Ebp, tol, cholqr ? kCqSwitch : 0.0, b.state, b.tr_ratio, cap, pass_skip,
+                              st);
+      tmark_end(h);
+      return e;
+    };
     // sketch (Alg. 5 step 2): C = M^T Omega, its eigSVD || M C, M^T M C
     tmark_begin(h, DASHSVD_KT_SKETCH, 0);
     HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, Cb[0], ld, cdt, ldc, b.planT.n_chunks,
@@ -893,6 +929,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
                               &b.state->alpha));
         tmark_end(h);
         HIPCHK(side(2, pass, Cb[pass & 1], done));
+        if (nosurr) HIPCHK(check_nosurr(pass));
       }
       launched += chunk;
       if (!(tol > 0.0 && launched < pmax)) continue;
@@ -1133,6 +1170,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     c.gpart = b.gpart;
     c.G = b.G;
     c.u_row_to = reorder ? b.inv_r : nullptr;
+    c.v_row_to = reorder ? b.inv_c : nullptr;
   }
   dashsvd_status s = DASHSVD_OK;
   if (tol > 0.0 && !hs.converged) s = DASHSVD_NOT_CONVERGED;
@@ -1151,6 +1189,8 @@ dashsvd_status dashsvd_run(dashsvd_handle *h, const dashsvd_csr *A, int32_t k, i
                 "LEARNED policy needs an MLP for l = k + oversampling (dashsvd_mlp_init / set_params)");
   if (h->opt.omega && h->opt.precision == DASHSVD_PREC_BF16_PANELS)
     return fail(h, DASHSVD_ERR_INVALID_ARG, "a caller-provided Omega is not supported with BF16 panels");
+  if (h->opt.pve_mode == DASHSVD_PVE_NOSURR && h->opt.precision == DASHSVD_PREC_BF16_PANELS)
+    return fail(h, DASHSVD_ERR_INVALID_ARG, "pve_mode NOSURR needs FP32 or FP64 panels");
   s = run_impl(h, A, k, p, tol, false, nullptr);
   h->info.status = s;
   return s;
@@ -1237,10 +1277,13 @@ dashsvd_status dashsvd_get_USV(dashsvd_handle *h, void *U, int64_t ldu, double *
   return DASHSVD_OK;
 }
 
-dashsvd_status dashsvd_evaluate(dashsvd_handle *h, const dashsvd_csr *A, const double *sigma_ref, int32_t n_ref,
-                                double *eps_pve, double *eps_sigma) {
-  if (!h) return DASHSVD_ERR_INVALID_ARG;
-  h->err.clear();
+}  // extern "C"
+
+// eps_PVE and eps_sigma of the last run (Sec. 4).  Leaves Z = A^T U (in the
+// solver's column order) in the n-row evaluation panel, leading dimension
+// k rounded up to 8, for the residual metric.
+static dashsvd_status evaluate_core(dashsvd_handle *h, const dashsvd_csr *A, const double *sigma_ref,
+                                    int32_t n_ref, double *eps_pve, double *eps_sigma) {
   if (!h->have || !h->ev_ctx.ok) return fail(h, DASHSVD_ERR_STATE, "no results: run first");
   auto &c = h->ev_ctx;
   if (!A || A->m != h->m || A->n != h->n || A->nnz != c.nnz)
@@ -1280,6 +1323,160 @@ dashsvd_status dashsvd_evaluate(dashsvd_handle *h, const dashsvd_csr *A, const d
   }
   if (eps_pve) *eps_pve = pve;
   if (eps_sigma) *eps_sigma = es;
+  return DASHSVD_OK;
+}
+
+// Largest eigenvalue of the symmetric tridiagonal matrix with diagonal
+// al[0..j) and off-diagonal be[0..j-1), by bisection on Sturm counts
+// (the number of negative pivots of T - x I is the number of eigenvalues
+// below x).
+static double tridiag_max_eig(int j, const std::vector<double> &al, const std::vector<double> &be) {
+  double lo = 0.0, hi = 0.0;
+  for (int i = 0; i < j; ++i) {
+    const double r = (i > 0 ? std::fabs(be[i - 1]) : 0.0) + (i + 1 < j ? std::fabs(be[i]) : 0.0);
+    lo = i == 0 ? al[i] - r : std::min(lo, al[i] - r);
+    hi = i == 0 ? al[i] + r : std::max(hi, al[i] + r);
+  }
+  auto below = [&](double x) {
+    int c = 0;
+    double d = 1.0;
+    for (int i = 0; i < j; ++i) {
+      d = al[i] - x - (i > 0 ? be[i - 1] * be[i - 1] / d : 0.0);
+      if (d == 0.0) d = -1e-300;
+      if (d < 0.0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200 && hi - lo > 4e-16 * std::max(std::fabs(lo), std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (below(mid) >= j) hi = mid;
+    else lo = mid;
+  }
+  return hi;
+}
+
+extern "C" {
+
+dashsvd_status dashsvd_evaluate(dashsvd_handle *h, const dashsvd_csr *A, const double *sigma_ref, int32_t n_ref,
+                                double *eps_pve, double *eps_sigma) {
+  if (!h) return DASHSVD_ERR_INVALID_ARG;
+  h->err.clear();
+  return evaluate_core(h, A, sigma_ref, n_ref, eps_pve, eps_sigma);
+}
+
+dashsvd_status dashsvd_evaluate_all(dashsvd_handle *h, const dashsvd_csr *A, const double *sigma_ref, int32_t n_ref,
+                                    int32_t max_steps, uint64_t seed, dashsvd_metrics *out) {
+  if (!h) return DASHSVD_ERR_INVALID_ARG;
+  h->err.clear();
+  if (!out || max_steps < 1) return fail(h, DASHSVD_ERR_INVALID_ARG, "metrics output and max_steps >= 1 needed");
+  std::memset(out, 0, sizeof(*out));
+  dashsvd_status s = evaluate_core(h, A, sigma_ref, n_ref, &out->eps_pve, &out->eps_sigma);
+  if (s != DASHSVD_OK) return s;
+  auto &c = h->ev_ctx;
+  hipStream_t st = h->st;
+  const int k = h->k;
+  const int ld8 = (int)round_up(k, 8);
+  const int64_t m = h->m, n = h->n;
+  const int steps = (int)std::min<int64_t>(max_steps, n);
+  const int J = std::max(k, steps + 1);
+  // panels of the solver's arena (free once U and V are formed): the n-row
+  // one holds Z = A^T U from evaluate_core, then serves with the m-row one
+  // the SpMMs of the Lanczos process (8 columns, the first used)
+  void *pan_n = c.wide ? c.panel_m : c.panel_n;
+  void *pan_m = c.wide ? c.panel_n : c.panel_m;
+  const int sideA = c.wide ? 1 : 0, sideAT = c.wide ? 0 : 1;
+  // FP64 evaluation buffers (column-major)
+  const size_t nU = (size_t)m * k, nV = (size_t)n * k, nQ = (size_t)J * n, nP = eval_partial_elems(J);
+  const size_t total = nU + nV + nQ + (size_t)m + (size_t)n + (size_t)J * 2 + nP + 8;
+  double *buf = nullptr;
+  if (hipMalloc(&buf, 8 * total) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(h, DASHSVD_ERR_OOM, "evaluation buffers");
+  }
+  double *Ucm = buf, *Vcm = Ucm + nU, *Q = Vcm + nV, *y = Q + nQ, *w = y + m, *t1 = w + n, *t2 = t1 + J,
+         *part = t2 + J, *scal = part + nP;
+  hipError_t e = hipSuccess;
+  auto run = [&](hipError_t x) {
+    if (e == hipSuccess) e = x;
+  };
+  std::vector<double> hs((size_t)k);
+  // eps_res = max_i ||A^T u_i - S_i v_i|| / sigma_i: Z (in the solver's
+  // column order) and V brought to that order, both column-major
+  run(launch_to_colmajor(n, k, pan_n, ld8, c.cdt, Q, n, nullptr, st));
+  run(launch_to_colmajor(n, k, h->V, k, h->out_dt, Vcm, n, c.v_row_to, st));
+  run(launch_resid_norms(n, k, Q, Vcm, n, h->S, part, t1, st));
+  run(hipMemcpyAsync(hs.data(), t1, 8 * (size_t)k, hipMemcpyDeviceToHost, st));
+  run(hipStreamSynchronize(st));
+  double res = 0.0;
+  for (int i = 0; i < k && e == hipSuccess; ++i) {
+    const double r = std::sqrt(hs[i]) / sigma_ref[i];
+    if (r > res || r != r) res = r;
+  }
+  out->eps_res = res;
+  // ||A - U S V^T||_2: Lanczos with full reorthogonalisation on E^T E in
+  // the solver's row and column orders (norms do not depend on them),
+  // started from the Gaussian vector of the Philox stream keyed by seed
+  run(launch_to_colmajor(m, k, h->U, k, h->out_dt, Ucm, m, c.u_row_to, st));
+  run(hipMemsetAsync(pan_n, 0, dsz(c.cdt) * (size_t)n * 8, st));
+  run(hipMemsetAsync(pan_m, 0, dsz(c.cdt) * (size_t)m * 8, st));
+  run(launch_gaussian(seed, n, 1, Q, 1, DASHSVD_F64, st, c.v_row_to));
+  run(launch_dots(n, 1, Q, n, Q, part, scal, st));
+  run(launch_scale_by_norm(n, Q, scal, Q, st));
+  const double conv = c.cdt == DASHSVD_F64 ? 1e-14 : 1e-9;
+  std::vector<double> al, be;
+  double lam = 0.0, lam_old = -1.0;
+  double hv[3];
+  int taken = 0;
+  for (int j = 0; j < steps && e == hipSuccess; ++j) {
+    double *q = Q + (size_t)j * n;
+    const Plan &pA = c.plan[sideA], &pT = c.plan[sideAT];
+    // y = A q - U (S .* (V^T q))
+    run(launch_copy2d(q, 1, DASHSVD_F64, pan_n, 8, c.cdt, n, 1, st));
+    run(launch_spmm(m, c.rp[sideA], c.col[sideA], c.val[sideA], c.vdt, pan_n, 8, c.cdt, pan_m, 8, c.cdt, 8,
+                    pA.n_chunks, pA.tasks, pA.n_long, pA.longs, pA.partial, c.T, nullptr, 0, nullptr, nullptr, st,
+                    nullptr, nullptr, n));
+    run(launch_dots(n, k, Vcm, n, q, part, t1, st));
+    run(launch_copy2d(pan_m, 8, c.cdt, y, 1, DASHSVD_F64, m, 1, st));
+    run(launch_combo(m, k, Ucm, m, t1, h->S, y, st));
+    // w = A^T y - V (S .* (U^T y))
+    run(launch_copy2d(y, 1, DASHSVD_F64, pan_m, 8, c.cdt, m, 1, st));
+    run(launch_spmm(n, c.rp[sideAT], c.col[sideAT], c.val[sideAT], c.vdt, pan_m, 8, c.cdt, pan_n, 8, c.cdt, 8,
+                    pT.n_chunks, pT.tasks, pT.n_long, pT.longs, pT.partial, c.T, nullptr, 0, nullptr, nullptr, st,
+                    nullptr, nullptr, m));
+    run(launch_dots(m, k, Ucm, m, y, part, t1, st));
+    run(launch_copy2d(pan_n, 8, c.cdt, w, 1, DASHSVD_F64, n, 1, st));
+    run(launch_combo(n, k, Vcm, n, t1, h->S, w, st));
+    // two rounds of Gram-Schmidt against q_0..q_j; alpha_j = q_j^T w is
+    // the sum of the two rounds' coefficients of q_j
+    run(launch_dots(n, j + 1, Q, n, w, part, t1, st));
+    run(launch_combo(n, j + 1, Q, n, t1, nullptr, w, st));
+    run(launch_dots(n, j + 1, Q, n, w, part, t2, st));
+    run(launch_combo(n, j + 1, Q, n, t2, nullptr, w, st));
+    run(launch_dots(n, 1, w, n, w, part, scal, st));
+    run(launch_scale_by_norm(n, w, scal, Q + (size_t)(j + 1) * n, st));
+    run(hipMemcpyAsync(&hv[0], t1 + j, 8, hipMemcpyDeviceToHost, st));
+    run(hipMemcpyAsync(&hv[1], t2 + j, 8, hipMemcpyDeviceToHost, st));
+    run(hipMemcpyAsync(&hv[2], scal, 8, hipMemcpyDeviceToHost, st));
+    run(hipStreamSynchronize(st));
+    if (e != hipSuccess) break;
+    const double a = hv[0] + hv[1], b = std::sqrt(hv[2] > 0.0 ? hv[2] : 0.0);
+    al.push_back(a);
+    be.push_back(b);
+    taken = j + 1;
+    const bool last = j + 1 == steps || !(b > 1e-14 * std::fabs(a));
+    if (last || (j + 1) % 5 == 0) {
+      lam = tridiag_max_eig(j + 1, al, be);
+      if (last || std::fabs(lam - lam_old) <= conv * lam) break;
+      lam_old = lam;
+    }
+  }
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(buf);
+  if (e != hipSuccess) return fail(h, DASHSVD_ERR_HIP, std::string("evaluation: ") + hipGetErrorString(e));
+  const double en = std::sqrt(lam > 0.0 ? lam : 0.0);
+  out->spec_norm = en;
+  out->eps_spec = (en - sigma_ref[k]) / sigma_ref[k];
+  out->lanczos_steps = taken;
   return DASHSVD_OK;
 }
 
@@ -1687,6 +1884,8 @@ dashsvd_status dashsvd_run_batched(dashsvd_handle *h, const dashsvd_csr *As, int
     dashsvd_status s = check_batch(h, As, count, k, p, tol);
     if (s != DASHSVD_OK) return s;
   }
+  if (h->opt.pve_mode == DASHSVD_PVE_NOSURR)
+    return fail(h, DASHSVD_ERR_INVALID_ARG, "pve_mode NOSURR is for single solves");
   if (!h->stg) {
     HIPCHK(hipStreamCreateWithFlags(&h->stg, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&h->ev_b0, hipEventDisableTiming));
@@ -2057,6 +2256,23 @@ dashsvd_status dashsvd_k_philox_raw(uint64_t seed, int64_t nwords, uint64_t *out
   dashsvd_handle *h = nullptr;
   if (nwords < 0 || !out) return fail(h, DASHSVD_ERR_INVALID_ARG, "philox arguments");
   HIPCHK(launch_philox_raw(seed, nwords, out, (hipStream_t)stream));
+  return DASHSVD_OK;
+}
+
+dashsvd_status dashsvd_k_sort_index(int64_t n, const uint32_t *keys_in, uint32_t *keys_out, int32_t *idx_out,
+                                    int32_t bits, int32_t descending, void *stream) {
+  dashsvd_handle *h = nullptr;
+  if (n < 0 || n > INT32_MAX || bits < 1 || bits > 32 || (n > 0 && (!keys_in || !keys_out || !idx_out)))
+    return fail(h, DASHSVD_ERR_INVALID_ARG, "sort arguments");
+  if (n == 0) return DASHSVD_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t bytes = sort_ws_bytes(n, (unsigned)bits, 4);
+  void *ws = nullptr;
+  if (hipMalloc(&ws, bytes) != hipSuccess) return fail(h, DASHSVD_ERR_OOM, "sort workspace");
+  hipError_t e = sort_keys_index(n, keys_in, keys_out, idx_out, (unsigned)bits, descending != 0, ws, bytes, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(ws);
+  HIPCHK(e);
   return DASHSVD_OK;
 }
 

@@ -6,19 +6,16 @@
 //   1. validation: one thread per nonzero finds its row by binary search in
 //      the row pointer, checks the column (range, strictly increasing in the
 //      row) and the value (finite), and records its row;
-//   2. a stable LSD radix sort of the column indices (only the bits that
-//      column numbers below n use) carrying, for FP32 values, the entry's
-//      row and value packed in 8 bytes (for FP64 values, the nonzero index):
-//      every column of A then lists its nonzeros in their CSR order, i.e. by
-//      increasing row, with no per-column sort and no atomics on the columns
-//      (a Zipf matrix sends a tenth of its nonzeros to its first column);
+//   2. the library's stable LSD radix sort (k_sort.hip) of the column
+//      indices (only the bits that column numbers below n use) carrying, for
+//      FP32 values, the entry's row and value packed in 8 bytes (for FP64
+//      values, the nonzero index): every column of A then lists its nonzeros
+//      in their CSR order, i.e. by increasing row, with no per-column sort
+//      and no atomics on the columns (a Zipf matrix sends a tenth of its
+//      nonzeros to its first column);
 //   3. one thread per entry writes its row and value (FP64: gathers them by
 //      the nonzero index), one thread per column finds where the column
 //      starts in the sorted keys.
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/iterator/counting_iterator.hpp>
-#include <rocprim/iterator/transform_iterator.hpp>
-
 #include "common.h"
 
 namespace dsv {
@@ -246,16 +243,6 @@ __global__ __launch_bounds__(256) void k_tgather_perm(int64_t nnz, const int32_t
   }
 }
 
-// Sort payload of nonzero i with an FP32 value: its row in the low word, the
-// value's bits in the high word.
-struct PackRowVal {
-  const int32_t *rowidx;
-  const float *val;
-  __device__ uint64_t operator()(int32_t i) const {
-    return (uint64_t)(uint32_t)rowidx[i] | ((uint64_t)__float_as_uint(val[i]) << 32);
-  }
-};
-
 // Sorted entry p with its packed (row, value): straight to position p of
 // CSR(A^T), or, with the degree order, to row inv_c[j] of the permuted A^T
 // at its offset inside column j = keys[p], the row renumbered inv_r[r].
@@ -446,40 +433,9 @@ hipError_t launch_validate(int64_t m, int64_t n, int64_t nnz, const int64_t *rp,
 size_t tws_keys_bytes(size_t cnt) { return (4 * (cnt + 64) + 255) / 256 * 256; }
 size_t tws_payload_bytes(size_t cnt) { return (8 * (cnt + 64) + 255) / 256 * 256; }
 
-auto packed_input(const int32_t *rowidx, const float *val) {
-  return rocprim::make_transform_iterator(rocprim::counting_iterator<int32_t>(0), PackRowVal{rowidx, val});
-}
-
-// Digits of 9 bits for the packed sort where that saves a pass over the
-// digits of 8 bits that rocPRIM's tuned configuration uses (column numbers of
-// 17 or 18 bits: 2 passes instead of 3; on a 100 000-column operator with
-// 10M nonzeros the solve took 9.85 instead of 9.93 ms, timed in one
-// process).  Same block shape and rank algorithm as the tuned configuration.
-using PackedSort9 = rocprim::radix_sort_config<
-    rocprim::default_config, rocprim::default_config,
-    rocprim::radix_sort_onesweep_config<rocprim::kernel_config<512, 16>, rocprim::kernel_config<512, 16>, 9,
-                                        rocprim::block_radix_rank_algorithm::match>>;
-bool packed_sort9(unsigned bits) { return (bits + 8) / 9 < (bits + 7) / 8; }
-
-hipError_t sort_packed(void *tmp, size_t &tmp_bytes, const uint32_t *col, uint32_t *keys, const int32_t *rowidx,
-                       const float *val, uint64_t *payload, size_t cnt, unsigned bits, hipStream_t st) {
-  if (packed_sort9(bits))
-    return rocprim::radix_sort_pairs<PackedSort9>(tmp, tmp_bytes, col, keys, packed_input(rowidx, val), payload,
-                                                  cnt, 0u, bits, st);
-  return rocprim::radix_sort_pairs(tmp, tmp_bytes, col, keys, packed_input(rowidx, val), payload, cnt, 0u, bits,
-                                   st);
-}
-
 size_t transpose_ws_bytes(int64_t n, int64_t nnz) {
-  size_t sort_idx = 0, sort_packed_bytes = 0;
   const size_t cnt = nnz > 0 ? (size_t)nnz : 1;
-  (void)rocprim::radix_sort_pairs(nullptr, sort_idx, (const uint32_t *)nullptr, (uint32_t *)nullptr,
-                                  rocprim::counting_iterator<int32_t>(0), (int32_t *)nullptr, cnt, 0u,
-                                  key_bits(n));
-  (void)sort_packed(nullptr, sort_packed_bytes, nullptr, nullptr, nullptr, nullptr, nullptr, cnt, key_bits(n),
-                    nullptr);
-  return tws_keys_bytes(cnt) + tws_payload_bytes(cnt) + (sort_idx > sort_packed_bytes ? sort_idx : sort_packed_bytes) +
-         256;
+  return tws_keys_bytes(cnt) + tws_payload_bytes(cnt) + sort_ws_bytes((int64_t)cnt, key_bits(n), 8) + 256;
 }
 
 hipError_t launch_transpose_keys(int64_t n, int64_t nnz, const int32_t *col, int64_t *rowT, void *ws,
@@ -493,11 +449,10 @@ hipError_t launch_transpose_keys(int64_t n, int64_t nnz, const int32_t *col, int
   if (nnz > 0) {
     // validated columns are in [0, n): sort on their low bits only
     const hipError_t e =
-        dtype == 0 ? sort_packed(tmp, tmp_bytes, (const uint32_t *)col, keys, rowidx, (const float *)val,
-                                 (uint64_t *)payload, (size_t)nnz, key_bits(n), st)
-                   : rocprim::radix_sort_pairs(tmp, tmp_bytes, (const uint32_t *)col, keys,
-                                               rocprim::counting_iterator<int32_t>(0), (int32_t *)payload,
-                                               (size_t)nnz, 0u, key_bits(n), st);
+        dtype == 0 ? sort_keys_packed(nnz, (const uint32_t *)col, rowidx, (const float *)val, keys,
+                                      (uint64_t *)payload, key_bits(n), tmp, tmp_bytes, st)
+                   : sort_keys_index(nnz, (const uint32_t *)col, keys, (int32_t *)payload, key_bits(n), false, tmp,
+                                     tmp_bytes, st);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_tbounds, dim3(grid_for(n + 1, 256, 16384)), dim3(256), 0, st, n, nnz, keys, rowT);
@@ -543,11 +498,8 @@ hipError_t launch_transpose(int64_t n, int64_t nnz, const int32_t *col, const in
 }
 
 size_t degree_order_ws_bytes(int64_t R) {
-  size_t sort_bytes = 0;
   const size_t cnt = R > 0 ? (size_t)R : 1;
-  (void)rocprim::radix_sort_pairs_desc(nullptr, sort_bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr,
-                                       rocprim::counting_iterator<int32_t>(0), (int32_t *)nullptr, cnt, 0u, 32u);
-  return 2 * 4 * (cnt + 64) + 8 * (cnt + 64) + sort_bytes + 256;
+  return 2 * 4 * (cnt + 64) + 8 * (cnt + 64) + sort_ws_bytes((int64_t)cnt, 32u, 4) + 256;
 }
 
 hipError_t launch_degree_order(int64_t R, const int64_t *rp, int64_t max_len, int32_t *perm, int32_t *inv,
@@ -562,9 +514,7 @@ hipError_t launch_degree_order(int64_t R, const int64_t *rp, int64_t max_len, in
   const int g = grid_for(R, 256, 16384);
   hipLaunchKernelGGL(k_degree_keys, dim3(g), dim3(256), 0, st, R, rp, keys);
   // lengths are at most max_len: sort on the bits that can be set
-  hipError_t e = rocprim::radix_sort_pairs_desc(tmp, tmp_bytes, (const uint32_t *)keys, keys_sorted,
-                                                rocprim::counting_iterator<int32_t>(0), perm, cnt, 0u,
-                                                key_bits(max_len + 1), st);
+  hipError_t e = sort_keys_index(R, keys, keys_sorted, perm, key_bits(max_len + 1), true, tmp, tmp_bytes, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_perm_invert, dim3(g), dim3(256), 0, st, R, rp, perm, inv, len);
   return launch_scan_i64(len, R, rp_new, scan_tmp, st);

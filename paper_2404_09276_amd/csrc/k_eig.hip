@@ -115,6 +115,7 @@ template <int MAXNR, int MAXIT, int BATCH, int CPL, int NT, bool BATCHED, bool R
 __global__ __launch_bounds__(NT) void k_eig(EigArgs a0, const EigArgs *__restrict__ arr) {
   const EigArgs &a = BATCHED ? arr[blockIdx.x] : a0;
   if (a.run_if && *a.run_if == 0) return;
+  if (a.skip_if && *a.skip_if) return;
   SolverState *state = a.state;
   if (!BATCHED && state && a.call_idx > 0 && threadIdx.x == 0) signal_started(&state->eig_started, a.call_idx);
   if (state && a.mode == 2) {
@@ -527,7 +528,54 @@ __global__ __launch_bounds__(NT) void k_eig(EigArgs a0, const EigArgs *__restric
   pass_tail(a, state, Ssh);
 }
 
+// Accuracy control without the surrogate: the check of eq. (18) on
+// E_i = Sb_i^2, the squared singular values of B = M Q, against the
+// previous pass's E' (the same ratio as the surrogate check of Alg. 5
+// step 5 with every shift set to zero).
+__global__ __launch_bounds__(kWave) void k_pve_nosurr(int k, int l, const double *__restrict__ Sb,
+                                                      double *__restrict__ Ebp, double tol, double cq_switch,
+                                                      SolverState *__restrict__ state,
+                                                      double *__restrict__ trace_ratio, int trace_cap,
+                                                      const int32_t *__restrict__ gate) {
+  if (gate && *gate) return;
+  const int tid = threadIdx.x;
+  double worst = 0.0;
+  const double ek1 = Sb[k] * Sb[k];
+  for (int i = tid; i < k; i += kWave) {
+    const double e = Sb[i] * Sb[i];
+    const double v = fabs(Ebp[i] - e) / ek1;
+    if (v > worst || v != v) worst = v;
+  }
+  // wavefront maximum (NaN wins, as in the surrogate check)
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    const double o = __shfl_xor(worst, off, kWave);
+    if (o > worst || o != o) worst = o;
+  }
+  const bool stop = tol > 0.0 && worst <= tol;
+  if (!stop)
+    for (int i = tid; i < l; i += kWave) Ebp[i] = Sb[i] * Sb[i];
+  if (tid == 0) {
+    const int j = state->pass;
+    if (j >= 1 && j - 1 < trace_cap) trace_ratio[j - 1] = worst;
+    state->ratio = worst;
+    if (cq_switch > 0.0 && tol > 0.0 && worst <= cq_switch * tol) state->cq_off = 1;
+    if (stop) {
+      state->converged = 1;
+      __hip_atomic_store(&state->done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_pve_nosurr(int k, int l, const double *Sb, double *Ebp, double tol, double cq_switch,
+                             SolverState *state, double *trace_ratio, int trace_cap, const int32_t *gate,
+                             hipStream_t st) {
+  if (k < 1 || l <= k || !state) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pve_nosurr, dim3(1), dim3(kWave), 0, st, k, l, Sb, Ebp, tol, cq_switch, state, trace_ratio,
+                     trace_cap, gate);
+  return hipGetLastError();
+}
 
 // Kernel variant, block size and dynamic LDS for size l (the layout rules of
 // the kernel, mirrored): CPL columns of V per lane, L = l padded to a

@@ -22,7 +22,7 @@ ERR_INVALID_ARG, ERR_BAD_CSR, ERR_NONFINITE, ERR_OOM, ERR_HIP, ERR_STATE = -1, -
 F32, F64, BF16 = 0, 1, 2
 PREC = {"fp32": 0, "fp64": 1, "bf16": 2}
 SHIFT = {"paper": 0, "none": 1, "fixed": 2, "schedule": 3, "learned": 4}
-PVE = {"r2": 0, "r1": 1}
+PVE = {"r2": 0, "r1": 1, "nosurr": 2}
 EIG = {"auto": 0, "jacobi": 1}
 # timing: False / True (every kernel group) / "spmm" (the two SpMM groups only)
 TIMING = {False: 0, True: 1, "spmm": 2}
@@ -60,26 +60,33 @@ class _Info(C.Structure):
                 ("ratio", C.c_double * MAX_TRACE), ("time_total_ms", C.c_double),
                 ("time_setup_ms", C.c_double), ("time_loop_ms", C.c_double),
                 ("time_final_ms", C.c_double), ("long_chunks_A", C.c_int64),
-                ("long_chunks_AT", C.c_int64), ("kt_ms", C.c_double * 9), ("kt_count", C.c_int32 * 9),
+                ("long_chunks_AT", C.c_int64), ("kt_ms", C.c_double * 10), ("kt_count", C.c_int32 * 10),
                 ("eig_calls", C.c_int32), ("eig_sweeps", C.c_int32),
                 ("sweeps_per_call", C.c_int32 * (MAX_TRACE + 2)), ("long_row_used", C.c_int32),
                 ("learned_n", C.c_int32),
                 ("promoted", C.c_int32), ("cholqr_calls", C.c_int32)]
 
-KT_NAMES = ["spmm", "spmm_t", "gram", "eig", "rescale", "transpose", "sketch", "final", "cholqr"]
+class _Metrics(C.Structure):
+    _fields_ = [("eps_pve", C.c_double), ("eps_sigma", C.c_double), ("eps_res", C.c_double),
+                ("eps_spec", C.c_double), ("spec_norm", C.c_double), ("lanczos_steps", C.c_int32),
+                ("pad", C.c_int32)]
+
+
+KT_NAMES = ["spmm", "spmm_t", "gram", "eig", "rescale", "transpose", "sketch", "final", "cholqr", "check"]
 
 
 _lib = None
 
 EXPORTS = [
     "dashsvd_create", "dashsvd_destroy", "dashsvd_set_options", "dashsvd_run", "dashsvd_get_USV",
-    "dashsvd_get_info", "dashsvd_get_trace", "dashsvd_evaluate", "dashsvd_run_batched",
+    "dashsvd_get_info", "dashsvd_get_trace", "dashsvd_evaluate", "dashsvd_evaluate_all", "dashsvd_run_batched",
     "dashsvd_get_USV_batched", "dashsvd_get_info_batched", "dashsvd_autotune", "dashsvd_mlp_init",
     "dashsvd_mlp_num_params", "dashsvd_mlp_set_params", "dashsvd_mlp_get_params", "dashsvd_mlp_forward",
     "dashsvd_mlp_grad", "dashsvd_mlp_train_step", "dashsvd_learned_features", "dashsvd_workspace_size",
     "dashsvd_workspace_size_batched", "dashsvd_handle_workspace_size", "dashsvd_set_workspace",
     "dashsvd_status_string",
-    "dashsvd_last_error", "dashsvd_k_gaussian", "dashsvd_k_philox_raw", "dashsvd_k_transpose",
+    "dashsvd_last_error", "dashsvd_k_gaussian", "dashsvd_k_philox_raw", "dashsvd_k_sort_index",
+    "dashsvd_k_transpose",
     "dashsvd_k_spmm", "dashsvd_k_spmm_static", "dashsvd_k_gram", "dashsvd_k_eig", "dashsvd_k_eig_prof", "dashsvd_k_cholqr", "dashsvd_k_rescale",
 ]
 
@@ -102,6 +109,7 @@ def lib():
         L.dashsvd_get_info.argtypes = [P, C.POINTER(_Info)]
         L.dashsvd_get_trace.argtypes = [P, P, i32]
         L.dashsvd_evaluate.argtypes = [P, C.POINTER(_Csr), P, i32, P, P]
+        L.dashsvd_evaluate_all.argtypes = [P, C.POINTER(_Csr), P, i32, i32, u64, C.POINTER(_Metrics)]
         L.dashsvd_run_batched.argtypes = [P, C.POINTER(_Csr), i32, i32, i32, f64]
         L.dashsvd_get_USV_batched.argtypes = [P, i32, P, i64, P, P, i64, i32, i32]
         L.dashsvd_get_info_batched.argtypes = [P, i32, C.POINTER(_Info)]
@@ -126,6 +134,7 @@ def lib():
         L.dashsvd_last_error.restype = C.c_char_p
         L.dashsvd_k_gaussian.argtypes = [u64, i64, i64, P, i64, i32, P]
         L.dashsvd_k_philox_raw.argtypes = [u64, i64, P, P]
+        L.dashsvd_k_sort_index.argtypes = [i64, P, P, P, i32, i32, P]
         L.dashsvd_k_transpose.argtypes = [i64, i64, i64, P, P, P, i32, P, P, P, P]
         L.dashsvd_k_spmm.argtypes = [i64, i64, i64, P, P, P, P, i64, i32, P, i64, i32, i32, P, i64, P,
                                      i32, P]
@@ -352,6 +361,18 @@ class DashSVD:
         _check(st, self._h)
         return pve.value, es.value
 
+    def evaluate_all(self, A, sigma_ref, max_steps: int = 200, seed: int = 7) -> dict:
+        """dashsvd_evaluate_all: the four Sec. 4 metrics of the last run (and
+        the Lanczos estimate of ||A - U S V^T||_2 with its step count)."""
+        s, keep = make_csr(A.m, A.n, A.row_ptr, A.col, A.val)
+        sr = np.ascontiguousarray(sigma_ref, dtype=np.float64)
+        out = _Metrics()
+        st = lib().dashsvd_evaluate_all(self._h, C.byref(s), _ptr(sr), int(sr.shape[0]), int(max_steps),
+                                        int(seed), C.byref(out))
+        del keep
+        _check(st, self._h)
+        return {f[0]: getattr(out, f[0]) for f in _Metrics._fields_ if f[0] != "pad"}
+
     def info(self) -> Info:
         raw = _Info()
         _check(lib().dashsvd_get_info(self._h, C.byref(raw)), self._h)
@@ -498,6 +519,12 @@ def k_gaussian(seed: int, out, stream=None):
 def k_philox_raw(seed: int, out, stream=None):
     """out: device int64 tensor (bit pattern of uint64 words)."""
     _check(lib().dashsvd_k_philox_raw(seed, out.numel(), _ptr(out), _stream_ptr(stream)))
+
+
+def k_sort_index(keys, keys_out, idx_out, bits: int, descending: bool = False, stream=None):
+    """Stable radix sort of the device int32/uint32 tensor keys on its low bits."""
+    _check(lib().dashsvd_k_sort_index(keys.numel(), _ptr(keys), _ptr(keys_out), _ptr(idx_out), int(bits),
+                                      int(bool(descending)), _stream_ptr(stream)))
 
 
 def k_transpose(m, n, row_ptr, col, val, rowT, colT, valT, stream=None):

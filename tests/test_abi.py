@@ -105,7 +105,7 @@ _LAYOUT_C = r"""
 #define F(T, f) printf("%s.%s %zu %zu\n", #T, #f, offsetof(T, f), sizeof(((T *)0)->f));
 #define S(T) printf("%s %zu\n", #T, sizeof(T));
 int main(void) {
-  S(dashsvd_csr) S(dashsvd_options) S(dashsvd_info)
+  S(dashsvd_csr) S(dashsvd_options) S(dashsvd_info) S(dashsvd_metrics)
   %FIELDS%
   return 0;
 }
@@ -120,7 +120,8 @@ def test_struct_layout_matches_header(tmp_path):
     import ctypes as C
     import subprocess
     from paper_2404_09276_amd import dashsvd as d
-    structs = {"dashsvd_csr": d._Csr, "dashsvd_options": d._Options, "dashsvd_info": d._Info}
+    structs = {"dashsvd_csr": d._Csr, "dashsvd_options": d._Options, "dashsvd_info": d._Info,
+               "dashsvd_metrics": d._Metrics}
     fields = "\n  ".join(f"F({cn}, {f[0]})" for cn, py in structs.items() for f in py._fields_)
     src = tmp_path / "layout.c"
     src.write_text(_LAYOUT_C.replace("%FIELDS%", fields))

@@ -89,8 +89,9 @@ def _transpose_case(torch, A, dtype=np.float32):
 
 
 def test_transpose_bitwise_all_segment_classes(torch_dev):
-    # Zipf columns: some > 2048 entries (bitmap ranking), some 65..2048
-    # (bitonic), many <= 64 (wavefront rank), singletons and empty columns.
+    # Zipf columns: some with more entries than a sort tile holds (4096),
+    # some of 65..2048, many of at most 64 (a wavefront's round), singletons
+    # and empty columns.
     A = synth.zipf_csr(30000, 6000, 600000, seed=5)
     cnt = np.bincount(A.col, minlength=A.n)
     assert cnt.max() > 2048 and ((cnt > 64) & (cnt <= 2048)).any() and (cnt <= 64).any()
@@ -98,11 +99,38 @@ def test_transpose_bitwise_all_segment_classes(torch_dev):
     _transpose_case(torch_dev, A, np.float64)
 
 
-def test_transpose_nine_bit_digit_sort(torch_dev):
-    # 300 columns (9 key bits) and 70 000 columns (17 key bits) take the
-    # sort with 9-bit digits (one and two passes)
+def test_transpose_radix_pass_counts(torch_dev):
+    # 300 columns (9 key bits: one pass of 9-bit digits), 70 000 (17 bits:
+    # two passes, 9 + 8), 300 000 (19 bits: three passes, 7 + 6 + 6) and 5
+    # (3 bits, one pass of 8 digits)
     _transpose_case(torch_dev, synth.zipf_csr(2000, 300, 40000, seed=6))
     _transpose_case(torch_dev, synth.zipf_csr(50000, 70000, 1000000, seed=7))
+    _transpose_case(torch_dev, synth.zipf_csr(40000, 300000, 600000, seed=8))
+    _transpose_case(torch_dev, synth.uniform_csr(4000, 5, 9000, seed=9))
+
+
+@pytest.mark.parametrize("n,bits", [(1, 1), (4095, 3), (4097, 9), (100003, 17), (250000, 20), (30011, 32)])
+@pytest.mark.parametrize("desc", [False, True])
+def test_radix_sort_stable_against_numpy(torch_dev, n, bits, desc):
+    """The radix sort alone: keys on their low bits, ascending or descending,
+    equal keys in input order; against NumPy's stable argsort, bit for bit,
+    with ragged last tiles, one to four passes and many equal keys."""
+    torch = torch_dev
+    from paper_2404_09276_amd import k_sort_index
+    rng = np.random.default_rng(n + bits)
+    hi = min(2 ** bits, 2 ** 31)
+    keys = rng.integers(0, hi, size=n, dtype=np.int64)
+    keys[: n // 3] = keys[0]  # a long run of one key
+    keys = keys.astype(np.uint32).view(np.int32)
+    kd = _dev(torch, keys)
+    ko = torch.empty_like(kd)
+    io = torch.empty(n, dtype=torch.int32, device="cuda")
+    k_sort_index(kd, ko, io, bits, desc)
+    torch.cuda.synchronize()
+    ku = keys.view(np.uint32).astype(np.int64)
+    order = np.argsort(-ku if desc else ku, kind="stable")
+    assert np.array_equal(io.cpu().numpy(), order.astype(np.int32))
+    assert np.array_equal(ko.cpu().numpy(), keys[order])
 
 
 def test_transpose_small_and_ragged(torch_dev):
