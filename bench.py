@@ -11,11 +11,15 @@ check passes, and the final Rayleigh-Ritz step.
 Printed: one JSON line with the metric, the roofline of the dominant kernel
 (the SpMM, the two sparse products of every pass, timed with HIP events on
 the stream it runs on inside the timed region) with its counter traffic, the
-Jacobi eigensolver against the FP64 ALU of its one CU, the Cholesky-QR pass
-solver's time, the other forms of the metric (BF16 panels, learned shift,
-batched), and the CPU oracle timed on the host cores.
+Jacobi eigensolver against the FP64 ALU of its one CU and of the chip, the
+Gram against the FP64 MFMA peak, the Cholesky-QR pass solver's time, the
+other forms of the metric (BF16 panels, learned shift, the accuracy control
+without the surrogate, batched, and BF16 against FP32 panels on the
+2,000,000 x 1,000,000 workload at tol 1e-2 and 1e-3), and the CPU oracle
+timed on the host cores (with the CPU model, and one 2000 x 1500 solve on one
+thread and on all of them).
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-forms]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-forms] [--no-c3]
   python bench.py --copy-probe   (a plain 1 GiB device copy, three times: the
                                   reference that calibrates the HBM counters)
   python bench.py --summarize-trace STATS_CSV COMMAND > kernel_stats.md
@@ -144,6 +148,77 @@ def batched_form(torch, steps):
                         "tol 1e-2, p_max 16"}
 
 
+def c3_forms(torch, stream, steps=2):
+    """zipf_2m (2,000,000 x 1,000,000, 100M nonzeros, Zipf 1.1, k = 100,
+    oversampling 50): BF16 panels against FP32 panels at tol 1e-2 and 1e-3,
+    each with its seconds per solve, passes and eps_PVE / eps_sigma against
+    the reference singular values of tests/golden (time-to-tolerance of the
+    two forms at the accuracy each reaches)."""
+    import synth
+    from paper_2404_09276_amd import DashSVD
+    A = synth.config_zipf_2m()
+
+    class Dev:
+        m, n, nnz = A.m, A.n, A.nnz
+        row_ptr = torch.from_numpy(A.row_ptr).cuda()
+        col = torch.from_numpy(A.col).cuda()
+        val = torch.from_numpy(A.val).cuda()
+    path = os.path.join(ROOT, "tests", "golden", "sigma_zipf_2m.json")
+    sig = np.array(json.load(open(path))["sigma"]) if os.path.exists(path) else None
+    out = {"workload": "zipf_2m: CSR 2000000x1000000, 100M nnz, Zipf 1.1 degrees, k=100, oversampling 50"}
+    for prec in ("bf16", "fp32"):
+        for tol in (1e-2, 1e-3):
+            h = DashSVD(precision=prec, p_max=64, seed=2003, stream=stream)
+            h.run(Dev, 100, 50, tol)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                h.run(Dev, 100, 50, tol)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t0) / steps
+            inf = h.info()
+            pve, es = h.evaluate(Dev, sig) if sig is not None else (None, None)
+            out[f"{prec}_tol{tol:g}"] = {"value": el, "unit": "s", "passes": inf.passes,
+                                         "converged": bool(inf.converged), "promoted": inf.promoted,
+                                         "eps_pve": pve, "eps_sigma": es}
+            h.close()
+    for tol in ("0.01", "0.001"):
+        b, f = out[f"bf16_tol{tol}"], out[f"fp32_tol{tol}"]
+        out[f"bf16_over_fp32_time_tol{tol}"] = b["value"] / f["value"]
+    del Dev
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_one_thread_small():
+    """One FP64 oracle solve of the 2000 x 1500 workload (k = 20,
+    oversampling 10, 5 passes) on one host thread and on all of them
+    (separate processes: OpenMP fixes its thread count at start)."""
+    import subprocess
+    code = ("import time, sys; sys.path.insert(0, %r); import numpy as np, oracle, synth; "
+            "A = synth.config_small(np.float64); t = time.perf_counter(); "
+            "[oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 20, 10, 5, 0.0, seed=2001) for _ in range(3)]; "
+            "print((time.perf_counter() - t) / 3, oracle.num_threads())" % ROOT)
+    res = {}
+    for label, env in (("one_thread", {"OMP_NUM_THREADS": "1"}), ("all_cores", {})):
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                           env=dict(os.environ, **env), timeout=600)
+        if r.returncode == 0:
+            t, thr = r.stdout.split()
+            res[label] = {"seconds": float(t), "threads": int(thr)}
+    return res
+
+
 def cpu_baseline(A, min_seconds=10.0):
     """The oracle as it stands on the host cores: full FP64 solves of the same
     workload (tol 1e-2, same Omega seed), repeated until min_seconds of CPU
@@ -159,8 +234,10 @@ def cpu_baseline(A, min_seconds=10.0):
             break
     t = (time.perf_counter() - t0) / runs
     return {"value": t, "unit": "s", "cores": oracle.num_threads(), "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"{runs} full solves of the workload (tol 1e-2, {passes} passes each), "
-                      f"mean seconds per solve"}
+                      f"mean seconds per solve",
+            "small_2000x1500_5_passes": cpu_one_thread_small()}
 
 
 def source_digest(*names):
@@ -294,6 +371,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("STATS_CSV", "COMMAND"))
     ap.add_argument("--summarize-pmc", nargs="+", metavar="ARG")
@@ -356,6 +434,10 @@ def main():
     # behind accepted Cholesky-QR calls and return at once)
     jac_calls = int(sum(max(0, i.eig_calls - i.cholqr_calls - 1) for i in dinfos))
     eig_tf = jacobi_flops(l, sweeps) / (eig_ms * 1e-3) / 1e12 if eig_ms else 0.0
+    # Gram of the pass blocks: the method's n l (l + 1) FP64 flops (upper
+    # triangle of C^T C) over the event time of a Gram launch (partials and
+    # their sum)
+    gram_tf = A.n * l * (l + 1) / (avg["gram"] * 1e-3) / 1e12 if avg["gram"] else 0.0
     out = {
         "metric": METRIC, "value": ms / 1e3, "unit": "s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": False, "scaling": "weak",
@@ -377,7 +459,11 @@ def main():
                          "frac": eig_tf / CU_FP64_TFLOPS, "traffic": traffic("eig"),
                          "flops_per_sweep": jacobi_flops(l, 1), "sweeps_timed": sweeps,
                          "avg_ms_per_call": eig_ms / jac_calls if jac_calls else 0.0,
-                         "peak_basis": "FP64 vector peak of the one CU the kernel runs on (78.6 TFLOP/s / 256)"},
+                         "peak_basis": "FP64 vector peak of the one CU the kernel runs on (78.6 TFLOP/s / 256)",
+                         "frac_of_chip_fp64": eig_tf / 78.6},
+        "roofline_gram": {"bound": "mfma", "kernel": "k_gram_partial + k_gram_reduce (FP64 MFMA, C^T C)",
+                          "achieved": gram_tf, "peak": 78.6, "unit": "TFLOP/s", "frac": gram_tf / 78.6,
+                          "flops_per_launch": A.n * l * (l + 1), "avg_ms": avg["gram"]},
         "cholqr": {"kernel": "k_cholqr (Cholesky-QR weights and Sturm-bisection eigenvalues, two workgroups)",
                    "calls_per_step": cnt["cholqr"] / ndetail, "avg_ms_per_launch": avg["cholqr"]},
         "kernel_groups_ms_per_step": {g: tot[g] / ndetail for g in tot},
@@ -397,7 +483,15 @@ def main():
                                              "fell_back": infl[-1].learned_fallback,
                                              "predicted_passes": infl[-1].learned_n,
                                              "eps_pve": pvel, "eps_sigma": esl}
+        eln, infn, pven, esn, _ = run_form(torch, Dev, nf, 1, stream, precision="fp32", pve_mode="nosurr")
+        out["forms"]["no_surrogate"] = {"value": eln / nf, "unit": "s", "passes": infn[-1].passes,
+                                        "eps_pve": pven, "eps_sigma": esn,
+                                        "time_over_surrogate": (eln / nf) / (ms / 1e3),
+                                        "about": "accuracy control without the surrogate (Sec. 4.3): "
+                                                 "sigma(A Q) after every pass, eq. (18)"}
         out["forms"]["batched"] = batched_form(torch, 3)
+        if not args.no_c3:
+            out["forms"]["c3"] = c3_forms(torch, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A)
     print(json.dumps(out), flush=True)

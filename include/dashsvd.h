@@ -150,6 +150,11 @@ typedef struct {
                              by non-increasing nonzero count (memory locality of the
                              products); U and V are returned in the caller's order.
                              AUTO (0): on from DASHSVD_REORDER_MIN_NNZ nonzeros */
+  int32_t slab_kib;       /* > 0: the SpMM cuts the long rows also at column-slab
+                             boundaries and runs their chunks slab by slab, each slab
+                             covering about this many KiB of gathered panel rows (one
+                             slab at a time in every XCD's L2); <= 0 (default): no
+                             slabs, chunks in row order */
 } dashsvd_options;
 
 #define DASHSVD_REORDER_AUTO 0

@@ -139,9 +139,17 @@ template <typename T, typename A, int N> __device__ __forceinline__ void load_n(
 // Row-split SpMM plan: rows longer than long_row nonzeros are cut into
 // chunks of long_row; each chunk writes a partial row, then one task per
 // long row sums its chunks in order (deterministic).
+// A chunk of a long row: nonzeros [begin, begin + len) of the row; its
+// partial row goes to slot `slot` of the partial buffer (the slots of a row
+// are consecutive, in column order).
 struct ChunkTask {
-  int64_t begin, end;
+  int64_t begin;
+  int32_t len;
+  int32_t slot;
 };
+// Long-row chunks are cut at column-slab boundaries (2^slab_log2 columns of
+// the gathered panel) and run slab by slab; at most kMaxSlabs slabs.
+constexpr int kMaxSlabs = 4096;
 struct LongRow {
   int64_t row, first;
   int64_t nch;
@@ -242,10 +250,19 @@ hipError_t launch_transpose_gather(int64_t nnz, const int32_t *rowidx, const voi
 // the two SpMM plans), so that the host reads them with one copy.
 hipError_t launch_plan_sizes(const int64_t *endM, const int64_t *endT, const int32_t *nlM, const int32_t *nlT,
                              int64_t *out, hipStream_t st);
-hipError_t launch_plan_count(int64_t R, const int64_t *rp, int32_t long_row, int64_t *nch,
-                             hipStream_t st);
-hipError_t launch_plan_fill(int64_t R, const int64_t *rp, int32_t long_row, const int64_t *off,
-                            ChunkTask *tasks, LongRow *longs, int32_t *nlong, hipStream_t st);
+// SpMM row-split plan: rows longer than long_row are cut into chunks at the
+// column-slab boundaries (slab_log2 >= 31: no slabs) and into pieces of at
+// most long_row nonzeros.  nch[r]: chunks of row r; tasks (slot order) and
+// tslab: each chunk and its slab; launch_plan_order then lists the chunks
+// slab by slab in `order` (slab_cnt: 2 (kMaxSlabs + 1) zeroed words; the
+// chunk count is read on the device at off[R]).
+hipError_t launch_plan_count(int64_t R, const int64_t *rp, const int32_t *col, int32_t long_row, int slab_log2,
+                             int64_t *nch, hipStream_t st);
+hipError_t launch_plan_fill(int64_t R, const int64_t *rp, const int32_t *col, int32_t long_row, int slab_log2,
+                            const int64_t *off, ChunkTask *tasks, int32_t *tslab, LongRow *longs, int32_t *nlong,
+                            hipStream_t st);
+hipError_t launch_plan_order(int nslabs, const int64_t *n_chunks, const ChunkTask *tasks, const int32_t *tslab,
+                             int32_t *slab_cnt, ChunkTask *order, hipStream_t st);
 
 // SpMM: Y = A X (- alpha Q).  dtypes: 0 f32, 1 f64, 2 bf16.
 hipError_t launch_spmm(int64_t R, const int64_t *rp, const int32_t *col, const void *val, int vdtype,

@@ -73,11 +73,32 @@ struct Plan {
   int64_t R = 0;
   int64_t n_chunks = 0, n_long = 0;
   int64_t *nch = nullptr, *off = nullptr;
-  ChunkTask *tasks = nullptr;
+  ChunkTask *tasks = nullptr;  // chunks in slot order
+  ChunkTask *order = nullptr;  // the same chunks slab by slab (the launch order)
+  int32_t *tslab = nullptr;    // slab of each chunk (slot order)
+  int32_t *slab_cnt = nullptr; // 2 (kMaxSlabs + 1) words, zero before the build
+  int slab_log2 = 31, nslabs = 1;
   LongRow *longs = nullptr;
   int32_t *nlong = nullptr;
   void *partial = nullptr;
 };
+
+// Column-slab width (log2, in columns of the operator = rows of the gathered
+// panel) of the long-row chunks: about slab_bytes of panel rows, a power of
+// two, at most kMaxSlabs slabs; 31 = no cuts (one slab, or slab_bytes <= 0,
+// the default: on the 10M-nonzero power-law benchmark matrix, slabs of 512
+// KiB to 8 MiB made the product of A 8-10 % slower, every chunk of the long
+// rows being resident at once anyway).
+int slab_log2_for(int64_t ncols, int64_t row_bytes, int64_t slab_bytes) {
+  if (ncols <= 0 || slab_bytes <= 0 || row_bytes <= 0) return 31;
+  int64_t w = slab_bytes / row_bytes;
+  if (w < 1) w = 1;
+  int lg = 0;
+  while (lg < 30 && ((int64_t)2 << lg) <= w) ++lg;
+  while (lg < 30 && ((ncols - 1) >> lg) + 1 > kMaxSlabs) ++lg;
+  if (((int64_t)1 << lg) >= ncols) return 31;
+  return lg;
+}
 
 }  // namespace
 
@@ -256,20 +277,43 @@ dashsvd_status ensure_arena(dashsvd_handle *h, size_t bytes) {
   return DASHSVD_OK;
 }
 
-// Row-split plan of a CSR with R rows (two phases around a host read).
+// Row-split plan of a CSR with R rows and ncols columns (two phases around a
+// host read).  A long row has at most len / T + 1 chunks of T plus one cut
+// per slab boundary it crosses.
 dashsvd_status plan_alloc(dashsvd_handle *h, Arena &ar, Plan &p, int64_t R, int64_t nnz, int32_t T,
-                          int ld, size_t acc_sz) {
+                          int ld, size_t acc_sz, int64_t ncols = 0, int64_t row_bytes = 0,
+                          int64_t slab_bytes = 0) {
   p.R = R;
-  const int64_t max_chunks = 2 * (nnz / T) + 1;
+  p.slab_log2 = slab_log2_for(ncols, row_bytes, slab_bytes);
+  p.nslabs = p.slab_log2 >= 31 ? 1 : (int)(((ncols - 1) >> p.slab_log2) + 1);
   const int64_t max_long = nnz / T + 1;
+  const int64_t max_chunks = 2 * (nnz / T) + 1 + (p.nslabs > 1 ? max_long * (p.nslabs - 1) : 0);
   p.nch = (int64_t *)ar.take(sizeof(int64_t) * (size_t)(R + 1));
   p.off = (int64_t *)ar.take(sizeof(int64_t) * (size_t)(R + 2));
   p.tasks = (ChunkTask *)ar.take(sizeof(ChunkTask) * (size_t)max_chunks);
+  p.order = (ChunkTask *)ar.take(sizeof(ChunkTask) * (size_t)max_chunks);
+  p.tslab = (int32_t *)ar.take(sizeof(int32_t) * (size_t)max_chunks);
+  p.slab_cnt = (int32_t *)ar.take(sizeof(int32_t) * 2 * (size_t)(kMaxSlabs + 1));
   p.longs = (LongRow *)ar.take(sizeof(LongRow) * (size_t)max_long);
   p.nlong = (int32_t *)ar.take(sizeof(int32_t) * 4);
   p.partial = ar.take(acc_sz * (size_t)ld * (size_t)max_chunks);
   (void)h;
   return DASHSVD_OK;
+}
+
+// The plan's kernels: chunk counts, their scan, the chunks in slot order and
+// then slab by slab (p.nlong and p.slab_cnt zeroed beforehand).
+hipError_t plan_build(Plan &p, const int64_t *rp, const int32_t *col, int32_t T, int64_t *scan_tmp, hipStream_t st) {
+  hipError_t e = launch_plan_count(p.R, rp, col, T, p.slab_log2, p.nch, st);
+  if (e == hipSuccess) e = launch_scan_i64(p.nch, p.R, p.off, scan_tmp, st);
+  if (e == hipSuccess) e = launch_plan_fill(p.R, rp, col, T, p.slab_log2, p.off, p.tasks, p.tslab, p.longs, p.nlong, st);
+  // one slab: the chunks run in slot order (row by row)
+  if (p.nslabs <= 1) {
+    p.order = p.tasks;
+    return e;
+  }
+  if (e == hipSuccess) e = launch_plan_order(p.nslabs, p.off + p.R, p.tasks, p.tslab, p.slab_cnt, p.order, st);
+  return e;
 }
 
 struct RunBufs {
@@ -528,8 +572,12 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   b.tws = ar.take(b.tws_bytes);
   const int64_t scan_n = (m > n ? m : n) + 1;
   b.scan_tmp = (int64_t *)ar.take(8 * scan_tmp_elems(scan_n));
-  plan_alloc(h, ar, b.planM, Mm, nnz, T, ldc, accsz);
-  plan_alloc(h, ar, b.planT, Mn, nnz, T, ldc, accsz);
+  // long-row chunks cut at slabs of the gathered panel: M gathers rows of
+  // the n-side panels (C, Q), M^T rows of the m-side ones (Z, Y)
+  const int64_t prow_b = (int64_t)ld * (int64_t)dsz(pdt);
+  const int64_t slab_b = h->opt.slab_kib > 0 ? (int64_t)h->opt.slab_kib << 10 : 0;
+  plan_alloc(h, ar, b.planM, Mm, nnz, T, ldc, accsz, Mn, prow_b, slab_b);
+  plan_alloc(h, ar, b.planT, Mn, nnz, T, ldc, accsz, Mm, prow_b, slab_b);
   b.Y = ar.take(dsz(pdt) * (size_t)Mm * ld);
   b.Q = ar.take(dsz(pdt) * (size_t)Mn * ld);
   b.C = ar.take(dsz(cdt) * (size_t)Mn * ld);
@@ -631,6 +679,8 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     z.add(b.flags, 4 * 8);
     z.add(b.planM.nlong, 16);
     z.add(b.planT.nlong, 16);
+    z.add(b.planM.slab_cnt, 8 * (size_t)(kMaxSlabs + 1));
+    z.add(b.planT.slab_cnt, 8 * (size_t)(kMaxSlabs + 1));
     z.add(b.state, sizeof(SolverState));
     z.add(b.Sprev, 8 * (size_t)l);
     z.add(b.Ebp, 8 * (size_t)l);
@@ -698,14 +748,8 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   const int32_t *mapM = reorder ? (wide ? b.perm_c : b.perm_r) : nullptr;
   const int32_t *mapN = reorder ? (wide ? b.perm_r : b.perm_c) : nullptr;
   // SpMM plans
-  Plan *plans[2] = {&b.planM, &b.planT};
-  const int64_t *rps[2] = {rpM, rpMT};
-  for (int i = 0; i < 2; ++i) {
-    Plan &pl = *plans[i];
-    HIPCHK(launch_plan_count(pl.R, rps[i], T, pl.nch, st));
-    HIPCHK(launch_scan_i64(pl.nch, pl.R, pl.off, b.scan_tmp, st));
-    HIPCHK(launch_plan_fill(pl.R, rps[i], T, pl.off, pl.tasks, pl.longs, pl.nlong, st));
-  }
+  HIPCHK(plan_build(b.planM, rpM, colM, T, b.scan_tmp, st));
+  HIPCHK(plan_build(b.planT, rpMT, colMT, T, b.scan_tmp, st));
   // the four plan sizes in one device buffer (the scan workspace is free
   // again), one copy to pinned memory, one wait
   int64_t *sizes_d = b.sizes;
@@ -836,7 +880,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       // every CU first, so they wait (bounded) until it is resident.
       if ((e = launch_wait_started(&b.state->eig_started, ea.call_idx, st)) != hipSuccess) return e;
       tmark_begin(h, DASHSVD_KT_SPMM, pass);
-      e = launch_spmm(Mm, rpM, colM, valM, vdt, Cin, ld, cdt, b.Z, ld, cdt, ldc, b.planM.n_chunks, b.planM.tasks,
+      e = launch_spmm(Mm, rpM, colM, valM, vdt, Cin, ld, cdt, b.Z, ld, cdt, ldc, b.planM.n_chunks, b.planM.order,
                       b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, skip, st, nullptr,
                       nullptr, Mn);
       tmark_end(h);
@@ -846,7 +890,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       // block stops the iteration before the product's workgroups start,
       // they return at once (the live flag, not the pass-start snapshot;
       // Z above is kept, the final step uses it)
-      e = launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Z, ld, cdt, b.X, ld, cdt, ldc, b.planT.n_chunks, b.planT.tasks,
+      e = launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Z, ld, cdt, b.X, ld, cdt, ldc, b.planT.n_chunks, b.planT.order,
                       b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr, gate, st, nullptr,
                       nullptr, Mm);
       tmark_end(h);
@@ -884,7 +928,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     // sketch (Alg. 5 step 2): C = M^T Omega, its eigSVD || M C, M^T M C
     tmark_begin(h, DASHSVD_KT_SKETCH, 0);
     HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, Cb[0], ld, cdt, ldc, b.planT.n_chunks,
-                       b.planT.tasks, b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr,
+                       b.planT.order, b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr,
                        nullptr, st, nullptr, nullptr, Mm));
     tmark_end(h);
     HIPCHK(side(1, 0, Cb[0], nullptr));
@@ -984,7 +1028,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       tmark_end(h);
       if (e != hipSuccess) return e;
       tmark_begin(h, DASHSVD_KT_SPMM, pass);
-      e = launch_spmm(Mm, rpM, colM, valM, vdt, Qc, ld, pcur, Yc, ld, pcur, ldc, b.planM.n_chunks, b.planM.tasks,
+      e = launch_spmm(Mm, rpM, colM, valM, vdt, Qc, ld, pcur, Yc, ld, pcur, ldc, b.planM.n_chunks, b.planM.order,
                       b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, skip, st, nullptr,
                       nullptr, Mn);
       tmark_end(h);
@@ -992,7 +1036,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     };
     // sketch (Alg. 5 step 2): C = M^T Omega ; Q = eigSVD(C).U ; Y = M Q
     tmark_begin(h, DASHSVD_KT_SKETCH, 0);
-    HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ldc, b.planT.n_chunks, b.planT.tasks,
+    HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ldc, b.planT.n_chunks, b.planT.order,
                        b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr, nullptr, st,
                        nullptr, nullptr, Mm));
     tmark_end(h);
@@ -1005,7 +1049,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
         const int pass = launched + c + 1;
         tmark_begin(h, DASHSVD_KT_SPMM_T, pass);
         HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, Yc, ld, pcur, b.C, ld, cdt, ldc, b.planT.n_chunks,
-                           b.planT.tasks, b.planT.n_long, b.planT.longs, b.planT.partial, T, Qc, ld,
+                           b.planT.order, b.planT.n_long, b.planT.longs, b.planT.partial, T, Qc, ld,
                            &b.state->alpha, done, st, nullptr, nullptr, Mm));
         tmark_end(h);
         HIPCHK(block_step(2, pass, done));
@@ -1025,7 +1069,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
           promoted = 1;
           HIPCHK(launch_rescale(Mn, l, b.C, ld, cdt, b.W, l, l, Qc, ld, pcur, nullptr, st));
           HIPCHK(launch_spmm(Mm, rpM, colM, valM, vdt, Qc, ld, pcur, Yc, ld, pcur, ldc, b.planM.n_chunks,
-                             b.planM.tasks, b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0,
+                             b.planM.order, b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0,
                              nullptr, nullptr, st, nullptr, nullptr, Mn));
         }
       }
@@ -1066,7 +1110,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     if (pfin != cdt) {
       // the BF16 form keeps an FP32 B
       HIPCHK(launch_spmm(Mm, rpM, colM, valM, vdt, Qfin, ld, pfin, b.B, ld, cdt, ldc, b.planM.n_chunks,
-                         b.planM.tasks, b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr,
+                         b.planM.order, b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr,
                          nullptr, st, nullptr, nullptr, Mn));
     } else {
       // promoted to FP32 panels: B is the last M Q
@@ -1303,7 +1347,7 @@ static dashsvd_status evaluate_core(dashsvd_handle *h, const dashsvd_csr *A, con
   HIPCHK(launch_copy2d(h->U, k, h->out_dt, Upad, ld8, c.cdt, urows, k, st, c.u_row_to));
   const Plan &pl = c.plan[side];
   HIPCHK(launch_spmm(zrows, c.rp[side], c.col[side], c.val[side], c.vdt, Upad, ld8, c.cdt, Z, ld8, c.cdt, ld8,
-                     pl.n_chunks, pl.tasks, pl.n_long, pl.longs, pl.partial, c.T, nullptr, 0, nullptr, nullptr,
+                     pl.n_chunks, pl.order, pl.n_long, pl.longs, pl.partial, c.T, nullptr, 0, nullptr, nullptr,
                      st, nullptr, nullptr, urows));
   // ||A^T u_i||^2 = (Z^T Z)_ii in FP64
   HIPCHK(launch_gram(zrows, k, Z, ld8, c.cdt, c.gpart, gram_blocks(zrows, k), c.G, nullptr, st, nullptr));
@@ -1433,7 +1477,7 @@ dashsvd_status dashsvd_evaluate_all(dashsvd_handle *h, const dashsvd_csr *A, con
     // y = A q - U (S .* (V^T q))
     run(launch_copy2d(q, 1, DASHSVD_F64, pan_n, 8, c.cdt, n, 1, st));
     run(launch_spmm(m, c.rp[sideA], c.col[sideA], c.val[sideA], c.vdt, pan_n, 8, c.cdt, pan_m, 8, c.cdt, 8,
-                    pA.n_chunks, pA.tasks, pA.n_long, pA.longs, pA.partial, c.T, nullptr, 0, nullptr, nullptr, st,
+                    pA.n_chunks, pA.order, pA.n_long, pA.longs, pA.partial, c.T, nullptr, 0, nullptr, nullptr, st,
                     nullptr, nullptr, n));
     run(launch_dots(n, k, Vcm, n, q, part, t1, st));
     run(launch_copy2d(pan_m, 8, c.cdt, y, 1, DASHSVD_F64, m, 1, st));
@@ -1441,7 +1485,7 @@ dashsvd_status dashsvd_evaluate_all(dashsvd_handle *h, const dashsvd_csr *A, con
     // w = A^T y - V (S .* (U^T y))
     run(launch_copy2d(y, 1, DASHSVD_F64, pan_m, 8, c.cdt, m, 1, st));
     run(launch_spmm(n, c.rp[sideAT], c.col[sideAT], c.val[sideAT], c.vdt, pan_m, 8, c.cdt, pan_n, 8, c.cdt, 8,
-                    pT.n_chunks, pT.tasks, pT.n_long, pT.longs, pT.partial, c.T, nullptr, 0, nullptr, nullptr, st,
+                    pT.n_chunks, pT.order, pT.n_long, pT.longs, pT.partial, c.T, nullptr, 0, nullptr, nullptr, st,
                     nullptr, nullptr, m));
     run(launch_dots(m, k, Ucm, m, y, part, t1, st));
     run(launch_copy2d(pan_n, 8, c.cdt, w, 1, DASHSVD_F64, n, 1, st));
@@ -1554,8 +1598,10 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
   b.tws_bytes = transpose_ws_bytes(n, nnz);
   b.tws = ar.take(b.tws_bytes);
   b.scan_tmp = (int64_t *)ar.take(8 * scan_tmp_elems(std::max(m, n) + 1));
-  plan_alloc(h, ar, b.planM, m, nnz, T, ld, accsz);
-  plan_alloc(h, ar, b.planT, n, nnz, T, ld, accsz);
+  const int64_t bprow_b = (int64_t)ld * (int64_t)dsz(pdt);
+  const int64_t bslab_b = h->opt.slab_kib > 0 ? (int64_t)h->opt.slab_kib << 10 : 0;
+  plan_alloc(h, ar, b.planM, m, nnz, T, ld, accsz, n, bprow_b, bslab_b);
+  plan_alloc(h, ar, b.planT, n, nnz, T, ld, accsz, m, bprow_b, bslab_b);
   b.Y = ar.take(dsz(pdt) * (size_t)m * ld);
   b.Q = ar.take(dsz(pdt) * (size_t)n * ld);
   b.C = ar.take(dsz(cdt) * (size_t)n * ld);
@@ -1597,6 +1643,8 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
   HIPCHK(hipMemsetAsync(b.flags, 0, 4 * 8, st));
   HIPCHK(hipMemsetAsync(b.planM.nlong, 0, 16, st));
   HIPCHK(hipMemsetAsync(b.planT.nlong, 0, 16, st));
+  HIPCHK(hipMemsetAsync(b.planM.slab_cnt, 0, 8 * (size_t)(kMaxSlabs + 1), st));
+  HIPCHK(hipMemsetAsync(b.planT.slab_cnt, 0, 8 * (size_t)(kMaxSlabs + 1), st));
   HIPCHK(hipMemsetAsync(b.state, 0, sizeof(SolverState) * (size_t)count, st));
   HIPCHK(hipMemsetAsync(b.Sprev, 0, 8 * (size_t)l * count, st));
   HIPCHK(hipMemsetAsync(b.tr_alpha, 0, 8 * (size_t)cap * count, st));
@@ -1628,14 +1676,8 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
   if ((hflags[0] & 1) || (hflags[2] & 1)) return fail(h, DASHSVD_ERR_BAD_CSR, "row_ptr/col_idx malformed");
   if (hflags[0] & 2) return fail(h, DASHSVD_ERR_NONFINITE, "NaN or Inf among the values");
   HIPCHK(launch_transpose(n, nnz, colA, b.rowidx, valA, vdt, b.rpT, b.colT, b.valT, b.tws, b.tws_bytes, st));
-  Plan *plans[2] = {&b.planM, &b.planT};
-  const int64_t *rps[2] = {rpA, b.rpT};
-  for (int i = 0; i < 2; ++i) {
-    Plan &pl = *plans[i];
-    HIPCHK(launch_plan_count(pl.R, rps[i], T, pl.nch, st));
-    HIPCHK(launch_scan_i64(pl.nch, pl.R, pl.off, b.scan_tmp, st));
-    HIPCHK(launch_plan_fill(pl.R, rps[i], T, pl.off, pl.tasks, pl.longs, pl.nlong, st));
-  }
+  HIPCHK(plan_build(b.planM, rpA, colA, T, b.scan_tmp, st));
+  HIPCHK(plan_build(b.planT, b.rpT, b.colT, T, b.scan_tmp, st));
   int64_t totals[2] = {0, 0};
   int32_t nlongs[2] = {0, 0};
   HIPCHK(hipMemcpyAsync(&totals[0], b.planM.off + b.planM.R, 8, hipMemcpyDeviceToHost, st));
@@ -1710,13 +1752,13 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
       e = launch_brescale(itN_d, nIN, l, b.C, nullptr, ld, cdt, b.W, (int64_t)ll, l, l, Qc, ld, pc, b.state,
                           gate, st);
     if (e == hipSuccess)
-      e = launch_spmm(m, rpA, colA, valA, vdt, Qc, ld, pc, Yc, ld, pc, ld, b.planM.n_chunks, b.planM.tasks,
+      e = launch_spmm(m, rpA, colA, valA, vdt, Qc, ld, pc, Yc, ld, pc, ld, b.planM.n_chunks, b.planM.order,
                       b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, nullptr, st,
                       gate ? rowmatM : nullptr, b.state, n);
     return e;
   };
   // sketch: C = M^T Omega, eigSVD, Y = M Q
-  HIPCHK(launch_spmm(n, b.rpT, b.colT, b.valT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ld, b.planT.n_chunks, b.planT.tasks,
+  HIPCHK(launch_spmm(n, b.rpT, b.colT, b.valT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ld, b.planT.n_chunks, b.planT.order,
                      b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr, nullptr, st, nullptr,
                      nullptr, m));
   HIPCHK(block(1, 0));
@@ -1725,7 +1767,7 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
     hipError_t e = launch_bsnap(b.state, count, 1, st);
     if (e == hipSuccess)
       e = launch_spmm(n, b.rpT, b.colT, b.valT, vdt, Yc, ld, pc, b.C, ld, cdt, ld, b.planT.n_chunks,
-                      b.planT.tasks, b.planT.n_long, b.planT.longs, b.planT.partial, T, Qc, ld, &b.state->alpha,
+                      b.planT.order, b.planT.n_long, b.planT.longs, b.planT.partial, T, Qc, ld, &b.state->alpha,
                       nullptr, st, rowmatN, b.state, m);
     if (e == hipSuccess) e = block(2, 1);
     return e;
@@ -1782,7 +1824,7 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
                                 1, st);
         if (eloop == hipSuccess)
           eloop = launch_spmm(m, rpA, colA, valA, vdt, Qc, ld, pc, Yc, ld, pc, ld, b.planM.n_chunks,
-                              b.planM.tasks, b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0,
+                              b.planM.order, b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0,
                               nullptr, nullptr, st, rowmatM, b.state, n);
         if (eloop == hipSuccess) sloop = capture();
       }
@@ -1797,7 +1839,7 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
   // final Rayleigh-Ritz of every matrix: B = M Q, eigSVD(B), U = B W(:,1:k),
   // V = Q Vs(:,1:k), signs
   HIPCHK(launch_bsnap(b.state, count, 0, st));
-  HIPCHK(launch_spmm(m, rpA, colA, valA, vdt, Qc, ld, pc, b.B, ld, cdt, ld, b.planM.n_chunks, b.planM.tasks,
+  HIPCHK(launch_spmm(m, rpA, colA, valA, vdt, Qc, ld, pc, b.B, ld, cdt, ld, b.planM.n_chunks, b.planM.order,
                      b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, nullptr, st, nullptr,
                      nullptr, n));
   HIPCHK(launch_bgram(itM_d, nIM, ioffM_d, count, l, b.B, ld, cdt, bpart, b.G, (int64_t)ll, b.state, 0, st));
@@ -2355,7 +2397,8 @@ void spmm_layout(const SpmmCall &c, Arena &a, Plan &pl, int64_t **scan_tmp) {
   const int ld = (int)round_up(c.l, 8);
   const size_t accsz = c.xdtype == DASHSVD_F64 ? 8 : 4;
   const int32_t T = c.long_row > 0 ? c.long_row : kDefaultLongRow;
-  plan_alloc(nullptr, a, pl, c.rows, c.nnz, T, ld, accsz);
+  const size_t xsz = c.xdtype == DASHSVD_F64 ? 8 : (c.xdtype == DASHSVD_BF16 ? 2 : 4);
+  plan_alloc(nullptr, a, pl, c.rows, c.nnz, T, ld, accsz, c.cols, c.ldx * (int64_t)xsz, 0);
   *scan_tmp = (int64_t *)a.take(8 * scan_tmp_elems(c.rows + 1));
 }
 
@@ -2383,10 +2426,9 @@ hipError_t spmm_run_on(const SpmmCall &c, char *base, size_t cap) {
   spmm_layout(c, a, pl, &scan_tmp);
   ZeroRanges z{};
   z.add(pl.nlong, 16);
+  z.add(pl.slab_cnt, 8 * (size_t)(kMaxSlabs + 1));
   hipError_t e = launch_zero_ranges(z, c.st);
-  if (e == hipSuccess) e = launch_plan_count(c.rows, c.row_ptr, T, pl.nch, c.st);
-  if (e == hipSuccess) e = launch_scan_i64(pl.nch, c.rows, pl.off, scan_tmp, c.st);
-  if (e == hipSuccess) e = launch_plan_fill(c.rows, c.row_ptr, T, pl.off, pl.tasks, pl.longs, pl.nlong, c.st);
+  if (e == hipSuccess) e = plan_build(pl, c.row_ptr, c.col, T, scan_tmp, c.st);
   int64_t tot = 0;
   int32_t nl = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&tot, pl.off + c.rows, 8, hipMemcpyDeviceToHost, c.st);
@@ -2394,7 +2436,7 @@ hipError_t spmm_run_on(const SpmmCall &c, char *base, size_t cap) {
   if (e == hipSuccess) e = hipStreamSynchronize(c.st);
   if (e == hipSuccess)
     e = launch_spmm(c.rows, c.row_ptr, c.col, c.val, vdt, c.X, c.ldx, c.xdtype, c.Y, c.ldy, c.ydtype, ld, tot,
-                    pl.tasks, nl, pl.longs, pl.partial, T, c.Q, c.ldq, c.alpha, nullptr, c.st, nullptr, nullptr,
+                    pl.order, nl, pl.longs, pl.partial, T, c.Q, c.ldq, c.alpha, nullptr, c.st, nullptr, nullptr,
                     c.cols);
   if (e == hipSuccess) e = hipStreamSynchronize(c.st);
   return e;

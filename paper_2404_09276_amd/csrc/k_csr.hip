@@ -351,20 +351,52 @@ unsigned key_bits(int64_t n) {
 }
 
 // ------------------------------------------------------------------ SpMM plan
+// Long rows are cut at column-slab boundaries and then into pieces of at most
+// long_row nonzeros; the products run the chunks slab by slab, so the panel
+// rows every compute unit gathers at a time come from one slab, which stays
+// in each XCD's L2.  Each chunk writes its own partial slot, and the slots of
+// a row are summed in slot order, so the results do not depend on the order
+// the chunks run in.
+
+// first position in col[lo, hi) whose column is >= key (columns sorted)
+__device__ __forceinline__ int64_t lower_col(const int32_t *__restrict__ col, int64_t lo, int64_t hi, int64_t key) {
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)col[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
 __global__ __launch_bounds__(256) void k_plan_count(int64_t R, const int64_t *__restrict__ rp,
-                                                    int32_t long_row, int64_t *__restrict__ nch) {
+                                                    const int32_t *__restrict__ col, int32_t long_row,
+                                                    int slab_log2, int64_t *__restrict__ nch) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += stride) {
-    const int64_t len = rp[r + 1] - rp[r];
-    nch[r] = len > long_row ? (len + long_row - 1) / long_row : 0;
+    const int64_t b = rp[r], e = rp[r + 1], len = e - b;
+    if (len <= long_row) {
+      nch[r] = 0;
+      continue;
+    }
+    if (slab_log2 >= 31) {
+      nch[r] = (len + long_row - 1) / long_row;
+      continue;
+    }
+    int64_t cnt = 0;
+    for (int64_t pos = b; pos < e;) {
+      const int64_t s = (int64_t)col[pos] >> slab_log2;
+      const int64_t q = lower_col(col, pos, e, (s + 1) << slab_log2);
+      cnt += (q - pos + long_row - 1) / long_row;
+      pos = q;
+    }
+    nch[r] = cnt;
   }
 }
 
 __global__ __launch_bounds__(256) void k_plan_fill(int64_t R, const int64_t *__restrict__ rp,
-                                                   int32_t long_row, const int64_t *__restrict__ off,
-                                                   ChunkTask *__restrict__ tasks,
-                                                   LongRow *__restrict__ longs,
-                                                   int32_t *__restrict__ nlong) {
+                                                   const int32_t *__restrict__ col, int32_t long_row,
+                                                   int slab_log2, const int64_t *__restrict__ off,
+                                                   ChunkTask *__restrict__ tasks, int32_t *__restrict__ tslab,
+                                                   LongRow *__restrict__ longs, int32_t *__restrict__ nlong) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += stride) {
     const int64_t b = rp[r], e = rp[r + 1];
@@ -376,12 +408,78 @@ __global__ __launch_bounds__(256) void k_plan_fill(int64_t R, const int64_t *__r
     lr.first = off[r];
     lr.nch = nc;
     longs[slot] = lr;
-    for (int64_t c = 0; c < nc; ++c) {
-      ChunkTask t;
-      t.begin = b + c * long_row;
-      t.end = t.begin + long_row < e ? t.begin + long_row : e;
-      tasks[off[r] + c] = t;
+    int64_t t = off[r];
+    for (int64_t pos = b; pos < e;) {
+      const int64_t s = slab_log2 >= 31 ? 0 : (int64_t)col[pos] >> slab_log2;
+      const int64_t q = slab_log2 >= 31 ? e : lower_col(col, pos, e, (s + 1) << slab_log2);
+      for (int64_t c0 = pos; c0 < q; c0 += long_row, ++t) {
+        ChunkTask ct;
+        ct.begin = c0;
+        ct.len = (int32_t)(c0 + long_row < q ? long_row : q - c0);
+        ct.slot = (int32_t)t;
+        tasks[t] = ct;
+        tslab[t] = (int32_t)s;
+      }
+      pos = q;
     }
+  }
+}
+
+// chunks per slab (integer atomics: the counts do not depend on their order)
+// (slabs past the last one, which only a caller's short column count can
+// produce, join the last slab: the order is a matter of speed only)
+__global__ __launch_bounds__(256) void k_plan_slab_hist(int nslabs, const int64_t *__restrict__ n_chunks,
+                                                        const int32_t *__restrict__ tslab,
+                                                        int32_t *__restrict__ cnt) {
+  const int64_t n = *n_chunks;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride)
+    atomicAdd(&cnt[min(tslab[t], nslabs - 1)], 1);
+}
+
+// exclusive scan of the nslabs counts, in place (one workgroup)
+__global__ __launch_bounds__(1024) void k_plan_slab_scan(int nslabs, int32_t *__restrict__ cnt) {
+  __shared__ int32_t part[1024];
+  constexpr int kPer = (kMaxSlabs + 1023) / 1024;
+  const int tid = threadIdx.x;
+  int32_t v[kPer];
+  int32_t sum = 0;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int i = tid * kPer + q;
+    v[q] = i < nslabs ? cnt[i] : 0;
+    sum += v[q];
+  }
+  part[tid] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int32_t x = tid >= o ? part[tid - o] : 0;
+    __syncthreads();
+    part[tid] += x;
+    __syncthreads();
+  }
+  int32_t run = part[tid] - sum;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int i = tid * kPer + q;
+    if (i < nslabs) cnt[i] = run;
+    run += v[q];
+  }
+}
+
+// chunk t to the next free place of its slab (the order inside a slab is
+// free: every chunk writes its own slot)
+__global__ __launch_bounds__(256) void k_plan_slab_place(int nslabs, const int64_t *__restrict__ n_chunks,
+                                                         const ChunkTask *__restrict__ tasks,
+                                                         const int32_t *__restrict__ tslab,
+                                                         const int32_t *__restrict__ start,
+                                                         int32_t *__restrict__ fill,
+                                                         ChunkTask *__restrict__ order) {
+  const int64_t n = *n_chunks;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+    const int32_t s = min(tslab[t], nslabs - 1);
+    order[start[s] + atomicAdd(&fill[s], 1)] = tasks[t];
   }
 }
 
@@ -544,18 +642,31 @@ hipError_t launch_plan_sizes(const int64_t *endM, const int64_t *endT, const int
   return hipGetLastError();
 }
 
-hipError_t launch_plan_count(int64_t R, const int64_t *rp, int32_t long_row, int64_t *nch,
-                             hipStream_t st) {
+hipError_t launch_plan_count(int64_t R, const int64_t *rp, const int32_t *col, int32_t long_row, int slab_log2,
+                             int64_t *nch, hipStream_t st) {
   if (R == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_plan_count, dim3(grid_for(R, 256, 16384)), dim3(256), 0, st, R, rp, long_row, nch);
+  hipLaunchKernelGGL(k_plan_count, dim3(grid_for(R, 256, 16384)), dim3(256), 0, st, R, rp, col, long_row, slab_log2,
+                     nch);
   return hipGetLastError();
 }
 
-hipError_t launch_plan_fill(int64_t R, const int64_t *rp, int32_t long_row, const int64_t *off,
-                            ChunkTask *tasks, LongRow *longs, int32_t *nlong, hipStream_t st) {
+hipError_t launch_plan_fill(int64_t R, const int64_t *rp, const int32_t *col, int32_t long_row, int slab_log2,
+                            const int64_t *off, ChunkTask *tasks, int32_t *tslab, LongRow *longs, int32_t *nlong,
+                            hipStream_t st) {
   if (R == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_plan_fill, dim3(grid_for(R, 256, 16384)), dim3(256), 0, st, R, rp, long_row, off,
-                     tasks, longs, nlong);
+  hipLaunchKernelGGL(k_plan_fill, dim3(grid_for(R, 256, 16384)), dim3(256), 0, st, R, rp, col, long_row, slab_log2,
+                     off, tasks, tslab, longs, nlong);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_order(int nslabs, const int64_t *n_chunks, const ChunkTask *tasks, const int32_t *tslab,
+                             int32_t *slab_cnt, ChunkTask *order, hipStream_t st) {
+  if (nslabs < 1 || nslabs > kMaxSlabs) return hipErrorInvalidValue;
+  int32_t *cnt = slab_cnt, *fill = slab_cnt + kMaxSlabs + 1;
+  hipLaunchKernelGGL(k_plan_slab_hist, dim3(256), dim3(256), 0, st, nslabs, n_chunks, tslab, cnt);
+  hipLaunchKernelGGL(k_plan_slab_scan, dim3(1), dim3(1024), 0, st, nslabs, cnt);
+  hipLaunchKernelGGL(k_plan_slab_place, dim3(256), dim3(256), 0, st, nslabs, n_chunks, tasks, tslab,
+                     (const int32_t *)cnt, fill, order);
   return hipGetLastError();
 }
 

@@ -13,11 +13,13 @@
 // per lane are in flight at once.
 //
 // Load balance (power-law degrees): rows with more than long_row nonzeros
-// are cut into chunks of long_row; each chunk is an independent task writing
-// a partial row, and a second kernel sums the chunks of each long row in
-// chunk order.  Nothing depends on scheduling order, so results repeat bit
-// for bit.  Tasks are numbered chunks first, then rows, so the heavy chunks
-// start early.
+// are cut into chunks (at column-slab boundaries, then into pieces of at most
+// long_row); each chunk is an independent task writing its own partial row,
+// and a second kernel sums the chunks of each long row in column order.
+// Nothing depends on scheduling order, so results repeat bit for bit.  Tasks
+// are numbered chunks first, then rows, so the heavy chunks start early; the
+// chunks run slab by slab, so the panel rows gathered at a time come from one
+// slab that each XCD's L2 holds.
 //
 // Gathers in flight: when the panel X is known to span less than 2 GB, the
 // gathers are raw buffer loads whose range check returns zero for offsets
@@ -91,12 +93,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(spmm_min_wa
   const int sub = lane / G, cl = lane - sub * G;
   if (sub >= rpw) return;
   const int64_t g = ((int64_t)blockIdx.x * 4 + wave) * rpw + sub;
-  int64_t b, e, row = -1;
+  int64_t b, e, row = -1, slot = 0;
   const double *alpha_row = alpha;
   if (g < n_chunks) {
     const ChunkTask t = tasks[g];
     b = t.begin;
-    e = t.end;
+    e = t.begin + t.len;
+    slot = t.slot;
   } else {
     row = g - n_chunks;
     if (row >= R) return;
@@ -198,7 +201,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(spmm_min_wa
     }
   }
   if (row < 0) {
-    store_n<TA, TA, V>(partial + g * ldp + cl * V, acc);
+    store_n<TA, TA, V>(partial + slot * ldp + cl * V, acc);
     return;
   }
   if constexpr (SHIFT) {

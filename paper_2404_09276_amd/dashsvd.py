@@ -50,7 +50,7 @@ class _Options(C.Structure):
                 ("long_row", C.c_int32), ("check_interval", C.c_int32), ("schedule", C.c_void_p),
                 ("omega", C.c_void_p), ("omega_dtype", C.c_int32), ("omega_on_device", C.c_int32),
                 ("timing", C.c_int32), ("tuning_db", C.c_char_p), ("eig_method", C.c_int32),
-                ("reorder", C.c_int32)]
+                ("reorder", C.c_int32), ("slab_kib", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -242,17 +242,18 @@ class DashSVD:
     def __init__(self, precision: str = "fp32", shift_policy: str = "paper", pve_mode: str = "r2",
                  p_max: int = -1, seed: int = 0, stream=None, long_row: int = 0,
                  check_interval: int = 1, schedule=None, omega=None, timing=False,
-                 tuning_db=None, eig_method: str = "auto", reorder="auto"):
+                 tuning_db=None, eig_method: str = "auto", reorder="auto", slab_kib: int = 0):
         self._h = C.c_void_p()
         self._keep = []
         opt = self._options(precision, shift_policy, pve_mode, p_max, seed, stream, long_row,
-                            check_interval, schedule, omega, timing, tuning_db, eig_method, reorder)
+                            check_interval, schedule, omega, timing, tuning_db, eig_method, reorder,
+                            slab_kib)
         st = lib().dashsvd_create(C.byref(self._h), C.byref(opt))
         _check(st, None)
 
     def _options(self, precision="fp32", shift_policy="paper", pve_mode="r2", p_max=-1, seed=0,
                  stream=None, long_row=0, check_interval=1, schedule=None, omega=None,
-                 timing=False, tuning_db=None, eig_method="auto", reorder="auto"):
+                 timing=False, tuning_db=None, eig_method="auto", reorder="auto", slab_kib=0):
         sched_arr = None
         if schedule is not None:
             sched_arr = np.ascontiguousarray(schedule, dtype=np.float64)
@@ -268,7 +269,8 @@ class DashSVD:
                         stream or None, long_row, check_interval,
                         _ptr(sched_arr).value if sched_arr is not None else None,
                         om_ptr, om_dt, om_dev, TIMING[timing],
-                        tuning_db.encode() if tuning_db else None, EIG[eig_method], REORDER[reorder])
+                        tuning_db.encode() if tuning_db else None, EIG[eig_method], REORDER[reorder],
+                        int(slab_kib))
 
     def set_workspace(self, buf):
         """dashsvd_set_workspace: run inside the caller's device buffer (a

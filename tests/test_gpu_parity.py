@@ -423,3 +423,18 @@ def test_caller_workspace(torch_dev):
                          seed=11)
     assert np.all(np.abs(Sb - ref.S) / ref.S <= 1e-5)
     h.close()
+
+
+def test_slab_cut_long_rows_match_oracle(torch_dev):
+    """Long rows cut also at column-slab boundaries (option slab_kib) and run
+    slab by slab: the same sigma and shifts as the oracle (FP32 bar) and as
+    the default row-order chunks, in the tall and the wide orientation."""
+    for shape in ((30000, 12000), (9000, 21000)):
+        A = synth.zipf_csr(shape[0], shape[1], 500000, seed=shape[0] + 3)
+        ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 20, 10, 4, 0.0, seed=31)
+        U, S, V, st, info, tr = _solve(A, 20, 10, 4, 0.0, 31, "fp32", long_row=64, slab_kib=16)
+        U0, S0, V0, st0, info0, tr0 = _solve(A, 20, 10, 4, 0.0, 31, "fp32", long_row=64)
+        assert st == 0 and info.long_chunks_A > info0.long_chunks_A
+        assert np.all(np.abs(S - ref.S) / ref.S <= 1e-5)
+        assert np.all(np.abs(S - S0) / S0 <= 1e-5)
+        assert np.allclose(info.alpha_used, ref.alpha, rtol=1e-5)
