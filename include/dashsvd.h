@@ -88,18 +88,26 @@ typedef int32_t dashsvd_status;
 #define DASHSVD_PVE_R1 1
 #define DASHSVD_PVE_NOSURR 2
 
-/* Orthonormalisation of the sketch and pass blocks (Alg. 3 inside Alg. 5).
- *   AUTO (default): Cholesky-QR.  W = R^-1 from G = C^T C = R^T R, so that
- *       Q = C W is orthonormal with the span of eigSVD's Q, and S from the
- *       eigenvalues of G (Householder tridiagonalisation and Sturm-count
- *       bisection, FP64).  The passes use only S and span(Q), which both
- *       bases share; the final Rayleigh-Ritz step always uses eigSVD with
- *       eigenvectors.  A block whose G is not safely positive definite
- *       (lambda_min <= 2^-32 lambda_max, or a failed factorisation) falls
- *       back to JACOBI for that call.
- *   JACOBI: eigSVD itself (Jacobi eigenvectors of G) for every block. */
+/* The eigensolver of eigSVD (Alg. 3 steps 1-4) for the sketch, pass and
+ * final blocks.
+ *   AUTO (default): the sketch and the early pass blocks by Cholesky-QR:
+ *       W = R^-1 from G = C^T C = R^T R, so that Q = C W is orthonormal with
+ *       the span of eigSVD's Q, and S from the eigenvalues of G (Householder
+ *       tridiagonalisation and Sturm-count bisection, FP64).  The passes use
+ *       only S and span(Q), which both bases share.  Two-sided Jacobi from
+ *       the first pass whose PVE ratio is within 100 tol, for the last two
+ *       pass blocks, where G is not safely positive definite (lambda_min <=
+ *       2^-32 lambda_max, or a failed factorisation) and for the final step.
+ *   JACOBI: two-sided Jacobi on G for every block.
+ *   ONESIDED: for l <= 128, one-sided Jacobi on the Cholesky factor of G
+ *       (rotations J orthogonalise the columns of R^T; R^T J = V diag(S)
+ *       gives the eigenvectors V and S = sqrt(eig G) together) for every
+ *       block; where the factorisation meets a non-positive pivot (G
+ *       singular to working precision) the call goes to the two-sided
+ *       solver, as do all calls above 128. */
 #define DASHSVD_EIG_AUTO 0
 #define DASHSVD_EIG_JACOBI 1
+#define DASHSVD_EIG_ONESIDED 2
 
 #define DASHSVD_MAX_L 160     /* largest supported l = k + oversampling */
 #define DASHSVD_MAX_TRACE 256 /* passes recorded in dashsvd_info */
@@ -478,6 +486,23 @@ dashsvd_status dashsvd_k_eig(int32_t l, const double *G, double *S, double *Vs, 
  * cycles of thread 0's own rotation work and V update. */
 dashsvd_status dashsvd_k_eig_prof(int32_t l, const double *G, double *S, double *Vs, double *W,
                                   int32_t *sweeps, long long *prof, void *stream);
+
+/* The eigensolver of dashsvd_k_eig by one-sided Jacobi (eig_method ONESIDED,
+ * Alg. 3 steps 1-4): the Cholesky factorisation G = R^T R, then Hestenes
+ * rotations orthogonalise the columns of R^T; R^T J = Vs diag(S).  Same
+ * outputs and ordering as dashsvd_k_eig; skip is the relative rotation
+ * threshold (2^-53 in the FP64 form, 2^-23 in the FP32 and BF16 forms;
+ * raised to l 2^-53, the rounding level of the dot products).  l <= 128.
+ * *accepted (host) is 0 when G is not positive definite to working
+ * precision (a non-positive or non-finite Cholesky pivot); then nothing
+ * is written.  *sweeps (device, optional): sweeps that rotated (a last one
+ * without rotations confirms convergence).  prof (device, optional, 6
+ * int64) accumulates, as seen by thread 0, the cycles of the dot products
+ * with their reduction, of the rotation parameters, of the column updates,
+ * of the column exchange with its barrier, the number of steps and the
+ * cycles of the Cholesky phase.  Synchronises the stream. */
+dashsvd_status dashsvd_k_eig_onesided(int32_t l, const double *G, double *S, double *Vs, double *W, double skip,
+                                      int32_t *sweeps, int32_t *accepted, long long *prof, void *stream);
 
 /* Orthonormalisation of a pass block without eigenvectors (the solver of
  * the sketch and power passes under eig_method AUTO): from G (device, l x l

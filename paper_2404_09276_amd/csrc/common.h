@@ -189,6 +189,9 @@ struct SolverState {
   // index of the last eigensolver call that has started on the device (the
   // main stream holds its SpMMs back until the call is resident on its CU)
   int32_t eig_started;
+  // 1 when the one-sided Jacobi eigensolver declined the current call (its
+  // Cholesky factorisation failed) and the two-sided one must run
+  int32_t j1_decline;
 };
 
 // ------------------------------------------------------------------ launchers
@@ -316,6 +319,8 @@ struct EigArgs {
   const int32_t *skip_if; // Jacobi only: when set, the call does nothing if *skip_if != 0
   double cq_switch;       // pass tail: set state->cq_off once ratio <= cq_switch x tol (0: never)
   int32_t call_idx;       // > 0: store it to state->eig_started when the call starts working
+  int32_t *decline;       // one-sided Jacobi: set to 1 when its Cholesky factorisation fails
+                          // (the two-sided kernel gated on it then runs), else 0
 };
 // Store idx to *flag (agent scope): an eigensolver call has started.
 __device__ __forceinline__ void signal_started(int32_t *flag, int32_t idx) {
@@ -378,6 +383,13 @@ hipError_t launch_cholqr(const EigArgs &a, hipStream_t st);
 // arr: count EigArgs in device memory, all with the same l; workgroup b
 // solves arr[b]
 hipError_t launch_eig_batched(const EigArgs *arr, int count, int l, hipStream_t st);
+// One-sided Jacobi on the Cholesky factor of G (k_eig1s.hip): the same
+// outputs and tail as launch_eig, for l <= 128 (hipErrorInvalidValue
+// above); declines (*a.decline = 1, nothing else written) when G is not
+// positive definite to working precision, and the two-sided kernel gated
+// on the flag (run_if = decline) then runs.
+hipError_t launch_eig1s(const EigArgs &a, hipStream_t st);
+hipError_t launch_eig1s_batched(const EigArgs *arr, int count, int l, hipStream_t st);
 
 // ------------------------------------------------------------------ batched form
 // One matrix of a batch inside the stacked block-diagonal operator.

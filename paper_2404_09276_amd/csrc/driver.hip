@@ -392,7 +392,7 @@ dashsvd_status dashsvd_set_options(dashsvd_handle *h, const dashsvd_options *opt
   if (o.precision < 0 || o.precision > 2) return fail(h, DASHSVD_ERR_INVALID_ARG, "precision");
   if (o.shift_policy < 0 || o.shift_policy > 4) return fail(h, DASHSVD_ERR_INVALID_ARG, "shift_policy");
   if (o.pve_mode < 0 || o.pve_mode > 2) return fail(h, DASHSVD_ERR_INVALID_ARG, "pve_mode");
-  if (o.eig_method < 0 || o.eig_method > 1) return fail(h, DASHSVD_ERR_INVALID_ARG, "eig_method");
+  if (o.eig_method < 0 || o.eig_method > 2) return fail(h, DASHSVD_ERR_INVALID_ARG, "eig_method");
   if (o.reorder < -1 || o.reorder > 1) return fail(h, DASHSVD_ERR_INVALID_ARG, "reorder");
   if (o.p_max < 0) o.p_max = kDefaultPmax;
   if (o.p_max > 100000) return fail(h, DASHSVD_ERR_INVALID_ARG, "p_max too large");
@@ -778,6 +778,19 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   // within kCqSwitch x tol (set on the device by the pass tail), and for
   // the blocks of passes p_max - 1 and p_max.
   const bool cholqr = h->opt.eig_method == DASHSVD_EIG_AUTO;
+  // ONESIDED: one-sided Jacobi on the Cholesky factor (l <= 128), the
+  // two-sided kernel where it declines
+  const bool onesided = h->opt.eig_method == DASHSVD_EIG_ONESIDED && l <= 128;
+  auto eig_solve = [&](const EigArgs &ea, hipStream_t s) -> hipError_t {
+    if (!onesided) return launch_eig(ea, s);
+    EigArgs e1 = ea;
+    e1.decline = &b.state->j1_decline;
+    hipError_t e = launch_eig1s(e1, s);
+    if (e != hipSuccess) return e;
+    EigArgs e2 = ea;
+    e2.run_if = &b.state->j1_decline;
+    return launch_eig(e2, s);
+  };
   constexpr double kCqSwitch = 100.0;
   const bool nosurr = h->opt.pve_mode == DASHSVD_PVE_NOSURR;
   auto make_eig = [&](int mode) {
@@ -832,7 +845,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     const bool cq = cholqr && !host_cq_off && pass + 1 < pmax;
     if (!cq) {
       tmark_begin(h, DASHSVD_KT_EIG, pass, s);
-      const hipError_t e = launch_eig(ea, s);
+      const hipError_t e = eig_solve(ea, s);
       tmark_end(h, s);
       return e;
     }
@@ -845,7 +858,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     EigArgs gated = ea;
     gated.run_if = &b.state->cq_fallback;
     tmark_begin(h, DASHSVD_KT_EIG, pass, s);
-    e = launch_eig(gated, s);
+    e = eig_solve(gated, s);
     tmark_end(h, s);
     return e;
   };
@@ -917,7 +930,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
         ev.S = b.Sb;
         ev.W = b.W2;
         ev.skip_if = pass_skip;
-        e = launch_eig(ev, st);
+        e = eig_solve(ev, st);
       }
       if (e == hipSuccess)
         e = launch_pve_nosurr(k, l, b.Sb, b.Ebp, tol, cholqr ? kCqSwitch : 0.0, b.state, b.tr_ratio, cap, pass_skip,
@@ -1096,7 +1109,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     {
       EigArgs ea = make_eig(3);
       ea.W = b.W2;
-      HIPCHK(launch_eig(ea, st));
+      HIPCHK(eig_solve(ea, st));
     }
     HIPCHK(launch_small_gemm(l, k, l, b.W, l, 0, b.W2, l, b.PU, k, st));
     HIPCHK(launch_small_gemm(l, k, l, b.W, l, 0, b.Vs, l, b.PV, k, st));
@@ -1119,7 +1132,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     HIPCHK(launch_gram(Mm, l, Bf, ld, cdt, b.gpart, nb_m, b.G, nullptr, st, nullptr));
     {
       EigArgs ea = make_eig(3);
-      HIPCHK(launch_eig(ea, st));
+      HIPCHK(eig_solve(ea, st));
     }
     HIPCHK(launch_rescale(Mm, l, Bf, ld, cdt, b.W, l, k, b.Uo, k, cdt, nullptr, st, nullptr, nullptr, mapM));
     HIPCHK(launch_rescale(Mn, l, Qf, ld, pfin, b.Vs, l, k, b.Vo, k, cdt, nullptr, st, nullptr, nullptr, mapN));
@@ -1623,7 +1636,9 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
   // BF16 panels: FP32 panels for the passes after a promotion
   b.Q32 = pdt != cdt ? ar.take(dsz(cdt) * (size_t)n * ld) : nullptr;
   b.Y32 = pdt != cdt ? ar.take(dsz(cdt) * (size_t)m * ld) : nullptr;
-  EigArgs *eargs = (EigArgs *)ar.take(sizeof(EigArgs) * 3 * (size_t)count);
+  // per matrix and mode: the arguments of the first eigensolver, then (one-
+  // sided solver) those of the two-sided one gated on its decline
+  EigArgs *eargs = (EigArgs *)ar.take(sizeof(EigArgs) * 6 * (size_t)count);
   int64_t *offM = (int64_t *)ar.take(8 * (size_t)(count + 1));
   int64_t *offN = (int64_t *)ar.take(8 * (size_t)(count + 1));
   int64_t *ioffM_d = (int64_t *)ar.take(8 * (size_t)(count + 1));
@@ -1705,7 +1720,7 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
     HIPCHK(hipMemcpyAsync(b.sched, h->sched.data(), 8 * h->sched.size(), hipMemcpyHostToDevice, st));
   // per-matrix eigSVD arguments for the sketch (mode 1), the passes (2) and
   // the final step (3)
-  std::vector<EigArgs> ea(3 * (size_t)count);
+  std::vector<EigArgs> ea(6 * (size_t)count);
   for (int mode = 1; mode <= 3; ++mode)
     for (int i = 0; i < count; ++i) {
       EigArgs &e = ea[(size_t)(mode - 1) * count + i];
@@ -1732,8 +1747,22 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
       e.sched_len = (int)h->sched.size();
       e.ndone = ndone;
       e.stagnation_guard = mode == 2 && pdt == DASHSVD_BF16;
+      e.decline = &b.state[i].j1_decline;
+      EigArgs &f = ea[(size_t)(mode + 2) * count + i];
+      f = e;
+      f.decline = nullptr;
+      f.run_if = &b.state[i].j1_decline;
     }
   HIPCHK(hipMemcpyAsync(eargs, ea.data(), sizeof(EigArgs) * ea.size(), hipMemcpyHostToDevice, st));
+  // ONESIDED: one-sided Jacobi on the Cholesky factor (l <= 128; two-sided
+  // where it declines); the batched form has no Cholesky-QR blocks
+  const bool onesided = h->opt.eig_method == DASHSVD_EIG_ONESIDED && l <= 128;
+  auto beig = [&](int mode) -> hipError_t {
+    const EigArgs *a1 = eargs + (size_t)(mode - 1) * count;
+    if (!onesided) return launch_eig_batched(a1, count, l, st);
+    const hipError_t e = launch_eig1s_batched(a1, count, l, st);
+    return e == hipSuccess ? launch_eig_batched(a1 + 3 * (size_t)count, count, l, st) : e;
+  };
   const int64_t nIM = (int64_t)itM.size(), nIN = (int64_t)itN.size();
 
   // Panels of the passes: BF16 (or the form's type) until a matrix's PVE
@@ -1747,7 +1776,7 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
   auto block = [&](int mode, int gate) -> hipError_t {
     hipError_t e = launch_bgram(itN_d, nIN, ioffN_d, count, l, b.C, ld, cdt, bpart, b.G, (int64_t)ll, b.state,
                                 gate, st);
-    if (e == hipSuccess) e = launch_eig_batched(eargs + (size_t)(mode - 1) * count, count, l, st);
+    if (e == hipSuccess) e = beig(mode);
     if (e == hipSuccess)
       e = launch_brescale(itN_d, nIN, l, b.C, nullptr, ld, cdt, b.W, (int64_t)ll, l, l, Qc, ld, pc, b.state,
                           gate, st);
@@ -1843,7 +1872,7 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
                      b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, nullptr, st, nullptr,
                      nullptr, n));
   HIPCHK(launch_bgram(itM_d, nIM, ioffM_d, count, l, b.B, ld, cdt, bpart, b.G, (int64_t)ll, b.state, 0, st));
-  HIPCHK(launch_eig_batched(eargs + 2 * (size_t)count, count, l, st));
+  HIPCHK(beig(3));
   HIPCHK(launch_brescale(itM_d, nIM, l, b.B, nullptr, ld, cdt, b.W, (int64_t)ll, l, k, b.Uo, k, cdt, b.state, 0,
                          st));
   HIPCHK(launch_brescale(itN_d, nIN, l, Qc, nullptr, ld, pc, b.Vs, (int64_t)ll, l, k, b.Vo, k, cdt, b.state, 0,
@@ -2557,6 +2586,35 @@ dashsvd_status dashsvd_k_eig_prof(int32_t l, const double *G, double *S, double 
   ea.prof = prof;
   ea.mode = 0;
   HIPCHK(launch_eig(ea, (hipStream_t)stream));
+  return DASHSVD_OK;
+}
+
+dashsvd_status dashsvd_k_eig_onesided(int32_t l, const double *G, double *S, double *Vs, double *W, double skip,
+                                      int32_t *sweeps, int32_t *accepted, long long *prof, void *stream) {
+  dashsvd_handle *h = nullptr;
+  if (l < 1 || l > 128 || !G || !S || !W || !accepted || !(skip >= 0.0) || !(skip < 1.0))
+    return fail(h, DASHSVD_ERR_INVALID_ARG, "one-sided eig arguments (l <= 128, 0 <= skip < 1)");
+  hipStream_t st = (hipStream_t)stream;
+  int32_t *flag = nullptr;
+  HIPCHK(hipMalloc(&flag, sizeof(int32_t)));
+  EigArgs ea;
+  std::memset(&ea, 0, sizeof(ea));
+  ea.l = l;
+  ea.skip = skip;
+  ea.G = G;
+  ea.S = S;
+  ea.Vs = Vs;
+  ea.W = W;
+  ea.sweeps = sweeps;
+  ea.prof = prof;
+  ea.decline = flag;
+  int32_t declined = 1;
+  hipError_t e = launch_eig1s(ea, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&declined, flag, 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(flag);
+  HIPCHK(e);
+  *accepted = declined ? 0 : 1;
   return DASHSVD_OK;
 }
 

@@ -23,7 +23,7 @@ F32, F64, BF16 = 0, 1, 2
 PREC = {"fp32": 0, "fp64": 1, "bf16": 2}
 SHIFT = {"paper": 0, "none": 1, "fixed": 2, "schedule": 3, "learned": 4}
 PVE = {"r2": 0, "r1": 1, "nosurr": 2}
-EIG = {"auto": 0, "jacobi": 1}
+EIG = {"auto": 0, "jacobi": 1, "onesided": 2}
 # timing: False / True (every kernel group) / "spmm" (the two SpMM groups only)
 TIMING = {False: 0, True: 1, "spmm": 2}
 # reorder: "auto" (from 2^22 nonzeros), True, False
@@ -87,7 +87,8 @@ EXPORTS = [
     "dashsvd_status_string",
     "dashsvd_last_error", "dashsvd_k_gaussian", "dashsvd_k_philox_raw", "dashsvd_k_sort_index",
     "dashsvd_k_transpose",
-    "dashsvd_k_spmm", "dashsvd_k_spmm_static", "dashsvd_k_gram", "dashsvd_k_eig", "dashsvd_k_eig_prof", "dashsvd_k_cholqr", "dashsvd_k_rescale",
+    "dashsvd_k_spmm", "dashsvd_k_spmm_static", "dashsvd_k_gram", "dashsvd_k_eig", "dashsvd_k_eig_prof", "dashsvd_k_eig_onesided",
+    "dashsvd_k_cholqr", "dashsvd_k_rescale",
 ]
 
 
@@ -142,6 +143,7 @@ def lib():
         L.dashsvd_k_gram.argtypes = [i64, i32, P, i64, i32, P, P]
         L.dashsvd_k_eig.argtypes = [i32, P, P, P, P, P, P]
         L.dashsvd_k_eig_prof.argtypes = [i32, P, P, P, P, P, P, P]
+        L.dashsvd_k_eig_onesided.argtypes = [i32, P, P, P, P, f64, P, P, P, P]
         L.dashsvd_k_rescale.argtypes = [i64, i32, P, i64, i32, P, i64, i32, P, i64, i32, P]
         for name in EXPORTS:
             if name not in ("dashsvd_destroy", "dashsvd_status_string", "dashsvd_last_error"):
@@ -560,6 +562,17 @@ def k_eig(G, S, Vs, W, sweeps=None, stream=None):
     l = G.shape[0]
     _check(lib().dashsvd_k_eig(l, _ptr(G), _ptr(S), _ptr(Vs), _ptr(W), _ptr(sweeps),
                                _stream_ptr(stream)))
+
+
+def k_eig_onesided(G, S, Vs, W, skip=2.0**-53, sweeps=None, prof=None, stream=None) -> bool:
+    """The one-sided Jacobi eigensolver (l <= 128); True if G was accepted
+    (positive definite to working precision), else nothing is written.
+    prof: optional device int64 tensor of 6 step-profile counters."""
+    l = G.shape[0]
+    acc = C.c_int32(0)
+    _check(lib().dashsvd_k_eig_onesided(l, _ptr(G), _ptr(S), _ptr(Vs), _ptr(W), C.c_double(skip), _ptr(sweeps),
+                                        C.byref(acc), _ptr(prof), _stream_ptr(stream)))
+    return bool(acc.value)
 
 
 def k_cholqr(G, S, W, stream=None) -> bool:

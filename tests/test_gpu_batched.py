@@ -63,6 +63,21 @@ def test_batched_fp64_matches_oracle_per_matrix(torch_dev):
         assert _vec_close(U, ref.U, 1e-8) and _vec_close(V, ref.V, 1e-8), i
 
 
+def test_batched_onesided_matches_oracle_per_matrix(torch_dev):
+    """eig_method ONESIDED in the batched form (one workgroup of the one-sided
+    kernel per member, the two-sided kernel gated on each member's decline
+    flag): every member against the oracle, FP64, fixed passes."""
+    mats = _batch(np.float64)
+    st, out, summary = _run(mats, 8, 4, 4, 0.0, 300, "fp64", eig_method="onesided")
+    assert st == 0 and summary.passes == 4
+    for i, A in enumerate(mats):
+        (U, S, V), info = out[i]
+        ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 8, 4, 4, 0.0, seed=300 + i)
+        assert np.abs(S - ref.S).max() / ref.S.max() <= 1e-10, i
+        assert np.allclose(info.alpha_used, ref.alpha, rtol=1e-10, atol=0), i
+        assert _vec_close(U, ref.U, 1e-8) and _vec_close(V, ref.V, 1e-8), i
+
+
 @pytest.mark.parametrize("mode", ["r2", "r1"])
 def test_batched_tolerance_each_matrix_stops_at_its_own_pass(torch_dev, mode):
     mats = _batch(np.float64)

@@ -348,6 +348,100 @@ def test_eig_rank_deficient_zeroes_w(torch_dev):
     assert np.allclose(S.cpu().numpy()[:3], So[:3], rtol=1e-12)
 
 
+# ------------------------------------------------------------------ one-sided Jacobi eigensolver
+def _eig1s(torch, G, skip=2.0**-53):
+    from paper_2404_09276_amd import k_eig_onesided
+    l = G.shape[0]
+    S = torch.full((l,), -1.0, dtype=torch.float64, device="cuda")
+    Vs = torch.full((l, l), -1.0, dtype=torch.float64, device="cuda")
+    W = torch.full((l, l), -1.0, dtype=torch.float64, device="cuda")
+    sw = torch.zeros(1, dtype=torch.int32, device="cuda")
+    acc = k_eig_onesided(_dev(torch, G), S, Vs, W, skip, sw)
+    return acc, S.cpu().numpy(), Vs.cpu().numpy(), W.cpu().numpy(), int(sw.cpu()[0])
+
+
+@pytest.mark.parametrize("l", [1, 2, 3, 5, 16, 24, 30, 31, 32, 33, 50, 63, 64, 65, 75, 96, 97, 110, 120, 127, 128])
+def test_eig_onesided_matches_lapack(torch_dev, l):
+    """Every layout (L = 32, 64, 96, 128) with ragged sizes: eigenvalues
+    against LAPACK and the oracle's Jacobi within the rounding of G, Vs
+    orthonormal eigenvectors (residual at the same level), W = Vs / S."""
+    rng = np.random.default_rng(100 + l)
+    B = rng.standard_normal((l + 7, l)) @ np.diag(np.logspace(0, -2, l))
+    G = B.T @ B
+    acc, s, V, Wm, sw = _eig1s(torch_dev, G)
+    assert acc
+    lam = np.linalg.eigvalsh(G)[::-1]
+    nrm = lam[0]
+    assert np.all(np.diff(s) <= 0)
+    assert np.abs(s**2 - lam).max() <= 100 * l * 2.2e-16 * nrm
+    assert np.abs(V.T @ V - np.eye(l)).max() < 1e-12
+    assert np.linalg.norm(G @ V - V * s**2) <= 100 * l * 2.2e-16 * nrm
+    assert np.allclose(Wm, V / s, rtol=1e-14, atol=0)
+    assert 0 <= sw <= 20
+    ev, _, _ = oracle.jacobi_eig(G)
+    assert np.abs(np.sqrt(np.maximum(ev[::-1], 0)) - s).max() <= 1e-12 * s[0]
+
+
+@pytest.mark.parametrize("l", [24, 120])
+def test_eig_onesided_fp32_threshold(torch_dev, l):
+    """The 2^-23 threshold of the FP32 and BF16 forms: Vs orthonormal to
+    about 2^-23 and eigenvalues within O(2^-46) relative, in fewer sweeps."""
+    rng = np.random.default_rng(7 + l)
+    B = rng.standard_normal((2 * l, l)) @ np.diag(np.logspace(0, -1, l))
+    G = B.T @ B
+    acc, s, V, Wm, sw = _eig1s(torch_dev, G, 2.0**-23)
+    acc64, s64, _, _, sw64 = _eig1s(torch_dev, G)
+    assert acc and acc64
+    lam = np.linalg.eigvalsh(G)[::-1]
+    assert np.abs(V.T @ V - np.eye(l)).max() < 4 * l * 2.0**-23
+    assert np.abs(s**2 - lam).max() <= 1e-10 * lam[0]
+    assert sw <= sw64
+
+
+def test_eig_onesided_diagonal_clustered_and_blocks(torch_dev):
+    """Diagonal (no rotation: zero sweeps), clustered and block-diagonal G."""
+    Gs = [np.diag([4.0, 9.0, 1.0, 16.0, 25.0]),
+          np.diag(np.r_[np.full(6, 2.0), np.full(6, 2.0 + 1e-9), [5.0]]) + 1e-12,
+          np.kron(np.eye(40), np.array([[2.0, 1.0], [1.0, 3.0]]))]
+    for n, G in enumerate(Gs):
+        l = G.shape[0]
+        acc, s, V, Wm, sw = _eig1s(torch_dev, G)
+        assert acc
+        lam = np.linalg.eigvalsh(G)[::-1]
+        assert np.allclose(s**2, lam, rtol=1e-14, atol=1e-14 * lam[0])
+        assert np.abs(V.T @ V - np.eye(l)).max() < 1e-13
+        if n == 0:
+            assert sw == 0
+            assert np.array_equal(np.abs(V) > 0.5, np.eye(5)[:, [4, 3, 1, 0, 2]] > 0.5)
+
+
+def test_eig_onesided_declines_singular_and_nonfinite(torch_dev):
+    """A non-positive or non-finite pivot declines (nothing written); a
+    rank-deficient G whose factorisation completes on rounding-level pivots
+    gives its nonzero eigenvalues and zero W columns past the rank."""
+    for G in (np.diag([1.0, 2.0, -1.0, 3.0]), np.diag([1.0, np.nan, 2.0]), np.diag([1.0, np.inf, 2.0]),
+              np.zeros((6, 6))):
+        acc, s, V, Wm, _ = _eig1s(torch_dev, G)
+        assert not acc
+        assert np.all(s == -1.0) and np.all(Wm == -1.0)
+    G = np.eye(5)
+    G[1, 3] = G[3, 1] = np.nan
+    acc, _, _, _, _ = _eig1s(torch_dev, G)
+    assert not acc
+    B = np.random.default_rng(2).standard_normal((40, 3)) @ np.random.default_rng(3).standard_normal((3, 8))
+    acc, s, V, Wm, _ = _eig1s(torch_dev, B.T @ B)
+    if acc:
+        assert np.all(Wm[:, 3:] == 0.0)
+        _, So, _, _ = oracle.eigsvd(B)
+        assert np.allclose(s[:3], So[:3], rtol=1e-12)
+
+
+def test_eig_onesided_rejects_large_l(torch_dev):
+    from paper_2404_09276_amd import DashSVDError
+    with pytest.raises(DashSVDError):
+        _eig1s(torch_dev, np.eye(129))
+
+
 # ------------------------------------------------------------------ Cholesky-QR pass solver
 def _cholqr(torch, G):
     from paper_2404_09276_amd import k_cholqr

@@ -340,44 +340,47 @@ def test_bf16_no_promotion_at_loose_tol(torch_dev):
 
 @pytest.mark.parametrize("prec,bar", [("fp64", 1e-10), ("fp32", 1e-5)])
 def test_eig_methods_agree(torch_dev, prec, bar):
-    """Pass blocks orthonormalised by Cholesky-QR with eigenvalues (AUTO) and
-    by the Jacobi eigSVD (JACOBI) give the same shifts, ratios, pass count
-    and singular values, both equal to the oracle's."""
+    """Blocks solved by Cholesky-QR with eigenvalues in the early passes
+    (AUTO), by two-sided Jacobi (JACOBI) and by one-sided Jacobi on the
+    Cholesky factor (ONESIDED) give the same shifts, ratios, pass count and
+    singular values, all equal to the oracle's."""
     A = synth.config_small(np.float64 if prec == "fp64" else np.float32)
     ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 20, 10, 64, 1e-2, seed=2001)
     out = {}
-    for meth in ("auto", "jacobi"):
+    for meth in ("auto", "jacobi", "onesided"):
         U, S, V, st, info, tr = _solve(A, 20, 10, 64, 1e-2, 2001, prec, eig_method=meth)
         assert st == 0 and info.converged
         assert np.all(np.abs(S - ref.S) / ref.S <= bar)
         out[meth] = (S, V, info)
-    Sa, Va, ia = out["auto"]
     Sj, Vj, ij = out["jacobi"]
+    Sc, Vc, ic = out["auto"]
     # Cholesky-QR from the sketch on; Jacobi for the last two pass blocks
     # (the PVE ratio reached 100 tol two passes before the end) and the
     # final step
-    assert 2 <= ia.cholqr_calls <= ia.eig_calls - 3 and ij.cholqr_calls == 0
-    assert list(ia.sweeps_per_call[:ia.cholqr_calls]) == [0] * ia.cholqr_calls
-    assert np.all(ia.sweeps_per_call[ia.cholqr_calls:] > 0)
-    assert ia.passes == ij.passes == ref.passes
-    assert np.allclose(ia.alpha_used, ij.alpha_used, rtol=bar)
-    assert np.allclose(ia.ratio, ij.ratio, rtol=100 * bar)
-    assert np.all(np.abs(Sa - Sj) / Sj <= bar)
-    assert _vec_close(Va, Vj, 1e-7 if prec == "fp64" else 2e-3)
+    assert 2 <= ic.cholqr_calls <= ic.eig_calls - 3 and ij.cholqr_calls == 0
+    assert list(ic.sweeps_per_call[:ic.cholqr_calls]) == [0] * ic.cholqr_calls
+    assert np.all(ic.sweeps_per_call[ic.cholqr_calls:] > 0)
+    for Sx, Vx, ix in (out["auto"], out["onesided"]):
+        assert ix.passes == ij.passes == ref.passes
+        assert np.allclose(ix.alpha_used, ij.alpha_used, rtol=bar)
+        assert np.allclose(ix.ratio, ij.ratio, rtol=100 * bar)
+        assert np.all(np.abs(Sx - Sj) / Sj <= bar)
+        assert _vec_close(Vx, Vj, 1e-7 if prec == "fp64" else 2e-3)
+    assert out["onesided"][2].cholqr_calls == 0
 
 
 def test_eig_methods_zipf_fp32(torch_dev):
-    """Power-law matrix, FP32 form, k = 40, s = 20: both methods reach the
-    oracle's singular values within the FP32 bar in the same passes."""
+    """Power-law matrix, FP32 form, k = 40, s = 20: the three methods reach
+    the oracle's singular values within the FP32 bar in the same passes."""
     A = synth.zipf_csr(20000, 12000, 300000, seed=31)
     ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 40, 20, 64, 1e-2, seed=7)
     passes = {}
-    for meth in ("auto", "jacobi"):
+    for meth in ("auto", "jacobi", "onesided"):
         U, S, V, st, info, tr = _solve(A, 40, 20, 64, 1e-2, 7, "fp32", eig_method=meth)
         assert st == 0
         assert np.all(np.abs(S - ref.S) / ref.S <= 1e-5)
         passes[meth] = info.passes
-    assert passes["auto"] == passes["jacobi"] == ref.passes
+    assert passes["auto"] == passes["jacobi"] == passes["onesided"] == ref.passes
 
 
 def test_caller_workspace(torch_dev):
