@@ -163,6 +163,11 @@ typedef struct {
                              covering about this many KiB of gathered panel rows (one
                              slab at a time in every XCD's L2); <= 0 (default): no
                              slabs, chunks in row order */
+  int64_t batch_nnz_max;  /* batched form: the members are run in consecutive groups
+                             (sub-batches) of at most this many nonzeros in total
+                             (and 2^31 - 1 rows, columns and nonzeros, the limit of the
+                             stacked operator's 32-bit indices); <= 0 (default):
+                             2^31 - 1.  A member larger than the limit is an error. */
 } dashsvd_options;
 
 #define DASHSVD_REORDER_AUTO 0
@@ -215,6 +220,10 @@ typedef struct {
                               passes to FP32 panels (the PVE ratio stayed above tol and above
                               0.8 x its previous value for two passes) */
   int32_t cholqr_calls;    /* eig_calls solved by Cholesky-QR (eig_method AUTO) */
+  int32_t sub_batches;     /* batched form: groups of members run one after the other (1 when
+                              the batch fits the limit of option batch_nnz_max) */
+  int32_t graph_launches;  /* batched form: launches of the captured pass graph (each holds
+                              check_interval passes; summed over the sub-batches) */
 } dashsvd_info;
 
 typedef struct dashsvd_handle dashsvd_handle;

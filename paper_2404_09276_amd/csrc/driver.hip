@@ -165,6 +165,13 @@ struct dashsvd_handle {
     int32_t *tr_sweeps = nullptr;                     // count x (cap + 2)
     dashsvd_info info;
   } bat;
+  // results of a batch run in several sub-batches, gathered member by
+  // member (the arena holds one sub-batch at a time); own device memory,
+  // grown as needed and kept across runs
+  struct BatchAll {
+    void *base = nullptr;
+    size_t cap = 0;
+  } ball;
   // learned-shift MLP (its own device memory, kept across runs)
   struct Mlp {
     bool ok = false;
@@ -462,6 +469,7 @@ void dashsvd_destroy(dashsvd_handle *h) {
   if (h->ev_b1) (void)hipEventDestroy(h->ev_b1);
   if (h->mlp.P) (void)hipFree(h->mlp.P);
   if (h->mlp.buf) (void)hipFree(h->mlp.buf);
+  if (h->ball.base) (void)hipFree(h->ball.base);
   delete h;
 }
 
@@ -1268,7 +1276,23 @@ dashsvd_status dashsvd_workspace_size(const dashsvd_csr *A, int32_t k, int32_t p
 }
 
 static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As, int32_t count, int32_t k,
-                                       int32_t p, double tol, bool measure_only, size_t *measured);
+                                       int32_t p, double tol, bool measure_only, size_t *measured,
+                                       int32_t member0 = 0);
+static std::vector<std::pair<int32_t, int32_t>> batch_groups(const dashsvd_handle *h, const dashsvd_csr *As,
+                                                             int32_t count);
+// Arena bytes of a batched run: the largest of its sub-batches.
+static dashsvd_status batched_arena_need(dashsvd_handle *h, const dashsvd_csr *As, int32_t count, int32_t k,
+                                         int32_t p, size_t *bytes) {
+  size_t need = 0;
+  for (const auto &g : batch_groups(h, As, count)) {
+    size_t b = 0;
+    const dashsvd_status s = run_batched_impl(h, As + g.first, g.second, k, p, 0.0, true, &b, g.first);
+    if (s != DASHSVD_OK) return s;
+    need = std::max(need, b);
+  }
+  *bytes = need;
+  return DASHSVD_OK;
+}
 static dashsvd_status check_batch(dashsvd_handle *h, const dashsvd_csr *As, int32_t count, int32_t k, int32_t p,
                                   double tol);
 
@@ -1282,7 +1306,7 @@ dashsvd_status dashsvd_workspace_size_batched(const dashsvd_csr *As, int32_t cou
   dashsvd_status s = dashsvd_set_options(&tmp, &o);
   if (s == DASHSVD_OK) s = check_batch(&tmp, As, count, k, p, 0.0);
   if (s != DASHSVD_OK) return s;
-  return run_batched_impl(&tmp, As, count, k, p, 0.0, true, bytes);
+  return batched_arena_need(&tmp, As, count, k, p, bytes);
 }
 
 dashsvd_status dashsvd_handle_workspace_size(const dashsvd_handle *h, const dashsvd_csr *As, int32_t count,
@@ -1296,8 +1320,7 @@ dashsvd_status dashsvd_handle_workspace_size(const dashsvd_handle *h, const dash
   tmp.tune = h->tune;
   dashsvd_status s = batched ? check_batch(&tmp, As, count, k, p, 0.0) : check_args(&tmp, As, k, p, 0.0);
   if (s != DASHSVD_OK) return s;
-  return batched ? run_batched_impl(&tmp, As, count, k, p, 0.0, true, bytes)
-                 : run_impl(&tmp, As, k, p, 0.0, true, bytes);
+  return batched ? batched_arena_need(&tmp, As, count, k, p, bytes) : run_impl(&tmp, As, k, p, 0.0, true, bytes);
 }
 
 dashsvd_status dashsvd_get_USV(dashsvd_handle *h, void *U, int64_t ldu, double *S, void *V, int64_t ldv,
@@ -1546,7 +1569,8 @@ dashsvd_status dashsvd_evaluate_all(dashsvd_handle *h, const dashsvd_csr *A, con
 // items.  The run is ordered after prior work on the handle's stream, which
 // waits for it in turn.
 static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As, int32_t count, int32_t k,
-                                       int32_t p, double tol, bool measure_only, size_t *measured) {
+                                       int32_t p, double tol, bool measure_only, size_t *measured,
+                                       int32_t member0) {
   const int prec = h->opt.precision;
   const int vdt = prec == DASHSVD_PREC_FP64 ? DASHSVD_F64 : DASHSVD_F32;
   const int pdt = prec == DASHSVD_PREC_FP64 ? DASHSVD_F64 : (prec == DASHSVD_PREC_BF16_PANELS ? DASHSVD_BF16 : DASHSVD_F32);
@@ -1590,7 +1614,7 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
   ar.reset(measure_only || ar.base == nullptr);
   if (!measure_only) {
     size_t need = 0;
-    run_batched_impl(h, As, count, k, p, tol, true, &need);
+    run_batched_impl(h, As, count, k, p, tol, true, &need, member0);
     dashsvd_status s = ensure_arena(h, need);
     if (s != DASHSVD_OK) return s;
     ar.reset(false);
@@ -1712,10 +1736,11 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
   b.planT.n_long = nlongs[1];
   HIPCHK(launch_browmat(offM, count, max_m, rowmatM, st));
   HIPCHK(launch_browmat(offN, count, max_n, rowmatN, st));
-  // Omega of matrix i from the Philox stream keyed (seed + i, 0)
+  // Omega of matrix i of the whole batch from the Philox stream keyed
+  // (seed + i, 0); this sub-batch starts at member0
   for (int i = 0; i < count; ++i)
-    HIPCHK(launch_gaussian(h->opt.seed + (uint64_t)i, As[i].m, l, (char *)b.Y + dsz(pdt) * (size_t)roff[i] * ld, ld,
-                           pdt, st));
+    HIPCHK(launch_gaussian(h->opt.seed + (uint64_t)(member0 + i), As[i].m, l,
+                           (char *)b.Y + dsz(pdt) * (size_t)roff[i] * ld, ld, pdt, st));
   if (!h->sched.empty())
     HIPCHK(hipMemcpyAsync(b.sched, h->sched.data(), 8 * h->sched.size(), hipMemcpyHostToDevice, st));
   // per-matrix eigSVD arguments for the sketch (mode 1), the passes (2) and
@@ -1801,15 +1826,22 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
     if (e == hipSuccess) e = block(2, 1);
     return e;
   };
+  // check_interval passes are captured as one graph and launched at once
+  // (all p_max of them, one launch, when check_interval >= p_max); the host
+  // reads the stop counters between launches.  A shorter last chunk is
+  // captured again.
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  auto capture = [&]() -> dashsvd_status {
+  int captured = 0;  // passes in the captured graph
+  auto capture = [&](int npass) -> dashsvd_status {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     exec = nullptr;
     graph = nullptr;
+    captured = 0;
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    hipError_t ec = pass();
+    hipError_t ec = hipSuccess;
+    for (int c = 0; c < npass && ec == hipSuccess; ++c) ec = pass();
     hipError_t ee = hipStreamEndCapture(st, &graph);
     if (ec != hipSuccess || ee != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -1822,22 +1854,27 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
       graph = nullptr;
       return fail(h, DASHSVD_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
     }
+    captured = npass;
     return DASHSVD_OK;
   };
+  const int every = h->opt.check_interval > 0 ? std::min(h->opt.check_interval, std::max(pmax, 1)) : 1;
   if (pmax > 0) {
-    dashsvd_status sc = capture();
+    dashsvd_status sc = capture(std::min(every, pmax));
     if (sc != DASHSVD_OK) return sc;
   }
-  const int every = h->opt.check_interval > 0 ? h->opt.check_interval : 1;
   int launched = 0;
   int promoted = 0;
+  int graph_launches = 0;
   HIPCHK(hipStreamSynchronize(st));
   const double t_loop0 = now_ms();
   hipError_t eloop = hipSuccess;
   dashsvd_status sloop = DASHSVD_OK;
   while (launched < pmax && eloop == hipSuccess && sloop == DASHSVD_OK) {
     const int chunk = (pmax - launched) < every ? (pmax - launched) : every;
-    for (int c = 0; c < chunk && eloop == hipSuccess; ++c) eloop = hipGraphLaunch(exec, st);
+    if (chunk != captured) sloop = capture(chunk);
+    if (sloop != DASHSVD_OK) break;
+    eloop = hipGraphLaunch(exec, st);
+    ++graph_launches;
     launched += chunk;
     if (eloop == hipSuccess && tol > 0.0 && launched < pmax) {
       int32_t nd[2] = {0, 0};
@@ -1855,7 +1892,7 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
           eloop = launch_spmm(m, rpA, colA, valA, vdt, Qc, ld, pc, Yc, ld, pc, ld, b.planM.n_chunks,
                               b.planM.order, b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0,
                               nullptr, nullptr, st, rowmatM, b.state, n);
-        if (eloop == hipSuccess) sloop = capture();
+        if (eloop == hipSuccess) sloop = capture(std::min(every, pmax - launched));
       }
     }
   }
@@ -1893,6 +1930,7 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
     bo.info.eig_sweeps += hs[i].eig_sweeps;
   }
   bo.info.l = l;
+  bo.info.graph_launches = graph_launches;
   bo.info.time_loop_ms = t_loop1 - t_loop0;
   bo.info.long_row_used = T;
   bo.info.promoted = promoted;
@@ -1926,6 +1964,14 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
 
 // Arguments of a batched run (as dashsvd_run for each matrix, plus the
 // batched form's own requirements).
+// Largest stacked index (rows, columns, nonzeros) of a sub-batch: the 32-bit
+// indices of the stacked operator, its transposition and its plans.
+constexpr int64_t kStackMax = (int64_t)INT32_MAX - 1;
+static int64_t batch_limit(const dashsvd_handle *h) {
+  const int64_t o = h->opt.batch_nnz_max;
+  return o > 0 && o < kStackMax ? o : kStackMax;
+}
+
 static dashsvd_status check_batch(dashsvd_handle *h, const dashsvd_csr *As, int32_t count, int32_t k, int32_t p,
                                   double tol) {
   if (!As || count < 1) return fail(h, DASHSVD_ERR_INVALID_ARG, "empty batch");
@@ -1944,7 +1990,133 @@ static dashsvd_status check_batch(dashsvd_handle *h, const dashsvd_csr *As, int3
       return fail(h, DASHSVD_ERR_INVALID_ARG, "batched form: mixed value types or memory spaces");
   }
   if (k + p > kBMaxL) return fail(h, DASHSVD_ERR_INVALID_ARG, "batched form: k + oversampling exceeds 64");
+  const int64_t lim = batch_limit(h);
+  for (int i = 0; i < count; ++i)
+    if (As[i].nnz > lim || As[i].m > kStackMax || As[i].n > kStackMax)
+      return fail(h, DASHSVD_ERR_INVALID_ARG, "batched form: matrix " + std::to_string(i) + " has " +
+                                                  std::to_string(As[i].nnz) + " nonzeros, above the sub-batch "
+                                                  "limit of " + std::to_string(lim));
   return DASHSVD_OK;
+}
+
+// Consecutive groups of members (first, count), each within the sub-batch
+// limit of nonzeros and the 32-bit limit of the stacked rows and columns.
+static std::vector<std::pair<int32_t, int32_t>> batch_groups(const dashsvd_handle *h, const dashsvd_csr *As,
+                                                             int32_t count) {
+  const int64_t lim = batch_limit(h);
+  std::vector<std::pair<int32_t, int32_t>> g;
+  int64_t z = 0, r = 0, c = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    if (g.empty() || z + As[i].nnz > lim || r + As[i].m > kStackMax || c + As[i].n > kStackMax) {
+      g.push_back({i, 0});
+      z = r = c = 0;
+    }
+    g.back().second += 1;
+    z += As[i].nnz;
+    r += As[i].m;
+    c += As[i].n;
+  }
+  return g;
+}
+
+// A run of several sub-batches: each group runs in the arena, then its
+// members' results are copied to the handle's own result buffers, which the
+// batched getters then read.
+static dashsvd_status run_sub_batches(dashsvd_handle *h, const dashsvd_csr *As, int32_t count, int32_t k,
+                                      int32_t p, double tol,
+                                      const std::vector<std::pair<int32_t, int32_t>> &groups) {
+  const int prec = h->opt.precision;
+  const int cdt = prec == DASHSVD_PREC_FP64 ? DASHSVD_F64 : DASHSVD_F32;
+  const size_t os = dsz(cdt);
+  const int l = k + p;
+  const int cap = h->opt.p_max > 0 ? h->opt.p_max : 1;
+  std::vector<int64_t> roff(count + 1, 0), coff(count + 1, 0);
+  for (int i = 0; i < count; ++i) {
+    roff[i + 1] = roff[i] + As[i].m;
+    coff[i + 1] = coff[i] + As[i].n;
+  }
+  // result layout: U, V, S, states, traces
+  size_t off = 0;
+  auto carve = [&](size_t bytes) {
+    const size_t o = off;
+    off = round_up(off + bytes, 256);
+    return o;
+  };
+  const size_t oU = carve(os * (size_t)roff[count] * k), oV = carve(os * (size_t)coff[count] * k);
+  const size_t oS = carve(8 * (size_t)l * count), oSt = carve(sizeof(SolverState) * (size_t)count);
+  const size_t oA = carve(8 * (size_t)cap * count), oR = carve(8 * (size_t)cap * count);
+  const size_t oW = carve(4 * (size_t)(cap + 2) * count);
+  if (off > h->ball.cap) {
+    if (h->ball.base) {
+      (void)hipStreamSynchronize(h->stg);
+      (void)hipFree(h->ball.base);
+      h->ball.base = nullptr;
+      h->ball.cap = 0;
+    }
+    HIPCHK(hipMalloc(&h->ball.base, off));
+    h->ball.cap = off;
+  }
+  char *base = (char *)h->ball.base;
+  hipStream_t st = h->stg;
+  dashsvd_info agg;
+  std::memset(&agg, 0, sizeof(agg));
+  agg.converged = 1;
+  for (const auto &g : groups) {
+    const int32_t g0 = g.first, gn = g.second;
+    dashsvd_status s = run_batched_impl(h, As + g0, gn, k, p, tol, false, nullptr, g0);
+    if (s < 0) return s;
+    auto &bo = h->bat;
+    const int64_t mr = roff[g0 + gn] - roff[g0], nc = coff[g0 + gn] - coff[g0];
+    HIPCHK(hipMemcpyAsync(base + oU + os * (size_t)roff[g0] * k, bo.Uo, os * (size_t)mr * k,
+                          hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(base + oV + os * (size_t)coff[g0] * k, bo.Vo, os * (size_t)nc * k,
+                          hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(base + oS + 8 * (size_t)l * g0, bo.S, 8 * (size_t)l * gn, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(base + oSt + sizeof(SolverState) * (size_t)g0, bo.state, sizeof(SolverState) * (size_t)gn,
+                          hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(base + oA + 8 * (size_t)cap * g0, bo.tr_alpha, 8 * (size_t)cap * gn,
+                          hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(base + oR + 8 * (size_t)cap * g0, bo.tr_ratio, 8 * (size_t)cap * gn,
+                          hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(base + oW + 4 * (size_t)(cap + 2) * g0, bo.tr_sweeps, 4 * (size_t)(cap + 2) * gn,
+                          hipMemcpyDeviceToDevice, st));
+    const dashsvd_info &gi = bo.info;
+    agg.passes = std::max(agg.passes, gi.passes);
+    agg.converged &= gi.converged;
+    agg.rank_deficient |= gi.rank_deficient;
+    agg.eig_calls += gi.eig_calls;
+    agg.eig_sweeps += gi.eig_sweeps;
+    agg.time_loop_ms += gi.time_loop_ms;
+    agg.promoted |= gi.promoted;
+    agg.graph_launches += gi.graph_launches;
+    agg.long_row_used = gi.long_row_used;
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  auto &bo = h->bat;
+  agg.l = l;
+  bo.info = agg;
+  bo.have = true;
+  bo.count = count;
+  bo.m.assign(count, 0);
+  bo.n.assign(count, 0);
+  for (int i = 0; i < count; ++i) {
+    bo.m[i] = As[i].m;
+    bo.n[i] = As[i].n;
+  }
+  bo.row_off = roff;
+  bo.col_off = coff;
+  bo.Uo = base + oU;
+  bo.Vo = base + oV;
+  bo.S = (double *)(base + oS);
+  bo.state = (SolverState *)(base + oSt);
+  bo.tr_alpha = (double *)(base + oA);
+  bo.tr_ratio = (double *)(base + oR);
+  bo.tr_sweeps = (int32_t *)(base + oW);
+  dashsvd_status s = DASHSVD_OK;
+  if (tol > 0.0 && !agg.converged) s = DASHSVD_NOT_CONVERGED;
+  else if (agg.rank_deficient) s = DASHSVD_RANK_DEFICIENT;
+  bo.info.status = s;
+  return s;
 }
 
 dashsvd_status dashsvd_run_batched(dashsvd_handle *h, const dashsvd_csr *As, int32_t count, int32_t k, int32_t p,
@@ -1965,10 +2137,13 @@ dashsvd_status dashsvd_run_batched(dashsvd_handle *h, const dashsvd_csr *As, int
   HIPCHK(hipEventRecord(h->ev_b0, h->st));
   HIPCHK(hipStreamWaitEvent(h->stg, h->ev_b0, 0));
   const double t0 = now_ms();
-  dashsvd_status s = run_batched_impl(h, As, count, k, p, tol, false, nullptr);
+  const auto groups = batch_groups(h, As, count);
+  dashsvd_status s = groups.size() == 1 ? run_batched_impl(h, As, count, k, p, tol, false, nullptr)
+                                        : run_sub_batches(h, As, count, k, p, tol, groups);
   (void)hipStreamSynchronize(h->stg);
   h->bat.info.time_total_ms = now_ms() - t0;
   h->bat.info.status = s;
+  h->bat.info.sub_batches = (int32_t)groups.size();
   return s;
 }
 

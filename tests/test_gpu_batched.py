@@ -78,6 +78,81 @@ def test_batched_onesided_matches_oracle_per_matrix(torch_dev):
         assert _vec_close(U, ref.U, 1e-8) and _vec_close(V, ref.V, 1e-8), i
 
 
+def _groups(mats, lim):
+    """The library's grouping rule: consecutive members, at most lim nonzeros."""
+    g, z = [], 0
+    for A in mats:
+        if not g or z + A.nnz > lim:
+            g.append(0)
+            z = 0
+        g[-1] += 1
+        z += A.nnz
+    return g
+
+
+@pytest.mark.parametrize("lim", [45000, 70000])
+def test_batched_sub_batches_match_oracle_and_whole_batch(torch_dev, lim):
+    """batch_nnz_max below the batch's total: the members run in consecutive
+    sub-batches (each its own stacked operator in the arena) and their
+    results are gathered; every member still draws Omega from seed + its
+    index in the whole batch, so it matches the oracle and the one-group run."""
+    mats = _batch(np.float64)
+    groups = _groups(mats, lim)
+    assert len(groups) > 1
+    st, out, summary = _run(mats, 8, 4, 4, 0.0, 300, "fp64", batch_nnz_max=lim)
+    st1, out1, summary1 = _run(mats, 8, 4, 4, 0.0, 300, "fp64")
+    assert st == 0 and st1 == 0
+    assert summary.sub_batches == len(groups) and summary1.sub_batches == 1
+    assert summary.passes == 4
+    for i, A in enumerate(mats):
+        (U, S, V), info = out[i]
+        (U1, S1, V1), info1 = out1[i]
+        ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 8, 4, 4, 0.0, seed=300 + i)
+        assert info.passes == 4
+        assert np.abs(S - ref.S).max() / ref.S.max() <= 1e-10, i
+        assert np.abs(S - S1).max() / S1.max() <= 1e-12, i
+        assert np.allclose(info.alpha_used, ref.alpha, rtol=1e-10, atol=0), i
+        assert _vec_close(U, ref.U, 1e-8) and _vec_close(V, ref.V, 1e-8), i
+
+
+def test_batched_sub_batches_tolerance_and_oversized_member(torch_dev):
+    """Tolerance runs stop each member at its own pass across sub-batches;
+    a member above the limit is an argument error."""
+    from paper_2404_09276_amd import DashSVD, DashSVDError
+    mats = _batch(np.float64)
+    st, out, summary = _run(mats, 8, 4, 30, 1e-3, 400, "fp64", batch_nnz_max=45000)
+    assert st == 0 and summary.converged and summary.sub_batches > 1
+    passes = []
+    for i, A in enumerate(mats):
+        (U, S, V), info = out[i]
+        ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 8, 4, 30, 1e-3, seed=400 + i)
+        if not np.any(np.abs(ref.ratio - 1e-3) < 1e-6 * 1e-3):
+            assert info.passes == ref.passes, i
+        assert np.abs(S - ref.S).max() / ref.S.max() <= 1e-10, i
+        passes.append(info.passes)
+    assert summary.passes == max(passes)
+    h = DashSVD(precision="fp64", p_max=4, seed=1, batch_nnz_max=10000)
+    with pytest.raises(DashSVDError):
+        h.run_batched(mats, 8, 4, 0.0)
+    h.close()
+
+
+@pytest.mark.parametrize("every", [3, 100])
+def test_batched_passes_per_graph_launch(torch_dev, every):
+    """check_interval passes captured as one graph (all p_max passes in one
+    launch when check_interval >= p_max, a shorter last chunk captured
+    again): the same results as one pass per launch, bit for bit."""
+    mats = _batch(np.float32)
+    st1, out1, s1 = _run(mats, 8, 4, 7, 0.0, 600, "fp32", check_interval=1)
+    st, out, s = _run(mats, 8, 4, 7, 0.0, 600, "fp32", check_interval=every)
+    assert st == st1 == 0
+    assert s1.graph_launches == 7 and s.graph_launches == -(-7 // every)
+    for i in range(len(mats)):
+        (U, S, V), _ = out[i]
+        (U1, S1, V1), _ = out1[i]
+        assert np.array_equal(S, S1) and np.array_equal(U, U1) and np.array_equal(V, V1), i
+
+
 @pytest.mark.parametrize("mode", ["r2", "r1"])
 def test_batched_tolerance_each_matrix_stops_at_its_own_pass(torch_dev, mode):
     mats = _batch(np.float64)
