@@ -22,6 +22,8 @@ thread and on all of them).
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-forms] [--no-c3]
   python bench.py --copy-probe   (a plain 1 GiB device copy, three times: the
                                   reference that calibrates the HBM counters)
+  python bench.py --c5-full      (only the batched workload at its stated scale,
+                                  about 6.9e9 nonzeros, one JSON line)
   python bench.py --summarize-trace STATS_CSV COMMAND > kernel_stats.md
   python bench.py --summarize-pmc FETCH_CSV WRITE_CSV COPY_FETCH_CSV COPY_WRITE_CSV COMMANDS > traffic.txt
                                  (the committed profile summaries, from the
@@ -146,6 +148,89 @@ def batched_form(torch, steps):
             "all_converged": bool(s.converged), "pass_loop_ms": s.time_loop_ms,
             "workload": "512 Zipf 1.1 matrices, rows U[1k,10k], k=16, oversampling 8, BF16 panels, "
                         "tol 1e-2, p_max 16"}
+
+
+def _c5_member(b):
+    import synth
+    A = synth.batched_zipf_member(b)
+    return b, A.m, A.n, A.row_ptr, A.col, A.val
+
+
+def batched_full_scale(torch):
+    """The batched workload at its stated scale: 512 power-law matrices, rows
+    U[1k, 100k], columns 0.5-1 x rows, density 0.05-1 %, Zipf 1.1 (about
+    6.9e9 nonzeros), k = 16, oversampling 8, BF16 panels, tol 1e-2, p_max 16,
+    all passes of a sub-batch in one graph launch (check_interval = p_max),
+    sub-batches below 2^31 nonzeros.  The members are generated on the host
+    cores in parallel and moved to the GPU before the timed run.  Checks:
+    three small members against the FP64 oracle at their own pass count
+    (sigma within 5e-3 relative, the BF16 bar) and the residual
+    max_i |A v_i - sigma_i u_i| / sigma_i of the two largest members."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor, as_completed
+    import numpy as np
+    import scipy.sparse as sp
+    import oracle
+    import synth
+    from paper_2404_09276_amd import DashSVD
+
+    count = 512
+    t0 = time.perf_counter()
+    dev = [None] * count
+    host_small = {}
+    nnz_total = 0
+    # a worker that dies raises (BrokenProcessPool) instead of leaving the pool waiting
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1), mp_context=mp.get_context("spawn")) as ex:
+        futs = [ex.submit(_c5_member, b) for b in range(count)]
+        for done, fut in enumerate(as_completed(futs)):
+            b, m, n, rp, col, val = fut.result()
+            class D:
+                pass
+            d = D()
+            d.m, d.n, d.nnz = m, n, int(rp[-1])
+            d.row_ptr = torch.from_numpy(rp).cuda()
+            d.col = torch.from_numpy(col).cuda()
+            d.val = torch.from_numpy(val).cuda()
+            dev[b] = d
+            nnz_total += d.nnz
+            if m <= 5000 and len(host_small) < 3:
+                host_small[b] = (m, n, rp, col, val)
+            if (done + 1) % 64 == 0:
+                print(f"c5 full scale: {done + 1}/{count} members on the GPU, {nnz_total / 1e9:.2f}e9 nonzeros, "
+                      f"{time.perf_counter() - t0:.0f} s", flush=True)
+    gen_s = time.perf_counter() - t0
+    h = DashSVD(precision="bf16", p_max=16, seed=5000, check_interval=16, stream=torch.cuda.current_stream())
+    t1 = time.perf_counter()
+    h.run_batched(dev, 16, 8, 1e-2)
+    torch.cuda.synchronize()
+    first_s = time.perf_counter() - t1
+    print(f"c5 full scale: first run {first_s:.2f} s", flush=True)
+    t1 = time.perf_counter()
+    h.run_batched(dev, 16, 8, 1e-2)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    s = h.info_batched(-1)
+    worst_small = 0.0
+    for b, (m, n, rp, col, val) in sorted(host_small.items()):
+        (U, S, V), info = h.get_usv_batched(b), h.info_batched(b)
+        ref = oracle.dashsvd(m, n, rp, col, val.astype(np.float64), 16, 8, info.passes, 0.0, seed=5000 + b)
+        worst_small = max(worst_small, float(np.max(np.abs(S - ref.S) / ref.S)))
+    big = sorted(range(count), key=lambda b: -dev[b].nnz)[:2]
+    worst_res = 0.0
+    for b in big:
+        U, S, V = h.get_usv_batched(b)
+        d = dev[b]
+        A = sp.csr_matrix((d.val.cpu().numpy(), d.col.cpu().numpy(), d.row_ptr.cpu().numpy()), shape=(d.m, d.n))
+        R = A @ V - U * S
+        worst_res = max(worst_res, float(np.max(np.linalg.norm(R, axis=0) / S)))
+    h.close()
+    return {"value": el, "unit": "s per batch", "matrices_per_s": count / el, "matrices": count,
+            "nnz_total": nnz_total, "sub_batches": s.sub_batches, "graph_launches": s.graph_launches,
+            "max_passes": s.passes, "all_converged": bool(s.converged), "pass_loop_ms": s.time_loop_ms,
+            "first_run_s": first_s, "generation_s": gen_s,
+            "small_members_sigma_rel_err_vs_oracle": worst_small, "large_members_residual": worst_res,
+            "workload": "512 Zipf 1.1 matrices, rows U[1k,100k], columns 0.5-1 x rows, density 0.05-1 %, "
+                        "k=16, oversampling 8, BF16 panels, tol 1e-2, p_max 16, one graph launch per sub-batch"}
 
 
 def c3_forms(torch, stream, steps=2):
@@ -373,6 +458,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--c5-full", action="store_true",
+                    help="only the batched workload at its stated scale (about 6.9e9 nonzeros)")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("STATS_CSV", "COMMAND"))
     ap.add_argument("--summarize-pmc", nargs="+", metavar="ARG")
     args = ap.parse_args()
@@ -399,6 +486,9 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.c5_full:
+        print(json.dumps({"batched_full_scale": batched_full_scale(torch)}), flush=True)
+        return
     A, Dev = load_workload(torch)
     stream = torch.cuda.current_stream()
     ndetail = 3

@@ -157,17 +157,23 @@ typedef struct {
   int32_t reorder;        /* DASHSVD_REORDER_*: solve P_r A P_c^T with rows and columns
                              by non-increasing nonzero count (memory locality of the
                              products); U and V are returned in the caller's order.
-                             AUTO (0): on from DASHSVD_REORDER_MIN_NNZ nonzeros */
+                             AUTO (0): the tuning database's choice for the shape,
+                             else on from DASHSVD_REORDER_MIN_NNZ nonzeros */
   int32_t slab_kib;       /* > 0: the SpMM cuts the long rows also at column-slab
                              boundaries and runs their chunks slab by slab, each slab
                              covering about this many KiB of gathered panel rows (one
-                             slab at a time in every XCD's L2); <= 0 (default): no
-                             slabs, chunks in row order */
+                             slab at a time in every XCD's L2); <= 0 (default): the
+                             tuning database's value for the shape, else no slabs
+                             (chunks in row order) */
   int64_t batch_nnz_max;  /* batched form: the members are run in consecutive groups
                              (sub-batches) of at most this many nonzeros in total
                              (and 2^31 - 1 rows, columns and nonzeros, the limit of the
                              stacked operator's 32-bit indices); <= 0 (default):
                              2^31 - 1.  A member larger than the limit is an error. */
+  int32_t lane_vectors;   /* SpMM: 16-byte panel vectors per lane, 1 (a row over ld / V
+                             lanes) or 2 (half as many lanes, twice the gathers in
+                             flight per lane; used where the row splits evenly); <= 0
+                             (default): the tuning database's value, else 1 */
 } dashsvd_options;
 
 #define DASHSVD_REORDER_AUTO 0
@@ -224,6 +230,9 @@ typedef struct {
                               the batch fits the limit of option batch_nnz_max) */
   int32_t graph_launches;  /* batched form: launches of the captured pass graph (each holds
                               check_interval passes; summed over the sub-batches) */
+  int32_t lane_vectors_used; /* SpMM lane vectors of the run (option, tuning database or 1) */
+  int32_t slab_kib_used;   /* SpMM column-slab KiB of the run (0: none) */
+  int32_t reordered;       /* 1 if the run iterated the degree-ordered operator */
 } dashsvd_info;
 
 typedef struct dashsvd_handle dashsvd_handle;
@@ -323,16 +332,25 @@ dashsvd_status dashsvd_get_USV_batched(dashsvd_handle *h, int32_t idx, void *U, 
  * all converged, total eig calls and sweeps, wall time). */
 dashsvd_status dashsvd_get_info_batched(dashsvd_handle *h, int32_t idx, dashsvd_info *out);
 
-/* Autotuner of the SpMM work split: times short runs (2 passes, tol 0) of
- * the given matrix (count == 1, dashsvd_run) or batch (count > 1,
- * dashsvd_run_batched) for each candidate long-row chunk length
- * (32 ... 1024 nonzeros), keeps the fastest by the SpMM kernel time (single
- * matrix) or the pass-loop time (batch), appends "key chunk_length" to the
- * text file db_path (if not NULL) and to the handle's table, and returns it
- * in *best.  The key is the shape bucket: precision, l rounded up to 8,
- * log2 of the rows and of the mean nonzeros per row of the operator, and
- * the form (single / batched).  The handle's other options are used and
- * left unchanged; the results of the tuning runs are discarded. */
+/* Autotuner of the SpMM work split and layout: times short runs (2 passes,
+ * tol 0, 3 repetitions, the fastest kept) of the given matrix (count == 1,
+ * dashsvd_run) or batch (count > 1, dashsvd_run_batched), by the SpMM kernel
+ * time (single matrix) or the pass-loop time (batch), over four knobs in
+ * turn, each at the best values found so far for the others (a coordinate
+ * search): the long-row chunk length (32 ... 1024 nonzeros: from row
+ * splitting towards an even split of the nonzeros), the lane vectors per
+ * row (1 or 2), the column slabs (none or 2 MiB) and, for a single matrix,
+ * the degree order (on or off; its setup is not in the timed SpMM time, so
+ * this knob compares the products only).  Knobs that the handle's options
+ * fix (long_row, lane_vectors, slab_kib > 0, reorder ON / OFF) keep the
+ * option's value.  Appends "key chunk_length lanes slab_kib reorder" to the
+ * text file db_path (if not NULL) and to the handle's table, and returns the
+ * chunk length in *best.  The key is the shape bucket: precision, l rounded
+ * up to 8, log2 of the rows and of the mean nonzeros per row of the
+ * operator, and the form (single / batched).  Runs whose options leave a
+ * knob at its default take its value from the table.  The handle's other
+ * options are left unchanged; the results of the tuning runs are
+ * discarded. */
 dashsvd_status dashsvd_autotune(dashsvd_handle *h, const dashsvd_csr *As, int32_t count, int32_t k,
                                 int32_t p, const char *db_path, int32_t *best);
 

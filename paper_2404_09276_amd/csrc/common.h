@@ -271,8 +271,8 @@ hipError_t launch_plan_order(int nslabs, const int64_t *n_chunks, const ChunkTas
 hipError_t launch_spmm(int64_t R, const int64_t *rp, const int32_t *col, const void *val, int vdtype,
                        const void *X, int64_t ldx, int xdtype, void *Y, int64_t ldy, int ydtype,
                        int ld_cols, int64_t n_chunks, const ChunkTask *tasks, int64_t n_long,
-                       const LongRow *longs, void *partial, int32_t long_row, const void *Q,
-                       int64_t ldq, const double *alpha, const int32_t *done, hipStream_t st,
+                       const LongRow *longs, void *partial, int32_t long_row, int lane_mult,
+                       const void *Q, int64_t ldq, const double *alpha, const int32_t *done, hipStream_t st,
                        const int32_t *rowmat = nullptr, const SolverState *bstate = nullptr,
                        int64_t xrows = 0);
 
@@ -285,6 +285,13 @@ size_t gram_partial_elems(int nblocks, int l);
 
 // Jacobi eigensolver + eigSVD tail.  mode: 0 = plain eig (kernel entry),
 // 1 = sketch, 2 = power pass (PVE check + shift update), 3 = final.
+// One entry of the tuning database (dashsvd_autotune): SpMM chunk length,
+// lane vectors per lane (1 or 2), column-slab KiB (0: none), degree order
+// (+1 on, -1 off, 0 by the size rule).
+struct TuneVal {
+  int32_t T = 0, vm = 1, slab_kib = 0, reorder = 0;
+};
+
 struct EigArgs {
   int l, k;
   double skip;      // Jacobi threshold: rotate only if |g_pq| > skip sqrt(|g_pp g_qq|)

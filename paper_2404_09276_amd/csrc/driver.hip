@@ -184,7 +184,7 @@ struct dashsvd_handle {
     int buf_batch = 0;
   } mlp;
   // SpMM chunk lengths by shape bucket (tuning database)
-  std::vector<std::pair<std::string, int>> tune;
+  std::vector<std::pair<std::string, TuneVal>> tune;
   // internal stream of the batched form (its pass is captured as a graph)
   hipStream_t stg = nullptr;
   hipEvent_t ev_b0 = nullptr, ev_b1 = nullptr;
@@ -401,6 +401,7 @@ dashsvd_status dashsvd_set_options(dashsvd_handle *h, const dashsvd_options *opt
   if (o.pve_mode < 0 || o.pve_mode > 2) return fail(h, DASHSVD_ERR_INVALID_ARG, "pve_mode");
   if (o.eig_method < 0 || o.eig_method > 2) return fail(h, DASHSVD_ERR_INVALID_ARG, "eig_method");
   if (o.reorder < -1 || o.reorder > 1) return fail(h, DASHSVD_ERR_INVALID_ARG, "reorder");
+  if (o.lane_vectors > 2) return fail(h, DASHSVD_ERR_INVALID_ARG, "lane_vectors (1 or 2; <= 0: tuned or 1)");
   if (o.p_max < 0) o.p_max = kDefaultPmax;
   if (o.p_max > 100000) return fail(h, DASHSVD_ERR_INVALID_ARG, "p_max too large");
   h->sched.clear();
@@ -413,10 +414,19 @@ dashsvd_status dashsvd_set_options(dashsvd_handle *h, const dashsvd_options *opt
   h->tune.clear();
   if (o.tuning_db) {
     if (FILE *f = std::fopen(o.tuning_db, "r")) {
-      char key[256];
-      int v = 0;
-      while (std::fscanf(f, "%255s %d", key, &v) == 2)
-        if (v > 0) h->tune.emplace_back(key, v);
+      // lines "key T [lanes slab_kib reorder]" (a line with only T keeps the
+      // other knobs at their defaults)
+      char line[512];
+      while (std::fgets(line, sizeof(line), f)) {
+        char key[256];
+        TuneVal v;
+        const int got = std::sscanf(line, "%255s %d %d %d %d", key, &v.T, &v.vm, &v.slab_kib, &v.reorder);
+        if (got < 2 || v.T <= 0) continue;
+        if (got < 3 || (v.vm != 1 && v.vm != 2)) v.vm = 1;
+        if (got < 4 || v.slab_kib < 0) v.slab_kib = 0;
+        if (got < 5 || v.reorder < -1 || v.reorder > 1) v.reorder = 0;
+        h->tune.emplace_back(key, v);
+      }
       std::fclose(f);
     }
   }
@@ -498,11 +508,32 @@ dashsvd_status dashsvd_set_workspace(dashsvd_handle *h, void *dev_ptr, size_t by
 
 // SpMM chunk length of a run: the option, else the tuned value of the
 // bucket (last entry wins), else the default.
+// The tuning database's entry for a shape bucket (the latest one), or null.
+static const TuneVal *tuned(const dashsvd_handle *h, const std::string &key) {
+  for (auto it = h->tune.rbegin(); it != h->tune.rend(); ++it)
+    if (it->first == key) return &it->second;
+  return nullptr;
+}
+
 static int32_t chunk_length(const dashsvd_handle *h, const std::string &key, int64_t nnz) {
   if (h->opt.long_row > 0) return h->opt.long_row;
-  for (auto it = h->tune.rbegin(); it != h->tune.rend(); ++it)
-    if (it->first == key) return it->second;
+  if (const TuneVal *t = tuned(h, key)) return t->T;
   return nnz >= DASHSVD_REORDER_MIN_NNZ ? kDefaultLongRowLarge : kDefaultLongRow;
+}
+
+// SpMM lanes per row: one 16-byte vector per lane (1) or two (2), from the
+// option, else the tuning database, else 1.
+static int lane_mult(const dashsvd_handle *h, const std::string &key) {
+  if (h->opt.lane_vectors > 0) return h->opt.lane_vectors;
+  const TuneVal *t = tuned(h, key);
+  return t ? t->vm : 1;
+}
+
+// Column-slab bytes of the SpMM plan: the option, else the tuning database.
+static int64_t slab_bytes(const dashsvd_handle *h, const std::string &key) {
+  if (h->opt.slab_kib > 0) return (int64_t)h->opt.slab_kib << 10;
+  const TuneVal *t = tuned(h, key);
+  return t && t->slab_kib > 0 ? (int64_t)t->slab_kib << 10 : 0;
 }
 
 static dashsvd_status check_args(dashsvd_handle *h, const dashsvd_csr *A, int32_t k, int32_t p, double tol) {
@@ -546,7 +577,9 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   const int ldc = (int)round_up(l, 8);
   const int64_t line_elems = (int64_t)(128 / (dsz(pdt) < dsz(cdt) ? dsz(pdt) : dsz(cdt)));
   const int ld = round_up(l, line_elems) * 8 <= (int64_t)ldc * 9 ? (int)round_up(l, line_elems) : ldc;
-  const int32_t T = chunk_length(h, tune_key(prec, ldc, Mm, nnz, false), nnz);
+  const std::string tkey = tune_key(prec, ldc, Mm, nnz, false);
+  const int32_t T = chunk_length(h, tkey, nnz);
+  const int vm = lane_mult(h, tkey);
   const int pmax = h->opt.p_max;
   const int cap = pmax > 0 ? pmax : 1;
   hipStream_t st = h->st;
@@ -583,7 +616,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   // long-row chunks cut at slabs of the gathered panel: M gathers rows of
   // the n-side panels (C, Q), M^T rows of the m-side ones (Z, Y)
   const int64_t prow_b = (int64_t)ld * (int64_t)dsz(pdt);
-  const int64_t slab_b = h->opt.slab_kib > 0 ? (int64_t)h->opt.slab_kib << 10 : 0;
+  const int64_t slab_b = slab_bytes(h, tkey);
   plan_alloc(h, ar, b.planM, Mm, nnz, T, ldc, accsz, Mn, prow_b, slab_b);
   plan_alloc(h, ar, b.planT, Mn, nnz, T, ldc, accsz, Mm, prow_b, slab_b);
   b.Y = ar.take(dsz(pdt) * (size_t)Mm * ld);
@@ -622,8 +655,10 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   b.sgn_idx = ar.take(8 * (size_t)sgn_blk * k + 4 * (size_t)k);
   if (h->opt.omega && !h->opt.omega_on_device)
     b.omega_dev = ar.take(dsz(h->opt.omega_dtype) * (size_t)Mm * l);
+  const TuneVal *tv = tuned(h, tkey);
   const bool reorder = h->opt.reorder == DASHSVD_REORDER_ON ||
-                       (h->opt.reorder == DASHSVD_REORDER_AUTO && nnz >= DASHSVD_REORDER_MIN_NNZ);
+                       (h->opt.reorder == DASHSVD_REORDER_AUTO &&
+                        (tv && tv->reorder ? tv->reorder > 0 : nnz >= DASHSVD_REORDER_MIN_NNZ));
   if (reorder) {
     b.perm_r = (int32_t *)ar.take(4 * (size_t)(m + 1));
     b.inv_r = (int32_t *)ar.take(4 * (size_t)(m + 1));
@@ -902,7 +937,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       if ((e = launch_wait_started(&b.state->eig_started, ea.call_idx, st)) != hipSuccess) return e;
       tmark_begin(h, DASHSVD_KT_SPMM, pass);
       e = launch_spmm(Mm, rpM, colM, valM, vdt, Cin, ld, cdt, b.Z, ld, cdt, ldc, b.planM.n_chunks, b.planM.order,
-                      b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, skip, st, nullptr,
+                      b.planM.n_long, b.planM.longs, b.planM.partial, T, vm, nullptr, 0, nullptr, skip, st, nullptr,
                       nullptr, Mn);
       tmark_end(h);
       if (e != hipSuccess) return e;
@@ -912,7 +947,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       // they return at once (the live flag, not the pass-start snapshot;
       // Z above is kept, the final step uses it)
       e = launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Z, ld, cdt, b.X, ld, cdt, ldc, b.planT.n_chunks, b.planT.order,
-                      b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr, gate, st, nullptr,
+                      b.planT.n_long, b.planT.longs, b.planT.partial, T, vm, nullptr, 0, nullptr, gate, st, nullptr,
                       nullptr, Mm);
       tmark_end(h);
       if (e != hipSuccess) return e;
@@ -949,7 +984,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     // sketch (Alg. 5 step 2): C = M^T Omega, its eigSVD || M C, M^T M C
     tmark_begin(h, DASHSVD_KT_SKETCH, 0);
     HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, Cb[0], ld, cdt, ldc, b.planT.n_chunks,
-                       b.planT.order, b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr,
+                       b.planT.order, b.planT.n_long, b.planT.longs, b.planT.partial, T, vm, nullptr, 0, nullptr,
                        nullptr, st, nullptr, nullptr, Mm));
     tmark_end(h);
     HIPCHK(side(1, 0, Cb[0], nullptr));
@@ -1050,7 +1085,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       if (e != hipSuccess) return e;
       tmark_begin(h, DASHSVD_KT_SPMM, pass);
       e = launch_spmm(Mm, rpM, colM, valM, vdt, Qc, ld, pcur, Yc, ld, pcur, ldc, b.planM.n_chunks, b.planM.order,
-                      b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, skip, st, nullptr,
+                      b.planM.n_long, b.planM.longs, b.planM.partial, T, vm, nullptr, 0, nullptr, skip, st, nullptr,
                       nullptr, Mn);
       tmark_end(h);
       return e;
@@ -1058,7 +1093,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     // sketch (Alg. 5 step 2): C = M^T Omega ; Q = eigSVD(C).U ; Y = M Q
     tmark_begin(h, DASHSVD_KT_SKETCH, 0);
     HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ldc, b.planT.n_chunks, b.planT.order,
-                       b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr, nullptr, st,
+                       b.planT.n_long, b.planT.longs, b.planT.partial, T, vm, nullptr, 0, nullptr, nullptr, st,
                        nullptr, nullptr, Mm));
     tmark_end(h);
     HIPCHK(block_step(1, 0, nullptr));
@@ -1070,7 +1105,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
         const int pass = launched + c + 1;
         tmark_begin(h, DASHSVD_KT_SPMM_T, pass);
         HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, Yc, ld, pcur, b.C, ld, cdt, ldc, b.planT.n_chunks,
-                           b.planT.order, b.planT.n_long, b.planT.longs, b.planT.partial, T, Qc, ld,
+                           b.planT.order, b.planT.n_long, b.planT.longs, b.planT.partial, T, vm, Qc, ld,
                            &b.state->alpha, done, st, nullptr, nullptr, Mm));
         tmark_end(h);
         HIPCHK(block_step(2, pass, done));
@@ -1090,7 +1125,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
           promoted = 1;
           HIPCHK(launch_rescale(Mn, l, b.C, ld, cdt, b.W, l, l, Qc, ld, pcur, nullptr, st));
           HIPCHK(launch_spmm(Mm, rpM, colM, valM, vdt, Qc, ld, pcur, Yc, ld, pcur, ldc, b.planM.n_chunks,
-                             b.planM.order, b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0,
+                             b.planM.order, b.planM.n_long, b.planM.longs, b.planM.partial, T, vm, nullptr, 0,
                              nullptr, nullptr, st, nullptr, nullptr, Mn));
         }
       }
@@ -1131,7 +1166,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     if (pfin != cdt) {
       // the BF16 form keeps an FP32 B
       HIPCHK(launch_spmm(Mm, rpM, colM, valM, vdt, Qfin, ld, pfin, b.B, ld, cdt, ldc, b.planM.n_chunks,
-                         b.planM.order, b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr,
+                         b.planM.order, b.planM.n_long, b.planM.longs, b.planM.partial, T, vm, nullptr, 0, nullptr,
                          nullptr, st, nullptr, nullptr, Mn));
     } else {
       // promoted to FP32 panels: B is the last M Q
@@ -1182,6 +1217,9 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   inf.cholqr_calls = hs.cq_calls;
   inf.learned_n = hs.learned_ready ? hs.learned_n : 0;
   inf.long_row_used = T;
+  inf.lane_vectors_used = vm;
+  inf.slab_kib_used = (int32_t)(slab_b >> 10);
+  inf.reordered = reorder ? 1 : 0;
   inf.time_total_ms = t_end - t0;
   inf.time_setup_ms = t_setup - t0;
   inf.time_loop_ms = t_loop - t_setup;
@@ -1383,7 +1421,7 @@ static dashsvd_status evaluate_core(dashsvd_handle *h, const dashsvd_csr *A, con
   HIPCHK(launch_copy2d(h->U, k, h->out_dt, Upad, ld8, c.cdt, urows, k, st, c.u_row_to));
   const Plan &pl = c.plan[side];
   HIPCHK(launch_spmm(zrows, c.rp[side], c.col[side], c.val[side], c.vdt, Upad, ld8, c.cdt, Z, ld8, c.cdt, ld8,
-                     pl.n_chunks, pl.order, pl.n_long, pl.longs, pl.partial, c.T, nullptr, 0, nullptr, nullptr,
+                     pl.n_chunks, pl.order, pl.n_long, pl.longs, pl.partial, c.T, 1, nullptr, 0, nullptr, nullptr,
                      st, nullptr, nullptr, urows));
   // ||A^T u_i||^2 = (Z^T Z)_ii in FP64
   HIPCHK(launch_gram(zrows, k, Z, ld8, c.cdt, c.gpart, gram_blocks(zrows, k), c.G, nullptr, st, nullptr));
@@ -1513,7 +1551,7 @@ dashsvd_status dashsvd_evaluate_all(dashsvd_handle *h, const dashsvd_csr *A, con
     // y = A q - U (S .* (V^T q))
     run(launch_copy2d(q, 1, DASHSVD_F64, pan_n, 8, c.cdt, n, 1, st));
     run(launch_spmm(m, c.rp[sideA], c.col[sideA], c.val[sideA], c.vdt, pan_n, 8, c.cdt, pan_m, 8, c.cdt, 8,
-                    pA.n_chunks, pA.order, pA.n_long, pA.longs, pA.partial, c.T, nullptr, 0, nullptr, nullptr, st,
+                    pA.n_chunks, pA.order, pA.n_long, pA.longs, pA.partial, c.T, 1, nullptr, 0, nullptr, nullptr, st,
                     nullptr, nullptr, n));
     run(launch_dots(n, k, Vcm, n, q, part, t1, st));
     run(launch_copy2d(pan_m, 8, c.cdt, y, 1, DASHSVD_F64, m, 1, st));
@@ -1521,7 +1559,7 @@ dashsvd_status dashsvd_evaluate_all(dashsvd_handle *h, const dashsvd_csr *A, con
     // w = A^T y - V (S .* (U^T y))
     run(launch_copy2d(y, 1, DASHSVD_F64, pan_m, 8, c.cdt, m, 1, st));
     run(launch_spmm(n, c.rp[sideAT], c.col[sideAT], c.val[sideAT], c.vdt, pan_m, 8, c.cdt, pan_n, 8, c.cdt, 8,
-                    pT.n_chunks, pT.order, pT.n_long, pT.longs, pT.partial, c.T, nullptr, 0, nullptr, nullptr, st,
+                    pT.n_chunks, pT.order, pT.n_long, pT.longs, pT.partial, c.T, 1, nullptr, 0, nullptr, nullptr, st,
                     nullptr, nullptr, m));
     run(launch_dots(m, k, Ucm, m, y, part, t1, st));
     run(launch_copy2d(pan_n, 8, c.cdt, w, 1, DASHSVD_F64, n, 1, st));
@@ -1594,7 +1632,9 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
     max_n = std::max(max_n, As[b].n);
   }
   const int64_t m = roff[count], n = coff[count], nnz = zoff[count];
-  const int32_t T = chunk_length(h, tune_key(prec, ld, m, nnz, true), 0);
+  const std::string tkey = tune_key(prec, ld, m, nnz, true);
+  const int32_t T = chunk_length(h, tkey, 0);
+  const int vm = lane_mult(h, tkey);
   if (m > INT32_MAX - 1 || n > INT32_MAX - 1 || nnz > INT32_MAX - 1)
     return fail(h, DASHSVD_ERR_INVALID_ARG, "batch too large for 32-bit indices of the stacked operator");
   // work items of both sides (rows of M: U, B; rows of M^T: C, Q, V)
@@ -1636,7 +1676,7 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
   b.tws = ar.take(b.tws_bytes);
   b.scan_tmp = (int64_t *)ar.take(8 * scan_tmp_elems(std::max(m, n) + 1));
   const int64_t bprow_b = (int64_t)ld * (int64_t)dsz(pdt);
-  const int64_t bslab_b = h->opt.slab_kib > 0 ? (int64_t)h->opt.slab_kib << 10 : 0;
+  const int64_t bslab_b = slab_bytes(h, tkey);
   plan_alloc(h, ar, b.planM, m, nnz, T, ld, accsz, n, bprow_b, bslab_b);
   plan_alloc(h, ar, b.planT, n, nnz, T, ld, accsz, m, bprow_b, bslab_b);
   b.Y = ar.take(dsz(pdt) * (size_t)m * ld);
@@ -1807,13 +1847,13 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
                           gate, st);
     if (e == hipSuccess)
       e = launch_spmm(m, rpA, colA, valA, vdt, Qc, ld, pc, Yc, ld, pc, ld, b.planM.n_chunks, b.planM.order,
-                      b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, nullptr, st,
+                      b.planM.n_long, b.planM.longs, b.planM.partial, T, vm, nullptr, 0, nullptr, nullptr, st,
                       gate ? rowmatM : nullptr, b.state, n);
     return e;
   };
   // sketch: C = M^T Omega, eigSVD, Y = M Q
   HIPCHK(launch_spmm(n, b.rpT, b.colT, b.valT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ld, b.planT.n_chunks, b.planT.order,
-                     b.planT.n_long, b.planT.longs, b.planT.partial, T, nullptr, 0, nullptr, nullptr, st, nullptr,
+                     b.planT.n_long, b.planT.longs, b.planT.partial, T, vm, nullptr, 0, nullptr, nullptr, st, nullptr,
                      nullptr, m));
   HIPCHK(block(1, 0));
   // one power pass of every running matrix, captured once and replayed
@@ -1821,7 +1861,7 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
     hipError_t e = launch_bsnap(b.state, count, 1, st);
     if (e == hipSuccess)
       e = launch_spmm(n, b.rpT, b.colT, b.valT, vdt, Yc, ld, pc, b.C, ld, cdt, ld, b.planT.n_chunks,
-                      b.planT.order, b.planT.n_long, b.planT.longs, b.planT.partial, T, Qc, ld, &b.state->alpha,
+                      b.planT.order, b.planT.n_long, b.planT.longs, b.planT.partial, T, vm, Qc, ld, &b.state->alpha,
                       nullptr, st, rowmatN, b.state, m);
     if (e == hipSuccess) e = block(2, 1);
     return e;
@@ -1890,7 +1930,7 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
                                 1, st);
         if (eloop == hipSuccess)
           eloop = launch_spmm(m, rpA, colA, valA, vdt, Qc, ld, pc, Yc, ld, pc, ld, b.planM.n_chunks,
-                              b.planM.order, b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0,
+                              b.planM.order, b.planM.n_long, b.planM.longs, b.planM.partial, T, vm, nullptr, 0,
                               nullptr, nullptr, st, rowmatM, b.state, n);
         if (eloop == hipSuccess) sloop = capture(std::min(every, pmax - launched));
       }
@@ -1906,7 +1946,7 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
   // V = Q Vs(:,1:k), signs
   HIPCHK(launch_bsnap(b.state, count, 0, st));
   HIPCHK(launch_spmm(m, rpA, colA, valA, vdt, Qc, ld, pc, b.B, ld, cdt, ld, b.planM.n_chunks, b.planM.order,
-                     b.planM.n_long, b.planM.longs, b.planM.partial, T, nullptr, 0, nullptr, nullptr, st, nullptr,
+                     b.planM.n_long, b.planM.longs, b.planM.partial, T, vm, nullptr, 0, nullptr, nullptr, st, nullptr,
                      nullptr, n));
   HIPCHK(launch_bgram(itM_d, nIM, ioffM_d, count, l, b.B, ld, cdt, bpart, b.G, (int64_t)ll, b.state, 0, st));
   HIPCHK(beig(3));
@@ -1933,6 +1973,8 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
   bo.info.graph_launches = graph_launches;
   bo.info.time_loop_ms = t_loop1 - t_loop0;
   bo.info.long_row_used = T;
+  bo.info.lane_vectors_used = vm;
+  bo.info.slab_kib_used = (int32_t)(bslab_b >> 10);
   bo.info.promoted = promoted;
   bo.have = true;
   bo.count = count;
@@ -2090,6 +2132,8 @@ static dashsvd_status run_sub_batches(dashsvd_handle *h, const dashsvd_csr *As, 
     agg.promoted |= gi.promoted;
     agg.graph_launches += gi.graph_launches;
     agg.long_row_used = gi.long_row_used;
+    agg.lane_vectors_used = gi.lane_vectors_used;
+    agg.slab_kib_used = gi.slab_kib_used;
   }
   HIPCHK(hipStreamSynchronize(st));
   auto &bo = h->bat;
@@ -2154,6 +2198,7 @@ dashsvd_status dashsvd_autotune(dashsvd_handle *h, const dashsvd_csr *As, int32_
   if (!As || count < 1) return fail(h, DASHSVD_ERR_INVALID_ARG, "empty input");
   const dashsvd_options saved = h->opt;
   const std::vector<double> saved_sched = h->sched;
+  const auto saved_tune = h->tune;
   const int ld = (int)round_up(k + p, 8);
   int64_t rows = 0, nnz = 0;
   for (int i = 0; i < count; ++i) {
@@ -2162,14 +2207,25 @@ dashsvd_status dashsvd_autotune(dashsvd_handle *h, const dashsvd_csr *As, int32_
     nnz += As[i].nnz;
   }
   const std::string key = tune_key(saved.precision, ld, rows, nnz, count > 1);
-  static const int32_t kCand[] = {32, 64, 128, 256, 512, 768, 1024};
-  double best_t = 0.0;
-  int32_t best_T = 0;
+  // start from the defaults (or the options that fix a knob)
+  TuneVal cur;
+  cur.T = saved.long_row > 0 ? saved.long_row : (nnz >= DASHSVD_REORDER_MIN_NNZ ? kDefaultLongRowLarge : kDefaultLongRow);
+  cur.vm = saved.lane_vectors > 0 ? saved.lane_vectors : 1;
+  cur.slab_kib = saved.slab_kib > 0 ? saved.slab_kib : 0;
+  cur.reorder = saved.reorder != DASHSVD_REORDER_AUTO ? saved.reorder
+                                                       : (nnz >= DASHSVD_REORDER_MIN_NNZ ? 1 : -1);
   dashsvd_status s = DASHSVD_OK;
-  for (int32_t T : kCand) {
-    h->opt.long_row = T;
+  // the fastest of three short runs of configuration v (milliseconds)
+  auto time_of = [&](const TuneVal &v) -> double {
+    h->opt = saved;
+    h->sched = saved_sched;
+    h->tune.clear();
+    h->opt.long_row = v.T;
+    h->opt.lane_vectors = v.vm;
+    h->opt.slab_kib = v.slab_kib;
+    h->opt.reorder = v.reorder;
     h->opt.p_max = 2;
-    h->opt.timing = count == 1 ? 1 : 0;
+    h->opt.timing = count == 1 ? DASHSVD_TIMING_SPMM : 0;
     h->opt.shift_policy = saved.shift_policy == DASHSVD_SHIFT_LEARNED ? DASHSVD_SHIFT_PAPER : saved.shift_policy;
     double t = 0.0;
     for (int rep = 0; rep < 3 && s >= 0; ++rep) {
@@ -2183,29 +2239,46 @@ dashsvd_status dashsvd_autotune(dashsvd_handle *h, const dashsvd_csr *As, int32_
       }
       if (rep == 0 || tr < t) t = tr;
     }
-    if (s < 0) break;
-    if (best_T == 0 || t < best_t) {
-      best_t = t;
-      best_T = T;
+    return t;
+  };
+  double best_t = time_of(cur);
+  auto knob = [&](int TuneVal::*field, std::initializer_list<int> cands, bool fixed) {
+    if (fixed) return;
+    for (int c : cands) {
+      if (s < 0) return;
+      if (c == cur.*field) continue;
+      TuneVal v = cur;
+      v.*field = c;
+      const double t = time_of(v);
+      if (s >= 0 && t < best_t) {
+        best_t = t;
+        cur = v;
+      }
     }
-  }
+  };
+  knob(&TuneVal::T, {32, 64, 128, 256, 512, 768, 1024}, saved.long_row > 0);
+  knob(&TuneVal::vm, {1, 2}, saved.lane_vectors > 0);
+  knob(&TuneVal::slab_kib, {0, 2048}, saved.slab_kib > 0);
+  knob(&TuneVal::reorder, {1, -1}, count > 1 || saved.reorder != DASHSVD_REORDER_AUTO);
   const std::string err = h->err;
   h->opt = saved;
   h->sched = saved_sched;
+  h->tune = saved_tune;
   h->have = false;
   h->bat.have = false;
   if (s < 0) {
     h->err = err;
     return s;
   }
-  h->tune.emplace_back(key, best_T);
+  if (count > 1) cur.reorder = 0;  // the batched form has no degree order
+  h->tune.emplace_back(key, cur);
   if (db_path) {
     FILE *f = std::fopen(db_path, "a");
     if (!f) return fail(h, DASHSVD_ERR_INVALID_ARG, std::string("cannot append to ") + db_path);
-    std::fprintf(f, "%s %d\n", key.c_str(), best_T);
+    std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), cur.T, cur.vm, cur.slab_kib, cur.reorder);
     std::fclose(f);
   }
-  if (best) *best = best_T;
+  if (best) *best = cur.T;
   return DASHSVD_OK;
 }
 
@@ -2640,7 +2713,7 @@ hipError_t spmm_run_on(const SpmmCall &c, char *base, size_t cap) {
   if (e == hipSuccess) e = hipStreamSynchronize(c.st);
   if (e == hipSuccess)
     e = launch_spmm(c.rows, c.row_ptr, c.col, c.val, vdt, c.X, c.ldx, c.xdtype, c.Y, c.ldy, c.ydtype, ld, tot,
-                    pl.order, nl, pl.longs, pl.partial, T, c.Q, c.ldq, c.alpha, nullptr, c.st, nullptr, nullptr,
+                    pl.order, nl, pl.longs, pl.partial, T, 1, c.Q, c.ldq, c.alpha, nullptr, c.st, nullptr, nullptr,
                     c.cols);
   if (e == hipSuccess) e = hipStreamSynchronize(c.st);
   return e;

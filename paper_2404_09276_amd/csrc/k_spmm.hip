@@ -326,17 +326,19 @@ hipError_t run_spmm_v(int64_t R, const int64_t *rp, const int32_t *col, const vo
 }
 
 // Lane width: one 16-byte vector of the panel type per lane, or two when a
-// row would need more than 64 lanes (FP64 panels with l > 128).
+// row would need more than 64 lanes (FP64 panels with l > 128) or when the
+// caller asks for it (lane_mult = 2, a tuning knob: half as many lanes per
+// row, twice the gathers in flight per lane) and the row splits evenly.
 template <typename TV, typename TX, typename TY>
 hipError_t run_spmm(int64_t R, const int64_t *rp, const int32_t *col, const void *val, const void *X,
                     int64_t ldx, void *Y, int64_t ldy, int ld_cols, int64_t n_chunks,
                     const ChunkTask *tasks, int64_t n_long, const LongRow *longs, void *partial,
-                    int32_t long_row, const void *Q, int64_t ldq, const double *alpha,
+                    int32_t long_row, int lane_mult, const void *Q, int64_t ldq, const double *alpha,
                     const int32_t *done, const int32_t *rowmat, const SolverState *bstate,
                     hipStream_t st, int64_t xrows) {
   using TA = typename acc_of<TX>::type;
   constexpr int V = vec16<TX, TA>::N;
-  if (ld_cols / V <= kWave)
+  if (ld_cols / V <= kWave && !(lane_mult == 2 && ld_cols % (2 * V) == 0))
     return run_spmm_v<TV, TX, TY, V>(R, rp, col, val, X, ldx, Y, ldy, ld_cols, n_chunks, tasks, n_long, longs,
                                      partial, long_row, Q, ldq, alpha, done, rowmat, bstate, st, xrows);
   return run_spmm_v<TV, TX, TY, 2 * V>(R, rp, col, val, X, ldx, Y, ldy, ld_cols, n_chunks, tasks, n_long,
@@ -348,23 +350,27 @@ hipError_t run_spmm(int64_t R, const int64_t *rp, const int32_t *col, const void
 hipError_t launch_spmm(int64_t R, const int64_t *rp, const int32_t *col, const void *val, int vdtype,
                        const void *X, int64_t ldx, int xdtype, void *Y, int64_t ldy, int ydtype,
                        int ld_cols, int64_t n_chunks, const ChunkTask *tasks, int64_t n_long,
-                       const LongRow *longs, void *partial, int32_t long_row, const void *Q,
-                       int64_t ldq, const double *alpha, const int32_t *done, hipStream_t st,
+                       const LongRow *longs, void *partial, int32_t long_row, int lane_mult,
+                       const void *Q, int64_t ldq, const double *alpha, const int32_t *done, hipStream_t st,
                        const int32_t *rowmat, const SolverState *bstate, int64_t xrows) {
   // supported combinations: (values, X/Q, Y) = (f32, f32, f32), (f64, f64, f64),
   // (f32, bf16, bf16), (f32, bf16, f32)
   if (xdtype == 0 && ydtype == 0 && vdtype == 0)
     return run_spmm<float, float, float>(R, rp, col, val, X, ldx, Y, ldy, ld_cols, n_chunks, tasks, n_long,
-                                         longs, partial, long_row, Q, ldq, alpha, done, rowmat, bstate, st, xrows);
+                                         longs, partial, long_row, lane_mult, Q, ldq, alpha, done, rowmat,
+                                         bstate, st, xrows);
   if (xdtype == 1 && ydtype == 1 && vdtype == 1)
     return run_spmm<double, double, double>(R, rp, col, val, X, ldx, Y, ldy, ld_cols, n_chunks, tasks,
-                                            n_long, longs, partial, long_row, Q, ldq, alpha, done, rowmat, bstate, st, xrows);
+                                            n_long, longs, partial, long_row, lane_mult, Q, ldq, alpha, done,
+                                            rowmat, bstate, st, xrows);
   if (xdtype == 2 && ydtype == 2 && vdtype == 0)
     return run_spmm<float, bf16, bf16>(R, rp, col, val, X, ldx, Y, ldy, ld_cols, n_chunks, tasks, n_long,
-                                       longs, partial, long_row, Q, ldq, alpha, done, rowmat, bstate, st, xrows);
+                                       longs, partial, long_row, lane_mult, Q, ldq, alpha, done, rowmat, bstate,
+                                       st, xrows);
   if (xdtype == 2 && ydtype == 0 && vdtype == 0)
     return run_spmm<float, bf16, float>(R, rp, col, val, X, ldx, Y, ldy, ld_cols, n_chunks, tasks, n_long,
-                                        longs, partial, long_row, Q, ldq, alpha, done, rowmat, bstate, st, xrows);
+                                        longs, partial, long_row, lane_mult, Q, ldq, alpha, done, rowmat, bstate,
+                                        st, xrows);
   return hipErrorInvalidValue;
 }
 

@@ -13,9 +13,11 @@ eps_PVE (Sec. 4) is measured against reference singular values.  The label
 is the c that meets eps_PVE <= tol in the fewest passes (ties go to the
 smaller c), and N* is that pass count.
 
-Training matrices: a pool of power-law matrices (rows U[20k, 100k], columns
+Training matrices: a pool of power-law matrices (rows U[lo, hi], columns
 U(0.5, 1) x rows, mean nonzeros per row log-uniform in [4, 64], Zipf 1.1
-degrees), seeds 10^6 + i; held-out matrices use seeds 2 x 10^6 + i.
+degrees), seeds 10^6 + i; held-out matrices use seeds 2 x 10^6 + i.  The
+shipped model uses rows U[50k, 500k] and five Omega seeds per matrix (each
+seed gives its own features and label).
 """
 import math
 
@@ -28,17 +30,32 @@ from .dashsvd import DashSVD
 C_FAMILY = (0.5, 0.6, 0.7, 0.8, 0.9)
 
 
+def pool_member(seed: int, rows=(20000, 100000), degree=(4.0, 64.0)):
+    """One power-law training / held-out matrix (see the module doc)."""
+    rng = np.random.default_rng(seed)
+    m = int(rng.integers(rows[0], rows[1] + 1))
+    n = max(1, int(np.floor(rng.uniform(0.5, 1.0) * m)))
+    deg = math.exp(rng.uniform(math.log(degree[0]), math.log(degree[1])))
+    nnz = min(int(round(deg * m)), m * n // 2)
+    return synth.zipf_csr(m, n, nnz, seed=seed)
+
+
 def pool(count: int, seed0: int, rows=(20000, 100000), degree=(4.0, 64.0)) -> list:
     """Power-law training / held-out matrices (see the module doc)."""
-    out = []
-    for i in range(count):
-        rng = np.random.default_rng(seed0 + i)
-        m = int(rng.integers(rows[0], rows[1] + 1))
-        n = max(1, int(np.floor(rng.uniform(0.5, 1.0) * m)))
-        deg = math.exp(rng.uniform(math.log(degree[0]), math.log(degree[1])))
-        nnz = min(int(round(deg * m)), m * n // 2)
-        out.append(synth.zipf_csr(m, n, nnz, seed=seed0 + i))
-    return out
+    return [pool_member(seed0 + i, rows, degree) for i in range(count)]
+
+
+def to_device(A, torch):
+    """A copy of CSR A whose arrays live on the GPU (the solver then reads
+    them in place)."""
+    class D:
+        pass
+    d = D()
+    d.m, d.n, d.nnz = A.m, A.n, A.nnz
+    d.row_ptr = torch.from_numpy(np.ascontiguousarray(A.row_ptr)).cuda()
+    d.col = torch.from_numpy(np.ascontiguousarray(A.col)).cuda()
+    d.val = torch.from_numpy(np.ascontiguousarray(A.val)).cuda()
+    return d
 
 
 def reference_sigma(A, k: int, seed: int = 11) -> np.ndarray:
@@ -85,22 +102,24 @@ def label(A, k: int, s: int, tol: float, seed: int, sigma_ref, precision: str = 
     return feats, c_star, n_star, table
 
 
-def collect(mats, k: int, s: int, tol: float, seed: int, precision: str = "fp32", log=None):
+def collect(mats, k: int, s: int, tol: float, seed: int, precision: str = "fp32", log=None, seeds_per_matrix=1):
     """Training arrays X (count x (3l+3)), Y (count x 2: c*, log N*) and the
-    per-matrix tables."""
+    per-sample tables; matrix i is run with the Omega seeds
+    seed + i * seeds_per_matrix + j, j < seeds_per_matrix, each a sample."""
     X, Y, tables = [], [], []
     for i, A in enumerate(mats):
         sig = reference_sigma(A, k)
-        r = label(A, k, s, tol, seed + i, sig, precision)
-        if r is None:
-            continue
-        f, c, n, table = r
-        X.append(f)
-        Y.append((c, math.log(n)))
-        tables.append(table)
-        if log:
-            log(f"  matrix {i}: {A.m}x{A.n} nnz {A.nnz}: c*={c} N*={n} "
-                + " ".join(f"({t[0]:.1f}:{t[1]},{t[2]:.1e})" for t in table))
+        for j in range(seeds_per_matrix):
+            r = label(A, k, s, tol, seed + i * seeds_per_matrix + j, sig, precision)
+            if r is None:
+                continue
+            f, c, n, table = r
+            X.append(f)
+            Y.append((c, math.log(n)))
+            tables.append(table)
+            if log:
+                log(f"  matrix {i} seed {j}: {A.m}x{A.n} nnz {A.nnz}: c*={c} N*={n} "
+                    + " ".join(f"({t[0]:.1f}:{t[1]},{t[2]:.1e})" for t in table))
     return np.array(X, dtype=np.float32), np.array(Y, dtype=np.float32), tables
 
 

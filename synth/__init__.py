@@ -212,21 +212,29 @@ def config_zipf_2m() -> CSR:
     return zipf_csr(2_000_000, 1_000_000, 100_000_000, seed=1003)
 
 
+def batched_zipf_shape(b: int, rows=(1000, 100000), density=(0.0005, 0.01), seed: int = 5000):
+    """(m, n, nnz) of member b of batched_zipf, without building it."""
+    rng = np.random.default_rng(seed + b)
+    m = int(rng.integers(rows[0], rows[1] + 1))
+    n = max(1, int(np.floor(rng.uniform(0.5, 1.0) * m)))
+    d = float(rng.uniform(density[0], density[1]))
+    return m, n, max(m, int(round(d * m * n)))
+
+
+def batched_zipf_member(b: int, rows=(1000, 100000), density=(0.0005, 0.01), seed: int = 5000) -> CSR:
+    """Member b of batched_zipf (independent of the others, so a batch can be
+    built in parallel)."""
+    m, n, nnz = batched_zipf_shape(b, rows, density, seed)
+    return zipf_csr(m, n, nnz, seed=seed + b)
+
+
 def batched_zipf(count: int, rows=(1000, 100000), density=(0.0005, 0.01), seed: int = 5000) -> list:
     """Batch of independent power-law matrices: matrix b has rows
     U[rows[0], rows[1]], columns floor(U(0.5, 1) * rows), density
     U[density[0], density[1]] and Zipf 1.1 degrees, drawn from seed + b
     (the full-size batched workload is 512 matrices with the default
     ranges)."""
-    out = []
-    for b in range(count):
-        rng = np.random.default_rng(seed + b)
-        m = int(rng.integers(rows[0], rows[1] + 1))
-        n = max(1, int(np.floor(rng.uniform(0.5, 1.0) * m)))
-        d = float(rng.uniform(density[0], density[1]))
-        nnz = max(m, int(round(d * m * n)))
-        out.append(zipf_csr(m, n, nnz, seed=seed + b))
-    return out
+    return [batched_zipf_member(b, rows, density, seed) for b in range(count)]
 
 
 OMEGA_SEED = {"small": 2001, "zipf_200k": 2002, "zipf_2m": 2003}

@@ -270,10 +270,12 @@ def test_batched_errors(torch_dev):
 
 
 def test_autotune_writes_and_applies_database(torch_dev, tmp_path):
-    """dashsvd_autotune picks one of its candidate chunk lengths for a single
-    matrix and for a batch, appends them to the database, and a handle that
-    reads the database runs with them; results stay within rounding of the
-    default chunking."""
+    """dashsvd_autotune searches the chunk length, the lane vectors, the
+    column slabs and (single matrix) the degree order for a single matrix and
+    for a batch, appends "key T lanes slab_kib reorder" to the database, and
+    a handle that reads the database runs with those knobs; results stay
+    within rounding of the default configuration.  Options that fix a knob
+    keep it."""
     from paper_2404_09276_amd import DashSVD
     db = str(tmp_path / "tune.txt")
     A = synth.zipf_csr(20000, 9000, 400000, seed=61)
@@ -282,21 +284,33 @@ def test_autotune_writes_and_applies_database(torch_dev, tmp_path):
     t1 = h.autotune(A, 16, 8, db)
     t2 = h.autotune(mats, 16, 8, db)
     h.close()
-    cands = {32, 64, 128, 256, 512, 1024}
+    cands = {32, 64, 128, 256, 512, 768, 1024}
     assert t1 in cands and t2 in cands
-    lines = open(db).read().split("\n")
-    assert lines[0].endswith(f"_s {t1}") and lines[1].endswith(f"_b {t2}")
+    lines = [ln.split() for ln in open(db).read().split("\n") if ln]
+    assert len(lines) == 2 and lines[0][0].endswith("_s") and lines[1][0].endswith("_b")
+    (T1, v1, s1, r1), (T2, v2, s2, r2) = [tuple(int(x) for x in ln[1:]) for ln in lines]
+    assert (T1, T2) == (t1, t2) and v1 in (1, 2) and v2 in (1, 2) and s1 in (0, 2048) and s2 in (0, 2048)
+    assert r1 in (1, -1) and r2 == 0
     h = DashSVD(precision="fp32", p_max=6, seed=3, tuning_db=db)
     U, S, V, st, info = h.solve(A, 16, 8, 0.0)
-    assert info.long_row_used == t1
+    assert (info.long_row_used, info.lane_vectors_used, info.slab_kib_used) == (T1, v1, s1)
+    assert info.reordered == (r1 > 0)
     h.run_batched(mats, 16, 8, 0.0)
-    assert h.info_batched(-1).long_row_used == t2
+    sb = h.info_batched(-1)
+    assert (sb.long_row_used, sb.lane_vectors_used, sb.slab_kib_used) == (T2, v2, s2)
     h.close()
     h = DashSVD(precision="fp32", p_max=6, seed=3)
     U0, S0, V0, st0, info0 = h.solve(A, 16, 8, 0.0)
     h.close()
-    assert info0.long_row_used == 128
+    assert info0.long_row_used == 128 and info0.lane_vectors_used == 1 and info0.slab_kib_used == 0
     assert np.all(np.abs(S - S0) / S0 <= 1e-5)
+    # a fixed knob stays fixed
+    h = DashSVD(precision="fp32", p_max=6, seed=3, lane_vectors=2, long_row=256)
+    assert h.autotune(A, 16, 8, None) == 256
+    U2, S2, V2, st2, info2 = h.solve(A, 16, 8, 0.0)
+    assert info2.lane_vectors_used == 2 and info2.long_row_used == 256
+    assert np.all(np.abs(S2 - S0) / S0 <= 1e-5)
+    h.close()
 
 
 def test_batched_bf16_promotion_guard(torch_dev):

@@ -42,6 +42,30 @@ def _vec_close(X, Xref, tol):
     return d.max() <= tol
 
 
+@pytest.mark.parametrize("prec,bar,k,s", [("fp64", 1e-10, 20, 10), ("fp32", 1e-5, 20, 10), ("fp32", 1e-5, 100, 20),
+                                          ("bf16", 5e-3, 20, 12)])
+def test_two_lane_vectors_match_oracle(torch_dev, prec, bar, k, s):
+    """lane_vectors = 2 (two 16-byte panel vectors per lane, half as many
+    lanes per row) on a power-law matrix with long rows, fixed passes: the
+    oracle's singular values within the form's bar, and the one-vector run's
+    within rounding (FP64, FP32: a tenth of the bar).  The long rows' chunk
+    partials are summed in another order when a workgroup holds more lane
+    groups, so FP32 sums differ in the last bits; with BF16 panels such a
+    difference can move a BF16 rounding of Y (2^-9 relative), so the two
+    BF16 runs are held to each other at the BF16 bar only.  BF16 with l = 32
+    (the row of 32 BF16 elements splits into 16-element lanes); a row that
+    does not split evenly keeps one vector per lane."""
+    A = synth.zipf_csr(30000, 12000, 500000, seed=73)
+    if prec == "fp64":
+        A.val = A.val.astype(np.float64)
+    ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val.astype(np.float64), k, s, 4, 0.0, seed=9)
+    U1, S1, V1, st1, info1, _ = _solve(A, k, s, 4, 0.0, 9, prec, lane_vectors=1)
+    U2, S2, V2, st2, info2, _ = _solve(A, k, s, 4, 0.0, 9, prec, lane_vectors=2)
+    assert st1 == st2 == 0 and info2.lane_vectors_used == 2
+    assert np.all(np.abs(S2 - ref.S) / ref.S <= bar)
+    assert np.all(np.abs(S2 - S1) / S1 <= {"fp64": 1e-12, "fp32": bar / 10, "bf16": bar}[prec])
+
+
 def test_small_fp64_fixed_passes(torch_dev):
     """2000 x 1500 uniform, k=20, s=10, 5 passes (Alg. 4): FP64 parity."""
     A = synth.config_small(np.float64)
