@@ -108,6 +108,14 @@ typedef int32_t dashsvd_status;
 #define DASHSVD_EIG_AUTO 0
 #define DASHSVD_EIG_JACOBI 1
 #define DASHSVD_EIG_ONESIDED 2
+/*   TRIDIAG: for l <= 128 in the FP32 and BF16 forms, every block by
+ *       the tridiagonal eigensolver (Householder reduction, multisection
+ *       eigenvalues, twisted-factorisation eigenvectors, back-transformation:
+ *       normwise accurate like the paper's LAPACK eig); where eigenvalues lie
+ *       within 2^-30 ||G|| of each other the call goes to the two-sided
+ *       solver, as do all calls above 128, calls without eigenvector output
+ *       and the FP64 form (whose Jacobi keeps relative accuracy). */
+#define DASHSVD_EIG_TRIDIAG 3
 
 #define DASHSVD_MAX_L 160     /* largest supported l = k + oversampling */
 #define DASHSVD_MAX_TRACE 256 /* passes recorded in dashsvd_info */
@@ -530,6 +538,17 @@ dashsvd_status dashsvd_k_eig_prof(int32_t l, const double *G, double *S, double 
  * cycles of the Cholesky phase.  Synchronises the stream. */
 dashsvd_status dashsvd_k_eig_onesided(int32_t l, const double *G, double *S, double *Vs, double *W, double skip,
                                       int32_t *sweeps, int32_t *accepted, long long *prof, void *stream);
+
+/* The eigensolver of dashsvd_k_eig by tridiagonalisation (eig_method
+ * TRIDIAG, Alg. 3 steps 1-4): Householder reduction G = H T H^T, the
+ * eigenvalues of T by multisection on Sturm counts, its eigenvectors from
+ * twisted factorisations, V = H Z.  Same outputs and ordering as
+ * dashsvd_k_eig; Vs is required (W and Vs also hold the factorisations
+ * before the results).  l <= 128.  *accepted (host) is 0 when two
+ * eigenvalues lie within 2^-30 ||G|| of each other or G has a non-finite
+ * entry; then nothing is written.  Synchronises the stream. */
+dashsvd_status dashsvd_k_eig_tridiag(int32_t l, const double *G, double *S, double *Vs, double *W,
+                                     int32_t *accepted, void *stream);
 
 /* Orthonormalisation of a pass block without eigenvectors (the solver of
  * the sketch and power passes under eig_method AUTO): from G (device, l x l

@@ -396,6 +396,12 @@ hipError_t launch_eig_batched(const EigArgs *arr, int count, int l, hipStream_t 
 // positive definite to working precision, and the two-sided kernel gated
 // on the flag (run_if = decline) then runs.
 hipError_t launch_eig1s(const EigArgs &a, hipStream_t st);
+// Tridiagonal eigensolver (k_eigtri.hip): Householder reduction, multisection
+// eigenvalues, twisted-factorisation eigenvectors, back-transformation; the
+// same outputs and tail as launch_eig for l <= 128 (a.W and a.Vs required:
+// they also serve as scratch); declines (*a.decline = 1, nothing written) on
+// eigenvalue clusters and non-finite G.
+hipError_t launch_eigtri(const EigArgs &a, hipStream_t st);
 hipError_t launch_eig1s_batched(const EigArgs *arr, int count, int l, hipStream_t st);
 
 // ------------------------------------------------------------------ batched form

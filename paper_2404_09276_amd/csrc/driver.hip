@@ -399,7 +399,7 @@ dashsvd_status dashsvd_set_options(dashsvd_handle *h, const dashsvd_options *opt
   if (o.precision < 0 || o.precision > 2) return fail(h, DASHSVD_ERR_INVALID_ARG, "precision");
   if (o.shift_policy < 0 || o.shift_policy > 4) return fail(h, DASHSVD_ERR_INVALID_ARG, "shift_policy");
   if (o.pve_mode < 0 || o.pve_mode > 2) return fail(h, DASHSVD_ERR_INVALID_ARG, "pve_mode");
-  if (o.eig_method < 0 || o.eig_method > 2) return fail(h, DASHSVD_ERR_INVALID_ARG, "eig_method");
+  if (o.eig_method < 0 || o.eig_method > 3) return fail(h, DASHSVD_ERR_INVALID_ARG, "eig_method");
   if (o.reorder < -1 || o.reorder > 1) return fail(h, DASHSVD_ERR_INVALID_ARG, "reorder");
   if (o.lane_vectors > 2) return fail(h, DASHSVD_ERR_INVALID_ARG, "lane_vectors (1 or 2; <= 0: tuned or 1)");
   if (o.p_max < 0) o.p_max = kDefaultPmax;
@@ -824,11 +824,15 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   // ONESIDED: one-sided Jacobi on the Cholesky factor (l <= 128), the
   // two-sided kernel where it declines
   const bool onesided = h->opt.eig_method == DASHSVD_EIG_ONESIDED && l <= 128;
+  // TRIDIAG: the tridiagonal eigensolver (l <= 128), the two-sided kernel
+  // where it declines
+  const bool tridiag = h->opt.eig_method == DASHSVD_EIG_TRIDIAG && l <= 128 && prec != DASHSVD_PREC_FP64;
   auto eig_solve = [&](const EigArgs &ea, hipStream_t s) -> hipError_t {
-    if (!onesided) return launch_eig(ea, s);
+    const bool tri = tridiag && ea.Vs && ea.W;
+    if (!onesided && !tri) return launch_eig(ea, s);
     EigArgs e1 = ea;
     e1.decline = &b.state->j1_decline;
-    hipError_t e = launch_eig1s(e1, s);
+    hipError_t e = tri ? launch_eigtri(e1, s) : launch_eig1s(e1, s);
     if (e != hipSuccess) return e;
     EigArgs e2 = ea;
     e2.run_if = &b.state->j1_decline;
@@ -2858,6 +2862,32 @@ dashsvd_status dashsvd_k_eig_onesided(int32_t l, const double *G, double *S, dou
   ea.decline = flag;
   int32_t declined = 1;
   hipError_t e = launch_eig1s(ea, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&declined, flag, 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(flag);
+  HIPCHK(e);
+  *accepted = declined ? 0 : 1;
+  return DASHSVD_OK;
+}
+
+dashsvd_status dashsvd_k_eig_tridiag(int32_t l, const double *G, double *S, double *Vs, double *W,
+                                     int32_t *accepted, void *stream) {
+  dashsvd_handle *h = nullptr;
+  if (l < 1 || l > 128 || !G || !S || !W || !Vs || !accepted)
+    return fail(h, DASHSVD_ERR_INVALID_ARG, "tridiagonal eig arguments (l <= 128, Vs required)");
+  hipStream_t st = (hipStream_t)stream;
+  int32_t *flag = nullptr;
+  HIPCHK(hipMalloc(&flag, sizeof(int32_t)));
+  EigArgs ea;
+  std::memset(&ea, 0, sizeof(ea));
+  ea.l = l;
+  ea.G = G;
+  ea.S = S;
+  ea.Vs = Vs;
+  ea.W = W;
+  ea.decline = flag;
+  int32_t declined = 1;
+  hipError_t e = launch_eigtri(ea, st);
   if (e == hipSuccess) e = hipMemcpyAsync(&declined, flag, 4, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   (void)hipFree(flag);

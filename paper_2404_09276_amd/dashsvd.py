@@ -23,7 +23,7 @@ F32, F64, BF16 = 0, 1, 2
 PREC = {"fp32": 0, "fp64": 1, "bf16": 2}
 SHIFT = {"paper": 0, "none": 1, "fixed": 2, "schedule": 3, "learned": 4}
 PVE = {"r2": 0, "r1": 1, "nosurr": 2}
-EIG = {"auto": 0, "jacobi": 1, "onesided": 2}
+EIG = {"auto": 0, "jacobi": 1, "onesided": 2, "tridiag": 3}
 # timing: False / True (every kernel group) / "spmm" (the two SpMM groups only)
 TIMING = {False: 0, True: 1, "spmm": 2}
 # reorder: "auto" (from 2^22 nonzeros), True, False
@@ -91,7 +91,7 @@ EXPORTS = [
     "dashsvd_last_error", "dashsvd_k_gaussian", "dashsvd_k_philox_raw", "dashsvd_k_sort_index",
     "dashsvd_k_transpose",
     "dashsvd_k_spmm", "dashsvd_k_spmm_static", "dashsvd_k_gram", "dashsvd_k_eig", "dashsvd_k_eig_prof", "dashsvd_k_eig_onesided",
-    "dashsvd_k_cholqr", "dashsvd_k_rescale",
+    "dashsvd_k_eig_tridiag", "dashsvd_k_cholqr", "dashsvd_k_rescale",
 ]
 
 
@@ -147,6 +147,7 @@ def lib():
         L.dashsvd_k_eig.argtypes = [i32, P, P, P, P, P, P]
         L.dashsvd_k_eig_prof.argtypes = [i32, P, P, P, P, P, P, P]
         L.dashsvd_k_eig_onesided.argtypes = [i32, P, P, P, P, f64, P, P, P, P]
+        L.dashsvd_k_eig_tridiag.argtypes = [i32, P, P, P, P, P, P]
         L.dashsvd_k_rescale.argtypes = [i64, i32, P, i64, i32, P, i64, i32, P, i64, i32, P]
         for name in EXPORTS:
             if name not in ("dashsvd_destroy", "dashsvd_status_string", "dashsvd_last_error"):
@@ -582,6 +583,15 @@ def k_eig_onesided(G, S, Vs, W, skip=2.0**-53, sweeps=None, prof=None, stream=No
     acc = C.c_int32(0)
     _check(lib().dashsvd_k_eig_onesided(l, _ptr(G), _ptr(S), _ptr(Vs), _ptr(W), C.c_double(skip), _ptr(sweeps),
                                         C.byref(acc), _ptr(prof), _stream_ptr(stream)))
+    return bool(acc.value)
+
+
+def k_eig_tridiag(G, S, Vs, W, stream=None) -> bool:
+    """The tridiagonal eigensolver (l <= 128); True if G was accepted (no
+    eigenvalue cluster, finite entries), else nothing is written."""
+    l = G.shape[0]
+    acc = C.c_int32(0)
+    _check(lib().dashsvd_k_eig_tridiag(l, _ptr(G), _ptr(S), _ptr(Vs), _ptr(W), C.byref(acc), _stream_ptr(stream)))
     return bool(acc.value)
 
 

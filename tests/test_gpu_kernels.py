@@ -442,6 +442,68 @@ def test_eig_onesided_rejects_large_l(torch_dev):
         _eig1s(torch_dev, np.eye(129))
 
 
+# ------------------------------------------------------------------ tridiagonal eigensolver
+def _eigtri(torch, G):
+    from paper_2404_09276_amd import k_eig_tridiag
+    l = G.shape[0]
+    S = torch.full((l,), -1.0, dtype=torch.float64, device="cuda")
+    Vs = torch.full((l, l), -1.0, dtype=torch.float64, device="cuda")
+    W = torch.full((l, l), -1.0, dtype=torch.float64, device="cuda")
+    acc = k_eig_tridiag(_dev(torch, G), S, Vs, W)
+    return acc, S.cpu().numpy(), Vs.cpu().numpy(), W.cpu().numpy()
+
+
+@pytest.mark.parametrize("l", [1, 2, 3, 5, 16, 24, 30, 31, 32, 33, 64, 65, 75, 96, 110, 120, 127, 128])
+def test_eig_tridiag_matches_lapack(torch_dev, l):
+    """Householder + multisection + twisted factorisations + back-transform,
+    ragged sizes up to 128: eigenvalues against LAPACK and the oracle's Jacobi
+    within 100 l eps ||G|| (normwise, as the paper's LAPACK eig), Vs
+    orthonormal to 1e-8 (graded spectra; the FP32 and BF16 forms that use it
+    store Q to 2^-24), residual at the eigenvalue level, W = Vs / S."""
+    rng = np.random.default_rng(400 + l)
+    B = rng.standard_normal((l + 7, l)) @ np.diag(np.logspace(0, -2, l))
+    G = B.T @ B
+    acc, s, V, Wm = _eigtri(torch_dev, G)
+    assert acc
+    lam = np.linalg.eigvalsh(G)[::-1]
+    nrm = lam[0]
+    assert np.all(np.diff(s) <= 0)
+    assert np.abs(s**2 - lam).max() <= 100 * l * 2.2e-16 * nrm
+    assert np.abs(V.T @ V - np.eye(l)).max() < 1e-8
+    assert np.linalg.norm(G @ V - V * s**2) <= 100 * l * 2.2e-16 * nrm
+    assert np.allclose(Wm, V / s, rtol=1e-14, atol=0)
+    ev, _, _ = oracle.jacobi_eig(G)
+    assert np.abs(np.sqrt(np.maximum(ev[::-1], 0)) ** 2 - s**2).max() <= 100 * l * 2.2e-16 * nrm
+
+
+def test_eig_tridiag_structured_and_declines(torch_dev):
+    """Already-tridiagonal and diagonal G (reflector-free steps), a dense G
+    with well separated eigenvalues; clusters (repeated eigenvalues, a
+    block-diagonal G with equal blocks) and non-finite G decline."""
+    rng = np.random.default_rng(5)
+    T = np.diag(np.arange(1.0, 41.0)) + np.diag(np.full(39, 0.3), 1) + np.diag(np.full(39, 0.3), -1)
+    Q, _ = np.linalg.qr(rng.standard_normal((50, 50)))
+    for G in (np.diag([4.0, 9.0, 1.0, 16.0, 25.0]), T, (Q * np.linspace(1.0, 50.0, 50)) @ Q.T):
+        G = 0.5 * (G + G.T)
+        l = G.shape[0]
+        acc, s, V, Wm = _eigtri(torch_dev, G)
+        assert acc
+        lam = np.linalg.eigvalsh(G)[::-1]
+        assert np.allclose(s**2, lam, rtol=0, atol=100 * l * 2.2e-16 * lam[0])
+        assert np.abs(V.T @ V - np.eye(l)).max() < 1e-12
+    for G in (np.diag([1.0, 2.0, 2.0, 3.0]), np.kron(np.eye(4), np.array([[2.0, 1.0], [1.0, 3.0]])),
+              np.diag([1.0, np.nan, 2.0])):
+        acc, s, V, Wm = _eigtri(torch_dev, G)
+        assert not acc
+        assert np.all(s == -1.0) and np.all(Wm == -1.0)
+
+
+def test_eig_tridiag_rejects_large_l(torch_dev):
+    from paper_2404_09276_amd import DashSVDError
+    with pytest.raises(DashSVDError):
+        _eigtri(torch_dev, np.eye(129))
+
+
 # ------------------------------------------------------------------ Cholesky-QR pass solver
 def _cholqr(torch, G):
     from paper_2404_09276_amd import k_cholqr

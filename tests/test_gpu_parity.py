@@ -393,6 +393,25 @@ def test_eig_methods_agree(torch_dev, prec, bar):
     assert out["onesided"][2].cholqr_calls == 0
 
 
+@pytest.mark.parametrize("prec,bar", [("fp32", 1e-5), ("bf16", 5e-3)])
+def test_eig_tridiag_method_matches_oracle(torch_dev, prec, bar):
+    """eig_method TRIDIAG (every block by the tridiagonal eigensolver) in the
+    FP32 and BF16 forms: the oracle's singular values within the form's bar;
+    FP32 also with the oracle's passes, shifts and ratios."""
+    A = synth.zipf_csr(20000, 12000, 300000, seed=31)
+    ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 40, 20, 64, 1e-2, seed=7)
+    U, S, V, st, info, tr = _solve(A, 40, 20, 64, 1e-2, 7, prec, eig_method="tridiag")
+    assert st == 0 and info.converged and info.cholqr_calls == 0
+    assert np.all(info.sweeps_per_call == 0)
+    assert np.all(np.abs(S - ref.S) / ref.S <= bar)
+    if prec == "fp32":
+        assert info.passes == ref.passes
+        assert np.allclose(info.alpha_used, ref.alpha, rtol=bar, atol=0)
+        assert np.allclose(info.ratio, ref.ratio, rtol=100 * bar, atol=0)
+        Uj, Sj, Vj, stj, infoj, _ = _solve(A, 40, 20, 64, 1e-2, 7, prec, eig_method="jacobi")
+        assert _vec_close(V, Vj, 2e-3) and _vec_close(U, Uj, 2e-3)
+
+
 def test_eig_methods_zipf_fp32(torch_dev):
     """Power-law matrix, FP32 form, k = 40, s = 20: the three methods reach
     the oracle's singular values within the FP32 bar in the same passes."""
