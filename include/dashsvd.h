@@ -90,32 +90,35 @@ typedef int32_t dashsvd_status;
 
 /* The eigensolver of eigSVD (Alg. 3 steps 1-4) for the sketch, pass and
  * final blocks.
- *   AUTO (default): the sketch and the early pass blocks by Cholesky-QR:
- *       W = R^-1 from G = C^T C = R^T R, so that Q = C W is orthonormal with
- *       the span of eigSVD's Q, and S from the eigenvalues of G (Householder
- *       tridiagonalisation and Sturm-count bisection, FP64).  The passes use
- *       only S and span(Q), which both bases share.  Two-sided Jacobi from
- *       the first pass whose PVE ratio is within 100 tol, for the last two
- *       pass blocks, where G is not safely positive definite (lambda_min <=
- *       2^-32 lambda_max, or a failed factorisation) and for the final step.
+ *   AUTO (default): TRIDIAG in the FP32 and BF16 forms, CHOLQR in the FP64
+ *       form.
  *   JACOBI: two-sided Jacobi on G for every block.
  *   ONESIDED: for l <= 128, one-sided Jacobi on the Cholesky factor of G
  *       (rotations J orthogonalise the columns of R^T; R^T J = V diag(S)
  *       gives the eigenvectors V and S = sqrt(eig G) together) for every
  *       block; where the factorisation meets a non-positive pivot (G
  *       singular to working precision) the call goes to the two-sided
- *       solver, as do all calls above 128. */
+ *       solver, as do all calls above 128.
+ *   TRIDIAG: in the FP32 and BF16 forms, every block by the tridiagonal
+ *       eigensolver (Householder reduction, multisection eigenvalues,
+ *       twisted-factorisation eigenvectors, back-transformation: normwise
+ *       accurate like the paper's LAPACK eig); where eigenvalues lie within
+ *       2^-30 ||G|| of each other the call goes to the two-sided solver, as
+ *       do calls without eigenvector output and the FP64 form (whose Jacobi
+ *       keeps relative accuracy).
+ *   CHOLQR: the sketch and the early pass blocks by Cholesky-QR: W = R^-1
+ *       from G = C^T C = R^T R, so that Q = C W is orthonormal with the span
+ *       of eigSVD's Q, and S from the eigenvalues of G (Householder
+ *       tridiagonalisation and Sturm-count bisection, FP64).  The passes use
+ *       only S and span(Q), which both bases share.  Two-sided Jacobi from
+ *       the first pass whose PVE ratio is within 100 tol, for the last two
+ *       pass blocks, where G is not safely positive definite (lambda_min <=
+ *       2^-32 lambda_max, or a failed factorisation) and for the final step. */
 #define DASHSVD_EIG_AUTO 0
 #define DASHSVD_EIG_JACOBI 1
 #define DASHSVD_EIG_ONESIDED 2
-/*   TRIDIAG: for l <= 128 in the FP32 and BF16 forms, every block by
- *       the tridiagonal eigensolver (Householder reduction, multisection
- *       eigenvalues, twisted-factorisation eigenvectors, back-transformation:
- *       normwise accurate like the paper's LAPACK eig); where eigenvalues lie
- *       within 2^-30 ||G|| of each other the call goes to the two-sided
- *       solver, as do all calls above 128, calls without eigenvector output
- *       and the FP64 form (whose Jacobi keeps relative accuracy). */
 #define DASHSVD_EIG_TRIDIAG 3
+#define DASHSVD_EIG_CHOLQR 4
 
 #define DASHSVD_MAX_L 160     /* largest supported l = k + oversampling */
 #define DASHSVD_MAX_TRACE 256 /* passes recorded in dashsvd_info */
@@ -540,15 +543,20 @@ dashsvd_status dashsvd_k_eig_onesided(int32_t l, const double *G, double *S, dou
                                       int32_t *sweeps, int32_t *accepted, long long *prof, void *stream);
 
 /* The eigensolver of dashsvd_k_eig by tridiagonalisation (eig_method
- * TRIDIAG, Alg. 3 steps 1-4): Householder reduction G = H T H^T, the
- * eigenvalues of T by multisection on Sturm counts, its eigenvectors from
- * twisted factorisations, V = H Z.  Same outputs and ordering as
- * dashsvd_k_eig; Vs is required (W and Vs also hold the factorisations
- * before the results).  l <= 128.  *accepted (host) is 0 when two
- * eigenvalues lie within 2^-30 ||G|| of each other or G has a non-finite
- * entry; then nothing is written.  Synchronises the stream. */
+ * TRIDIAG, Alg. 3 steps 1-4): Householder reduction G = H T H^T in one
+ * workgroup, then one wave per eigenvalue: multisection on Sturm counts,
+ * the eigenvector of T from its twisted factorisation, V = H z.  Same
+ * outputs and ordering as dashsvd_k_eig; Vs is required (W holds the
+ * reflectors before the result).  l <= 160.  *accepted (host) is 0 when two
+ * eigenvalues lie within 2^-30 ||G|| of each other, or G is zero or has a
+ * non-finite entry; then S, Vs and W hold no result.  prof (device,
+ * optional, 6 int64): cycles of the reduction, then, as seen by the first
+ * wave of the eigenvalue kernel, of the multisection, the isolation check,
+ * the factorisations with the twist and z, the back-transformation, and
+ * the cycles of the last workgroup's W and tail.  Allocates a small
+ * workspace; synchronises the stream. */
 dashsvd_status dashsvd_k_eig_tridiag(int32_t l, const double *G, double *S, double *Vs, double *W,
-                                     int32_t *accepted, void *stream);
+                                     int32_t *accepted, long long *prof, void *stream);
 
 /* Orthonormalisation of a pass block without eigenvectors (the solver of
  * the sketch and power passes under eig_method AUTO): from G (device, l x l

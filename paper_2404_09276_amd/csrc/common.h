@@ -327,7 +327,9 @@ struct EigArgs {
   double cq_switch;       // pass tail: set state->cq_off once ratio <= cq_switch x tol (0: never)
   int32_t call_idx;       // > 0: store it to state->eig_started when the call starts working
   int32_t *decline;       // one-sided Jacobi: set to 1 when its Cholesky factorisation fails
-                          // (the two-sided kernel gated on it then runs), else 0
+                          // (the two-sided kernel gated on it then runs), else 0; the
+                          // tridiagonal solver: set to 1 on clusters or non-finite G
+  double *tri_ws;         // tridiagonal solver: workspace of kTriWsBytes
 };
 // Store idx to *flag (agent scope): an eigensolver call has started.
 __device__ __forceinline__ void signal_started(int32_t *flag, int32_t idx) {
@@ -396,11 +398,15 @@ hipError_t launch_eig_batched(const EigArgs *arr, int count, int l, hipStream_t 
 // positive definite to working precision, and the two-sided kernel gated
 // on the flag (run_if = decline) then runs.
 hipError_t launch_eig1s(const EigArgs &a, hipStream_t st);
-// Tridiagonal eigensolver (k_eigtri.hip): Householder reduction, multisection
-// eigenvalues, twisted-factorisation eigenvectors, back-transformation; the
-// same outputs and tail as launch_eig for l <= 128 (a.W and a.Vs required:
-// they also serve as scratch); declines (*a.decline = 1, nothing written) on
-// eigenvalue clusters and non-finite G.
+// Tridiagonal eigensolver (k_eigtri.hip): Householder reduction in one
+// workgroup, then one wave per eigenvalue (multisection, twisted-
+// factorisation eigenvector, back-transformation); the same outputs and tail
+// as launch_eig for l <= kTriMaxL.  a.W, a.Vs, a.decline and a.tri_ws
+// (kTriWsBytes: the tridiagonal, the reflectors, flags) are required.
+// Declines (*a.decline = 1; S, Vs and W then hold no result, the state is
+// untouched) on eigenvalue clusters and zero or non-finite G.
+constexpr int kTriMaxL = 160;
+constexpr size_t kTriWsBytes = 8 * (4 * (size_t)kTriMaxL + 16 + (size_t)kTriMaxL * kTriMaxL);
 hipError_t launch_eigtri(const EigArgs &a, hipStream_t st);
 hipError_t launch_eig1s_batched(const EigArgs *arr, int count, int l, hipStream_t st);
 

@@ -350,6 +350,7 @@ struct RunBufs {
   double *G2 = nullptr, *T2 = nullptr, *W2 = nullptr, *PU = nullptr, *PV = nullptr;  // final step
   double *Sb = nullptr, *Ebp = nullptr;  // check without the surrogate: sigma(M Q), previous sigma(M Q)^2
   SolverState *state = nullptr;
+  double *tri_ws = nullptr;  // tridiagonal eigensolver workspace
   double *tr_alpha = nullptr, *tr_ratio = nullptr, *tr_s = nullptr;
   int32_t *tr_sweeps = nullptr;
   double *sched = nullptr;
@@ -399,7 +400,7 @@ dashsvd_status dashsvd_set_options(dashsvd_handle *h, const dashsvd_options *opt
   if (o.precision < 0 || o.precision > 2) return fail(h, DASHSVD_ERR_INVALID_ARG, "precision");
   if (o.shift_policy < 0 || o.shift_policy > 4) return fail(h, DASHSVD_ERR_INVALID_ARG, "shift_policy");
   if (o.pve_mode < 0 || o.pve_mode > 2) return fail(h, DASHSVD_ERR_INVALID_ARG, "pve_mode");
-  if (o.eig_method < 0 || o.eig_method > 3) return fail(h, DASHSVD_ERR_INVALID_ARG, "eig_method");
+  if (o.eig_method < 0 || o.eig_method > 4) return fail(h, DASHSVD_ERR_INVALID_ARG, "eig_method");
   if (o.reorder < -1 || o.reorder > 1) return fail(h, DASHSVD_ERR_INVALID_ARG, "reorder");
   if (o.lane_vectors > 2) return fail(h, DASHSVD_ERR_INVALID_ARG, "lane_vectors (1 or 2; <= 0: tuned or 1)");
   if (o.p_max < 0) o.p_max = kDefaultPmax;
@@ -643,6 +644,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   b.Sb = (double *)ar.take(8 * (size_t)l);
   b.Ebp = (double *)ar.take(8 * (size_t)l);
   b.state = (SolverState *)ar.take(sizeof(SolverState));
+  b.tri_ws = (double *)ar.take(kTriWsBytes);
   b.tr_alpha = (double *)ar.take(8 * (size_t)cap);
   b.tr_ratio = (double *)ar.take(8 * (size_t)cap);
   b.tr_s = (double *)ar.take(8 * (size_t)cap * l);
@@ -811,27 +813,33 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   const double t_setup = now_ms();  // host time: the setup kernels may still run
 
   // ---------------------------------------------------------------- eigSVD pieces
-  // Sketch and pass blocks: Cholesky-QR with eigenvalues (Jacobi where it
-  // declines), or Jacobi throughout.  Cholesky-QR keeps the span but not
-  // the principal (Ritz) basis, and the next block C = A Q of a
-  // non-principal Q has nearly collinear columns whose FP32 storage loses
-  // the small directions by about eps kappa(C).  The last two blocks before
-  // the final step fix the accuracy of its products, so they are always
-  // Jacobi: AUTO switches to Jacobi after the first pass whose PVE ratio is
-  // within kCqSwitch x tol (set on the device by the pass tail), and for
-  // the blocks of passes p_max - 1 and p_max.
-  const bool cholqr = h->opt.eig_method == DASHSVD_EIG_AUTO;
+  // Sketch and pass blocks: the tridiagonal eigensolver, Cholesky-QR with
+  // eigenvalues, one-sided or two-sided Jacobi (the two-sided kernel where
+  // the others decline).  Cholesky-QR keeps the span but not the principal
+  // (Ritz) basis, and the next block C = A Q of a non-principal Q has nearly
+  // collinear columns whose FP32 storage loses the small directions by about
+  // eps kappa(C).  The last two blocks before the final step fix the
+  // accuracy of its products, so they are always Jacobi: CHOLQR switches to
+  // Jacobi after the first pass whose PVE ratio is within kCqSwitch x tol
+  // (set on the device by the pass tail), and for the blocks of passes
+  // p_max - 1 and p_max.
+  // AUTO: TRIDIAG in the FP32 and BF16 forms, CHOLQR in the FP64 form
+  const int meth = h->opt.eig_method != DASHSVD_EIG_AUTO ? h->opt.eig_method
+                   : prec == DASHSVD_PREC_FP64         ? DASHSVD_EIG_CHOLQR
+                                                       : DASHSVD_EIG_TRIDIAG;
+  const bool cholqr = meth == DASHSVD_EIG_CHOLQR;
   // ONESIDED: one-sided Jacobi on the Cholesky factor (l <= 128), the
   // two-sided kernel where it declines
-  const bool onesided = h->opt.eig_method == DASHSVD_EIG_ONESIDED && l <= 128;
-  // TRIDIAG: the tridiagonal eigensolver (l <= 128), the two-sided kernel
-  // where it declines
-  const bool tridiag = h->opt.eig_method == DASHSVD_EIG_TRIDIAG && l <= 128 && prec != DASHSVD_PREC_FP64;
+  const bool onesided = meth == DASHSVD_EIG_ONESIDED && l <= 128;
+  // TRIDIAG: the tridiagonal eigensolver (l <= kTriMaxL), the two-sided
+  // kernel where it declines
+  const bool tridiag = meth == DASHSVD_EIG_TRIDIAG && l <= kTriMaxL && prec != DASHSVD_PREC_FP64;
   auto eig_solve = [&](const EigArgs &ea, hipStream_t s) -> hipError_t {
     const bool tri = tridiag && ea.Vs && ea.W;
     if (!onesided && !tri) return launch_eig(ea, s);
     EigArgs e1 = ea;
     e1.decline = &b.state->j1_decline;
+    e1.tri_ws = b.tri_ws;
     hipError_t e = tri ? launch_eigtri(e1, s) : launch_eig1s(e1, s);
     if (e != hipSuccess) return e;
     EigArgs e2 = ea;
@@ -2871,13 +2879,14 @@ dashsvd_status dashsvd_k_eig_onesided(int32_t l, const double *G, double *S, dou
 }
 
 dashsvd_status dashsvd_k_eig_tridiag(int32_t l, const double *G, double *S, double *Vs, double *W,
-                                     int32_t *accepted, void *stream) {
+                                     int32_t *accepted, long long *prof, void *stream) {
   dashsvd_handle *h = nullptr;
-  if (l < 1 || l > 128 || !G || !S || !W || !Vs || !accepted)
-    return fail(h, DASHSVD_ERR_INVALID_ARG, "tridiagonal eig arguments (l <= 128, Vs required)");
+  if (l < 1 || l > kTriMaxL || !G || !S || !W || !Vs || !accepted)
+    return fail(h, DASHSVD_ERR_INVALID_ARG, "tridiagonal eig arguments (l <= 160, Vs required)");
   hipStream_t st = (hipStream_t)stream;
-  int32_t *flag = nullptr;
-  HIPCHK(hipMalloc(&flag, sizeof(int32_t)));
+  // the decline flag, then the workspace
+  void *mem = nullptr;
+  HIPCHK(hipMalloc(&mem, 256 + kTriWsBytes));
   EigArgs ea;
   std::memset(&ea, 0, sizeof(ea));
   ea.l = l;
@@ -2885,12 +2894,14 @@ dashsvd_status dashsvd_k_eig_tridiag(int32_t l, const double *G, double *S, doub
   ea.S = S;
   ea.Vs = Vs;
   ea.W = W;
-  ea.decline = flag;
+  ea.decline = (int32_t *)mem;
+  ea.tri_ws = (double *)((char *)mem + 256);
+  ea.prof = prof;
   int32_t declined = 1;
   hipError_t e = launch_eigtri(ea, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(&declined, flag, 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&declined, mem, 4, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  (void)hipFree(flag);
+  (void)hipFree(mem);
   HIPCHK(e);
   *accepted = declined ? 0 : 1;
   return DASHSVD_OK;

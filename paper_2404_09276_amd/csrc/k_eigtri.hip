@@ -1,45 +1,66 @@
 // Eigen-decomposition of the Gram matrix of an eigSVD block (Alg. 3 steps
-// 1-4) through a symmetric tridiagonal form, in one workgroup:
-//   1. Householder reduction G = H T H^T (Golub & Van Loan Sec. 8.3.1); the
-//      reflector vector of step p is kept in row p of the reduced matrix;
-//   2. every eigenvalue of T by multisection on Sturm counts (Sec. 8.4.1):
-//      eight lanes per eigenvalue evaluate eight points a step, and 17 steps
-//      narrow the Gershgorin interval below 2^-53 of its width;
-//   3. every eigenvector of T from its twisted factorisation
+// 1-4) through a symmetric tridiagonal form, in two kernels:
+//   1. k_tri_reduce, one workgroup with G in registers (a TY x 16 thread
+//      grid, cyclic: thread (ty, tx) holds rows ty + TY a and columns
+//      tx + 16 b): Householder reduction G = H T H^T (Golub & Van Loan
+//      Sec. 8.3.1).  Step p: the grid row holding row p forms the reflector
+//      v of x = A(p, p+1:) and publishes it (barrier); every thread forms
+//      its rows' part of A22 v, summed over its grid row by a DPP
+//      reduce-scatter, and of v^T A22 v (barrier); then A22 -= v w^T + w v^T
+//      with u = beta A22 v and w = u - (beta/2)(v^T u) v in registers.  The
+//      reflectors, T (scaled by a power of two) and the Gershgorin interval
+//      go to the workspace;
+//   2. k_tri_vectors, one wave per eigenvalue, four a workgroup: the
+//      eigenvalue by multisection of the Gershgorin interval on Sturm counts
+//      (Sec. 8.4.1; 64 points a step, nine steps narrow the interval below
+//      2^-54 of its width); a check that no other eigenvalue lies within
+//      2^-30 ||T|| of it; its eigenvector from the twisted factorisation
 //      T - lambda I = N_t Delta N_t^T at the twist index t where |gamma_t| is
 //      smallest: z_t = 1 and two recurrences outward (one step of inverse
 //      iteration from e_t; Dhillon and Parlett, Linear Algebra Appl. 387,
-//      2004), normalised;
-//   4. V = H Z, the reflectors applied to Z held in registers (eight lanes a
-//      column, no barrier: the columns are independent).
-// Outputs as the Jacobi kernels: S = sqrt(eig G) descending, W = V diag(1/S)
-// with columns zeroed where S <= S_max sqrt(l eps), Vs = V, and the pass
-// tail (PVE check, shift rule) for a power-pass block.
-//
+//      2004), normalised; then V = H z (the column in registers, the
+//      reflectors staged through LDS for the workgroup, a wave-wide sum a
+//      reflector), written to Vs and, divided by S, to W;
+//   3. the workgroup of step 2 that finishes last: the columns of W where
+//      S <= S_max sqrt(l eps) zeroed, and the pass tail (PVE check, shift
+//      rule) for a power-pass block.
+// S is sqrt(eig G) in descending order, as from the Jacobi kernels.
 // Accuracy is normwise (an eigenvalue to about eps ||G||, an eigenvector to
 // about eps ||G|| / gap), as with the paper's LAPACK eigensolver; the solver
-// uses this kernel for the FP32 and BF16 forms, whose Jacobi threshold is
+// uses these kernels for the FP32 and BF16 forms, whose Jacobi threshold is
 // 2^-23.  Where two eigenvalues lie within 2^-30 ||G|| of each other their
-// vectors would not be orthogonal to that level, and a non-finite G has no
-// decomposition: the call then declines (*decline = 1, nothing written) and
-// the two-sided Jacobi kernel launched after it on the same stream runs.
-// l <= 128 (G in LDS as a square array).  W and Vs serve as scratch for the
-// factorisations of step 3 before they receive the results.
+// vectors would not be orthogonal to that level, and a non-finite or zero G
+// has no usable decomposition: the call then declines (*decline = 1, the
+// solver state untouched) and the two-sided Jacobi kernel launched after it
+// on the same stream runs.  l <= kTriMaxL.
 #include <cstring>
 
 #include "common.h"
+#include "lanes.h"
 #include "pass_tail.h"
 
 namespace dsv {
 
 namespace {
 
-constexpr int kTT = 1024;          // threads
-constexpr int kTWaves = kTT / kWave;
-constexpr int kTMaxL = 128;
-constexpr int kPts = 8;            // evaluation points per eigenvalue and step
-constexpr int kSectSteps = 17;     // 9^17 > 2^53
+constexpr int kVWaves = 4;  // waves (eigenvalues) of a vectors workgroup
+constexpr int kVT = kVWaves * kWave;
+constexpr int kZRows = (kTriMaxL + kWave - 1) / kWave;  // rows of a column a lane holds
+constexpr int kSectPts = kWave;                           // points a multisection step
+constexpr int kSectSteps = 9;                             // 65^9 > 2^54
 constexpr double kPivMin = 0x1.0p-1000;
+
+// workspace: scaled diagonal, off-diagonal and its squares, reflector
+// coefficients (kTriMaxL each), then lo, hi, |T| bound and the exponent,
+// two ints (the status and the arrival count of the vectors kernel), and
+// the reflector rows
+constexpr int kWsTd = 0, kWsTe = kTriMaxL, kWsTe2 = 2 * kTriMaxL, kWsBet = 3 * kTriMaxL, kWsHdr = 4 * kTriMaxL;
+constexpr int kWsFlags = kWsHdr + 8;
+constexpr int kWsRef = kWsHdr + 16;  // reflector rows, l x l
+static_assert(8 * ((size_t)kWsRef + (size_t)kTriMaxL * kTriMaxL) <= kTriWsBytes, "workspace layout");
+constexpr int kRefChunk = 8;                                       // reflector rows an LDS chunk
+constexpr int kRefLoads = (kRefChunk * kTriMaxL + kVT - 1) / kVT;  // loads a thread a chunk
+constexpr int kGo = 0, kDeclined = 1, kSkip = 2;
 
 __device__ __forceinline__ double rcp_nr(double x) {
   double r = __builtin_amdgcn_rcp(x);
@@ -49,42 +70,86 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return fma(r, e, r);
 }
 
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
-  return x;
-}
-
-// sum over the eight lanes of an aligned group
-__device__ __forceinline__ double sum8(double x) {
-  x += __shfl_xor(x, 1, 8);
-  x += __shfl_xor(x, 2, 8);
-  x += __shfl_xor(x, 4, 8);
-  return x;
-}
+__device__ __forceinline__ double guard(double q) { return fabs(q) < kPivMin ? -kPivMin : q; }
 
 // Number of eigenvalues of the tridiagonal (d, off-diagonal squares e2) below
 // x: the negative pivots of the LDL^T factorisation of T - x I, a pivot of
 // magnitude below kPivMin taken as -kPivMin (T is scaled so that its entries
 // are below 1).
 __device__ __forceinline__ int sturm_count(const double *d, const double *e2, int n, double x) {
-  double q = d[0] - x;
-  if (fabs(q) < kPivMin) q = -kPivMin;
+  double q = guard(d[0] - x);
   int c = q < 0.0 ? 1 : 0;
+#pragma unroll 4
   for (int i = 1; i < n; ++i) {
-    q = (d[i] - x) - e2[i - 1] * rcp_nr(q);
-    if (fabs(q) < kPivMin) q = -kPivMin;
+    q = guard((d[i] - x) - e2[i - 1] * rcp_nr(q));
     c += q < 0.0 ? 1 : 0;
   }
   return c;
 }
 
-__device__ __forceinline__ double guard(double q) { return fabs(q) < kPivMin ? -kPivMin : q; }
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, kWave));
+  return x;
+}
+__device__ __forceinline__ double wave_min(double x) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) x = fmin(x, __shfl_xor(x, o, kWave));
+  return x;
+}
 
-__global__ __launch_bounds__(kTT) void k_eigtri(EigArgs a) {
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+// One halving level of a reduce-scatter inside a row of 16 lanes: lanes
+// with bit B of the lane index clear keep the lower half of the N values,
+// the others the upper half, and each adds the half its partner (the DPP
+// permutation CTRL, which flips bit B and no bit already split) sent.
+template <int N, int B, int CTRL>
+__device__ __forceinline__ void rs_level(double *v, int lane) {
+  const bool up = (lane >> B) & 1;
+#pragma unroll
+  for (int i = 0; i < N / 2; ++i) {
+    const double send = up ? v[i] : v[i + N / 2];
+    const double keep = up ? v[i + N / 2] : v[i];
+    v[i] = keep + lanes_dpp<CTRL>(send);
+  }
+}
+
+// Each of the NV values (NV a power of two <= 16) summed over the 16 lanes
+// of a DPP row: lane j of the row ends with the sum of value j >> (4 -
+// log2 NV).  Bits 3, 2, 1, 0 of the lane index are split in that order by
+// the row mirror (lane ^ 15), half mirror (^ 7), ^ 2 and ^ 1, as long as
+// values remain to split, and summed plainly after.
+template <int NV>
+__device__ __forceinline__ double row_reduce_scatter(double (&v)[NV], int lane) {
+  static_assert(NV == 1 || NV == 2 || NV == 4 || NV == 8 || NV == 16, "NV");
+  if constexpr (NV >= 2) rs_level<NV, 3, 0x140>(v, lane); else v[0] += lanes_dpp<0x140>(v[0]);
+  if constexpr (NV >= 4) rs_level<NV / 2, 2, 0x141>(v, lane); else v[0] += lanes_dpp<0x141>(v[0]);
+  if constexpr (NV >= 8) rs_level<NV / 4, 1, 0x4E>(v, lane); else v[0] += lanes_dpp<0x4E>(v[0]);
+  if constexpr (NV >= 16) rs_level<NV / 8, 0, 0xB1>(v, lane); else v[0] += lanes_dpp<0xB1>(v[0]);
+  return v[0];
+}
+
+constexpr int log2c(int n) { return n <= 1 ? 0 : 1 + log2c(n / 2); }
+constexpr int pow2ceil(int n) { return n <= 1 ? 1 : 2 * pow2ceil((n + 1) / 2); }
+
+// Householder reduction by a TY x 16 thread grid: thread (ty, tx) holds
+// rows ty + TY a (a < RR) and columns tx + 16 b (b < RC) of G, so that
+// the 16 threads of a row of the grid are one DPP row of lanes.
+template <int TY, int RR, int RC>
+__global__ __launch_bounds__(TY * 16) void k_tri_reduce(EigArgs a) {
+  constexpr int TX = 16;
+  constexpr int NT = TY * TX, NWv = NT / kWave, TYW = kWave / TX;  // rows of the grid a wave holds
+  constexpr int NV = pow2ceil(RR), SPL = log2c(NV);
+  const int tid = threadIdx.x, lane = tid & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);  // scalar: uniform branches
+  const int ty = tid / TX, tx = tid % TX;
+  const int ty_top = (wave + 1) * TYW - 1;  // largest grid row of this wave
+  double *ws = a.tri_ws;
+  int32_t *flags = reinterpret_cast<int32_t *>(ws + kWsFlags);
   if ((a.run_if && *a.run_if == 0) || (a.skip_if && *a.skip_if)) {
-    if (tid == 0 && a.decline) *a.decline = 0;
+    if (tid == 0) {
+      flags[0] = kSkip;
+      *a.decline = 0;
+    }
     return;
   }
   SolverState *state = a.state;
@@ -94,313 +159,465 @@ __global__ __launch_bounds__(kTT) void k_eigtri(EigArgs a) {
     __syncthreads();
     if (tid == 0) state->skip_rescale = stopped;
     if (stopped) {
-      if (tid == 0 && a.decline) *a.decline = 0;
+      if (tid == 0) {
+        flags[0] = kSkip;
+        *a.decline = 0;
+      }
       return;
     }
   }
+  const long long t0 = a.prof ? (long long)clock64() : 0;
   const int l = a.l;
-  extern __shared__ double A[];  // l x l, row-major
-  __shared__ double vv[kTMaxL], uu[kTMaxL], dd[kTMaxL], ee[kTMaxL], bet[kTMaxL];
-  __shared__ double td[kTMaxL], te[kTMaxL], te2[kTMaxL], lam[kTMaxL], znrm[kTMaxL];
-  __shared__ double Ssh[kTMaxL];
-  __shared__ int twist[kTMaxL];
-  __shared__ double part[2][kTWaves];
-  __shared__ int s_bad;
-  int pc = 0;  // partial-sum buffer in use (double-buffered: one barrier a sum)
-  auto block_sum = [&](double x) __attribute__((always_inline)) -> double {
-    x = wave_sum(x);
-    if (lane == 0) part[pc][wave] = x;
-    __syncthreads();
-    double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < kTWaves; ++w) s += part[pc][w];
-    pc ^= 1;
-    return s;
-  };
+  constexpr int LR = TY * RR, LC = TX * RC;  // rows and columns the grid covers
+  static_assert(LR == LC, "square tiles");
+  __shared__ double vb[2][LC];   // reflector of the step (double-buffered by step parity)
+  __shared__ double xrow[LC];    // row p, from its holders
+  __shared__ double ub[LR];      // u = beta A22 v
+  __shared__ double part[NWv];   // partial sums of v^T A22 v
+  __shared__ double sbeta[2];
+  __shared__ double dd[LR], ee[LR];
 
-  if (tid == 0) s_bad = 0;
-  __syncthreads();
-  for (int idx = tid; idx < l * l; idx += kTT) {
-    const double g = a.G[idx];
-    A[idx] = g;
-    if (!(fabs(g) < INFINITY)) s_bad = 1;
-  }
-  __syncthreads();
-  if (s_bad) {
-    if (tid == 0 && a.decline) *a.decline = 1;
+  double A[RR][RC];
+  int bad = 0;
+#pragma unroll
+  for (int i0 = 0; i0 < RR; ++i0)
+#pragma unroll
+    for (int c0 = 0; c0 < RC; ++c0) {
+      const int i = ty + TY * i0, c = tx + TX * c0;
+      const double g = (i < l && c < l) ? a.G[(size_t)i * l + c] : 0.0;
+      if (!(fabs(g) < INFINITY)) bad = 1;
+      A[i0][c0] = g;
+    }
+  if (__syncthreads_or(bad)) {
+    if (tid == 0) {
+      flags[0] = kDeclined;
+      *a.decline = 1;
+    }
     return;
   }
 
-  // ------------------------------------------------------------ 1. Householder
-  // Step p: x = A(p+1:, p) (read as row p), v = x - alpha e_1, beta = 2 / v^T v,
-  // u = beta A22 v, w = u - (beta/2)(v^T u) v, A22 -= v w^T + w v^T.  v goes to
-  // row p (A(p, p+1:)), beta to bet[p], the diagonal and alpha to dd, ee.
-  const int gseg = tid / 8, qseg = tid % 8;
-  const int ty = tid / 32, tx = tid % 32;
-  for (int p = 0; p + 2 < l; ++p) {
-    const int m = l - 1 - p;
-    double *rowp = A + (size_t)p * l + p + 1;  // x, then v
-    double sq = 0.0;
-    for (int i = 1 + tid; i < m; i += kTT) sq = fma(rowp[i], rowp[i], sq);
-    const double tail = block_sum(sq);
-    const double x0 = rowp[0];
-    if (tail == 0.0) {
-      // already reduced: H = I
-      if (tid == 0) {
-        dd[p] = A[(size_t)p * l + p];
-        ee[p] = x0;
-        bet[p] = 0.0;
-      }
-      continue;
-    }
-    const double nrm = sqrt(fma(x0, x0, tail));
-    const double alpha = x0 >= 0.0 ? -nrm : nrm;
-    const double v0 = x0 - alpha;  // no cancellation: x0 and -alpha share the sign
-    const double beta = 2.0 / fma(v0, v0, tail);
-    for (int i = tid; i < m; i += kTT) vv[i] = i == 0 ? v0 : rowp[i];
-    __syncthreads();
-    if (tid == 0) {
-      dd[p] = A[(size_t)p * l + p];
-      ee[p] = alpha;
-      bet[p] = beta;
-      rowp[0] = v0;
-    }
-    // u = beta A22 v, one row per 8-lane group; v^T u for K
-    double acc = 0.0;
-    for (int ii = gseg; ii < m; ii += kTT / 8) {
-      const double *ar = A + (size_t)(p + 1 + ii) * l + p + 1;
-      double s = 0.0;
-      for (int kk = qseg; kk < m; kk += 8) s = fma(ar[kk], vv[kk], s);
-      s = sum8(s) * beta;
-      if (qseg == 0) {
-        uu[ii] = s;
-        acc = fma(vv[ii], s, acc);
-      }
-    }
-    const double K = 0.5 * beta * block_sum(acc);
-    // A22 -= v w^T + w v^T, w = u - K v; a 32 x 32 thread grid over the block
-    for (int ii = ty; ii < m; ii += kTT / 32) {
-      const double vi = vv[ii], wi = fma(-K, vi, uu[ii]);
-      double *ar = A + (size_t)(p + 1 + ii) * l + p + 1;
-      for (int kk = tx; kk < m; kk += 32) {
-        const double vk = vv[kk], wk = fma(-K, vk, uu[kk]);
-        ar[kk] = fma(-vi, wk, fma(-wi, vk, ar[kk]));
-      }
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    if (l >= 2) {
-      dd[l - 2] = A[(size_t)(l - 2) * l + l - 2];
-      dd[l - 1] = A[(size_t)(l - 1) * l + l - 1];
-      ee[l - 2] = A[(size_t)(l - 1) * l + l - 2];
-      bet[l - 2] = 0.0;
-    } else {
-      dd[0] = A[0];
-    }
-    if (l >= 1) bet[l - 1] = 0.0;
-  }
-  __syncthreads();
-
-  // ------------------------------------------------------------ 2. eigenvalues
-  // T scaled by a power of two so that its largest entry lies in [1/2, 1)
-  double mx = 0.0;
-  for (int i = 0; i < l; ++i) mx = fmax(mx, fabs(dd[i]));
-  for (int i = 0; i + 1 < l; ++i) mx = fmax(mx, fabs(ee[i]));
-  int ex = 0;
-  if (mx > 0.0) (void)frexp(mx, &ex);
-  for (int i = tid; i < l; i += kTT) {
-    td[i] = ldexp(dd[i], -ex);
-    if (i + 1 < l) {
-      te[i] = ldexp(ee[i], -ex);
-      te2[i] = te[i] * te[i];
-    }
-  }
-  __syncthreads();
-  {
-    double lo = INFINITY, hi = -INFINITY;
-    for (int i = 0; i < l; ++i) {
-      const double r = (i > 0 ? fabs(te[i - 1]) : 0.0) + (i + 1 < l ? fabs(te[i]) : 0.0);
-      lo = fmin(lo, td[i] - r);
-      hi = fmax(hi, td[i] + r);
-    }
-    const double wid = fmax(fmax(fabs(lo), fabs(hi)), 0x1.0p-900);
-    lo -= 0x1.0p-40 * wid;
-    hi += 0x1.0p-40 * wid;
-    // eigenvalue r (ascending) by the kPts lanes of group r: each step
-    // evaluates the count at kPts interior points of [lo_r, hi_r) and keeps
-    // the piece where it passes r; count(lo_r) <= r < count(hi_r)
-    const int r = tid / kPts, qq = tid % kPts;
-    if (r < l) {
-      double lo_r = lo, hi_r = hi;
-      for (int it = 0; it < kSectSteps; ++it) {
-        const double x = lo_r + (hi_r - lo_r) * ((double)(qq + 1) / (double)(kPts + 1));
-        const int c = sturm_count(td, te2, l, x);
-        double nhi = hi_r, nlo = lo_r;
-        bool found = false;
+  // Step p = k TY + j: row p is row k of the tiles of grid row j.  The loop
+  // over k is unrolled, so that the register row is known to the compiler.
 #pragma unroll
-        for (int z = 0; z < kPts; ++z) {
-          const int cz = __shfl(c, z, kPts);
-          const double xz = __shfl(x, z, kPts);
-          if (!found && cz > r) {
-            nhi = xz;
-            found = true;
+  for (int k = 0; k < RR; ++k) {
+    for (int j = 0; j < TY; ++j) {
+      const int p = k * TY + j;
+      if (p + 2 >= l) break;
+      const int buf = p & 1;
+      if (wave == j / TYW) {
+        // grid row j (one DPP row of this wave) forms the reflector of
+        // x = A(p, p+1:); the whole wave runs the cross-lane sum
+        double sq = 0.0;
+        if (ty == j) {
+#pragma unroll
+          for (int c0 = 0; c0 < RC; ++c0) {
+            const int c = tx + TX * c0;
+            xrow[c] = A[k][c0];
+            if (c > p + 1) sq = fma(A[k][c0], A[k][c0], sq);
           }
         }
-#pragma unroll
-        for (int z = 0; z < kPts; ++z) {
-          const int cz = __shfl(c, z, kPts);
-          const double xz = __shfl(x, z, kPts);
-          if (cz <= r && xz < nhi) nlo = xz;
+        lanes_wave_sync();
+        double sv[1] = {sq};
+        sq = row_reduce_scatter<1>(sv, lane);
+        const double x0 = xrow[p + 1], app = xrow[p];
+        double alpha = x0, v0 = 0.0, beta = 0.0;
+        if (sq > 0.0) {
+          const double nrm = sqrt(fma(x0, x0, sq));
+          alpha = x0 >= 0.0 ? -nrm : nrm;
+          v0 = x0 - alpha;  // no cancellation: x0 and -alpha share the sign
+          beta = 2.0 / fma(v0, v0, sq);
         }
-        lo_r = nlo;
-        hi_r = nhi;
+        if (ty == j) {
+#pragma unroll
+          for (int c0 = 0; c0 < RC; ++c0) {
+            const int c = tx + TX * c0;
+            const double v = beta == 0.0 ? 0.0 : (c == p + 1 ? v0 : (c > p + 1 ? A[k][c0] : 0.0));
+            vb[buf][c] = v;
+            if (c < l) ws[kWsRef + (size_t)p * l + c] = v;
+          }
+          if (tx == 0) {
+            dd[p] = app;
+            ee[p] = alpha;
+            sbeta[buf] = beta;
+            ws[kWsBet + p] = beta;
+          }
+        }
       }
-      if (qq == 0) lam[r] = 0.5 * (lo_r + hi_r);
+      __syncthreads();
+      const double beta = sbeta[buf];
+      if (beta == 0.0) continue;  // H = I (uniform)
+      // rows of tiles wholly at or above row p take no part (a scalar test
+      // per row of tiles; columns at or left of p have v = u = 0)
+      double vr[RR], vc[RC], t[NV];
+#pragma unroll
+      for (int i0 = 0; i0 < RR; ++i0) vr[i0] = vb[buf][ty + TY * i0];
+#pragma unroll
+      for (int c0 = 0; c0 < RC; ++c0) vc[c0] = vb[buf][tx + TX * c0];
+      double kp = 0.0;
+#pragma unroll
+      for (int i0 = 0; i0 < NV; ++i0) {
+        double s = 0.0;
+        if (i0 < RR && TY * i0 + ty_top > p) {
+#pragma unroll
+          for (int c0 = 0; c0 < RC; ++c0) s = fma(A[i0 < RR ? i0 : 0][c0], vc[c0], s);
+          kp = fma(vr[i0 < RR ? i0 : 0], s, kp);
+        }
+        t[i0] = s;
+      }
+      // u for row ty + TY (tx >> (4 - SPL)), held by every lane whose low
+      // 4 - SPL bits are zero
+      const double us = row_reduce_scatter<NV>(t, lane);
+      {
+        const int ai = tx >> (4 - SPL);
+        const int i = ty + TY * ai;
+        if ((tx & ((1 << (4 - SPL)) - 1)) == 0 && ai < RR) ub[i] = i > p ? beta * us : 0.0;
+      }
+      kp = lanes_wave_sum(kp);
+      if (lane == 0) part[wave] = kp;
+      __syncthreads();
+      double ksum = 0.0;
+#pragma unroll
+      for (int w = 0; w < NWv; ++w) ksum += part[w];
+      // K = (beta / 2) v^T u with u = beta A22 v
+      const double K = 0.5 * beta * beta * ksum;
+      double wc[RC];
+#pragma unroll
+      for (int c0 = 0; c0 < RC; ++c0) wc[c0] = fma(-K, vc[c0], ub[tx + TX * c0]);
+#pragma unroll
+      for (int i0 = 0; i0 < RR; ++i0) {
+        if (TY * i0 + ty_top > p) {
+          const double wr = fma(-K, vr[i0], ub[ty + TY * i0]);
+#pragma unroll
+          for (int c0 = 0; c0 < RC; ++c0) A[i0][c0] = fma(-vr[i0], wc[c0], fma(-wr, vc[c0], A[i0][c0]));
+        }
+      }
     }
   }
+  // the last 2 x 2 block (1 x 1 for l = 1)
+#pragma unroll
+  for (int i0 = 0; i0 < RR; ++i0)
+#pragma unroll
+    for (int c0 = 0; c0 < RC; ++c0) {
+      const int i = ty + TY * i0, c = tx + TX * c0;
+      if (i < l && i >= l - 2 && c == i) dd[i] = A[i0][c0];
+      if (l >= 2 && i == l - 1 && c == l - 2) ee[l - 2] = A[i0][c0];
+    }
   __syncthreads();
-  // clusters: eigenvalues within 2^-30 of the largest magnitude of each other
-  {
-    const double big = fmax(fabs(lam[0]), fabs(lam[l - 1]));
-    for (int r = tid; r + 1 < l; r += kTT)
-      if (!(lam[r + 1] - lam[r] > 0x1.0p-30 * big)) s_bad = 1;
+  if (a.prof && tid == 0) a.prof[0] = (long long)clock64() - t0;
+  if (wave != 0) return;
+  // T scaled by a power of two so that its largest entry lies in [1/2, 1),
+  // and the Gershgorin interval of the scaled T
+  double mx = 0.0;
+  for (int i = lane; i < l; i += kWave) {
+    mx = fmax(mx, fabs(dd[i]));
+    if (i + 1 < l) mx = fmax(mx, fabs(ee[i]));
   }
-  __syncthreads();
-  if (s_bad) {
-    if (tid == 0 && a.decline) *a.decline = 1;
-    return;
+  mx = wave_max(mx);
+  const bool ok = mx > 0.0 && mx < INFINITY;
+  int ex = 0;
+  if (ok) (void)frexp(mx, &ex);
+  double lo = INFINITY, hi = -INFINITY;
+  for (int i = lane; i < l; i += kWave) {
+    const double di = ldexp(dd[i], -ex);
+    const double em = i > 0 ? ldexp(ee[i - 1], -ex) : 0.0;
+    const double ep = i + 1 < l ? ldexp(ee[i], -ex) : 0.0;
+    ws[kWsTd + i] = di;
+    if (i + 1 < l) {
+      ws[kWsTe + i] = ep;
+      ws[kWsTe2 + i] = ep * ep;
+    }
+    const double rad = fabs(em) + fabs(ep);
+    lo = fmin(lo, di - rad);
+    hi = fmax(hi, di + rad);
   }
-  if (tid == 0 && a.decline) *a.decline = 0;
+  lo = wave_min(lo);
+  hi = wave_max(hi);
+  if (lane == 0) {
+    const double big = fmax(fabs(lo), fabs(hi));
+    // widened by 2^-40 of its magnitude, well above the rounding of the counts
+    ws[kWsHdr + 0] = lo - 0x1.0p-40 * big;
+    ws[kWsHdr + 1] = hi + 0x1.0p-40 * big;
+    ws[kWsHdr + 2] = big;
+    ws[kWsHdr + 3] = (double)ex;
+    flags[1] = 0;  // arrivals of the vectors kernel
+    flags[0] = ok ? kGo : kDeclined;
+    *a.decline = ok ? 0 : 1;
+  }
+}
 
-  // ------------------------------------------------------------ 3. eigenvectors of T
-  // lane r: D- backward into Wk, D+ forward into Vk with gamma_i = D+_i +
-  // D-_i - (d_i - lambda), then z outward from the twist t, written over the
-  // factor it consumed (rows < t in Vk, rows > t in Wk; z_t = 1 implied).
-  double *Wk = a.W, *Vk = a.Vs;
-  if (tid < l) {
-    const int r = tid;
-    const double lm = lam[r];
-    double q = guard(td[l - 1] - lm);
-    Wk[(size_t)(l - 1) * l + r] = q;
-    for (int i = l - 2; i >= 0; --i) {
-      q = guard((td[i] - lm) - te2[i] * rcp_nr(q));
-      Wk[(size_t)i * l + r] = q;
+__global__ __launch_bounds__(kVT) void k_tri_vectors(EigArgs a) {
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  const double *ws = a.tri_ws;
+  int32_t *flags = reinterpret_cast<int32_t *>(a.tri_ws + kWsFlags);
+  if (flags[0] != kGo) return;  // declined or skipped by the reduction
+  const int l = a.l;
+  __shared__ double td[kTriMaxL], te[kTriMaxL], te2[kTriMaxL], bet[kTriMaxL];
+  __shared__ double dp[kVWaves][kTriMaxL], dm[kVWaves][kTriMaxL], zz[kVWaves][kTriMaxL];
+  __shared__ double refl[2][kRefChunk][kTriMaxL];  // reflector rows, double-buffered chunks
+  for (int i = tid; i < l; i += kVT) {
+    td[i] = ws[kWsTd + i];
+    bet[i] = i + 2 < l ? ws[kWsBet + i] : 0.0;
+    te[i] = i + 1 < l ? ws[kWsTe + i] : 0.0;
+    te2[i] = i + 1 < l ? ws[kWsTe2 + i] : 0.0;
+  }
+  const double lo = ws[kWsHdr + 0], hi = ws[kWsHdr + 1], big = ws[kWsHdr + 2];
+  const int ex = (int)ws[kWsHdr + 3];
+  __syncthreads();
+
+  const int r = blockIdx.x * kVWaves + wv;  // eigenvalue (ascending) of this wave
+  // optional phase profile: cycles of wave 0 of workgroup 0
+  const bool stamp = a.prof && blockIdx.x == 0 && tid == 0;
+  long long ts = stamp ? (long long)clock64() : 0;
+  auto mark = [&](int slot) {
+    if (stamp) {
+      const long long now = (long long)clock64();
+      a.prof[slot] = now - ts;
+      ts = now;
     }
-    double dp = guard(td[0] - lm);
-    Vk[r] = dp;
-    double best = fabs(Wk[r]);  // gamma_0 = D-_0
+  };
+  bool act = false;  // this wave has an isolated eigenvalue and its z (wave-uniform)
+  double lam = 0.0;
+  double zr[kZRows];
+#pragma unroll
+  for (int s = 0; s < kZRows; ++s) zr[s] = 0.0;
+  if (r < l) {
+    // multisection: count(lo_r) <= r < count(hi_r); lane z evaluates point
+    // z + 1 of 65, the new interval is between the last point whose count
+    // is <= r below the first point whose count passes r
+    constexpr double kStep = 1.0 / (double)(kSectPts + 1);
+    double lo_r = lo, hi_r = hi;
+    for (int it = 0; it < kSectSteps; ++it) {
+      const double w = hi_r - lo_r;
+      const double x = fma(w, (double)(lane + 1) * kStep, lo_r);
+      const int c = sturm_count(td, te2, l, x);
+      const unsigned long long above = __ballot(c > r);
+      const int first = above ? __builtin_ctzll(above) : kWave;
+      const unsigned long long low = first >= kWave ? ~0ull : ((1ull << first) - 1ull);
+      const unsigned long long below = __ballot(c <= r) & low;
+      const int lastb = below ? 63 - __builtin_clzll(below) : -1;
+      const double nhi = first < kWave ? fma(w, (double)(first + 1) * kStep, lo_r) : hi_r;
+      const double nlo = lastb >= 0 ? fma(w, (double)(lastb + 1) * kStep, lo_r) : lo_r;
+      lo_r = nlo;
+      hi_r = nhi;
+    }
+    lam = 0.5 * (lo_r + hi_r);
+    mark(1);
+    // isolation: exactly r eigenvalues below lam - d and r + 1 below lam + d
+    const double dl = 0x1.0p-30 * big;
+    const int cc = sturm_count(td, te2, l, (lane & 1) ? lam + dl : lam - dl);
+    bool iso = __shfl(cc, 0, kWave) == r && __shfl(cc, 1, kWave) == r + 1;
+    mark(2);
+    double *dpw = dp[wv], *dmw = dm[wv], *zw = zz[wv];
     int t = 0;
-    // (unrolled so that the loads of D- are issued ahead of the D+ chain)
-#pragma unroll 4
-    for (int i = 1; i < l; ++i) {
-      dp = guard((td[i] - lm) - te2[i - 1] * rcp_nr(dp));
-      Vk[(size_t)i * l + r] = dp;
-      const double gm = fabs(dp + Wk[(size_t)i * l + r] - (td[i] - lm));
-      if (gm < best) {
-        best = gm;
-        t = i;
+    if (iso) {
+      // D+ forward (lane 0) and D- backward (lane 1)
+      if (lane < 2) {
+        const bool fw = lane == 0;
+        double *dst = fw ? dpw : dmw;
+        int i = fw ? 0 : l - 1;
+        double q = guard(td[i] - lam);
+        dst[i] = q;
+        for (int k = 1; k < l; ++k) {
+          i = fw ? k : l - 1 - k;
+          const double e2 = te2[fw ? i - 1 : i];
+          q = guard((td[i] - lam) - e2 * rcp_nr(q));
+          dst[i] = q;
+        }
+      }
+      lanes_wave_sync();
+      // twist: the smallest |gamma_i|, gamma_i = D+_i + D-_i - (d_i - lambda)
+      double best = INFINITY;
+      t = 0x7fffffff;
+#pragma unroll
+      for (int s = 0; s < kZRows; ++s) {
+        const int i = lane + kWave * s;
+        if (i < l) {
+          const double g = fabs(dpw[i] + dmw[i] - (td[i] - lam));
+          if (g < best) {
+            best = g;
+            t = i;
+          }
+        }
+      }
+#pragma unroll
+      for (int o = kWave / 2; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, kWave);
+        const int ot = __shfl_xor(t, o, kWave);
+        if (ob < best || (ob == best && ot < t)) {
+          best = ob;
+          t = ot;
+        }
+      }
+      iso = t < l;
+    }
+    if (iso) {
+      // z_t = 1, then z_i = -(e_i / D+_i) z_(i+1) below t (lane 0) and
+      // z_i = -(e_(i-1) / D-_i) z_(i-1) above t (lane 1)
+      if (lane < 2) {
+        const bool dn = lane == 0;
+        const int cnt = dn ? t : l - 1 - t;
+        double z = 1.0;
+        if (dn) zw[t] = 1.0;
+        for (int k = 1; k <= cnt; ++k) {
+          const int i = dn ? t - k : t + k;
+          const double num = te[dn ? i : i - 1];
+          const double den = dn ? dpw[i] : dmw[i];
+          z = -(num * rcp_nr(den)) * z;
+          zw[i] = z;
+        }
+      }
+      lanes_wave_sync();
+      double nz = 0.0;
+#pragma unroll
+      for (int s = 0; s < kZRows; ++s) {
+        const int i = lane + kWave * s;
+        zr[s] = i < l ? zw[i] : 0.0;
+        nz = fma(zr[s], zr[s], nz);
+      }
+      nz = lanes_wave_sum(nz);
+      const double inv = 1.0 / sqrt(nz);
+#pragma unroll
+      for (int s = 0; s < kZRows; ++s) zr[s] *= inv;
+      act = true;
+      mark(3);
+    } else if (lane == 0) {
+      __hip_atomic_store(a.decline, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+
+  // V = H_0 H_1 ... H_(l-3) z.  The reflector rows (zero at and left of the
+  // diagonal, all zero where beta_p = 0) pass through LDS in chunks of
+  // kRefChunk rows, p descending, loaded by the whole workgroup one chunk
+  // ahead; every wave takes part in the loads and barriers.
+  {
+    const double *Rf = ws + kWsRef;
+    const int np = l > 2 ? l - 2 : 0;  // reflectors 0 .. l-3
+    const int nch = (np + kRefChunk - 1) / kRefChunk;
+    const int per = kRefChunk * l;  // doubles a chunk
+    int es[kRefLoads], ei[kRefLoads];  // (row of the chunk, column) of this thread's loads
+#pragma unroll
+    for (int q = 0; q < kRefLoads; ++q) {
+      const int e = tid + kVT * q;
+      es[q] = e < per ? e / l : kRefChunk;
+      ei[q] = e < per ? e - es[q] * l : 0;
+    }
+    double reg[kRefLoads];
+    auto chunk_load = [&](int c) {
+#pragma unroll
+      for (int q = 0; q < kRefLoads; ++q) {
+        const int p = l - 3 - kRefChunk * c - es[q];
+        reg[q] = (es[q] < kRefChunk && p >= 0) ? Rf[(size_t)p * l + ei[q]] : 0.0;
+      }
+    };
+    auto chunk_store = [&](int b) {
+#pragma unroll
+      for (int q = 0; q < kRefLoads; ++q)
+        if (es[q] < kRefChunk) refl[b][es[q]][ei[q]] = reg[q];
+    };
+    if (nch > 0) {
+      chunk_load(0);
+      chunk_store(0);
+    }
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+      if (c + 1 < nch) chunk_load(c + 1);
+      if (act) {
+        const int rows = min(kRefChunk, np - kRefChunk * c);
+#pragma unroll
+        for (int s = 0; s < kRefChunk; ++s) {
+          if (s < rows) {
+            const int p = l - 3 - kRefChunk * c - s;
+            const double *vp = refl[c & 1][s];
+            double vv[kZRows];
+            double sum = 0.0;
+#pragma unroll
+            for (int k = 0; k < kZRows; ++k) {
+              const int i = lane + kWave * k;
+              vv[k] = i < l ? vp[i] : 0.0;
+              sum = fma(vv[k], zr[k], sum);
+            }
+            sum = lanes_wave_sum(sum) * bet[p];
+#pragma unroll
+            for (int k = 0; k < kZRows; ++k) zr[k] = fma(-vv[k], sum, zr[k]);
+          }
+        }
+      }
+      if (c + 1 < nch) chunk_store((c + 1) & 1);
+      __syncthreads();
+    }
+  }
+  if (act) {
+    mark(4);
+    const int rk = l - 1 - r;
+    const double sv = sqrt(fmax(ldexp(lam, ex), 0.0));
+    const double iv = 1.0 / sv;  // columns with S <= S_max sqrt(l eps) are zeroed below
+#pragma unroll
+    for (int s = 0; s < kZRows; ++s) {
+      const int i = lane + kWave * s;
+      if (i < l) {
+        a.Vs[(size_t)i * l + rk] = zr[s];
+        a.W[(size_t)i * l + rk] = zr[s] * iv;
       }
     }
-    double nz = 1.0, z = 1.0;
-#pragma unroll 4
-    for (int i = t - 1; i >= 0; --i) {
-      z = -(te[i] * rcp_nr(Vk[(size_t)i * l + r])) * z;
-      Vk[(size_t)i * l + r] = z;
-      nz = fma(z, z, nz);
-    }
-    z = 1.0;
-#pragma unroll 4
-    for (int i = t + 1; i < l; ++i) {
-      z = -(te[i - 1] * rcp_nr(Wk[(size_t)i * l + r])) * z;
-      Wk[(size_t)i * l + r] = z;
-      nz = fma(z, z, nz);
-    }
-    twist[r] = t;
-    znrm[r] = sqrt(nz);
+    if (lane == 0) a.S[rk] = sv;
   }
+
+  // ------------------------------------------------------------ the last workgroup
+  __threadfence();
   __syncthreads();
-
-  // ------------------------------------------------------------ 4. V = H Z
-  // column j over the 8 lanes of group j: lane g holds rows g + 8 s
-  constexpr int kRows = kTMaxL / 8;
-  const int j = tid / 8, g8 = tid % 8;
-  double vcol[kRows];
-  const bool colj = j < l;
-  {
-    const int tj = colj ? twist[j] : 0;
-    const double inv = colj ? 1.0 / znrm[j] : 0.0;
-#pragma unroll
-    for (int s = 0; s < kRows; ++s) {
-      const int i = g8 + 8 * s;
-      double z = 0.0;
-      if (colj && i < l) z = i == tj ? 1.0 : (i < tj ? Vk[(size_t)i * l + j] : Wk[(size_t)i * l + j]);
-      vcol[s] = z * inv;
-    }
-  }
-  __syncthreads();  // every column is in registers before W and Vs are written
-  for (int p = l - 3; p >= 0; --p) {
-    const double b = bet[p];
-    if (b == 0.0) continue;  // uniform
-    const double *vp = A + (size_t)p * l;  // v_p(i) = A(p, i), i > p
-    double s = 0.0;
-#pragma unroll
-    for (int s_ = 0; s_ < kRows; ++s_) {
-      const int i = g8 + 8 * s_;
-      if (i > p && i < l) s = fma(vp[i], vcol[s_], s);
-    }
-    const double w = sum8(s) * b;
-#pragma unroll
-    for (int s_ = 0; s_ < kRows; ++s_) {
-      const int i = g8 + 8 * s_;
-      if (i > p && i < l) vcol[s_] = fma(-vp[i], w, vcol[s_]);
-    }
-  }
-
-  // ------------------------------------------------------------ tail
-  // eigenvalue j (ascending) has rank l - 1 - j in the descending order
-  for (int r = tid; r < l; r += kTT) Ssh[l - 1 - r] = sqrt(fmax(ldexp(lam[r], ex), 0.0));
+  __shared__ int s_last;
+  if (tid == 0) s_last = atomicAdd(&flags[1], 1) == (int)gridDim.x - 1;
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  const long long tt = a.prof ? (long long)clock64() : 0;
+  if (tid == 0) flags[1] = 0;
+  if (__hip_atomic_load(a.decline, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  __shared__ double Ssh[kTriMaxL];
+  for (int i = tid; i < l; i += kVT) Ssh[i] = a.S[i];
   __syncthreads();
   const double tau = Ssh[0] * sqrt((double)l * 2.220446049250313e-16);
-  for (int i = tid; i < l; i += kTT) a.S[i] = Ssh[i];
-  if (colj) {
-    const int rk = l - 1 - j;
-    const double sv = Ssh[rk];
-    const double iv = sv > tau ? 1.0 / sv : 0.0;
-#pragma unroll
-    for (int s_ = 0; s_ < kRows; ++s_) {
-      const int i = g8 + 8 * s_;
-      if (i < l) {
-        a.W[(size_t)i * l + rk] = vcol[s_] * iv;
-        a.Vs[(size_t)i * l + rk] = vcol[s_];
-      }
-    }
-  }
+  for (int c = wv; c < l; c += kVWaves)
+    if (!(Ssh[c] > tau))
+      for (int i = lane; i < l; i += kWave) a.W[(size_t)i * l + c] = 0.0;
   if (a.sweeps && tid == 0) *a.sweeps = 0;
+  if (a.prof && tid == 0) a.prof[5] = (long long)clock64() - tt;
+  SolverState *state = a.state;
   if (!state) return;
   if (tid == 0) {
     if (a.trace_sweeps && state->eig_calls < a.trace_cap + 2) a.trace_sweeps[state->eig_calls] = 0;
     state->eig_calls += 1;
+    if (!(Ssh[l - 1] > tau)) state->deficient = 1;
   }
-  if (tid == 0 && !(Ssh[l - 1] > tau)) state->deficient = 1;
   if (a.mode != 2) return;
   __syncthreads();
   pass_tail(a, state, Ssh);
 }
 
+template <int TY, int RR, int RC>
+hipError_t launch_reduce(const EigArgs &a, hipStream_t st) {
+  hipLaunchKernelGGL((k_tri_reduce<TY, RR, RC>), dim3(1), dim3(TY * 16), 0, st, a);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_eigtri(const EigArgs &a, hipStream_t st) {
-  if (a.l < 1 || a.l > kTMaxL || !a.Vs || !a.W || !a.S) return hipErrorInvalidValue;
-  const size_t shm = sizeof(double) * (size_t)a.l * (size_t)a.l;
-  static size_t shm_set = 64 * 1024;
-  if (shm > shm_set) {
-    const hipError_t e =
-        hipFuncSetAttribute((const void *)k_eigtri, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-    shm_set = shm;
-  }
-  hipLaunchKernelGGL(k_eigtri, dim3(1), dim3(kTT), shm, st, a);
+  if (a.l < 1 || a.l > kTriMaxL || !a.Vs || !a.W || !a.S || !a.decline || !a.tri_ws) return hipErrorInvalidValue;
+  // one wave a SIMD up to l = 128 (tiles of up to 8 x 8 a thread), two above
+  hipError_t e;
+  if (a.l <= 32)
+    e = launch_reduce<16, 2, 2>(a, st);
+  else if (a.l <= 64)
+    e = launch_reduce<16, 4, 4>(a, st);
+  else if (a.l <= 96)
+    e = launch_reduce<16, 6, 6>(a, st);
+  else if (a.l <= 128)
+    e = launch_reduce<16, 8, 8>(a, st);
+  else
+    e = launch_reduce<32, 5, 10>(a, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tri_vectors, dim3((a.l + kVWaves - 1) / kVWaves), dim3(kVT), 0, st, a);
   return hipGetLastError();
 }
 

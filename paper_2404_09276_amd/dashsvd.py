@@ -23,7 +23,7 @@ F32, F64, BF16 = 0, 1, 2
 PREC = {"fp32": 0, "fp64": 1, "bf16": 2}
 SHIFT = {"paper": 0, "none": 1, "fixed": 2, "schedule": 3, "learned": 4}
 PVE = {"r2": 0, "r1": 1, "nosurr": 2}
-EIG = {"auto": 0, "jacobi": 1, "onesided": 2, "tridiag": 3}
+EIG = {"auto": 0, "jacobi": 1, "onesided": 2, "tridiag": 3, "cholqr": 4}
 # timing: False / True (every kernel group) / "spmm" (the two SpMM groups only)
 TIMING = {False: 0, True: 1, "spmm": 2}
 # reorder: "auto" (from 2^22 nonzeros), True, False
@@ -147,7 +147,7 @@ def lib():
         L.dashsvd_k_eig.argtypes = [i32, P, P, P, P, P, P]
         L.dashsvd_k_eig_prof.argtypes = [i32, P, P, P, P, P, P, P]
         L.dashsvd_k_eig_onesided.argtypes = [i32, P, P, P, P, f64, P, P, P, P]
-        L.dashsvd_k_eig_tridiag.argtypes = [i32, P, P, P, P, P, P]
+        L.dashsvd_k_eig_tridiag.argtypes = [i32, P, P, P, P, P, P, P]
         L.dashsvd_k_rescale.argtypes = [i64, i32, P, i64, i32, P, i64, i32, P, i64, i32, P]
         for name in EXPORTS:
             if name not in ("dashsvd_destroy", "dashsvd_status_string", "dashsvd_last_error"):
@@ -586,12 +586,14 @@ def k_eig_onesided(G, S, Vs, W, skip=2.0**-53, sweeps=None, prof=None, stream=No
     return bool(acc.value)
 
 
-def k_eig_tridiag(G, S, Vs, W, stream=None) -> bool:
-    """The tridiagonal eigensolver (l <= 128); True if G was accepted (no
-    eigenvalue cluster, finite entries), else nothing is written."""
+def k_eig_tridiag(G, S, Vs, W, prof=None, stream=None) -> bool:
+    """The tridiagonal eigensolver (l <= 160); True if G was accepted (no
+    eigenvalue cluster, nonzero finite entries), else S, Vs and W hold no
+    result.  prof: optional device int64 tensor of 6 phase cycle counts."""
     l = G.shape[0]
     acc = C.c_int32(0)
-    _check(lib().dashsvd_k_eig_tridiag(l, _ptr(G), _ptr(S), _ptr(Vs), _ptr(W), C.byref(acc), _stream_ptr(stream)))
+    _check(lib().dashsvd_k_eig_tridiag(l, _ptr(G), _ptr(S), _ptr(Vs), _ptr(W), C.byref(acc),
+                                       _ptr(prof) if prof is not None else None, _stream_ptr(stream)))
     return bool(acc.value)
 
 

@@ -365,26 +365,39 @@ def test_bf16_no_promotion_at_loose_tol(torch_dev):
 @pytest.mark.parametrize("prec,bar", [("fp64", 1e-10), ("fp32", 1e-5)])
 def test_eig_methods_agree(torch_dev, prec, bar):
     """Blocks solved by Cholesky-QR with eigenvalues in the early passes
-    (AUTO), by two-sided Jacobi (JACOBI) and by one-sided Jacobi on the
-    Cholesky factor (ONESIDED) give the same shifts, ratios, pass count and
-    singular values, all equal to the oracle's."""
+    (CHOLQR), by two-sided Jacobi (JACOBI), by one-sided Jacobi on the
+    Cholesky factor (ONESIDED) and, in the FP32 form, by the tridiagonal
+    solver give the same shifts, ratios, pass count and singular values,
+    all equal to the oracle's; AUTO is CHOLQR in the FP64 form and the
+    tridiagonal solver in the FP32 form."""
     A = synth.config_small(np.float64 if prec == "fp64" else np.float32)
     ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 20, 10, 64, 1e-2, seed=2001)
     out = {}
-    for meth in ("auto", "jacobi", "onesided"):
+    meths = ("auto", "jacobi", "onesided", "cholqr") + (("tridiag",) if prec != "fp64" else ())
+    for meth in meths:
         U, S, V, st, info, tr = _solve(A, 20, 10, 64, 1e-2, 2001, prec, eig_method=meth)
         assert st == 0 and info.converged
         assert np.all(np.abs(S - ref.S) / ref.S <= bar)
         out[meth] = (S, V, info)
     Sj, Vj, ij = out["jacobi"]
-    Sc, Vc, ic = out["auto"]
+    Sc, Vc, ic = out["cholqr"]
     # Cholesky-QR from the sketch on; Jacobi for the last two pass blocks
     # (the PVE ratio reached 100 tol two passes before the end) and the
     # final step
     assert 2 <= ic.cholqr_calls <= ic.eig_calls - 3 and ij.cholqr_calls == 0
     assert list(ic.sweeps_per_call[:ic.cholqr_calls]) == [0] * ic.cholqr_calls
     assert np.all(ic.sweeps_per_call[ic.cholqr_calls:] > 0)
-    for Sx, Vx, ix in (out["auto"], out["onesided"]):
+    ia = out["auto"][2]
+    if prec == "fp64":
+        assert ia.cholqr_calls == ic.cholqr_calls and list(ia.sweeps_per_call) == list(ic.sweeps_per_call)
+    else:
+        # every call by the tridiagonal solver (no sweeps), none declined
+        assert ia.cholqr_calls == 0 and np.all(ia.sweeps_per_call == 0)
+        assert list(out["tridiag"][2].sweeps_per_call) == list(ia.sweeps_per_call)
+    for meth in meths:
+        if meth == "jacobi":
+            continue
+        Sx, Vx, ix = out[meth]
         assert ix.passes == ij.passes == ref.passes
         assert np.allclose(ix.alpha_used, ij.alpha_used, rtol=bar)
         assert np.allclose(ix.ratio, ij.ratio, rtol=100 * bar)
@@ -393,14 +406,15 @@ def test_eig_methods_agree(torch_dev, prec, bar):
     assert out["onesided"][2].cholqr_calls == 0
 
 
-@pytest.mark.parametrize("prec,bar", [("fp32", 1e-5), ("bf16", 5e-3)])
-def test_eig_tridiag_method_matches_oracle(torch_dev, prec, bar):
+@pytest.mark.parametrize("prec,bar,k,s", [("fp32", 1e-5, 40, 20), ("bf16", 5e-3, 40, 20), ("fp32", 1e-5, 100, 50)])
+def test_eig_tridiag_method_matches_oracle(torch_dev, prec, bar, k, s):
     """eig_method TRIDIAG (every block by the tridiagonal eigensolver) in the
-    FP32 and BF16 forms: the oracle's singular values within the form's bar;
-    FP32 also with the oracle's passes, shifts and ratios."""
+    FP32 and BF16 forms, l = 60 and l = 150 (five rows and columns of G a
+    thread in the reduction): the oracle's singular values within the form's
+    bar; FP32 also with the oracle's passes, shifts and ratios."""
     A = synth.zipf_csr(20000, 12000, 300000, seed=31)
-    ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 40, 20, 64, 1e-2, seed=7)
-    U, S, V, st, info, tr = _solve(A, 40, 20, 64, 1e-2, 7, prec, eig_method="tridiag")
+    ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, k, s, 64, 1e-2, seed=7)
+    U, S, V, st, info, tr = _solve(A, k, s, 64, 1e-2, 7, prec, eig_method="tridiag")
     assert st == 0 and info.converged and info.cholqr_calls == 0
     assert np.all(info.sweeps_per_call == 0)
     assert np.all(np.abs(S - ref.S) / ref.S <= bar)
@@ -408,7 +422,7 @@ def test_eig_tridiag_method_matches_oracle(torch_dev, prec, bar):
         assert info.passes == ref.passes
         assert np.allclose(info.alpha_used, ref.alpha, rtol=bar, atol=0)
         assert np.allclose(info.ratio, ref.ratio, rtol=100 * bar, atol=0)
-        Uj, Sj, Vj, stj, infoj, _ = _solve(A, 40, 20, 64, 1e-2, 7, prec, eig_method="jacobi")
+        Uj, Sj, Vj, stj, infoj, _ = _solve(A, k, s, 64, 1e-2, 7, prec, eig_method="jacobi")
         assert _vec_close(V, Vj, 2e-3) and _vec_close(U, Uj, 2e-3)
 
 
@@ -418,12 +432,12 @@ def test_eig_methods_zipf_fp32(torch_dev):
     A = synth.zipf_csr(20000, 12000, 300000, seed=31)
     ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 40, 20, 64, 1e-2, seed=7)
     passes = {}
-    for meth in ("auto", "jacobi", "onesided"):
+    for meth in ("auto", "jacobi", "onesided", "cholqr"):
         U, S, V, st, info, tr = _solve(A, 40, 20, 64, 1e-2, 7, "fp32", eig_method=meth)
         assert st == 0
         assert np.all(np.abs(S - ref.S) / ref.S <= 1e-5)
         passes[meth] = info.passes
-    assert passes["auto"] == passes["jacobi"] == passes["onesided"] == ref.passes
+    assert passes["auto"] == passes["jacobi"] == passes["onesided"] == passes["cholqr"] == ref.passes
 
 
 def test_caller_workspace(torch_dev):
