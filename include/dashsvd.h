@@ -550,10 +550,12 @@ dashsvd_status dashsvd_k_eig_onesided(int32_t l, const double *G, double *S, dou
  * reflectors before the result).  l <= 160.  *accepted (host) is 0 when two
  * eigenvalues lie within 2^-30 ||G|| of each other, or G is zero or has a
  * non-finite entry; then S, Vs and W hold no result.  prof (device,
- * optional, 6 int64): cycles of the reduction, then, as seen by the first
+ * optional, 8 int64): cycles of the reduction, then, as seen by the first
  * wave of the eigenvalue kernel, of the multisection, the isolation check,
- * the factorisations with the twist and z, the back-transformation, and
- * the cycles of the last workgroup's W and tail.  Allocates a small
+ * the factorisations with the twist and z, the back-transformation, the
+ * cycles of the last workgroup's W and tail, and, summed over the steps of
+ * the reduction as seen by its first thread, the cycles to the end of the
+ * reflector's publication and of the product A22 v.  Allocates a small
  * workspace; synchronises the stream. */
 dashsvd_status dashsvd_k_eig_tridiag(int32_t l, const double *G, double *S, double *Vs, double *W,
                                      int32_t *accepted, long long *prof, void *stream);

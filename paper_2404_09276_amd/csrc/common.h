@@ -320,7 +320,7 @@ struct EigArgs {
   int mlp_D, mlp_H;
   double mlp_cmax;
   double shape_feat[3];
-  long long *prof;      // optional step profile (6 counters), null in the solver
+  long long *prof;      // optional step profile (6 counters; 8 for the tridiagonal solver), null in the solver
   int32_t *trace_sweeps;  // sweeps of call c (c = state->eig_calls before this call), [cap + 2]
   const int32_t *run_if;  // Jacobi only: when set, the call does nothing unless *run_if != 0
   const int32_t *skip_if; // Jacobi only: when set, the call does nothing if *skip_if != 0

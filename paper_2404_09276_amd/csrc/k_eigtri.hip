@@ -34,6 +34,7 @@
 // solver state untouched) and the two-sided Jacobi kernel launched after it
 // on the same stream runs.  l <= kTriMaxL.
 #include <cstring>
+#include <utility>
 
 #include "common.h"
 #include "lanes.h"
@@ -71,6 +72,19 @@ __device__ __forceinline__ double rcp_nr(double x) {
 }
 
 __device__ __forceinline__ double guard(double q) { return fabs(q) < kPivMin ? -kPivMin : q; }
+
+// sqrt(x) for x > 0: the hardware reciprocal square root refined by two
+// Newton steps (near 1 ulp) in [2^-700, 2^700], the library's elsewhere
+__device__ __forceinline__ double sqrt_fast(double x) {
+  if (x > 0x1.0p-700 && x < 0x1.0p700) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return x * y;
+  }
+  return sqrt(x);
+}
 
 // Number of eigenvalues of the tridiagonal (d, off-diagonal squares e2) below
 // x: the negative pivots of the LDL^T factorisation of T - x I, a pivot of
@@ -129,6 +143,13 @@ __device__ __forceinline__ double row_reduce_scatter(double (&v)[NV], int lane) 
 }
 
 constexpr int log2c(int n) { return n <= 1 ? 0 : 1 + log2c(n / 2); }
+
+// f(integral_constant<int, K>) for K = 0, 1, ..., in order, each expanded
+// at compile time
+template <class F, int... Ks>
+__device__ __forceinline__ void for_each_const(F &&f, std::integer_sequence<int, Ks...>) {
+  (f(std::integral_constant<int, Ks>{}), ...);
+}
 constexpr int pow2ceil(int n) { return n <= 1 ? 1 : 2 * pow2ceil((n + 1) / 2); }
 
 // Householder reduction by a TY x 16 thread grid: thread (ty, tx) holds
@@ -142,7 +163,6 @@ __global__ __launch_bounds__(TY * 16) void k_tri_reduce(EigArgs a) {
   const int tid = threadIdx.x, lane = tid & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);  // scalar: uniform branches
   const int ty = tid / TX, tx = tid % TX;
-  const int ty_top = (wave + 1) * TYW - 1;  // largest grid row of this wave
   double *ws = a.tri_ws;
   int32_t *flags = reinterpret_cast<int32_t *>(ws + kWsFlags);
   if ((a.run_if && *a.run_if == 0) || (a.skip_if && *a.skip_if)) {
@@ -167,6 +187,7 @@ __global__ __launch_bounds__(TY * 16) void k_tri_reduce(EigArgs a) {
     }
   }
   const long long t0 = a.prof ? (long long)clock64() : 0;
+  long long c1 = 0, c2 = 0;  // profile: cycles to the end of phase 1 and of phase 2, summed
   const int l = a.l;
   constexpr int LR = TY * RR, LC = TX * RC;  // rows and columns the grid covers
   static_assert(LR == LC, "square tiles");
@@ -175,7 +196,10 @@ __global__ __launch_bounds__(TY * 16) void k_tri_reduce(EigArgs a) {
   __shared__ double ub[LR];      // u = beta A22 v
   __shared__ double part[NWv];   // partial sums of v^T A22 v
   __shared__ double sbeta[2];
-  __shared__ double dd[LR], ee[LR];
+  __shared__ double dd[LR], ee[LR], bl[LR];
+  // reflector of step p: entries p+1 .. l-1 from rf[p (2 LC - p - 1) / 2]
+  // (the rows of the strict upper triangle, packed), copied out at the end
+  __shared__ double rf[LC * (LC - 1) / 2];
 
   double A[RR][RC];
   int bad = 0;
@@ -196,14 +220,16 @@ __global__ __launch_bounds__(TY * 16) void k_tri_reduce(EigArgs a) {
     return;
   }
 
-  // Step p = k TY + j: row p is row k of the tiles of grid row j.  The loop
-  // over k is unrolled, so that the register row is known to the compiler.
-#pragma unroll
-  for (int k = 0; k < RR; ++k) {
+  // Step p = k TY + j: row p is row k of the tiles of grid row j.  Each k
+  // is a block of code of its own, so that the register row and the tile
+  // bounds below are constants.
+  auto block = [&](auto kc) __attribute__((always_inline)) {
+    constexpr int k = decltype(kc)::value;
     for (int j = 0; j < TY; ++j) {
       const int p = k * TY + j;
       if (p + 2 >= l) break;
       const int buf = p & 1;
+      const long long ta = a.prof ? (long long)clock64() : 0;
       if (wave == j / TYW) {
         // grid row j (one DPP row of this wave) forms the reflector of
         // x = A(p, p+1:); the whole wave runs the cross-lane sum
@@ -222,10 +248,11 @@ __global__ __launch_bounds__(TY * 16) void k_tri_reduce(EigArgs a) {
         const double x0 = xrow[p + 1], app = xrow[p];
         double alpha = x0, v0 = 0.0, beta = 0.0;
         if (sq > 0.0) {
-          const double nrm = sqrt(fma(x0, x0, sq));
+          const double nrm = sqrt_fast(fma(x0, x0, sq));
           alpha = x0 >= 0.0 ? -nrm : nrm;
           v0 = x0 - alpha;  // no cancellation: x0 and -alpha share the sign
-          beta = 2.0 / fma(v0, v0, sq);
+          const double vv = fma(v0, v0, sq);
+          beta = vv > 0x1.0p-1000 && vv < 0x1.0p1000 ? 2.0 * rcp_nr(vv) : 2.0 / vv;
         }
         if (ty == j) {
 #pragma unroll
@@ -233,33 +260,37 @@ __global__ __launch_bounds__(TY * 16) void k_tri_reduce(EigArgs a) {
             const int c = tx + TX * c0;
             const double v = beta == 0.0 ? 0.0 : (c == p + 1 ? v0 : (c > p + 1 ? A[k][c0] : 0.0));
             vb[buf][c] = v;
-            if (c < l) ws[kWsRef + (size_t)p * l + c] = v;
+            if (c > p && c < l) rf[p * (2 * LC - p - 1) / 2 + (c - p - 1)] = v;
           }
           if (tx == 0) {
             dd[p] = app;
             ee[p] = alpha;
             sbeta[buf] = beta;
-            ws[kWsBet + p] = beta;
+            bl[p] = beta;
           }
         }
       }
       __syncthreads();
+      const long long tb = a.prof ? (long long)clock64() : 0;
+      c1 += tb - ta;
       const double beta = sbeta[buf];
-      if (beta == 0.0) continue;  // H = I (uniform)
-      // rows of tiles wholly at or above row p take no part (a scalar test
-      // per row of tiles; columns at or left of p have v = u = 0)
+      // tiles of rows below k and of columns below C0 lie wholly at or above
+      // row p, or at or left of column p (p >= TY k): the loops start past
+      // them (bounds known once the loop over k is unrolled)
+      const int C0 = (TY * k) / TX;
       double vr[RR], vc[RC], t[NV];
 #pragma unroll
-      for (int i0 = 0; i0 < RR; ++i0) vr[i0] = vb[buf][ty + TY * i0];
+      for (int i0 = k; i0 < RR; ++i0) vr[i0] = vb[buf][ty + TY * i0];
 #pragma unroll
-      for (int c0 = 0; c0 < RC; ++c0) vc[c0] = vb[buf][tx + TX * c0];
+      for (int c0 = C0; c0 < RC; ++c0) vc[c0] = vb[buf][tx + TX * c0];
+      if (beta == 0.0) continue;  // H = I (uniform)
       double kp = 0.0;
 #pragma unroll
       for (int i0 = 0; i0 < NV; ++i0) {
         double s = 0.0;
-        if (i0 < RR && TY * i0 + ty_top > p) {
+        if (i0 >= k && i0 < RR) {
 #pragma unroll
-          for (int c0 = 0; c0 < RC; ++c0) s = fma(A[i0 < RR ? i0 : 0][c0], vc[c0], s);
+          for (int c0 = C0; c0 < RC; ++c0) s = fma(A[i0 < RR ? i0 : 0][c0], vc[c0], s);
           kp = fma(vr[i0 < RR ? i0 : 0], s, kp);
         }
         t[i0] = s;
@@ -275,24 +306,24 @@ __global__ __launch_bounds__(TY * 16) void k_tri_reduce(EigArgs a) {
       kp = lanes_wave_sum(kp);
       if (lane == 0) part[wave] = kp;
       __syncthreads();
+      if (a.prof) c2 += (long long)clock64() - tb;
       double ksum = 0.0;
 #pragma unroll
       for (int w = 0; w < NWv; ++w) ksum += part[w];
       // K = (beta / 2) v^T u with u = beta A22 v
       const double K = 0.5 * beta * beta * ksum;
-      double wc[RC];
+      double wc[RC], wr[RR];
 #pragma unroll
-      for (int c0 = 0; c0 < RC; ++c0) wc[c0] = fma(-K, vc[c0], ub[tx + TX * c0]);
+      for (int c0 = C0; c0 < RC; ++c0) wc[c0] = fma(-K, vc[c0], ub[tx + TX * c0]);
 #pragma unroll
-      for (int i0 = 0; i0 < RR; ++i0) {
-        if (TY * i0 + ty_top > p) {
-          const double wr = fma(-K, vr[i0], ub[ty + TY * i0]);
+      for (int i0 = k; i0 < RR; ++i0) wr[i0] = fma(-K, vr[i0], ub[ty + TY * i0]);
 #pragma unroll
-          for (int c0 = 0; c0 < RC; ++c0) A[i0][c0] = fma(-vr[i0], wc[c0], fma(-wr, vc[c0], A[i0][c0]));
-        }
-      }
+      for (int i0 = k; i0 < RR; ++i0)
+#pragma unroll
+        for (int c0 = C0; c0 < RC; ++c0) A[i0][c0] = fma(-vr[i0], wc[c0], fma(-wr[i0], vc[c0], A[i0][c0]));
     }
-  }
+  };
+  for_each_const(block, std::make_integer_sequence<int, RR>{});
   // the last 2 x 2 block (1 x 1 for l = 1)
 #pragma unroll
   for (int i0 = 0; i0 < RR; ++i0)
@@ -303,7 +334,18 @@ __global__ __launch_bounds__(TY * 16) void k_tri_reduce(EigArgs a) {
       if (l >= 2 && i == l - 1 && c == l - 2) ee[l - 2] = A[i0][c0];
     }
   __syncthreads();
-  if (a.prof && tid == 0) a.prof[0] = (long long)clock64() - t0;
+  // the reflector rows (zero at and left of the diagonal) and coefficients
+  // to the workspace
+  for (int p = 0; p + 2 < l; ++p) {
+    const int off = p * (2 * LC - p - 1) / 2;
+    for (int c = tid; c < l; c += NT) ws[kWsRef + (size_t)p * l + c] = c > p ? rf[off + (c - p - 1)] : 0.0;
+  }
+  for (int p = tid; p + 2 < l; p += NT) ws[kWsBet + p] = bl[p];
+  if (a.prof && tid == 0) {
+    a.prof[0] = (long long)clock64() - t0;
+    a.prof[6] = c1;
+    a.prof[7] = c2;
+  }
   if (wave != 0) return;
   // T scaled by a power of two so that its largest entry lies in [1/2, 1),
   // and the Gershgorin interval of the scaled T

@@ -589,7 +589,7 @@ def k_eig_onesided(G, S, Vs, W, skip=2.0**-53, sweeps=None, prof=None, stream=No
 def k_eig_tridiag(G, S, Vs, W, prof=None, stream=None) -> bool:
     """The tridiagonal eigensolver (l <= 160); True if G was accepted (no
     eigenvalue cluster, nonzero finite entries), else S, Vs and W hold no
-    result.  prof: optional device int64 tensor of 6 phase cycle counts."""
+    result.  prof: optional device int64 tensor of 8 phase cycle counts."""
     l = G.shape[0]
     acc = C.c_int32(0)
     _check(lib().dashsvd_k_eig_tridiag(l, _ptr(G), _ptr(S), _ptr(Vs), _ptr(W), C.byref(acc),
