@@ -26,6 +26,7 @@ thread and on all of them).
                                   about 6.9e9 nonzeros, one JSON line)
   python bench.py --summarize-trace STATS_CSV COMMAND > kernel_stats.md
   python bench.py --summarize-pmc FETCH_CSV WRITE_CSV COPY_FETCH_CSV COPY_WRITE_CSV COMMANDS > traffic.txt
+  python bench.py --summarize-mfma COUNTER_CSV COMMAND > mfma.md
                                  (the committed profile summaries, from the
                                   rocprofv3 outputs of the commands given)
 """
@@ -345,12 +346,13 @@ def source_digest(*names):
 # The SpMM's counter traffic depends on the kernel, on the order of the
 # operator's rows and columns (the degree order is built in k_csr.hip) and on
 # the panel layout (the leading dimension is chosen in driver.hip).
-TRAFFIC_SOURCES = {"spmm": ("k_spmm.hip", "k_csr.hip", "driver.hip"), "eig": ("k_eig.hip",)}
+TRAFFIC_SOURCES = {"spmm": ("k_spmm.hip", "k_csr.hip", "driver.hip"), "eig": ("k_eigtri.hip",)}
 
 
 def traffic(kind):
     """HBM bytes per launch of a kernel ("spmm": one SpMM, k_spmm and its
-    long-row kernel; "eig": one Jacobi call) from the committed rocprofv3
+    long-row kernel; "eig": one tridiagonal eigSVD call, its two kernels)
+    from the committed rocprofv3
     counter summary (FETCH_SIZE + WRITE_SIZE, calibrated on a copy kernel),
     or None when it is missing or the kernel source changed since."""
     if not os.path.exists(TRAFFIC_FILE):
@@ -435,18 +437,18 @@ def summarize_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, commands
     # one SpMM launch = k_spmm + its long-row kernel (mean over the dispatches)
     spmm_b = sum(r[4] * r[1] for r in spmm) / max(1, sum(r[1] for r in spmm))
     spmm_b += sum(r[4] * r[1] for r in spmm_long) / max(1, sum(r[1] for r in spmm))
-    # Jacobi calls: dispatches that did work (the gated launches behind an
-    # accepted Cholesky-QR call return at once and read almost nothing)
-    eig_f, eig_w = [], []
-    for name, cnt, f, w, mb, fl, wl in rows:
-        if name.startswith("k_eig<"):
-            for a, b in zip(fl, wl):
-                if a > 16.0:
-                    eig_f.append(a)
-                    eig_w.append(b)
-    eig_b = (fcal * np.mean(eig_f) + wcal * np.mean(eig_w)) * 1024 if eig_f else 0.0
-    print("# One SpMM launch = k_spmm + k_spmm_long (means over their dispatches); one Jacobi call = the k_eig")
-    print("# dispatches that read more than 16 KiB (the others are gated launches that returned at once).")
+    # tridiagonal eigSVD calls: k_tri_reduce + k_tri_vectors (means over
+    # their dispatches; the Jacobi launch behind each call returns at once
+    # unless the call declined)
+    eig_b, eig_n = 0.0, 0
+    for pre in ("k_tri_reduce<", "k_tri_vectors"):
+        sel = [r for r in rows if r[0].startswith(pre)]
+        n = sum(r[1] for r in sel)
+        if n:
+            eig_b += sum(r[4] * r[1] for r in sel) / n * 1e6
+            eig_n = n
+    print("# One SpMM launch = k_spmm + k_spmm_long (means over their dispatches); one eigSVD call =")
+    print("# k_tri_reduce + k_tri_vectors (means over their dispatches).")
     print(f"# Algorithmic bytes per launch for comparison: SpMM (A C) {spmm_bytes(200000, 100000, 10**7, 120) / 1e6:.1f} MB,"
           f" SpMM (A^T Z) {spmm_bytes(100000, 200000, 10**7, 120) / 1e6:.1f} MB.")
     print(f"fetch_calibration {fcal:.6f}")
@@ -455,7 +457,45 @@ def summarize_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, commands
     print(f"spmm_bytes_per_launch {spmm_b * 1e6:.0f}")
     print(f"eig_sha256 {source_digest(*TRAFFIC_SOURCES['eig'])}")
     print(f"eig_bytes_per_launch {eig_b:.0f}")
-    print(f"eig_calls_counted {len(eig_f)}")
+    print(f"eig_calls_counted {eig_n}")
+
+
+def summarize_mfma(csv_path, command):
+    """Per-kernel MFMA utilisation from SQ_VALU_MFMA_BUSY_CYCLES,
+    GRBM_GUI_ACTIVE and SQ_INSTS_VALU_MFMA_MOPS_F64 (rocprofv3 --pmc): busy
+    cycles over (the kernel's duration x 2.4 GHz x 1024 SIMDs), and over
+    (GRBM_GUI_ACTIVE / 8 x 1024), the per-dispatch GRBM value being the sum
+    over the 8 XCDs and including the profiler's window around the kernel;
+    and the FP64 MFMA flops (512 a MOP)."""
+    import csv
+    per = {}
+    for r in csv.DictReader(open(csv_path)):
+        d = per.setdefault((r["Kernel_Name"], r["Dispatch_Id"]), {})
+        d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        d["dur_ns"] = float(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    simds, clock = 256 * 4, 2.4e9
+    agg = {}
+    for (name, _), c in per.items():
+        if "SQ_VALU_MFMA_BUSY_CYCLES" not in c or "GRBM_GUI_ACTIVE" not in c:
+            continue
+        a = agg.setdefault(short_name(name), [0, 0.0, 0.0, 0.0, 0.0])
+        a[0] += 1
+        a[1] += c["SQ_VALU_MFMA_BUSY_CYCLES"]
+        a[2] += c["GRBM_GUI_ACTIVE"]
+        a[3] += c.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0)
+        a[4] += c["dur_ns"]
+    print(f"Command (from /tmp; R = repository root):\n\n    {command}\n")
+    print("| kernel | dispatches | mean duration us | MFMA busy / (duration x 2.4 GHz x 1024 SIMDs) "
+          "| MFMA busy / (GRBM_GUI_ACTIVE / 8 x 1024) | FP64 MFMA flops a dispatch | FP64 MFMA TFLOP/s |")
+    print("|---|---:|---:|---:|---:|---:|---:|")
+    for name, (n, busy, act, mops, dur) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        if busy <= 0:
+            continue
+        fl = 512.0 * mops / n
+        print(f"| `{name[:60]}` | {n} | {dur / n / 1e3:.1f} | {100.0 * busy / (dur * 1e-9 * clock * simds):.1f} % | "
+              f"{100.0 * busy / (act / 8.0 * simds):.1f} % | {fl:.3e} | {fl / (dur / n * 1e-9) / 1e12:.1f} |")
+    print("\nThe Gram kernel computes whole 16 x 16 upper tiles; the method's work per pass block is "
+          f"n l (l + 1) = {100000 * 120 * 121:.3e} flops (upper triangle of C^T C). Dense FP64 MFMA peak: 78.6 TFLOP/s.")
 
 
 def main():
@@ -471,6 +511,7 @@ def main():
                     help="only the batched workload at its stated scale (about 6.9e9 nonzeros)")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("STATS_CSV", "COMMAND"))
     ap.add_argument("--summarize-pmc", nargs="+", metavar="ARG")
+    ap.add_argument("--summarize-mfma", nargs=2, metavar=("COUNTER_CSV", "COMMAND"))
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
@@ -478,6 +519,9 @@ def main():
     if args.summarize_pmc:
         a = args.summarize_pmc
         summarize_pmc(a[0], a[1], a[2], a[3], a[4:])
+        return
+    if args.summarize_mfma:
+        summarize_mfma(*args.summarize_mfma)
         return
     if args.copy_probe:
         import torch
@@ -557,7 +601,7 @@ def main():
                          "kernel": "k_tri_reduce + k_tri_vectors (tridiagonal eigSVD: Householder reduction "
                                    "in one workgroup, then one wave per eigenvalue)",
                          "achieved": eig_tf, "peak": CU_FP64_TFLOPS, "unit": "TFLOP/s",
-                         "frac": eig_tf / CU_FP64_TFLOPS, "traffic": None,
+                         "frac": eig_tf / CU_FP64_TFLOPS, "traffic": traffic("eig"),
                          "flops_per_call": tridiag_flops(l), "calls_timed": tri_calls,
                          "jacobi_sweeps_after_declines": sweeps,
                          "avg_ms_per_call": eig_ms / tri_calls if tri_calls else 0.0,

@@ -336,9 +336,12 @@ __global__ __launch_bounds__(TY * 16) void k_tri_reduce(EigArgs a) {
   __syncthreads();
   // the reflector rows (zero at and left of the diagonal) and coefficients
   // to the workspace
-  for (int p = 0; p + 2 < l; ++p) {
-    const int off = p * (2 * LC - p - 1) / 2;
-    for (int c = tid; c < l; c += NT) ws[kWsRef + (size_t)p * l + c] = c > p ? rf[off + (c - p - 1)] : 0.0;
+  {
+    // rows of LC columns, NT / LC of them at a time (TX divides both)
+    constexpr int RPI = NT / LC > 0 ? NT / LC : 1;
+    const int c = tid % LC;
+    for (int p = tid / LC; p + 2 < l; p += RPI)
+      if (c < l && tid < RPI * LC) ws[kWsRef + (size_t)p * l + c] = c > p ? rf[p * (2 * LC - p - 1) / 2 + (c - p - 1)] : 0.0;
   }
   for (int p = tid; p + 2 < l; p += NT) ws[kWsBet + p] = bl[p];
   if (a.prof && tid == 0) {
