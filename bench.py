@@ -24,6 +24,8 @@ thread and on all of them).
                                   reference that calibrates the HBM counters)
   python bench.py --c5-full      (only the batched workload at its stated scale,
                                   about 6.9e9 nonzeros, one JSON line)
+  python bench.py --c3-only      (only the 2M-row forms, one solve each: for profiles)
+  python bench.py --batched-only (only the batched form: for profiles)
   python bench.py --summarize-trace STATS_CSV COMMAND > kernel_stats.md
   python bench.py --summarize-pmc FETCH_CSV WRITE_CSV COPY_FETCH_CSV COPY_WRITE_CSV COMMANDS > traffic.txt
   python bench.py --summarize-mfma COUNTER_CSV COMMAND > mfma.md
@@ -506,6 +508,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-c3", action="store_true")
+    ap.add_argument("--c3-only", action="store_true",
+                    help="only the 2M-row forms (BF16 and FP32 panels, tol 1e-2 and 1e-3), one solve each")
+    ap.add_argument("--batched-only", action="store_true", help="only the batched form")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--c5-full", action="store_true",
                     help="only the batched workload at its stated scale (about 6.9e9 nonzeros)")
@@ -541,6 +546,12 @@ def main():
     torch.cuda.set_device(0)
     if args.c5_full:
         print(json.dumps({"batched_full_scale": batched_full_scale(torch)}), flush=True)
+        return
+    if args.c3_only:
+        print(json.dumps({"c3": c3_forms(torch, torch.cuda.current_stream(), steps=1)}), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps({"batched": batched_form(torch, 3)}), flush=True)
         return
     A, Dev = load_workload(torch)
     stream = torch.cuda.current_stream()
@@ -594,6 +605,10 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "SpMM (k_spmm + k_spmm_long), the two products of a pass",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic("spmm"),
+                     # the counters' bytes (L2 misses of the gathers, served by the
+                     # last-level cache or HBM) per second of a launch
+                     "traffic_gbs": (traffic("spmm") / (0.5 * pair_ms * 1e-3) / 1e9
+                                     if traffic("spmm") and pair_ms else None),
                      "bytes_per_launch": {"spmm": b1, "spmm_t": b2},
                      "avg_ms": {"spmm": avg["spmm"], "spmm_t": avg["spmm_t"]},
                      "gbs": {"spmm": gbs1, "spmm_t": gbs2}},
@@ -630,6 +645,10 @@ def main():
                                              "fell_back": infl[-1].learned_fallback,
                                              "predicted_passes": infl[-1].learned_n,
                                              "eps_pve": pvel, "eps_sigma": esl}
+        el64, inf64, pve64, es64, _ = run_form(torch, Dev, nf, 1, stream, precision="fp64")
+        out["forms"]["fp64"] = {"value": el64 / nf, "unit": "s", "passes": inf64[-1].passes,
+                                "eps_pve": pve64, "eps_sigma": es64, "cholqr_calls": inf64[-1].cholqr_calls,
+                                "about": "FP64 panels and SpMM, Cholesky-QR for the early blocks, Jacobi after"}
         eln, infn, pven, esn, _ = run_form(torch, Dev, nf, 1, stream, precision="fp32", pve_mode="nosurr")
         out["forms"]["no_surrogate"] = {"value": eln / nf, "unit": "s", "passes": infn[-1].passes,
                                         "eps_pve": pven, "eps_sigma": esn,
