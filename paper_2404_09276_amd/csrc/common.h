@@ -198,6 +198,11 @@ struct SolverState {
 // (defined in the .hip files; all asynchronous on `st`)
 hipError_t launch_gaussian(uint64_t seed, int64_t rows, int64_t cols, void *out, int64_t ld,
                            int dtype, hipStream_t st, const int32_t *row_to = nullptr);
+// The Omega of a batch in one launch: matrix i (stacked rows off[i] ..
+// off[i + 1], device) keyed seed0 + i, boff (device) the prefix of its
+// blocks of 4 elements (nblk in all); equal to one launch_gaussian a matrix.
+hipError_t launch_gaussian_batched(uint64_t seed0, int count, const int64_t *off, const int64_t *boff,
+                                   int64_t nblk, int64_t cols, void *out, int64_t ld, int dtype, hipStream_t st);
 hipError_t launch_philox_raw(uint64_t seed, int64_t nwords, uint64_t *out, hipStream_t st);
 
 hipError_t launch_scan_i64(const int64_t *in, int64_t n, int64_t *out, int64_t *tmp, hipStream_t st);

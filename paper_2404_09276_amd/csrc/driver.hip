@@ -1719,6 +1719,7 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
   int64_t *offN = (int64_t *)ar.take(8 * (size_t)(count + 1));
   int64_t *ioffM_d = (int64_t *)ar.take(8 * (size_t)(count + 1));
   int64_t *ioffN_d = (int64_t *)ar.take(8 * (size_t)(count + 1));
+  int64_t *boffM = (int64_t *)ar.take(8 * (size_t)(count + 1));  // Omega's blocks of 4 per matrix, prefix
   BItem *itM_d = (BItem *)ar.take(sizeof(BItem) * itM.size());
   BItem *itN_d = (BItem *)ar.take(sizeof(BItem) * itN.size());
   double *bpart = (double *)ar.take(8 * bgram_partial_elems((int64_t)std::max(itM.size(), itN.size()), l));
@@ -1779,6 +1780,9 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
   HIPCHK(hipMemcpyAsync(offN, coff.data(), 8 * (size_t)(count + 1), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(ioffM_d, ioffM.data(), 8 * (size_t)(count + 1), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(ioffN_d, ioffN.data(), 8 * (size_t)(count + 1), hipMemcpyHostToDevice, st));
+  std::vector<int64_t> boff(count + 1, 0);
+  for (int i = 0; i < count; ++i) boff[i + 1] = boff[i] + (As[i].m * (int64_t)l + 3) / 4;
+  HIPCHK(hipMemcpyAsync(boffM, boff.data(), 8 * (size_t)(count + 1), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(itM_d, itM.data(), sizeof(BItem) * itM.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(itN_d, itN.data(), sizeof(BItem) * itN.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -1789,10 +1793,9 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
   HIPCHK(launch_browmat(offM, count, max_m, rowmatM, st));
   HIPCHK(launch_browmat(offN, count, max_n, rowmatN, st));
   // Omega of matrix i of the whole batch from the Philox stream keyed
-  // (seed + i, 0); this sub-batch starts at member0
-  for (int i = 0; i < count; ++i)
-    HIPCHK(launch_gaussian(h->opt.seed + (uint64_t)(member0 + i), As[i].m, l,
-                           (char *)b.Y + dsz(pdt) * (size_t)roff[i] * ld, ld, pdt, st));
+  // (seed + i, 0); this sub-batch starts at member0; one launch
+  HIPCHK(launch_gaussian_batched(h->opt.seed + (uint64_t)member0, count, offM, boffM, boff[count], l, b.Y, ld, pdt,
+                                 st));
   if (!h->sched.empty())
     HIPCHK(hipMemcpyAsync(b.sched, h->sched.data(), 8 * h->sched.size(), hipMemcpyHostToDevice, st));
   // per-matrix eigSVD arguments for the sketch (mode 1), the passes (2) and

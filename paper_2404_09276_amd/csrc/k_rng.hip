@@ -76,6 +76,44 @@ __global__ __launch_bounds__(256) void k_gaussian(uint64_t seed, int64_t rows, i
   }
 }
 
+// Omega of a batch in one launch: matrix i (rows off[i] .. off[i+1] of the
+// stacked panel) from the Philox stream keyed (seed0 + i, 0), its blocks of
+// 4 elements numbered from 0 within the matrix (boff: their prefix over the
+// matrices), so each matrix gets the values a launch of k_gaussian of its
+// own gives.
+template <typename TO>
+__global__ __launch_bounds__(256) void k_gaussian_batched(uint64_t seed0, int count,
+                                                          const int64_t *__restrict__ off,
+                                                          const int64_t *__restrict__ boff, int64_t cols,
+                                                          TO *__restrict__ out, int64_t ld) {
+  const int64_t nblk = boff[count];
+  for (int64_t gb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gb < nblk;
+       gb += (int64_t)gridDim.x * blockDim.x) {
+    // the last matrix whose blocks start at or before gb (empty matrices
+    // start where the next one does and are passed over)
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (boff[mid] <= gb) lo = mid; else hi = mid - 1;
+    }
+    const int64_t b = gb - boff[lo];
+    const int64_t total = (off[lo + 1] - off[lo]) * cols;
+    uint64_t w[4];
+    philox4x64_10((uint64_t)b + 1, 0, 0, 0, seed0 + (uint64_t)lo, 0, w);
+    double z[4];
+    box_muller(w[0], w[1], z[0], z[1]);
+    box_muller(w[2], w[3], z[2], z[3]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t e = 4 * b + i;
+      if (e < total) {
+        const int64_t r = e / cols, c = e - r * cols;
+        elem<TO>::st(out + (off[lo] + r) * ld + c, (decltype(elem<TO>::ld(out)))z[i]);
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_philox_raw(uint64_t seed, int64_t nwords,
                                                     uint64_t *__restrict__ out) {
   const int64_t nblk = (nwords + 3) / 4;
@@ -109,6 +147,22 @@ hipError_t launch_gaussian(uint64_t seed, int64_t rows, int64_t cols, void *out,
     hipLaunchKernelGGL(k_gaussian<double>, dim3(g), dim3(256), 0, st, seed, rows, cols, (double *)out, ld, row_to);
   else
     hipLaunchKernelGGL(k_gaussian<bf16>, dim3(g), dim3(256), 0, st, seed, rows, cols, (bf16 *)out, ld, row_to);
+  return hipGetLastError();
+}
+
+hipError_t launch_gaussian_batched(uint64_t seed0, int count, const int64_t *off, const int64_t *boff,
+                                   int64_t nblk, int64_t cols, void *out, int64_t ld, int dtype, hipStream_t st) {
+  if (nblk == 0 || count <= 0) return hipSuccess;
+  const int g = grid_for(nblk, 256);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_gaussian_batched<float>, dim3(g), dim3(256), 0, st, seed0, count, off, boff, cols,
+                       (float *)out, ld);
+  else if (dtype == 1)
+    hipLaunchKernelGGL(k_gaussian_batched<double>, dim3(g), dim3(256), 0, st, seed0, count, off, boff, cols,
+                       (double *)out, ld);
+  else
+    hipLaunchKernelGGL(k_gaussian_batched<bf16>, dim3(g), dim3(256), 0, st, seed0, count, off, boff, cols,
+                       (bf16 *)out, ld);
   return hipGetLastError();
 }
 
