@@ -195,47 +195,77 @@ __global__ __launch_bounds__(kBThreads) void k_brescale(const BItem *__restrict_
 
 // Sign normalisation of matrix b (one workgroup): for each column the entry
 // of largest magnitude of V_b (lowest row on ties) becomes positive, and U_b
-// is flipped alike.
+// is flipped alike.  Columns go kBSignCols at a time: each thread reads
+// whole row segments and keeps the largest entry of every column of the
+// group, the wavefronts reduce them lane to lane, wavefront 0 combines the
+// wavefronts and picks the signs, then one pass flips the rows of V_b and
+// U_b.
+constexpr int kBSignCols = 16;
 template <typename T>
 __global__ __launch_bounds__(kBThreads) void k_bsign(const int64_t *__restrict__ voff, const int64_t *__restrict__ uoff,
                                                      int k, T *__restrict__ V, T *__restrict__ U, int64_t ld) {
-  __shared__ double smax[kBThreads];
-  __shared__ int64_t sidx[kBThreads];
-  __shared__ double sgn;
-  const int b = blockIdx.x;
+  constexpr int NW = kBThreads / kWave;
+  __shared__ double smax[NW][kBSignCols];
+  __shared__ int64_t sidx[NW][kBSignCols];
+  __shared__ double sgn[kBSignCols];
+  const int b = blockIdx.x, lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int64_t v0 = voff[b], v1 = voff[b + 1], u0 = uoff[b], u1 = uoff[b + 1];
-  for (int i = 0; i < k; ++i) {
-    double best = -1.0;
-    int64_t bi = INT64_MAX;
-    for (int64_t r = v0 + threadIdx.x; r < v1; r += kBThreads) {
-      const double a = fabs(to_d(V[r * ld + i]));
-      if (a > best) {
-        best = a;
-        bi = r;
-      }
+  for (int i0 = 0; i0 < k; i0 += kBSignCols) {
+    const int nc = k - i0 < kBSignCols ? k - i0 : kBSignCols;
+    double best[kBSignCols];
+    int64_t bi[kBSignCols];
+#pragma unroll
+    for (int j = 0; j < kBSignCols; ++j) {
+      best[j] = -1.0;
+      bi[j] = INT64_MAX;
     }
-    smax[threadIdx.x] = best;
-    sidx[threadIdx.x] = bi;
-    __syncthreads();
-    for (int s = kBThreads / 2; s > 0; s >>= 1) {
-      if (threadIdx.x < s) {
-        const double a = smax[threadIdx.x + s];
-        const int64_t ii = sidx[threadIdx.x + s];
-        if (a > smax[threadIdx.x] || (a == smax[threadIdx.x] && ii < sidx[threadIdx.x])) {
-          smax[threadIdx.x] = a;
-          sidx[threadIdx.x] = ii;
+    for (int64_t r = v0 + threadIdx.x; r < v1; r += kBThreads) {
+#pragma unroll
+      for (int j = 0; j < kBSignCols; ++j) {
+        if (j < nc) {
+          const double a = fabs(to_d(V[r * ld + i0 + j]));
+          if (a > best[j]) {  // rows rise within a thread: the first of equals stays
+            best[j] = a;
+            bi[j] = r;
+          }
         }
       }
-      __syncthreads();
     }
-    if (threadIdx.x == 0) sgn = (sidx[0] < v1 && to_d(V[sidx[0] * ld + i]) < 0.0) ? -1.0 : 1.0;
+#pragma unroll
+    for (int j = 0; j < kBSignCols; ++j) {
+#pragma unroll
+      for (int o = kWave / 2; o > 0; o >>= 1) {
+        const double a = __shfl_xor(best[j], o, kWave);
+        const int64_t ii = __shfl_xor(bi[j], o, kWave);
+        if (a > best[j] || (a == best[j] && ii < bi[j])) {
+          best[j] = a;
+          bi[j] = ii;
+        }
+      }
+      if (lane == 0) {
+        smax[wave][j] = best[j];
+        sidx[wave][j] = bi[j];
+      }
+    }
     __syncthreads();
-    if (sgn < 0.0) {
-      for (int64_t r = v0 + threadIdx.x; r < v1; r += kBThreads)
-        elem<T>::st(V + r * ld + i, (decltype(elem<T>::ld(V)))(-to_d(V[r * ld + i])));
-      for (int64_t r = u0 + threadIdx.x; r < u1; r += kBThreads)
-        elem<T>::st(U + r * ld + i, (decltype(elem<T>::ld(U)))(-to_d(U[r * ld + i])));
+    if (threadIdx.x < nc) {
+      const int j = threadIdx.x;
+      double a = smax[0][j];
+      int64_t ii = sidx[0][j];
+      for (int w = 1; w < NW; ++w)
+        if (smax[w][j] > a || (smax[w][j] == a && sidx[w][j] < ii)) {
+          a = smax[w][j];
+          ii = sidx[w][j];
+        }
+      sgn[j] = (ii < v1 && to_d(V[ii * ld + i0 + j]) < 0.0) ? -1.0 : 1.0;
     }
+    __syncthreads();
+    for (int64_t r = v0 + threadIdx.x; r < v1; r += kBThreads)
+      for (int j = 0; j < nc; ++j)
+        if (sgn[j] < 0.0) elem<T>::st(V + r * ld + i0 + j, (decltype(elem<T>::ld(V)))(-to_d(V[r * ld + i0 + j])));
+    for (int64_t r = u0 + threadIdx.x; r < u1; r += kBThreads)
+      for (int j = 0; j < nc; ++j)
+        if (sgn[j] < 0.0) elem<T>::st(U + r * ld + i0 + j, (decltype(elem<T>::ld(U)))(-to_d(U[r * ld + i0 + j])));
     __syncthreads();
   }
 }
