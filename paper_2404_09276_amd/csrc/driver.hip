@@ -917,6 +917,47 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     tmark_end(h, s);
     return e;
   };
+  // Stop test one chunk behind (both pass orders): the flags of a chunk are
+  // copied to pinned host memory behind its work, and the host reads them
+  // only once the next chunk is queued, so the GPU does not idle while the
+  // host decides; a chunk queued after the stop returns at the first
+  // instruction of each kernel.
+  struct Flags {  // copy of SolverState from `ratio` to `cq_off`, then `stagnant` and `promote`
+    double ratio;
+    int32_t pass, done, cq_off, stagnant, promote, pad;
+  };
+  static_assert(offsetof(SolverState, pass) == offsetof(SolverState, ratio) + 8 &&
+                    offsetof(SolverState, done) == offsetof(SolverState, ratio) + 12 &&
+                    offsetof(SolverState, cq_off) == offsetof(SolverState, ratio) + 16 &&
+                    offsetof(SolverState, promote) == offsetof(SolverState, stagnant) + 4,
+                "flag copy layout");
+  // two slots in front of the plan sizes (bytes 64..95 of the pinned area)
+  static_assert(2 * sizeof(Flags) <= 64, "flag slots");
+  Flags *hf = reinterpret_cast<Flags *>(h->hflags);
+  double r_old = 0.0, r_new = 0.0;  // the last two ratios read
+  bool stop = false;
+  bool promote_read = false;  // BF16 panels: the pass tail asked for FP32 panels
+  int stagnant_read = 0;      // BF16 panels: flat passes so far (2 ask for FP32)
+  int stop_pass = 0;  // passes executed, as read with the stop flag
+  auto copy_flags = [&](int slot, hipStream_t s) -> hipError_t {
+    hipError_t e = hipMemcpyAsync(&hf[slot], &b.state->ratio, 20, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&hf[slot].stagnant, &b.state->stagnant, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(h->ev_flag[slot], s);
+    return e;
+  };
+  auto read_slot = [&](int slot) -> hipError_t {
+    const hipError_t e = hipEventSynchronize(h->ev_flag[slot]);
+    if (e != hipSuccess) return e;
+    host_cq_off = hf[slot].cq_off;
+    stop = hf[slot].done != 0;
+    stop_pass = hf[slot].pass;
+    promote_read = hf[slot].promote != 0;
+    stagnant_read = hf[slot].stagnant;
+    r_old = r_new;
+    r_new = hf[slot].ratio;
+    return hipSuccess;
+  };
   int32_t eig_launches = 0;  // eigensolver calls launched beside the SpMMs (signal index)
   int last_pass = 0;  // passes whose eigSVD ran (the final block's C, Z, W)
   int promoted = 0;   // BF16 panels switched to FP32 by the stagnation guard
@@ -1000,36 +1041,10 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
                        nullptr, st, nullptr, nullptr, Mm));
     tmark_end(h);
     HIPCHK(side(1, 0, Cb[0], nullptr));
-    // power passes (steps 3-8).  Stop test one chunk behind: the flags of
-    // a chunk are copied to pinned host memory behind its work, and the host
-    // reads them only once the next chunk is queued, so the GPU does not
-    // idle while the host decides; a chunk queued after the stop returns at
-    // the first instruction of each kernel.
+    // power passes (steps 3-8), the stop test one chunk behind.
     // When the ratios read so far predict that the chunk just queued meets
     // tol, the host waits for that chunk's flags instead (one host round
     // trip, against a whole chunk of launches that would return at once).
-    struct Flags {  // copy of SolverState from `ratio` to `cq_off`
-      double ratio;
-      int32_t pass, done, cq_off, pad;
-    };
-    static_assert(offsetof(SolverState, pass) == offsetof(SolverState, ratio) + 8 &&
-                      offsetof(SolverState, done) == offsetof(SolverState, ratio) + 12 &&
-                      offsetof(SolverState, cq_off) == offsetof(SolverState, ratio) + 16,
-                  "flag copy layout");
-    Flags *hf = reinterpret_cast<Flags *>(h->hflags);  // two slots
-    double r_old = 0.0, r_new = 0.0;  // the last two ratios read
-    bool stop = false;
-    int stop_pass = 0;  // passes executed, as read with the stop flag
-    auto read_slot = [&](int slot) -> hipError_t {
-      const hipError_t e = hipEventSynchronize(h->ev_flag[slot]);
-      if (e != hipSuccess) return e;
-      host_cq_off = hf[slot].cq_off;
-      stop = hf[slot].done != 0;
-      stop_pass = hf[slot].pass;
-      r_old = r_new;
-      r_new = hf[slot].ratio;
-      return hipSuccess;
-    };
     int launched = 0;
     int pending = -1;  // flag slot copied but not read yet
     while (launched < pmax) {
@@ -1046,8 +1061,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       launched += chunk;
       if (!(tol > 0.0 && launched < pmax)) continue;
       const int slot = pending == 0 ? 1 : 0;
-      HIPCHK(hipMemcpyAsync(&hf[slot], &b.state->ratio, sizeof(Flags) - 4, hipMemcpyDeviceToHost, st));
-      HIPCHK(hipEventRecord(h->ev_flag[slot], st));
+      HIPCHK(copy_flags(slot, st));
       if (pending >= 0) {
         HIPCHK(read_slot(pending));
         if (stop) break;
@@ -1109,8 +1123,28 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
                        nullptr, nullptr, Mm));
     tmark_end(h);
     HIPCHK(block_step(1, 0, nullptr));
-    // power passes (steps 3-8): C = M^T Y - alpha Q ; eigSVD(C) ; check ; shift
+    // power passes (steps 3-8): C = M^T Y - alpha Q ; eigSVD(C) ; check ;
+    // shift; the stop test one chunk behind, as in the overlapped order.  A
+    // request for FP32 panels follows a flat pass: once the flags read show
+    // one, the host reads the chunk just queued at once, so the panels
+    // switch before the next chunk, as with a read after every chunk.
     int launched = 0;
+    int pending = -1;  // flag slot copied but not read yet
+    auto promote_now = [&]() -> hipError_t {
+      pcur = cdt;
+      Qc = b.Q32;
+      Yc = b.Y32;
+      promoted = 1;
+      // not gated on the stop flag: when the chunk queued behind the request
+      // stopped, the final step reads these FP32 panels (Q = C W of its
+      // last block, as its BF16 ones)
+      hipError_t e = launch_rescale(Mn, l, b.C, ld, cdt, b.W, l, l, Qc, ld, pcur, nullptr, st);
+      if (e == hipSuccess)
+        e = launch_spmm(Mm, rpM, colM, valM, vdt, Qc, ld, pcur, Yc, ld, pcur, ldc, b.planM.n_chunks,
+                        b.planM.order, b.planM.n_long, b.planM.longs, b.planM.partial, T, vm, nullptr, 0, nullptr,
+                        nullptr, st, nullptr, nullptr, Mn);
+      return e;
+    };
     while (launched < pmax) {
       const int chunk = (pmax - launched) < every ? (pmax - launched) : every;
       for (int c = 0; c < chunk; ++c) {
@@ -1123,23 +1157,29 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
         HIPCHK(block_step(2, pass, done));
       }
       launched += chunk;
-      if (tol > 0.0 && launched < pmax) {
-        int32_t flags[3] = {0, 0, 0};  // done, cq_off, promote
-        HIPCHK(hipMemcpyAsync(&flags[0], done, 8, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(&flags[2], &b.state->promote, 4, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        host_cq_off = flags[1];
-        if (flags[0]) break;
-        if (flags[2] && pcur == DASHSVD_BF16) {
-          pcur = cdt;
-          Qc = b.Q32;
-          Yc = b.Y32;
-          promoted = 1;
-          HIPCHK(launch_rescale(Mn, l, b.C, ld, cdt, b.W, l, l, Qc, ld, pcur, nullptr, st));
-          HIPCHK(launch_spmm(Mm, rpM, colM, valM, vdt, Qc, ld, pcur, Yc, ld, pcur, ldc, b.planM.n_chunks,
-                             b.planM.order, b.planM.n_long, b.planM.longs, b.planM.partial, T, vm, nullptr, 0,
-                             nullptr, nullptr, st, nullptr, nullptr, Mn));
-        }
+      if (!(tol > 0.0 && launched < pmax)) continue;
+      const int slot = pending == 0 ? 1 : 0;
+      HIPCHK(copy_flags(slot, st));
+      if (pending >= 0) {
+        HIPCHK(read_slot(pending));
+        if (stop) break;
+        if (promote_read && pcur == DASHSVD_BF16) HIPCHK(promote_now());
+      }
+      pending = slot;
+      // geometric extrapolation of the ratio over the chunk just queued, or
+      // a flat pass before it (the chunk may ask for FP32 panels)
+      bool now = pcur == DASHSVD_BF16 && stagnant_read >= 1;
+      if (r_old > 0.0 && r_new > 0.0 && r_new < r_old) {
+        const double q = r_new / r_old;
+        double pred = r_new;
+        for (int c = 0; c < chunk; ++c) pred *= q;
+        now = now || pred <= 1.5 * tol;
+      }
+      if (now) {
+        HIPCHK(read_slot(slot));
+        pending = -1;
+        if (stop) break;
+        if (promote_read && pcur == DASHSVD_BF16) HIPCHK(promote_now());
       }
     }
     HIPCHK(hipStreamSynchronize(st));
