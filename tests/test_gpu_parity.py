@@ -321,6 +321,30 @@ def test_rank_deficient_matrix(torch_dev):
     assert np.allclose(S[:3], sv[:3], rtol=1e-10)
 
 
+def test_rank_deficient_matrix_fp32_tridiagonal_declines(torch_dev):
+    """FP32 form (AUTO: the tridiagonal eigSVD) on a matrix of rank exactly 3
+    with l = 8.  The Grams of the sketch block (M^T Omega) and of the final
+    block (M Q) have five eigenvalues at zero, equal up to rounding: those
+    calls decline to the two-sided Jacobi kernel behind them (its sweeps are
+    recorded).  The shifted pass blocks M^T M Q - alpha Q move the null
+    directions to alpha^2, where rounding separates them by more than
+    2^-30 ||G||, and the tridiagonal solver keeps them.  The solve reports
+    the rank deficiency and the three nonzero singular values within the
+    FP32 bar."""
+    rng = np.random.default_rng(4)
+    # integer factors: D is exactly of rank 3 in FP32
+    D = (rng.integers(-3, 4, (300, 3)) @ rng.integers(-3, 4, (3, 200))).astype(np.float64)
+    A = synth.dense_to_csr(D, dtype=np.float32)
+    U, S, V, st, info, tr = _solve(A, 4, 4, 3, 0.0, 1, "fp32")
+    sw = np.asarray(info.sweeps_per_call[:info.eig_calls])
+    assert st == 2 and info.rank_deficient
+    assert info.cholqr_calls == 0 and info.eig_calls == 5
+    assert sw[0] > 0 and sw[-1] > 0 and np.all(sw[1:-1] == 0)
+    sv = np.linalg.svd(D, compute_uv=False)
+    assert np.allclose(S[:3], sv[:3], rtol=1e-5)
+    assert S[3] <= 1e-6 * S[0]
+
+
 @pytest.mark.parametrize("shape,prec,atol", [((2000, 1500), "fp64", 1e-9), ((2000, 1500), "fp32", 2e-5),
                                              ((700, 1900), "fp64", 1e-9)])
 def test_evaluate_matches_oracle_metrics(torch_dev, shape, prec, atol):
