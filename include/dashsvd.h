@@ -185,7 +185,16 @@ typedef struct {
                              lanes) or 2 (half as many lanes, twice the gathers in
                              flight per lane; used where the row splits evenly); <= 0
                              (default): the tuning database's value, else 1 */
+  int32_t dense_head;     /* DASHSVD_HEAD_*: with the degree order, the leading rows of M and
+                             of M^T that hold at least max(long_row + 1, columns / 16)
+                             nonzeros each (at most 128; none if fewer than 16) are
+                             multiplied as a dense block on the matrix cores instead of
+                             by the row-split SpMM.  AUTO (0, default): on where the degree
+                             order is on and l rounded up to 8 is at most 128; OFF (-1) */
 } dashsvd_options;
+
+#define DASHSVD_HEAD_AUTO 0
+#define DASHSVD_HEAD_OFF (-1)
 
 #define DASHSVD_REORDER_AUTO 0
 #define DASHSVD_REORDER_ON 1
@@ -244,6 +253,8 @@ typedef struct {
   int32_t lane_vectors_used; /* SpMM lane vectors of the run (option, tuning database or 1) */
   int32_t slab_kib_used;   /* SpMM column-slab KiB of the run (0: none) */
   int32_t reordered;       /* 1 if the run iterated the degree-ordered operator */
+  int32_t head_rows;       /* rows of M multiplied as a dense head (option dense_head; 0: none) */
+  int32_t head_rows_t;     /* the same for M^T */
 } dashsvd_info;
 
 typedef struct dashsvd_handle dashsvd_handle;

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdashsvd.so")
-SOURCES = ["k_rng.hip", "k_csr.hip", "k_spmm.hip", "k_dense.hip", "k_eig.hip", "k_eig1s.hip", "k_eigtri.hip", "k_cholqr.hip", "k_batched.hip", "k_mlp.hip", "k_eval.hip", "k_sort.hip", "driver.hip"]
+SOURCES = ["k_rng.hip", "k_csr.hip", "k_spmm.hip", "k_head.hip", "k_dense.hip", "k_eig.hip", "k_eig1s.hip", "k_eigtri.hip", "k_cholqr.hip", "k_batched.hip", "k_mlp.hip", "k_eval.hip", "k_sort.hip", "driver.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

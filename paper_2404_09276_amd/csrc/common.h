@@ -256,16 +256,18 @@ hipError_t launch_transpose_gather(int64_t nnz, const int32_t *rowidx, const voi
                                    const int64_t *rp_new = nullptr);
 // out[0..3] = *endM, *endT, *nlM, *nlT (chunk totals and long-row counts of
 // the two SpMM plans), so that the host reads them with one copy.
+// out[0..5]: chunk counts, long-row counts and dense-head rows (hM, hT may be null: 0) of the two plans
 hipError_t launch_plan_sizes(const int64_t *endM, const int64_t *endT, const int32_t *nlM, const int32_t *nlT,
-                             int64_t *out, hipStream_t st);
+                             const int32_t *hM, const int32_t *hT, int64_t *out, hipStream_t st);
 // SpMM row-split plan: rows longer than long_row are cut into chunks at the
 // column-slab boundaries (slab_log2 >= 31: no slabs) and into pieces of at
 // most long_row nonzeros.  nch[r]: chunks of row r; tasks (slot order) and
 // tslab: each chunk and its slab; launch_plan_order then lists the chunks
 // slab by slab in `order` (slab_cnt: 2 (kMaxSlabs + 1) zeroed words; the
 // chunk count is read on the device at off[R]).
+// head (device, may be null): rows below *head get no chunks (a dense head)
 hipError_t launch_plan_count(int64_t R, const int64_t *rp, const int32_t *col, int32_t long_row, int slab_log2,
-                             int64_t *nch, hipStream_t st);
+                             int64_t *nch, hipStream_t st, const int32_t *head = nullptr);
 hipError_t launch_plan_fill(int64_t R, const int64_t *rp, const int32_t *col, int32_t long_row, int slab_log2,
                             const int64_t *off, ChunkTask *tasks, int32_t *tslab, LongRow *longs, int32_t *nlong,
                             hipStream_t st);
@@ -280,6 +282,35 @@ hipError_t launch_spmm(int64_t R, const int64_t *rp, const int32_t *col, const v
                        const void *Q, int64_t ldq, const double *alpha, const int32_t *done, hipStream_t st,
                        const int32_t *rowmat = nullptr, const SolverState *bstate = nullptr,
                        int64_t xrows = 0);
+
+// Dense head of a degree-ordered operand (k_head.hip): its first H rows
+// (at most kHeadMax, each with at least max(long_row + 1, ncols / 16)
+// nonzeros, none if fewer than kHeadMinRows qualify or if they hold fewer
+// than kHeadNnzPerCol nonzeros per column of M) are multiplied as a
+// dense block on the matrix cores; the SpMM plan leaves them out.  Dt holds
+// M[0:H, :]^T (ncols x kHeadMax) in the accumulation type of the products
+// (tdtype 1 = f64 for FP64 panels, else 0 = f32); part holds kHeadSplits
+// partial products.
+constexpr int kHeadMax = 128;
+constexpr int kHeadMinRows = 16;
+constexpr int kHeadSplits = 256;
+size_t head_dt_bytes(int64_t ncols, int tdtype);
+size_t head_part_bytes(int tdtype);
+// the row ranges of the splits stay within 32-bit buffer offsets, ldc <= kHeadMax
+bool head_fits(int64_t K, int64_t ldx, int xdtype, int ldc);
+// the head's nonzeros must be at least this many times the operator's columns
+constexpr int kHeadNnzPerCol = 16;
+// *out = H of the rows of a degree-ordered CSR (thr = least nonzeros of a head
+// row, min_nnz = least nonzeros of the whole head)
+hipError_t launch_head_count(int64_t R, const int64_t *rp, int64_t thr, int64_t min_nnz, int32_t *out,
+                             hipStream_t st);
+// Dt (ncols x kHeadMax) from the first H rows of the CSR of M
+hipError_t launch_head_build(int64_t ncols, const int64_t *rp, const int32_t *col, const void *val, int vdtype,
+                             int H, void *Dt, int tdtype, hipStream_t st);
+// rows 0..H-1 of Y = M X (- alpha Q), X with K rows; same dtypes and done flag as launch_spmm
+hipError_t launch_head_product(int H, int64_t K, const void *X, int64_t ldx, int xdtype, int ldc, const void *Dt,
+                               int tdtype, void *part, void *Y, int64_t ldy, int ydtype, const void *Q,
+                               int64_t ldq, const double *alpha, const int32_t *done, hipStream_t st);
 
 // snap (optional): receives *done as read at the start of the Gram kernel,
 // i.e. whether the iteration had already stopped when this pass began.

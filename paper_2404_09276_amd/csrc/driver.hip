@@ -81,6 +81,14 @@ struct Plan {
   LongRow *longs = nullptr;
   int32_t *nlong = nullptr;
   void *partial = nullptr;
+  // dense head (k_head.hip): the first `head` rows of a degree-ordered
+  // operator, left out of the chunks and multiplied as a dense block
+  int32_t *head_dev = nullptr;  // H as counted on the device (null: no head)
+  int32_t head = 0;             // H as read back by the host
+  int64_t head_cols = 0;        // columns of the operator (rows of the panel it multiplies)
+  int head_t = 0;               // type of Dt and of the partial products: 1 f64, 0 f32
+  void *dt = nullptr;           // M[0:H, :]^T, head_cols x kHeadMax
+  void *hpart = nullptr;        // kHeadSplits partial products
 };
 
 // Column-slab width (log2, in columns of the operator = rows of the gathered
@@ -289,7 +297,7 @@ dashsvd_status ensure_arena(dashsvd_handle *h, size_t bytes) {
 // per slab boundary it crosses.
 dashsvd_status plan_alloc(dashsvd_handle *h, Arena &ar, Plan &p, int64_t R, int64_t nnz, int32_t T,
                           int ld, size_t acc_sz, int64_t ncols = 0, int64_t row_bytes = 0,
-                          int64_t slab_bytes = 0) {
+                          int64_t slab_bytes = 0, int head_t = -1) {
   p.R = R;
   p.slab_log2 = slab_log2_for(ncols, row_bytes, slab_bytes);
   p.nslabs = p.slab_log2 >= 31 ? 1 : (int)(((ncols - 1) >> p.slab_log2) + 1);
@@ -304,6 +312,17 @@ dashsvd_status plan_alloc(dashsvd_handle *h, Arena &ar, Plan &p, int64_t R, int6
   p.longs = (LongRow *)ar.take(sizeof(LongRow) * (size_t)max_long);
   p.nlong = (int32_t *)ar.take(sizeof(int32_t) * 4);
   p.partial = ar.take(acc_sz * (size_t)ld * (size_t)max_chunks);
+  // a dense head (head_t >= 0): its count, Dt and the partial products
+  p.head = 0;
+  p.head_cols = ncols;
+  p.head_dev = nullptr;
+  p.dt = p.hpart = nullptr;
+  if (head_t >= 0 && ncols > 0) {
+    p.head_t = head_t;
+    p.head_dev = (int32_t *)ar.take(16);
+    p.dt = ar.take(head_dt_bytes(ncols, head_t));
+    p.hpart = ar.take(head_part_bytes(head_t));
+  }
   (void)h;
   return DASHSVD_OK;
 }
@@ -311,7 +330,7 @@ dashsvd_status plan_alloc(dashsvd_handle *h, Arena &ar, Plan &p, int64_t R, int6
 // The plan's kernels: chunk counts, their scan, the chunks in slot order and
 // then slab by slab (p.nlong and p.slab_cnt zeroed beforehand).
 hipError_t plan_build(Plan &p, const int64_t *rp, const int32_t *col, int32_t T, int64_t *scan_tmp, hipStream_t st) {
-  hipError_t e = launch_plan_count(p.R, rp, col, T, p.slab_log2, p.nch, st);
+  hipError_t e = launch_plan_count(p.R, rp, col, T, p.slab_log2, p.nch, st, p.head_dev);
   if (e == hipSuccess) e = launch_scan_i64(p.nch, p.R, p.off, scan_tmp, st);
   if (e == hipSuccess) e = launch_plan_fill(p.R, rp, col, T, p.slab_log2, p.off, p.tasks, p.tslab, p.longs, p.nlong, st);
   // one slab: the chunks run in slot order (row by row)
@@ -320,6 +339,20 @@ hipError_t plan_build(Plan &p, const int64_t *rp, const int32_t *col, int32_t T,
     return e;
   }
   if (e == hipSuccess) e = launch_plan_order(p.nslabs, p.off + p.R, p.tasks, p.tslab, p.slab_cnt, p.order, st);
+  return e;
+}
+
+// A product with a plan's operator: the row-split SpMM over the rows of the
+// plan, then its dense head rows (k_head.hip) when it has them.  Same
+// arguments as launch_spmm; X has p.head_cols rows.
+hipError_t plan_spmm(const Plan &p, int64_t R, const int64_t *rp, const int32_t *col, const void *val, int vdt,
+                     const void *X, int64_t ldx, int xdt, void *Y, int64_t ldy, int ydt, int ldc, int32_t T, int vm,
+                     const void *Q, int64_t ldq, const double *alpha, const int32_t *done, hipStream_t st) {
+  hipError_t e = launch_spmm(R, rp, col, val, vdt, X, ldx, xdt, Y, ldy, ydt, ldc, p.n_chunks, p.order, p.n_long,
+                             p.longs, p.partial, T, vm, Q, ldq, alpha, done, st, nullptr, nullptr, p.head_cols);
+  if (e == hipSuccess && p.head > 0)
+    e = launch_head_product(p.head, p.head_cols, X, ldx, xdt, ldc, p.dt, p.head_t, p.hpart, Y, ldy, ydt, Q, ldq,
+                            alpha, done, st);
   return e;
 }
 
@@ -402,6 +435,7 @@ dashsvd_status dashsvd_set_options(dashsvd_handle *h, const dashsvd_options *opt
   if (o.pve_mode < 0 || o.pve_mode > 2) return fail(h, DASHSVD_ERR_INVALID_ARG, "pve_mode");
   if (o.eig_method < 0 || o.eig_method > 4) return fail(h, DASHSVD_ERR_INVALID_ARG, "eig_method");
   if (o.reorder < -1 || o.reorder > 1) return fail(h, DASHSVD_ERR_INVALID_ARG, "reorder");
+  if (o.dense_head < -1 || o.dense_head > 0) return fail(h, DASHSVD_ERR_INVALID_ARG, "dense_head");
   if (o.lane_vectors > 2) return fail(h, DASHSVD_ERR_INVALID_ARG, "lane_vectors (1 or 2; <= 0: tuned or 1)");
   if (o.p_max < 0) o.p_max = kDefaultPmax;
   if (o.p_max > 100000) return fail(h, DASHSVD_ERR_INVALID_ARG, "p_max too large");
@@ -609,7 +643,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   b.valT = ar.take(dsz(vdt) * (size_t)(nnz + 1));
   b.rowidx = (int32_t *)ar.take(4 * (size_t)(nnz + 1));
   b.flags = (int32_t *)ar.take(4 * 8);
-  b.sizes = (int64_t *)ar.take(8 * 4);
+  b.sizes = (int64_t *)ar.take(8 * 6);
   b.tws_bytes = transpose_ws_bytes(n, nnz);
   b.tws = ar.take(b.tws_bytes);
   const int64_t scan_n = (m > n ? m : n) + 1;
@@ -618,8 +652,17 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   // the n-side panels (C, Q), M^T rows of the m-side ones (Z, Y)
   const int64_t prow_b = (int64_t)ld * (int64_t)dsz(pdt);
   const int64_t slab_b = slab_bytes(h, tkey);
-  plan_alloc(h, ar, b.planM, Mm, nnz, T, ldc, accsz, Mn, prow_b, slab_b);
-  plan_alloc(h, ar, b.planT, Mn, nnz, T, ldc, accsz, Mm, prow_b, slab_b);
+  const TuneVal *tv = tuned(h, tkey);
+  const bool reorder = h->opt.reorder == DASHSVD_REORDER_ON ||
+                       (h->opt.reorder == DASHSVD_REORDER_AUTO &&
+                        (tv && tv->reorder ? tv->reorder > 0 : nnz >= DASHSVD_REORDER_MIN_NNZ));
+  // dense heads of M and M^T: only in the degree order (the head is then a
+  // prefix of the rows), and for panels whose rows fit the head kernels
+  const int head_t = prec == DASHSVD_PREC_FP64 ? 1 : 0;
+  const bool heads = reorder && h->opt.dense_head != DASHSVD_HEAD_OFF && ldc <= kHeadMax &&
+                     head_fits(Mn > Mm ? Mn : Mm, ld, cdt, ldc);
+  plan_alloc(h, ar, b.planM, Mm, nnz, T, ldc, accsz, Mn, prow_b, slab_b, heads ? head_t : -1);
+  plan_alloc(h, ar, b.planT, Mn, nnz, T, ldc, accsz, Mm, prow_b, slab_b, heads ? head_t : -1);
   b.Y = ar.take(dsz(pdt) * (size_t)Mm * ld);
   b.Q = ar.take(dsz(pdt) * (size_t)Mn * ld);
   b.C = ar.take(dsz(cdt) * (size_t)Mn * ld);
@@ -657,10 +700,6 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   b.sgn_idx = ar.take(8 * (size_t)sgn_blk * k + 4 * (size_t)k);
   if (h->opt.omega && !h->opt.omega_on_device)
     b.omega_dev = ar.take(dsz(h->opt.omega_dtype) * (size_t)Mm * l);
-  const TuneVal *tv = tuned(h, tkey);
-  const bool reorder = h->opt.reorder == DASHSVD_REORDER_ON ||
-                       (h->opt.reorder == DASHSVD_REORDER_AUTO &&
-                        (tv && tv->reorder ? tv->reorder > 0 : nnz >= DASHSVD_REORDER_MIN_NNZ));
   if (reorder) {
     b.perm_r = (int32_t *)ar.take(4 * (size_t)(m + 1));
     b.inv_r = (int32_t *)ar.take(4 * (size_t)(m + 1));
@@ -792,6 +831,14 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   // caller's order (null without the degree order)
   const int32_t *mapM = reorder ? (wide ? b.perm_c : b.perm_r) : nullptr;
   const int32_t *mapN = reorder ? (wide ? b.perm_r : b.perm_c) : nullptr;
+  // dense heads: the leading rows with at least max(T + 1, columns / 16)
+  // nonzeros (the plans leave them out)
+  if (b.planM.head_dev)
+    HIPCHK(launch_head_count(Mm, rpM, std::max<int64_t>(T + 1, (Mn + 15) / 16), kHeadNnzPerCol * Mn,
+                             b.planM.head_dev, st));
+  if (b.planT.head_dev)
+    HIPCHK(launch_head_count(Mn, rpMT, std::max<int64_t>(T + 1, (Mm + 15) / 16), kHeadNnzPerCol * Mm,
+                             b.planT.head_dev, st));
   // SpMM plans
   HIPCHK(plan_build(b.planM, rpM, colM, T, b.scan_tmp, st));
   HIPCHK(plan_build(b.planT, rpMT, colMT, T, b.scan_tmp, st));
@@ -799,14 +846,21 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   // again), one copy to pinned memory, one wait
   int64_t *sizes_d = b.sizes;
   int64_t *sizes_h = (int64_t *)(h->hflags + 16);
-  HIPCHK(launch_plan_sizes(b.planM.off + b.planM.R, b.planT.off + b.planT.R, b.planM.nlong, b.planT.nlong, sizes_d,
-                           st));
-  HIPCHK(hipMemcpyAsync(sizes_h, sizes_d, 32, hipMemcpyDeviceToHost, st));
+  HIPCHK(launch_plan_sizes(b.planM.off + b.planM.R, b.planT.off + b.planT.R, b.planM.nlong, b.planT.nlong,
+                           b.planM.head_dev, b.planT.head_dev, sizes_d, st));
+  HIPCHK(hipMemcpyAsync(sizes_h, sizes_d, 48, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   b.planM.n_chunks = sizes_h[0];
   b.planT.n_chunks = sizes_h[1];
   b.planM.n_long = (int32_t)sizes_h[2];
   b.planT.n_long = (int32_t)sizes_h[3];
+  b.planM.head = (int32_t)sizes_h[4];
+  b.planT.head = (int32_t)sizes_h[5];
+  // Dt of each head from its first rows
+  if (b.planM.head > 0)
+    HIPCHK(launch_head_build(Mn, rpM, colM, valM, vdt, b.planM.head, b.planM.dt, b.planM.head_t, st));
+  if (b.planT.head > 0)
+    HIPCHK(launch_head_build(Mm, rpMT, colMT, valMT, vdt, b.planT.head, b.planT.dt, b.planT.head_t, st));
   if (!h->sched.empty())
     HIPCHK(hipMemcpyAsync(b.sched, h->sched.data(), 8 * h->sched.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamWaitEvent(st, h->ev_eig, 0));  // Omega is ready
@@ -989,9 +1043,8 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       // every CU first, so they wait (bounded) until it is resident.
       if ((e = launch_wait_started(&b.state->eig_started, ea.call_idx, st)) != hipSuccess) return e;
       tmark_begin(h, DASHSVD_KT_SPMM, pass);
-      e = launch_spmm(Mm, rpM, colM, valM, vdt, Cin, ld, cdt, b.Z, ld, cdt, ldc, b.planM.n_chunks, b.planM.order,
-                      b.planM.n_long, b.planM.longs, b.planM.partial, T, vm, nullptr, 0, nullptr, skip, st, nullptr,
-                      nullptr, Mn);
+      e = plan_spmm(b.planM, Mm, rpM, colM, valM, vdt, Cin, ld, cdt, b.Z, ld, cdt, ldc, T, vm, nullptr, 0, nullptr,
+                    skip, st);
       tmark_end(h);
       if (e != hipSuccess) return e;
       tmark_begin(h, DASHSVD_KT_SPMM_T, pass);
@@ -999,9 +1052,8 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       // block stops the iteration before the product's workgroups start,
       // they return at once (the live flag, not the pass-start snapshot;
       // Z above is kept, the final step uses it)
-      e = launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Z, ld, cdt, b.X, ld, cdt, ldc, b.planT.n_chunks, b.planT.order,
-                      b.planT.n_long, b.planT.longs, b.planT.partial, T, vm, nullptr, 0, nullptr, gate, st, nullptr,
-                      nullptr, Mm);
+      e = plan_spmm(b.planT, Mn, rpMT, colMT, valMT, vdt, b.Z, ld, cdt, b.X, ld, cdt, ldc, T, vm, nullptr, 0, nullptr,
+                    gate, st);
       tmark_end(h);
       if (e != hipSuccess) return e;
       return hipStreamWaitEvent(st, h->ev_eig, 0);
@@ -1036,9 +1088,8 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     };
     // sketch (Alg. 5 step 2): C = M^T Omega, its eigSVD || M C, M^T M C
     tmark_begin(h, DASHSVD_KT_SKETCH, 0);
-    HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, Cb[0], ld, cdt, ldc, b.planT.n_chunks,
-                       b.planT.order, b.planT.n_long, b.planT.longs, b.planT.partial, T, vm, nullptr, 0, nullptr,
-                       nullptr, st, nullptr, nullptr, Mm));
+    HIPCHK(plan_spmm(b.planT, Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, Cb[0], ld, cdt, ldc, T, vm, nullptr, 0,
+                     nullptr, nullptr, st));
     tmark_end(h);
     HIPCHK(side(1, 0, Cb[0], nullptr));
     // power passes (steps 3-8), the stop test one chunk behind.
@@ -1110,17 +1161,15 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       tmark_end(h);
       if (e != hipSuccess) return e;
       tmark_begin(h, DASHSVD_KT_SPMM, pass);
-      e = launch_spmm(Mm, rpM, colM, valM, vdt, Qc, ld, pcur, Yc, ld, pcur, ldc, b.planM.n_chunks, b.planM.order,
-                      b.planM.n_long, b.planM.longs, b.planM.partial, T, vm, nullptr, 0, nullptr, skip, st, nullptr,
-                      nullptr, Mn);
+      e = plan_spmm(b.planM, Mm, rpM, colM, valM, vdt, Qc, ld, pcur, Yc, ld, pcur, ldc, T, vm, nullptr, 0, nullptr,
+                    skip, st);
       tmark_end(h);
       return e;
     };
     // sketch (Alg. 5 step 2): C = M^T Omega ; Q = eigSVD(C).U ; Y = M Q
     tmark_begin(h, DASHSVD_KT_SKETCH, 0);
-    HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ldc, b.planT.n_chunks, b.planT.order,
-                       b.planT.n_long, b.planT.longs, b.planT.partial, T, vm, nullptr, 0, nullptr, nullptr, st,
-                       nullptr, nullptr, Mm));
+    HIPCHK(plan_spmm(b.planT, Mn, rpMT, colMT, valMT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ldc, T, vm, nullptr, 0, nullptr,
+                     nullptr, st));
     tmark_end(h);
     HIPCHK(block_step(1, 0, nullptr));
     // power passes (steps 3-8): C = M^T Y - alpha Q ; eigSVD(C) ; check ;
@@ -1140,9 +1189,8 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       // last block, as its BF16 ones)
       hipError_t e = launch_rescale(Mn, l, b.C, ld, cdt, b.W, l, l, Qc, ld, pcur, nullptr, st);
       if (e == hipSuccess)
-        e = launch_spmm(Mm, rpM, colM, valM, vdt, Qc, ld, pcur, Yc, ld, pcur, ldc, b.planM.n_chunks,
-                        b.planM.order, b.planM.n_long, b.planM.longs, b.planM.partial, T, vm, nullptr, 0, nullptr,
-                        nullptr, st, nullptr, nullptr, Mn);
+        e = plan_spmm(b.planM, Mm, rpM, colM, valM, vdt, Qc, ld, pcur, Yc, ld, pcur, ldc, T, vm, nullptr, 0, nullptr,
+                      nullptr, st);
       return e;
     };
     while (launched < pmax) {
@@ -1150,9 +1198,8 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
       for (int c = 0; c < chunk; ++c) {
         const int pass = launched + c + 1;
         tmark_begin(h, DASHSVD_KT_SPMM_T, pass);
-        HIPCHK(launch_spmm(Mn, rpMT, colMT, valMT, vdt, Yc, ld, pcur, b.C, ld, cdt, ldc, b.planT.n_chunks,
-                           b.planT.order, b.planT.n_long, b.planT.longs, b.planT.partial, T, vm, Qc, ld,
-                           &b.state->alpha, done, st, nullptr, nullptr, Mm));
+        HIPCHK(plan_spmm(b.planT, Mn, rpMT, colMT, valMT, vdt, Yc, ld, pcur, b.C, ld, cdt, ldc, T, vm, Qc, ld,
+                         &b.state->alpha, done, st));
         tmark_end(h);
         HIPCHK(block_step(2, pass, done));
       }
@@ -1217,9 +1264,8 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
     void *Qf = Qfin, *Bf = b.B;
     if (pfin != cdt) {
       // the BF16 form keeps an FP32 B
-      HIPCHK(launch_spmm(Mm, rpM, colM, valM, vdt, Qfin, ld, pfin, b.B, ld, cdt, ldc, b.planM.n_chunks,
-                         b.planM.order, b.planM.n_long, b.planM.longs, b.planM.partial, T, vm, nullptr, 0, nullptr,
-                         nullptr, st, nullptr, nullptr, Mn));
+      HIPCHK(plan_spmm(b.planM, Mm, rpM, colM, valM, vdt, Qfin, ld, pfin, b.B, ld, cdt, ldc, T, vm, nullptr, 0,
+                       nullptr, nullptr, st));
     } else {
       // promoted to FP32 panels: B is the last M Q
       Bf = Yfin;
@@ -1272,6 +1318,8 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   inf.lane_vectors_used = vm;
   inf.slab_kib_used = (int32_t)(slab_b >> 10);
   inf.reordered = reorder ? 1 : 0;
+  inf.head_rows = b.planM.head;
+  inf.head_rows_t = b.planT.head;
   inf.time_total_ms = t_end - t0;
   inf.time_setup_ms = t_setup - t0;
   inf.time_loop_ms = t_loop - t_setup;
@@ -1472,9 +1520,8 @@ static dashsvd_status evaluate_core(dashsvd_handle *h, const dashsvd_csr *A, con
   // with the degree order, U (rows of A) enters in the permuted row order
   HIPCHK(launch_copy2d(h->U, k, h->out_dt, Upad, ld8, c.cdt, urows, k, st, c.u_row_to));
   const Plan &pl = c.plan[side];
-  HIPCHK(launch_spmm(zrows, c.rp[side], c.col[side], c.val[side], c.vdt, Upad, ld8, c.cdt, Z, ld8, c.cdt, ld8,
-                     pl.n_chunks, pl.order, pl.n_long, pl.longs, pl.partial, c.T, 1, nullptr, 0, nullptr, nullptr,
-                     st, nullptr, nullptr, urows));
+  HIPCHK(plan_spmm(pl, zrows, c.rp[side], c.col[side], c.val[side], c.vdt, Upad, ld8, c.cdt, Z, ld8, c.cdt, ld8, c.T,
+                   1, nullptr, 0, nullptr, nullptr, st));
   // ||A^T u_i||^2 = (Z^T Z)_ii in FP64
   HIPCHK(launch_gram(zrows, k, Z, ld8, c.cdt, c.gpart, gram_blocks(zrows, k), c.G, nullptr, st, nullptr));
   std::vector<double> G((size_t)k * k), S(k);
@@ -1602,17 +1649,15 @@ dashsvd_status dashsvd_evaluate_all(dashsvd_handle *h, const dashsvd_csr *A, con
     const Plan &pA = c.plan[sideA], &pT = c.plan[sideAT];
     // y = A q - U (S .* (V^T q))
     run(launch_copy2d(q, 1, DASHSVD_F64, pan_n, 8, c.cdt, n, 1, st));
-    run(launch_spmm(m, c.rp[sideA], c.col[sideA], c.val[sideA], c.vdt, pan_n, 8, c.cdt, pan_m, 8, c.cdt, 8,
-                    pA.n_chunks, pA.order, pA.n_long, pA.longs, pA.partial, c.T, 1, nullptr, 0, nullptr, nullptr, st,
-                    nullptr, nullptr, n));
+    run(plan_spmm(pA, m, c.rp[sideA], c.col[sideA], c.val[sideA], c.vdt, pan_n, 8, c.cdt, pan_m, 8, c.cdt, 8, c.T, 1,
+                  nullptr, 0, nullptr, nullptr, st));
     run(launch_dots(n, k, Vcm, n, q, part, t1, st));
     run(launch_copy2d(pan_m, 8, c.cdt, y, 1, DASHSVD_F64, m, 1, st));
     run(launch_combo(m, k, Ucm, m, t1, h->S, y, st));
     // w = A^T y - V (S .* (U^T y))
     run(launch_copy2d(y, 1, DASHSVD_F64, pan_m, 8, c.cdt, m, 1, st));
-    run(launch_spmm(n, c.rp[sideAT], c.col[sideAT], c.val[sideAT], c.vdt, pan_m, 8, c.cdt, pan_n, 8, c.cdt, 8,
-                    pT.n_chunks, pT.order, pT.n_long, pT.longs, pT.partial, c.T, 1, nullptr, 0, nullptr, nullptr, st,
-                    nullptr, nullptr, m));
+    run(plan_spmm(pT, n, c.rp[sideAT], c.col[sideAT], c.val[sideAT], c.vdt, pan_m, 8, c.cdt, pan_n, 8, c.cdt, 8, c.T,
+                  1, nullptr, 0, nullptr, nullptr, st));
     run(launch_dots(m, k, Ucm, m, y, part, t1, st));
     run(launch_copy2d(pan_n, 8, c.cdt, w, 1, DASHSVD_F64, n, 1, st));
     run(launch_combo(n, k, Vcm, n, t1, h->S, w, st));
@@ -1907,9 +1952,8 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
     return e;
   };
   // sketch: C = M^T Omega, eigSVD, Y = M Q
-  HIPCHK(launch_spmm(n, b.rpT, b.colT, b.valT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ld, b.planT.n_chunks, b.planT.order,
-                     b.planT.n_long, b.planT.longs, b.planT.partial, T, vm, nullptr, 0, nullptr, nullptr, st, nullptr,
-                     nullptr, m));
+  HIPCHK(plan_spmm(b.planT, n, b.rpT, b.colT, b.valT, vdt, b.Y, ld, pdt, b.C, ld, cdt, ld, T, vm, nullptr, 0, nullptr,
+                   nullptr, st));
   HIPCHK(block(1, 0));
   // one power pass of every running matrix, captured once and replayed
   auto pass = [&]() -> hipError_t {
@@ -2000,9 +2044,8 @@ static dashsvd_status run_batched_impl(dashsvd_handle *h, const dashsvd_csr *As,
   // final Rayleigh-Ritz of every matrix: B = M Q, eigSVD(B), U = B W(:,1:k),
   // V = Q Vs(:,1:k), signs
   HIPCHK(launch_bsnap(b.state, count, 0, st));
-  HIPCHK(launch_spmm(m, rpA, colA, valA, vdt, Qc, ld, pc, b.B, ld, cdt, ld, b.planM.n_chunks, b.planM.order,
-                     b.planM.n_long, b.planM.longs, b.planM.partial, T, vm, nullptr, 0, nullptr, nullptr, st, nullptr,
-                     nullptr, n));
+  HIPCHK(plan_spmm(b.planM, m, rpA, colA, valA, vdt, Qc, ld, pc, b.B, ld, cdt, ld, T, vm, nullptr, 0, nullptr, nullptr,
+                   st));
   HIPCHK(launch_bgram(itM_d, nIM, ioffM_d, count, l, b.B, ld, cdt, bpart, b.G, (int64_t)ll, b.state, 0, st));
   HIPCHK(beig(3));
   HIPCHK(launch_brescale(itM_d, nIM, l, b.B, nullptr, ld, cdt, b.W, (int64_t)ll, l, k, b.Uo, k, cdt, b.state, 0,

@@ -335,12 +335,15 @@ __global__ __launch_bounds__(256) void k_permute_entries(int64_t nnz, const int6
 // The sizes the host needs to launch the products, in one place for one copy.
 __global__ void k_plan_sizes(const int64_t *__restrict__ endM, const int64_t *__restrict__ endT,
                              const int32_t *__restrict__ nlM, const int32_t *__restrict__ nlT,
+                             const int32_t *__restrict__ hM, const int32_t *__restrict__ hT,
                              int64_t *__restrict__ out) {
   if (threadIdx.x == 0) {
     out[0] = *endM;
     out[1] = *endT;
     out[2] = *nlM;
     out[3] = *nlT;
+    out[4] = hM ? *hM : 0;
+    out[5] = hT ? *hT : 0;
   }
 }
 
@@ -367,13 +370,17 @@ __device__ __forceinline__ int64_t lower_col(const int32_t *__restrict__ col, in
   return lo;
 }
 
+// Rows below *head (the dense head, longer than long_row) get no chunks:
+// the product's head kernels write them.
 __global__ __launch_bounds__(256) void k_plan_count(int64_t R, const int64_t *__restrict__ rp,
                                                     const int32_t *__restrict__ col, int32_t long_row,
-                                                    int slab_log2, int64_t *__restrict__ nch) {
+                                                    int slab_log2, int64_t *__restrict__ nch,
+                                                    const int32_t *__restrict__ head) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t h = head ? *head : 0;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += stride) {
     const int64_t b = rp[r], e = rp[r + 1], len = e - b;
-    if (len <= long_row) {
+    if (len <= long_row || r < h) {
       nch[r] = 0;
       continue;
     }
@@ -637,16 +644,16 @@ hipError_t launch_permute_entries(int64_t nnz, const int64_t *rp, const int32_t 
 }
 
 hipError_t launch_plan_sizes(const int64_t *endM, const int64_t *endT, const int32_t *nlM, const int32_t *nlT,
-                             int64_t *out, hipStream_t st) {
-  hipLaunchKernelGGL(k_plan_sizes, dim3(1), dim3(64), 0, st, endM, endT, nlM, nlT, out);
+                             const int32_t *hM, const int32_t *hT, int64_t *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_plan_sizes, dim3(1), dim3(64), 0, st, endM, endT, nlM, nlT, hM, hT, out);
   return hipGetLastError();
 }
 
 hipError_t launch_plan_count(int64_t R, const int64_t *rp, const int32_t *col, int32_t long_row, int slab_log2,
-                             int64_t *nch, hipStream_t st) {
+                             int64_t *nch, hipStream_t st, const int32_t *head) {
   if (R == 0) return hipSuccess;
   hipLaunchKernelGGL(k_plan_count, dim3(grid_for(R, 256, 16384)), dim3(256), 0, st, R, rp, col, long_row, slab_log2,
-                     nch);
+                     nch, head);
   return hipGetLastError();
 }
 

@@ -28,6 +28,7 @@ EIG = {"auto": 0, "jacobi": 1, "onesided": 2, "tridiag": 3, "cholqr": 4}
 TIMING = {False: 0, True: 1, "spmm": 2}
 # reorder: "auto" (from 2^22 nonzeros), True, False
 REORDER = {"auto": 0, True: 1, False: -1}
+HEAD = {"auto": 0, "off": -1}
 MAX_L = 160
 MAX_TRACE = 256
 
@@ -51,7 +52,7 @@ class _Options(C.Structure):
                 ("omega", C.c_void_p), ("omega_dtype", C.c_int32), ("omega_on_device", C.c_int32),
                 ("timing", C.c_int32), ("tuning_db", C.c_char_p), ("eig_method", C.c_int32),
                 ("reorder", C.c_int32), ("slab_kib", C.c_int32), ("batch_nnz_max", C.c_int64),
-                ("lane_vectors", C.c_int32)]
+                ("lane_vectors", C.c_int32), ("dense_head", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -67,7 +68,7 @@ class _Info(C.Structure):
                 ("learned_n", C.c_int32),
                 ("promoted", C.c_int32), ("cholqr_calls", C.c_int32), ("sub_batches", C.c_int32),
                 ("graph_launches", C.c_int32), ("lane_vectors_used", C.c_int32), ("slab_kib_used", C.c_int32),
-                ("reordered", C.c_int32)]
+                ("reordered", C.c_int32), ("head_rows", C.c_int32), ("head_rows_t", C.c_int32)]
 
 class _Metrics(C.Structure):
     _fields_ = [("eps_pve", C.c_double), ("eps_sigma", C.c_double), ("eps_res", C.c_double),
@@ -245,6 +246,8 @@ class Info:
     lane_vectors_used: int = 1
     slab_kib_used: int = 0
     reordered: bool = False
+    head_rows: int = 0
+    head_rows_t: int = 0
 
 
 class DashSVD:
@@ -254,19 +257,19 @@ class DashSVD:
                  p_max: int = -1, seed: int = 0, stream=None, long_row: int = 0,
                  check_interval: int = 1, schedule=None, omega=None, timing=False,
                  tuning_db=None, eig_method: str = "auto", reorder="auto", slab_kib: int = 0,
-                 batch_nnz_max: int = 0, lane_vectors: int = 0):
+                 batch_nnz_max: int = 0, lane_vectors: int = 0, dense_head="auto"):
         self._h = C.c_void_p()
         self._keep = []
         opt = self._options(precision, shift_policy, pve_mode, p_max, seed, stream, long_row,
                             check_interval, schedule, omega, timing, tuning_db, eig_method, reorder,
-                            slab_kib, batch_nnz_max, lane_vectors)
+                            slab_kib, batch_nnz_max, lane_vectors, dense_head)
         st = lib().dashsvd_create(C.byref(self._h), C.byref(opt))
         _check(st, None)
 
     def _options(self, precision="fp32", shift_policy="paper", pve_mode="r2", p_max=-1, seed=0,
                  stream=None, long_row=0, check_interval=1, schedule=None, omega=None,
                  timing=False, tuning_db=None, eig_method="auto", reorder="auto", slab_kib=0,
-                 batch_nnz_max=0, lane_vectors=0):
+                 batch_nnz_max=0, lane_vectors=0, dense_head="auto"):
         sched_arr = None
         if schedule is not None:
             sched_arr = np.ascontiguousarray(schedule, dtype=np.float64)
@@ -283,7 +286,7 @@ class DashSVD:
                         _ptr(sched_arr).value if sched_arr is not None else None,
                         om_ptr, om_dt, om_dev, TIMING[timing],
                         tuning_db.encode() if tuning_db else None, EIG[eig_method], REORDER[reorder],
-                        int(slab_kib), int(batch_nnz_max), int(lane_vectors))
+                        int(slab_kib), int(batch_nnz_max), int(lane_vectors), HEAD[dense_head])
 
     def set_workspace(self, buf):
         """dashsvd_set_workspace: run inside the caller's device buffer (a
@@ -630,7 +633,8 @@ def _info_from(raw) -> Info:
                 dict(zip(KT_NAMES, list(raw.kt_count))), raw.eig_calls, raw.eig_sweeps,
                 np.array(raw.sweeps_per_call[:min(raw.eig_calls, MAX_TRACE + 2)]),
                 bool(raw.promoted), raw.long_row_used, raw.learned_n, raw.cholqr_calls, raw.sub_batches,
-                raw.graph_launches, raw.lane_vectors_used, raw.slab_kib_used, bool(raw.reordered))
+                raw.graph_launches, raw.lane_vectors_used, raw.slab_kib_used, bool(raw.reordered),
+                raw.head_rows, raw.head_rows_t)
 
 
 def workspace_size_batched(mats, k: int, p: int, precision: str = "fp32") -> int:

@@ -248,6 +248,61 @@ def test_degree_order_matches_oracle(torch_dev, shape, prec):
     assert np.all(res <= rref + (1e-9 if prec == "fp64" else 1e-4))
 
 
+def _expected_heads(A, long_row):
+    """Dense-head row counts of M and M^T from the degree sequences alone:
+    the leading rows (non-increasing degree) with at least
+    max(long_row + 1, ceil(columns / 16)) nonzeros, at most 128; none if
+    fewer than 16, or if they hold fewer than 16 nonzeros per column."""
+    deg_r = np.sort(np.diff(A.row_ptr))[::-1]
+    deg_c = np.sort(np.bincount(A.col, minlength=A.n))[::-1]
+    wide = A.m < A.n
+    dM, dT = (deg_c, deg_r) if wide else (deg_r, deg_c)
+    Mm, Mn = (A.n, A.m) if wide else (A.m, A.n)
+
+    def count(d, ncols):
+        thr = max(long_row + 1, -(-ncols // 16))
+        short = np.nonzero(d < thr)[0]
+        h = min(128, int(short[0]) if len(short) else len(d))
+        return h if h >= 16 and d[:h].sum() >= 16 * ncols else 0
+    return count(dM, Mn), count(dT, Mm)
+
+
+@pytest.mark.parametrize("shape,nnz,prec,long_row", [((30000, 12000), 500000, "fp32", 0),
+                                                     ((6000, 15000), 600000, "fp32", 0),
+                                                     ((8000, 5000), 500000, "fp64", 0),
+                                                     ((8000, 5000), 500000, "fp64", 400),
+                                                     ((8000, 5000), 500000, "bf16", 0)])
+def test_dense_head_matches_oracle_and_plain_spmm(torch_dev, shape, nnz, prec, long_row):
+    """The dense heads of M and M^T (leading degree-ordered rows multiplied
+    on the matrix cores, the row-split SpMM taking the rest): the head sizes
+    are those the degree sequences give, and the solve matches the oracle at
+    the form's bar (FP64 1e-10; FP32 1e-5; BF16 panels 2e-2, where the head
+    of M^T also takes the shifted product C = M^T Y - alpha Q) and the solve
+    with the heads switched off to the same bar; tall and wide, one head or
+    both, FP64 with a longer chunk length (a higher least degree)."""
+    m, n = shape
+    A = synth.zipf_csr(m, n, nnz, seed=m + n)
+    if prec == "fp64":
+        A.val = A.val.astype(np.float64)
+    hM, hT = _expected_heads(A, long_row if long_row > 0 else 128)
+    assert hM > 0
+    ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 20, 10, 4, 0.0, seed=31)
+    bar = {"fp64": 1e-10, "fp32": 1e-5, "bf16": 2e-2}[prec]
+    out = {}
+    for head in ("auto", "off"):
+        U, S, V, st, info, tr = _solve(A, 20, 10, 4, 0.0, 31, prec, reorder=True, long_row=long_row,
+                                       dense_head=head)
+        assert st == 0
+        out[head] = (S, info)
+    S, info = out["auto"]
+    assert (info.head_rows, info.head_rows_t) == (hM, hT)
+    assert (out["off"][1].head_rows, out["off"][1].head_rows_t) == (0, 0)
+    assert np.all(np.abs(S - ref.S) / ref.S <= bar)
+    if prec != "bf16":
+        assert np.allclose(info.alpha_used, ref.alpha, rtol=bar)
+    assert np.all(np.abs(S - out["off"][0]) / out["off"][0] <= bar)
+
+
 def test_degree_order_same_result_as_plain_order(torch_dev):
     """Reordering changes only the summation order: with and without it the
     singular values agree to FP32 rounding, the vectors to the sign, and the
