@@ -348,7 +348,7 @@ def source_digest(*names):
 # The SpMM's counter traffic depends on the kernel, on the order of the
 # operator's rows and columns (the degree order is built in k_csr.hip) and on
 # the panel layout (the leading dimension is chosen in driver.hip).
-TRAFFIC_SOURCES = {"spmm": ("k_spmm.hip", "k_csr.hip", "driver.hip"), "eig": ("k_eigtri.hip",)}
+TRAFFIC_SOURCES = {"spmm": ("k_spmm.hip", "k_head.hip", "k_csr.hip", "driver.hip"), "eig": ("k_eigtri.hip",)}
 
 
 def traffic(kind):
@@ -436,9 +436,11 @@ def summarize_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, commands
     print("#")
     spmm = [r for r in rows if r[0].startswith("k_spmm<")]
     spmm_long = [r for r in rows if r[0].startswith("k_spmm_long<")]
-    # one SpMM launch = k_spmm + its long-row kernel (mean over the dispatches)
-    spmm_b = sum(r[4] * r[1] for r in spmm) / max(1, sum(r[1] for r in spmm))
-    spmm_b += sum(r[4] * r[1] for r in spmm_long) / max(1, sum(r[1] for r in spmm))
+    heads = [r for r in rows if r[0].startswith("k_head_partial<") or r[0].startswith("k_head_reduce<")]
+    # one SpMM launch = k_spmm + its long-row kernel + the dense head kernels
+    # of the products that have one (all summed, over the k_spmm dispatches)
+    n_spmm = max(1, sum(r[1] for r in spmm))
+    spmm_b = sum(r[4] * r[1] for r in spmm + spmm_long + heads) / n_spmm
     # tridiagonal eigSVD calls: k_tri_reduce + k_tri_vectors (means over
     # their dispatches; the Jacobi launch behind each call returns at once
     # unless the call declined)
@@ -449,7 +451,8 @@ def summarize_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, commands
         if n:
             eig_b += sum(r[4] * r[1] for r in sel) / n * 1e6
             eig_n = n
-    print("# One SpMM launch = k_spmm + k_spmm_long (means over their dispatches); one eigSVD call =")
+    print("# One SpMM launch = k_spmm + k_spmm_long + the dense head (k_head_partial + k_head_reduce, A C only),")
+    print("# their bytes summed over the k_spmm dispatches; one eigSVD call =")
     print("# k_tri_reduce + k_tri_vectors (means over their dispatches).")
     print(f"# Algorithmic bytes per launch for comparison: SpMM (A C) {spmm_bytes(200000, 100000, 10**7, 120) / 1e6:.1f} MB,"
           f" SpMM (A^T Z) {spmm_bytes(100000, 200000, 10**7, 120) / 1e6:.1f} MB.")
@@ -601,8 +604,10 @@ def main():
                    "form": "plain FP32", "passes": inf.passes, "converged": inf.converged,
                    "eps_pve": pve, "eps_sigma": es, "eig_calls": inf.eig_calls,
                    "cholqr_calls": inf.cholqr_calls, "eig_sweeps": inf.eig_sweeps,
-                   "sweeps_per_call": [int(x) for x in inf.sweeps_per_call]},
-        "roofline": {"bound": "hbm", "kernel": "SpMM (k_spmm + k_spmm_long), the two products of a pass",
+                   "sweeps_per_call": [int(x) for x in inf.sweeps_per_call],
+                   "dense_head_rows": [inf.head_rows, inf.head_rows_t]},
+        "roofline": {"bound": "hbm", "kernel": "SpMM (k_spmm + k_spmm_long + dense head k_head_partial + "
+                     "k_head_reduce), the two products of a pass",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic("spmm"),
                      # the counters' bytes (L2 misses of the gathers, served by the
