@@ -190,7 +190,7 @@ typedef struct {
                              nonzeros each (at most 128; none if fewer than 16) are
                              multiplied as a dense block on the matrix cores instead of
                              by the row-split SpMM.  AUTO (0, default): on where the degree
-                             order is on and l rounded up to 8 is at most 128; OFF (-1) */
+                             order is on (l rounded up to 8 at most 160); OFF (-1) */
 } dashsvd_options;
 
 #define DASHSVD_HEAD_AUTO 0

@@ -292,11 +292,12 @@ hipError_t launch_spmm(int64_t R, const int64_t *rp, const int32_t *col, const v
 // (tdtype 1 = f64 for FP64 panels, else 0 = f32); part holds kHeadSplits
 // partial products.
 constexpr int kHeadMax = 128;
+constexpr int kHeadMaxCols = 160;  // panel columns (ldc) the head kernels take
 constexpr int kHeadMinRows = 16;
 constexpr int kHeadSplits = 256;
 size_t head_dt_bytes(int64_t ncols, int tdtype);
 size_t head_part_bytes(int tdtype);
-// the row ranges of the splits stay within 32-bit buffer offsets, ldc <= kHeadMax
+// the row ranges of the splits stay within 32-bit buffer offsets, ldc <= kHeadMaxCols
 bool head_fits(int64_t K, int64_t ldx, int xdtype, int ldc);
 // the head's nonzeros must be at least this many times the operator's columns
 constexpr int kHeadNnzPerCol = 16;

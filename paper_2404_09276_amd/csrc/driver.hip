@@ -659,7 +659,7 @@ static dashsvd_status run_impl(dashsvd_handle *h, const dashsvd_csr *A, int32_t 
   // dense heads of M and M^T: only in the degree order (the head is then a
   // prefix of the rows), and for panels whose rows fit the head kernels
   const int head_t = prec == DASHSVD_PREC_FP64 ? 1 : 0;
-  const bool heads = reorder && h->opt.dense_head != DASHSVD_HEAD_OFF && ldc <= kHeadMax &&
+  const bool heads = reorder && h->opt.dense_head != DASHSVD_HEAD_OFF && ldc <= kHeadMaxCols &&
                      head_fits(Mn > Mm ? Mn : Mm, ld, cdt, ldc);
   plan_alloc(h, ar, b.planM, Mm, nnz, T, ldc, accsz, Mn, prow_b, slab_b, heads ? head_t : -1);
   plan_alloc(h, ar, b.planT, Mn, nnz, T, ldc, accsz, Mm, prow_b, slab_b, heads ? head_t : -1);

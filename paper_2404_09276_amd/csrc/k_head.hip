@@ -37,10 +37,11 @@ namespace {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-// Partial products: 8 x 8 tiles of 16 x 16 per split, in the accumulator
-// layout (tile, lane, register).
+// Partial products: 8 x 10 tiles of 16 x 16 per split (H <= 128 rows,
+// ldc <= 160 columns), in the accumulator layout (tile, lane, register).
 constexpr int kHeadTiles = kHeadMax / 16;
-constexpr int64_t kHeadSplitElems = (int64_t)kHeadTiles * kHeadTiles * 256;
+constexpr int kHeadTilesJ = kHeadMaxCols / 16;
+constexpr int64_t kHeadSplitElems = (int64_t)kHeadTiles * kHeadTilesJ * 256;
 
 template <typename TA> struct head_mfma;
 template <> struct head_mfma<float> {
@@ -207,11 +208,11 @@ __global__ __launch_bounds__(256) void k_head_partial(int64_t K, const TX *__res
       // accumulators stored directly read back stale rows)
       TA x0 = acc0[j][q];
       asm volatile("" : "+v"(x0));
-      out[(int64_t)(ti0 * kHeadTiles + j) * 256 + lane * 4 + q] = x0;
+      out[(int64_t)(ti0 * kHeadTilesJ + j) * 256 + lane * 4 + q] = x0;
       if (two) {
         TA x1 = acc1[j][q];
         asm volatile("" : "+v"(x1));
-        out[(int64_t)(ti1 * kHeadTiles + j) * 256 + lane * 4 + q] = x1;
+        out[(int64_t)(ti1 * kHeadTilesJ + j) * 256 + lane * 4 + q] = x1;
       }
     }
   }
@@ -232,7 +233,7 @@ __global__ __launch_bounds__(256) void k_head_reduce(int H, int ldc, const TA *_
   const int ti = tile / TJ, tj = tile - ti * TJ;
   const int wave = threadIdx.x >> 6, t = threadIdx.x & 63;
   const int e = (blockIdx.x & 3) * 64 + t;
-  const TA *p = part + (int64_t)(ti * kHeadTiles + tj) * 256 + e;
+  const TA *p = part + (int64_t)(ti * kHeadTilesJ + tj) * 256 + e;
   constexpr int SQ = kHeadSplits / 4;
   const int s0 = wave * SQ;
   TA sum = (TA)0;
@@ -268,8 +269,10 @@ hipError_t run_head(int H, int64_t K, const void *X, int64_t ldx, int ldc, const
     if (two) DSV_HEAD_PARTIAL(2, true); else DSV_HEAD_PARTIAL(2, false);
   } else if (TJ <= 4) {
     if (two) DSV_HEAD_PARTIAL(4, true); else DSV_HEAD_PARTIAL(4, false);
-  } else {
+  } else if (TJ <= 8) {
     if (two) DSV_HEAD_PARTIAL(8, true); else DSV_HEAD_PARTIAL(8, false);
+  } else {
+    if (two) DSV_HEAD_PARTIAL(kHeadTilesJ, true); else DSV_HEAD_PARTIAL(kHeadTilesJ, false);
   }
 #undef DSV_HEAD_PARTIAL
   if (alpha)
@@ -293,7 +296,7 @@ bool head_fits(int64_t K, int64_t ldx, int xdtype, int ldc) {
   const int64_t xs = xdtype == 1 ? 8 : xdtype == 2 ? 2 : 4;
   const int64_t rows = K / kHeadSplits + 1 + 4 * 6;
   const int64_t wmax = (ldx * xs > kHeadMax * 8 ? ldx * xs : kHeadMax * 8);
-  return ldc <= kHeadMax && rows * wmax < ((int64_t)1 << 31) - 4096;
+  return ldc <= kHeadMaxCols && rows * wmax < ((int64_t)1 << 31) - 4096;
 }
 
 hipError_t launch_head_count(int64_t R, const int64_t *rp, int64_t thr, int64_t min_nnz, int32_t *out,

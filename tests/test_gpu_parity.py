@@ -267,30 +267,33 @@ def _expected_heads(A, long_row):
     return count(dM, Mn), count(dT, Mm)
 
 
-@pytest.mark.parametrize("shape,nnz,prec,long_row", [((30000, 12000), 500000, "fp32", 0),
-                                                     ((6000, 15000), 600000, "fp32", 0),
-                                                     ((8000, 5000), 500000, "fp64", 0),
-                                                     ((8000, 5000), 500000, "fp64", 400),
-                                                     ((8000, 5000), 500000, "bf16", 0)])
-def test_dense_head_matches_oracle_and_plain_spmm(torch_dev, shape, nnz, prec, long_row):
+@pytest.mark.parametrize("shape,nnz,prec,long_row,k,s", [((30000, 12000), 500000, "fp32", 0, 20, 10),
+                                                         ((6000, 15000), 600000, "fp32", 0, 20, 10),
+                                                         ((8000, 5000), 500000, "fp32", 0, 100, 50),
+                                                         ((8000, 5000), 500000, "fp64", 0, 20, 10),
+                                                         ((8000, 5000), 500000, "fp64", 400, 20, 10),
+                                                         ((8000, 5000), 500000, "fp64", 0, 100, 50),
+                                                         ((8000, 5000), 500000, "bf16", 0, 20, 10)])
+def test_dense_head_matches_oracle_and_plain_spmm(torch_dev, shape, nnz, prec, long_row, k, s):
     """The dense heads of M and M^T (leading degree-ordered rows multiplied
     on the matrix cores, the row-split SpMM taking the rest): the head sizes
     are those the degree sequences give, and the solve matches the oracle at
     the form's bar (FP64 1e-10; FP32 1e-5; BF16 panels 2e-2, where the head
     of M^T also takes the shifted product C = M^T Y - alpha Q) and the solve
     with the heads switched off to the same bar; tall and wide, one head or
-    both, FP64 with a longer chunk length (a higher least degree)."""
+    both, l = 30 and l = 150 (ten tile columns), FP64 with a longer chunk
+    length (a higher least degree)."""
     m, n = shape
     A = synth.zipf_csr(m, n, nnz, seed=m + n)
     if prec == "fp64":
         A.val = A.val.astype(np.float64)
     hM, hT = _expected_heads(A, long_row if long_row > 0 else 128)
     assert hM > 0
-    ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 20, 10, 4, 0.0, seed=31)
+    ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, k, s, 4, 0.0, seed=31)
     bar = {"fp64": 1e-10, "fp32": 1e-5, "bf16": 2e-2}[prec]
     out = {}
     for head in ("auto", "off"):
-        U, S, V, st, info, tr = _solve(A, 20, 10, 4, 0.0, 31, prec, reorder=True, long_row=long_row,
+        U, S, V, st, info, tr = _solve(A, k, s, 4, 0.0, 31, prec, reorder=True, long_row=long_row,
                                        dense_head=head)
         assert st == 0
         out[head] = (S, info)
