@@ -301,8 +301,14 @@ def test_dense_head_matches_oracle_and_plain_spmm(torch_dev, shape, nnz, prec, l
     assert (info.head_rows, info.head_rows_t) == (hM, hT)
     assert (out["off"][1].head_rows, out["off"][1].head_rows_t) == (0, 0)
     assert np.all(np.abs(S - ref.S) / ref.S <= bar)
-    if prec != "bf16":
+    # the shifts come from the smallest singular value of each block (Alg. 5
+    # step 6), on the scale of sigma^2: in FP32 the Gram and its eigenvalues
+    # carry normwise rounding, about l eps ||G|| = l eps sigma_1^2, which
+    # at l = 150 is 1e-5 of sigma_1^2 (3e-5 of the shift itself here)
+    if prec == "fp64":
         assert np.allclose(info.alpha_used, ref.alpha, rtol=bar)
+    elif prec == "fp32":
+        assert np.all(np.abs(info.alpha_used - ref.alpha) <= 1e-6 * ref.S[0] ** 2)
     assert np.all(np.abs(S - out["off"][0]) / out["off"][0] <= bar)
 
 
