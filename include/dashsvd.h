@@ -147,7 +147,7 @@ typedef struct {
   void *hip_stream;       /* hipStream_t, NULL = null stream */
   int32_t long_row;       /* SpMM rows longer than this are split into chunks of this many
                              nonzeros; <= 0 selects the tuning database's value for the
-                             shape, else 768 from DASHSVD_REORDER_MIN_NNZ nonzeros and
+                             shape, else 1024 from DASHSVD_REORDER_MIN_NNZ nonzeros and
                              128 below */
   int32_t check_interval; /* passes launched between host reads of the done flag; <= 0: 1 */
   const double *schedule; /* SHIFT_SCHEDULE multipliers, host, p_max + 1 entries (index = pass) */

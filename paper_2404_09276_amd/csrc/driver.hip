@@ -34,11 +34,12 @@ thread_local std::string g_create_error;
 
 constexpr int kDefaultLongRow = 128;
 // Default chunk length from DASHSVD_REORDER_MIN_NNZ nonzeros: on the
-// degree-ordered power-law operators of that size, chunks of 768 nonzeros
-// gave the fastest products (fewer partial rows; on the 10M-nonzero
-// benchmark matrix the solve took 9.89 ms against 10.06, 9.99 and 9.90 ms
-// with 384, 512 and 1024, timed in one process).
-constexpr int kDefaultLongRowLarge = 768;
+// degree-ordered power-law operators of that size with their dense head,
+// chunks of 1024 nonzeros gave the fastest products (fewer partial rows; on
+// the 10M-nonzero benchmark matrix the solve took 7.38 ms against 7.66, 7.56
+// and 7.60 ms with 512, 768 and 1536, timed in one process; the 100M-nonzero
+// matrix is within 1 % from 768 to 2048).
+constexpr int kDefaultLongRowLarge = 1024;
 constexpr int kDefaultPmax = 64;
 
 size_t dsz(int dt) { return dt == DASHSVD_F64 ? 8 : (dt == DASHSVD_BF16 ? 2 : 4); }

@@ -150,10 +150,10 @@ def test_zipf_2m_bf16_full_size(torch_dev, zipf_2m, tol):
 
 def test_zipf_200k_fp32_sigma_parity_with_oracle(torch_dev):
     """The benchmarked workload against the oracle run live: same Omega
-    (Philox seed 2002), default options (degree order on, 768-nonzero
-    chunks, Cholesky-QR then Jacobi blocks).  Equal N_p at tol 1e-2; sigma
-    within 1e-5 relative element by element; per-pass shifts within 1e-5
-    relative.  The ratio is a difference of surrogates E_i = S_i + alpha of
+    (Philox seed 2002), default options (degree order on with its dense
+    head, 1024-nonzero chunks, the tridiagonal eigSVD).  Equal N_p at tol
+    1e-2; sigma within 1e-5 relative element by element; per-pass shifts
+    within 1e-5 relative.  The ratio is a difference of surrogates E_i = S_i + alpha of
     size up to E_1, divided by E_{k+1}: FP32 panels perturb each E_i by about
     1e-6 E_i, so the ratios are held to 1e-5 * E_1 / E_{k+1} absolute."""
     torch = torch_dev
