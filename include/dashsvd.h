@@ -147,8 +147,8 @@ typedef struct {
   void *hip_stream;       /* hipStream_t, NULL = null stream */
   int32_t long_row;       /* SpMM rows longer than this are split into chunks of this many
                              nonzeros; <= 0 selects the tuning database's value for the
-                             shape, else 1024 from DASHSVD_REORDER_MIN_NNZ nonzeros and
-                             128 below */
+                             shape, else 1024 (768 with BF16 panels) from
+                             DASHSVD_REORDER_MIN_NNZ nonzeros and 128 below */
   int32_t check_interval; /* passes launched between host reads of the done flag; <= 0: 1 */
   const double *schedule; /* SHIFT_SCHEDULE multipliers, host, p_max + 1 entries (index = pass) */
   const void *omega;      /* optional caller-provided Omega (rows = max(m,n), l columns,

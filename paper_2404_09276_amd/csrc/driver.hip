@@ -35,11 +35,13 @@ thread_local std::string g_create_error;
 constexpr int kDefaultLongRow = 128;
 // Default chunk length from DASHSVD_REORDER_MIN_NNZ nonzeros: on the
 // degree-ordered power-law operators of that size with their dense head,
-// chunks of 1024 nonzeros gave the fastest products (fewer partial rows; on
-// the 10M-nonzero benchmark matrix the solve took 7.38 ms against 7.66, 7.56
-// and 7.60 ms with 512, 768 and 1536, timed in one process; the 100M-nonzero
-// matrix is within 1 % from 768 to 2048).
+// chunks of 1024 nonzeros gave the fastest FP32 products (fewer partial rows;
+// on the 10M-nonzero benchmark matrix the solve took 7.38 ms against 7.66,
+// 7.56 and 7.60 ms with 512, 768 and 1536, timed in one process; the
+// 100M-nonzero matrix is within 1 % from 768 to 2048).  BF16 panels gather
+// rows half as wide, and 768 stays faster for them (8.10 against 8.38 ms).
 constexpr int kDefaultLongRowLarge = 1024;
+constexpr int kDefaultLongRowLargeBf16 = 768;
 constexpr int kDefaultPmax = 64;
 
 size_t dsz(int dt) { return dt == DASHSVD_F64 ? 8 : (dt == DASHSVD_BF16 ? 2 : 4); }
@@ -554,7 +556,8 @@ static const TuneVal *tuned(const dashsvd_handle *h, const std::string &key) {
 static int32_t chunk_length(const dashsvd_handle *h, const std::string &key, int64_t nnz) {
   if (h->opt.long_row > 0) return h->opt.long_row;
   if (const TuneVal *t = tuned(h, key)) return t->T;
-  return nnz >= DASHSVD_REORDER_MIN_NNZ ? kDefaultLongRowLarge : kDefaultLongRow;
+  if (nnz < DASHSVD_REORDER_MIN_NNZ) return kDefaultLongRow;
+  return h->opt.precision == DASHSVD_PREC_BF16_PANELS ? kDefaultLongRowLargeBf16 : kDefaultLongRowLarge;
 }
 
 // SpMM lanes per row: one 16-byte vector per lane (1) or two (2), from the
