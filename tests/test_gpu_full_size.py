@@ -153,9 +153,10 @@ def test_zipf_200k_fp32_sigma_parity_with_oracle(torch_dev):
     (Philox seed 2002), default options (degree order on with its dense
     head, 1024-nonzero chunks, the tridiagonal eigSVD).  Equal N_p at tol
     1e-2; sigma within 1e-5 relative element by element; per-pass shifts
-    within 1e-5 relative.  The ratio is a difference of surrogates E_i = S_i + alpha of
-    size up to E_1, divided by E_{k+1}: FP32 panels perturb each E_i by about
-    1e-6 E_i, so the ratios are held to 1e-5 * E_1 / E_{k+1} absolute."""
+    within 1e-5 relative.  The ratio is a difference of surrogates E_i =
+    S_i + alpha of size up to E_1, divided by E_{k+1}: FP32 panels perturb
+    each E_i by about 1e-6 E_i, so the ratios are held to
+    1e-5 * E_1 / E_{k+1} absolute."""
     torch = torch_dev
     A = synth.config_zipf_200k()
     seed = synth.OMEGA_SEED["zipf_200k"]
@@ -168,6 +169,11 @@ def test_zipf_200k_fp32_sigma_parity_with_oracle(torch_dev):
     try:
         assert st == 0 and info.converged and ref.converged
         assert info.passes == ref.passes
+        # the first 128 rows of A (each at least 100000 / 16 nonzeros) take
+        # the dense head; A^T's qualifying rows hold too few nonzeros
+        deg = np.sort(np.diff(A.row_ptr))[::-1]
+        assert deg[127] >= A.n // 16 and info.reordered
+        assert (info.head_rows, info.head_rows_t) == (128, 0)
         rel = np.abs(S - ref.S) / ref.S
         print(f"zipf_200k fp32 vs oracle: max sigma rel err {rel.max():.2e}", flush=True)
         assert np.all(rel <= 1e-5)
