@@ -312,6 +312,26 @@ def test_dense_head_matches_oracle_and_plain_spmm(torch_dev, shape, nnz, prec, l
     assert np.all(np.abs(S - out["off"][0]) / out["off"][0] <= bar)
 
 
+def test_dense_head_repeats_bit_for_bit_and_small_l(torch_dev):
+    """The head's partial products are summed in a fixed order: two solves
+    with the heads on give the same bits.  A narrow panel (l = 8, one tile
+    column of the head kernels, most of it padding) matches the oracle and
+    the solve without the heads."""
+    A = synth.zipf_csr(8000, 5000, 500000, seed=13000)
+    hM, hT = _expected_heads(A, 128)
+    assert hM > 0 and hT > 0
+    r1 = _solve(A, 20, 10, 5, 0.0, 3, "fp32", reorder=True)
+    r2 = _solve(A, 20, 10, 5, 0.0, 3, "fp32", reorder=True)
+    assert (r1[4].head_rows, r1[4].head_rows_t) == (hM, hT)
+    assert np.array_equal(r1[1], r2[1]) and np.array_equal(r1[0], r2[0]) and np.array_equal(r1[2], r2[2])
+    ref = oracle.dashsvd(A.m, A.n, A.row_ptr, A.col, A.val, 4, 4, 4, 0.0, seed=5)
+    U, S, V, st, info, tr = _solve(A, 4, 4, 4, 0.0, 5, "fp32", reorder=True)
+    U0, S0, V0, st0, info0, tr0 = _solve(A, 4, 4, 4, 0.0, 5, "fp32", reorder=True, dense_head="off")
+    assert st == 0 and st0 == 0 and info.head_rows == hM and info0.head_rows == 0
+    assert np.all(np.abs(S - ref.S) / ref.S <= 1e-5)
+    assert np.all(np.abs(S - S0) / S0 <= 1e-5)
+
+
 def test_degree_order_same_result_as_plain_order(torch_dev):
     """Reordering changes only the summation order: with and without it the
     singular values agree to FP32 rounding, the vectors to the sign, and the
