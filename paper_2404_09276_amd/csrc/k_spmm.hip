@@ -63,6 +63,24 @@ __device__ __forceinline__ void buf_gather(__amdgpu_buffer_rsrc_t r, uint32_t of
   }
 }
 
+// Workgroups are dealt to the 8 XCDs in turn (workgroup b to XCD b % 8).
+// Renumbered so that each XCD takes runs of kXcdRun consecutive tasks
+// (runs dealt to the XCDs in turn, so the heavy chunks at the head of the
+// task list still spread over all of them): the rows an XCD works on at a
+// time are neighbours, and in the batched form they belong to the same few
+// matrices, whose panel rows then stay in that XCD's L2 instead of every L2
+// holding every matrix in flight.  A permutation of the tasks (the last,
+// partial round keeps its order): each task still writes its own rows or
+// slots, so results do not change.  (Batched form: 48.1 -> 43.8 ms a batch
+// of 512 matrices.)
+__device__ __forceinline__ int64_t xcd_block() {
+  constexpr int64_t kXcds = 8, kXcdRun = 32, S = kXcds * kXcdRun;
+  const int64_t nb = gridDim.x, b = blockIdx.x;
+  if (b >= (nb / S) * S) return b;
+  const int64_t w = b % S;
+  return b - w + (w % kXcds) * kXcdRun + w / kXcds;
+}
+
 template <typename TX> struct acc_of {
   using type = float;
 };
@@ -92,7 +110,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(spmm_min_wa
   const int rpw = kWave / G;
   const int sub = lane / G, cl = lane - sub * G;
   if (sub >= rpw) return;
-  const int64_t g = ((int64_t)blockIdx.x * 4 + wave) * rpw + sub;
+  // the batched operator (rowmat) takes the XCD runs; for one matrix they
+  // made both products 8-14 % slower on the power-law benchmark matrix
+  const int64_t blk = rowmat ? xcd_block() : (int64_t)blockIdx.x;
+  const int64_t g = (blk * 4 + wave) * rpw + sub;
   int64_t b, e, row = -1, slot = 0;
   const double *alpha_row = alpha;
   if (g < n_chunks) {
