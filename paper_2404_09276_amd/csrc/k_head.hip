@@ -16,7 +16,8 @@
 //     nonzeros (the dense product reads the whole panel once, about what
 //     that many gathers of the row-split kernel cost);
 //   - k_head_clear, k_head_scatter: Dt = M[0:H, :]^T as a dense
-//     ncols x kHeadMax array (zero past H);
+//     ncols x kHeadMax array (its columns H..Hp-1 zero, Hp = H rounded up
+//     to 16; the columns past Hp are never read);
 //   - k_head_partial: kHeadSplits row ranges of the panel X; block s forms
 //     the H x ldc product Dt[range]^T X[range] on v_mfma_f32_16x16x4 (FP32
 //     and BF16 panels, FP32 accumulation as in the SpMM) or
